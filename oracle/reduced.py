@@ -1,0 +1,127 @@
+"""Reduced CBFM system with the Calderon multiplicative preconditioner
+(Sec. III-C).
+
+  C^JM = blkdiag(C^J_1..C^J_M, C^M_1..C^M_M)       (N x N_CBF)
+  C^MJ = blkdiag(C^M_1..C^M_M, C^J_1..C^J_M)
+  G^CBF = (C^JM)^H G_ffff C^MJ,  G_ffff = blkdiag(G, G)
+  outer:  [(C^JM)^H Z C^MJ] (G^CBF)^{-1} y = (C^JM)^H v
+  inner:  G^CBF j_CBF = y
+  j = C^MJ j_CBF
+
+The outer system is solved by restarted GMRES with modified Gram-Schmidt
+Arnoldi (Saad 2003), x0 = 0, stopping on the relative residual of the
+preconditioned system; the inner system by a dense LU (an exact inverse).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .cbf import CBFSet
+
+
+def expand(cb: CBFSet, ne: int, which: str):
+    """Dense ne x (sum L) block matrix of C^M or C^J (columns cell by cell)."""
+    Ls = cb.L
+    off = np.concatenate([[0], np.cumsum(Ls)])
+    C = np.zeros((ne, off[-1]), dtype=np.complex128)
+    mats = cb.CM if which == "M" else cb.CJ
+    for c, ix in enumerate(cb.cells):
+        C[np.ix_(ix, np.arange(off[c], off[c + 1]))] = mats[c]
+    return C
+
+
+def cbf_matrices(cb: CBFSet, ne: int):
+    CM = expand(cb, ne, "M")
+    CJ = expand(cb, ne, "J")
+    Z0 = np.zeros_like(CM)
+    CJM = np.block([[CJ, Z0], [Z0, CM]])
+    CMJ = np.block([[CM, Z0], [Z0, CJ]])
+    return CJM, CMJ
+
+
+def project(Z, CJM, CMJ):
+    """Z_r = (C^JM)^H Z C^MJ."""
+    return CJM.conj().T @ Z @ CMJ
+
+
+def gram_cbf(G, CJM, CMJ):
+    ne = G.shape[0]
+    Gff = np.zeros((2 * ne, 2 * ne))
+    Gff[:ne, :ne] = G
+    Gff[ne:, ne:] = G
+    return CJM.conj().T @ Gff @ CMJ
+
+
+def gmres(matvec, b, tol=1e-12, restart=100, max_iter=1000):
+    """Restarted GMRES(restart) for one right-hand side.  Returns
+    (x, iterations, relative residual history)."""
+    b = np.asarray(b, dtype=np.complex128)
+    n = len(b)
+    x = np.zeros(n, dtype=np.complex128)
+    bn = np.linalg.norm(b)
+    hist = [1.0]
+    if bn == 0:
+        return x, 0, hist
+    it = 0
+    r = b.copy()
+    while it < max_iter:
+        beta = np.linalg.norm(r)
+        if beta / bn <= tol:
+            break
+        m = min(restart, max_iter - it)
+        Vb = np.zeros((m + 1, n), dtype=np.complex128)
+        H = np.zeros((m + 1, m), dtype=np.complex128)
+        Vb[0] = r / beta
+        cs = np.zeros(m, dtype=np.complex128)
+        sn = np.zeros(m, dtype=np.complex128)
+        g = np.zeros(m + 1, dtype=np.complex128)
+        g[0] = beta
+        kk = 0
+        for kk in range(m):
+            wv = matvec(Vb[kk])
+            for i in range(kk + 1):
+                H[i, kk] = np.vdot(Vb[i], wv)
+                wv = wv - H[i, kk] * Vb[i]
+            H[kk + 1, kk] = np.linalg.norm(wv)
+            if H[kk + 1, kk] != 0:
+                Vb[kk + 1] = wv / H[kk + 1, kk]
+            for i in range(kk):                         # previous rotations
+                t = cs[i] * H[i, kk] + sn[i] * H[i + 1, kk]
+                H[i + 1, kk] = -np.conj(sn[i]) * H[i, kk] + np.conj(cs[i]) * H[i + 1, kk]
+                H[i, kk] = t
+            a, bb = H[kk, kk], H[kk + 1, kk]
+            den = np.sqrt(abs(a) ** 2 + abs(bb) ** 2)
+            cs[kk] = np.conj(a) / den if den else 1.0
+            sn[kk] = np.conj(bb) / den if den else 0.0
+            H[kk, kk] = den
+            H[kk + 1, kk] = 0
+            g[kk + 1] = -np.conj(sn[kk]) * g[kk]
+            g[kk] = cs[kk] * g[kk]
+            it += 1
+            hist.append(abs(g[kk + 1]) / bn)
+            if hist[-1] <= tol:
+                kk += 1
+                break
+        else:
+            kk = m
+        y = np.linalg.solve(np.triu(H[:kk, :kk]), g[:kk]) if kk else np.zeros(0)
+        x = x + Vb[:kk].T @ y
+        r = b - matvec(x)
+        if hist[-1] <= tol:
+            break
+    return x, it, hist
+
+
+def solve_reduced(Zr, Gcbf, vr, tol=1e-12, restart=100, max_iter=1000):
+    """Right-preconditioned GMRES on Z_r G^-1 y = v_r, then j_CBF = G^-1 y,
+    for every column of ``vr``.  Returns (j_CBF, iterations, histories)."""
+    vr = np.asarray(vr).reshape(Zr.shape[0], -1)
+    Ginv = np.linalg.inv(Gcbf)
+    out = np.zeros_like(vr)
+    its, hists = [], []
+    for c in range(vr.shape[1]):
+        y, it, h = gmres(lambda u: Zr @ (Ginv @ u), vr[:, c], tol, restart, max_iter)
+        out[:, c] = Ginv @ y
+        its.append(it)
+        hists.append(h)
+    return out, its, hists

@@ -1,0 +1,121 @@
+"""Seeded synthetic workloads shaped like the paper's experiments.
+
+Units: free-space wavelength lambda0 = 1, so k0 = 2 pi.  Exterior medium is
+vacuum, interior (eps_r, mu_r = 1).  An incidence is a row
+``(kx, ky, kz, px, py, pz)``: unit propagation direction k and unit
+polarisation p (p . k = 0), amplitude 1, phase reference at the origin.
+
+Only geometry, block ids and directions are produced here; every
+integral-equation quantity is computed separately by the oracle and by the
+GPU library.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .blocks import octant_blocks, rcb_blocks
+from .meshes import cube, cylinder, icosphere
+
+ETA0 = 376.730313668  # free-space wave impedance (ohm); passed to both sides
+
+
+def sph_dir(theta, phi):
+    """Unit vector r(theta, phi) and the spherical unit vectors theta, phi."""
+    st, ct, sp, cp = np.sin(theta), np.cos(theta), np.sin(phi), np.cos(phi)
+    r = np.stack([st * cp, st * sp, ct], axis=-1)
+    th = np.stack([ct * cp, ct * sp, -st], axis=-1)
+    ph = np.stack([-sp, cp, np.zeros_like(sp)], axis=-1)
+    return r, th, ph
+
+
+def generating_set(theta_s=0.0, dtheta=30.0, n_theta=12, phi_s=0.0, dphi=30.0,
+                   n_phi=6, pols=("theta", "phi")) -> np.ndarray:
+    """Plane waves used to generate CBFs (eq. for the spherical sampling and
+    Table I): propagation along r(theta, phi) for theta = theta_s + i dtheta,
+    i < n_theta, phi = phi_s + j dphi, j < n_phi; polarisation theta-hat
+    and/or phi-hat.  Table I defaults give s = 12 * 6 * 2 = 144 waves.
+    Column order: theta index slowest, then phi, then polarisation.
+    """
+    rows = []
+    for i in range(n_theta):
+        for j in range(n_phi):
+            th = np.deg2rad(theta_s + i * dtheta)
+            ph = np.deg2rad(phi_s + j * dphi)
+            r, t, p = sph_dir(np.array(th), np.array(ph))
+            for pol in pols:
+                rows.append(np.concatenate([r, t if pol == "theta" else p]))
+    return np.array(rows, dtype=np.float64)
+
+
+def random_incidences(n: int, seed: int) -> np.ndarray:
+    """Arrival directions d = normalise(N(0, I3)); k = -d, p = theta-hat(d)."""
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    theta = np.arccos(np.clip(d[:, 2], -1, 1))
+    phi = np.arctan2(d[:, 1], d[:, 0])
+    _, th, _ = sph_dir(theta, phi)
+    return np.concatenate([-d, th], axis=1)
+
+
+@dataclass
+class Workload:
+    name: str
+    V: np.ndarray
+    T: np.ndarray
+    edge_block: np.ndarray
+    nblocks: int
+    eps_r: complex
+    mu_r: complex
+    inc: np.ndarray            # (nrhs, 6)
+    gen: np.ndarray            # (s, 6) CBF generating waves
+    delta_svd: float = 1e-3
+    k0: float = 2 * np.pi
+    eta0: float = ETA0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def nt(self):
+        return len(self.T)
+
+
+def sphere_c1() -> Workload:
+    """Dielectric sphere radius 0.5, eps_r 4, 320 triangles, octant cells,
+    one x-polarised plane wave travelling along -z."""
+    V, T = icosphere(2, 0.5)
+    return Workload("sphere320_er4", V, T, octant_blocks(V, T), 8, 4.0 + 0j, 1.0 + 0j,
+                    np.array([[0, 0, -1, 1, 0, 0]], dtype=np.float64), generating_set())
+
+
+def cube_c2(nrhs: int = 64) -> Workload:
+    """Dielectric cube edge 1, eps_r 2.5, 12x12 squares per face (1728 tri),
+    27 RCB cells, 64 seeded incidences."""
+    V, T = cube(12, 1.0)
+    return Workload("cube1728_er2.5", V, T, rcb_blocks(V, T, 27), 27, 2.5 + 0j, 1.0 + 0j,
+                    random_incidences(nrhs, 2111), generating_set())
+
+
+def sphere_c3() -> Workload:
+    """Lossy sphere radius 2, eps_r 4 - 0.1j, 5120 tri, 64 RCB cells."""
+    V, T = icosphere(4, 2.0)
+    return Workload("sphere5120_er4-0.1j", V, T, rcb_blocks(V, T, 64), 64, 4.0 - 0.1j, 1.0 + 0j,
+                    np.array([[0, 0, -1, 1, 0, 0]], dtype=np.float64), generating_set())
+
+
+def cylinder_c5() -> Workload:
+    """Cylinder r 1, h 6, eps_r 3, 19,968 tri, 96 RCB cells, 32 monostatic
+    theta-polarised incidences over theta = 45 deg * k / 31, phi = 0."""
+    V, T = cylinder(16, 88, 1.0, 6.0)
+    th = np.deg2rad(45.0 * np.arange(32) / 31.0)
+    r, t, _ = sph_dir(th, np.zeros_like(th))
+    inc = np.concatenate([-r, t], axis=1)
+    return Workload("cylinder19968_er3", V, T, rcb_blocks(V, T, 96), 96, 3.0 + 0j, 1.0 + 0j,
+                    inc, generating_set())
+
+
+def small_cylinder(K=2, n_h=4, nblocks=4, eps_r=3.0 + 0j) -> Workload:
+    V, T = cylinder(K, n_h, 0.3, 0.8)
+    return Workload(f"cyl{len(T)}", V, T, rcb_blocks(V, T, nblocks), nblocks, eps_r, 1.0 + 0j,
+                    random_incidences(3, 7), generating_set())
