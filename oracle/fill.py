@@ -128,7 +128,8 @@ def near_local(m: RWGMesh, k, p, q):
     else:
         # V(r) = int_Q g (r - r') summed over both media
         ksq = k[0] * k[0] + k[1] * k[1]
-        Vs = -(2.0 * pot["Gm3"] - 0.5 * ksq * (-pot["Vm1"])) / FOUR_PI
+        # int (r - r')/R = -Vm1
+        Vs = -(2.0 * pot["Gm3"] - 0.5 * ksq * pot["Vm1"]) / FOUR_PI
         grs = _gr(k[0], R) + _gr(k[1], R)
         Vk = Vs + Aq * np.einsum("kj,j,kji->ki", grs, w, diff)
         # int_Q grad'G x f_b = -(s_b l_b / 2Aq) V x (r - q_b)
