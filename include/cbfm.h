@@ -1,0 +1,265 @@
+/*
+ * cbfm.h - C ABI of the MI355X (gfx950) implementation of the characteristic
+ * basis function method with the Calderon multiplicative preconditioner for
+ * the PMCHWT formulation of scattering by a homogeneous dielectric body
+ * (Tanaka, Niino, Nishimura, arXiv 2111.11058).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Units: lengths in free-space wavelengths is customary but not required;
+ *   k0 and eta0 are passed explicitly.  Time convention e^{jwt}; Green's
+ *   function G_i = e^{-j k_i R} / (4 pi R) (paper Sec. II-A).
+ * - Exterior medium 1 is vacuum (k1 = k0, eta1 = eta0).  The interior medium
+ *   2 has relative eps_r and mu_r (complex; a lossy eps_r = e' - j e'' has
+ *   Im k2 < 0).  k2 = k0 sqrt(eps_r mu_r), eta2 = eta0 sqrt(mu_r/eps_r),
+ *   principal square roots.
+ * - RWG basis (paper Sec. II-B, Rao-Wilton-Glisson): edges are the unique
+ *   vertex pairs (min v, max v) sorted lexicographically ("canonical order");
+ *   T+ of an edge is the triangle whose counter-clockwise (outward) cycle
+ *   runs min -> max; f = (l / 2A+)(r - p+) on T+, (l / 2A-)(p- - r) on T-.
+ * - Operators (paper Sec. II-B, Galerkin entries of K_i and T_i):
+ *     [T_i]_mn = j k_i int int G_i [f_m . f_n - div f_m div f_n / k_i^2]
+ *     [K_i]_mn = int int f_m . (grad' G_i x f_n)     (gradient on the source)
+ *   With this reading of the operator signs the solved coefficient vector is
+ *   the negative of the physical currents; far fields and RCS are unchanged.
+ *   Z = [[K, -TE], [TH, K]] with K = K1 + K2, TE = eta1 T1 + eta2 T2,
+ *   TH = T1/eta1 + T2/eta2; unknowns [alpha^M ; alpha^J] (discretised PMCHWT
+ *   system and coefficient vector, Sec. II-B).
+ * - Quadrature: 7-point degree-5 rule on every triangle; near triangle pairs
+ *   (same triangle, a shared vertex, or centroid distance < 1.5 x the longer
+ *   of the two longest edges) use closed-form integration of the 1/R, R
+ *   (resp. 1/R^3, 1/R) parts on the source triangle; K of a coplanar near
+ *   pair is 0.
+ * - Complex numbers are interleaved (re, im): double2 for FP64, float2 for
+ *   FP32, matching torch.complex128 / torch.complex64 elements.
+ * - Matrices are row-major with an explicit leading dimension.  A block of
+ *   several vectors (right-hand sides) is stored vector after vector:
+ *   element i of vector c at [c * n + i].
+ * - Device pointers ("_dev") must point to device memory of the current HIP
+ *   device, large enough for the stated extent; host pointers ("_host") are
+ *   read or written during the call only.  All device work is enqueued on
+ *   ``stream`` (a hipStream_t; NULL = the default stream) and the call
+ *   returns without synchronising unless it says otherwise.  Calls that
+ *   return host results synchronise the stream.
+ * - Handles (cbfm_mesh, cbfm_cbf) own their device memory and are immutable
+ *   after creation; several streams may use one handle concurrently.
+ * - Errors: every call returns a cbfm_status; no C++ exception crosses the
+ *   ABI.  On CBFM_E_ARG / CBFM_E_MESH outputs are untouched.
+ *   cbfm_last_error() gives a thread-local message for the last failure.
+ */
+#ifndef CBFM_H
+#define CBFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cbfm_mesh_s* cbfm_mesh;
+typedef struct cbfm_cbf_s* cbfm_cbf;
+
+typedef enum {
+  CBFM_OK = 0,
+  CBFM_E_ARG = -1,     /* invalid argument (null pointer, size, range)      */
+  CBFM_E_MESH = -2,    /* not a closed, consistently oriented 2-manifold    */
+  CBFM_E_NOMEM = -3,   /* device or host allocation failed                  */
+  CBFM_E_HIP = -4,     /* a HIP / rocSOLVER call failed                     */
+  CBFM_E_NOCONV = -5,  /* GMRES reached max_iter; outputs hold the iterate  */
+  CBFM_E_RANK = -6,    /* a cell kept no CBF (L_m = 0)                      */
+  CBFM_E_STATE = -7    /* handles of different meshes mixed                 */
+} cbfm_status;
+
+typedef enum { CBFM_FP64 = 0, CBFM_FP32 = 1 } cbfm_precision;
+
+/* Output layout of cbfm_fill_pmchwt: three nrow x ncol complex matrices,
+   matrix after matrix. */
+enum {
+  CBFM_LAYOUT_MEDIA3 = 0, /* [K1 + K2, T1, T2]                                */
+  CBFM_LAYOUT_OPS3 = 1    /* [K, TE = eta1 T1 + eta2 T2, TH = T1/eta1 + T2/eta2] */
+};
+
+/* Interior medium and free-space constants. */
+typedef struct {
+  double k0;            /* free-space wavenumber                      */
+  double eta0;          /* free-space wave impedance                  */
+  double eps_re, eps_im;/* interior relative permittivity             */
+  double mu_re, mu_im;  /* interior relative permeability             */
+} cbfm_medium;
+
+/* Thread-local description of the last error (never NULL). */
+const char* cbfm_last_error(void);
+
+/* ABI version (incremented on incompatible change). */
+int32_t cbfm_version(void);
+
+/* -------------------------------------------------------------- timers ---
+ * Opt-in kernel timing for measurement: when enabled, the library records a
+ * pair of HIP events on the launch stream around each launch of a named
+ * kernel family and accumulates the elapsed times when they are read.
+ * Names: "fill_regular", "fill_near", "assemble", "gemm".
+ * cbfm_timer_enable(1) enables and clears all timers, (0) disables.
+ * cbfm_timer_read synchronises the recorded events and returns the number
+ * of launches and their total duration in milliseconds (CBFM_E_ARG for an
+ * unknown name).                                                           */
+cbfm_status cbfm_timer_enable(int32_t on);
+cbfm_status cbfm_timer_read(const char* name, int64_t* launches, double* total_ms);
+
+/* ---------------------------------------------------------------- mesh ---
+ * cbfm_mesh_load: validate a closed triangle mesh and build the RWG tables
+ * (paper Sec. II-B basis expansion; Sec. III-A cell division: every edge
+ * belongs to exactly one cell).
+ *   xyz_host   nv x 3 vertex coordinates (double)
+ *   tri_host   nt x 3 vertex indices (int32), counter-clockwise seen from
+ *              outside
+ *   edge_block_host  ne entries in canonical edge order giving each edge's
+ *              cell in [0, nblocks), or NULL for a single cell (nblocks is
+ *              then ignored)
+ * Fails with CBFM_E_MESH if an edge is not shared by exactly two triangles
+ * with opposite directions, a triangle is degenerate, the enclosed volume is
+ * not positive, or a cell is empty.  Uploads the tables to the current
+ * device (synchronous).  The handle is freed with cbfm_mesh_free.
+ */
+cbfm_status cbfm_mesh_load(const double* xyz_host, int64_t nv, const int32_t* tri_host,
+                           int64_t nt, const int32_t* edge_block_host, int32_t nblocks,
+                           cbfm_mesh* out);
+
+/* Sizes: RWG count ne, triangle count nt, cell count, near-pair count
+   (any pointer may be NULL). */
+cbfm_status cbfm_mesh_info(cbfm_mesh m, int64_t* ne, int64_t* nt, int32_t* nblocks,
+                           int64_t* n_near);
+
+/* Canonical edge table: ne x 2 vertex ids (int32, host), or NULL; the
+   cell of each edge (int32, host), or NULL. */
+cbfm_status cbfm_mesh_edges(cbfm_mesh m, int32_t* edge_vertices_host, int32_t* edge_block_host);
+
+void cbfm_mesh_free(cbfm_mesh m);
+
+/* cbfm_mesh_analyze: the host-side part of cbfm_mesh_load only (validation,
+   canonical edges, near-pair list), touching no device, e.g. to check a mesh
+   on a machine without a GPU.  Same arguments and failures as
+   cbfm_mesh_load.  Outputs (each may be NULL): ne; edges_host (ne x 2,
+   capacity 3 nt / 2 rows); tri_edge_host and tri_sign_host (nt x 3: edge
+   and RWG sign (+1 on T+, -1 on T-) of the local function whose free vertex
+   is vertex a of the triangle); n_near; near_host (n_near x 3: P, Q,
+   coplanar; capacity given by near_cap rows, CBFM_E_ARG if too small).    */
+cbfm_status cbfm_mesh_analyze(const double* xyz_host, int64_t nv, const int32_t* tri_host,
+                              int64_t nt, const int32_t* edge_block_host, int32_t nblocks,
+                              int64_t* ne, int32_t* edges_host, int32_t* tri_edge_host,
+                              int32_t* tri_sign_host, int64_t* n_near, int32_t* near_host,
+                              int64_t near_cap);
+
+/* ---------------------------------------------------------------- fill ---
+ * cbfm_fill_pmchwt: Galerkin matrices of the PMCHWT operators (paper
+ * Sec. II-B, entries [K_i]_mn, [T_i]_mn and the block matrix Z) for test
+ * RWGs row0 .. row0+nrow-1 and trial RWGs col0 .. col0+ncol-1 (canonical
+ * order).
+ *   precision  CBFM_FP64: arithmetic and output in double (out: double2);
+ *              CBFM_FP32: regular pairs in float, near pairs in double,
+ *              output float2.
+ *   layout     CBFM_LAYOUT_MEDIA3 or CBFM_LAYOUT_OPS3 (see above)
+ *   out_dev    3 matrices, matrix o element (r, c) at
+ *              out_dev[(o * nrow + r) * ld + c]; ld >= ncol
+ * Uses stream-ordered scratch of about 3 * 9 * ntr * ntc complex elements,
+ * ntr/ntc the triangles touching the row/column ranges.
+ */
+cbfm_status cbfm_fill_pmchwt(cbfm_mesh m, const cbfm_medium* med, int32_t precision,
+                             int64_t row0, int64_t nrow, int64_t col0, int64_t ncol,
+                             int32_t layout, void* out_dev, int64_t ld, void* stream);
+
+/* cbfm_rhs: tested incident plane waves (paper Sec. II-B, v^E and v^H):
+   v = [v^E ; v^H] with v^E_m = int f_m . E_inc, v^H_m = -int f_m . H_inc,
+   E_inc = p exp(-j k0 k . r), H_inc = k x E_inc / eta0, 7-point rule.
+     inc_host  nrhs x 6 doubles (kx, ky, kz, px, py, pz), unit k, unit p
+     v_dev     nrhs x 2ne double2, vector after vector                      */
+cbfm_status cbfm_rhs(cbfm_mesh m, const cbfm_medium* med, const double* inc_host, int64_t nrhs,
+                     void* v_dev, void* stream);
+
+/* ---------------------------------------------------------------- CBFs ---
+ * cbfm_build_cbf: primary CBFs with dual orthogonalisation (paper Sec.
+ * III-A eq. of the primary CBFs, Sec. III-B eqs. of G_m, G'_m, the SVD and
+ * C^M = J^M U_L, C^J = J^J V_L): per cell, Z_mm J_m = V_m for the n_gen
+ * generating waves (LU), G'_m = (J^M)^H G_m J^J, SVD, keep sigma_i/sigma_1 >=
+ * delta_svd (at most max_L if max_L > 0).  FP64 throughout.
+ * Synchronises the stream (the kept counts L_m are host data).
+ * Returns CBFM_E_RANK if a cell keeps no CBF.                              */
+typedef struct {
+  const double* gen_host; /* n_gen x 6 (k, p) generating plane waves */
+  int32_t n_gen;
+  double delta_svd;
+  int32_t max_L;          /* 0 = no cap */
+} cbfm_cbf_params;
+
+cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_params* prm,
+                           void* stream, cbfm_cbf* out);
+
+/* cbfm_cbf_import: wrap given CBFs (for parity checks with an external
+   computation).  L_host: per-cell counts; CM_host / CJ_host: cell after cell,
+   each N_m x L_m row-major double2 with rows in canonical edge order of the
+   cell's edges; sigma_host: sum(L) doubles (cell after cell).              */
+cbfm_status cbfm_cbf_import(cbfm_mesh m, const int32_t* L_host, const void* CM_host,
+                            const void* CJ_host, const double* sigma_host, void* stream,
+                            cbfm_cbf* out);
+
+/* Sizes: total N_CBF = 2 sum L, per-cell L (nblocks int32, or NULL), kept
+   singular values (sum L doubles, cell after cell, or NULL).               */
+cbfm_status cbfm_cbf_info(cbfm_cbf c, int64_t* n_cbf, int32_t* L_host, double* sigma_host);
+
+/* Copy the CBF coefficients to the host in the cbfm_cbf_import layout.     */
+cbfm_status cbfm_cbf_export(cbfm_cbf c, void* CM_host, void* CJ_host);
+
+void cbfm_cbf_free(cbfm_cbf c);
+
+/* ---------------------------------------------------------- projection ---
+ * cbfm_project: reduced matrix Z_r = (C^JM)^H Z C^MJ (paper Sec. III-C,
+ * outer CBFM equation): rows [J-test CBFs of cells 1..M ; M-test CBFs],
+ * columns [M-trial CBFs ; J-trial CBFs], each group cell after cell.
+ * The PMCHWT fill is computed inside (precision as in cbfm_fill_pmchwt) and
+ * projected on the matrix cores; Z is held only in stream-ordered scratch.
+ *   Zr_dev  N_CBF x N_CBF double2, row-major, ldz >= N_CBF                 */
+cbfm_status cbfm_project(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, int32_t precision,
+                         void* Zr_dev, int64_t ldz, void* stream);
+
+/* ----------------------------------------------------------------- CMP ---
+ * cbfm_cmp_apply: x = (G^CBF)^{-1} y with G^CBF = (C^JM)^H G_ffff C^MJ
+ * (paper Sec. III-C, CBF Gram matrix and inner CBFM equation), exact
+ * (LU factors kept in the cbfm_cbf handle, formed on first use).
+ *   y_dev, x_dev  nrhs x N_CBF double2, vector after vector (may alias)    */
+cbfm_status cbfm_cmp_apply(cbfm_cbf c, int64_t nrhs, const void* y_dev, void* x_dev,
+                           void* stream);
+
+/* --------------------------------------------------------------- solve ---
+ * cbfm_solve: for each incidence, v_r = (C^JM)^H v, right-preconditioned
+ * GMRES on Z_r (G^CBF)^{-1} y = v_r (x0 = 0, restart, stop at relative
+ * residual <= tol), j_CBF = (G^CBF)^{-1} y, j = C^MJ j_CBF (paper Sec. III-C
+ * outer/inner equations and the current reconstruction), then RCS (paper's
+ * monostatic definition, Knott): with N = int J e^{jk0 r.r'}, L = int M
+ * e^{jk0 r.r'}, sigma = k0^2/(4 pi) |eta0 N_perp - r x L|^2 (|E0| = 1).
+ *   inc_host   nrhs x 6 (k, p)
+ *   Zr_dev     from cbfm_project, ldz
+ *   j_dev      nrhs x 2ne double2 output [alpha^M ; alpha^J] (or NULL)
+ *   iters_host, relres_host   nrhs outputs (or NULL)
+ *   dirs_host  ndir x 3 unit observation directions -> rcs_host nrhs x ndir
+ *              total bistatic sigma; NULL -> monostatic co-polarised sigma
+ *              (direction -k, component along p), rcs_host nrhs
+ *   use_cmp    1: right preconditioner (G^CBF)^{-1}; 0: none (y = j_CBF)
+ * Synchronises the stream.  CBFM_E_NOCONV if some RHS did not reach tol.  */
+typedef struct {
+  double tol;
+  int32_t max_iter;
+  int32_t restart;
+  int32_t use_cmp;
+} cbfm_solver_params;
+
+cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, const void* Zr_dev,
+                       int64_t ldz, const double* inc_host, int64_t nrhs,
+                       const cbfm_solver_params* prm, void* j_dev, int32_t* iters_host,
+                       double* relres_host, const double* dirs_host, int64_t ndir,
+                       double* rcs_host, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CBFM_H */

@@ -17,6 +17,7 @@ from __future__ import annotations
 from dataclasses import dataclass
 
 import numpy as np
+import scipy.linalg
 
 from . import quadrature as qd
 from .excitation import rhs
@@ -72,7 +73,9 @@ def primary_currents(m: RWGMesh, Kop, TE, TH, edges, gen, k0, eta0, V=None):
 def dual_cbfs(JM, JJ, Gm, delta_svd):
     """SVD of G'_m = JM^H Gm JJ, truncation, C^M = JM U_L, C^J = JJ V_L."""
     Gp = JM.conj().T @ Gm @ JJ
-    U, S, Vh = np.linalg.svd(Gp)
+    # LAPACK's QR-iteration SVD (gesvd): robust on the numerically
+    # rank-deficient G'_m (rank <= N_m < s)
+    U, S, Vh = scipy.linalg.svd(Gp, lapack_driver="gesvd")
     L = int(np.count_nonzero(S / S[0] >= delta_svd))
     return JM @ U[:, :L], JJ @ Vh.conj().T[:, :L], S[:L], S
 

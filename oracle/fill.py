@@ -189,3 +189,40 @@ def combine(Kop, T1, T2, eta):
 def assemble_Z(Kop, TE, TH):
     """Z = [[K, -TE], [TH, K]] acting on [alpha^M; alpha^J]."""
     return np.block([[Kop, -TE], [TH, Kop]])
+
+
+def fill_rows(m: RWGMesh, k, rows, chunk=4096):
+    """Rows ``rows`` (RWG ids) of K (=K1+K2), T1, T2, each (len(rows), ne),
+    computing only the triangle pairs those rows need."""
+    rows = np.asarray(rows)
+    tris = np.unique(np.concatenate([m.tplus[rows], m.tminus[rows]]))
+    near = near_pairs(m)
+    near_set = set(map(tuple, near.tolist()))
+    nt = m.nt
+    K = np.zeros((len(tris), nt, 3, 3), dtype=np.complex128)
+    T = np.zeros((2, len(tris), nt, 3, 3), dtype=np.complex128)
+    PP, QQ, II = [], [], []
+    for i, p in enumerate(tris):
+        for q in range(nt):
+            if (p, q) in near_set:
+                Kc, Tc = near_local(m, k, p, q)
+                K[i, q] = Kc
+                T[:, i, q] = Tc
+            else:
+                PP.append(p)
+                QQ.append(q)
+                II.append(i)
+    PP, QQ, II = map(np.asarray, (PP, QQ, II))
+    for s in range(0, len(PP), chunk):
+        Kc, Tc = regular_local(m, k, PP[s:s + chunk], QQ[s:s + chunk])
+        K[II[s:s + chunk], QQ[s:s + chunk]] = Kc
+        T[:, II[s:s + chunk], QQ[s:s + chunk]] = Tc
+    pos = {int(t): i for i, t in enumerate(tris)}
+    out = [np.zeros((len(rows), m.ne), dtype=np.complex128) for _ in range(3)]
+    for r, e in enumerate(rows):
+        for tp, ap in ((m.tplus[e], m.aplus[e]), (m.tminus[e], m.aminus[e])):
+            i = pos[int(tp)]
+            for X, Y in zip(out, (K, T[0], T[1])):
+                # Y[i, q, ap, b] -> column tri_edge[q, b]
+                np.add.at(X[r], m.tri_edge.ravel(), Y[i, :, ap, :].ravel())
+    return out

@@ -1,0 +1,342 @@
+"""Thin ctypes binding of libcbfm (include/cbfm.h).
+
+Argument marshalling only: every computation happens in the HIP library.
+PyTorch supplies device memory (tensors passed by ``data_ptr``) and streams
+(``torch.cuda.current_stream().cuda_stream``).  Importing this module does not
+load the library; the first call does, and raises if it is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcbfm.so")
+
+FP64, FP32 = 0, 1
+LAYOUT_MEDIA3, LAYOUT_OPS3 = 0, 1
+
+STATUS = {0: "OK", -1: "E_ARG", -2: "E_MESH", -3: "E_NOMEM", -4: "E_HIP", -5: "E_NOCONV",
+          -6: "E_RANK", -7: "E_STATE"}
+
+
+class CBFMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Medium(C.Structure):
+    _fields_ = [("k0", C.c_double), ("eta0", C.c_double), ("eps_re", C.c_double),
+                ("eps_im", C.c_double), ("mu_re", C.c_double), ("mu_im", C.c_double)]
+
+    @classmethod
+    def make(cls, k0, eta0, eps_r, mu_r=1.0):
+        e, m = complex(eps_r), complex(mu_r)
+        return cls(float(k0), float(eta0), e.real, e.imag, m.real, m.imag)
+
+
+class CbfParams(C.Structure):
+    _fields_ = [("gen_host", C.POINTER(C.c_double)), ("n_gen", C.c_int32),
+                ("delta_svd", C.c_double), ("max_L", C.c_int32)]
+
+
+class SolverParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32),
+                ("use_cmp", C.c_int32)]
+
+
+_lib = None
+_P = C.c_void_p
+_I64 = C.c_int64
+_I32 = C.c_int32
+
+
+def lib():
+    """Load libcbfm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2111_11058_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    sig = {
+        "cbfm_last_error": (C.c_char_p, []),
+        "cbfm_timer_enable": (_I32, [_I32]),
+        "cbfm_timer_read": (_I32, [C.c_char_p, C.POINTER(_I64), C.POINTER(C.c_double)]),
+        "cbfm_version": (_I32, []),
+        "cbfm_mesh_load": (_I32, [_P, _I64, _P, _I64, _P, _I32, C.POINTER(_P)]),
+        "cbfm_mesh_info": (_I32, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32), C.POINTER(_I64)]),
+        "cbfm_mesh_edges": (_I32, [_P, _P, _P]),
+        "cbfm_mesh_free": (None, [_P]),
+        "cbfm_mesh_analyze": (_I32, [_P, _I64, _P, _I64, _P, _I32, C.POINTER(_I64), _P, _P, _P,
+                                     C.POINTER(_I64), _P, _I64]),
+        "cbfm_fill_pmchwt": (_I32, [_P, C.POINTER(Medium), _I32, _I64, _I64, _I64, _I64, _I32, _P, _I64, _P]),
+        "cbfm_rhs": (_I32, [_P, C.POINTER(Medium), _P, _I64, _P, _P]),
+        "cbfm_build_cbf": (_I32, [_P, C.POINTER(Medium), C.POINTER(CbfParams), _P, C.POINTER(_P)]),
+        "cbfm_cbf_import": (_I32, [_P, _P, _P, _P, _P, _P, C.POINTER(_P)]),
+        "cbfm_cbf_info": (_I32, [_P, C.POINTER(_I64), _P, _P]),
+        "cbfm_cbf_export": (_I32, [_P, _P, _P]),
+        "cbfm_cbf_free": (None, [_P]),
+        "cbfm_project": (_I32, [_P, C.POINTER(Medium), _P, _I32, _P, _I64, _P]),
+        "cbfm_cmp_apply": (_I32, [_P, _I64, _P, _P, _P]),
+        "cbfm_solve": (_I32, [_P, C.POINTER(Medium), _P, _P, _I64, _P, _I64, C.POINTER(SolverParams), _P,
+                              _P, _P, _P, _I64, _P, _P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(code):
+    if code != 0:
+        raise CBFMError(code, lib().cbfm_last_error().decode())
+    return code
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, numel=None, what="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{what} has {t.numel()} elements, need {numel}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def timer_enable(on=True):
+    """Enable (and clear) or disable the library's per-kernel event timers."""
+    _check(lib().cbfm_timer_enable(int(bool(on))))
+
+
+def timer_read(name):
+    """(launches, total milliseconds) recorded for kernel family ``name``."""
+    n, ms = _I64(), C.c_double()
+    _check(lib().cbfm_timer_read(name.encode(), C.byref(n), C.byref(ms)))
+    return n.value, ms.value
+
+
+def mesh_analyze(V, T, edge_block=None, nblocks=None):
+    """Host-only mesh validation (cbfm_mesh_analyze): returns (edges,
+    tri_edge, tri_sign, near) with near rows (P, Q, coplanar).  Needs no
+    GPU."""
+    L = lib()
+    V, pV = _host(V, np.float64)
+    T, pT = _host(T, np.int32)
+    if edge_block is not None:
+        eb, peb = _host(edge_block, np.int32)
+        nb = int(nblocks if nblocks is not None else eb.max() + 1)
+    else:
+        peb, nb = None, 1
+    ne, nn = _I64(), _I64()
+    _check(L.cbfm_mesh_analyze(pV, len(V), pT, len(T), peb, nb, C.byref(ne), None, None, None, C.byref(nn),
+                               None, 0))
+    E = np.zeros((ne.value, 2), np.int32)
+    TE = np.zeros((len(T), 3), np.int32)
+    TS = np.zeros((len(T), 3), np.int32)
+    N = np.zeros((nn.value, 3), np.int32)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    _check(L.cbfm_mesh_analyze(pV, len(V), pT, len(T), peb, nb, C.byref(ne), ptr(E), ptr(TE), ptr(TS), C.byref(nn),
+                               ptr(N), nn.value))
+    return E, TE, TS, N
+
+
+class Mesh:
+    """Handle of a loaded mesh (cbfm_mesh)."""
+
+    def __init__(self, V, T, edge_block=None, nblocks=None):
+        L = lib()
+        V, pV = _host(V, np.float64)
+        T, pT = _host(T, np.int32)
+        if edge_block is not None:
+            eb, peb = _host(edge_block, np.int32)
+            nb = int(nblocks if nblocks is not None else eb.max() + 1)
+        else:
+            peb, nb = None, 1
+        h = C.c_void_p()
+        _check(L.cbfm_mesh_load(pV, len(V), pT, len(T), peb, nb, C.byref(h)))
+        self._h = h
+        ne, nt, nbk, nn = _I64(), _I64(), _I32(), _I64()
+        _check(L.cbfm_mesh_info(h, C.byref(ne), C.byref(nt), C.byref(nbk), C.byref(nn)))
+        self.ne, self.nt, self.nblocks, self.n_near = ne.value, nt.value, nbk.value, nn.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def edges(self):
+        ev = np.zeros((self.ne, 2), np.int32)
+        eb = np.zeros(self.ne, np.int32)
+        _check(lib().cbfm_mesh_edges(self._h, ev.ctypes.data_as(C.c_void_p), eb.ctypes.data_as(C.c_void_p)))
+        return ev, eb
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cbfm_mesh_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fill_pmchwt(mesh: Mesh, medium: Medium, out, precision=FP64, layout=LAYOUT_MEDIA3,
+                row0=0, nrow=None, col0=0, ncol=None, ld=None, stream=None):
+    """cbfm_fill_pmchwt into ``out`` (3 x nrow x ld complex tensor)."""
+    import torch
+    nrow = mesh.ne - row0 if nrow is None else nrow
+    ncol = mesh.ne - col0 if ncol is None else ncol
+    ld = ncol if ld is None else ld
+    dt = torch.complex128 if precision == FP64 else torch.complex64
+    p = _dev(out, dt, 3 * nrow * ld, "out")
+    _check(lib().cbfm_fill_pmchwt(mesh.handle, C.byref(medium), precision, row0, nrow, col0, ncol,
+                                  layout, p, ld, _stream(stream)))
+    return out
+
+
+def rhs(mesh: Mesh, medium: Medium, inc, out, stream=None):
+    """cbfm_rhs: ``out`` is (nrhs, 2 ne) complex128."""
+    import torch
+    inc, pi = _host(inc, np.float64)
+    inc = inc.reshape(-1, 6)
+    p = _dev(out, torch.complex128, len(inc) * 2 * mesh.ne, "out")
+    _check(lib().cbfm_rhs(mesh.handle, C.byref(medium), pi, len(inc), p, _stream(stream)))
+    return out
+
+
+class CBF:
+    """Handle of a CBF set (cbfm_cbf)."""
+
+    def __init__(self, h, mesh):
+        self._h = h
+        self.mesh = mesh
+        n = _I64()
+        L = np.zeros(mesh.nblocks, np.int32)
+        _check(lib().cbfm_cbf_info(h, C.byref(n), L.ctypes.data_as(C.c_void_p), None))
+        self.n_cbf = n.value
+        self.L = L
+        sig = np.zeros(int(L.sum()))
+        _check(lib().cbfm_cbf_info(h, None, None, sig.ctypes.data_as(C.c_void_p)))
+        self.sigma = sig
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self):
+        """(CM, CJ) as lists of per-cell (N_m, L_m) complex arrays."""
+        ev, eb = self.mesh.edges()
+        N = np.bincount(eb, minlength=self.mesh.nblocks)
+        tot = int((N * self.L).sum())
+        CM = np.zeros(tot, np.complex128)
+        CJ = np.zeros(tot, np.complex128)
+        _check(lib().cbfm_cbf_export(self._h, CM.ctypes.data_as(C.c_void_p), CJ.ctypes.data_as(C.c_void_p)))
+        outM, outJ, o = [], [], 0
+        for n, l in zip(N, self.L):
+            outM.append(CM[o:o + n * l].reshape(n, l))
+            outJ.append(CJ[o:o + n * l].reshape(n, l))
+            o += n * l
+        return outM, outJ
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cbfm_cbf_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_cbf(mesh: Mesh, medium: Medium, gen, delta_svd=1e-3, max_L=0, stream=None) -> CBF:
+    gen, _ = _host(gen, np.float64)
+    gen = gen.reshape(-1, 6)
+    prm = CbfParams(gen.ctypes.data_as(C.POINTER(C.c_double)), len(gen), float(delta_svd), int(max_L))
+    h = C.c_void_p()
+    _check(lib().cbfm_build_cbf(mesh.handle, C.byref(medium), C.byref(prm), _stream(stream), C.byref(h)))
+    return CBF(h, mesh)
+
+
+def cbf_import(mesh: Mesh, CM_cells, CJ_cells, sigma_cells, stream=None) -> CBF:
+    L = np.array([c.shape[1] for c in CM_cells], np.int32)
+    CM = np.ascontiguousarray(np.concatenate([np.asarray(c, np.complex128).ravel() for c in CM_cells]))
+    CJ = np.ascontiguousarray(np.concatenate([np.asarray(c, np.complex128).ravel() for c in CJ_cells]))
+    sg = np.ascontiguousarray(np.concatenate([np.asarray(s, np.float64) for s in sigma_cells]))
+    h = C.c_void_p()
+    _check(lib().cbfm_cbf_import(mesh.handle, L.ctypes.data_as(C.c_void_p), CM.ctypes.data_as(C.c_void_p),
+                                 CJ.ctypes.data_as(C.c_void_p), sg.ctypes.data_as(C.c_void_p),
+                                 _stream(stream), C.byref(h)))
+    return CBF(h, mesh)
+
+
+def project(mesh: Mesh, medium: Medium, cbf: CBF, out, precision=FP64, ldz=None, stream=None):
+    import torch
+    n = cbf.n_cbf
+    ldz = n if ldz is None else ldz
+    p = _dev(out, torch.complex128, n * ldz, "Zr")
+    _check(lib().cbfm_project(mesh.handle, C.byref(medium), cbf.handle, precision, p, ldz, _stream(stream)))
+    return out
+
+
+def cmp_apply(cbf: CBF, y, x, stream=None):
+    import torch
+    nrhs = y.numel() // cbf.n_cbf
+    py = _dev(y, torch.complex128, nrhs * cbf.n_cbf, "y")
+    px = _dev(x, torch.complex128, nrhs * cbf.n_cbf, "x")
+    _check(lib().cbfm_cmp_apply(cbf.handle, nrhs, py, px, _stream(stream)))
+    return x
+
+
+def solve(mesh: Mesh, medium: Medium, cbf: CBF, Zr, inc, tol=1e-6, max_iter=1000, restart=100,
+          use_cmp=True, j_out=None, dirs=None, ldz=None, stream=None, raise_noconv=False):
+    """cbfm_solve.  Returns dict(iters, relres, rcs, status)."""
+    import torch
+    inc, pi = _host(inc, np.float64)
+    inc = inc.reshape(-1, 6)
+    nrhs = len(inc)
+    n = cbf.n_cbf
+    ldz = n if ldz is None else ldz
+    pz = _dev(Zr, torch.complex128, n * ldz, "Zr")
+    pj = _dev(j_out, torch.complex128, nrhs * 2 * mesh.ne, "j") if j_out is not None else None
+    iters = np.zeros(nrhs, np.int32)
+    relres = np.zeros(nrhs)
+    if dirs is not None:
+        dirs, pd = _host(dirs, np.float64)
+        dirs = dirs.reshape(-1, 3)
+        nd = len(dirs)
+        rcs = np.zeros((nrhs, nd))
+    else:
+        pd, nd = None, 0
+        rcs = np.zeros(nrhs)
+    prm = SolverParams(float(tol), int(max_iter), int(restart), int(bool(use_cmp)))
+    code = lib().cbfm_solve(mesh.handle, C.byref(medium), cbf.handle, pz, ldz, pi, nrhs, C.byref(prm), pj,
+                            iters.ctypes.data_as(C.c_void_p), relres.ctypes.data_as(C.c_void_p), pd, nd,
+                            rcs.ctypes.data_as(C.c_void_p), _stream(stream))
+    if code != 0 and (code != -5 or raise_noconv):
+        _check(code)
+    return dict(iters=iters, relres=relres, rcs=rcs, status=STATUS.get(code, code))

@@ -1,0 +1,32 @@
+// CBF handle and the Calderon preconditioner (see cbf.hip).
+#pragma once
+
+#include <rocblas/rocblas.h>
+
+#include <mutex>
+
+#include "internal.h"
+
+struct cbfm_cbf_s {
+  const cbfm_mesh_s* mesh = nullptr;
+  std::vector<int32_t> L;      // kept CBFs per cell (per current)
+  std::vector<int64_t> off;    // prefix sums of L (nblocks + 1)
+  std::vector<int64_t> coff;   // element offsets of cell blocks in CM / CJ (nblocks + 1)
+  int64_t NL = 0;              // sum of L
+  cbfm::DevBuf CM, CJ;         // per cell N_b x L_b row-major double2, cell after cell
+  std::vector<double> sigma;   // kept singular values, cell after cell
+  cbfm::DevBuf d_L, d_off, d_coff, d_cell_off, d_edge_block;
+  // LU factors of B = (C^M)^H G C^J, formed on first use
+  std::mutex mu;
+  bool factored = false;
+  cbfm::DevBuf Bmat, ipiv;
+};
+
+namespace cbfm {
+
+rocblas_handle blas_handle(hipStream_t s);
+std::mutex& blas_mutex();
+// x <- (G^CBF)^{-1} x in place, nrhs vectors of length 2 NL
+void cmp_apply_dev(cbfm_cbf_s* c, int64_t nrhs, double2* x, hipStream_t s);
+
+}  // namespace cbfm

@@ -1,0 +1,118 @@
+// Batched, variable-size complex double GEMM on the gfx950 matrix cores:
+//   C = alpha * op(A) * op(B) (+ C if accumulate)
+// op in {N, T (transpose), C (conjugate transpose), R (conjugate)}, all
+// matrices row-major complex double with leading dimensions.
+//
+// One wavefront computes one 16 x 16 tile of C with v_mfma_f64_16x16x4_f64
+// (real): for each group of 16 k it does 4 x 4 MFMAs, the four real
+// products Ar*Br, -Ai*Bi, Ar*Bi, Ai*Br.  Lane L holds A[L % 16][k] and
+// B[k][L % 16] for k = k0 + 4 (L / 16) + t, t = 0..3 (any assignment of the
+// 16 k values to (slot, step) works as long as A and B agree), which lets
+// each lane load 4 consecutive elements when op(A) is not transposed.
+// The accumulator element r of lane L is C[4 r + L / 16][L % 16] (measured
+// on gfx950 with indexed operands: rows are interleaved across the four
+// lane groups).
+#include "internal.h"
+#include "gemm.h"
+
+namespace cbfm {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double2 ld_op(const double2* __restrict__ X, int64_t ld, int op, int64_t i, int64_t k,
+                                         int64_t rows, int64_t cols) {
+  // element op(X)[i][k]; rows x cols is the shape of op(X); zero outside
+  if (i >= rows || k >= cols) return make_double2(0.0, 0.0);
+  double2 v;
+  if (op == OP_N || op == OP_R)
+    v = X[i * ld + k];
+  else
+    v = X[k * ld + i];
+  if (op == OP_C || op == OP_R) v.y = -v.y;
+  return v;
+}
+
+__global__ void __launch_bounds__(256) zgemm_batched_kernel(const GemmDesc* __restrict__ desc, int ndesc,
+                                                            int64_t total_tiles) {
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= total_tiles) return;
+  // descriptor holding this tile (tile_start ascending)
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].tile_start <= tile)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const GemmDesc d = desc[lo];
+  const int64_t t = tile - d.tile_start;
+  const int64_t ntn = (d.N + 15) / 16;
+  const int64_t m0 = (t / ntn) * 16, n0 = (t % ntn) * 16;
+  const int64_t ia = m0 + (lane & 15);  // row of op(A) this lane loads
+  const int64_t jb = n0 + (lane & 15);  // column of op(B) this lane loads
+  const int slot = lane >> 4;
+  dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+  for (int64_t k0 = 0; k0 < d.K; k0 += 16) {
+    double2 a[4], b[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t k = k0 + 4 * slot + s;
+      a[s] = ld_op(d.A, d.lda, d.opA, ia, k, d.M, d.K);
+      b[s] = ld_op(d.B, d.ldb, d.opB, k, jb, d.K, d.N);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].x, b[s].x, cr, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[s].y, b[s].y, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].x, b[s].y, ci, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].y, b[s].x, ci, 0, 0, 0);
+    }
+  }
+  const int64_t col = n0 + (lane & 15);
+  if (col >= d.N) return;
+  // (transposed stores write 4 rows of one column per lane; plain stores one
+  // column of 4 rows, 16 lanes side by side)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = m0 + 4 * r + slot;
+    if (row < d.M) {
+      const double xr = cr[r], xi = ci[r];
+      double2 v = make_double2(d.alpha_re * xr - d.alpha_im * xi, d.alpha_re * xi + d.alpha_im * xr);
+      double2* p = d.transC ? d.C + col * d.ldc + row : d.C + row * d.ldc + col;
+      if (d.accumulate) {
+        const double2 o = *p;
+        v.x += o.x;
+        v.y += o.y;
+      }
+      *p = v;
+    }
+  }
+}
+
+void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s) {
+  if (descs.empty()) return;
+  int64_t tiles = 0;
+  std::vector<GemmDesc> live;
+  for (GemmDesc d : descs) {
+    CBFM_REQUIRE(d.M >= 0 && d.N >= 0 && d.K >= 0, CBFM_E_ARG, "negative GEMM size");
+    if (d.M == 0 || d.N == 0) continue;
+    d.tile_start = tiles;
+    tiles += ((d.M + 15) / 16) * ((d.N + 15) / 16);
+    live.push_back(d);
+  }
+  if (live.empty()) return;
+  Scratch dev(live.size() * sizeof(GemmDesc), s);
+  CBFM_HIP(hipMemcpyAsync(dev.p, live.data(), live.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
+  const int64_t blocks = (tiles + 3) / 4;
+  TimedLaunch tl(T_GEMM, s);
+  hipLaunchKernelGGL(zgemm_batched_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dev.as<GemmDesc>(),
+                     (int)live.size(), tiles);
+  CBFM_HIP(hipGetLastError());
+  // the descriptor staging buffer is host memory of this frame
+  CBFM_HIP(hipStreamSynchronize(s));
+  (void)tl;
+}
+
+}  // namespace cbfm

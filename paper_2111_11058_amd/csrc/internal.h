@@ -1,0 +1,196 @@
+// Internal structures of libcbfm (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cbfm.h"
+
+namespace cbfm {
+
+void set_error(const std::string& msg);
+
+struct Error {
+  cbfm_status code;
+  std::string msg;
+};
+
+#define CBFM_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::cbfm::Error{CBFM_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define CBFM_REQUIRE(cond, code, msg)                 \
+  do {                                                \
+    if (!(cond)) throw ::cbfm::Error{code, (msg)};    \
+  } while (0)
+
+// Run a body, translating exceptions into a status.
+template <typename F>
+cbfm_status guarded(F&& f) {
+  try {
+    f();
+    return CBFM_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return CBFM_E_NOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return CBFM_E_HIP;
+  }
+}
+
+// Device buffer owned by a handle.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) return;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error{CBFM_E_NOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed"};
+    }
+    bytes = n;
+  }
+  template <typename T>
+  void upload(const std::vector<T>& v) {
+    alloc(v.size() * sizeof(T));
+    if (!v.empty()) CBFM_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// Stream-ordered scratch released at scope exit (hipFreeAsync on the stream).
+struct Scratch {
+  void* p = nullptr;
+  hipStream_t s = nullptr;
+  Scratch(size_t bytes, hipStream_t stream) : s(stream) {
+    if (bytes == 0) return;
+    hipError_t e = hipMallocAsync(&p, bytes, stream);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error{CBFM_E_NOMEM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed"};
+    }
+  }
+  ~Scratch() {
+    if (p) (void)hipFreeAsync(p, s);
+  }
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// Per-triangle geometry, structure of arrays, in one precision.  Points are
+// stored relative to the triangle's centroid; the centroid itself is kept
+// in double for both precisions (pair offsets are formed in double).
+template <typename R>
+struct TriTab {
+  const R* q[3];    // quadrature points, [k * nt + t], k < 7
+  const R* v[3];    // vertices (free vertices of the local functions), [a * nt + t]
+  const R* c;       // s_a * l_a, [a * nt + t]
+  const double* cen[3];  // centroid
+  int64_t nt;
+};
+
+struct NearPair {
+  int32_t p, q;     // triangles
+  int32_t i, j;     // positions in the row / column triangle lists
+  int32_t coplanar; // K of the pair is zero
+  int32_t pad;
+};
+
+struct MeshHost {
+  int64_t nv = 0, nt = 0, ne = 0;
+  int32_t nblocks = 1;
+  std::vector<double> V;            // nv*3
+  std::vector<int32_t> T;           // nt*3
+  std::vector<int32_t> edges;       // ne*2 canonical
+  std::vector<int32_t> tplus, tminus, aplus, aminus;
+  std::vector<int32_t> tri_edge;    // nt*3
+  std::vector<int32_t> tri_sign;    // nt*3
+  std::vector<double> length;       // ne
+  std::vector<double> area;         // nt
+  std::vector<double> normal;       // nt*3
+  std::vector<double> centroid;     // nt*3
+  std::vector<int32_t> edge_block;  // ne
+  std::vector<int32_t> perm;        // internal (cell-sorted) -> canonical
+  std::vector<int32_t> iperm;       // canonical -> internal
+  std::vector<int64_t> cell_off;    // nblocks+1 offsets into the internal order
+  std::vector<NearPair> near;       // all near pairs (i = p, j = q)
+};
+
+}  // namespace cbfm
+
+struct cbfm_mesh_s {
+  cbfm::MeshHost h;
+  // device tables
+  cbfm::DevBuf q64, v64, c64, q32, v32, c32, cen;   // SoA geometry
+  cbfm::DevBuf tri_edge, tri_sign, tplus, tminus, aplus, aminus, length, area;
+  cbfm::DevBuf tri_xyz;        // nt*9 absolute vertex coordinates (double)
+  cbfm::DevBuf perm, iperm;    // int32
+  cbfm::TriTab<double> tab64() const;
+  cbfm::TriTab<float> tab32() const;
+};
+
+namespace cbfm {
+
+// Opt-in launch timing (see cbfm_timer_enable): start/stop bracket one
+// launch of kernel family `id` on stream s; no-ops when timing is off.
+enum TimerId { T_FILL_REGULAR = 0, T_FILL_NEAR = 1, T_ASSEMBLE = 2, T_GEMM = 3, T_COUNT = 4 };
+struct TimedLaunch {
+  TimedLaunch(int id, hipStream_t s);
+  ~TimedLaunch();
+  int id;
+  hipStream_t s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+struct Media {
+  // exterior k1 real; interior k2 = k2r + j k2i (k2i <= 0 when lossy)
+  double k1, k2r, k2i;
+  std::complex<double> eta1, eta2;
+};
+
+Media make_media(const cbfm_medium* med);
+
+// Fill the triangle-local matrix for row triangles x column triangles into
+// `local` (3 ops x 3*nrt x 3*nct complex of the given precision, ops per
+// layout) and overwrite the near pairs.  Implemented in fill.hip.
+void fill_local(const cbfm_mesh_s* m, const Media& md, int precision, int layout,
+                const int32_t* rowTris_dev, int64_t nrt, const int32_t* colTris_dev, int64_t nct,
+                const NearPair* near_dev, int64_t nnear, void* local, hipStream_t s);
+
+void rhs_launch(const cbfm_mesh_s* m, const Media& md, double eta0, const double* inc_dev, int64_t nrhs,
+                void* v_dev, hipStream_t s);
+
+// Gather the RWG matrices [op][r][c] (r < nrow, c < ncol) of the listed
+// canonical edges from a triangle-local buffer.  With precision FP32 the
+// local buffer holds float2 and Z receives double2 when out_fp64 is set.
+void assemble(const cbfm_mesh_s* m, int precision, const void* local, int64_t nrt, int64_t nct,
+              const int32_t* rowEdges, int64_t nrow, const int32_t* colEdges, int64_t ncol,
+              const int32_t* rowPos, const int32_t* colPos, void* Z, int64_t zop_stride, int64_t ldz,
+              hipStream_t s, int out_fp64 = 0);
+
+}  // namespace cbfm

@@ -1,0 +1,540 @@
+// Reduced solve and RCS (paper Sec. III-C outer/inner CBFM equations and
+// the current reconstruction; monostatic RCS after Knott).
+//
+//   v_r = (C^JM)^H v                   (tested incident fields, projected)
+//   GMRES on  Z_r (G^CBF)^{-1} y = v_r, x0 = 0, restarted   (right precond.)
+//   j_CBF = (G^CBF)^{-1} y,   j = C^MJ j_CBF
+//   sigma = k0^2 / (4 pi) |eta0 N_perp - rhat x L|^2
+//
+// GMRES runs on the device for all right-hand sides at once, each with its
+// own Krylov space (Saad's GMRES with classical Gram-Schmidt applied twice
+// and complex Givens rotations).  Matrix-vector products are matrix-core
+// GEMMs over all right-hand sides; the Hessenberg updates run one thread per
+// right-hand side.  The host only reads the convergence flags each step.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "cbf.h"
+#include "gemm.h"
+
+namespace cbfm {
+
+// ------------------------------------------------------------- small kernels
+// out[c][i] = in[c][perm[i]] (gather, forward) or out[c][perm[i]] = in[c][i]
+// for both halves of 2ne-long vectors
+__global__ void permute_kernel(const double2* __restrict__ in, double2* __restrict__ out, const int32_t* __restrict__ perm,
+                               int64_t ne, int64_t nv, int forward) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (i >= ne || c >= nv) return;
+  const int64_t base = c * 2 * ne;
+  const int64_t p = perm[i];
+  if (forward) {
+    out[base + i] = in[base + p];
+    out[base + ne + i] = in[base + ne + p];
+  } else {
+    out[base + p] = in[base + i];
+    out[base + ne + p] = in[base + ne + i];
+  }
+}
+
+// h[i * ldh + c] (+)= sum_k conj(V[i][c][k]) u[c][k], i <= j; one block per (i, c)
+__global__ void __launch_bounds__(256) dots_kernel(const double2* __restrict__ V, int64_t vstride, const double2* __restrict__ u,
+                                                   int64_t n, int64_t nrhs, const int32_t* __restrict__ active,
+                                                   double2* __restrict__ h, int64_t ldh, int accumulate) {
+  const int64_t i = blockIdx.x, c = blockIdx.y;
+  if (!active[c]) return;
+  const double2* v = V + i * vstride + c * n;
+  const double2* w = u + c * n;
+  double re = 0, im = 0;
+  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+    const double2 a = v[k], b = w[k];
+    re += a.x * b.x + a.y * b.y;
+    im += a.x * b.y - a.y * b.x;
+  }
+  __shared__ double sre[256], sim[256];
+  sre[threadIdx.x] = re;
+  sim[threadIdx.x] = im;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      sre[threadIdx.x] += sre[threadIdx.x + st];
+      sim[threadIdx.x] += sim[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double2 r = make_double2(sre[0], sim[0]);
+    if (accumulate) {
+      r.x += h[i * ldh + c].x;
+      r.y += h[i * ldh + c].y;
+    }
+    h[i * ldh + c] = r;
+  }
+}
+
+// u[c] -= sum_{i<=j} coef[i][c] V[i][c]   (coef taken from `h` at [i*ldh+c])
+__global__ void orth_update_kernel(const double2* __restrict__ V, int64_t vstride, double2* __restrict__ u, int64_t n,
+                                   int64_t jp1, const int32_t* __restrict__ active, const double2* __restrict__ h,
+                                   int64_t ldh) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (k >= n || !active[c]) return;
+  double2 acc = u[c * n + k];
+  for (int64_t i = 0; i < jp1; ++i) {
+    const double2 a = h[i * ldh + c], v = V[i * vstride + c * n + k];
+    acc.x -= a.x * v.x - a.y * v.y;
+    acc.y -= a.x * v.y + a.y * v.x;
+  }
+  u[c * n + k] = acc;
+}
+
+// nrm[c] = ||u[c]||
+__global__ void __launch_bounds__(256) norm_kernel(const double2* __restrict__ u, int64_t n, double* __restrict__ nrm) {
+  const int64_t c = blockIdx.x;
+  double s = 0;
+  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+    const double2 a = u[c * n + k];
+    s += a.x * a.x + a.y * a.y;
+  }
+  __shared__ double sh[256];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) nrm[c] = sqrt(sh[0]);
+}
+
+// out[c] = in[c] / nrm[c] (zero if nrm[c] == 0); only active vectors
+__global__ void scale_kernel(const double2* __restrict__ in, double2* __restrict__ out, int64_t n,
+                             const double* __restrict__ nrm, const int32_t* __restrict__ active) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (k >= n || !active[c]) return;
+  const double s = nrm[c] > 0 ? 1.0 / nrm[c] : 0.0;
+  const double2 a = in[c * n + k];
+  out[c * n + k] = make_double2(a.x * s, a.y * s);
+}
+
+// h[i][c] += d[i][c] for i < jp1
+__global__ void add_coef_kernel(double2* __restrict__ h, const double2* __restrict__ d, int64_t total) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= total) return;
+  h[k] = make_double2(h[k].x + d[k].x, h[k].y + d[k].y);
+}
+
+// r[c] = b[c] - r[c]
+__global__ void sub_from_kernel(const double2* __restrict__ b, double2* __restrict__ r, int64_t total) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= total) return;
+  r[k] = make_double2(b[k].x - r[k].x, b[k].y - r[k].y);
+}
+
+struct GmresState {
+  double2* H;      // [c][(m+1) * m], column-major in (row i, col j): H[c][j*(m+1)+i]
+  double2* cs;     // [c][m]
+  double2* sn;     // [c][m]
+  double2* g;      // [c][m+1]
+  double2* hcol;   // [i][c] current column (m+1 rows)
+  double* nrm;     // [c]
+  double* bnorm;   // [c]
+  double* res;     // [c] residual estimate / bnorm
+  int32_t* active; // [c]
+  int32_t* kc;     // [c] Krylov dimension reached
+};
+
+// Start a cycle: g = beta e1, active = beta/bnorm > tol, kc = 0.
+__global__ void cycle_init_kernel(GmresState st, int64_t m, int64_t nrhs, double tol) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nrhs) return;
+  const double beta = st.nrm[c];
+  for (int64_t i = 0; i <= m; ++i) st.g[c * (m + 1) + i] = make_double2(0, 0);
+  st.g[c * (m + 1)] = make_double2(beta, 0);
+  const double r = st.bnorm[c] > 0 ? beta / st.bnorm[c] : 0.0;
+  st.res[c] = r;
+  st.active[c] = r > tol ? 1 : 0;
+  st.kc[c] = 0;
+}
+
+// Column j of the Hessenberg matrix from hcol (rows 0..j) and nrm (row j+1);
+// apply previous rotations, form the new one, update g, test convergence.
+__global__ void givens_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs, double tol) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nrhs || !st.active[c]) return;
+  double2* H = st.H + c * (m + 1) * m + j * (m + 1);
+  for (int64_t i = 0; i <= j; ++i) H[i] = st.hcol[i * nrhs + c];
+  H[j + 1] = make_double2(st.nrm[c], 0);
+  double2* cs = st.cs + c * m;
+  double2* sn = st.sn + c * m;
+  for (int64_t i = 0; i < j; ++i) {
+    const double2 a = H[i], b = H[i + 1], cc = cs[i], ss = sn[i];
+    // t = c a + s b ;  b' = -conj(s) a + conj(c) b
+    const double2 t = make_double2(cc.x * a.x - cc.y * a.y + ss.x * b.x - ss.y * b.y,
+                                   cc.x * a.y + cc.y * a.x + ss.x * b.y + ss.y * b.x);
+    const double2 b2 = make_double2(-(ss.x * a.x + ss.y * a.y) + (cc.x * b.x + cc.y * b.y),
+                                    -(ss.x * a.y - ss.y * a.x) + (cc.x * b.y - cc.y * b.x));
+    H[i] = t;
+    H[i + 1] = b2;
+  }
+  const double2 a = H[j], b = H[j + 1];
+  const double den = sqrt(a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y);
+  double2 cc = make_double2(1, 0), ss = make_double2(0, 0);
+  if (den > 0) {
+    cc = make_double2(a.x / den, -a.y / den);  // conj(a)/den
+    ss = make_double2(b.x / den, -b.y / den);  // conj(b)/den
+  }
+  cs[j] = cc;
+  sn[j] = ss;
+  H[j] = make_double2(den, 0);
+  H[j + 1] = make_double2(0, 0);
+  double2* g = st.g + c * (m + 1);
+  const double2 gj = g[j];
+  // g[j+1] = -conj(s) g[j];  g[j] = c g[j]
+  g[j + 1] = make_double2(-(ss.x * gj.x + ss.y * gj.y), -(ss.x * gj.y - ss.y * gj.x));
+  g[j] = make_double2(cc.x * gj.x - cc.y * gj.y, cc.x * gj.y + cc.y * gj.x);
+  const double r = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y) / st.bnorm[c];
+  st.res[c] = r;
+  st.kc[c] = (int32_t)(j + 1);
+  if (r <= tol || den == 0.0) st.active[c] = 0;
+}
+
+// y = H^{-1} g over the first kc[c] rows (upper triangular); stored in g.
+__global__ void backsolve_kernel(GmresState st, int64_t m, int64_t nrhs) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nrhs) return;
+  const int64_t k = st.kc[c];
+  const double2* H = st.H + c * (m + 1) * m;
+  double2* g = st.g + c * (m + 1);
+  for (int64_t i = k - 1; i >= 0; --i) {
+    double2 s = g[i];
+    for (int64_t l = i + 1; l < k; ++l) {
+      const double2 h = H[l * (m + 1) + i], y = g[l];
+      s.x -= h.x * y.x - h.y * y.y;
+      s.y -= h.x * y.y + h.y * y.x;
+    }
+    const double2 d = H[i * (m + 1) + i];
+    const double dd = d.x * d.x + d.y * d.y;
+    g[i] = dd > 0 ? make_double2((s.x * d.x + s.y * d.y) / dd, (s.y * d.x - s.x * d.y) / dd) : make_double2(0, 0);
+  }
+}
+
+// x[c] += sum_{i < kc[c]} y[c][i] V[i][c]
+__global__ void x_update_kernel(GmresState st, const double2* __restrict__ V, int64_t vstride, double2* __restrict__ x,
+                                int64_t n, int64_t m) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (k >= n) return;
+  const int64_t kc = st.kc[c];
+  const double2* y = st.g + c * (m + 1);
+  double2 acc = x[c * n + k];
+  for (int64_t i = 0; i < kc; ++i) {
+    const double2 a = y[i], v = V[i * vstride + c * n + k];
+    acc.x += a.x * v.x - a.y * v.y;
+    acc.y += a.x * v.y + a.y * v.x;
+  }
+  x[c * n + k] = acc;
+}
+
+// ------------------------------------------------------------- far field
+// One block per (rhs, direction): radiation vectors N (from alpha^J) and L
+// (from alpha^M) over all triangles and quadrature points, then sigma.
+struct FarArgs {
+  const double* xyz9;
+  const int32_t* tri_edge;
+  const double* c64;   // s_a l_a, [a * nt + t]
+  int64_t nt, ne;
+  double bary[7][3];
+  double w[7];
+  double k0, eta0;
+};
+
+__global__ void __launch_bounds__(256) farfield_kernel(FarArgs fa, const double2* __restrict__ j, const double* __restrict__ dirs,
+                                                       const double* __restrict__ pol, int64_t ndir,
+                                                       double* __restrict__ sigma) {
+  const int64_t d = blockIdx.x, c = blockIdx.y;
+  const double r[3] = {dirs[(c * ndir + d) * 3], dirs[(c * ndir + d) * 3 + 1], dirs[(c * ndir + d) * 3 + 2]};
+  const double2* aM = j + c * 2 * fa.ne;
+  const double2* aJ = aM + fa.ne;
+  double acc[12] = {0};  // N (re, im) x3, L (re, im) x3
+  for (int64_t t = threadIdx.x; t < fa.nt; t += blockDim.x) {
+    const double* P = fa.xyz9 + t * 9;
+    double2 cJ[3], cM[3];
+    for (int a = 0; a < 3; ++a) {
+      const int e = fa.tri_edge[t * 3 + a];
+      const double ca = fa.c64[a * fa.nt + t] * 0.5;  // int_T f = sum_k w_k A (c/2A)(r - p) -> c/2
+      cJ[a] = make_double2(aJ[e].x * ca, aJ[e].y * ca);
+      cM[a] = make_double2(aM[e].x * ca, aM[e].y * ca);
+    }
+    for (int k = 0; k < 7; ++k) {
+      double rk[3];
+      for (int x = 0; x < 3; ++x) rk[x] = fa.bary[k][0] * P[x] + fa.bary[k][1] * P[3 + x] + fa.bary[k][2] * P[6 + x];
+      double sn, cs;
+      sincos(fa.k0 * (r[0] * rk[0] + r[1] * rk[1] + r[2] * rk[2]), &sn, &cs);  // e^{+j k0 r.r'}
+      const double wk = fa.w[k];
+      for (int a = 0; a < 3; ++a) {
+        const double2 pJ = make_double2(wk * (cJ[a].x * cs - cJ[a].y * sn), wk * (cJ[a].x * sn + cJ[a].y * cs));
+        const double2 pM = make_double2(wk * (cM[a].x * cs - cM[a].y * sn), wk * (cM[a].x * sn + cM[a].y * cs));
+        for (int x = 0; x < 3; ++x) {
+          const double dv = rk[x] - P[a * 3 + x];
+          acc[2 * x] += pJ.x * dv;
+          acc[2 * x + 1] += pJ.y * dv;
+          acc[6 + 2 * x] += pM.x * dv;
+          acc[6 + 2 * x + 1] += pM.y * dv;
+        }
+      }
+    }
+  }
+  __shared__ double sh[12][256];
+  for (int q = 0; q < 12; ++q) sh[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+      for (int q = 0; q < 12; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double N[3][2], L[3][2];
+    for (int x = 0; x < 3; ++x) {
+      N[x][0] = sh[2 * x][0];
+      N[x][1] = sh[2 * x + 1][0];
+      L[x][0] = sh[6 + 2 * x][0];
+      L[x][1] = sh[6 + 2 * x + 1][0];
+    }
+    const double rn[2] = {r[0] * N[0][0] + r[1] * N[1][0] + r[2] * N[2][0], r[0] * N[0][1] + r[1] * N[1][1] + r[2] * N[2][1]};
+    double F[3][2];
+    for (int x = 0; x < 3; ++x) {
+      const int x1 = (x + 1) % 3, x2 = (x + 2) % 3;
+      for (int p = 0; p < 2; ++p) {
+        const double nperp = N[x][p] - r[x] * rn[p];
+        const double rxl = r[x1] * L[x2][p] - r[x2] * L[x1][p];
+        F[x][p] = fa.eta0 * nperp - rxl;
+      }
+    }
+    double s2;
+    if (pol) {
+      const double* pp = pol + (c * ndir + d) * 3;
+      const double fr = F[0][0] * pp[0] + F[1][0] * pp[1] + F[2][0] * pp[2];
+      const double fi = F[0][1] * pp[0] + F[1][1] * pp[1] + F[2][1] * pp[2];
+      s2 = fr * fr + fi * fi;
+    } else {
+      s2 = 0;
+      for (int x = 0; x < 3; ++x) s2 += F[x][0] * F[x][0] + F[x][1] * F[x][1];
+    }
+    sigma[c * ndir + d] = fa.k0 * fa.k0 / (4.0 * M_PI) * s2;
+  }
+}
+
+static dim3 grid2(int64_t n, int64_t m) { return dim3((unsigned)((n + 255) / 256), (unsigned)m); }
+
+// u = A w with A = Z_r (G^CBF)^{-1} (use_cmp) or Z_r; w is overwritten.
+static void apply_A(cbfm_cbf_s* c, const double2* Zr, int64_t ldz, int64_t nrhs, double2* w, double2* u, bool use_cmp,
+                    hipStream_t s) {
+  const int64_t n = 2 * c->NL;
+  if (use_cmp) cmp_apply_dev(c, nrhs, w, s);
+  // u^T (n x nrhs) = Z_r (n x n) w^T
+  std::vector<GemmDesc> d{gemm(Zr, ldz, OP_N, w, n, OP_T, u, n, n, nrhs, n)};
+  d[0].transC = 1;
+  zgemm_batched(d, s);
+}
+
+}  // namespace cbfm
+
+using namespace cbfm;
+
+extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, const void* Zr_v, int64_t ldz,
+                                  const double* inc, int64_t nrhs, const cbfm_solver_params* prm, void* j_dev,
+                                  int32_t* iters, double* relres, const double* dirs, int64_t ndir, double* rcs,
+                                  void* stream) {
+  cbfm_status noconv = CBFM_OK;
+  cbfm_status st = guarded([&] {
+    CBFM_REQUIRE(m && c && Zr_v && inc && prm, CBFM_E_ARG, "null argument");
+    CBFM_REQUIRE(c->mesh == m, CBFM_E_STATE, "CBF set belongs to another mesh");
+    CBFM_REQUIRE(nrhs >= 1 && nrhs <= 65535, CBFM_E_ARG, "nrhs out of range");
+    CBFM_REQUIRE(ldz >= 2 * c->NL, CBFM_E_ARG, "ldz < N_CBF");
+    CBFM_REQUIRE(prm->tol > 0 && prm->max_iter >= 1 && prm->restart >= 1, CBFM_E_ARG, "bad solver parameters");
+    CBFM_REQUIRE(dirs == nullptr || ndir >= 1, CBFM_E_ARG, "ndir must be >= 1 with dirs");
+    const Media md = make_media(med);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const MeshHost& h = m->h;
+    const int64_t ne = h.ne, NL = c->NL, n = 2 * NL, nb = h.nblocks;
+    const double2* Zr = static_cast<const double2*>(Zr_v);
+    const bool use_cmp = prm->use_cmp != 0;
+    const int64_t mres = std::min<int64_t>(prm->restart, std::max<int64_t>(prm->max_iter, 1));
+    // ---- right-hand sides and their projection
+    Scratch dinc(nrhs * 6 * sizeof(double), s);
+    CBFM_HIP(hipMemcpyAsync(dinc.p, inc, nrhs * 6 * sizeof(double), hipMemcpyHostToDevice, s));
+    Scratch v(nrhs * 2 * ne * sizeof(double2), s), vint(nrhs * 2 * ne * sizeof(double2), s);
+    rhs_launch(m, md, med->eta0, dinc.as<double>(), nrhs, v.p, s);
+    hipLaunchKernelGGL(permute_kernel, grid2(ne, nrhs), dim3(256), 0, s, v.as<double2>(), vint.as<double2>(),
+                       m->perm.as<int32_t>(), ne, nrhs, 1);
+    Scratch b(nrhs * n * sizeof(double2), s);
+    {
+      std::vector<GemmDesc> ds;
+      for (int a = 0; a < nb; ++a) {
+        const int64_t Na = h.cell_off[a + 1] - h.cell_off[a], r0 = h.cell_off[a];
+        // [v_r]_J-part = (C^J_a)^H v^E_a,  [v_r]_M-part = (C^M_a)^H v^H_a  (per vector: v . conj(C))
+        ds.push_back(gemm(vint.as<double2>() + r0, 2 * ne, OP_N, c->CJ.as<double2>() + c->coff[a], c->L[a], OP_R,
+                          b.as<double2>() + c->off[a], n, nrhs, c->L[a], Na));
+        ds.push_back(gemm(vint.as<double2>() + ne + r0, 2 * ne, OP_N, c->CM.as<double2>() + c->coff[a], c->L[a], OP_R,
+                          b.as<double2>() + NL + c->off[a], n, nrhs, c->L[a], Na));
+      }
+      zgemm_batched(ds, s);
+    }
+    // ---- GMRES state
+    Scratch V((mres + 1) * nrhs * n * sizeof(double2), s);
+    Scratch x(nrhs * n * sizeof(double2), s), w(nrhs * n * sizeof(double2), s), u(nrhs * n * sizeof(double2), s);
+    Scratch Hs(nrhs * (mres + 1) * mres * sizeof(double2), s), csb(nrhs * mres * sizeof(double2), s),
+        snb(nrhs * mres * sizeof(double2), s), gb(nrhs * (mres + 1) * sizeof(double2), s),
+        hcol((mres + 1) * nrhs * sizeof(double2), s), dbl(3 * nrhs * sizeof(double), s), ints(2 * nrhs * sizeof(int32_t), s);
+    GmresState gs{Hs.as<double2>(), csb.as<double2>(), snb.as<double2>(), gb.as<double2>(), hcol.as<double2>(),
+                  dbl.as<double>(), dbl.as<double>() + nrhs, dbl.as<double>() + 2 * nrhs, ints.as<int32_t>(),
+                  ints.as<int32_t>() + nrhs};
+    const int64_t vstride = nrhs * n;
+    CBFM_HIP(hipMemsetAsync(x.p, 0, nrhs * n * sizeof(double2), s));
+    hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, b.as<double2>(), n, gs.bnorm);
+    std::vector<int32_t> its(nrhs, 0), act(nrhs), done(nrhs, 0);
+    std::vector<double> res(nrhs, 1.0);
+    std::vector<int32_t> all_active(nrhs, 1);
+    Scratch allact(nrhs * sizeof(int32_t), s);
+    CBFM_HIP(hipMemcpyAsync(allact.p, all_active.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    int64_t total = 0;
+    const double tol = prm->tol;
+    for (;;) {
+      // r = b - A x  (x = 0 on the first cycle)
+      double2* r = u.as<double2>();
+      if (total == 0) {
+        CBFM_HIP(hipMemcpyAsync(r, b.p, nrhs * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      } else {
+        CBFM_HIP(hipMemcpyAsync(w.p, x.p, nrhs * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        apply_A(c, Zr, ldz, nrhs, w.as<double2>(), r, use_cmp, s);
+        hipLaunchKernelGGL(sub_from_kernel, dim3((unsigned)((nrhs * n + 255) / 256)), dim3(256), 0, s, b.as<double2>(), r,
+                           nrhs * n);
+      }
+      hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, r, n, gs.nrm);
+      hipLaunchKernelGGL(cycle_init_kernel, dim3((unsigned)((nrhs + 63) / 64)), dim3(64), 0, s, gs, mres, nrhs, tol);
+      hipLaunchKernelGGL(scale_kernel, grid2(n, nrhs), dim3(256), 0, s, r, V.as<double2>(), n, gs.nrm, allact.as<int32_t>());
+      CBFM_HIP(hipMemcpyAsync(act.data(), gs.active, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      CBFM_HIP(hipStreamSynchronize(s));
+      if (std::none_of(act.begin(), act.end(), [](int32_t a) { return a != 0; })) break;
+      if (total >= prm->max_iter) break;
+      for (int64_t j = 0; j < mres && total < prm->max_iter; ++j) {
+        double2* Vj = V.as<double2>() + j * vstride;
+        double2* Vn = V.as<double2>() + (j + 1) * vstride;
+        CBFM_HIP(hipMemcpyAsync(w.p, Vj, nrhs * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        apply_A(c, Zr, ldz, nrhs, w.as<double2>(), u.as<double2>(), use_cmp, s);
+        // classical Gram-Schmidt, twice
+        for (int pass = 0; pass < 2; ++pass) {
+          double2* hc = pass == 0 ? gs.hcol : w.as<double2>();  // second pass coefficients in scratch w
+          hipLaunchKernelGGL(dots_kernel, dim3((unsigned)(j + 1), (unsigned)nrhs), dim3(256), 0, s, V.as<double2>(),
+                             vstride, u.as<double2>(), n, nrhs, gs.active, hc, nrhs, 0);
+          hipLaunchKernelGGL(orth_update_kernel, grid2(n, nrhs), dim3(256), 0, s, V.as<double2>(), vstride,
+                             u.as<double2>(), n, j + 1, gs.active, hc, nrhs);
+          if (pass == 1)  // Hessenberg column = first + second pass coefficients
+            hipLaunchKernelGGL(add_coef_kernel, dim3((unsigned)(((j + 1) * nrhs + 255) / 256)), dim3(256), 0, s, gs.hcol,
+                               w.as<double2>(), (j + 1) * nrhs);
+        }
+        hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, u.as<double2>(), n, gs.nrm);
+        hipLaunchKernelGGL(scale_kernel, grid2(n, nrhs), dim3(256), 0, s, u.as<double2>(), Vn, n, gs.nrm, gs.active);
+        hipLaunchKernelGGL(givens_kernel, dim3((unsigned)((nrhs + 63) / 64)), dim3(64), 0, s, gs, mres, j, nrhs, tol);
+        CBFM_HIP(hipGetLastError());
+        ++total;
+        CBFM_HIP(hipMemcpyAsync(act.data(), gs.active, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CBFM_HIP(hipStreamSynchronize(s));
+        for (int64_t q = 0; q < nrhs; ++q)
+          if (!done[q]) its[q] = (int32_t)total;
+        for (int64_t q = 0; q < nrhs; ++q)
+          if (!act[q]) done[q] = 1;
+        if (std::none_of(act.begin(), act.end(), [](int32_t a) { return a != 0; })) break;
+      }
+      hipLaunchKernelGGL(backsolve_kernel, dim3((unsigned)((nrhs + 63) / 64)), dim3(64), 0, s, gs, mres, nrhs);
+      hipLaunchKernelGGL(x_update_kernel, grid2(n, nrhs), dim3(256), 0, s, gs, V.as<double2>(), vstride, x.as<double2>(),
+                         n, mres);
+      CBFM_HIP(hipGetLastError());
+      std::fill(done.begin(), done.end(), 0);
+      if (total >= prm->max_iter) {
+        // final residual check below
+        break;
+      }
+    }
+    // true relative residual of the preconditioned system
+    {
+      double2* r = u.as<double2>();
+      CBFM_HIP(hipMemcpyAsync(w.p, x.p, nrhs * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      apply_A(c, Zr, ldz, nrhs, w.as<double2>(), r, use_cmp, s);
+      hipLaunchKernelGGL(sub_from_kernel, dim3((unsigned)((nrhs * n + 255) / 256)), dim3(256), 0, s, b.as<double2>(), r,
+                         nrhs * n);
+      hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, r, n, gs.nrm);
+      std::vector<double> rn(nrhs), bn(nrhs);
+      CBFM_HIP(hipMemcpyAsync(rn.data(), gs.nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+      CBFM_HIP(hipMemcpyAsync(bn.data(), gs.bnorm, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+      CBFM_HIP(hipStreamSynchronize(s));
+      for (int64_t q = 0; q < nrhs; ++q) {
+        res[q] = bn[q] > 0 ? rn[q] / bn[q] : 0.0;
+        if (res[q] > tol * 10.0) noconv = CBFM_E_NOCONV;
+      }
+    }
+    // j_CBF = G^{-1} x ; j = C^MJ j_CBF
+    double2* jc = x.as<double2>();
+    if (use_cmp) cmp_apply_dev(c, nrhs, jc, s);
+    Scratch jint(nrhs * 2 * ne * sizeof(double2), s), jout(nrhs * 2 * ne * sizeof(double2), s);
+    {
+      std::vector<GemmDesc> ds;
+      for (int a = 0; a < nb; ++a) {
+        const int64_t Na = h.cell_off[a + 1] - h.cell_off[a], r0 = h.cell_off[a];
+        // alpha^M_a = C^M_a beta^M_a, alpha^J_a = C^J_a beta^J_a  (per vector: beta . C^T)
+        ds.push_back(gemm(jc + c->off[a], n, OP_N, c->CM.as<double2>() + c->coff[a], c->L[a], OP_T,
+                          jint.as<double2>() + r0, 2 * ne, nrhs, Na, c->L[a]));
+        ds.push_back(gemm(jc + NL + c->off[a], n, OP_N, c->CJ.as<double2>() + c->coff[a], c->L[a], OP_T,
+                          jint.as<double2>() + ne + r0, 2 * ne, nrhs, Na, c->L[a]));
+      }
+      zgemm_batched(ds, s);
+    }
+    double2* jfinal = j_dev ? static_cast<double2*>(j_dev) : jout.as<double2>();
+    hipLaunchKernelGGL(permute_kernel, grid2(ne, nrhs), dim3(256), 0, s, jint.as<double2>(), jfinal,
+                       m->perm.as<int32_t>(), ne, nrhs, 0);
+    CBFM_HIP(hipGetLastError());
+    // ---- RCS
+    if (rcs) {
+      const int64_t nd = dirs ? ndir : 1;
+      std::vector<double> hd(nrhs * nd * 3), hp;
+      if (dirs) {
+        for (int64_t q = 0; q < nrhs; ++q) std::memcpy(&hd[q * nd * 3], dirs, nd * 3 * sizeof(double));
+      } else {
+        hp.resize(nrhs * 3);
+        for (int64_t q = 0; q < nrhs; ++q)
+          for (int x3 = 0; x3 < 3; ++x3) {
+            hd[q * 3 + x3] = -inc[q * 6 + x3];
+            hp[q * 3 + x3] = inc[q * 6 + 3 + x3];
+          }
+      }
+      Scratch ddir(hd.size() * sizeof(double), s), dpol(hp.size() * sizeof(double), s),
+          dsig(nrhs * nd * sizeof(double), s);
+      CBFM_HIP(hipMemcpyAsync(ddir.p, hd.data(), hd.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      if (!hp.empty()) CBFM_HIP(hipMemcpyAsync(dpol.p, hp.data(), hp.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      FarArgs fa{};
+      fa.xyz9 = m->tri_xyz.as<double>();
+      fa.tri_edge = m->tri_edge.as<int32_t>();
+      fa.c64 = m->c64.as<double>();
+      fa.nt = h.nt;
+      fa.ne = ne;
+      const double s15 = std::sqrt(15.0);
+      const double qa = (6.0 - s15) / 21.0, qb = (6.0 + s15) / 21.0;
+      const double wa = (155.0 - s15) / 1200.0, wb = (155.0 + s15) / 1200.0;
+      const double Bq[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {1 - 2 * qa, qa, qa}, {qa, 1 - 2 * qa, qa}, {qa, qa, 1 - 2 * qa},
+                               {1 - 2 * qb, qb, qb},        {qb, 1 - 2 * qb, qb}, {qb, qb, 1 - 2 * qb}};
+      const double Wq[7] = {9.0 / 40.0, wa, wa, wa, wb, wb, wb};
+      std::memcpy(fa.bary, Bq, sizeof(Bq));
+      std::memcpy(fa.w, Wq, sizeof(Wq));
+      fa.k0 = med->k0;
+      fa.eta0 = med->eta0;
+      hipLaunchKernelGGL(farfield_kernel, dim3((unsigned)nd, (unsigned)nrhs), dim3(256), 0, s, fa, jfinal, ddir.as<double>(),
+                         hp.empty() ? nullptr : dpol.as<double>(), nd, dsig.as<double>());
+      CBFM_HIP(hipGetLastError());
+      CBFM_HIP(hipMemcpyAsync(rcs, dsig.p, nrhs * nd * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    CBFM_HIP(hipStreamSynchronize(s));
+    if (iters) std::memcpy(iters, its.data(), nrhs * sizeof(int32_t));
+    if (relres) std::memcpy(relres, res.data(), nrhs * sizeof(double));
+    if (noconv != CBFM_OK) set_error("GMRES did not reach the tolerance for every right-hand side");
+  });
+  return st != CBFM_OK ? st : noconv;
+}

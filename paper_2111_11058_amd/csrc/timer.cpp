@@ -1,0 +1,80 @@
+// Opt-in launch timing with HIP events (cbfm_timer_enable / cbfm_timer_read).
+#include <cstring>
+#include <mutex>
+
+#include "internal.h"
+
+namespace cbfm {
+
+namespace {
+std::mutex g_mu;
+bool g_on = false;
+struct Rec {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  int64_t launches = 0;
+  double ms = 0;
+};
+Rec g_rec[T_COUNT];
+const char* g_names[T_COUNT] = {"fill_regular", "fill_near", "assemble", "gemm"};
+
+void drain(Rec& r) {
+  for (auto& p : r.pending) {
+    float ms = 0;
+    if (hipEventSynchronize(p.second) == hipSuccess && hipEventElapsedTime(&ms, p.first, p.second) == hipSuccess) {
+      r.ms += ms;
+      r.launches += 1;
+    }
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  r.pending.clear();
+}
+}  // namespace
+
+TimedLaunch::TimedLaunch(int id_, hipStream_t s_) : id(id_), s(s_) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_on) return;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    e0 = e1 = nullptr;
+    return;
+  }
+  (void)hipEventRecord(e0, s);
+}
+
+TimedLaunch::~TimedLaunch() {
+  if (!e0) return;
+  (void)hipEventRecord(e1, s);
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_rec[id].pending.push_back({e0, e1});
+}
+
+}  // namespace cbfm
+
+using namespace cbfm;
+
+extern "C" cbfm_status cbfm_timer_enable(int32_t on) {
+  return guarded([&] {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto& r : g_rec) {
+      drain(r);
+      r.launches = 0;
+      r.ms = 0;
+    }
+    g_on = on != 0;
+  });
+}
+
+extern "C" cbfm_status cbfm_timer_read(const char* name, int64_t* launches, double* total_ms) {
+  return guarded([&] {
+    CBFM_REQUIRE(name != nullptr, CBFM_E_ARG, "timer name is NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (int i = 0; i < T_COUNT; ++i)
+      if (std::strcmp(name, g_names[i]) == 0) {
+        drain(g_rec[i]);
+        if (launches) *launches = g_rec[i].launches;
+        if (total_ms) *total_ms = g_rec[i].ms;
+        return;
+      }
+    throw Error{CBFM_E_ARG, std::string("unknown timer ") + name};
+  });
+}
