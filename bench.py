@@ -125,7 +125,7 @@ def main():
     log(f"bench: {w.name} nt={w.nt} cells={w.nblocks} nrhs={len(w.inc)}")
     mesh = cbfm.Mesh(w.V, w.T, w.edge_block, w.nblocks)
     med = cbfm.Medium.make(w.k0, w.eta0, w.eps_r, w.mu_r)
-    solver = dict(tol=1e-6, max_iter=1000, restart=200)
+    solver = dict(tol=1e-6)
     state = {}
 
     def step(precision):
@@ -138,7 +138,8 @@ def main():
         cbfm.project(mesh, med, cb, Zr, precision)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        out = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, **solver)
+        # full (unrestarted) GMRES: the Krylov dimension is bounded by N_CBF
+        out = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, max_iter=n, restart=n, **solver)
         t2 = time.perf_counter()
         return cb, out, t1 - t0, t2 - t1
 

@@ -16,10 +16,10 @@ struct cbfm_cbf_s {
   cbfm::DevBuf CM, CJ;         // per cell N_b x L_b row-major double2, cell after cell
   std::vector<double> sigma;   // kept singular values, cell after cell
   cbfm::DevBuf d_L, d_off, d_coff, d_cell_off, d_edge_block;
-  // LU factors of B = (C^M)^H G C^J, formed on first use
+  // B^{-1} for B = (C^M)^H G C^J (row-major), formed on first use
   std::mutex mu;
   bool factored = false;
-  cbfm::DevBuf Bmat, ipiv;
+  cbfm::DevBuf Binv;
 };
 
 namespace cbfm {
@@ -28,5 +28,7 @@ rocblas_handle blas_handle(hipStream_t s);
 std::mutex& blas_mutex();
 // x <- (G^CBF)^{-1} x in place, nrhs vectors of length 2 NL
 void cmp_apply_dev(cbfm_cbf_s* c, int64_t nrhs, double2* x, hipStream_t s);
+// B^{-1} (NL x NL, row-major), formed on first use
+const double2* cmp_inverse(cbfm_cbf_s* c, hipStream_t s);
 
 }  // namespace cbfm

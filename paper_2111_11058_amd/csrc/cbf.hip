@@ -13,7 +13,7 @@
 // it is zero on the diagonal and for RWGs sharing no triangle.
 //
 // G^CBF = blkdiag(A, B) with B = (C^M)^H G C^J and A = (C^J)^H G C^M =
-// -B^H (G real antisymmetric), so one LU of B serves both halves.
+// -B^H (G real antisymmetric), so one inverse of B serves both halves.
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
@@ -148,14 +148,6 @@ __global__ void gram_times_cj_kernel(const int32_t* __restrict__ perm, const int
   GC[m * NL + col] = acc;
 }
 
-// x[c][i] = s * conj(x[c][i]) for i < n, vectors of stride `ld`
-__global__ void conj_scale_kernel(double2* __restrict__ x, int64_t n, int64_t ld, int64_t nv, double s) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
-  if (i >= n || c >= nv) return;
-  double2 v = x[c * ld + i];
-  x[c * ld + i] = make_double2(s * v.x, -s * v.y);
-}
-
 // ------------------------------------------------------------- host helpers
 static std::vector<int32_t> cell_edges(const MeshHost& h, int b) {
   return std::vector<int32_t>(h.perm.begin() + h.cell_off[b], h.perm.begin() + h.cell_off[b + 1]);
@@ -177,7 +169,9 @@ void cbf_finish(cbfm_cbf_s* c) {
   c->d_edge_block.upload(h.edge_block);
 }
 
-// LU of B = (C^M)^H G C^J (row-major, i.e. B^T column-major for rocSOLVER).
+// B^{-1} for B = (C^M)^H G C^J.  rocSOLVER works column-major, so it sees
+// M = B^T; LU + inversion of M leaves M^{-1} = (B^{-1})^T in column-major
+// order, i.e. B^{-1} in the row-major layout used here.
 static void cmp_factor(cbfm_cbf_s* c, hipStream_t s) {
   const cbfm_mesh_s* m = c->mesh;
   const MeshHost& h = m->h;
@@ -190,49 +184,49 @@ static void cmp_factor(cbfm_cbf_s* c, hipStream_t s) {
                      m->tplus.as<int32_t>(), m->tminus.as<int32_t>(), m->aplus.as<int32_t>(), m->aminus.as<int32_t>(),
                      m->tri_edge.as<int32_t>(), m->tri_sign.as<int32_t>(), m->length.as<double>(), GC.as<double2>());
   CBFM_HIP(hipGetLastError());
-  c->Bmat.alloc(NL * NL * sizeof(double2));
+  c->Binv.alloc(NL * NL * sizeof(double2));
   std::vector<GemmDesc> ds;
   for (int a = 0; a < h.nblocks; ++a) {
     const int64_t Na = h.cell_off[a + 1] - h.cell_off[a];
     ds.push_back(gemm(c->CM.as<double2>() + c->coff[a], c->L[a], OP_C, GC.as<double2>() + h.cell_off[a] * NL, NL,
-                      OP_N, c->Bmat.as<double2>() + c->off[a] * NL, NL, c->L[a], NL, Na));
+                      OP_N, c->Binv.as<double2>() + c->off[a] * NL, NL, c->L[a], NL, Na));
   }
   zgemm_batched(ds, s);
-  c->ipiv.alloc(NL * sizeof(rocblas_int));
-  Scratch info(sizeof(rocblas_int), s);
+  Scratch ipiv(NL * sizeof(rocblas_int), s);
+  Scratch info(2 * sizeof(rocblas_int), s);
   {
     std::lock_guard<std::mutex> lk(blas_mutex());
     rocblas_handle bh = blas_handle(s);
-    CBFM_RS(rocsolver_zgetrf(bh, (rocblas_int)NL, (rocblas_int)NL, (rocblas_double_complex*)c->Bmat.p,
-                             (rocblas_int)NL, c->ipiv.as<rocblas_int>(), info.as<rocblas_int>()));
+    CBFM_RS(rocsolver_zgetrf(bh, (rocblas_int)NL, (rocblas_int)NL, (rocblas_double_complex*)c->Binv.p,
+                             (rocblas_int)NL, ipiv.as<rocblas_int>(), info.as<rocblas_int>()));
+    CBFM_RS(rocsolver_zgetri(bh, (rocblas_int)NL, (rocblas_double_complex*)c->Binv.p, (rocblas_int)NL,
+                             ipiv.as<rocblas_int>(), info.as<rocblas_int>() + 1));
   }
-  rocblas_int hinfo = 0;
-  CBFM_HIP(hipMemcpyAsync(&hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+  rocblas_int hinfo[2] = {0, 0};
+  CBFM_HIP(hipMemcpyAsync(hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost, s));
   CBFM_HIP(hipStreamSynchronize(s));
-  CBFM_REQUIRE(hinfo == 0, CBFM_E_RANK, "G^CBF is singular (zero pivot " + std::to_string(hinfo) + ")");
+  CBFM_REQUIRE(hinfo[0] == 0 && hinfo[1] == 0, CBFM_E_RANK,
+               "G^CBF is singular (zero pivot " + std::to_string(hinfo[0]) + ")");
   c->factored = true;
 }
 
+const double2* cmp_inverse(cbfm_cbf_s* c, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!c->factored) cmp_factor(c, s);
+  return c->Binv.as<double2>();
+}
+
+// x <- (G^CBF)^{-1} x with (G^CBF)^{-1} = blkdiag(-(B^{-1})^H, B^{-1}); for
+// vectors stored as rows: x1 <- -x1 conj(B^{-1}),  x2 <- x2 (B^{-1})^T.
 void cmp_apply_dev(cbfm_cbf_s* c, int64_t nrhs, double2* x, hipStream_t s) {
-  {
-    std::lock_guard<std::mutex> lk(c->mu);
-    if (!c->factored) cmp_factor(c, s);
-  }
+  const double2* Bi = cmp_inverse(c, s);
   const int64_t NL = c->NL, n = 2 * NL;
   if (nrhs == 0 || NL == 0) return;
-  // first half: A x1 = y1 with A = -B^H  ->  M conj(x1) = -conj(y1), M = B^T
-  dim3 grid((unsigned)((NL + 255) / 256), (unsigned)nrhs);
-  hipLaunchKernelGGL(conj_scale_kernel, grid, dim3(256), 0, s, x, NL, n, nrhs, -1.0);
-  std::lock_guard<std::mutex> lk(blas_mutex());
-  rocblas_handle bh = blas_handle(s);
-  CBFM_RS(rocsolver_zgetrs(bh, rocblas_operation_none, (rocblas_int)NL, (rocblas_int)nrhs,
-                           (rocblas_double_complex*)c->Bmat.p, (rocblas_int)NL, c->ipiv.as<rocblas_int>(),
-                           (rocblas_double_complex*)x, (rocblas_int)n));
-  hipLaunchKernelGGL(conj_scale_kernel, grid, dim3(256), 0, s, x, NL, n, nrhs, 1.0);
-  // second half: B x2 = y2  ->  M^T x2 = y2
-  CBFM_RS(rocsolver_zgetrs(bh, rocblas_operation_transpose, (rocblas_int)NL, (rocblas_int)nrhs,
-                           (rocblas_double_complex*)c->Bmat.p, (rocblas_int)NL, c->ipiv.as<rocblas_int>(),
-                           (rocblas_double_complex*)(x + NL), (rocblas_int)n));
+  Scratch y(nrhs * n * sizeof(double2), s);
+  CBFM_HIP(hipMemcpyAsync(y.p, x, nrhs * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  std::vector<GemmDesc> ds{gemm(y.as<double2>(), n, OP_N, Bi, NL, OP_R, x, n, nrhs, NL, NL, -1.0),
+                           gemm(y.as<double2>() + NL, n, OP_N, Bi, NL, OP_T, x + NL, n, nrhs, NL, NL)};
+  zgemm_batched(ds, s);
 }
 
 // Per-cell support triangles and the near pairs inside it.

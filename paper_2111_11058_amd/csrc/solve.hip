@@ -38,59 +38,51 @@ __global__ void permute_kernel(const double2* __restrict__ in, double2* __restri
   }
 }
 
-// h[i * ldh + c] (+)= sum_k conj(V[i][c][k]) u[c][k], i <= j; one block per (i, c)
-__global__ void __launch_bounds__(256) dots_kernel(const double2* __restrict__ V, int64_t vstride, const double2* __restrict__ u,
-                                                   int64_t n, int64_t nrhs, const int32_t* __restrict__ active,
-                                                   double2* __restrict__ h, int64_t ldh, int accumulate) {
-  const int64_t i = blockIdx.x, c = blockIdx.y;
+// h[i * nrhs + c] = sum_k conj(V[i][c][k]) u[c][k] for i <= j; one wavefront
+// per (i, c) dot product, four per block
+__global__ void __launch_bounds__(256) dots_kernel(const double2* __restrict__ V, int64_t vstride,
+                                                   const double2* __restrict__ u, int64_t n, int64_t nrhs, int64_t jp1,
+                                                   const int32_t* __restrict__ active, double2* __restrict__ h) {
+  const int64_t id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (id >= jp1 * nrhs) return;
+  const int64_t i = id / nrhs, c = id % nrhs;
   if (!active[c]) return;
   const double2* v = V + i * vstride + c * n;
   const double2* w = u + c * n;
   double re = 0, im = 0;
-  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+  for (int64_t k = lane; k < n; k += 64) {
     const double2 a = v[k], b = w[k];
     re += a.x * b.x + a.y * b.y;
     im += a.x * b.y - a.y * b.x;
   }
-  __shared__ double sre[256], sim[256];
-  sre[threadIdx.x] = re;
-  sim[threadIdx.x] = im;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
-      sre[threadIdx.x] += sre[threadIdx.x + st];
-      sim[threadIdx.x] += sim[threadIdx.x + st];
-    }
-    __syncthreads();
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
   }
-  if (threadIdx.x == 0) {
-    double2 r = make_double2(sre[0], sim[0]);
-    if (accumulate) {
-      r.x += h[i * ldh + c].x;
-      r.y += h[i * ldh + c].y;
-    }
-    h[i * ldh + c] = r;
-  }
+  if (lane == 0) h[i * nrhs + c] = make_double2(re, im);
 }
 
-// u[c] -= sum_{i<=j} coef[i][c] V[i][c]   (coef taken from `h` at [i*ldh+c])
+// u[c] -= sum_{i<=j} h[i][c] V[i][c]
 __global__ void orth_update_kernel(const double2* __restrict__ V, int64_t vstride, double2* __restrict__ u, int64_t n,
-                                   int64_t jp1, const int32_t* __restrict__ active, const double2* __restrict__ h,
-                                   int64_t ldh) {
+                                   int64_t jp1, int64_t nrhs, const int32_t* __restrict__ active,
+                                   const double2* __restrict__ h) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
   if (k >= n || !active[c]) return;
   double2 acc = u[c * n + k];
   for (int64_t i = 0; i < jp1; ++i) {
-    const double2 a = h[i * ldh + c], v = V[i * vstride + c * n + k];
+    const double2 a = h[i * nrhs + c], v = V[i * vstride + c * n + k];
     acc.x -= a.x * v.x - a.y * v.y;
     acc.y -= a.x * v.y + a.y * v.x;
   }
   u[c * n + k] = acc;
 }
 
-// nrm[c] = ||u[c]||
-__global__ void __launch_bounds__(256) norm_kernel(const double2* __restrict__ u, int64_t n, double* __restrict__ nrm) {
+// nrm[c] = ||u[c]|| (one block per vector); skipped for inactive vectors
+__global__ void __launch_bounds__(256) norm_kernel(const double2* __restrict__ u, int64_t n, double* __restrict__ nrm,
+                                                   const int32_t* __restrict__ active) {
   const int64_t c = blockIdx.x;
+  if (active && !active[c]) return;
   double s = 0;
   for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
     const double2 a = u[c * n + k];
@@ -110,37 +102,39 @@ __global__ void __launch_bounds__(256) norm_kernel(const double2* __restrict__ u
 __global__ void scale_kernel(const double2* __restrict__ in, double2* __restrict__ out, int64_t n,
                              const double* __restrict__ nrm, const int32_t* __restrict__ active) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
-  if (k >= n || !active[c]) return;
+  if (k >= n || (active && !active[c])) return;
   const double s = nrm[c] > 0 ? 1.0 / nrm[c] : 0.0;
   const double2 a = in[c * n + k];
   out[c * n + k] = make_double2(a.x * s, a.y * s);
 }
 
-// h[i][c] += d[i][c] for i < jp1
+// h[k] += d[k]
 __global__ void add_coef_kernel(double2* __restrict__ h, const double2* __restrict__ d, int64_t total) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= total) return;
   h[k] = make_double2(h[k].x + d[k].x, h[k].y + d[k].y);
 }
 
-// r[c] = b[c] - r[c]
+// r = b - r
 __global__ void sub_from_kernel(const double2* __restrict__ b, double2* __restrict__ r, int64_t total) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= total) return;
   r[k] = make_double2(b[k].x - r[k].x, b[k].y - r[k].y);
 }
 
+// Per right-hand side state, right-hand side index fastest (coalesced).
 struct GmresState {
-  double2* H;      // [c][(m+1) * m], column-major in (row i, col j): H[c][j*(m+1)+i]
-  double2* cs;     // [c][m]
-  double2* sn;     // [c][m]
-  double2* g;      // [c][m+1]
-  double2* hcol;   // [i][c] current column (m+1 rows)
+  double2* H;      // column j, row i at [(j * (m + 1) + i) * nrhs + c]
+  double2* cs;     // [i * nrhs + c]
+  double2* sn;     // [i * nrhs + c]
+  double2* g;      // [i * nrhs + c], i <= m
+  double2* hcol;   // new column, [i * nrhs + c]
   double* nrm;     // [c]
   double* bnorm;   // [c]
   double* res;     // [c] residual estimate / bnorm
   int32_t* active; // [c]
-  int32_t* kc;     // [c] Krylov dimension reached
+  int32_t* kc;     // [c] Krylov dimension reached in this cycle
+  int32_t* its;    // [c] iterations spent (all cycles)
 };
 
 // Start a cycle: g = beta e1, active = beta/bnorm > tol, kc = 0.
@@ -148,8 +142,8 @@ __global__ void cycle_init_kernel(GmresState st, int64_t m, int64_t nrhs, double
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nrhs) return;
   const double beta = st.nrm[c];
-  for (int64_t i = 0; i <= m; ++i) st.g[c * (m + 1) + i] = make_double2(0, 0);
-  st.g[c * (m + 1)] = make_double2(beta, 0);
+  for (int64_t i = 0; i <= m; ++i) st.g[i * nrhs + c] = make_double2(0, 0);
+  st.g[c] = make_double2(beta, 0);
   const double r = st.bnorm[c] > 0 ? beta / st.bnorm[c] : 0.0;
   st.res[c] = r;
   st.active[c] = r > tol ? 1 : 0;
@@ -157,77 +151,71 @@ __global__ void cycle_init_kernel(GmresState st, int64_t m, int64_t nrhs, double
 }
 
 // Column j of the Hessenberg matrix from hcol (rows 0..j) and nrm (row j+1);
-// apply previous rotations, form the new one, update g, test convergence.
+// apply the previous rotations, form the new one, update g, test convergence.
 __global__ void givens_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs, double tol) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nrhs || !st.active[c]) return;
-  double2* H = st.H + c * (m + 1) * m + j * (m + 1);
-  for (int64_t i = 0; i <= j; ++i) H[i] = st.hcol[i * nrhs + c];
-  H[j + 1] = make_double2(st.nrm[c], 0);
-  double2* cs = st.cs + c * m;
-  double2* sn = st.sn + c * m;
+  double2 a = st.hcol[c];
   for (int64_t i = 0; i < j; ++i) {
-    const double2 a = H[i], b = H[i + 1], cc = cs[i], ss = sn[i];
+    const double2 b = st.hcol[(i + 1) * nrhs + c], cc = st.cs[i * nrhs + c], ss = st.sn[i * nrhs + c];
     // t = c a + s b ;  b' = -conj(s) a + conj(c) b
     const double2 t = make_double2(cc.x * a.x - cc.y * a.y + ss.x * b.x - ss.y * b.y,
                                    cc.x * a.y + cc.y * a.x + ss.x * b.y + ss.y * b.x);
     const double2 b2 = make_double2(-(ss.x * a.x + ss.y * a.y) + (cc.x * b.x + cc.y * b.y),
                                     -(ss.x * a.y - ss.y * a.x) + (cc.x * b.y - cc.y * b.x));
-    H[i] = t;
-    H[i + 1] = b2;
+    st.H[(j * (m + 1) + i) * nrhs + c] = t;
+    a = b2;
   }
-  const double2 a = H[j], b = H[j + 1];
-  const double den = sqrt(a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y);
+  const double2 b = make_double2(st.nrm[c], 0);
+  const double den = sqrt(a.x * a.x + a.y * a.y + b.x * b.x);
   double2 cc = make_double2(1, 0), ss = make_double2(0, 0);
   if (den > 0) {
     cc = make_double2(a.x / den, -a.y / den);  // conj(a)/den
-    ss = make_double2(b.x / den, -b.y / den);  // conj(b)/den
+    ss = make_double2(b.x / den, 0.0);         // conj(b)/den, b real
   }
-  cs[j] = cc;
-  sn[j] = ss;
-  H[j] = make_double2(den, 0);
-  H[j + 1] = make_double2(0, 0);
-  double2* g = st.g + c * (m + 1);
-  const double2 gj = g[j];
+  st.cs[j * nrhs + c] = cc;
+  st.sn[j * nrhs + c] = ss;
+  st.H[(j * (m + 1) + j) * nrhs + c] = make_double2(den, 0);
+  const double2 gj = st.g[j * nrhs + c];
   // g[j+1] = -conj(s) g[j];  g[j] = c g[j]
-  g[j + 1] = make_double2(-(ss.x * gj.x + ss.y * gj.y), -(ss.x * gj.y - ss.y * gj.x));
-  g[j] = make_double2(cc.x * gj.x - cc.y * gj.y, cc.x * gj.y + cc.y * gj.x);
-  const double r = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y) / st.bnorm[c];
+  const double2 gn = make_double2(-(ss.x * gj.x + ss.y * gj.y), -(ss.x * gj.y - ss.y * gj.x));
+  st.g[(j + 1) * nrhs + c] = gn;
+  st.g[j * nrhs + c] = make_double2(cc.x * gj.x - cc.y * gj.y, cc.x * gj.y + cc.y * gj.x);
+  const double r = sqrt(gn.x * gn.x + gn.y * gn.y) / st.bnorm[c];
   st.res[c] = r;
   st.kc[c] = (int32_t)(j + 1);
+  st.its[c] += 1;
   if (r <= tol || den == 0.0) st.active[c] = 0;
 }
 
-// y = H^{-1} g over the first kc[c] rows (upper triangular); stored in g.
+// y = H^{-1} g over the first kc[c] rows (upper triangular), in place in g.
 __global__ void backsolve_kernel(GmresState st, int64_t m, int64_t nrhs) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nrhs) return;
   const int64_t k = st.kc[c];
-  const double2* H = st.H + c * (m + 1) * m;
-  double2* g = st.g + c * (m + 1);
   for (int64_t i = k - 1; i >= 0; --i) {
-    double2 s = g[i];
+    double2 s = st.g[i * nrhs + c];
     for (int64_t l = i + 1; l < k; ++l) {
-      const double2 h = H[l * (m + 1) + i], y = g[l];
+      const double2 h = st.H[(l * (m + 1) + i) * nrhs + c], y = st.g[l * nrhs + c];
       s.x -= h.x * y.x - h.y * y.y;
       s.y -= h.x * y.y + h.y * y.x;
     }
-    const double2 d = H[i * (m + 1) + i];
+    const double2 d = st.H[(i * (m + 1) + i) * nrhs + c];
     const double dd = d.x * d.x + d.y * d.y;
-    g[i] = dd > 0 ? make_double2((s.x * d.x + s.y * d.y) / dd, (s.y * d.x - s.x * d.y) / dd) : make_double2(0, 0);
+    st.g[i * nrhs + c] =
+        dd > 0 ? make_double2((s.x * d.x + s.y * d.y) / dd, (s.y * d.x - s.x * d.y) / dd) : make_double2(0, 0);
   }
 }
 
-// x[c] += sum_{i < kc[c]} y[c][i] V[i][c]
+// x[c] += sum_{i < kc[c]} y[i][c] V[i][c]
 __global__ void x_update_kernel(GmresState st, const double2* __restrict__ V, int64_t vstride, double2* __restrict__ x,
-                                int64_t n, int64_t m) {
+                                int64_t n, int64_t nrhs) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
   if (k >= n) return;
   const int64_t kc = st.kc[c];
-  const double2* y = st.g + c * (m + 1);
   double2 acc = x[c * n + k];
   for (int64_t i = 0; i < kc; ++i) {
-    const double2 a = y[i], v = V[i * vstride + c * n + k];
+    const double2 a = st.g[i * nrhs + c], v = V[i * vstride + c * n + k];
     acc.x += a.x * v.x - a.y * v.y;
     acc.y += a.x * v.y + a.y * v.x;
   }
@@ -325,13 +313,10 @@ __global__ void __launch_bounds__(256) farfield_kernel(FarArgs fa, const double2
 
 static dim3 grid2(int64_t n, int64_t m) { return dim3((unsigned)((n + 255) / 256), (unsigned)m); }
 
-// u = A w with A = Z_r (G^CBF)^{-1} (use_cmp) or Z_r; w is overwritten.
-static void apply_A(cbfm_cbf_s* c, const double2* Zr, int64_t ldz, int64_t nrhs, double2* w, double2* u, bool use_cmp,
-                    hipStream_t s) {
-  const int64_t n = 2 * c->NL;
-  if (use_cmp) cmp_apply_dev(c, nrhs, w, s);
-  // u^T (n x nrhs) = Z_r (n x n) w^T
-  std::vector<GemmDesc> d{gemm(Zr, ldz, OP_N, w, n, OP_T, u, n, n, nrhs, n)};
+// u = A w for row-stored vectors w (nrhs x n): u^T = A w^T.
+static void apply_op(const double2* A, int64_t lda, int64_t n, int64_t nrhs, const double2* w, double2* u,
+                     hipStream_t s) {
+  std::vector<GemmDesc> d{gemm(A, lda, OP_N, w, n, OP_T, u, n, n, nrhs, n)};
   d[0].transC = 1;
   zgemm_batched(d, s);
 }
@@ -379,90 +364,95 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
       }
       zgemm_batched(ds, s);
     }
+    // ---- operator: right-preconditioned A = Z_r (G^CBF)^{-1}, formed once,
+    // with (G^CBF)^{-1} = blkdiag(-(B^{-1})^H, B^{-1})
+    const double2* Aop = Zr;
+    int64_t lda = ldz;
+    Scratch Ap(use_cmp ? n * n * sizeof(double2) : 0, s);
+    if (use_cmp) {
+      const double2* Bi = cmp_inverse(c, s);
+      std::vector<GemmDesc> ds{gemm(Zr, ldz, OP_N, Bi, NL, OP_C, Ap.as<double2>(), n, n, NL, NL, -1.0),
+                               gemm(Zr + NL, ldz, OP_N, Bi, NL, OP_N, Ap.as<double2>() + NL, n, n, NL, NL)};
+      zgemm_batched(ds, s);
+      Aop = Ap.as<double2>();
+      lda = n;
+    }
     // ---- GMRES state
     Scratch V((mres + 1) * nrhs * n * sizeof(double2), s);
-    Scratch x(nrhs * n * sizeof(double2), s), w(nrhs * n * sizeof(double2), s), u(nrhs * n * sizeof(double2), s);
+    Scratch x(nrhs * n * sizeof(double2), s), u(nrhs * n * sizeof(double2), s);
     Scratch Hs(nrhs * (mres + 1) * mres * sizeof(double2), s), csb(nrhs * mres * sizeof(double2), s),
         snb(nrhs * mres * sizeof(double2), s), gb(nrhs * (mres + 1) * sizeof(double2), s),
-        hcol((mres + 1) * nrhs * sizeof(double2), s), dbl(3 * nrhs * sizeof(double), s), ints(2 * nrhs * sizeof(int32_t), s);
+        hcol((mres + 1) * nrhs * sizeof(double2), s), h2((mres + 1) * nrhs * sizeof(double2), s),
+        dbl(3 * nrhs * sizeof(double), s), ints(3 * nrhs * sizeof(int32_t), s);
     GmresState gs{Hs.as<double2>(), csb.as<double2>(), snb.as<double2>(), gb.as<double2>(), hcol.as<double2>(),
                   dbl.as<double>(), dbl.as<double>() + nrhs, dbl.as<double>() + 2 * nrhs, ints.as<int32_t>(),
-                  ints.as<int32_t>() + nrhs};
+                  ints.as<int32_t>() + nrhs, ints.as<int32_t>() + 2 * nrhs};
     const int64_t vstride = nrhs * n;
+    const dim3 g1((unsigned)((nrhs + 63) / 64)), b1(64);
     CBFM_HIP(hipMemsetAsync(x.p, 0, nrhs * n * sizeof(double2), s));
-    hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, b.as<double2>(), n, gs.bnorm);
-    std::vector<int32_t> its(nrhs, 0), act(nrhs), done(nrhs, 0);
+    CBFM_HIP(hipMemsetAsync(gs.its, 0, nrhs * sizeof(int32_t), s));
+    hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, b.as<double2>(), n, gs.bnorm, nullptr);
+    std::vector<int32_t> act(nrhs), its(nrhs, 0);
     std::vector<double> res(nrhs, 1.0);
-    std::vector<int32_t> all_active(nrhs, 1);
-    Scratch allact(nrhs * sizeof(int32_t), s);
-    CBFM_HIP(hipMemcpyAsync(allact.p, all_active.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
     int64_t total = 0;
     const double tol = prm->tol;
+    const int check_every = 4;  // iterations between host convergence checks
+    auto any_active = [&]() {
+      CBFM_HIP(hipMemcpyAsync(act.data(), gs.active, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      CBFM_HIP(hipStreamSynchronize(s));
+      return std::any_of(act.begin(), act.end(), [](int32_t a) { return a != 0; });
+    };
     for (;;) {
       // r = b - A x  (x = 0 on the first cycle)
       double2* r = u.as<double2>();
       if (total == 0) {
         CBFM_HIP(hipMemcpyAsync(r, b.p, nrhs * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
       } else {
-        CBFM_HIP(hipMemcpyAsync(w.p, x.p, nrhs * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
-        apply_A(c, Zr, ldz, nrhs, w.as<double2>(), r, use_cmp, s);
+        apply_op(Aop, lda, n, nrhs, x.as<double2>(), r, s);
         hipLaunchKernelGGL(sub_from_kernel, dim3((unsigned)((nrhs * n + 255) / 256)), dim3(256), 0, s, b.as<double2>(), r,
                            nrhs * n);
       }
-      hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, r, n, gs.nrm);
-      hipLaunchKernelGGL(cycle_init_kernel, dim3((unsigned)((nrhs + 63) / 64)), dim3(64), 0, s, gs, mres, nrhs, tol);
-      hipLaunchKernelGGL(scale_kernel, grid2(n, nrhs), dim3(256), 0, s, r, V.as<double2>(), n, gs.nrm, allact.as<int32_t>());
-      CBFM_HIP(hipMemcpyAsync(act.data(), gs.active, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      CBFM_HIP(hipStreamSynchronize(s));
-      if (std::none_of(act.begin(), act.end(), [](int32_t a) { return a != 0; })) break;
-      if (total >= prm->max_iter) break;
+      hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, r, n, gs.nrm, nullptr);
+      hipLaunchKernelGGL(cycle_init_kernel, g1, b1, 0, s, gs, mres, nrhs, tol);
+      hipLaunchKernelGGL(scale_kernel, grid2(n, nrhs), dim3(256), 0, s, r, V.as<double2>(), n, gs.nrm, nullptr);
+      if (!any_active() || total >= prm->max_iter) break;
       for (int64_t j = 0; j < mres && total < prm->max_iter; ++j) {
-        double2* Vj = V.as<double2>() + j * vstride;
+        const double2* Vj = V.as<double2>() + j * vstride;
         double2* Vn = V.as<double2>() + (j + 1) * vstride;
-        CBFM_HIP(hipMemcpyAsync(w.p, Vj, nrhs * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
-        apply_A(c, Zr, ldz, nrhs, w.as<double2>(), u.as<double2>(), use_cmp, s);
-        // classical Gram-Schmidt, twice
-        for (int pass = 0; pass < 2; ++pass) {
-          double2* hc = pass == 0 ? gs.hcol : w.as<double2>();  // second pass coefficients in scratch w
-          hipLaunchKernelGGL(dots_kernel, dim3((unsigned)(j + 1), (unsigned)nrhs), dim3(256), 0, s, V.as<double2>(),
-                             vstride, u.as<double2>(), n, nrhs, gs.active, hc, nrhs, 0);
-          hipLaunchKernelGGL(orth_update_kernel, grid2(n, nrhs), dim3(256), 0, s, V.as<double2>(), vstride,
-                             u.as<double2>(), n, j + 1, gs.active, hc, nrhs);
-          if (pass == 1)  // Hessenberg column = first + second pass coefficients
-            hipLaunchKernelGGL(add_coef_kernel, dim3((unsigned)(((j + 1) * nrhs + 255) / 256)), dim3(256), 0, s, gs.hcol,
-                               w.as<double2>(), (j + 1) * nrhs);
-        }
-        hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, u.as<double2>(), n, gs.nrm);
+        apply_op(Aop, lda, n, nrhs, Vj, u.as<double2>(), s);
+        // classical Gram-Schmidt, twice; Hessenberg column = sum of both passes
+        const dim3 gd((unsigned)(((j + 1) * nrhs + 3) / 4));
+        hipLaunchKernelGGL(dots_kernel, gd, dim3(256), 0, s, V.as<double2>(), vstride, u.as<double2>(), n, nrhs, j + 1,
+                           gs.active, gs.hcol);
+        hipLaunchKernelGGL(orth_update_kernel, grid2(n, nrhs), dim3(256), 0, s, V.as<double2>(), vstride,
+                           u.as<double2>(), n, j + 1, nrhs, gs.active, gs.hcol);
+        hipLaunchKernelGGL(dots_kernel, gd, dim3(256), 0, s, V.as<double2>(), vstride, u.as<double2>(), n, nrhs, j + 1,
+                           gs.active, h2.as<double2>());
+        hipLaunchKernelGGL(orth_update_kernel, grid2(n, nrhs), dim3(256), 0, s, V.as<double2>(), vstride,
+                           u.as<double2>(), n, j + 1, nrhs, gs.active, h2.as<double2>());
+        hipLaunchKernelGGL(add_coef_kernel, dim3((unsigned)(((j + 1) * nrhs + 255) / 256)), dim3(256), 0, s, gs.hcol,
+                           h2.as<double2>(), (j + 1) * nrhs);
+        hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, u.as<double2>(), n, gs.nrm, gs.active);
         hipLaunchKernelGGL(scale_kernel, grid2(n, nrhs), dim3(256), 0, s, u.as<double2>(), Vn, n, gs.nrm, gs.active);
-        hipLaunchKernelGGL(givens_kernel, dim3((unsigned)((nrhs + 63) / 64)), dim3(64), 0, s, gs, mres, j, nrhs, tol);
+        hipLaunchKernelGGL(givens_kernel, g1, b1, 0, s, gs, mres, j, nrhs, tol);
         CBFM_HIP(hipGetLastError());
         ++total;
-        CBFM_HIP(hipMemcpyAsync(act.data(), gs.active, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        CBFM_HIP(hipStreamSynchronize(s));
-        for (int64_t q = 0; q < nrhs; ++q)
-          if (!done[q]) its[q] = (int32_t)total;
-        for (int64_t q = 0; q < nrhs; ++q)
-          if (!act[q]) done[q] = 1;
-        if (std::none_of(act.begin(), act.end(), [](int32_t a) { return a != 0; })) break;
+        if ((j + 1) % check_every == 0 && !any_active()) break;
       }
-      hipLaunchKernelGGL(backsolve_kernel, dim3((unsigned)((nrhs + 63) / 64)), dim3(64), 0, s, gs, mres, nrhs);
+      hipLaunchKernelGGL(backsolve_kernel, g1, b1, 0, s, gs, mres, nrhs);
       hipLaunchKernelGGL(x_update_kernel, grid2(n, nrhs), dim3(256), 0, s, gs, V.as<double2>(), vstride, x.as<double2>(),
-                         n, mres);
+                         n, nrhs);
       CBFM_HIP(hipGetLastError());
-      std::fill(done.begin(), done.end(), 0);
-      if (total >= prm->max_iter) {
-        // final residual check below
-        break;
-      }
+      if (total >= prm->max_iter) break;
     }
+    CBFM_HIP(hipMemcpyAsync(its.data(), gs.its, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     // true relative residual of the preconditioned system
     {
       double2* r = u.as<double2>();
-      CBFM_HIP(hipMemcpyAsync(w.p, x.p, nrhs * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
-      apply_A(c, Zr, ldz, nrhs, w.as<double2>(), r, use_cmp, s);
+      apply_op(Aop, lda, n, nrhs, x.as<double2>(), r, s);
       hipLaunchKernelGGL(sub_from_kernel, dim3((unsigned)((nrhs * n + 255) / 256)), dim3(256), 0, s, b.as<double2>(), r,
                          nrhs * n);
-      hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, r, n, gs.nrm);
+      hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, r, n, gs.nrm, nullptr);
       std::vector<double> rn(nrhs), bn(nrhs);
       CBFM_HIP(hipMemcpyAsync(rn.data(), gs.nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
       CBFM_HIP(hipMemcpyAsync(bn.data(), gs.bnorm, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
