@@ -3,7 +3,7 @@
 // op in {N, T (transpose), C (conjugate transpose), R (conjugate)}, all
 // matrices row-major complex double with leading dimensions.
 //
-// One wavefront computes one 16 x 16 tile of C with v_mfma_f64_16x16x4_f64
+// A wavefront computes a 16 x 16 tile of C with v_mfma_f64_16x16x4_f64
 // (real): for each group of 16 k it does 4 x 4 MFMAs, the four real
 // products Ar*Br, -Ai*Bi, Ar*Bi, Ai*Br.  Lane L holds A[L % 16][k] and
 // B[k][L % 16] for k = k0 + 4 (L / 16) + t, t = 0..3 (any assignment of the
@@ -21,22 +21,36 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double2 ld_op(const double2* __restrict__ X, int64_t ld, int op, int64_t i, int64_t k,
                                          int64_t rows, int64_t cols) {
-  // element op(X)[i][k]; rows x cols is the shape of op(X); zero outside
-  if (i >= rows || k >= cols) return make_double2(0.0, 0.0);
-  double2 v;
-  if (op == OP_N || op == OP_R)
-    v = X[i * ld + k];
-  else
-    v = X[k * ld + i];
-  if (op == OP_C || op == OP_R) v.y = -v.y;
+  // element op(X)[i][k]; rows x cols is the shape of op(X); zero outside.
+  // Branch-free: an out-of-range lane loads element (0, 0) and discards it.
+  const bool ok = i < rows && k < cols;
+  const int64_t ii = ok ? i : 0, kk = ok ? k : 0;
+  const int64_t idx = (op == OP_N || op == OP_R) ? ii * ld + kk : kk * ld + ii;
+  double2 v = X[idx];
+  v.x = ok ? v.x : 0.0;
+  v.y = ok ? ((op == OP_C || op == OP_R) ? -v.y : v.y) : 0.0;
   return v;
 }
 
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(x & 0xffffffff));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// SPLITK = 1: each of the 4 wavefronts of a block owns a tile.
+// SPLITK = 4: the 4 wavefronts share one tile, each taking every 4th group
+// of 16 k, and the partial tiles are summed through LDS (few, deep tiles).
+template <int SPLITK>
 __global__ void __launch_bounds__(256) zgemm_batched_kernel(const GemmDesc* __restrict__ desc, int ndesc,
                                                             int64_t total_tiles) {
   const int lane = threadIdx.x & 63;
-  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (tile >= total_tiles) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // wave-uniform tile and descriptor (readfirstlane makes the K loop a scalar
+  // loop: the accumulators then stay in the matrix-core registers across it)
+  const int64_t tile = SPLITK == 1 ? (int64_t)blockIdx.x * 4 + wave : (int64_t)blockIdx.x;
+  __shared__ double red[SPLITK == 1 ? 1 : 3 * 64 * 8];
+  if (tile >= total_tiles) return;  // uniform per block when SPLITK == 4
   // descriptor holding this tile (tile_start ascending)
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
@@ -46,7 +60,18 @@ __global__ void __launch_bounds__(256) zgemm_batched_kernel(const GemmDesc* __re
     else
       hi = mid - 1;
   }
-  const GemmDesc d = desc[lo];
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  GemmDesc d = desc[lo];
+  // the descriptor is wave-uniform: keep its sizes in scalar registers
+  d.M = uniform64(d.M);
+  d.N = uniform64(d.N);
+  d.K = uniform64(d.K);
+  d.lda = uniform64(d.lda);
+  d.ldb = uniform64(d.ldb);
+  d.ldc = uniform64(d.ldc);
+  d.tile_start = uniform64(d.tile_start);
+  d.opA = __builtin_amdgcn_readfirstlane(d.opA);
+  d.opB = __builtin_amdgcn_readfirstlane(d.opB);
   const int64_t t = tile - d.tile_start;
   const int64_t ntn = (d.N + 15) / 16;
   const int64_t m0 = (t / ntn) * 16, n0 = (t % ntn) * 16;
@@ -54,13 +79,28 @@ __global__ void __launch_bounds__(256) zgemm_batched_kernel(const GemmDesc* __re
   const int64_t jb = n0 + (lane & 15);  // column of op(B) this lane loads
   const int slot = lane >> 4;
   dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-  for (int64_t k0 = 0; k0 < d.K; k0 += 16) {
-    double2 a[4], b[4];
+  const int64_t kstep = 16 * SPLITK;
+  int64_t k0 = SPLITK == 1 ? 0 : 16 * wave;
+  double2 a[4], b[4];
+  if (k0 < d.K) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int64_t k = k0 + 4 * slot + s;
       a[s] = ld_op(d.A, d.lda, d.opA, ia, k, d.M, d.K);
       b[s] = ld_op(d.B, d.ldb, d.opB, k, jb, d.K, d.N);
+    }
+  }
+  for (; k0 < d.K; k0 += kstep) {
+    // prefetch the next group while the matrix cores work on this one
+    double2 an[4], bn[4];
+    const int64_t k1 = k0 + kstep;
+    if (k1 < d.K) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t k = k1 + 4 * slot + s;
+        an[s] = ld_op(d.A, d.lda, d.opA, ia, k, d.M, d.K);
+        bn[s] = ld_op(d.B, d.ldb, d.opB, k, jb, d.K, d.N);
+      }
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -69,11 +109,38 @@ __global__ void __launch_bounds__(256) zgemm_batched_kernel(const GemmDesc* __re
       ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].x, b[s].y, ci, 0, 0, 0);
       ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].y, b[s].x, ci, 0, 0, 0);
     }
+    if (k1 < d.K) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        a[s] = an[s];
+        b[s] = bn[s];
+      }
+    }
+  }
+  if (SPLITK > 1) {
+    // waves 1..3 hand their partial tiles to wave 0
+    if (wave > 0) {
+      double* r = red + ((wave - 1) * 64 + lane) * 8;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        r[q] = cr[q];
+        r[4 + q] = ci[q];
+      }
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      const double* r = red + (w * 64 + lane) * 8;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cr[q] += r[q];
+        ci[q] += r[4 + q];
+      }
+    }
   }
   const int64_t col = n0 + (lane & 15);
   if (col >= d.N) return;
-  // (transposed stores write 4 rows of one column per lane; plain stores one
-  // column of 4 rows, 16 lanes side by side)
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int64_t row = m0 + 4 * r + slot;
@@ -105,10 +172,14 @@ void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s) {
   if (live.empty()) return;
   Scratch dev(live.size() * sizeof(GemmDesc), s);
   CBFM_HIP(hipMemcpyAsync(dev.p, live.data(), live.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
-  const int64_t blocks = (tiles + 3) / 4;
   TimedLaunch tl(T_GEMM, s);
-  hipLaunchKernelGGL(zgemm_batched_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dev.as<GemmDesc>(),
-                     (int)live.size(), tiles);
+  // few tiles: one tile per block, K split over its 4 wavefronts
+  if (tiles < 4096)
+    hipLaunchKernelGGL(zgemm_batched_kernel<4>, dim3((unsigned)tiles), dim3(256), 0, s, dev.as<GemmDesc>(),
+                       (int)live.size(), tiles);
+  else
+    hipLaunchKernelGGL(zgemm_batched_kernel<1>, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s,
+                       dev.as<GemmDesc>(), (int)live.size(), tiles);
   CBFM_HIP(hipGetLastError());
   // the descriptor staging buffer is host memory of this frame
   CBFM_HIP(hipStreamSynchronize(s));

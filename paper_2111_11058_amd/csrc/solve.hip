@@ -7,8 +7,8 @@
 //   sigma = k0^2 / (4 pi) |eta0 N_perp - rhat x L|^2
 //
 // GMRES runs on the device for all right-hand sides at once, each with its
-// own Krylov space (Saad's GMRES with classical Gram-Schmidt applied twice
-// and complex Givens rotations).  Matrix-vector products are matrix-core
+// own Krylov space (Saad's GMRES; classical Gram-Schmidt with selective
+// re-orthogonalisation; complex Givens rotations).  Matrix-vector products are matrix-core
 // GEMMs over all right-hand sides; the Hessenberg updates run one thread per
 // right-hand side.  The host only reads the convergence flags each step.
 #include <algorithm>
@@ -70,6 +70,7 @@ __global__ void orth_update_kernel(const double2* __restrict__ V, int64_t vstrid
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
   if (k >= n || !active[c]) return;
   double2 acc = u[c * n + k];
+#pragma unroll 4
   for (int64_t i = 0; i < jp1; ++i) {
     const double2 a = h[i * nrhs + c], v = V[i * vstride + c * n + k];
     acc.x -= a.x * v.x - a.y * v.y;
@@ -108,11 +109,22 @@ __global__ void scale_kernel(const double2* __restrict__ in, double2* __restrict
   out[c * n + k] = make_double2(a.x * s, a.y * s);
 }
 
-// h[k] += d[k]
-__global__ void add_coef_kernel(double2* __restrict__ h, const double2* __restrict__ d, int64_t total) {
+// h[i][c] += d[i][c] where mask[c] (second Gram-Schmidt pass taken)
+__global__ void add_coef_kernel(double2* __restrict__ h, const double2* __restrict__ d, int64_t total, int64_t nrhs,
+                                const int32_t* __restrict__ mask) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= total) return;
+  if (k >= total || !mask[k % nrhs]) return;
   h[k] = make_double2(h[k].x + d[k].x, h[k].y + d[k].y);
+}
+
+// Selective re-orthogonalisation (Daniel-Gragg-Kaufman-Stewart): a second
+// classical Gram-Schmidt pass only where the first one removed more than
+// 1 - 1/sqrt(2) of the vector's norm.
+__global__ void reorth_mask_kernel(const double* __restrict__ before, const double* __restrict__ after,
+                                   const int32_t* __restrict__ active, int32_t* __restrict__ mask, int64_t nrhs) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nrhs) return;
+  mask[c] = active[c] && after[c] < 0.7071067811865476 * before[c];
 }
 
 // r = b - r
@@ -156,8 +168,15 @@ __global__ void givens_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs,
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nrhs || !st.active[c]) return;
   double2 a = st.hcol[c];
+  double2 bq = j > 0 ? st.hcol[nrhs + c] : make_double2(0, 0);
+  double2 cq = j > 0 ? st.cs[c] : make_double2(0, 0), sq = j > 0 ? st.sn[c] : make_double2(0, 0);
   for (int64_t i = 0; i < j; ++i) {
-    const double2 b = st.hcol[(i + 1) * nrhs + c], cc = st.cs[i * nrhs + c], ss = st.sn[i * nrhs + c];
+    const double2 b = bq, cc = cq, ss = sq;
+    if (i + 1 < j) {  // next operands, independent of the rotation chain
+      bq = st.hcol[(i + 2) * nrhs + c];
+      cq = st.cs[(i + 1) * nrhs + c];
+      sq = st.sn[(i + 1) * nrhs + c];
+    }
     // t = c a + s b ;  b' = -conj(s) a + conj(c) b
     const double2 t = make_double2(cc.x * a.x - cc.y * a.y + ss.x * b.x - ss.y * b.y,
                                    cc.x * a.y + cc.y * a.x + ss.x * b.y + ss.y * b.x);
@@ -188,22 +207,28 @@ __global__ void givens_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs,
   if (r <= tol || den == 0.0) st.active[c] = 0;
 }
 
-// y = H^{-1} g over the first kc[c] rows (upper triangular), in place in g.
-__global__ void backsolve_kernel(GmresState st, int64_t m, int64_t nrhs) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nrhs) return;
+// y = H^{-1} g over the first kc[c] rows (upper triangular), in place in g;
+// one block per right-hand side, column-oriented back substitution.
+__global__ void __launch_bounds__(256) backsolve_kernel(GmresState st, int64_t m, int64_t nrhs) {
+  const int64_t c = blockIdx.x;
   const int64_t k = st.kc[c];
+  __shared__ double2 yi;
   for (int64_t i = k - 1; i >= 0; --i) {
-    double2 s = st.g[i * nrhs + c];
-    for (int64_t l = i + 1; l < k; ++l) {
-      const double2 h = st.H[(l * (m + 1) + i) * nrhs + c], y = st.g[l * nrhs + c];
-      s.x -= h.x * y.x - h.y * y.y;
-      s.y -= h.x * y.y + h.y * y.x;
+    if (threadIdx.x == 0) {
+      const double2 s = st.g[i * nrhs + c], d = st.H[(i * (m + 1) + i) * nrhs + c];
+      const double dd = d.x * d.x + d.y * d.y;
+      yi = dd > 0 ? make_double2((s.x * d.x + s.y * d.y) / dd, (s.y * d.x - s.x * d.y) / dd) : make_double2(0, 0);
+      st.g[i * nrhs + c] = yi;
     }
-    const double2 d = st.H[(i * (m + 1) + i) * nrhs + c];
-    const double dd = d.x * d.x + d.y * d.y;
-    st.g[i * nrhs + c] =
-        dd > 0 ? make_double2((s.x * d.x + s.y * d.y) / dd, (s.y * d.x - s.x * d.y) / dd) : make_double2(0, 0);
+    __syncthreads();
+    const double2 y = yi;
+    for (int64_t t = threadIdx.x; t < i; t += blockDim.x) {
+      const double2 h = st.H[(i * (m + 1) + t) * nrhs + c];
+      double2* gt = st.g + t * nrhs + c;
+      gt->x -= h.x * y.x - h.y * y.y;
+      gt->y -= h.x * y.y + h.y * y.x;
+    }
+    __syncthreads();
   }
 }
 
@@ -383,7 +408,8 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
     Scratch Hs(nrhs * (mres + 1) * mres * sizeof(double2), s), csb(nrhs * mres * sizeof(double2), s),
         snb(nrhs * mres * sizeof(double2), s), gb(nrhs * (mres + 1) * sizeof(double2), s),
         hcol((mres + 1) * nrhs * sizeof(double2), s), h2((mres + 1) * nrhs * sizeof(double2), s),
-        dbl(3 * nrhs * sizeof(double), s), ints(3 * nrhs * sizeof(int32_t), s);
+        dbl(3 * nrhs * sizeof(double), s), ints(3 * nrhs * sizeof(int32_t), s), nrm0(nrhs * sizeof(double), s),
+        mask2(nrhs * sizeof(int32_t), s);
     GmresState gs{Hs.as<double2>(), csb.as<double2>(), snb.as<double2>(), gb.as<double2>(), hcol.as<double2>(),
                   dbl.as<double>(), dbl.as<double>() + nrhs, dbl.as<double>() + 2 * nrhs, ints.as<int32_t>(),
                   ints.as<int32_t>() + nrhs, ints.as<int32_t>() + 2 * nrhs};
@@ -420,26 +446,33 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
         const double2* Vj = V.as<double2>() + j * vstride;
         double2* Vn = V.as<double2>() + (j + 1) * vstride;
         apply_op(Aop, lda, n, nrhs, Vj, u.as<double2>(), s);
-        // classical Gram-Schmidt, twice; Hessenberg column = sum of both passes
+        // classical Gram-Schmidt with selective re-orthogonalisation; the
+        // Hessenberg column is the sum of the passes taken
         const dim3 gd((unsigned)(((j + 1) * nrhs + 3) / 4));
+        hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, u.as<double2>(), n, nrm0.as<double>(),
+                           gs.active);
         hipLaunchKernelGGL(dots_kernel, gd, dim3(256), 0, s, V.as<double2>(), vstride, u.as<double2>(), n, nrhs, j + 1,
                            gs.active, gs.hcol);
         hipLaunchKernelGGL(orth_update_kernel, grid2(n, nrhs), dim3(256), 0, s, V.as<double2>(), vstride,
                            u.as<double2>(), n, j + 1, nrhs, gs.active, gs.hcol);
-        hipLaunchKernelGGL(dots_kernel, gd, dim3(256), 0, s, V.as<double2>(), vstride, u.as<double2>(), n, nrhs, j + 1,
-                           gs.active, h2.as<double2>());
-        hipLaunchKernelGGL(orth_update_kernel, grid2(n, nrhs), dim3(256), 0, s, V.as<double2>(), vstride,
-                           u.as<double2>(), n, j + 1, nrhs, gs.active, h2.as<double2>());
-        hipLaunchKernelGGL(add_coef_kernel, dim3((unsigned)(((j + 1) * nrhs + 255) / 256)), dim3(256), 0, s, gs.hcol,
-                           h2.as<double2>(), (j + 1) * nrhs);
         hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, u.as<double2>(), n, gs.nrm, gs.active);
+        hipLaunchKernelGGL(reorth_mask_kernel, g1, b1, 0, s, nrm0.as<double>(), gs.nrm, gs.active, mask2.as<int32_t>(),
+                           nrhs);
+        hipLaunchKernelGGL(dots_kernel, gd, dim3(256), 0, s, V.as<double2>(), vstride, u.as<double2>(), n, nrhs, j + 1,
+                           mask2.as<int32_t>(), h2.as<double2>());
+        hipLaunchKernelGGL(orth_update_kernel, grid2(n, nrhs), dim3(256), 0, s, V.as<double2>(), vstride,
+                           u.as<double2>(), n, j + 1, nrhs, mask2.as<int32_t>(), h2.as<double2>());
+        hipLaunchKernelGGL(add_coef_kernel, dim3((unsigned)(((j + 1) * nrhs + 255) / 256)), dim3(256), 0, s, gs.hcol,
+                           h2.as<double2>(), (j + 1) * nrhs, nrhs, mask2.as<int32_t>());
+        hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, u.as<double2>(), n, gs.nrm,
+                           mask2.as<int32_t>());
         hipLaunchKernelGGL(scale_kernel, grid2(n, nrhs), dim3(256), 0, s, u.as<double2>(), Vn, n, gs.nrm, gs.active);
         hipLaunchKernelGGL(givens_kernel, g1, b1, 0, s, gs, mres, j, nrhs, tol);
         CBFM_HIP(hipGetLastError());
         ++total;
         if ((j + 1) % check_every == 0 && !any_active()) break;
       }
-      hipLaunchKernelGGL(backsolve_kernel, g1, b1, 0, s, gs, mres, nrhs);
+      hipLaunchKernelGGL(backsolve_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, mres, nrhs);
       hipLaunchKernelGGL(x_update_kernel, grid2(n, nrhs), dim3(256), 0, s, gs, V.as<double2>(), vstride, x.as<double2>(),
                          n, nrhs);
       CBFM_HIP(hipGetLastError());
