@@ -4,9 +4,14 @@
 // build:  per cell m
 //   Z_mm   = cell block of [[K, -TE], [TH, K]]            (fill kernels, FP64)
 //   J_m    = Z_mm^{-1} V_m  for the generating waves      (batched LU)
-//   G'_m   = (J^M)^H G_m J^J, G_m the rotated RWG Gram     (matrix-core GEMM)
-//   G'_m   = U S V^H, keep sigma_i / sigma_1 >= delta_svd (batched SVD)
+//   G'_m   = (J^M)^H G_m J^J, G_m the rotated RWG Gram
+//   G'_m   = U S V^H, keep sigma_i / sigma_1 >= delta_svd
 //   C^M_m  = J^M U_L,  C^J_m = J^J V_L
+// The SVD is taken of an r x r core, r = min(s, N_m): with the QR
+// factorisations (J^M)^H = Q_M R_M and (J^J)^H = Q_J R_J (batched geqrf),
+// G'_m = Q_M (R_M G_m R_J^H) Q_J^H, so with R_M G_m R_J^H = U_c S V_c^H the
+// singular values are those of G'_m and, since J^M Q_M = R_M^H,
+// C^M_m = R_M^H U_c,L and C^J_m = R_J^H V_c,L (matrix-core GEMMs).
 // G_m is taken in closed form: for two RWGs a != b of one triangle with
 // counter-clockwise local indices, int (n x f_a) . f_b = e_ab l_a l_b / 6
 // times the RWG signs, e_ab = +1 if b follows a cyclically, -1 otherwise;
@@ -115,6 +120,32 @@ __global__ void pack_v_kernel(const double2* __restrict__ v, int64_t ne, const i
   else if (r < 2 * N)
     x = v[(int64_t)c * 2 * ne + ne + ed[r - N]];
   out[(int64_t)c * n + r] = x;
+}
+
+// From a cell's solved currents J = [J^M; J^J] (column-major n x S, the
+// magnetic rows first), write (J^M)^H and (J^J)^H as column-major S x Nmax
+// matrices (blockIdx.z picks which), zero beyond the cell's N columns.
+__global__ void pack_jh_kernel(const double2* __restrict__ J, int n, int S, int N, int Nmax,
+                               double2* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y, w = blockIdx.z;
+  if (r >= S) return;
+  double2 x = make_double2(0.0, 0.0);
+  if (c < N) {
+    x = J[(int64_t)r * n + w * N + c];
+    x.y = -x.y;
+  }
+  out[(int64_t)w * S * Nmax + (int64_t)c * S + r] = x;
+}
+
+// Row-major r x Nmax copy of the triangular factor that geqrf left in the
+// upper triangle of a column-major S x Nmax matrix (blockIdx.z: M or J).
+__global__ void extract_r_kernel(const double2* __restrict__ qr, int S, int N, int Nmax, int rk,
+                                 double2* __restrict__ R) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y, w = blockIdx.z;
+  if (j >= Nmax) return;
+  double2 x = make_double2(0.0, 0.0);
+  if (i <= j && j < N) x = qr[(int64_t)w * S * Nmax + (int64_t)j * S + i];
+  R[(int64_t)w * rk * Nmax + (int64_t)i * Nmax + j] = x;
 }
 
 // GC[m][col] = sum_n G[perm[m], n] C^J_full[n][col], rows in internal order.
@@ -344,41 +375,64 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
     CBFM_HIP(hipStreamSynchronize(s));
     for (int b = 0; b < nb; ++b)
       CBFM_REQUIRE(hinfo[b] == 0, CBFM_E_RANK, "cell " + std::to_string(b) + ": Z_mm is singular");
-    // G'_m (column-major s x s) = transpose of the row-major -Jt_J G_m conj(J^M)
+    // QR of (J^M)^H and (J^J)^H (column-major S x Nmax, zero-padded)
+    const int rk = std::min(S, Nmax);
+    Scratch QA((size_t)nb * 2 * S * Nmax * sizeof(double2), s);
+    Scratch tau((size_t)nb * 2 * rk * sizeof(double2), s);
+    for (int b = 0; b < nb; ++b) {
+      const int Nb = (int)cs[b].edges.size();
+      hipLaunchKernelGGL(pack_jh_kernel, dim3((S + 255) / 256, Nmax, 2), dim3(256), 0, s,
+                         Vpad.as<double2>() + (size_t)b * n * S, n, S, Nb, Nmax,
+                         QA.as<double2>() + (size_t)b * 2 * S * Nmax);
+    }
+    CBFM_HIP(hipGetLastError());
+    {
+      std::lock_guard<std::mutex> lk(blas_mutex());
+      rocblas_handle bh = blas_handle(s);
+      CBFM_RS(rocsolver_zgeqrf_strided_batched(bh, S, Nmax, (rocblas_double_complex*)QA.p, S,
+                                               (rocblas_stride)S * Nmax, (rocblas_double_complex*)tau.p,
+                                               (rocblas_stride)rk, 2 * nb));
+    }
+    // R factors (row-major rk x Nmax) and the core X = C^T, C = R_M G_m R_J^H
+    // (G_m real antisymmetric: X = conj(R_J) G_m^T R_M^T = -conj(R_J) G_m R_M^T)
+    Scratch Rf((size_t)nb * 2 * rk * Nmax * sizeof(double2), s);
     Scratch Gm((size_t)nb * Nmax * Nmax * sizeof(double2), s);
-    Scratch T2((size_t)nb * Nmax * S * sizeof(double2), s);
-    Scratch Gp((size_t)nb * S * S * sizeof(double2), s);
+    Scratch T2((size_t)nb * Nmax * rk * sizeof(double2), s);
+    Scratch core((size_t)nb * rk * rk * sizeof(double2), s);
     std::vector<GemmDesc> d1, d2;
     for (int b = 0; b < nb; ++b) {
       const int Nb = (int)cs[b].edges.size();
+      double2* R = Rf.as<double2>() + (size_t)b * 2 * rk * Nmax;  // R_M, then R_J
+      hipLaunchKernelGGL(extract_r_kernel, dim3((Nmax + 255) / 256, rk, 2), dim3(256), 0, s,
+                         QA.as<double2>() + (size_t)b * 2 * S * Nmax, S, Nb, Nmax, rk, R);
       double2* G = Gm.as<double2>() + (size_t)b * Nmax * Nmax;
       hipLaunchKernelGGL(cell_gram_kernel, dim3((Nb + 255) / 256, Nb), dim3(256), 0, s, ptr[b].edges, Nb,
                          m->tplus.as<int32_t>(), m->tminus.as<int32_t>(), m->aplus.as<int32_t>(),
                          m->aminus.as<int32_t>(), m->tri_edge.as<int32_t>(), m->tri_sign.as<int32_t>(),
                          m->length.as<double>(), G);
-      const double2* V = Vpad.as<double2>() + (size_t)b * n * S;  // Jt_M at V, Jt_J at V + Nb (ld n)
-      double2* t2 = T2.as<double2>() + (size_t)b * Nmax * S;
-      d1.push_back(gemm(G, Nb, OP_N, V, n, OP_C, t2, S, Nb, S, Nb));
-      d2.push_back(gemm(V + Nb, n, OP_N, t2, S, OP_N, Gp.as<double2>() + (size_t)b * S * S, S, S, S, Nb, -1.0));
+      double2* t2 = T2.as<double2>() + (size_t)b * Nmax * rk;
+      d1.push_back(gemm(G, Nb, OP_N, R, Nmax, OP_T, t2, rk, Nb, rk, Nb));
+      d2.push_back(gemm(R + (size_t)rk * Nmax, Nmax, OP_R, t2, rk, OP_N, core.as<double2>() + (size_t)b * rk * rk, rk,
+                        rk, rk, Nb, -1.0));
     }
     CBFM_HIP(hipGetLastError());
     zgemm_batched(d1, s);
     zgemm_batched(d2, s);
-    // SVD
-    Scratch sv((size_t)nb * S * sizeof(double), s);
-    Scratch U((size_t)nb * S * S * sizeof(double2), s);
-    Scratch Vh((size_t)nb * S * S * sizeof(double2), s);
-    Scratch E((size_t)nb * S * sizeof(double), s);
+    // SVD of the cores
+    Scratch sv((size_t)nb * rk * sizeof(double), s);
+    Scratch U((size_t)nb * rk * rk * sizeof(double2), s);
+    Scratch Vh((size_t)nb * rk * rk * sizeof(double2), s);
+    Scratch E((size_t)nb * rk * sizeof(double), s);
     {
       std::lock_guard<std::mutex> lk(blas_mutex());
       rocblas_handle bh = blas_handle(s);
       CBFM_RS(rocsolver_zgesvd_strided_batched(
-          bh, rocblas_svect_singular, rocblas_svect_singular, S, S, (rocblas_double_complex*)Gp.p, S,
-          (rocblas_stride)S * S, sv.as<double>(), S, (rocblas_double_complex*)U.p, S, (rocblas_stride)S * S,
-          (rocblas_double_complex*)Vh.p, S, (rocblas_stride)S * S, E.as<double>(), S, rocblas_outofplace,
+          bh, rocblas_svect_singular, rocblas_svect_singular, rk, rk, (rocblas_double_complex*)core.p, rk,
+          (rocblas_stride)rk * rk, sv.as<double>(), rk, (rocblas_double_complex*)U.p, rk, (rocblas_stride)rk * rk,
+          (rocblas_double_complex*)Vh.p, rk, (rocblas_stride)rk * rk, E.as<double>(), rk, rocblas_outofplace,
           info.as<rocblas_int>(), nb));
     }
-    std::vector<double> hs((size_t)nb * S);
+    std::vector<double> hs((size_t)nb * rk);
     CBFM_HIP(hipMemcpyAsync(hs.data(), sv.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     CBFM_HIP(hipMemcpyAsync(hinfo.data(), info.p, nb * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
     CBFM_HIP(hipStreamSynchronize(s));
@@ -389,10 +443,10 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
       c->mesh = m;
       c->L.resize(nb);
       for (int b = 0; b < nb; ++b) {
-        const double* sb = &hs[(size_t)b * S];
+        const double* sb = &hs[(size_t)b * rk];
         int L = 0;
         const int Nb = (int)cs[b].edges.size();
-        while (L < S && L < Nb && sb[L] > 0 && sb[L] >= prm->delta_svd * sb[0]) ++L;
+        while (L < rk && L < Nb && sb[L] > 0 && sb[L] >= prm->delta_svd * sb[0]) ++L;
         if (prm->max_L > 0) L = std::min(L, prm->max_L);
         CBFM_REQUIRE(L > 0, CBFM_E_RANK, "cell " + std::to_string(b) + " keeps no CBF");
         c->L[b] = L;
@@ -401,14 +455,15 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
       cbf_finish(c);
       c->CM.alloc(std::max<int64_t>(1, c->coff[nb]) * sizeof(double2));
       c->CJ.alloc(std::max<int64_t>(1, c->coff[nb]) * sizeof(double2));
+      // C^M = R_M^H U_c,L and C^J = R_J^H V_c,L (U_c column-major, V_c^H column-major)
       std::vector<GemmDesc> d3;
       for (int b = 0; b < nb; ++b) {
         const int Nb = (int)cs[b].edges.size();
-        const double2* V = Vpad.as<double2>() + (size_t)b * n * S;
-        d3.push_back(gemm(V, n, OP_T, U.as<double2>() + (size_t)b * S * S, S, OP_T, c->CM.as<double2>() + c->coff[b],
-                          c->L[b], Nb, c->L[b], S));
-        d3.push_back(gemm(V + Nb, n, OP_T, Vh.as<double2>() + (size_t)b * S * S, S, OP_R,
-                          c->CJ.as<double2>() + c->coff[b], c->L[b], Nb, c->L[b], S));
+        const double2* R = Rf.as<double2>() + (size_t)b * 2 * rk * Nmax;
+        d3.push_back(gemm(R, Nmax, OP_C, U.as<double2>() + (size_t)b * rk * rk, rk, OP_T,
+                          c->CM.as<double2>() + c->coff[b], c->L[b], Nb, c->L[b], rk));
+        d3.push_back(gemm(R + (size_t)rk * Nmax, Nmax, OP_C, Vh.as<double2>() + (size_t)b * rk * rk, rk, OP_R,
+                          c->CJ.as<double2>() + c->coff[b], c->L[b], Nb, c->L[b], rk));
       }
       zgemm_batched(d3, s);
     } catch (...) {
