@@ -38,17 +38,33 @@ __global__ void permute_kernel(const double2* __restrict__ in, double2* __restri
   }
 }
 
-// h[i * nrhs + c] = sum_k conj(V[i][c][k]) u[c][k] for i <= j; one wavefront
-// per (i, c) dot product, four per block
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// Sum over a block of 256 threads, the same order on every call.
+__device__ inline double block_sum256(double s, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  __syncthreads();  // sh may still be read from a previous call
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// h[i * nrhs + c] = sum_k conj(V[i][c][k]) u[c][k] for i < jp1 and, with
+// self != 0, h[jp1 * nrhs + c] = ||u[c]||^2; one wavefront per dot product,
+// four per block, only for right-hand sides with flag[c].
 __global__ void __launch_bounds__(256) dots_kernel(const double2* __restrict__ V, int64_t vstride,
                                                    const double2* __restrict__ u, int64_t n, int64_t nrhs, int64_t jp1,
-                                                   const int32_t* __restrict__ active, double2* __restrict__ h) {
+                                                   int self, const int32_t* __restrict__ flag,
+                                                   double2* __restrict__ h) {
   const int64_t id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (id >= jp1 * nrhs) return;
+  if (id >= (jp1 + self) * nrhs) return;
   const int64_t i = id / nrhs, c = id % nrhs;
-  if (!active[c]) return;
-  const double2* v = V + i * vstride + c * n;
+  if (!flag[c]) return;
+  const double2* v = i < jp1 ? V + i * vstride + c * n : u + c * n;
   const double2* w = u + c * n;
   double re = 0, im = 0;
   for (int64_t k = lane; k < n; k += 64) {
@@ -63,20 +79,70 @@ __global__ void __launch_bounds__(256) dots_kernel(const double2* __restrict__ V
   if (lane == 0) h[i * nrhs + c] = make_double2(re, im);
 }
 
-// u[c] -= sum_{i<=j} h[i][c] V[i][c]
-__global__ void orth_update_kernel(const double2* __restrict__ V, int64_t vstride, double2* __restrict__ u, int64_t n,
-                                   int64_t jp1, int64_t nrhs, const int32_t* __restrict__ active,
-                                   const double2* __restrict__ h) {
+// One classical Gram-Schmidt update u[c] -= sum_{i<jp1} h[i][c] V[i][c] for
+// the right-hand sides with flag[c]; each block stores the partial sum of
+// |u|^2 over its rows in part[c * gridDim.x + blockIdx.x].  Block 0 of each
+// right-hand side also
+//  - first pass (mask given): sets mask[c] when the projection removed more
+//    than half of the squared norm, sum_i |h_i|^2 > ||u||^2 / 2 with ||u||^2
+//    in h[jp1] -- the Daniel-Gragg-Kaufman-Stewart test (after < before /
+//    sqrt 2) for a second pass;
+//  - second pass (hsum given): adds h into hsum, so that the Hessenberg column
+//    is the sum of both passes.
+__global__ void __launch_bounds__(256) orth_update_kernel(const double2* __restrict__ V, int64_t vstride,
+                                                          double2* __restrict__ u, int64_t n, int64_t jp1, int64_t nrhs,
+                                                          const int32_t* __restrict__ flag, const double2* h,
+                                                          double* __restrict__ part, int32_t* __restrict__ mask,
+                                                          double2* hsum) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
-  if (k >= n || !active[c]) return;
-  double2 acc = u[c * n + k];
-#pragma unroll 4
-  for (int64_t i = 0; i < jp1; ++i) {
-    const double2 a = h[i * nrhs + c], v = V[i * vstride + c * n + k];
-    acc.x -= a.x * v.x - a.y * v.y;
-    acc.y -= a.x * v.y + a.y * v.x;
+  if (!flag[c]) {  // uniform over the block
+    if (mask && blockIdx.x == 0 && threadIdx.x == 0) mask[c] = 0;
+    return;
   }
-  u[c * n + k] = acc;
+  __shared__ double sh[4];
+  double s = 0;
+  if (k < n) {
+    double2 acc = u[c * n + k];
+#pragma unroll 4
+    for (int64_t i = 0; i < jp1; ++i) {
+      const double2 a = h[i * nrhs + c], v = V[i * vstride + c * n + k];
+      acc.x -= a.x * v.x - a.y * v.y;
+      acc.y -= a.x * v.y + a.y * v.x;
+    }
+    u[c * n + k] = acc;
+    s = acc.x * acc.x + acc.y * acc.y;
+  }
+  s = block_sum256(s, sh);
+  if (threadIdx.x == 0) part[c * gridDim.x + blockIdx.x] = s;
+  if (blockIdx.x != 0) return;
+  if (mask) {
+    double q = 0;
+    for (int64_t i = threadIdx.x; i < jp1; i += blockDim.x) {
+      const double2 a = h[i * nrhs + c];
+      q += a.x * a.x + a.y * a.y;
+    }
+    q = block_sum256(q, sh);
+    if (threadIdx.x == 0) mask[c] = q > 0.5 * h[jp1 * nrhs + c].x ? 1 : 0;
+  }
+  if (hsum)
+    for (int64_t i = threadIdx.x; i < jp1; i += blockDim.x) hsum[i * nrhs + c] = cadd(hsum[i * nrhs + c], h[i * nrhs + c]);
+}
+
+// nrm[c] = sqrt(sum of the np partial sums of |u[c]|^2); out[c] = u[c] / nrm[c]
+// (zero if nrm[c] == 0); only right-hand sides with flag[c]
+__global__ void normalize_kernel(const double2* __restrict__ u, double2* __restrict__ out, int64_t n,
+                                 const double* __restrict__ part, int np, double* __restrict__ nrm,
+                                 const int32_t* __restrict__ flag) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (!flag[c]) return;
+  double q = 0;
+  for (int b = 0; b < np; ++b) q += part[c * np + b];
+  const double nr = sqrt(q);
+  if (blockIdx.x == 0 && threadIdx.x == 0) nrm[c] = nr;
+  if (k >= n) return;
+  const double sc = nr > 0 ? 1.0 / nr : 0.0;
+  const double2 a = u[c * n + k];
+  out[c * n + k] = make_double2(a.x * sc, a.y * sc);
 }
 
 // nrm[c] = ||u[c]|| (one block per vector); skipped for inactive vectors
@@ -89,42 +155,19 @@ __global__ void __launch_bounds__(256) norm_kernel(const double2* __restrict__ u
     const double2 a = u[c * n + k];
     s += a.x * a.x + a.y * a.y;
   }
-  __shared__ double sh[256];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) nrm[c] = sqrt(sh[0]);
+  __shared__ double sh[4];
+  s = block_sum256(s, sh);
+  if (threadIdx.x == 0) nrm[c] = sqrt(s);
 }
 
-// out[c] = in[c] / nrm[c] (zero if nrm[c] == 0); only active vectors
+// out[c] = in[c] / nrm[c] (zero if nrm[c] == 0)
 __global__ void scale_kernel(const double2* __restrict__ in, double2* __restrict__ out, int64_t n,
-                             const double* __restrict__ nrm, const int32_t* __restrict__ active) {
+                             const double* __restrict__ nrm) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
-  if (k >= n || (active && !active[c])) return;
+  if (k >= n) return;
   const double s = nrm[c] > 0 ? 1.0 / nrm[c] : 0.0;
   const double2 a = in[c * n + k];
   out[c * n + k] = make_double2(a.x * s, a.y * s);
-}
-
-// h[i][c] += d[i][c] where mask[c] (second Gram-Schmidt pass taken)
-__global__ void add_coef_kernel(double2* __restrict__ h, const double2* __restrict__ d, int64_t total, int64_t nrhs,
-                                const int32_t* __restrict__ mask) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= total || !mask[k % nrhs]) return;
-  h[k] = make_double2(h[k].x + d[k].x, h[k].y + d[k].y);
-}
-
-// Selective re-orthogonalisation (Daniel-Gragg-Kaufman-Stewart): a second
-// classical Gram-Schmidt pass only where the first one removed more than
-// 1 - 1/sqrt(2) of the vector's norm.
-__global__ void reorth_mask_kernel(const double* __restrict__ before, const double* __restrict__ after,
-                                   const int32_t* __restrict__ active, int32_t* __restrict__ mask, int64_t nrhs) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nrhs) return;
-  mask[c] = active[c] && after[c] < 0.7071067811865476 * before[c];
 }
 
 // r = b - r
@@ -162,29 +205,49 @@ __global__ void cycle_init_kernel(GmresState st, int64_t m, int64_t nrhs, double
   st.kc[c] = 0;
 }
 
-// Column j of the Hessenberg matrix from hcol (rows 0..j) and nrm (row j+1);
+// Column j of the Hessenberg matrix from hcol (rows 0..j) and nrm (row j+1):
 // apply the previous rotations, form the new one, update g, test convergence.
-__global__ void givens_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs, double tol) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nrhs || !st.active[c]) return;
-  double2 a = st.hcol[c];
-  double2 bq = j > 0 ? st.hcol[nrhs + c] : make_double2(0, 0);
-  double2 cq = j > 0 ? st.cs[c] : make_double2(0, 0), sq = j > 0 ? st.sn[c] : make_double2(0, 0);
-  for (int64_t i = 0; i < j; ++i) {
-    const double2 b = bq, cc = cq, ss = sq;
-    if (i + 1 < j) {  // next operands, independent of the rotation chain
-      bq = st.hcol[(i + 2) * nrhs + c];
-      cq = st.cs[(i + 1) * nrhs + c];
-      sq = st.sn[(i + 1) * nrhs + c];
-    }
-    // t = c a + s b ;  b' = -conj(s) a + conj(c) b
-    const double2 t = make_double2(cc.x * a.x - cc.y * a.y + ss.x * b.x - ss.y * b.y,
-                                   cc.x * a.y + cc.y * a.x + ss.x * b.y + ss.y * b.x);
-    const double2 b2 = make_double2(-(ss.x * a.x + ss.y * a.y) + (cc.x * b.x + cc.y * b.y),
-                                    -(ss.x * a.y - ss.y * a.x) + (cc.x * b.y - cc.y * b.x));
-    st.H[(j * (m + 1) + i) * nrhs + c] = t;
-    a = b2;
+// One wavefront per right-hand side.  Rotation i maps (a_i, h_{i+1}) to
+// (c_i a_i + s_i h_{i+1}, a_{i+1}) with a_{i+1} = -conj(s_i) a_i + conj(c_i)
+// h_{i+1}, a_0 = h_0: the carried a_i follow an affine recurrence, so each
+// lane composes the maps of a contiguous run of rotations, a scan over the
+// lanes gives every run its incoming a_i, and the runs are then replayed in
+// parallel.
+__global__ void __launch_bounds__(256) givens_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs, double tol) {
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= nrhs || !st.active[c]) return;  // uniform over the wavefront
+  const int64_t K = (j + 63) / 64;
+  const int64_t i0 = std::min<int64_t>(j, lane * K), i1 = std::min<int64_t>(j, i0 + K);
+  double2 P = make_double2(1, 0), Q = make_double2(0, 0);
+  for (int64_t i = i0; i < i1; ++i) {
+    const double2 sn = st.sn[i * nrhs + c], cs = st.cs[i * nrhs + c], b = st.hcol[(i + 1) * nrhs + c];
+    const double2 Pi = make_double2(-sn.x, sn.y);  // -conj(s_i)
+    const double2 Qi = cmul(make_double2(cs.x, -cs.y), b);
+    Q = cadd(cmul(Pi, Q), Qi);
+    P = cmul(Pi, P);
   }
+  // inclusive scan: after it, (P, Q) maps a_0 to the carry leaving this run
+  for (int off = 1; off < 64; off <<= 1) {
+    const double2 Po = make_double2(__shfl_up(P.x, off, 64), __shfl_up(P.y, off, 64));
+    const double2 Qo = make_double2(__shfl_up(Q.x, off, 64), __shfl_up(Q.y, off, 64));
+    if (lane >= off) {
+      Q = cadd(cmul(P, Qo), Q);
+      P = cmul(P, Po);
+    }
+  }
+  const double2 a0 = st.hcol[c];
+  const double2 Pe = make_double2(__shfl_up(P.x, 1, 64), __shfl_up(P.y, 1, 64));
+  const double2 Qe = make_double2(__shfl_up(Q.x, 1, 64), __shfl_up(Q.y, 1, 64));
+  double2 a = lane == 0 ? a0 : cadd(cmul(Pe, a0), Qe);
+  for (int64_t i = i0; i < i1; ++i) {
+    const double2 sn = st.sn[i * nrhs + c], cs = st.cs[i * nrhs + c], b = st.hcol[(i + 1) * nrhs + c];
+    st.H[(j * (m + 1) + i) * nrhs + c] = cadd(cmul(cs, a), cmul(sn, b));
+    a = cadd(cmul(make_double2(-sn.x, sn.y), a), cmul(make_double2(cs.x, -cs.y), b));
+  }
+  const int last = j == 0 ? 0 : (int)((j - 1) / K);  // lane that ends with a_j
+  a = make_double2(__shfl(a.x, last, 64), __shfl(a.y, last, 64));
+  if (lane != 0) return;
   const double2 b = make_double2(st.nrm[c], 0);
   const double den = sqrt(a.x * a.x + a.y * a.y + b.x * b.x);
   double2 cc = make_double2(1, 0), ss = make_double2(0, 0);
@@ -336,6 +399,44 @@ __global__ void __launch_bounds__(256) farfield_kernel(FarArgs fa, const double2
   }
 }
 
+// Device flags read back through pinned host memory: post() queues a copy
+// and an event, wait() blocks on the last posted copy; sync_read() copies and
+// waits at once.
+struct PinnedFlags {
+  int64_t n;
+  int32_t* host = nullptr;
+  hipEvent_t ev = nullptr;
+  bool posted = false;
+  explicit PinnedFlags(int64_t count) : n(count) {
+    CBFM_HIP(hipHostMalloc((void**)&host, n * sizeof(int32_t), hipHostMallocDefault));
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipHostFree(host);
+      throw Error{CBFM_E_HIP, "hipEventCreate failed"};
+    }
+  }
+  ~PinnedFlags() {
+    if (posted) (void)hipEventSynchronize(ev);
+    (void)hipEventDestroy(ev);
+    (void)hipHostFree(host);
+  }
+  PinnedFlags(const PinnedFlags&) = delete;
+  PinnedFlags& operator=(const PinnedFlags&) = delete;
+  void post(const int32_t* dev, hipStream_t s) {
+    CBFM_HIP(hipMemcpyAsync(host, dev, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    CBFM_HIP(hipEventRecord(ev, s));
+    posted = true;
+  }
+  const int32_t* wait() {
+    if (posted) CBFM_HIP(hipEventSynchronize(ev));
+    posted = false;
+    return host;
+  }
+  const int32_t* sync_read(const int32_t* dev, hipStream_t s) {
+    post(dev, s);
+    return wait();
+  }
+};
+
 static dim3 grid2(int64_t n, int64_t m) { return dim3((unsigned)((n + 255) / 256), (unsigned)m); }
 
 // u = A w for row-stored vectors w (nrhs x n): u^T = A w^T.
@@ -405,28 +506,32 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
     // ---- GMRES state
     Scratch V((mres + 1) * nrhs * n * sizeof(double2), s);
     Scratch x(nrhs * n * sizeof(double2), s), u(nrhs * n * sizeof(double2), s);
+    const int np = (int)((n + 255) / 256);  // partial norm sums per vector
     Scratch Hs(nrhs * (mres + 1) * mres * sizeof(double2), s), csb(nrhs * mres * sizeof(double2), s),
         snb(nrhs * mres * sizeof(double2), s), gb(nrhs * (mres + 1) * sizeof(double2), s),
-        hcol((mres + 1) * nrhs * sizeof(double2), s), h2((mres + 1) * nrhs * sizeof(double2), s),
-        dbl(3 * nrhs * sizeof(double), s), ints(3 * nrhs * sizeof(int32_t), s), nrm0(nrhs * sizeof(double), s),
+        hcol((mres + 2) * nrhs * sizeof(double2), s), h2((mres + 1) * nrhs * sizeof(double2), s),
+        dbl(3 * nrhs * sizeof(double), s), ints(3 * nrhs * sizeof(int32_t), s), part(nrhs * np * sizeof(double), s),
         mask2(nrhs * sizeof(int32_t), s);
     GmresState gs{Hs.as<double2>(), csb.as<double2>(), snb.as<double2>(), gb.as<double2>(), hcol.as<double2>(),
                   dbl.as<double>(), dbl.as<double>() + nrhs, dbl.as<double>() + 2 * nrhs, ints.as<int32_t>(),
                   ints.as<int32_t>() + nrhs, ints.as<int32_t>() + 2 * nrhs};
     const int64_t vstride = nrhs * n;
-    const dim3 g1((unsigned)((nrhs + 63) / 64)), b1(64);
+    const dim3 g1((unsigned)((nrhs + 63) / 64)), b1(64), g4((unsigned)((nrhs + 3) / 4));
     CBFM_HIP(hipMemsetAsync(x.p, 0, nrhs * n * sizeof(double2), s));
     CBFM_HIP(hipMemsetAsync(gs.its, 0, nrhs * sizeof(int32_t), s));
     hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, b.as<double2>(), n, gs.bnorm, nullptr);
-    std::vector<int32_t> act(nrhs), its(nrhs, 0);
+    std::vector<int32_t> its(nrhs, 0);
     std::vector<double> res(nrhs, 1.0);
     int64_t total = 0;
     const double tol = prm->tol;
-    const int check_every = 4;  // iterations between host convergence checks
-    auto any_active = [&]() {
-      CBFM_HIP(hipMemcpyAsync(act.data(), gs.active, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      CBFM_HIP(hipStreamSynchronize(s));
-      return std::any_of(act.begin(), act.end(), [](int32_t a) { return a != 0; });
+    // Convergence flags go to pinned host memory every few iterations and are
+    // read one check later, so the host never waits for the device inside a
+    // cycle; iterations queued after the last right-hand side converged do
+    // nothing (every kernel skips inactive right-hand sides).
+    const int check_every = 4;
+    PinnedFlags flags(nrhs);
+    auto all_done = [&](const int32_t* a) {
+      return std::none_of(a, a + nrhs, [](int32_t v) { return v != 0; });
     };
     for (;;) {
       // r = b - A x  (x = 0 on the first cycle)
@@ -440,37 +545,35 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
       }
       hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, r, n, gs.nrm, nullptr);
       hipLaunchKernelGGL(cycle_init_kernel, g1, b1, 0, s, gs, mres, nrhs, tol);
-      hipLaunchKernelGGL(scale_kernel, grid2(n, nrhs), dim3(256), 0, s, r, V.as<double2>(), n, gs.nrm, nullptr);
-      if (!any_active() || total >= prm->max_iter) break;
+      hipLaunchKernelGGL(scale_kernel, grid2(n, nrhs), dim3(256), 0, s, r, V.as<double2>(), n, gs.nrm);
+      if (all_done(flags.sync_read(gs.active, s)) || total >= prm->max_iter) break;
+      int pending = 0;  // flag copies queued in this cycle
       for (int64_t j = 0; j < mres && total < prm->max_iter; ++j) {
         const double2* Vj = V.as<double2>() + j * vstride;
         double2* Vn = V.as<double2>() + (j + 1) * vstride;
         apply_op(Aop, lda, n, nrhs, Vj, u.as<double2>(), s);
-        // classical Gram-Schmidt with selective re-orthogonalisation; the
-        // Hessenberg column is the sum of the passes taken
-        const dim3 gd((unsigned)(((j + 1) * nrhs + 3) / 4));
-        hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, u.as<double2>(), n, nrm0.as<double>(),
-                           gs.active);
-        hipLaunchKernelGGL(dots_kernel, gd, dim3(256), 0, s, V.as<double2>(), vstride, u.as<double2>(), n, nrhs, j + 1,
-                           gs.active, gs.hcol);
+        // classical Gram-Schmidt; a second pass where the first removed most
+        // of the vector (the Hessenberg column is the sum of the passes)
+        hipLaunchKernelGGL(dots_kernel, dim3((unsigned)(((j + 2) * nrhs + 3) / 4)), dim3(256), 0, s, V.as<double2>(),
+                           vstride, u.as<double2>(), n, nrhs, j + 1, 1, gs.active, gs.hcol);
         hipLaunchKernelGGL(orth_update_kernel, grid2(n, nrhs), dim3(256), 0, s, V.as<double2>(), vstride,
-                           u.as<double2>(), n, j + 1, nrhs, gs.active, gs.hcol);
-        hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, u.as<double2>(), n, gs.nrm, gs.active);
-        hipLaunchKernelGGL(reorth_mask_kernel, g1, b1, 0, s, nrm0.as<double>(), gs.nrm, gs.active, mask2.as<int32_t>(),
-                           nrhs);
-        hipLaunchKernelGGL(dots_kernel, gd, dim3(256), 0, s, V.as<double2>(), vstride, u.as<double2>(), n, nrhs, j + 1,
-                           mask2.as<int32_t>(), h2.as<double2>());
+                           u.as<double2>(), n, j + 1, nrhs, gs.active, gs.hcol, part.as<double>(), mask2.as<int32_t>(),
+                           nullptr);
+        hipLaunchKernelGGL(dots_kernel, dim3((unsigned)(((j + 1) * nrhs + 3) / 4)), dim3(256), 0, s, V.as<double2>(),
+                           vstride, u.as<double2>(), n, nrhs, j + 1, 0, mask2.as<int32_t>(), h2.as<double2>());
         hipLaunchKernelGGL(orth_update_kernel, grid2(n, nrhs), dim3(256), 0, s, V.as<double2>(), vstride,
-                           u.as<double2>(), n, j + 1, nrhs, mask2.as<int32_t>(), h2.as<double2>());
-        hipLaunchKernelGGL(add_coef_kernel, dim3((unsigned)(((j + 1) * nrhs + 255) / 256)), dim3(256), 0, s, gs.hcol,
-                           h2.as<double2>(), (j + 1) * nrhs, nrhs, mask2.as<int32_t>());
-        hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, u.as<double2>(), n, gs.nrm,
-                           mask2.as<int32_t>());
-        hipLaunchKernelGGL(scale_kernel, grid2(n, nrhs), dim3(256), 0, s, u.as<double2>(), Vn, n, gs.nrm, gs.active);
-        hipLaunchKernelGGL(givens_kernel, g1, b1, 0, s, gs, mres, j, nrhs, tol);
+                           u.as<double2>(), n, j + 1, nrhs, mask2.as<int32_t>(), h2.as<double2>(), part.as<double>(),
+                           nullptr, gs.hcol);
+        hipLaunchKernelGGL(normalize_kernel, grid2(n, nrhs), dim3(256), 0, s, u.as<double2>(), Vn, n, part.as<double>(),
+                           np, gs.nrm, gs.active);
+        hipLaunchKernelGGL(givens_kernel, g4, dim3(256), 0, s, gs, mres, j, nrhs, tol);
         CBFM_HIP(hipGetLastError());
         ++total;
-        if ((j + 1) % check_every == 0 && !any_active()) break;
+        if ((j + 1) % check_every == 0) {
+          if (pending > 0 && all_done(flags.wait())) break;
+          flags.post(gs.active, s);
+          ++pending;
+        }
       }
       hipLaunchKernelGGL(backsolve_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, mres, nrhs);
       hipLaunchKernelGGL(x_update_kernel, grid2(n, nrhs), dim3(256), 0, s, gs, V.as<double2>(), vstride, x.as<double2>(),
