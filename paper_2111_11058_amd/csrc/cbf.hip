@@ -8,10 +8,12 @@
 //   G'_m   = U S V^H, keep sigma_i / sigma_1 >= delta_svd
 //   C^M_m  = J^M U_L,  C^J_m = J^J V_L
 // The SVD is taken of an r x r core, r = min(s, N_m): with the QR
-// factorisations (J^M)^H = Q_M R_M and (J^J)^H = Q_J R_J (batched geqrf),
-// G'_m = Q_M (R_M G_m R_J^H) Q_J^H, so with R_M G_m R_J^H = U_c S V_c^H the
-// singular values are those of G'_m and, since J^M Q_M = R_M^H,
-// C^M_m = R_M^H U_c,L and C^J_m = R_J^H V_c,L (matrix-core GEMMs).
+// factorisations (J^M)^H = Q_M R_M and (J^J)^H = Q_J R_J (Householder, R
+// only), G'_m = Q_M X Q_J^H with X = R_M G_m R_J^H, so with X = U_c S V_c^H
+// the singular values are those of G'_m and, since J^M Q_M = R_M^H,
+// C^M_m = R_M^H U_c,L and C^J_m = R_J^H V_c,L (matrix-core GEMMs).  The
+// core's SVD is one-sided Jacobi (one block per cell) on R_X^H, X = Q_X R_X,
+// which yields S and V_c; U_c = X V_c S^{-1}.
 // G_m is taken in closed form: for two RWGs a != b of one triangle with
 // counter-clockwise local indices, int (n x f_a) . f_b = e_ab l_a l_b / 6
 // times the RWG signs, e_ab = +1 if b follows a cyclically, -1 otherwise;
@@ -137,15 +139,217 @@ __global__ void pack_jh_kernel(const double2* __restrict__ J, int n, int S, int 
   out[(int64_t)w * S * Nmax + (int64_t)c * S + r] = x;
 }
 
-// Row-major r x Nmax copy of the triangular factor that geqrf left in the
-// upper triangle of a column-major S x Nmax matrix (blockIdx.z: M or J).
-__global__ void extract_r_kernel(const double2* __restrict__ qr, int S, int N, int Nmax, int rk,
-                                 double2* __restrict__ R) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y, w = blockIdx.z;
-  if (j >= Nmax) return;
-  double2 x = make_double2(0.0, 0.0);
-  if (i <= j && j < N) x = qr[(int64_t)w * S * Nmax + (int64_t)j * S + i];
-  R[(int64_t)w * rk * Nmax + (int64_t)i * Nmax + j] = x;
+__device__ inline double wave_sum(double x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// In-place Householder QR of the column-major m x ncol matrix A (lda), only R
+// kept: afterwards the upper triangle of the first kmax = min(m, ncol) rows
+// holds R and the entries below the diagonal of the first kmax columns are
+// zero.  Reflector k is H = I - beta v v^H with v = x - alpha e_1, x the
+// column below the diagonal, alpha = -e^{i arg x_0} ||x||, beta = 2 / v^H v =
+// 1 / (||x||^2 + |x_0| ||x||).  Every thread of the block calls it; v is LDS
+// scratch of m entries, sc one LDS double.
+template <typename P>
+__device__ void householder_r(P A, int lda, int m, int ncol, double2* v, double* sc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int kmax = min(m, ncol);
+  for (int k = 0; k < kmax; ++k) {
+    P col = A + (int64_t)k * lda;
+    if (wave == 0) {
+      double q = 0;
+      for (int i = k + lane; i < m; i += 64) {
+        const double2 x = col[i];
+        q += x.x * x.x + x.y * x.y;
+      }
+      q = wave_sum(q);
+      const double nx = sqrt(q);
+      const double2 x0 = col[k];
+      const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y);
+      const double2 ph = ax0 > 0 ? make_double2(x0.x / ax0, x0.y / ax0) : make_double2(1.0, 0.0);
+      const double2 alpha = make_double2(-ph.x * nx, -ph.y * nx);
+      for (int i = k + lane; i < m; i += 64) {
+        double2 x = col[i];
+        if (i == k) x = make_double2(x.x - alpha.x, x.y - alpha.y);
+        v[i] = x;
+        col[i] = i == k ? alpha : make_double2(0.0, 0.0);
+      }
+      if (lane == 0) *sc = nx > 0 ? 1.0 / (q + ax0 * nx) : 0.0;
+    }
+    __syncthreads();
+    const double beta = *sc;
+    if (beta != 0.0) {
+      for (int j = k + 1 + wave; j < ncol; j += nw) {
+        P cj = A + (int64_t)j * lda;
+        double wr = 0, wi = 0;  // v^H a
+        for (int i = k + lane; i < m; i += 64) {
+          const double2 a = cj[i], w = v[i];
+          wr += w.x * a.x + w.y * a.y;
+          wi += w.x * a.y - w.y * a.x;
+        }
+        wr = beta * wave_sum(wr);
+        wi = beta * wave_sum(wi);
+        for (int i = k + lane; i < m; i += 64) {
+          const double2 w = v[i];
+          double2 a = cj[i];
+          a.x -= wr * w.x - wi * w.y;
+          a.y -= wr * w.y + wi * w.x;
+          cj[i] = a;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// R factors of (J^M)^H and (J^J)^H of every cell: block b takes the column-
+// major S x Nmax matrix b of qa (cell b / 2, its first N columns) and writes
+// R as row-major rk x Nmax (zero below the diagonal and beyond column N).
+__global__ void __launch_bounds__(1024) cell_qr_kernel(double2* __restrict__ qa, int S, int Nmax,
+                                                       const int32_t* __restrict__ ncell, int rk,
+                                                       double2* __restrict__ R) {
+  extern __shared__ double2 v[];  // S entries
+  __shared__ double sc;
+  const int b = blockIdx.x, N = ncell[b / 2];
+  double2* A = qa + (int64_t)b * S * Nmax;
+  householder_r(A, S, S, N, v, &sc);
+  const int kmax = min(S, N);
+  double2* Rb = R + (int64_t)b * rk * Nmax;
+  for (int64_t e = threadIdx.x; e < (int64_t)rk * Nmax; e += blockDim.x) {
+    const int i = (int)(e / Nmax), j = (int)(e % Nmax);
+    Rb[e] = (i <= j && j < N && i < kmax) ? A[(int64_t)j * S + i] : make_double2(0.0, 0.0);
+  }
+}
+
+// One-sided (Hestenes) Jacobi on the columns of the column-major nc x nc
+// matrix B (ldb): pairs of columns are rotated, in the round-robin order that
+// lets every wavefront of the block rotate a disjoint pair at once, until in
+// one sweep no pair has |b_p^H b_q| > tol ||b_p|| ||b_q||.  The 2 x 2 step
+// for alpha = ||b_p||^2, beta = ||b_q||^2, gamma = b_p^H b_q = |gamma| e:
+// zeta = (beta - alpha) / (2 |gamma|), t = sign(zeta) / (|zeta| +
+// sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t,
+// (b_p, b_q) <- (c b_p - s conj(e) b_q, s e b_p + c b_q).
+// Returns the number of sweeps, or -1 if max_sweeps ran out.
+template <typename P>
+__device__ int hestenes_jacobi(P B, int ldb, int nc, double tol, int max_sweeps, int* flag) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int ne = nc + (nc & 1);  // an odd count plays against an empty column
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    __syncthreads();
+    if (threadIdx.x == 0) *flag = 0;
+    __syncthreads();
+    for (int step = 0; step < ne - 1; ++step) {
+      for (int pr = wave; pr < ne / 2; pr += nw) {
+        const int qr = ne - 1 - pr;
+        const int p = pr == 0 ? 0 : 1 + (pr - 1 + step) % (ne - 1);
+        const int q = 1 + (qr - 1 + step) % (ne - 1);
+        if (p >= nc || q >= nc) continue;
+        P x = B + (int64_t)p * ldb;
+        P y = B + (int64_t)q * ldb;
+        double al = 0, be = 0, gr = 0, gi = 0;
+        for (int i = lane; i < nc; i += 64) {
+          const double2 a = x[i], c = y[i];
+          al += a.x * a.x + a.y * a.y;
+          be += c.x * c.x + c.y * c.y;
+          gr += a.x * c.x + a.y * c.y;
+          gi += a.x * c.y - a.y * c.x;
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        gr = wave_sum(gr);
+        gi = wave_sum(gi);
+        const double ag = sqrt(gr * gr + gi * gi);
+        const int rot = __shfl((al * be > 0 && ag > tol * sqrt(al * be)) ? 1 : 0, 0, 64);
+        if (!rot) continue;
+        const double z = (be - al) / (2.0 * ag);
+        const double t = (z >= 0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+        const double er = gr / ag, ei = gi / ag;
+        for (int i = lane; i < nc; i += 64) {
+          const double2 a = x[i], c = y[i];
+          // a' = cs a - sn conj(e) c ;  c' = sn e a + cs c
+          x[i] = make_double2(cs * a.x - sn * (er * c.x + ei * c.y), cs * a.y - sn * (er * c.y - ei * c.x));
+          y[i] = make_double2(sn * (er * a.x - ei * a.y) + cs * c.x, sn * (er * a.y + ei * a.x) + cs * c.y);
+        }
+        if (lane == 0) *flag = 1;
+      }
+      __syncthreads();
+    }
+    if (*flag == 0) return sweep + 1;
+  }
+  return -1;
+}
+
+// SVD of each cell's core X (column-major rk x rk, leading nc = min(N, rk)
+// block nonzero): X = Q R (Householder), then one-sided Jacobi on B = R^H,
+// B W = U~ S.  Since R = W S U~^H, X = (Q W) S U~^H: U~ are the right
+// singular vectors of X and S its singular values.  Written sorted by
+// decreasing sigma: sigma (rk per cell, zero beyond nc), Ut = U~ and
+// Uts = U~ S^{-1} (column-major rk x rk, first nc columns, zero rows beyond
+// nc), info = 0, or 1 if the sweeps ran out.  LDS = true keeps the nc x nc
+// working matrix in LDS, else in work (rk x rk per cell).
+template <bool LDS>
+__global__ void __launch_bounds__(1024) core_svd_kernel(const double2* __restrict__ X, int rk,
+                                                        const int32_t* __restrict__ ncell, double2* work, double tol,
+                                                        int max_sweeps, double* __restrict__ sigma,
+                                                        double2* __restrict__ Ut, double2* __restrict__ Uts,
+                                                        int32_t* __restrict__ info) {
+  extern __shared__ double2 lds[];
+  __shared__ double sc;
+  __shared__ int flag;
+  const int b = blockIdx.x, nc = min((int)ncell[b], rk);
+  double2* A = LDS ? lds : work + (int64_t)b * rk * rk;
+  double2* v = LDS ? lds + (int64_t)nc * nc : lds;            // nc entries
+  double* nrm = reinterpret_cast<double*>(v + nc);             // nc entries
+  int* rank = reinterpret_cast<int*>(nrm + nc);                // nc entries
+  const double2* Xb = X + (int64_t)b * rk * rk;
+  for (int64_t e = threadIdx.x; e < (int64_t)nc * nc; e += blockDim.x) {
+    const int i = (int)(e % nc), j = (int)(e / nc);
+    A[e] = Xb[(int64_t)j * rk + i];
+  }
+  __syncthreads();
+  householder_r(A, nc, nc, nc, v, &sc);
+  // B = R^H in place (lower triangular)
+  for (int64_t e = threadIdx.x; e < (int64_t)nc * nc; e += blockDim.x) {
+    const int i = (int)(e % nc), j = (int)(e / nc);
+    if (i < j) continue;
+    const double2 r = A[(int64_t)i * nc + j];  // R[j][i]
+    A[e] = make_double2(r.x, -r.y);
+    if (i > j) A[(int64_t)i * nc + j] = make_double2(0.0, 0.0);
+  }
+  const int sweeps = hestenes_jacobi(A, nc, nc, tol, max_sweeps, &flag);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int j = wave; j < nc; j += nw) {
+    double q = 0;
+    for (int i = lane; i < nc; i += 64) {
+      const double2 a = A[(int64_t)j * nc + i];
+      q += a.x * a.x + a.y * a.y;
+    }
+    q = wave_sum(q);
+    if (lane == 0) nrm[j] = sqrt(q);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nc; j += blockDim.x) {
+    int r = 0;
+    for (int k = 0; k < nc; ++k) r += (nrm[k] > nrm[j] || (nrm[k] == nrm[j] && k < j)) ? 1 : 0;
+    rank[j] = r;
+    sigma[(int64_t)b * rk + r] = nrm[j];
+  }
+  for (int j = nc + (int)threadIdx.x; j < rk; j += blockDim.x) sigma[(int64_t)b * rk + j] = 0.0;
+  __syncthreads();
+  for (int j = wave; j < nc; j += nw) {
+    const double sg = nrm[j];
+    const double s1 = sg > 0 ? 1.0 / sg : 0.0, s2 = s1 * s1;
+    double2* u = Ut + (int64_t)b * rk * rk + (int64_t)rank[j] * rk;
+    double2* us = Uts + (int64_t)b * rk * rk + (int64_t)rank[j] * rk;
+    for (int i = lane; i < rk; i += 64) {
+      const double2 a = i < nc ? A[(int64_t)j * nc + i] : make_double2(0.0, 0.0);
+      u[i] = make_double2(a.x * s1, a.y * s1);
+      us[i] = make_double2(a.x * s2, a.y * s2);
+    }
+  }
+  if (threadIdx.x == 0) info[b] = sweeps < 0 ? 1 : 0;
 }
 
 // GC[m][col] = sum_n G[perm[m], n] C^J_full[n][col], rows in internal order.
@@ -260,6 +464,28 @@ void cmp_apply_dev(cbfm_cbf_s* c, int64_t nrhs, double2* x, hipStream_t s) {
   zgemm_batched(ds, s);
 }
 
+// Dynamic LDS that a core_svd_kernel<true> block may use on the current
+// device (the kernel's attribute is raised to it once per device).
+static size_t core_svd_lds_limit() {
+  static std::mutex mu;
+  static std::map<int, size_t> limit;
+  std::lock_guard<std::mutex> lk(mu);
+  int dev = 0;
+  CBFM_HIP(hipGetDevice(&dev));
+  auto it = limit.find(dev);
+  if (it != limit.end()) return it->second;
+  int maxsh = 0;
+  CBFM_HIP(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  size_t lim = maxsh > 256 ? (size_t)maxsh - 256 : 0;  // room for the kernel's static LDS
+  if (lim > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(&core_svd_kernel<true>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess) {
+    (void)hipGetLastError();
+    lim = 65536;
+  }
+  limit[dev] = lim;
+  return lim;
+}
+
 // Per-cell support triangles and the near pairs inside it.
 struct CellSupport {
   std::vector<int32_t> tris, pos, edges;
@@ -297,6 +523,7 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
     *out = nullptr;
     CBFM_REQUIRE(prm->gen_host && prm->n_gen > 0, CBFM_E_ARG, "need generating waves");
     CBFM_REQUIRE(prm->delta_svd >= 0 && prm->delta_svd <= 1, CBFM_E_ARG, "delta_svd outside [0, 1]");
+    CBFM_REQUIRE(prm->n_gen <= 4096, CBFM_E_ARG, "n_gen above 4096");
     const Media md = make_media(med);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const MeshHost& h = m->h;
@@ -375,36 +602,31 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
     CBFM_HIP(hipStreamSynchronize(s));
     for (int b = 0; b < nb; ++b)
       CBFM_REQUIRE(hinfo[b] == 0, CBFM_E_RANK, "cell " + std::to_string(b) + ": Z_mm is singular");
-    // QR of (J^M)^H and (J^J)^H (column-major S x Nmax, zero-padded)
+    // QR of (J^M)^H and (J^J)^H (column-major S x Nmax, zero-padded): R only
     const int rk = std::min(S, Nmax);
+    std::vector<int32_t> hN(nb);
+    for (int b = 0; b < nb; ++b) hN[b] = (int32_t)cs[b].edges.size();
+    Scratch dN((size_t)nb * sizeof(int32_t), s);
+    CBFM_HIP(hipMemcpyAsync(dN.p, hN.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, s));
     Scratch QA((size_t)nb * 2 * S * Nmax * sizeof(double2), s);
-    Scratch tau((size_t)nb * 2 * rk * sizeof(double2), s);
     for (int b = 0; b < nb; ++b) {
-      const int Nb = (int)cs[b].edges.size();
       hipLaunchKernelGGL(pack_jh_kernel, dim3((S + 255) / 256, Nmax, 2), dim3(256), 0, s,
-                         Vpad.as<double2>() + (size_t)b * n * S, n, S, Nb, Nmax,
+                         Vpad.as<double2>() + (size_t)b * n * S, n, S, hN[b], Nmax,
                          QA.as<double2>() + (size_t)b * 2 * S * Nmax);
     }
+    Scratch Rf((size_t)nb * 2 * rk * Nmax * sizeof(double2), s);  // per cell R_M, then R_J
+    hipLaunchKernelGGL(cell_qr_kernel, dim3(2 * nb), dim3(1024), (size_t)S * sizeof(double2), s, QA.as<double2>(), S,
+                       Nmax, dN.as<int32_t>(), rk, Rf.as<double2>());
     CBFM_HIP(hipGetLastError());
-    {
-      std::lock_guard<std::mutex> lk(blas_mutex());
-      rocblas_handle bh = blas_handle(s);
-      CBFM_RS(rocsolver_zgeqrf_strided_batched(bh, S, Nmax, (rocblas_double_complex*)QA.p, S,
-                                               (rocblas_stride)S * Nmax, (rocblas_double_complex*)tau.p,
-                                               (rocblas_stride)rk, 2 * nb));
-    }
-    // R factors (row-major rk x Nmax) and the core X = C^T, C = R_M G_m R_J^H
-    // (G_m real antisymmetric: X = conj(R_J) G_m^T R_M^T = -conj(R_J) G_m R_M^T)
-    Scratch Rf((size_t)nb * 2 * rk * Nmax * sizeof(double2), s);
+    // core X = R_M G_m R_J^H (column-major rk x rk), computed as its row-major
+    // transpose conj(R_J) G_m^T R_M^T = -conj(R_J) G_m R_M^T (G_m antisymmetric)
     Scratch Gm((size_t)nb * Nmax * Nmax * sizeof(double2), s);
     Scratch T2((size_t)nb * Nmax * rk * sizeof(double2), s);
     Scratch core((size_t)nb * rk * rk * sizeof(double2), s);
     std::vector<GemmDesc> d1, d2;
     for (int b = 0; b < nb; ++b) {
-      const int Nb = (int)cs[b].edges.size();
-      double2* R = Rf.as<double2>() + (size_t)b * 2 * rk * Nmax;  // R_M, then R_J
-      hipLaunchKernelGGL(extract_r_kernel, dim3((Nmax + 255) / 256, rk, 2), dim3(256), 0, s,
-                         QA.as<double2>() + (size_t)b * 2 * S * Nmax, S, Nb, Nmax, rk, R);
+      const int Nb = hN[b];
+      const double2* R = Rf.as<double2>() + (size_t)b * 2 * rk * Nmax;
       double2* G = Gm.as<double2>() + (size_t)b * Nmax * Nmax;
       hipLaunchKernelGGL(cell_gram_kernel, dim3((Nb + 255) / 256, Nb), dim3(256), 0, s, ptr[b].edges, Nb,
                          m->tplus.as<int32_t>(), m->tminus.as<int32_t>(), m->aplus.as<int32_t>(),
@@ -418,26 +640,33 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
     CBFM_HIP(hipGetLastError());
     zgemm_batched(d1, s);
     zgemm_batched(d2, s);
-    // SVD of the cores
+    // SVD of the cores: right singular vectors U~ and U~ S^{-1}
     Scratch sv((size_t)nb * rk * sizeof(double), s);
-    Scratch U((size_t)nb * rk * rk * sizeof(double2), s);
-    Scratch Vh((size_t)nb * rk * rk * sizeof(double2), s);
-    Scratch E((size_t)nb * rk * sizeof(double), s);
+    Scratch Ut((size_t)nb * rk * rk * sizeof(double2), s);
+    Scratch Uts((size_t)nb * rk * rk * sizeof(double2), s);
     {
-      std::lock_guard<std::mutex> lk(blas_mutex());
-      rocblas_handle bh = blas_handle(s);
-      CBFM_RS(rocsolver_zgesvd_strided_batched(
-          bh, rocblas_svect_singular, rocblas_svect_singular, rk, rk, (rocblas_double_complex*)core.p, rk,
-          (rocblas_stride)rk * rk, sv.as<double>(), rk, (rocblas_double_complex*)U.p, rk, (rocblas_stride)rk * rk,
-          (rocblas_double_complex*)Vh.p, rk, (rocblas_stride)rk * rk, E.as<double>(), rk, rocblas_outofplace,
-          info.as<rocblas_int>(), nb));
+      const int ncmax = std::min(Nmax, rk);
+      const size_t lds = (size_t)ncmax * ncmax * sizeof(double2) + (size_t)ncmax * (sizeof(double2) + 12);
+      const double tol = std::sqrt((double)ncmax) * 2.220446049250313e-16;
+      const int max_sweeps = 60;
+      if (lds <= core_svd_lds_limit()) {
+        hipLaunchKernelGGL(core_svd_kernel<true>, dim3(nb), dim3(1024), lds, s, core.as<double2>(), rk,
+                           dN.as<int32_t>(), nullptr, tol, max_sweeps, sv.as<double>(), Ut.as<double2>(),
+                           Uts.as<double2>(), info.as<int32_t>());
+      } else {
+        Scratch work((size_t)nb * rk * rk * sizeof(double2), s);
+        hipLaunchKernelGGL(core_svd_kernel<false>, dim3(nb), dim3(1024), (size_t)ncmax * (sizeof(double2) + 12), s,
+                           core.as<double2>(), rk, dN.as<int32_t>(), work.as<double2>(), tol, max_sweeps,
+                           sv.as<double>(), Ut.as<double2>(), Uts.as<double2>(), info.as<int32_t>());
+      }
+      CBFM_HIP(hipGetLastError());
     }
     std::vector<double> hs((size_t)nb * rk);
     CBFM_HIP(hipMemcpyAsync(hs.data(), sv.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     CBFM_HIP(hipMemcpyAsync(hinfo.data(), info.p, nb * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
     CBFM_HIP(hipStreamSynchronize(s));
     for (int b = 0; b < nb; ++b)
-      CBFM_REQUIRE(hinfo[b] == 0, CBFM_E_HIP, "cell " + std::to_string(b) + ": SVD did not converge");
+      CBFM_REQUIRE(hinfo[b] == 0, CBFM_E_HIP, "cell " + std::to_string(b) + ": Jacobi SVD did not converge");
     auto* c = new cbfm_cbf_s();
     try {
       c->mesh = m;
@@ -445,7 +674,7 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
       for (int b = 0; b < nb; ++b) {
         const double* sb = &hs[(size_t)b * rk];
         int L = 0;
-        const int Nb = (int)cs[b].edges.size();
+        const int Nb = hN[b];
         while (L < rk && L < Nb && sb[L] > 0 && sb[L] >= prm->delta_svd * sb[0]) ++L;
         if (prm->max_L > 0) L = std::min(L, prm->max_L);
         CBFM_REQUIRE(L > 0, CBFM_E_RANK, "cell " + std::to_string(b) + " keeps no CBF");
@@ -455,17 +684,22 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
       cbf_finish(c);
       c->CM.alloc(std::max<int64_t>(1, c->coff[nb]) * sizeof(double2));
       c->CJ.alloc(std::max<int64_t>(1, c->coff[nb]) * sizeof(double2));
-      // C^M = R_M^H U_c,L and C^J = R_J^H V_c,L (U_c column-major, V_c^H column-major)
-      std::vector<GemmDesc> d3;
+      // C^J = R_J^H V_L with V = U~;  C^M = R_M^H U_L with U = X V S^{-1} = X U~ S^{-1}
+      Scratch W((size_t)std::max<int64_t>(1, c->coff[nb]) * sizeof(double2), s);
+      std::vector<GemmDesc> d3, d4;
       for (int b = 0; b < nb; ++b) {
-        const int Nb = (int)cs[b].edges.size();
+        const int Nb = hN[b], nc = std::min(Nb, rk), L = c->L[b];
         const double2* R = Rf.as<double2>() + (size_t)b * 2 * rk * Nmax;
-        d3.push_back(gemm(R, Nmax, OP_C, U.as<double2>() + (size_t)b * rk * rk, rk, OP_T,
-                          c->CM.as<double2>() + c->coff[b], c->L[b], Nb, c->L[b], rk));
-        d3.push_back(gemm(R + (size_t)rk * Nmax, Nmax, OP_C, Vh.as<double2>() + (size_t)b * rk * rk, rk, OP_R,
-                          c->CJ.as<double2>() + c->coff[b], c->L[b], Nb, c->L[b], rk));
+        const double2* ub = Ut.as<double2>() + (size_t)b * rk * rk;
+        const double2* usb = Uts.as<double2>() + (size_t)b * rk * rk;
+        double2* wb = W.as<double2>() + c->coff[b];  // nc x L row-major (nc <= N_b)
+        d3.push_back(gemm(core.as<double2>() + (size_t)b * rk * rk, rk, OP_T, usb, rk, OP_T, wb, L, nc, L, nc));
+        d3.push_back(gemm(R + (size_t)rk * Nmax, Nmax, OP_C, ub, rk, OP_T, c->CJ.as<double2>() + c->coff[b], L, Nb, L,
+                          nc));
+        d4.push_back(gemm(R, Nmax, OP_C, wb, L, OP_N, c->CM.as<double2>() + c->coff[b], L, Nb, L, nc));
       }
       zgemm_batched(d3, s);
+      zgemm_batched(d4, s);
     } catch (...) {
       delete c;
       throw;
