@@ -158,7 +158,7 @@ def main():
         log(f"warmup {i}")
         step(cbfm.FP64)
     torch.cuda.synchronize()
-    cbfm.timer_enable(True)
+    cbfm.timer_enable(["fill_regular"])
     proj_t, solve_t, iters = [], [], []
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -171,7 +171,7 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     nl, ms = cbfm.timer_read("fill_regular")
-    cbfm.timer_enable(False)
+    cbfm.timer_enable(None)
     nt = w.nt
     pairs_per_step = nt * nt + int((cell_supports(w) ** 2).sum())
     flops = FLOP_PER_PAIR * pairs_per_step * args.steps

@@ -98,12 +98,14 @@ int32_t cbfm_version(void);
  * Opt-in kernel timing for measurement: when enabled, the library records a
  * pair of HIP events on the launch stream around each launch of a named
  * kernel family and accumulates the elapsed times when they are read.
- * Names: "fill_regular", "fill_near", "assemble", "gemm".
- * cbfm_timer_enable(1) enables and clears all timers, (0) disables.
+ * Names: "fill_regular", "fill_near", "assemble", "gemm" (bits 0-3).
+ * cbfm_timer_enable(mask) clears all timers and times the families whose
+ * bit is set in mask (-1: all, 0: none).  Every timed launch adds two event
+ * records to its stream, so time only the families being measured.
  * cbfm_timer_read synchronises the recorded events and returns the number
  * of launches and their total duration in milliseconds (CBFM_E_ARG for an
  * unknown name).                                                           */
-cbfm_status cbfm_timer_enable(int32_t on);
+cbfm_status cbfm_timer_enable(int32_t mask);
 cbfm_status cbfm_timer_read(const char* name, int64_t* launches, double* total_ms);
 
 /* ---------------------------------------------------------------- mesh ---

@@ -125,9 +125,16 @@ def _host(a, dtype):
     return a, a.ctypes.data_as(C.c_void_p)
 
 
-def timer_enable(on=True):
-    """Enable (and clear) or disable the library's per-kernel event timers."""
-    _check(lib().cbfm_timer_enable(int(bool(on))))
+TIMERS = ("fill_regular", "fill_near", "assemble", "gemm")
+
+
+def timer_enable(names=TIMERS):
+    """Clear the library's per-kernel event timers and time the kernel
+    families in ``names`` (an empty sequence or None disables timing)."""
+    mask = 0
+    for n in names or ():
+        mask |= 1 << TIMERS.index(n)
+    _check(lib().cbfm_timer_enable(mask))
 
 
 def timer_read(name):

@@ -222,10 +222,28 @@ __global__ void __launch_bounds__(1024) cell_qr_kernel(double2* __restrict__ qa,
   }
 }
 
+// x moved across the lanes of each row of 16 by a DPP pattern.
+template <int CTRL>
+__device__ inline double dpp_double(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over each row of 16 lanes; a butterfly, so every lane of the row ends
+// with the same bits.
+__device__ inline double row16_sum(double x) {
+  x += dpp_double<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+  x += dpp_double<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+  x += dpp_double<0x141>(x);  // row_half_mirror: the other quad of the half row
+  x += dpp_double<0x140>(x);  // row_mirror: the other half row
+  return x;
+}
+
 // One-sided (Hestenes) Jacobi on the columns of the column-major nc x nc
 // matrix B (ldb): pairs of columns are rotated, in the round-robin order that
-// lets every wavefront of the block rotate a disjoint pair at once, until in
-// one sweep no pair has |b_p^H b_q| > tol ||b_p|| ||b_q||.  The 2 x 2 step
+// lets each row of 16 lanes of the block rotate a disjoint pair at once, until
+// in one sweep no pair has |b_p^H b_q| > tol ||b_p|| ||b_q||.  The 2 x 2 step
 // for alpha = ||b_p||^2, beta = ||b_q||^2, gamma = b_p^H b_q = |gamma| e:
 // zeta = (beta - alpha) / (2 |gamma|), t = sign(zeta) / (|zeta| +
 // sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t,
@@ -233,14 +251,14 @@ __global__ void __launch_bounds__(1024) cell_qr_kernel(double2* __restrict__ qa,
 // Returns the number of sweeps, or -1 if max_sweeps ran out.
 template <typename P>
 __device__ int hestenes_jacobi(P B, int ldb, int nc, double tol, int max_sweeps, int* flag) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int gl = threadIdx.x & 15, grp = threadIdx.x >> 4, ngrp = blockDim.x >> 4;
   const int ne = nc + (nc & 1);  // an odd count plays against an empty column
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     __syncthreads();
     if (threadIdx.x == 0) *flag = 0;
     __syncthreads();
     for (int step = 0; step < ne - 1; ++step) {
-      for (int pr = wave; pr < ne / 2; pr += nw) {
+      for (int pr = grp; pr < ne / 2; pr += ngrp) {
         const int qr = ne - 1 - pr;
         const int p = pr == 0 ? 0 : 1 + (pr - 1 + step) % (ne - 1);
         const int q = 1 + (qr - 1 + step) % (ne - 1);
@@ -248,31 +266,30 @@ __device__ int hestenes_jacobi(P B, int ldb, int nc, double tol, int max_sweeps,
         P x = B + (int64_t)p * ldb;
         P y = B + (int64_t)q * ldb;
         double al = 0, be = 0, gr = 0, gi = 0;
-        for (int i = lane; i < nc; i += 64) {
+        for (int i = gl; i < nc; i += 16) {
           const double2 a = x[i], c = y[i];
           al += a.x * a.x + a.y * a.y;
           be += c.x * c.x + c.y * c.y;
           gr += a.x * c.x + a.y * c.y;
           gi += a.x * c.y - a.y * c.x;
         }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        gr = wave_sum(gr);
-        gi = wave_sum(gi);
+        al = row16_sum(al);
+        be = row16_sum(be);
+        gr = row16_sum(gr);
+        gi = row16_sum(gi);
         const double ag = sqrt(gr * gr + gi * gi);
-        const int rot = __shfl((al * be > 0 && ag > tol * sqrt(al * be)) ? 1 : 0, 0, 64);
-        if (!rot) continue;
+        if (!(al * be > 0 && ag > tol * sqrt(al * be))) continue;  // same on the 16 lanes
         const double z = (be - al) / (2.0 * ag);
         const double t = (z >= 0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
         const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
         const double er = gr / ag, ei = gi / ag;
-        for (int i = lane; i < nc; i += 64) {
+        for (int i = gl; i < nc; i += 16) {
           const double2 a = x[i], c = y[i];
           // a' = cs a - sn conj(e) c ;  c' = sn e a + cs c
           x[i] = make_double2(cs * a.x - sn * (er * c.x + ei * c.y), cs * a.y - sn * (er * c.y - ei * c.x));
           y[i] = make_double2(sn * (er * a.x - ei * a.y) + cs * c.x, sn * (er * a.y + ei * a.x) + cs * c.y);
         }
-        if (lane == 0) *flag = 1;
+        if (gl == 0) *flag = 1;
       }
       __syncthreads();
     }

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "internal.h"
+
 #include <cstdint>
 #include <vector>
 
@@ -46,5 +48,18 @@ inline GemmDesc gemm(const double2* A, int64_t lda, int opA, const double2* B, i
 
 // Launch all GEMMs of `descs` in one kernel on stream s (synchronises s).
 void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s);
+
+// Groups of GEMMs whose descriptors are uploaded to the device once (one
+// synchronisation, in the constructor); launch(g) then runs group g with no
+// host round trip.  The descriptor memory is freed in stream order.
+class GemmPlan {
+ public:
+  GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t s);
+  void launch(size_t g, hipStream_t s) const;
+
+ private:
+  Scratch dev_;
+  std::vector<int64_t> first_, count_, tiles_;
+};
 
 }  // namespace cbfm

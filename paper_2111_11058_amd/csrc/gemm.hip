@@ -158,32 +158,66 @@ __global__ void __launch_bounds__(256) zgemm_batched_kernel(const GemmDesc* __re
   }
 }
 
-void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s) {
-  if (descs.empty()) return;
+// Tile offsets of a group of descriptors (empty products dropped); returns
+// the group's tile count.
+static int64_t number_tiles(const std::vector<GemmDesc>& in, std::vector<GemmDesc>& out) {
   int64_t tiles = 0;
-  std::vector<GemmDesc> live;
-  for (GemmDesc d : descs) {
+  for (GemmDesc d : in) {
     CBFM_REQUIRE(d.M >= 0 && d.N >= 0 && d.K >= 0, CBFM_E_ARG, "negative GEMM size");
     if (d.M == 0 || d.N == 0) continue;
     d.tile_start = tiles;
     tiles += ((d.M + 15) / 16) * ((d.N + 15) / 16);
-    live.push_back(d);
+    out.push_back(d);
   }
-  if (live.empty()) return;
-  Scratch dev(live.size() * sizeof(GemmDesc), s);
-  CBFM_HIP(hipMemcpyAsync(dev.p, live.data(), live.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
+  return tiles;
+}
+
+static void launch_descs(const GemmDesc* dev, int count, int64_t tiles, hipStream_t s) {
   TimedLaunch tl(T_GEMM, s);
   // few tiles: one tile per block, K split over its 4 wavefronts
   if (tiles < 4096)
-    hipLaunchKernelGGL(zgemm_batched_kernel<4>, dim3((unsigned)tiles), dim3(256), 0, s, dev.as<GemmDesc>(),
-                       (int)live.size(), tiles);
+    hipLaunchKernelGGL(zgemm_batched_kernel<4>, dim3((unsigned)tiles), dim3(256), 0, s, dev, count, tiles);
   else
-    hipLaunchKernelGGL(zgemm_batched_kernel<1>, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s,
-                       dev.as<GemmDesc>(), (int)live.size(), tiles);
+    hipLaunchKernelGGL(zgemm_batched_kernel<1>, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, dev, count,
+                       tiles);
   CBFM_HIP(hipGetLastError());
+}
+
+void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s) {
+  if (descs.empty()) return;
+  std::vector<GemmDesc> live;
+  const int64_t tiles = number_tiles(descs, live);
+  if (live.empty()) return;
+  Scratch dev(live.size() * sizeof(GemmDesc), s);
+  CBFM_HIP(hipMemcpyAsync(dev.p, live.data(), live.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
+  launch_descs(dev.as<GemmDesc>(), (int)live.size(), tiles, s);
   // the descriptor staging buffer is host memory of this frame
   CBFM_HIP(hipStreamSynchronize(s));
-  (void)tl;
+}
+
+GemmPlan::GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t s)
+    : dev_(std::max<size_t>(1, [&] {
+             size_t k = 0;
+             for (const auto& g : groups) k += g.size();
+             return k;
+           }()) * sizeof(GemmDesc),
+           s) {
+  std::vector<GemmDesc> all;
+  for (const auto& g : groups) {
+    first_.push_back((int64_t)all.size());
+    tiles_.push_back(number_tiles(g, all));
+    count_.push_back((int64_t)all.size() - first_.back());
+  }
+  if (!all.empty()) {
+    CBFM_HIP(hipMemcpyAsync(dev_.p, all.data(), all.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
+    CBFM_HIP(hipStreamSynchronize(s));  // `all` is host memory of this frame
+  }
+}
+
+void GemmPlan::launch(size_t g, hipStream_t s) const {
+  CBFM_REQUIRE(g < tiles_.size(), CBFM_E_ARG, "GEMM plan group out of range");
+  if (count_[g] == 0) return;
+  launch_descs(dev_.as<GemmDesc>() + first_[g], (int)count_[g], tiles_[g], s);
 }
 
 }  // namespace cbfm

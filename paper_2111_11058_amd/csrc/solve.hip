@@ -533,6 +533,14 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
     auto all_done = [&](const int32_t* a) {
       return std::none_of(a, a + nrhs, [](int32_t v) { return v != 0; });
     };
+    // u = A v_j for every Krylov index j, descriptors uploaded once
+    std::vector<std::vector<GemmDesc>> mv(mres);
+    for (int64_t j = 0; j < mres; ++j) {
+      GemmDesc d = gemm(Aop, lda, OP_N, V.as<double2>() + j * vstride, n, OP_T, u.as<double2>(), n, n, nrhs, n);
+      d.transC = 1;
+      mv[j].push_back(d);
+    }
+    const GemmPlan matvec(mv, s);
     for (;;) {
       // r = b - A x  (x = 0 on the first cycle)
       double2* r = u.as<double2>();
@@ -549,9 +557,8 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
       if (all_done(flags.sync_read(gs.active, s)) || total >= prm->max_iter) break;
       int pending = 0;  // flag copies queued in this cycle
       for (int64_t j = 0; j < mres && total < prm->max_iter; ++j) {
-        const double2* Vj = V.as<double2>() + j * vstride;
         double2* Vn = V.as<double2>() + (j + 1) * vstride;
-        apply_op(Aop, lda, n, nrhs, Vj, u.as<double2>(), s);
+        matvec.launch((size_t)j, s);
         // classical Gram-Schmidt; a second pass where the first removed most
         // of the vector (the Hessenberg column is the sum of the passes)
         hipLaunchKernelGGL(dots_kernel, dim3((unsigned)(((j + 2) * nrhs + 3) / 4)), dim3(256), 0, s, V.as<double2>(),

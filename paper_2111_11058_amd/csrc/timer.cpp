@@ -8,7 +8,7 @@ namespace cbfm {
 
 namespace {
 std::mutex g_mu;
-bool g_on = false;
+uint32_t g_mask = 0;  // bit i: kernel family i is timed
 struct Rec {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
   int64_t launches = 0;
@@ -33,7 +33,7 @@ void drain(Rec& r) {
 
 TimedLaunch::TimedLaunch(int id_, hipStream_t s_) : id(id_), s(s_) {
   std::lock_guard<std::mutex> lk(g_mu);
-  if (!g_on) return;
+  if (!(g_mask >> id & 1u)) return;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     e0 = e1 = nullptr;
     return;
@@ -60,7 +60,7 @@ extern "C" cbfm_status cbfm_timer_enable(int32_t on) {
       r.launches = 0;
       r.ms = 0;
     }
-    g_on = on != 0;
+    g_mask = (uint32_t)on;
   });
 }
 
