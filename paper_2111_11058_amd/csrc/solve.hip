@@ -7,10 +7,11 @@
 //   sigma = k0^2 / (4 pi) |eta0 N_perp - rhat x L|^2
 //
 // GMRES runs on the device for all right-hand sides at once, each with its
-// own Krylov space (Saad's GMRES; classical Gram-Schmidt with selective
-// re-orthogonalisation; complex Givens rotations).  Matrix-vector products are matrix-core
-// GEMMs over all right-hand sides; the Hessenberg updates run one thread per
-// right-hand side.  The host only reads the convergence flags each step.
+// own Krylov space (Saad's GMRES; classical Gram-Schmidt with delayed
+// re-orthogonalisation; complex Givens rotations).  Matrix-vector products
+// are matrix-core GEMMs over all right-hand sides; the Hessenberg updates
+// run one wavefront per right-hand side.  The host reads the convergence
+// flags every few iterations, one read behind.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -43,109 +44,32 @@ __device__ inline double2 cmul(double2 a, double2 b) {
 }
 __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 
-// Sum over a block of 256 threads, the same order on every call.
-__device__ inline double block_sum256(double s, double* sh) {
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  __syncthreads();  // sh may still be read from a previous call
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-  __syncthreads();
-  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+__device__ inline double2 cconjmul(double2 a, double2 b) {  // conj(a) b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ inline double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// x moved across the lanes of each row of 16 by a DPP pattern.
+template <int CTRL>
+__device__ inline double dpp_double(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
 }
 
-// h[i * nrhs + c] = sum_k conj(V[i][c][k]) u[c][k] for i < jp1 and, with
-// self != 0, h[jp1 * nrhs + c] = ||u[c]||^2; one wavefront per dot product,
-// four per block, only for right-hand sides with flag[c].
-__global__ void __launch_bounds__(256) dots_kernel(const double2* __restrict__ V, int64_t vstride,
-                                                   const double2* __restrict__ u, int64_t n, int64_t nrhs, int64_t jp1,
-                                                   int self, const int32_t* __restrict__ flag,
-                                                   double2* __restrict__ h) {
-  const int64_t id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (id >= (jp1 + self) * nrhs) return;
-  const int64_t i = id / nrhs, c = id % nrhs;
-  if (!flag[c]) return;
-  const double2* v = i < jp1 ? V + i * vstride + c * n : u + c * n;
-  const double2* w = u + c * n;
-  double re = 0, im = 0;
-  for (int64_t k = lane; k < n; k += 64) {
-    const double2 a = v[k], b = w[k];
-    re += a.x * b.x + a.y * b.y;
-    im += a.x * b.y - a.y * b.x;
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    re += __shfl_xor(re, off, 64);
-    im += __shfl_xor(im, off, 64);
-  }
-  if (lane == 0) h[i * nrhs + c] = make_double2(re, im);
+// Sum over the 64 lanes of a wavefront as a butterfly: every lane ends with
+// the same bits.
+__device__ inline double wave_sum(double x) {
+  x += dpp_double<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+  x += dpp_double<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+  x += dpp_double<0x141>(x);  // row_half_mirror
+  x += dpp_double<0x140>(x);  // row_mirror
+  x += __shfl_xor(x, 16, 64);
+  x += __shfl_xor(x, 32, 64);
+  return x;
 }
 
-// One classical Gram-Schmidt update u[c] -= sum_{i<jp1} h[i][c] V[i][c] for
-// the right-hand sides with flag[c]; each block stores the partial sum of
-// |u|^2 over its rows in part[c * gridDim.x + blockIdx.x].  Block 0 of each
-// right-hand side also
-//  - first pass (mask given): sets mask[c] when the projection removed more
-//    than half of the squared norm, sum_i |h_i|^2 > ||u||^2 / 2 with ||u||^2
-//    in h[jp1] -- the Daniel-Gragg-Kaufman-Stewart test (after < before /
-//    sqrt 2) for a second pass;
-//  - second pass (hsum given): adds h into hsum, so that the Hessenberg column
-//    is the sum of both passes.
-__global__ void __launch_bounds__(256) orth_update_kernel(const double2* __restrict__ V, int64_t vstride,
-                                                          double2* __restrict__ u, int64_t n, int64_t jp1, int64_t nrhs,
-                                                          const int32_t* __restrict__ flag, const double2* h,
-                                                          double* __restrict__ part, int32_t* __restrict__ mask,
-                                                          double2* hsum) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
-  if (!flag[c]) {  // uniform over the block
-    if (mask && blockIdx.x == 0 && threadIdx.x == 0) mask[c] = 0;
-    return;
-  }
-  __shared__ double sh[4];
-  double s = 0;
-  if (k < n) {
-    double2 acc = u[c * n + k];
-#pragma unroll 4
-    for (int64_t i = 0; i < jp1; ++i) {
-      const double2 a = h[i * nrhs + c], v = V[i * vstride + c * n + k];
-      acc.x -= a.x * v.x - a.y * v.y;
-      acc.y -= a.x * v.y + a.y * v.x;
-    }
-    u[c * n + k] = acc;
-    s = acc.x * acc.x + acc.y * acc.y;
-  }
-  s = block_sum256(s, sh);
-  if (threadIdx.x == 0) part[c * gridDim.x + blockIdx.x] = s;
-  if (blockIdx.x != 0) return;
-  if (mask) {
-    double q = 0;
-    for (int64_t i = threadIdx.x; i < jp1; i += blockDim.x) {
-      const double2 a = h[i * nrhs + c];
-      q += a.x * a.x + a.y * a.y;
-    }
-    q = block_sum256(q, sh);
-    if (threadIdx.x == 0) mask[c] = q > 0.5 * h[jp1 * nrhs + c].x ? 1 : 0;
-  }
-  if (hsum)
-    for (int64_t i = threadIdx.x; i < jp1; i += blockDim.x) hsum[i * nrhs + c] = cadd(hsum[i * nrhs + c], h[i * nrhs + c]);
-}
-
-// nrm[c] = sqrt(sum of the np partial sums of |u[c]|^2); out[c] = u[c] / nrm[c]
-// (zero if nrm[c] == 0); only right-hand sides with flag[c]
-__global__ void normalize_kernel(const double2* __restrict__ u, double2* __restrict__ out, int64_t n,
-                                 const double* __restrict__ part, int np, double* __restrict__ nrm,
-                                 const int32_t* __restrict__ flag) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
-  if (!flag[c]) return;
-  double q = 0;
-  for (int b = 0; b < np; ++b) q += part[c * np + b];
-  const double nr = sqrt(q);
-  if (blockIdx.x == 0 && threadIdx.x == 0) nrm[c] = nr;
-  if (k >= n) return;
-  const double sc = nr > 0 ? 1.0 / nr : 0.0;
-  const double2 a = u[c * n + k];
-  out[c * n + k] = make_double2(a.x * sc, a.y * sc);
-}
-
-// nrm[c] = ||u[c]|| (one block per vector); skipped for inactive vectors
+// nrm[c] = ||u[c]|| (one block of 256 per vector); skipped for inactive vectors
 __global__ void __launch_bounds__(256) norm_kernel(const double2* __restrict__ u, int64_t n, double* __restrict__ nrm,
                                                    const int32_t* __restrict__ active) {
   const int64_t c = blockIdx.x;
@@ -155,9 +79,11 @@ __global__ void __launch_bounds__(256) norm_kernel(const double2* __restrict__ u
     const double2 a = u[c * n + k];
     s += a.x * a.x + a.y * a.y;
   }
+  s = wave_sum(s);
   __shared__ double sh[4];
-  s = block_sum256(s, sh);
-  if (threadIdx.x == 0) nrm[c] = sqrt(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) nrm[c] = sqrt((sh[0] + sh[1]) + (sh[2] + sh[3]));
 }
 
 // out[c] = in[c] / nrm[c] (zero if nrm[c] == 0)
@@ -177,19 +103,38 @@ __global__ void sub_from_kernel(const double2* __restrict__ b, double2* __restri
   r[k] = make_double2(b[k].x - r[k].x, b[k].y - r[k].y);
 }
 
-// Per right-hand side state, right-hand side index fastest (coalesced).
+// Arnoldi with classical Gram-Schmidt and delayed re-orthogonalisation (the
+// second Gram-Schmidt pass of q_j is taken in iteration j, together with the
+// first pass of w = A q_j, so that every iteration reads the Krylov basis
+// twice instead of four times).  In iteration j, with q_0..q_{j-1} final
+// and q_j orthogonalised once:
+//   a_i = q_i^H q_j, b_i = q_i^H w (i < j), alpha = q_j^H q_j, beta = q_j^H w
+//   gamma = sqrt(alpha - |a|^2),  q_j <- (q_j - Q a) / gamma
+//   column j-1 of H (A q_{j-1} was expanded in the old q_j):
+//       H[l][j-1] += H[j][j-1] a_l (l < j),  H[j][j-1] *= gamma
+//   A q_j(new) = (w - A Q a) / gamma with A Q a = Q_{j+1} p, p = H a, so
+//   h_l = (b_l - p_l) / gamma (l < j), h_j = ((beta - a^H b) / gamma - p_j) / gamma
+//   w <- w / gamma - sum_{l <= j} c_l q_l,  c_l = p_l / gamma + h_l
+//   H[l][j] = h_l, H[j+1][j] = ||w||, q_{j+1} = w / ||w||
+// Column j-1 is final after the correction, so the Givens rotations and the
+// convergence test run one iteration behind the matrix-vector product.
 struct GmresState {
-  double2* H;      // column j, row i at [(j * (m + 1) + i) * nrhs + c]
-  double2* cs;     // [i * nrhs + c]
-  double2* sn;     // [i * nrhs + c]
-  double2* g;      // [i * nrhs + c], i <= m
-  double2* hcol;   // new column, [i * nrhs + c]
-  double* nrm;     // [c]
-  double* bnorm;   // [c]
-  double* res;     // [c] residual estimate / bnorm
-  int32_t* active; // [c]
-  int32_t* kc;     // [c] Krylov dimension reached in this cycle
-  int32_t* its;    // [c] iterations spent (all cycles)
+  double2* R;       // rotated Hessenberg (upper triangular): column j, row i at [(j * (m + 1) + i) * nrhs + c]
+  double2* H;       // Hessenberg matrix of the final basis, same layout
+  double2* cs;      // [i * nrhs + c]
+  double2* sn;      // [i * nrhs + c]
+  double2* g;       // [i * nrhs + c], i <= m
+  double2* d1;      // [i * nrhs + c]: a_i, alpha at i = j
+  double2* d2;      // [i * nrhs + c]: b_i, beta at i = j
+  double2* coef;    // [i * nrhs + c]: c_i
+  double2* ab;      // [c] a^H b
+  double* gam;      // [c] gamma
+  double* nrm;      // [c]
+  double* bnorm;    // [c]
+  double* res;      // [c] residual estimate / bnorm
+  int32_t* active;  // [c]
+  int32_t* kc;      // [c] Krylov dimension reached in this cycle
+  int32_t* its;     // [c] iterations spent (all cycles)
 };
 
 // Start a cycle: g = beta e1, active = beta/bnorm > tol, kc = 0.
@@ -205,26 +150,101 @@ __global__ void cycle_init_kernel(GmresState st, int64_t m, int64_t nrhs, double
   st.kc[c] = 0;
 }
 
-// Column j of the Hessenberg matrix from hcol (rows 0..j) and nrm (row j+1):
-// apply the previous rotations, form the new one, update g, test convergence.
-// One wavefront per right-hand side.  Rotation i maps (a_i, h_{i+1}) to
-// (c_i a_i + s_i h_{i+1}, a_{i+1}) with a_{i+1} = -conj(s_i) a_i + conj(c_i)
-// h_{i+1}, a_0 = h_0: the carried a_i follow an affine recurrence, so each
-// lane composes the maps of a contiguous run of rotations, a scan over the
-// lanes gives every run its incoming a_i, and the runs are then replayed in
-// parallel.
-__global__ void __launch_bounds__(256) givens_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs, double tol) {
+// d1[i] = q_i^H q_j and d2[i] = q_i^H w for i <= j: one wavefront per
+// right-hand side and run of four basis vectors, four per block.
+__global__ void __launch_bounds__(256) dots2_kernel(const double2* __restrict__ V, int64_t vstride,
+                                                    const double2* __restrict__ w, int64_t n, int64_t nrhs, int64_t j,
+                                                    GmresState st) {
+  const int64_t id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t runs = (j + 4) / 4;
+  if (id >= runs * nrhs) return;
+  const int64_t run = id / nrhs, c = id % nrhs;
+  if (!st.active[c]) return;
+  const int64_t i0 = run * 4;
+  const int cnt = (int)std::min<int64_t>(4, j + 1 - i0);
+  const double2* qj = V + j * vstride + c * n;
+  const double2* wc = w + c * n;
+  const double2* qi = V + i0 * vstride + c * n;
+  double2 s1[4], s2[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) s1[t] = s2[t] = make_double2(0, 0);
+  for (int64_t k = lane; k < n; k += 64) {
+    const double2 x = qj[k], y = wc[k];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < cnt) {
+        const double2 v = qi[t * vstride + k];
+        s1[t] = cadd(s1[t], cconjmul(v, x));
+        s2[t] = cadd(s2[t], cconjmul(v, y));
+      }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (t >= cnt) break;
+    const double2 r1 = make_double2(wave_sum(s1[t].x), wave_sum(s1[t].y));
+    const double2 r2 = make_double2(wave_sum(s2[t].x), wave_sum(s2[t].y));
+    if (lane == 0) {
+      st.d1[(i0 + t) * nrhs + c] = r1;
+      st.d2[(i0 + t) * nrhs + c] = r2;
+    }
+  }
+}
+
+// Per right-hand side (one wavefront each): gamma and a^H b, then column
+// jc = j - 1 made final (corrected for the new q_j unless correct == 0, the
+// end of a cycle, when it is taken as it stands) and reduced by the Givens
+// rotations; the new rotation updates g and the convergence test.
+// Rotation i maps (a_i, h_{i+1}) to (c_i a_i + s_i h_{i+1}, a_{i+1}) with
+// a_{i+1} = -conj(s_i) a_i + conj(c_i) h_{i+1}, a_0 = h_0: the carried a_i
+// follow an affine recurrence, so each lane composes the maps of a
+// contiguous run of rotations, a scan over the lanes gives every run its
+// incoming a_i, and the runs are then replayed in parallel.
+__global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs, double tol,
+                                                     int correct) {
   const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= nrhs || !st.active[c]) return;  // uniform over the wavefront
-  const int64_t K = (j + 63) / 64;
-  const int64_t i0 = std::min<int64_t>(j, lane * K), i1 = std::min<int64_t>(j, i0 + K);
+  double gam = 1.0;
+  bool breakdown = false;
+  if (correct) {
+    double aa = 0;
+    double2 ab = make_double2(0, 0);
+    for (int64_t l = lane; l < j; l += 64) {
+      const double2 a = st.d1[l * nrhs + c];
+      aa += a.x * a.x + a.y * a.y;
+      ab = cadd(ab, cconjmul(a, st.d2[l * nrhs + c]));
+    }
+    aa = wave_sum(aa);
+    ab = make_double2(wave_sum(ab.x), wave_sum(ab.y));
+    const double alpha = st.d1[j * nrhs + c].x;
+    const double g2 = alpha - aa;
+    // q_j nearly inside the span of q_0..q_{j-1}: the Krylov space is
+    // (numerically) invariant, taken as a breakdown
+    breakdown = !(g2 > 0.25 * alpha);
+    gam = breakdown ? 1.0 : sqrt(g2);
+    if (lane == 0) {
+      st.gam[c] = gam;
+      st.ab[c] = ab;
+    }
+  }
+  if (j == 0) return;
+  const int64_t jc = j - 1, col = jc * (m + 1);
+  const double2 hs = st.H[(col + jc + 1) * nrhs + c];  // H[jc+1][jc], real
+  auto corrected = [&](int64_t l) {  // H[l][jc] for the final basis, l <= jc
+    double2 h = st.H[(col + l) * nrhs + c];
+    if (correct) h = cadd(h, cmul(hs, st.d1[l * nrhs + c]));
+    return h;
+  };
+  const double hsub = correct ? (breakdown ? 0.0 : hs.x * gam) : hs.x;
+  const int64_t K = (jc + 63) / 64;
+  const int64_t i0 = std::min<int64_t>(jc, lane * K), i1 = std::min<int64_t>(jc, i0 + K);
   double2 P = make_double2(1, 0), Q = make_double2(0, 0);
   for (int64_t i = i0; i < i1; ++i) {
-    const double2 sn = st.sn[i * nrhs + c], cs = st.cs[i * nrhs + c], b = st.hcol[(i + 1) * nrhs + c];
+    const double2 sn = st.sn[i * nrhs + c], cs = st.cs[i * nrhs + c], b = corrected(i + 1);
+    if (correct) st.H[(col + i + 1) * nrhs + c] = b;
     const double2 Pi = make_double2(-sn.x, sn.y);  // -conj(s_i)
-    const double2 Qi = cmul(make_double2(cs.x, -cs.y), b);
-    Q = cadd(cmul(Pi, Q), Qi);
+    Q = cadd(cmul(Pi, Q), cmul(make_double2(cs.x, -cs.y), b));
     P = cmul(Pi, P);
   }
   // inclusive scan: after it, (P, Q) maps a_0 to the carry leaving this run
@@ -236,38 +256,151 @@ __global__ void __launch_bounds__(256) givens_kernel(GmresState st, int64_t m, i
       P = cmul(P, Po);
     }
   }
-  const double2 a0 = st.hcol[c];
+  const double2 a0 = corrected(0);
   const double2 Pe = make_double2(__shfl_up(P.x, 1, 64), __shfl_up(P.y, 1, 64));
   const double2 Qe = make_double2(__shfl_up(Q.x, 1, 64), __shfl_up(Q.y, 1, 64));
   double2 a = lane == 0 ? a0 : cadd(cmul(Pe, a0), Qe);
   for (int64_t i = i0; i < i1; ++i) {
-    const double2 sn = st.sn[i * nrhs + c], cs = st.cs[i * nrhs + c], b = st.hcol[(i + 1) * nrhs + c];
-    st.H[(j * (m + 1) + i) * nrhs + c] = cadd(cmul(cs, a), cmul(sn, b));
+    // this lane stored the final H[i+1][jc] above (or it was final already)
+    const double2 sn = st.sn[i * nrhs + c], cs = st.cs[i * nrhs + c], b = st.H[(col + i + 1) * nrhs + c];
+    st.R[(col + i) * nrhs + c] = cadd(cmul(cs, a), cmul(sn, b));
     a = cadd(cmul(make_double2(-sn.x, sn.y), a), cmul(make_double2(cs.x, -cs.y), b));
   }
-  const int last = j == 0 ? 0 : (int)((j - 1) / K);  // lane that ends with a_j
+  const int last = jc == 0 ? 0 : (int)((jc - 1) / K);  // lane that ends with a_jc
   a = make_double2(__shfl(a.x, last, 64), __shfl(a.y, last, 64));
   if (lane != 0) return;
-  const double2 b = make_double2(st.nrm[c], 0);
-  const double den = sqrt(a.x * a.x + a.y * a.y + b.x * b.x);
+  if (correct) {
+    st.H[col * nrhs + c] = a0;
+    st.H[(col + jc + 1) * nrhs + c] = make_double2(hsub, 0);
+  }
+  const double den = sqrt(a.x * a.x + a.y * a.y + hsub * hsub);
   double2 cc = make_double2(1, 0), ss = make_double2(0, 0);
   if (den > 0) {
     cc = make_double2(a.x / den, -a.y / den);  // conj(a)/den
-    ss = make_double2(b.x / den, 0.0);         // conj(b)/den, b real
+    ss = make_double2(hsub / den, 0.0);        // conj(h)/den, h real
   }
-  st.cs[j * nrhs + c] = cc;
-  st.sn[j * nrhs + c] = ss;
-  st.H[(j * (m + 1) + j) * nrhs + c] = make_double2(den, 0);
-  const double2 gj = st.g[j * nrhs + c];
-  // g[j+1] = -conj(s) g[j];  g[j] = c g[j]
+  st.cs[jc * nrhs + c] = cc;
+  st.sn[jc * nrhs + c] = ss;
+  st.R[(col + jc) * nrhs + c] = make_double2(den, 0);
+  const double2 gj = st.g[jc * nrhs + c];
+  // g[jc+1] = -conj(s) g[jc];  g[jc] = c g[jc]
   const double2 gn = make_double2(-(ss.x * gj.x + ss.y * gj.y), -(ss.x * gj.y - ss.y * gj.x));
-  st.g[(j + 1) * nrhs + c] = gn;
-  st.g[j * nrhs + c] = make_double2(cc.x * gj.x - cc.y * gj.y, cc.x * gj.y + cc.y * gj.x);
+  st.g[(jc + 1) * nrhs + c] = gn;
+  st.g[jc * nrhs + c] = cmul(cc, gj);
   const double r = sqrt(gn.x * gn.x + gn.y * gn.y) / st.bnorm[c];
   st.res[c] = r;
-  st.kc[c] = (int32_t)(j + 1);
+  st.kc[c] = (int32_t)(jc + 1);
   st.its[c] += 1;
-  if (r <= tol || den == 0.0) st.active[c] = 0;
+  if (r <= tol || den == 0.0 || breakdown) st.active[c] = 0;
+}
+
+// Column j of H and the update coefficients: p_l = sum_i H[l][i] a_i over
+// the final columns i < j (upper Hessenberg: i >= l - 1), then h_l and c_l
+// as above.  One block per row l; lane = right-hand side (64 per block
+// row), the four wavefronts take every fourth column and are summed through
+// LDS in a fixed order.
+__global__ void __launch_bounds__(256) coef_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs) {
+  const int64_t l = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.y * 64 + lane;
+  const bool on = c < nrhs && st.active[c];
+  double2 p0 = make_double2(0, 0), p1 = p0;
+  if (on) {
+    const int64_t lo = l > 0 ? l - 1 : 0;
+    const double2* Hl = st.H + l * nrhs + c;  // column i at Hl[i * (m + 1) * nrhs]
+    const double2* a = st.d1 + c;
+    const int64_t cs = (m + 1) * nrhs;
+    int64_t i = lo + wv;
+    for (; i + 4 < j; i += 8) {
+      p0 = cadd(p0, cmul(Hl[i * cs], a[i * nrhs]));
+      p1 = cadd(p1, cmul(Hl[(i + 4) * cs], a[(i + 4) * nrhs]));
+    }
+    if (i < j) p0 = cadd(p0, cmul(Hl[i * cs], a[i * nrhs]));
+    p0 = cadd(p0, p1);
+  }
+  __shared__ double2 sh[3][64];
+  if (wv > 0) sh[wv - 1][lane] = p0;
+  __syncthreads();
+  if (wv > 0 || !on) return;
+  const double2 p = cadd(cadd(p0, sh[0][lane]), cadd(sh[1][lane], sh[2][lane]));
+  const double ig = 1.0 / st.gam[c];
+  const double2 b = st.d2[l * nrhs + c];
+  double2 h;
+  if (l < j) {
+    h = cscale(make_double2(b.x - p.x, b.y - p.y), ig);
+  } else {
+    const double2 ab = st.ab[c];
+    h = cscale(make_double2((b.x - ab.x) * ig - p.x, (b.y - ab.y) * ig - p.y), ig);
+  }
+  st.H[(j * (m + 1) + l) * nrhs + c] = h;
+  st.coef[l * nrhs + c] = cadd(cscale(p, ig), h);
+}
+
+// The update pass: q_j <- (q_j - sum_{i<j} a_i q_i) / gamma and w <- w / gamma
+// - sum_{i<j} c_i q_i - c_j q_j(new).  A block of four wavefronts takes 64
+// consecutive rows of one right-hand side, wavefront v summing over the
+// basis vectors i = v mod 4; wavefront 0 combines the partial sums in a
+// fixed order and stores the row block's sum of |w|^2 in part.
+__global__ void __launch_bounds__(256) dcgs_update_kernel(double2* __restrict__ V, int64_t vstride,
+                                                          double2* __restrict__ w, int64_t n, int64_t nrhs, int64_t j,
+                                                          GmresState st, double* __restrict__ part) {
+  const int64_t c = blockIdx.y;
+  if (!st.active[c]) return;  // uniform over the block
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t k = (int64_t)blockIdx.x * 64 + lane;
+  const bool in = k < n;
+  const int64_t kk = in ? k : 0;
+  double2 s1 = make_double2(0, 0), s2 = make_double2(0, 0);
+  const double2* base = V + c * n + kk;
+#pragma unroll 4
+  for (int64_t i = wv; i < j; i += 4) {
+    const double2 v = base[i * vstride];
+    s1 = cadd(s1, cmul(st.d1[i * nrhs + c], v));
+    s2 = cadd(s2, cmul(st.coef[i * nrhs + c], v));
+  }
+  __shared__ double2 sh[3][64][2];
+  if (wv > 0) {
+    sh[wv - 1][lane][0] = s1;
+    sh[wv - 1][lane][1] = s2;
+  }
+  __syncthreads();
+  if (wv > 0) return;
+  for (int t = 0; t < 3; ++t) {
+    s1 = cadd(s1, sh[t][lane][0]);
+    s2 = cadd(s2, sh[t][lane][1]);
+  }
+  const double ig = 1.0 / st.gam[c];
+  double q2 = 0;
+  if (in) {
+    double2* qj = V + j * vstride + c * n + k;
+    const double2 qo = *qj;
+    const double2 qn = cscale(make_double2(qo.x - s1.x, qo.y - s1.y), ig);
+    *qj = qn;
+    const double2 wo = w[c * n + k];
+    const double2 cj = st.coef[j * nrhs + c];
+    const double2 t = cadd(s2, cmul(cj, qn));
+    const double2 wn = make_double2(wo.x * ig - t.x, wo.y * ig - t.y);
+    w[c * n + k] = wn;
+    q2 = wn.x * wn.x + wn.y * wn.y;
+  }
+  q2 = wave_sum(q2);
+  if (lane == 0) part[c * gridDim.x + blockIdx.x] = q2;
+}
+
+// nu = sqrt(sum of the np partial sums of |w|^2); H[j+1][j] = nu and
+// q_{j+1} = w / nu (zero if nu == 0); only active right-hand sides.
+__global__ void normalize_kernel(const double2* __restrict__ w, double2* __restrict__ out, int64_t n,
+                                 const double* __restrict__ part, int np, GmresState st, int64_t m, int64_t j,
+                                 int64_t nrhs) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (!st.active[c]) return;
+  double q = 0;
+  for (int b = 0; b < np; ++b) q += part[c * np + b];
+  const double nu = sqrt(q);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st.H[(j * (m + 1) + j + 1) * nrhs + c] = make_double2(nu, 0);
+  if (k >= n) return;
+  const double sc = nu > 0 ? 1.0 / nu : 0.0;
+  out[c * n + k] = cscale(w[c * n + k], sc);
 }
 
 // y = H^{-1} g over the first kc[c] rows (upper triangular), in place in g;
@@ -278,7 +411,7 @@ __global__ void __launch_bounds__(256) backsolve_kernel(GmresState st, int64_t m
   __shared__ double2 yi;
   for (int64_t i = k - 1; i >= 0; --i) {
     if (threadIdx.x == 0) {
-      const double2 s = st.g[i * nrhs + c], d = st.H[(i * (m + 1) + i) * nrhs + c];
+      const double2 s = st.g[i * nrhs + c], d = st.R[(i * (m + 1) + i) * nrhs + c];
       const double dd = d.x * d.x + d.y * d.y;
       yi = dd > 0 ? make_double2((s.x * d.x + s.y * d.y) / dd, (s.y * d.x - s.x * d.y) / dd) : make_double2(0, 0);
       st.g[i * nrhs + c] = yi;
@@ -286,7 +419,7 @@ __global__ void __launch_bounds__(256) backsolve_kernel(GmresState st, int64_t m
     __syncthreads();
     const double2 y = yi;
     for (int64_t t = threadIdx.x; t < i; t += blockDim.x) {
-      const double2 h = st.H[(i * (m + 1) + t) * nrhs + c];
+      const double2 h = st.R[(i * (m + 1) + t) * nrhs + c];
       double2* gt = st.g + t * nrhs + c;
       gt->x -= h.x * y.x - h.y * y.y;
       gt->y -= h.x * y.y + h.y * y.x;
@@ -506,15 +639,15 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
     // ---- GMRES state
     Scratch V((mres + 1) * nrhs * n * sizeof(double2), s);
     Scratch x(nrhs * n * sizeof(double2), s), u(nrhs * n * sizeof(double2), s);
-    const int np = (int)((n + 255) / 256);  // partial norm sums per vector
-    Scratch Hs(nrhs * (mres + 1) * mres * sizeof(double2), s), csb(nrhs * mres * sizeof(double2), s),
-        snb(nrhs * mres * sizeof(double2), s), gb(nrhs * (mres + 1) * sizeof(double2), s),
-        hcol((mres + 2) * nrhs * sizeof(double2), s), h2((mres + 1) * nrhs * sizeof(double2), s),
-        dbl(3 * nrhs * sizeof(double), s), ints(3 * nrhs * sizeof(int32_t), s), part(nrhs * np * sizeof(double), s),
-        mask2(nrhs * sizeof(int32_t), s);
-    GmresState gs{Hs.as<double2>(), csb.as<double2>(), snb.as<double2>(), gb.as<double2>(), hcol.as<double2>(),
-                  dbl.as<double>(), dbl.as<double>() + nrhs, dbl.as<double>() + 2 * nrhs, ints.as<int32_t>(),
-                  ints.as<int32_t>() + nrhs, ints.as<int32_t>() + 2 * nrhs};
+    const int np = (int)((n + 63) / 64);  // partial norm sums per vector (64-row blocks)
+    const size_t hbytes = (size_t)nrhs * (mres + 1) * mres * sizeof(double2), cbytes = (size_t)nrhs * (mres + 1) * sizeof(double2);
+    Scratch Rs(hbytes, s), Hs(hbytes, s), csb(nrhs * mres * sizeof(double2), s), snb(nrhs * mres * sizeof(double2), s),
+        gb(cbytes, s), d1b(cbytes, s), d2b(cbytes, s), coefb(cbytes, s), abb(nrhs * sizeof(double2), s),
+        dbl(5 * nrhs * sizeof(double), s), ints(3 * nrhs * sizeof(int32_t), s), part(nrhs * np * sizeof(double), s);
+    GmresState gs{Rs.as<double2>(),          Hs.as<double2>(),          csb.as<double2>(),          snb.as<double2>(),
+                  gb.as<double2>(),          d1b.as<double2>(),         d2b.as<double2>(),          coefb.as<double2>(),
+                  abb.as<double2>(),         dbl.as<double>(),          dbl.as<double>() + nrhs,    dbl.as<double>() + 2 * nrhs,
+                  dbl.as<double>() + 3 * nrhs, ints.as<int32_t>(),      ints.as<int32_t>() + nrhs,  ints.as<int32_t>() + 2 * nrhs};
     const int64_t vstride = nrhs * n;
     const dim3 g1((unsigned)((nrhs + 63) / 64)), b1(64), g4((unsigned)((nrhs + 3) / 4));
     CBFM_HIP(hipMemsetAsync(x.p, 0, nrhs * n * sizeof(double2), s));
@@ -556,32 +689,31 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
       hipLaunchKernelGGL(scale_kernel, grid2(n, nrhs), dim3(256), 0, s, r, V.as<double2>(), n, gs.nrm);
       if (all_done(flags.sync_read(gs.active, s)) || total >= prm->max_iter) break;
       int pending = 0;  // flag copies queued in this cycle
+      int64_t jlast = -1;
       for (int64_t j = 0; j < mres && total < prm->max_iter; ++j) {
         double2* Vn = V.as<double2>() + (j + 1) * vstride;
-        matvec.launch((size_t)j, s);
-        // classical Gram-Schmidt; a second pass where the first removed most
-        // of the vector (the Hessenberg column is the sum of the passes)
-        hipLaunchKernelGGL(dots_kernel, dim3((unsigned)(((j + 2) * nrhs + 3) / 4)), dim3(256), 0, s, V.as<double2>(),
-                           vstride, u.as<double2>(), n, nrhs, j + 1, 1, gs.active, gs.hcol);
-        hipLaunchKernelGGL(orth_update_kernel, grid2(n, nrhs), dim3(256), 0, s, V.as<double2>(), vstride,
-                           u.as<double2>(), n, j + 1, nrhs, gs.active, gs.hcol, part.as<double>(), mask2.as<int32_t>(),
-                           nullptr);
-        hipLaunchKernelGGL(dots_kernel, dim3((unsigned)(((j + 1) * nrhs + 3) / 4)), dim3(256), 0, s, V.as<double2>(),
-                           vstride, u.as<double2>(), n, nrhs, j + 1, 0, mask2.as<int32_t>(), h2.as<double2>());
-        hipLaunchKernelGGL(orth_update_kernel, grid2(n, nrhs), dim3(256), 0, s, V.as<double2>(), vstride,
-                           u.as<double2>(), n, j + 1, nrhs, mask2.as<int32_t>(), h2.as<double2>(), part.as<double>(),
-                           nullptr, gs.hcol);
+        matvec.launch((size_t)j, s);  // u = A q_j
+        hipLaunchKernelGGL(dots2_kernel, dim3((unsigned)(((j + 4) / 4 * nrhs + 3) / 4)), dim3(256), 0, s,
+                           V.as<double2>(), vstride, u.as<double2>(), n, nrhs, j, gs);
+        hipLaunchKernelGGL(column_kernel, g4, dim3(256), 0, s, gs, mres, j, nrhs, tol, 1);
+        hipLaunchKernelGGL(coef_kernel, dim3((unsigned)(j + 1), (unsigned)((nrhs + 63) / 64)), dim3(256), 0, s, gs, mres,
+                           j, nrhs);
+        hipLaunchKernelGGL(dcgs_update_kernel, dim3((unsigned)np, (unsigned)nrhs), dim3(256), 0, s, V.as<double2>(),
+                           vstride, u.as<double2>(), n, nrhs, j, gs, part.as<double>());
         hipLaunchKernelGGL(normalize_kernel, grid2(n, nrhs), dim3(256), 0, s, u.as<double2>(), Vn, n, part.as<double>(),
-                           np, gs.nrm, gs.active);
-        hipLaunchKernelGGL(givens_kernel, g4, dim3(256), 0, s, gs, mres, j, nrhs, tol);
+                           np, gs, mres, j, nrhs);
         CBFM_HIP(hipGetLastError());
         ++total;
+        jlast = j;
         if ((j + 1) % check_every == 0) {
           if (pending > 0 && all_done(flags.wait())) break;
           flags.post(gs.active, s);
           ++pending;
         }
       }
+      // the last column of the cycle, taken without the delayed correction
+      if (jlast >= 0)
+        hipLaunchKernelGGL(column_kernel, g4, dim3(256), 0, s, gs, mres, jlast + 1, nrhs, tol, 0);
       hipLaunchKernelGGL(backsolve_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, mres, nrhs);
       hipLaunchKernelGGL(x_update_kernel, grid2(n, nrhs), dim3(256), 0, s, gs, V.as<double2>(), vstride, x.as<double2>(),
                          n, nrhs);
