@@ -119,16 +119,57 @@ static FillConsts make_consts(const Media& md, int layout) {
 }
 
 // ------------------------------------------------------------- phase helpers
-__device__ __forceinline__ void phase(double x_rad, double /*rev*/, double& s, double& c) {
-  sincos(x_rad, &s, &c);
+// sin and cos of 2 pi x, x in revolutions: x = n / 4 + f with n = rint(4 x),
+// |f| <= 1/8 (the subtraction loses at most an ulp of 1/8), theta = 2 pi f
+// in [-pi/4, pi/4], Taylor series of sin to theta^15 / 15! and of cos to
+// theta^16 / 16! (remainders below 5e-17 there), then the quadrant n mod 4
+// rotates the pair.  The phases here are small multiples of 2 pi (k R over
+// a scatterer), where this reduction is exact enough.
+__device__ __forceinline__ void sincos_rev(double x, double& s, double& c) {
+  const double q = rint(4.0 * x);
+  const double f = fma(-0.25, q, x);
+  const double t = f * 6.283185307179586;
+  const double t2 = t * t;
+  double ps = -1.0 / 1307674368000.0;  // -1/15!
+  ps = fma(ps, t2, 1.0 / 6227020800.0);
+  ps = fma(ps, t2, -1.0 / 39916800.0);
+  ps = fma(ps, t2, 1.0 / 362880.0);
+  ps = fma(ps, t2, -1.0 / 5040.0);
+  ps = fma(ps, t2, 1.0 / 120.0);
+  ps = fma(ps, t2, -1.0 / 6.0);
+  const double sn = fma(ps * t2, t, t);
+  double pc = 1.0 / 20922789888000.0;  // 1/16!
+  pc = fma(pc, t2, -1.0 / 87178291200.0);
+  pc = fma(pc, t2, 1.0 / 479001600.0);
+  pc = fma(pc, t2, -1.0 / 3628800.0);
+  pc = fma(pc, t2, 1.0 / 40320.0);
+  pc = fma(pc, t2, -1.0 / 720.0);
+  pc = fma(pc, t2, 1.0 / 24.0);
+  pc = fma(pc, t2, -0.5);
+  const double cs = fma(pc, t2, 1.0);
+  const int n = (int)(long long)q & 3;
+  s = n == 0 ? sn : n == 1 ? cs : n == 2 ? -sn : -cs;
+  c = n == 0 ? cs : n == 1 ? -sn : n == 2 ? -cs : sn;
 }
+__device__ __forceinline__ void phase(double /*x_rad*/, double x_rev, double& s, double& c) { sincos_rev(x_rev, s, c); }
 __device__ __forceinline__ void phase(float /*x_rad*/, float x_rev, float& s, float& c) {
   // hardware sine/cosine take the angle in revolutions
   const float f = __builtin_amdgcn_fractf(x_rev);
   s = __builtin_amdgcn_sinf(f);
   c = __builtin_amdgcn_cosf(f);
 }
-__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+// 1 / sqrt(x): the hardware estimate refined by two Newton steps
+// y <- y + y (1 - x y^2) / 2 (quadratic convergence; the residual is formed
+// with an FMA).
+__device__ __forceinline__ double rsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double r = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, r, y);
+  }
+  return y;
+}
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double expo(double x) { return exp(x); }
 __device__ __forceinline__ float expo(float x) { return __expf(x); }
