@@ -119,37 +119,44 @@ static FillConsts make_consts(const Media& md, int layout) {
 }
 
 // ------------------------------------------------------------- phase helpers
-// sin and cos of 2 pi x, x in revolutions: x = n / 4 + f with n = rint(4 x),
-// |f| <= 1/8 (the subtraction loses at most an ulp of 1/8), theta = 2 pi f
-// in [-pi/4, pi/4], Taylor series of sin to theta^15 / 15! and of cos to
-// theta^16 / 16! (remainders below 5e-17 there), then the quadrant n mod 4
-// rotates the pair.  The phases here are small multiples of 2 pi (k R over
-// a scatterer), where this reduction is exact enough.
+// sin and cos of 2 pi x, x in revolutions: x = n / 2 + f with n = rint(2 x),
+// |f| <= 1/4 (the subtraction loses at most an ulp of 1/4), theta = 2 pi f
+// in [-pi/2, pi/2], Taylor series of sin to theta^21 / 21! and of cos to
+// theta^22 / 22! (remainders below 2e-18 there); a half turn only flips
+// both signs, applied to the sign bits.  The phases here are small
+// multiples of 2 pi (k R over a scatterer), where this reduction is exact
+// enough.
 __device__ __forceinline__ void sincos_rev(double x, double& s, double& c) {
-  const double q = rint(4.0 * x);
-  const double f = fma(-0.25, q, x);
+  const double q = rint(2.0 * x);
+  const double f = fma(-0.5, q, x);
+  const int flip = ((int)q & 1) << 31;
   const double t = f * 6.283185307179586;
   const double t2 = t * t;
-  double ps = -1.0 / 1307674368000.0;  // -1/15!
-  ps = fma(ps, t2, 1.0 / 6227020800.0);
-  ps = fma(ps, t2, -1.0 / 39916800.0);
-  ps = fma(ps, t2, 1.0 / 362880.0);
-  ps = fma(ps, t2, -1.0 / 5040.0);
-  ps = fma(ps, t2, 1.0 / 120.0);
-  ps = fma(ps, t2, -1.0 / 6.0);
-  const double sn = fma(ps * t2, t, t);
-  double pc = 1.0 / 20922789888000.0;  // 1/16!
-  pc = fma(pc, t2, -1.0 / 87178291200.0);
-  pc = fma(pc, t2, 1.0 / 479001600.0);
-  pc = fma(pc, t2, -1.0 / 3628800.0);
-  pc = fma(pc, t2, 1.0 / 40320.0);
-  pc = fma(pc, t2, -1.0 / 720.0);
-  pc = fma(pc, t2, 1.0 / 24.0);
-  pc = fma(pc, t2, -0.5);
-  const double cs = fma(pc, t2, 1.0);
-  const int n = (int)(long long)q & 3;
-  s = n == 0 ? sn : n == 1 ? cs : n == 2 ? -sn : -cs;
-  c = n == 0 ? cs : n == 1 ? -sn : n == 2 ? -cs : sn;
+  double ps = -1.0 / 51090942171709440000.0;  // -1/21!
+  ps = fma(ps, t2, 1.0 / 121645100408832000.0);
+  ps = fma(ps, t2, -1.0 / 355687428096000.0);
+  ps = fma(ps, t2, 1.0 / 1307674368000.0);
+  ps = fma(ps, t2, -1.0 / 6227020800.0);
+  ps = fma(ps, t2, 1.0 / 39916800.0);
+  ps = fma(ps, t2, -1.0 / 362880.0);
+  ps = fma(ps, t2, 1.0 / 5040.0);
+  ps = fma(ps, t2, -1.0 / 120.0);
+  ps = fma(ps, t2, 1.0 / 6.0);
+  const double sn = fma(-(ps * t2), t, t);
+  double pc = 1.0 / 1124000727777607680000.0;  // 1/22!
+  pc = fma(pc, t2, -1.0 / 2432902008176640000.0);
+  pc = fma(pc, t2, 1.0 / 6402373705728000.0);
+  pc = fma(pc, t2, -1.0 / 20922789888000.0);
+  pc = fma(pc, t2, 1.0 / 87178291200.0);
+  pc = fma(pc, t2, -1.0 / 479001600.0);
+  pc = fma(pc, t2, 1.0 / 3628800.0);
+  pc = fma(pc, t2, -1.0 / 40320.0);
+  pc = fma(pc, t2, 1.0 / 720.0);
+  pc = fma(pc, t2, -1.0 / 24.0);
+  pc = fma(pc, t2, 0.5);
+  const double cs = fma(-pc, t2, 1.0);
+  s = __hiloint2double(__double2hiint(sn) ^ flip, __double2loint(sn));
+  c = __hiloint2double(__double2hiint(cs) ^ flip, __double2loint(cs));
 }
 __device__ __forceinline__ void phase(double /*x_rad*/, double x_rev, double& s, double& c) { sincos_rev(x_rev, s, c); }
 __device__ __forceinline__ void phase(float /*x_rad*/, float x_rev, float& s, float& c) {
@@ -158,25 +165,24 @@ __device__ __forceinline__ void phase(float /*x_rad*/, float x_rev, float& s, fl
   s = __builtin_amdgcn_sinf(f);
   c = __builtin_amdgcn_cosf(f);
 }
-// 1 / sqrt(x): the hardware estimate refined by two Newton steps
-// y <- y + y (1 - x y^2) / 2 (quadratic convergence; the residual is formed
-// with an FMA).
+// 1 / sqrt(x): the hardware estimate (relative error about 5e-8 on gfx950)
+// refined by one Newton step y <- y + y (1 - x y^2) / 2, which squares the
+// error (a few 1e-15; the residual is formed with an FMA).
 __device__ __forceinline__ double rsq(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const double r = fma(-(x * y), y, 1.0);
-    y = fma(0.5 * y, r, y);
-  }
-  return y;
+  const double y = __builtin_amdgcn_rsq(x);
+  const double r = fma(-(x * y), y, 1.0);
+  return fma(0.5 * y, r, y);
 }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double expo(double x) { return exp(x); }
 __device__ __forceinline__ float expo(float x) { return __expf(x); }
 
 // ------------------------------------------------------------- regular kernel
+// Two wavefronts per SIMD at least: the FP64 instance then fits in 256
+// VGPRs (one or two spilled outside the point loops), which hides the
+// latency of its dependent FP64 chains far better than one wavefront.
 template <typename R, bool LOSSY>
-__global__ void __launch_bounds__(256) fill_regular_kernel(
+__global__ void __launch_bounds__(256, 2) fill_regular_kernel(
     TriTab<R> tab, const int32_t* __restrict__ rowTris, const int32_t* __restrict__ colTris,
     int64_t nct, FillConsts fc, cx<R>* __restrict__ out, int64_t op_stride, int64_t ldl) {
   const int64_t i = blockIdx.y;
