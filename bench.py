@@ -14,12 +14,17 @@ squares per face (1,728 triangles, 2,592 RWGs, 5,184 unknowns), 27 cells,
 64 seeded incidences, CBFs from the 144 Table-I plane waves, delta_SVD 1e-3.
 
 value = logical triangle pair-evaluations (N_tri^2 per step) per second of
-the whole step.  The roofline entry is for the dominant kernel, the
-regular-pair fill, from HIP events recorded around its launches.
+the whole step.  After the timed steps one more step runs with the library's
+event timers on; the roofline entry is for the kernel family with the most
+GPU time in it (algorithmic work per launch over the average launch
+duration), and roofline_kernels lists every timed family.  HBM traffic per
+launch comes from the committed counter summary when the kernel's source is
+unchanged since it was measured, else it is null.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -40,6 +45,17 @@ METRIC = "PMCHWT fill+projection pair-evals/s; solves/s with p50/p99 latency"
 #   + 9 local pairs x 110 (K 38, two media X_i 36, two output operators 36)
 FLOP_PER_PAIR = 49 * 73 + 7 * 190 + 9 * 110
 PEAK_FP64_VALU = 78.6e12
+PEAK_FP64_MFMA = 78.6e12
+PEAK_HBM = 8.0e12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cube1728.txt")
+
+# timer family -> (kernel, bound, peak, unit, scale of the timer's work unit)
+FAMILIES = {
+    "fill_regular": ("fill_regular_kernel<double>", "alu", PEAK_FP64_VALU, "TFLOP/s", FLOP_PER_PAIR),
+    "gemm": ("zgemm_batched_kernel", "mfma", PEAK_FP64_MFMA, "TFLOP/s", 1.0),
+    "gmres_dots": ("dots2_kernel", "hbm", PEAK_HBM, "GB/s", 1.0),
+    "gmres_update": ("dcgs_update_kernel", "hbm", PEAK_HBM, "GB/s", 1.0),
+}
 
 
 def log(*a):
@@ -55,23 +71,89 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cell_supports(w):
-    """Triangle count of each cell's RWG support (the CBF build fills each
-    cell's support against itself)."""
-    from synth.meshes import edges_canonical
-    E = edges_canonical(w.T)
-    key = {(int(a), int(b)): i for i, (a, b) in enumerate(E)}
-    tri_of = [[] for _ in range(len(E))]
-    for t, (a, b, c) in enumerate(w.T.tolist()):
-        for u, v in ((a, b), (b, c), (c, a)):
-            tri_of[key[(min(u, v), max(u, v))]].append(t)
-    sizes = []
-    for c in range(w.nblocks):
-        ts = set()
-        for e in np.nonzero(w.edge_block == c)[0]:
-            ts.update(tri_of[e])
-        sizes.append(len(ts))
-    return np.array(sizes)
+def measured_traffic():
+    """Per-kernel HBM bytes per launch from the committed counter summary,
+    kept only where the kernel's source file still has the hash recorded
+    with the measurement."""
+    out = {}
+    if not os.path.exists(TRAFFIC_FILE):
+        return out
+    for line in open(TRAFFIC_FILE):
+        if not line.startswith("kernel="):
+            continue
+        f = dict(kv.split("=", 1) for kv in line.split())
+        src = os.path.join(ROOT, f["source"])
+        if os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == f["sha256"]:
+            out[f["kernel"]] = float(f["bytes_per_dispatch"])
+    return out
+
+
+# timer family -> (substring of the kernel symbol, source file)
+FAMILY_SOURCES = {
+    "fill_regular": ("fill_regular_kernel<double", "paper_2111_11058_amd/csrc/fill.hip"),
+    "gemm": ("zgemm_batched_kernel", "paper_2111_11058_amd/csrc/gemm.hip"),
+    "gmres_dots": ("dots2_kernel", "paper_2111_11058_amd/csrc/solve.hip"),
+    "gmres_update": ("dcgs_update_kernel", "paper_2111_11058_amd/csrc/solve.hip"),
+}
+
+
+def write_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, cmd):
+    """Turn four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE of this
+    benchmark, then of the 1 GiB copy) into the traffic summary: per kernel
+    family the mean KiB per dispatch, scaled so that the copy reads and
+    writes exactly 1 GiB, with the hash of the kernel's source."""
+    import csv
+    from collections import defaultdict
+
+    def per_dispatch(d, sub):
+        acc = defaultdict(float)
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            if sub in r["Kernel_Name"]:
+                acc[r["Dispatch_Id"]] += float(r["Counter_Value"])
+        return list(acc.values())
+
+    gib_kib = float(1 << 20)
+    fs = gib_kib / np.mean(per_dispatch(cfetch_dir, "__amd_rocclr_copyBuffer"))
+    ws = gib_kib / np.mean(per_dispatch(cwrite_dir, "__amd_rocclr_copyBuffer"))
+    lines = ["# HBM traffic per dispatch, cube1728 bench step (FP64), from rocprofv3 --pmc",
+             f"# command: {cmd}",
+             f"# calibration: a 1 GiB device copy reads {1 / fs:.4f} GiB by FETCH_SIZE and writes "
+             f"{1 / ws:.4f} GiB by WRITE_SIZE; scales fetch x{fs:.4f}, write x{ws:.4f}"]
+    for fam, (sub, src) in FAMILY_SOURCES.items():
+        f, w = per_dispatch(fetch_dir, sub), per_dispatch(write_dir, sub)
+        if not f or not w:
+            continue
+        sha = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+        fk, wk = float(np.mean(f)), float(np.mean(w))
+        b = (fk * fs + wk * ws) * 1024.0
+        lines.append(f"kernel={fam} symbol={sub.split('<')[0]} source={src} sha256={sha} dispatches={len(f)} "
+                     f"fetch_kib={fk:.1f} write_kib={wk:.1f} bytes_per_dispatch={b:.0f}")
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def rooflines(cbfm, step):
+    """One step with every timer family on: achieved rate of each family
+    against its peak; the dominant family is the one with the most time."""
+    cbfm.timer_enable(list(FAMILIES))
+    step()
+    traffic = measured_traffic()
+    rows = {}
+    for fam, (kernel, bound, peak, unit, scale) in FAMILIES.items():
+        n, ms, work = cbfm.timer_read(fam, with_work=True)
+        if n == 0 or ms <= 0:
+            continue
+        per_launch = work * scale / n
+        avg_s = ms * 1e-3 / n
+        ach = per_launch / avg_s
+        div = 1e12 if unit == "TFLOP/s" else 1e9
+        rows[fam] = {"bound": bound, "achieved": ach / div, "peak": peak / div, "unit": unit, "frac": ach / peak,
+                     "traffic": traffic.get(fam), "kernel": kernel, "launches": n, "avg_launch_ms": ms / n,
+                     "total_ms": ms, "work_per_launch": per_launch}
+    cbfm.timer_enable(None)
+    dom = max(rows, key=lambda k: rows[k]["total_ms"])
+    return rows[dom], rows
 
 
 def cpu_baseline(w, sample, seed=5):
@@ -114,7 +196,13 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-fill comparison leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for the HBM byte counters)")
+    ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write the traffic summary from four rocprofv3 --pmc output folders (no GPU use)")
+    ap.add_argument("--traffic-command", default="", help="command line recorded in the traffic summary")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic, args.traffic_command)
+        return
     if args.copy_calibration:
         import torch
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
@@ -158,7 +246,6 @@ def main():
         log(f"warmup {i}")
         step(cbfm.FP64)
     torch.cuda.synchronize()
-    cbfm.timer_enable(["fill_regular"])
     proj_t, solve_t, iters = [], [], []
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -170,12 +257,8 @@ def main():
             f"iters max {out['iters'].max()} status {out['status']}")
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
-    nl, ms = cbfm.timer_read("fill_regular")
-    cbfm.timer_enable(None)
     nt = w.nt
-    pairs_per_step = nt * nt + int((cell_supports(w) ** 2).sum())
-    flops = FLOP_PER_PAIR * pairs_per_step * args.steps
-    achieved = flops / (ms * 1e-3) if ms > 0 else 0.0
+    roof, roofs = rooflines(cbfm, lambda: step(cbfm.FP64))
     nrhs = len(w.inc)
     lat = np.array(solve_t)
     result = {
@@ -199,11 +282,9 @@ def main():
         "solve_batch_latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                                    "p99": float(np.percentile(lat, 99) * 1e3)},
         "gmres_iterations": {"mean": float(np.mean(iters)), "max": int(np.max(iters))},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
-                     "kernel": "fill_regular_kernel<double>", "launches": nl,
-                     "avg_launch_ms": ms / max(nl, 1), "flop_per_pair": FLOP_PER_PAIR,
-                     "pairs_per_step": pairs_per_step},
+        "roofline": roof,
+        "roofline_kernels": roofs,
+        "flop_per_pair": FLOP_PER_PAIR,
     }
     if not args.no_fp32:
         # same step with the regular-pair fill in FP32 (near pairs, CBFs, solve in FP64)

@@ -98,15 +98,21 @@ int32_t cbfm_version(void);
  * Opt-in kernel timing for measurement: when enabled, the library records a
  * pair of HIP events on the launch stream around each launch of a named
  * kernel family and accumulates the elapsed times when they are read.
- * Names: "fill_regular", "fill_near", "assemble", "gemm" (bits 0-3).
+ * Names (bit i of the mask) and the unit of their algorithmic work:
+ *   0 "fill_regular"  triangle pairs      1 "fill_near"    near pairs
+ *   2 "assemble"      (none, 0)           3 "gemm"         real flops
+ *   4 "gmres_dots"    bytes of basis vectors the Arnoldi dot pass reads
+ *   5 "gmres_update"  bytes the Arnoldi update pass reads and writes
+ * (the GMRES figures count every right-hand side of the batch, also those
+ * already converged, which the kernels skip).
  * cbfm_timer_enable(mask) clears all timers and times the families whose
  * bit is set in mask (-1: all, 0: none).  Every timed launch adds two event
  * records to its stream, so time only the families being measured.
  * cbfm_timer_read synchronises the recorded events and returns the number
- * of launches and their total duration in milliseconds (CBFM_E_ARG for an
- * unknown name).                                                           */
+ * of launches, their total duration in milliseconds and their summed work
+ * (any output may be NULL; CBFM_E_ARG for an unknown name).               */
 cbfm_status cbfm_timer_enable(int32_t mask);
-cbfm_status cbfm_timer_read(const char* name, int64_t* launches, double* total_ms);
+cbfm_status cbfm_timer_read(const char* name, int64_t* launches, double* total_ms, double* work);
 
 /* ---------------------------------------------------------------- mesh ---
  * cbfm_mesh_load: validate a closed triangle mesh and build the RWG tables

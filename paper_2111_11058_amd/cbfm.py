@@ -66,7 +66,7 @@ def lib():
     sig = {
         "cbfm_last_error": (C.c_char_p, []),
         "cbfm_timer_enable": (_I32, [_I32]),
-        "cbfm_timer_read": (_I32, [C.c_char_p, C.POINTER(_I64), C.POINTER(C.c_double)]),
+        "cbfm_timer_read": (_I32, [C.c_char_p, C.POINTER(_I64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "cbfm_version": (_I32, []),
         "cbfm_mesh_load": (_I32, [_P, _I64, _P, _I64, _P, _I32, C.POINTER(_P)]),
         "cbfm_mesh_info": (_I32, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32), C.POINTER(_I64)]),
@@ -125,7 +125,7 @@ def _host(a, dtype):
     return a, a.ctypes.data_as(C.c_void_p)
 
 
-TIMERS = ("fill_regular", "fill_near", "assemble", "gemm")
+TIMERS = ("fill_regular", "fill_near", "assemble", "gemm", "gmres_dots", "gmres_update")
 
 
 def timer_enable(names=TIMERS):
@@ -137,11 +137,12 @@ def timer_enable(names=TIMERS):
     _check(lib().cbfm_timer_enable(mask))
 
 
-def timer_read(name):
-    """(launches, total milliseconds) recorded for kernel family ``name``."""
-    n, ms = _I64(), C.c_double()
-    _check(lib().cbfm_timer_read(name.encode(), C.byref(n), C.byref(ms)))
-    return n.value, ms.value
+def timer_read(name, with_work=False):
+    """(launches, total milliseconds[, algorithmic work]) recorded for kernel
+    family ``name`` (work units: see TIMERS in include/cbfm.h)."""
+    n, ms, wk = _I64(), C.c_double(), C.c_double()
+    _check(lib().cbfm_timer_read(name.encode(), C.byref(n), C.byref(ms), C.byref(wk)))
+    return (n.value, ms.value, wk.value) if with_work else (n.value, ms.value)
 
 
 def mesh_analyze(V, T, edge_block=None, nblocks=None):

@@ -627,7 +627,7 @@ void fill_local(const cbfm_mesh_s* m, const Media& md, int precision, int layout
   CBFM_REQUIRE(nrt <= 65535, CBFM_E_ARG, "too many row triangles for one launch");
   dim3 grid((unsigned)((nct + 255) / 256), (unsigned)nrt);
   {
-  TimedLaunch tl(T_FILL_REGULAR, s);
+  TimedLaunch tl(T_FILL_REGULAR, s, (double)nrt * (double)nct);  // work: triangle pairs
   if (precision == CBFM_FP64) {
     auto* out = static_cast<cx<double>*>(local);
     if (lossy)
@@ -648,7 +648,7 @@ void fill_local(const cbfm_mesh_s* m, const Media& md, int precision, int layout
   }
   CBFM_HIP(hipGetLastError());
   }
-  TimedLaunch tn(T_FILL_NEAR, s);
+  TimedLaunch tn(T_FILL_NEAR, s, (double)nnear);  // work: near pairs
   if (precision == CBFM_FP64)
     near_stage(m, fc, near, nnear, static_cast<cx<double>*>(local), op_stride, ldl, s);
   else

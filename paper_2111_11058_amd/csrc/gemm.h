@@ -60,6 +60,7 @@ class GemmPlan {
  private:
   Scratch dev_;
   std::vector<int64_t> first_, count_, tiles_;
+  std::vector<double> flops_;
 };
 
 }  // namespace cbfm

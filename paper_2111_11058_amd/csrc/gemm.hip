@@ -160,20 +160,21 @@ __global__ void __launch_bounds__(256) zgemm_batched_kernel(const GemmDesc* __re
 
 // Tile offsets of a group of descriptors (empty products dropped); returns
 // the group's tile count.
-static int64_t number_tiles(const std::vector<GemmDesc>& in, std::vector<GemmDesc>& out) {
+static int64_t number_tiles(const std::vector<GemmDesc>& in, std::vector<GemmDesc>& out, double* flops) {
   int64_t tiles = 0;
   for (GemmDesc d : in) {
     CBFM_REQUIRE(d.M >= 0 && d.N >= 0 && d.K >= 0, CBFM_E_ARG, "negative GEMM size");
     if (d.M == 0 || d.N == 0) continue;
     d.tile_start = tiles;
     tiles += ((d.M + 15) / 16) * ((d.N + 15) / 16);
+    *flops += 8.0 * (double)d.M * (double)d.N * (double)d.K;  // complex multiply-add = 8 real flops
     out.push_back(d);
   }
   return tiles;
 }
 
-static void launch_descs(const GemmDesc* dev, int count, int64_t tiles, hipStream_t s) {
-  TimedLaunch tl(T_GEMM, s);
+static void launch_descs(const GemmDesc* dev, int count, int64_t tiles, double flops, hipStream_t s) {
+  TimedLaunch tl(T_GEMM, s, flops);
   // few tiles: one tile per block, K split over its 4 wavefronts
   if (tiles < 4096)
     hipLaunchKernelGGL(zgemm_batched_kernel<4>, dim3((unsigned)tiles), dim3(256), 0, s, dev, count, tiles);
@@ -186,11 +187,12 @@ static void launch_descs(const GemmDesc* dev, int count, int64_t tiles, hipStrea
 void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s) {
   if (descs.empty()) return;
   std::vector<GemmDesc> live;
-  const int64_t tiles = number_tiles(descs, live);
+  double flops = 0;
+  const int64_t tiles = number_tiles(descs, live, &flops);
   if (live.empty()) return;
   Scratch dev(live.size() * sizeof(GemmDesc), s);
   CBFM_HIP(hipMemcpyAsync(dev.p, live.data(), live.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
-  launch_descs(dev.as<GemmDesc>(), (int)live.size(), tiles, s);
+  launch_descs(dev.as<GemmDesc>(), (int)live.size(), tiles, flops, s);
   // the descriptor staging buffer is host memory of this frame
   CBFM_HIP(hipStreamSynchronize(s));
 }
@@ -205,7 +207,9 @@ GemmPlan::GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t
   std::vector<GemmDesc> all;
   for (const auto& g : groups) {
     first_.push_back((int64_t)all.size());
-    tiles_.push_back(number_tiles(g, all));
+    double f = 0;
+    tiles_.push_back(number_tiles(g, all, &f));
+    flops_.push_back(f);
     count_.push_back((int64_t)all.size() - first_.back());
   }
   if (!all.empty()) {
@@ -217,7 +221,7 @@ GemmPlan::GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t
 void GemmPlan::launch(size_t g, hipStream_t s) const {
   CBFM_REQUIRE(g < tiles_.size(), CBFM_E_ARG, "GEMM plan group out of range");
   if (count_[g] == 0) return;
-  launch_descs(dev_.as<GemmDesc>() + first_[g], (int)count_[g], tiles_[g], s);
+  launch_descs(dev_.as<GemmDesc>() + first_[g], (int)count_[g], tiles_[g], flops_[g], s);
 }
 
 }  // namespace cbfm

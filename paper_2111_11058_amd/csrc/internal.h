@@ -157,13 +157,24 @@ struct cbfm_mesh_s {
 namespace cbfm {
 
 // Opt-in launch timing (see cbfm_timer_enable): start/stop bracket one
-// launch of kernel family `id` on stream s; no-ops when timing is off.
-enum TimerId { T_FILL_REGULAR = 0, T_FILL_NEAR = 1, T_ASSEMBLE = 2, T_GEMM = 3, T_COUNT = 4 };
+// launch of kernel family `id` on stream s, with its algorithmic work (the
+// family's unit: triangle pairs, real flops or bytes); no-ops when timing
+// is off.
+enum TimerId {
+  T_FILL_REGULAR = 0,
+  T_FILL_NEAR = 1,
+  T_ASSEMBLE = 2,
+  T_GEMM = 3,
+  T_GMRES_DOTS = 4,
+  T_GMRES_UPDATE = 5,
+  T_COUNT = 6
+};
 struct TimedLaunch {
-  TimedLaunch(int id, hipStream_t s);
+  TimedLaunch(int id, hipStream_t s, double work = 0.0);
   ~TimedLaunch();
   int id;
   hipStream_t s;
+  double work;
   hipEvent_t e0 = nullptr, e1 = nullptr;
 };
 

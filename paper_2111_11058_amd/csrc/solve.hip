@@ -693,13 +693,21 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
       for (int64_t j = 0; j < mres && total < prm->max_iter; ++j) {
         double2* Vn = V.as<double2>() + (j + 1) * vstride;
         matvec.launch((size_t)j, s);  // u = A q_j
-        hipLaunchKernelGGL(dots2_kernel, dim3((unsigned)(((j + 4) / 4 * nrhs + 3) / 4)), dim3(256), 0, s,
-                           V.as<double2>(), vstride, u.as<double2>(), n, nrhs, j, gs);
+        {
+          // work: bytes of q_0..q_j and w for every right-hand side
+          TimedLaunch tl(T_GMRES_DOTS, s, 16.0 * (double)(j + 2) * (double)nrhs * (double)n);
+          hipLaunchKernelGGL(dots2_kernel, dim3((unsigned)(((j + 4) / 4 * nrhs + 3) / 4)), dim3(256), 0, s,
+                             V.as<double2>(), vstride, u.as<double2>(), n, nrhs, j, gs);
+        }
         hipLaunchKernelGGL(column_kernel, g4, dim3(256), 0, s, gs, mres, j, nrhs, tol, 1);
         hipLaunchKernelGGL(coef_kernel, dim3((unsigned)(j + 1), (unsigned)((nrhs + 63) / 64)), dim3(256), 0, s, gs, mres,
                            j, nrhs);
-        hipLaunchKernelGGL(dcgs_update_kernel, dim3((unsigned)np, (unsigned)nrhs), dim3(256), 0, s, V.as<double2>(),
-                           vstride, u.as<double2>(), n, nrhs, j, gs, part.as<double>());
+        {
+          // work: bytes of q_0..q_{j-1} read, q_j and w read and written
+          TimedLaunch tl(T_GMRES_UPDATE, s, 16.0 * (double)(j + 4) * (double)nrhs * (double)n);
+          hipLaunchKernelGGL(dcgs_update_kernel, dim3((unsigned)np, (unsigned)nrhs), dim3(256), 0, s,
+                             V.as<double2>(), vstride, u.as<double2>(), n, nrhs, j, gs, part.as<double>());
+        }
         hipLaunchKernelGGL(normalize_kernel, grid2(n, nrhs), dim3(256), 0, s, u.as<double2>(), Vn, n, part.as<double>(),
                            np, gs, mres, j, nrhs);
         CBFM_HIP(hipGetLastError());
