@@ -51,16 +51,22 @@ void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s);
 
 // Groups of GEMMs whose descriptors are uploaded to the device once (one
 // synchronisation, in the constructor); launch(g) then runs group g with no
-// host round trip.  The descriptor memory is freed in stream order.
+// host round trip.  The descriptor memory is freed in stream order.  With
+// tune, each new shape class among the groups is timed once in every
+// launch shape (only groups whose products overwrite results that overlap
+// no operand) and the fastest is used from then on by every GEMM of that
+// class in the process.
 class GemmPlan {
  public:
-  GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t s);
+  GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t s, bool tune = true);
   void launch(size_t g, hipStream_t s) const;
 
  private:
+  bool tune_;
   Scratch dev_;
   std::vector<int64_t> first_, count_, tiles_;
   std::vector<double> flops_;
+  std::vector<int> variant_;
 };
 
 }  // namespace cbfm

@@ -12,6 +12,10 @@
 // The accumulator element r of lane L is C[4 r + L / 16][L % 16] (measured
 // on gfx950 with indexed operands: rows are interleaved across the four
 // lane groups).
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "internal.h"
 #include "gemm.h"
 
@@ -39,17 +43,18 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) {
 }
 
 // SPLITK = 1: each of the 4 wavefronts of a block owns a tile.
-// SPLITK = 4: the 4 wavefronts share one tile, each taking every 4th group
-// of 16 k, and the partial tiles are summed through LDS (few, deep tiles).
+// SPLITK > 1: the SPLITK wavefronts of a block share one tile, each taking
+// every SPLITK-th group of 16 k, and the partial tiles are summed through
+// LDS (few, deep tiles: more loads in flight per tile).
 template <int SPLITK>
-__global__ void __launch_bounds__(256) zgemm_batched_kernel(const GemmDesc* __restrict__ desc, int ndesc,
-                                                            int64_t total_tiles) {
+__global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK)
+    zgemm_batched_kernel(const GemmDesc* __restrict__ desc, int ndesc, int64_t total_tiles) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // wave-uniform tile and descriptor (readfirstlane makes the K loop a scalar
   // loop: the accumulators then stay in the matrix-core registers across it)
   const int64_t tile = SPLITK == 1 ? (int64_t)blockIdx.x * 4 + wave : (int64_t)blockIdx.x;
-  __shared__ double red[SPLITK == 1 ? 1 : 3 * 64 * 8];
+  __shared__ double red[SPLITK == 1 ? 1 : (SPLITK - 1) * 64 * 8];
   if (tile >= total_tiles) return;  // uniform per block when SPLITK == 4
   // descriptor holding this tile (tile_start ascending)
   int lo = 0, hi = ndesc - 1;
@@ -118,7 +123,7 @@ __global__ void __launch_bounds__(256) zgemm_batched_kernel(const GemmDesc* __re
     }
   }
   if (SPLITK > 1) {
-    // waves 1..3 hand their partial tiles to wave 0
+    // waves 1..SPLITK-1 hand their partial tiles to wave 0
     if (wave > 0) {
       double* r = red + ((wave - 1) * 64 + lane) * 8;
 #pragma unroll
@@ -130,7 +135,7 @@ __global__ void __launch_bounds__(256) zgemm_batched_kernel(const GemmDesc* __re
     __syncthreads();
     if (wave > 0) return;
 #pragma unroll
-    for (int w = 0; w < 3; ++w) {
+    for (int w = 0; w < SPLITK - 1; ++w) {
       const double* r = red + (w * 64 + lane) * 8;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -173,15 +178,121 @@ static int64_t number_tiles(const std::vector<GemmDesc>& in, std::vector<GemmDes
   return tiles;
 }
 
-static void launch_descs(const GemmDesc* dev, int count, int64_t tiles, double flops, hipStream_t s) {
-  TimedLaunch tl(T_GEMM, s, flops);
-  // few tiles: one tile per block, K split over its 4 wavefronts
-  if (tiles < 4096)
-    hipLaunchKernelGGL(zgemm_batched_kernel<4>, dim3((unsigned)tiles), dim3(256), 0, s, dev, count, tiles);
-  else
-    hipLaunchKernelGGL(zgemm_batched_kernel<1>, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, dev, count,
-                       tiles);
+// Launch shapes: four tiles per block (one per wavefront), or one tile per
+// block with K split over 4 or 8 wavefronts (16 would need more registers
+// than a 1024-thread block leaves a lane).
+enum { GV_TILE4 = 0, GV_SPLIT4, GV_SPLIT8, GV_COUNT };
+
+static void launch_variant(int v, const GemmDesc* dev, int count, int64_t tiles, hipStream_t s) {
+  const dim3 one((unsigned)tiles);
+  switch (v) {
+    case GV_TILE4:
+      hipLaunchKernelGGL(zgemm_batched_kernel<1>, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, dev, count,
+                         tiles);
+      break;
+    case GV_SPLIT4:
+      hipLaunchKernelGGL(zgemm_batched_kernel<4>, one, dim3(256), 0, s, dev, count, tiles);
+      break;
+    default:
+      hipLaunchKernelGGL(zgemm_batched_kernel<8>, one, dim3(512), 0, s, dev, count, tiles);
+      break;
+  }
   CBFM_HIP(hipGetLastError());
+}
+
+// Shape class of a group for the tuning cache.
+struct GemmKey {
+  int dev, count, opA, opB;
+  int64_t tiles, M, N, K;
+  bool operator<(const GemmKey& o) const {
+    return std::tie(dev, count, opA, opB, tiles, M, N, K) < std::tie(o.dev, o.count, o.opA, o.opB, o.tiles, o.M, o.N, o.K);
+  }
+};
+
+static std::mutex g_tune_mu;
+static std::map<GemmKey, int> g_tuned;  // launch shape measured fastest, per shape class
+
+static GemmKey key_of(const GemmDesc* d, int count, int64_t tiles) {
+  int dev = 0;
+  CBFM_HIP(hipGetDevice(&dev));
+  int64_t K = 0;
+  for (int i = 0; i < count; ++i) K = std::max(K, d[i].K);
+  return GemmKey{dev, count, d[0].opA, d[0].opB, tiles, d[0].M, d[0].N, K};
+}
+
+// Without a measurement: few tiles get the K split over four wavefronts.
+static int choose(const GemmKey& k) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(k);
+  if (it != g_tuned.end()) return it->second;
+  return k.tiles < 4096 ? GV_SPLIT4 : GV_TILE4;
+}
+
+static void launch_descs(const GemmDesc* dev, int count, int64_t tiles, double flops, int variant, hipStream_t s) {
+  TimedLaunch tl(T_GEMM, s, flops);
+  launch_variant(variant, dev, count, tiles, s);
+}
+
+// Elements spanned by an operand or the result of a descriptor.
+static int64_t extent(int64_t rows, int64_t cols, int64_t ld) { return (rows - 1) * ld + cols; }
+
+// A group may be run repeatedly for timing only if every product overwrites
+// its result without reading it and no result overlaps an operand.
+static bool rerunnable(const std::vector<GemmDesc>& g) {
+  for (const GemmDesc& d : g) {
+    if (d.accumulate) return false;
+    const char* c0 = reinterpret_cast<const char*>(d.C);
+    const char* c1 = c0 + 16 * (d.transC ? extent(d.N, d.M, d.ldc) : extent(d.M, d.N, d.ldc));
+    for (const GemmDesc& e : g) {
+      const bool ta = e.opA == OP_T || e.opA == OP_C, tb = e.opB == OP_T || e.opB == OP_C;
+      const char* a0 = reinterpret_cast<const char*>(e.A);
+      const char* a1 = a0 + 16 * (ta ? extent(e.K, e.M, e.lda) : extent(e.M, e.K, e.lda));
+      const char* b0 = reinterpret_cast<const char*>(e.B);
+      const char* b1 = b0 + 16 * (tb ? extent(e.N, e.K, e.ldb) : extent(e.K, e.N, e.ldb));
+      if ((c0 < a1 && a0 < c1) || (c0 < b1 && b0 < c1)) return false;
+    }
+  }
+  return true;
+}
+
+// Autotuning: time every launch shape on the group itself (one warm-up and
+// three timed launches each) and remember the fastest for its shape class.
+static void tune_group(const GemmKey& key, const GemmDesc* dev, int count, int64_t tiles, hipStream_t s) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_tuned.count(key)) return;
+  }
+  hipEvent_t e0, e1;
+  CBFM_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    throw Error{CBFM_E_HIP, "hipEventCreate failed"};
+  }
+  int best = choose(key);
+  float best_ms = 0;
+  try {
+    for (int v = 0; v < GV_COUNT; ++v) {
+      launch_variant(v, dev, count, tiles, s);
+      CBFM_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) launch_variant(v, dev, count, tiles, s);
+      CBFM_HIP(hipEventRecord(e1, s));
+      CBFM_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      CBFM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (v == 0 || ms < best_ms) {
+        best = v;
+        best_ms = ms;
+      }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = best;
 }
 
 void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s) {
@@ -192,13 +303,14 @@ void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s) {
   if (live.empty()) return;
   Scratch dev(live.size() * sizeof(GemmDesc), s);
   CBFM_HIP(hipMemcpyAsync(dev.p, live.data(), live.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
-  launch_descs(dev.as<GemmDesc>(), (int)live.size(), tiles, flops, s);
+  launch_descs(dev.as<GemmDesc>(), (int)live.size(), tiles, flops, choose(key_of(live.data(), (int)live.size(), tiles)),
+               s);
   // the descriptor staging buffer is host memory of this frame
   CBFM_HIP(hipStreamSynchronize(s));
 }
 
-GemmPlan::GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t s)
-    : dev_(std::max<size_t>(1, [&] {
+GemmPlan::GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t s, bool tune)
+    : tune_(tune), dev_(std::max<size_t>(1, [&] {
              size_t k = 0;
              for (const auto& g : groups) k += g.size();
              return k;
@@ -216,12 +328,21 @@ GemmPlan::GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t
     CBFM_HIP(hipMemcpyAsync(dev_.p, all.data(), all.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
     CBFM_HIP(hipStreamSynchronize(s));  // `all` is host memory of this frame
   }
+  for (size_t g = 0; g < groups.size(); ++g) {
+    if (count_[g] == 0) {
+      variant_.push_back(GV_TILE4);
+      continue;
+    }
+    const GemmKey k = key_of(all.data() + first_[g], (int)count_[g], tiles_[g]);
+    if (tune_ && rerunnable(groups[g])) tune_group(k, dev_.as<GemmDesc>() + first_[g], (int)count_[g], tiles_[g], s);
+    variant_.push_back(choose(k));
+  }
 }
 
 void GemmPlan::launch(size_t g, hipStream_t s) const {
   CBFM_REQUIRE(g < tiles_.size(), CBFM_E_ARG, "GEMM plan group out of range");
   if (count_[g] == 0) return;
-  launch_descs(dev_.as<GemmDesc>() + first_[g], (int)count_[g], tiles_[g], flops_[g], s);
+  launch_descs(dev_.as<GemmDesc>() + first_[g], (int)count_[g], tiles_[g], flops_[g], variant_[g], s);
 }
 
 }  // namespace cbfm
