@@ -193,7 +193,7 @@ def main():
     ap.add_argument("--workload", default="cube1728", choices=["cube1728", "sphere320"])
     ap.add_argument("--cpu-sample", type=int, default=250000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-fill comparison leg")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the precision-form legs (FP32 fill, mixed FP32 and split-BF16)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for the HBM byte counters)")
     ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -227,7 +227,7 @@ def main():
     solver = dict(tol=1e-6)
     state = {}
 
-    def step(precision):
+    def step(precision, inner_fp32=False):
         cb = cbfm.build_cbf(mesh, med, w.gen, w.delta_svd)
         n = cb.n_cbf
         Zr = state.get(n)
@@ -238,7 +238,8 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         # full (unrestarted) GMRES: the Krylov dimension is bounded by N_CBF
-        out = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, max_iter=n, restart=n, **solver)
+        out = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, max_iter=(3 if inner_fp32 else 1) * n, restart=n,
+                         inner_fp32=inner_fp32, **solver)
         t2 = time.perf_counter()
         return cb, out, t1 - t0, t2 - t1
 
@@ -287,13 +288,32 @@ def main():
         "flop_per_pair": FLOP_PER_PAIR,
     }
     if not args.no_fp32:
-        # same step with the regular-pair fill in FP32 (near pairs, CBFs, solve in FP64)
-        step(cbfm.FP32)
-        t32 = []
-        for _ in range(max(1, args.steps // 2)):
-            _, out32, tp, ts = step(cbfm.FP32)
-            t32.append(tp)
-        result["fp32_fill"] = {"fill_projection_pair_evals_per_s": nt * nt / float(np.median(t32))}
+        # the precision forms on the same workload: FP32 regular fill with the
+        # FP64 projection and solve; and the mixed forms (FP32 fill, FP32 or
+        # split-BF16 matrix-core projection, float GMRES cycles refined
+        # against the double residual).  CBF build, near pairs, the SVD and
+        # the refinement residual stay FP64.  RCS error against this run's
+        # FP64 step.
+        rcs64 = out["rcs"]
+        forms = {}
+        for name, prec, inner in (("fp32_fill", cbfm.FP32, False), ("mixed_fp32", cbfm.MIXED_FP32, True),
+                                  ("mixed_bf16x3", cbfm.MIXED_BF16X3, True)):
+            step(prec, inner)
+            tp_l, ts_l, tt = [], [], time.perf_counter()
+            k = max(1, args.steps // 2)
+            for _ in range(k):
+                _, o, tp, ts = step(prec, inner)
+                tp_l.append(tp)
+                ts_l.append(ts)
+            torch.cuda.synchronize()
+            tt = time.perf_counter() - tt
+            forms[name] = {"value": nt * nt * k / tt, "ms_per_step": tt / k * 1e3,
+                           "fill_projection_pair_evals_per_s": nt * nt / float(np.median(tp_l)),
+                           "solves_per_s": nrhs * k / float(np.sum(ts_l)),
+                           "gmres_iterations_max": int(o["iters"].max()), "status": o["status"],
+                           "rcs_max_rel_err_vs_fp64": float(np.max(np.abs(o["rcs"] - rcs64) / rcs64))}
+            log(f"{name}: {forms[name]}")
+        result["precision_forms"] = forms
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)

@@ -71,7 +71,16 @@ typedef enum {
   CBFM_E_STATE = -7    /* handles of different meshes mixed                 */
 } cbfm_status;
 
-typedef enum { CBFM_FP64 = 0, CBFM_FP32 = 1 } cbfm_precision;
+typedef enum {
+  CBFM_FP64 = 0,       /* everything in double                                  */
+  CBFM_FP32 = 1,       /* regular-pair fill in float; the rest in double        */
+  CBFM_MIXED_FP32 = 2, /* projection only: float fill and panel, projection on  */
+                       /* the FP32 matrix cores (FP32 accumulation)             */
+  CBFM_MIXED_BF16 = 3, /* projection only: as MIXED_FP32 with BF16 inputs to   */
+                       /* the matrix cores (FP32 accumulation)                  */
+  CBFM_MIXED_BF16X3 = 4 /* projection only: split BF16 (x = hi + lo, products  */
+                        /* hi hi + hi lo + lo hi, about 16 significant bits)    */
+} cbfm_precision;
 
 /* Output layout of cbfm_fill_pmchwt: three nrow x ncol complex matrices,
    matrix after matrix. */
@@ -224,8 +233,12 @@ void cbfm_cbf_free(cbfm_cbf c);
  * cbfm_project: reduced matrix Z_r = (C^JM)^H Z C^MJ (paper Sec. III-C,
  * outer CBFM equation): rows [J-test CBFs of cells 1..M ; M-test CBFs],
  * columns [M-trial CBFs ; J-trial CBFs], each group cell after cell.
- * The PMCHWT fill is computed inside (precision as in cbfm_fill_pmchwt) and
- * projected on the matrix cores; Z is held only in stream-ordered scratch.
+ * The PMCHWT fill is computed inside and projected on the matrix cores; Z
+ * is held only in stream-ordered scratch.  precision: CBFM_FP64, CBFM_FP32
+ * (fill as in cbfm_fill_pmchwt, projection in double) or the mixed forms
+ * CBFM_MIXED_FP32 / CBFM_MIXED_BF16 / CBFM_MIXED_BF16X3 (float fill, float
+ * panel, FP32, BF16 or split-BF16 matrix-core projection with FP32
+ * accumulation; Z_r still stored double).
  *   Zr_dev  N_CBF x N_CBF double2, row-major, ldz >= N_CBF                 */
 cbfm_status cbfm_project(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, int32_t precision,
                          void* Zr_dev, int64_t ldz, void* stream);
@@ -256,9 +269,14 @@ cbfm_status cbfm_cmp_apply(cbfm_cbf c, int64_t nrhs, const void* y_dev, void* x_
  * Synchronises the stream.  CBFM_E_NOCONV if some RHS did not reach tol.  */
 typedef struct {
   double tol;
-  int32_t max_iter;
-  int32_t restart;
+  int32_t max_iter;   /* Arnoldi iterations over all cycles                */
+  int32_t restart;    /* cycle length                                      */
   int32_t use_cmp;
+  int32_t inner_fp32; /* 1: mixed form -- Krylov basis and operator in     */
+                      /* float, each cycle started from the residual       */
+                      /* b - A x formed in double (iterative refinement)   */
+                      /* and stopped once it has reduced it by inner_tol   */
+  double inner_tol;   /* mixed form only; 0 -> 1e-6                         */
 } cbfm_solver_params;
 
 cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, const void* Zr_dev,

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcbfm.so")
 
-FP64, FP32 = 0, 1
+FP64, FP32, MIXED_FP32, MIXED_BF16, MIXED_BF16X3 = 0, 1, 2, 3, 4
 LAYOUT_MEDIA3, LAYOUT_OPS3 = 0, 1
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_MESH", -3: "E_NOMEM", -4: "E_HIP", -5: "E_NOCONV",
@@ -46,7 +46,7 @@ class CbfParams(C.Structure):
 
 class SolverParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32),
-                ("use_cmp", C.c_int32)]
+                ("use_cmp", C.c_int32), ("inner_fp32", C.c_int32), ("inner_tol", C.c_double)]
 
 
 _lib = None
@@ -321,8 +321,11 @@ def cmp_apply(cbf: CBF, y, x, stream=None):
 
 
 def solve(mesh: Mesh, medium: Medium, cbf: CBF, Zr, inc, tol=1e-6, max_iter=1000, restart=100,
-          use_cmp=True, j_out=None, dirs=None, ldz=None, stream=None, raise_noconv=False):
-    """cbfm_solve.  Returns dict(iters, relres, rcs, status)."""
+          use_cmp=True, j_out=None, dirs=None, ldz=None, stream=None, raise_noconv=False, inner_fp32=False,
+          inner_tol=0.0):
+    """cbfm_solve.  Returns dict(iters, relres, rcs, status).  inner_fp32
+    selects the mixed form (float Krylov cycles refined against the double
+    residual, each cycle reducing it by inner_tol)."""
     import torch
     inc, pi = _host(inc, np.float64)
     inc = inc.reshape(-1, 6)
@@ -341,7 +344,8 @@ def solve(mesh: Mesh, medium: Medium, cbf: CBF, Zr, inc, tol=1e-6, max_iter=1000
     else:
         pd, nd = None, 0
         rcs = np.zeros(nrhs)
-    prm = SolverParams(float(tol), int(max_iter), int(restart), int(bool(use_cmp)))
+    prm = SolverParams(float(tol), int(max_iter), int(restart), int(bool(use_cmp)), int(bool(inner_fp32)),
+                       float(inner_tol))
     code = lib().cbfm_solve(mesh.handle, C.byref(medium), cbf.handle, pz, ldz, pi, nrhs, C.byref(prm), pj,
                             iters.ctypes.data_as(C.c_void_p), relres.ctypes.data_as(C.c_void_p), pd, nd,
                             rcs.ctypes.data_as(C.c_void_p), _stream(stream))

@@ -49,6 +49,63 @@ inline GemmDesc gemm(const double2* A, int64_t lda, int opA, const double2* B, i
 // Launch all GEMMs of `descs` in one kernel on stream s (synchronises s).
 void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s);
 
+// Complex GEMM on the FP32 or BF16 matrix cores with FP32 accumulation.
+// Operands and result may each be complex double (converted on load or
+// store) or complex float; layout and ops as GemmDesc.  XG_BF16X3 splits
+// each float operand into two BF16 parts and keeps three of the four
+// partial products (about 16 significant bits).
+enum { XG_FP32 = 0, XG_BF16 = 1, XG_BF16X3 = 2 };
+struct GemmDescX {
+  const void* A;
+  const void* B;
+  void* C;
+  int64_t lda, ldb, ldc;
+  int64_t M, N, K;
+  int32_t opA, opB;
+  int32_t a64, b64, c64;  // 1: complex double, 0: complex float
+  int32_t transC;
+  float alpha_re, alpha_im;
+  int64_t tile_start;  // filled by xgemm_batched
+};
+
+inline GemmDescX gemmx(const void* A, int a64, int64_t lda, int opA, const void* B, int b64, int64_t ldb, int opB,
+                       void* C, int c64, int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha = 1.0f) {
+  GemmDescX d{};
+  d.A = A;
+  d.B = B;
+  d.C = C;
+  d.lda = lda;
+  d.ldb = ldb;
+  d.ldc = ldc;
+  d.M = M;
+  d.N = N;
+  d.K = K;
+  d.opA = opA;
+  d.opB = opB;
+  d.a64 = a64;
+  d.b64 = b64;
+  d.c64 = c64;
+  d.alpha_re = alpha;
+  d.alpha_im = 0.0f;
+  return d;
+}
+
+// mode XG_FP32 or XG_BF16; synchronises s.
+void xgemm_batched(std::vector<GemmDescX>& descs, int mode, hipStream_t s);
+
+// As GemmPlan, for the FP32 / BF16 matrix cores (no tuning).
+class XGemmPlan {
+ public:
+  XGemmPlan(const std::vector<std::vector<GemmDescX>>& groups, int mode, hipStream_t s);
+  void launch(size_t g, hipStream_t s) const;
+
+ private:
+  int mode_;
+  Scratch dev_;
+  std::vector<int64_t> first_, count_, tiles_;
+  std::vector<double> flops_;
+};
+
 // Groups of GEMMs whose descriptors are uploaded to the device once (one
 // synchronisation, in the constructor); launch(g) then runs group g with no
 // host round trip.  The descriptor memory is freed in stream order.  With

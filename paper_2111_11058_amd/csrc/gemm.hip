@@ -163,6 +163,246 @@ __global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK)
   }
 }
 
+// ------------------------------------------------------------------------
+// FP32 / BF16 matrix cores (FP32 accumulation).  v_mfma_f32_16x16x4f32 and
+// v_mfma_f32_16x16x32_bf16 take A[L % 16][k] and B[k][L % 16] in lane L for
+// the k of the lane's slot L / 16 (one k per slot in FP32, eight
+// consecutive k per slot in BF16); their accumulator element r of lane L is
+// C[4 (L / 16) + r][L % 16] (measured on gfx950; unlike the FP64
+// instruction, the four rows of a lane are consecutive).
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ float2 ldx(const void* __restrict__ X, int is64, int64_t ld, int op, int64_t i, int64_t k,
+                                      int64_t rows, int64_t cols) {
+  const bool ok = i < rows && k < cols;
+  const int64_t ii = ok ? i : 0, kk = ok ? k : 0;
+  const int64_t idx = (op == OP_N || op == OP_R) ? ii * ld + kk : kk * ld + ii;
+  float2 v;
+  if (is64) {
+    const double2 d = static_cast<const double2*>(X)[idx];
+    v = make_float2((float)d.x, (float)d.y);
+  } else {
+    v = static_cast<const float2*>(X)[idx];
+  }
+  v.x = ok ? v.x : 0.0f;
+  v.y = ok ? ((op == OP_C || op == OP_R) ? -v.y : v.y) : 0.0f;
+  return v;
+}
+
+template <int MODE, int SPLITK>
+__global__ void __launch_bounds__(256) xgemm_batched_kernel(const GemmDescX* __restrict__ desc, int ndesc,
+                                                            int64_t total_tiles) {
+  constexpr int KG = MODE == XG_FP32 ? 16 : 32;  // k per step of a wavefront
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t tile = SPLITK == 1 ? (int64_t)blockIdx.x * 4 + wave : (int64_t)blockIdx.x;
+  __shared__ float red[SPLITK == 1 ? 1 : (SPLITK - 1) * 64 * 8];
+  if (tile >= total_tiles) return;  // uniform per block when SPLITK > 1
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].tile_start <= tile)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  GemmDescX d = desc[lo];
+  d.M = uniform64(d.M);
+  d.N = uniform64(d.N);
+  d.K = uniform64(d.K);
+  d.lda = uniform64(d.lda);
+  d.ldb = uniform64(d.ldb);
+  d.ldc = uniform64(d.ldc);
+  d.tile_start = uniform64(d.tile_start);
+  d.opA = __builtin_amdgcn_readfirstlane(d.opA);
+  d.opB = __builtin_amdgcn_readfirstlane(d.opB);
+  d.a64 = __builtin_amdgcn_readfirstlane(d.a64);
+  d.b64 = __builtin_amdgcn_readfirstlane(d.b64);
+  const int64_t t = tile - d.tile_start;
+  const int64_t ntn = (d.N + 15) / 16;
+  const int64_t m0 = (t / ntn) * 16, n0 = (t % ntn) * 16;
+  const int64_t ia = m0 + (lane & 15), jb = n0 + (lane & 15);
+  const int slot = lane >> 4;
+  flt4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+  for (int64_t k0 = SPLITK == 1 ? 0 : (int64_t)KG * wave; k0 < d.K; k0 += (int64_t)KG * SPLITK) {
+    if constexpr (MODE == XG_FP32) {
+      float2 a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t k = k0 + 4 * slot + q;
+        a[q] = ldx(d.A, d.a64, d.lda, d.opA, ia, k, d.M, d.K);
+        b[q] = ldx(d.B, d.b64, d.ldb, d.opB, k, jb, d.K, d.N);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q].x, b[q].x, cr, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[q].y, b[q].y, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q].x, b[q].y, ci, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q].y, b[q].x, ci, 0, 0, 0);
+      }
+    } else if constexpr (MODE == XG_BF16) {
+      bf16x8 ar, ai, an, br, bi;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t k = k0 + 8 * slot + q;
+        const float2 a = ldx(d.A, d.a64, d.lda, d.opA, ia, k, d.M, d.K);
+        const float2 b = ldx(d.B, d.b64, d.ldb, d.opB, k, jb, d.K, d.N);
+        ar[q] = (__bf16)a.x;
+        ai[q] = (__bf16)a.y;
+        an[q] = (__bf16)(-a.y);
+        br[q] = (__bf16)b.x;
+        bi[q] = (__bf16)b.y;
+      }
+      cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br, cr, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(an, bi, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, bi, ci, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, br, ci, 0, 0, 0);
+    } else {
+      // split BF16: x = hi + lo with hi = bf16(x), lo = bf16(x - hi); the
+      // products hi*hi + hi*lo + lo*hi keep about 16 significant bits
+      bf16x8 arh, arl, aih, ail, anh, anl, brh, brl, bih, bil;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t k = k0 + 8 * slot + q;
+        const float2 a = ldx(d.A, d.a64, d.lda, d.opA, ia, k, d.M, d.K);
+        const float2 b = ldx(d.B, d.b64, d.ldb, d.opB, k, jb, d.K, d.N);
+        arh[q] = (__bf16)a.x;
+        arl[q] = (__bf16)(a.x - (float)arh[q]);
+        aih[q] = (__bf16)a.y;
+        ail[q] = (__bf16)(a.y - (float)aih[q]);
+        anh[q] = -aih[q];
+        anl[q] = -ail[q];
+        brh[q] = (__bf16)b.x;
+        brl[q] = (__bf16)(b.x - (float)brh[q]);
+        bih[q] = (__bf16)b.y;
+        bil[q] = (__bf16)(b.y - (float)bih[q]);
+      }
+#define XG_SPLIT3(acc, xh, xl, yh, yl)                                  \
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, yh, acc, 0, 0, 0); \
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yl, acc, 0, 0, 0); \
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yh, acc, 0, 0, 0);
+      XG_SPLIT3(cr, arh, arl, brh, brl)
+      XG_SPLIT3(cr, anh, anl, bih, bil)
+      XG_SPLIT3(ci, arh, arl, bih, bil)
+      XG_SPLIT3(ci, aih, ail, brh, brl)
+#undef XG_SPLIT3
+    }
+  }
+  if (SPLITK > 1) {
+    if (wave > 0) {
+      float* r = red + ((wave - 1) * 64 + lane) * 8;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        r[q] = cr[q];
+        r[4 + q] = ci[q];
+      }
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int w = 0; w < SPLITK - 1; ++w) {
+      const float* r = red + (w * 64 + lane) * 8;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cr[q] += r[q];
+        ci[q] += r[4 + q];
+      }
+    }
+  }
+  const int64_t col = n0 + (lane & 15);
+  if (col >= d.N) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = m0 + 4 * slot + r;
+    if (row < d.M) {
+      const float xr = cr[r], xi = ci[r];
+      const float vr = d.alpha_re * xr - d.alpha_im * xi, vi = d.alpha_re * xi + d.alpha_im * xr;
+      const int64_t off = d.transC ? col * d.ldc + row : row * d.ldc + col;
+      if (d.c64)
+        static_cast<double2*>(d.C)[off] = make_double2(vr, vi);
+      else
+        static_cast<float2*>(d.C)[off] = make_float2(vr, vi);
+    }
+  }
+}
+
+static int64_t number_tiles_x(const std::vector<GemmDescX>& in, std::vector<GemmDescX>& out, double* flops) {
+  int64_t tiles = 0;
+  for (GemmDescX d : in) {
+    CBFM_REQUIRE(d.M >= 0 && d.N >= 0 && d.K >= 0, CBFM_E_ARG, "negative GEMM size");
+    if (d.M == 0 || d.N == 0) continue;
+    d.tile_start = tiles;
+    tiles += ((d.M + 15) / 16) * ((d.N + 15) / 16);
+    *flops += 8.0 * (double)d.M * (double)d.N * (double)d.K;
+    out.push_back(d);
+  }
+  return tiles;
+}
+
+static void launch_x(const GemmDescX* dd, int n, int64_t tiles, double flops, int mode, hipStream_t s) {
+  TimedLaunch tl(T_GEMM, s, flops);
+  const bool few = tiles < 4096;
+  const dim3 g(few ? (unsigned)tiles : (unsigned)((tiles + 3) / 4));
+  if (mode == XG_BF16) {
+    if (few)
+      hipLaunchKernelGGL((xgemm_batched_kernel<XG_BF16, 4>), g, dim3(256), 0, s, dd, n, tiles);
+    else
+      hipLaunchKernelGGL((xgemm_batched_kernel<XG_BF16, 1>), g, dim3(256), 0, s, dd, n, tiles);
+  } else if (mode == XG_BF16X3) {
+    if (few)
+      hipLaunchKernelGGL((xgemm_batched_kernel<XG_BF16X3, 4>), g, dim3(256), 0, s, dd, n, tiles);
+    else
+      hipLaunchKernelGGL((xgemm_batched_kernel<XG_BF16X3, 1>), g, dim3(256), 0, s, dd, n, tiles);
+  } else {
+    if (few)
+      hipLaunchKernelGGL((xgemm_batched_kernel<XG_FP32, 4>), g, dim3(256), 0, s, dd, n, tiles);
+    else
+      hipLaunchKernelGGL((xgemm_batched_kernel<XG_FP32, 1>), g, dim3(256), 0, s, dd, n, tiles);
+  }
+  CBFM_HIP(hipGetLastError());
+}
+
+void xgemm_batched(std::vector<GemmDescX>& descs, int mode, hipStream_t s) {
+  if (descs.empty()) return;
+  std::vector<GemmDescX> live;
+  double flops = 0;
+  const int64_t tiles = number_tiles_x(descs, live, &flops);
+  if (live.empty()) return;
+  Scratch dev(live.size() * sizeof(GemmDescX), s);
+  CBFM_HIP(hipMemcpyAsync(dev.p, live.data(), live.size() * sizeof(GemmDescX), hipMemcpyHostToDevice, s));
+  launch_x(dev.as<GemmDescX>(), (int)live.size(), tiles, flops, mode, s);
+  CBFM_HIP(hipStreamSynchronize(s));  // the descriptor staging buffer is host memory of this frame
+}
+
+XGemmPlan::XGemmPlan(const std::vector<std::vector<GemmDescX>>& groups, int mode, hipStream_t s)
+    : mode_(mode), dev_(std::max<size_t>(1, [&] {
+                          size_t k = 0;
+                          for (const auto& g : groups) k += g.size();
+                          return k;
+                        }()) * sizeof(GemmDescX),
+                        s) {
+  std::vector<GemmDescX> all;
+  for (const auto& g : groups) {
+    first_.push_back((int64_t)all.size());
+    double f = 0;
+    tiles_.push_back(number_tiles_x(g, all, &f));
+    flops_.push_back(f);
+    count_.push_back((int64_t)all.size() - first_.back());
+  }
+  if (!all.empty()) {
+    CBFM_HIP(hipMemcpyAsync(dev_.p, all.data(), all.size() * sizeof(GemmDescX), hipMemcpyHostToDevice, s));
+    CBFM_HIP(hipStreamSynchronize(s));  // `all` is host memory of this frame
+  }
+}
+
+void XGemmPlan::launch(size_t g, hipStream_t s) const {
+  CBFM_REQUIRE(g < tiles_.size(), CBFM_E_ARG, "GEMM plan group out of range");
+  if (count_[g] == 0) return;
+  launch_x(dev_.as<GemmDescX>() + first_[g], (int)count_[g], tiles_[g], flops_[g], mode_, s);
+}
+
 // Tile offsets of a group of descriptors (empty products dropped); returns
 // the group's tile count.
 static int64_t number_tiles(const std::vector<GemmDesc>& in, std::vector<GemmDesc>& out, double* flops) {

@@ -5,8 +5,9 @@
 // Rows are processed in panels of whole cells.  For a panel the fill
 // kernels produce the triangle-local blocks of the panel's test triangles
 // against every source triangle, the gather kernel assembles the panel's
-// rows of K, TE, TH (upcast to double), and two batched matrix-core GEMM
-// launches form
+// rows of K, TE, TH (upcast to double, or kept in float for the mixed
+// forms), and two batched matrix-core GEMM launches (FP64, or FP32 / BF16
+// inputs with FP32 accumulation) form
 //   W_X[rows, cell b] = X[rows, cell b] C_b          (X in K, TE, TH)
 //   Z_r[cell a rows]  = C_a^H W_X[cell a rows, :]
 // so only one panel of Z exists at a time.
@@ -28,7 +29,11 @@ void project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int preci
   const MeshHost& h = m->h;
   const int nb = h.nblocks;
   const int64_t ne = h.ne, nt = h.nt, NL = c->NL;
-  const size_t esz = precision == CBFM_FP64 ? 16 : 8;
+  // mixed forms: FP32 regular fill, panel and W in complex float, projection
+  // on the FP32 or BF16 matrix cores (FP32 accumulation), Z_r stored double
+  const bool mixed = precision == CBFM_MIXED_FP32 || precision == CBFM_MIXED_BF16 || precision == CBFM_MIXED_BF16X3;
+  const int fillp = precision == CBFM_FP64 ? CBFM_FP64 : CBFM_FP32;
+  const size_t esz = fillp == CBFM_FP64 ? 16 : 8;
   // column side: every triangle, every edge (internal order)
   std::vector<int32_t> iota(nt);
   for (int64_t t = 0; t < nt; ++t) iota[t] = (int32_t)t;
@@ -100,10 +105,46 @@ void project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int preci
     auto* d_nl = (NearPair*)put(nl.data(), sizeof(NearPair) * nl.size());
     CBFM_HIP(hipMemcpyAsync(idx.p, host.data(), ib, hipMemcpyHostToDevice, s));
     Scratch local((size_t)27 * nrt * nt * esz, s);
-    Scratch Zp((size_t)3 * nrow * ne * sizeof(double2), s);
-    Scratch W((size_t)4 * nrow * NL * sizeof(double2), s);
-    fill_local(m, md, precision, CBFM_LAYOUT_OPS3, d_rows, nrt, colTris, nt, d_nl, (int64_t)nl.size(), local.p, s);
-    assemble(m, precision, local.p, nrt, nt, d_re, nrow, colEdges, ne, d_pos, colPos, Zp.p, nrow * ne, ne, s, 1);
+    const size_t zsz = mixed ? sizeof(float2) : sizeof(double2);
+    Scratch Zp((size_t)3 * nrow * ne * zsz, s);
+    Scratch W((size_t)4 * nrow * NL * zsz, s);
+    fill_local(m, md, fillp, CBFM_LAYOUT_OPS3, d_rows, nrt, colTris, nt, d_nl, (int64_t)nl.size(), local.p, s);
+    assemble(m, fillp, local.p, nrt, nt, d_re, nrow, colEdges, ne, d_pos, colPos, Zp.p, nrow * ne, ne, s,
+             mixed ? 0 : 1);
+    if (mixed) {
+      const float2* Zk = Zp.as<float2>();
+      const float2* Zte = Zk + nrow * ne;
+      const float2* Zth = Zte + nrow * ne;
+      float2* Wkm = W.as<float2>();
+      float2* Wkj = Wkm + nrow * NL;
+      float2* Wte = Wkj + nrow * NL;
+      float2* Wth = Wte + nrow * NL;
+      std::vector<GemmDescX> x1, x2;
+      for (int b = 0; b < nb; ++b) {
+        const int64_t Nb = h.cell_off[b + 1] - h.cell_off[b], cb0 = h.cell_off[b];
+        const double2* CMb = c->CM.as<double2>() + c->coff[b];
+        const double2* CJb = c->CJ.as<double2>() + c->coff[b];
+        const int64_t Lb = c->L[b], ob = c->off[b];
+        x1.push_back(gemmx(Zk + cb0, 0, ne, OP_N, CMb, 1, Lb, OP_N, Wkm + ob, 0, NL, nrow, Lb, Nb));
+        x1.push_back(gemmx(Zk + cb0, 0, ne, OP_N, CJb, 1, Lb, OP_N, Wkj + ob, 0, NL, nrow, Lb, Nb));
+        x1.push_back(gemmx(Zte + cb0, 0, ne, OP_N, CJb, 1, Lb, OP_N, Wte + ob, 0, NL, nrow, Lb, Nb));
+        x1.push_back(gemmx(Zth + cb0, 0, ne, OP_N, CMb, 1, Lb, OP_N, Wth + ob, 0, NL, nrow, Lb, Nb));
+      }
+      for (int a = p0; a < p1; ++a) {
+        const int64_t Na = h.cell_off[a + 1] - h.cell_off[a], ra = h.cell_off[a] - r0;
+        const double2* CMa = c->CM.as<double2>() + c->coff[a];
+        const double2* CJa = c->CJ.as<double2>() + c->coff[a];
+        const int64_t La = c->L[a], oa = c->off[a];
+        x2.push_back(gemmx(CJa, 1, La, OP_C, Wkm + ra * NL, 0, NL, OP_N, Zr + oa * ldz, 1, ldz, La, NL, Na));
+        x2.push_back(gemmx(CJa, 1, La, OP_C, Wte + ra * NL, 0, NL, OP_N, Zr + oa * ldz + NL, 1, ldz, La, NL, Na, -1.0f));
+        x2.push_back(gemmx(CMa, 1, La, OP_C, Wth + ra * NL, 0, NL, OP_N, Zr + (NL + oa) * ldz, 1, ldz, La, NL, Na));
+        x2.push_back(gemmx(CMa, 1, La, OP_C, Wkj + ra * NL, 0, NL, OP_N, Zr + (NL + oa) * ldz + NL, 1, ldz, La, NL, Na));
+      }
+      const int mode = precision == CBFM_MIXED_BF16 ? XG_BF16 : precision == CBFM_MIXED_BF16X3 ? XG_BF16X3 : XG_FP32;
+      xgemm_batched(x1, mode, s);
+      xgemm_batched(x2, mode, s);
+      continue;  // xgemm_batched synchronised the stream
+    }
     double2* Zk = Zp.as<double2>();
     double2* Zte = Zk + nrow * ne;
     double2* Zth = Zte + nrow * ne;
@@ -147,7 +188,9 @@ extern "C" cbfm_status cbfm_project(cbfm_mesh m, const cbfm_medium* med, cbfm_cb
   return guarded([&] {
     CBFM_REQUIRE(m && c && Zr, CBFM_E_ARG, "null argument");
     CBFM_REQUIRE(c->mesh == m, CBFM_E_STATE, "CBF set belongs to another mesh");
-    CBFM_REQUIRE(precision == CBFM_FP64 || precision == CBFM_FP32, CBFM_E_ARG, "unknown precision");
+    CBFM_REQUIRE(precision == CBFM_FP64 || precision == CBFM_FP32 || precision == CBFM_MIXED_FP32 ||
+                     precision == CBFM_MIXED_BF16 || precision == CBFM_MIXED_BF16X3,
+                 CBFM_E_ARG, "unknown precision");
     CBFM_REQUIRE(ldz >= 2 * c->NL, CBFM_E_ARG, "ldz < N_CBF");
     const Media md = make_media(med);
     // scratch budget per panel: a quarter of the free device memory, at most 32 GiB

@@ -44,6 +44,16 @@ __device__ inline double2 cmul(double2 a, double2 b) {
 }
 __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 
+// Krylov vectors are stored as complex double (plain form) or complex
+// float (inner solves of the mixed form); arithmetic is always double.
+__device__ inline double2 ld2(const double2* p) { return *p; }
+__device__ inline double2 ld2(const float2* p) {
+  const float2 v = *p;
+  return make_double2(v.x, v.y);
+}
+__device__ inline void st2(double2* p, double2 v) { *p = v; }
+__device__ inline void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+
 __device__ inline double2 cconjmul(double2 a, double2 b) {  // conj(a) b
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
@@ -87,13 +97,23 @@ __global__ void __launch_bounds__(256) norm_kernel(const double2* __restrict__ u
 }
 
 // out[c] = in[c] / nrm[c] (zero if nrm[c] == 0)
-__global__ void scale_kernel(const double2* __restrict__ in, double2* __restrict__ out, int64_t n,
+template <typename TV>
+__global__ void scale_kernel(const double2* __restrict__ in, TV* __restrict__ out, int64_t n,
                              const double* __restrict__ nrm) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
   if (k >= n) return;
   const double s = nrm[c] > 0 ? 1.0 / nrm[c] : 0.0;
   const double2 a = in[c * n + k];
-  out[c * n + k] = make_double2(a.x * s, a.y * s);
+  st2(out + c * n + k, make_double2(a.x * s, a.y * s));
+}
+
+// out = in rounded to complex float
+__global__ void to_float_kernel(const double2* __restrict__ in, int64_t ldi, float2* __restrict__ out, int64_t ldo,
+                                int64_t rows, int64_t cols) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+  if (k >= cols || r >= rows) return;
+  const double2 v = in[r * ldi + k];
+  out[r * ldo + k] = make_float2((float)v.x, (float)v.y);
 }
 
 // r = b - r
@@ -132,13 +152,16 @@ struct GmresState {
   double* nrm;      // [c]
   double* bnorm;    // [c]
   double* res;      // [c] residual estimate / bnorm
+  double* tgt;      // [c] residual norm at which this cycle stops
   int32_t* active;  // [c]
   int32_t* kc;      // [c] Krylov dimension reached in this cycle
   int32_t* its;     // [c] iterations spent (all cycles)
 };
 
-// Start a cycle: g = beta e1, active = beta/bnorm > tol, kc = 0.
-__global__ void cycle_init_kernel(GmresState st, int64_t m, int64_t nrhs, double tol) {
+// Start a cycle: g = beta e1, active = beta/bnorm > tol, kc = 0; the cycle
+// stops at the residual norm max(tol bnorm, inner beta) (inner = 0: at tol;
+// inner > 0: the relative reduction asked of an inner solve).
+__global__ void cycle_init_kernel(GmresState st, int64_t m, int64_t nrhs, double tol, double inner) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nrhs) return;
   const double beta = st.nrm[c];
@@ -147,13 +170,15 @@ __global__ void cycle_init_kernel(GmresState st, int64_t m, int64_t nrhs, double
   const double r = st.bnorm[c] > 0 ? beta / st.bnorm[c] : 0.0;
   st.res[c] = r;
   st.active[c] = r > tol ? 1 : 0;
+  st.tgt[c] = fmax(tol * st.bnorm[c], inner * beta);
   st.kc[c] = 0;
 }
 
 // d1[i] = q_i^H q_j and d2[i] = q_i^H w for i <= j: one wavefront per
 // right-hand side and run of four basis vectors, four per block.
-__global__ void __launch_bounds__(256) dots2_kernel(const double2* __restrict__ V, int64_t vstride,
-                                                    const double2* __restrict__ w, int64_t n, int64_t nrhs, int64_t j,
+template <typename TV>
+__global__ void __launch_bounds__(256) dots2_kernel(const TV* __restrict__ V, int64_t vstride,
+                                                    const TV* __restrict__ w, int64_t n, int64_t nrhs, int64_t j,
                                                     GmresState st) {
   const int64_t id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -163,18 +188,18 @@ __global__ void __launch_bounds__(256) dots2_kernel(const double2* __restrict__ 
   if (!st.active[c]) return;
   const int64_t i0 = run * 4;
   const int cnt = (int)std::min<int64_t>(4, j + 1 - i0);
-  const double2* qj = V + j * vstride + c * n;
-  const double2* wc = w + c * n;
-  const double2* qi = V + i0 * vstride + c * n;
+  const TV* qj = V + j * vstride + c * n;
+  const TV* wc = w + c * n;
+  const TV* qi = V + i0 * vstride + c * n;
   double2 s1[4], s2[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) s1[t] = s2[t] = make_double2(0, 0);
   for (int64_t k = lane; k < n; k += 64) {
-    const double2 x = qj[k], y = wc[k];
+    const double2 x = ld2(qj + k), y = ld2(wc + k);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
       if (t < cnt) {
-        const double2 v = qi[t * vstride + k];
+        const double2 v = ld2(qi + t * vstride + k);
         s1[t] = cadd(s1[t], cconjmul(v, x));
         s2[t] = cadd(s2[t], cconjmul(v, y));
       }
@@ -200,7 +225,7 @@ __global__ void __launch_bounds__(256) dots2_kernel(const double2* __restrict__ 
 // follow an affine recurrence, so each lane composes the maps of a
 // contiguous run of rotations, a scan over the lanes gives every run its
 // incoming a_i, and the runs are then replayed in parallel.
-__global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs, double tol,
+__global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs,
                                                      int correct) {
   const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -287,11 +312,11 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
   const double2 gn = make_double2(-(ss.x * gj.x + ss.y * gj.y), -(ss.x * gj.y - ss.y * gj.x));
   st.g[(jc + 1) * nrhs + c] = gn;
   st.g[jc * nrhs + c] = cmul(cc, gj);
-  const double r = sqrt(gn.x * gn.x + gn.y * gn.y) / st.bnorm[c];
-  st.res[c] = r;
+  const double ra = sqrt(gn.x * gn.x + gn.y * gn.y);
+  st.res[c] = ra / st.bnorm[c];
   st.kc[c] = (int32_t)(jc + 1);
   st.its[c] += 1;
-  if (r <= tol || den == 0.0 || breakdown) st.active[c] = 0;
+  if (ra <= st.tgt[c] || den == 0.0 || breakdown) st.active[c] = 0;
 }
 
 // Column j of H and the update coefficients: p_l = sum_i H[l][i] a_i over
@@ -341,8 +366,9 @@ __global__ void __launch_bounds__(256) coef_kernel(GmresState st, int64_t m, int
 // consecutive rows of one right-hand side, wavefront v summing over the
 // basis vectors i = v mod 4; wavefront 0 combines the partial sums in a
 // fixed order and stores the row block's sum of |w|^2 in part.
-__global__ void __launch_bounds__(256) dcgs_update_kernel(double2* __restrict__ V, int64_t vstride,
-                                                          double2* __restrict__ w, int64_t n, int64_t nrhs, int64_t j,
+template <typename TV>
+__global__ void __launch_bounds__(256) dcgs_update_kernel(TV* __restrict__ V, int64_t vstride,
+                                                          TV* __restrict__ w, int64_t n, int64_t nrhs, int64_t j,
                                                           GmresState st, double* __restrict__ part) {
   const int64_t c = blockIdx.y;
   if (!st.active[c]) return;  // uniform over the block
@@ -351,10 +377,10 @@ __global__ void __launch_bounds__(256) dcgs_update_kernel(double2* __restrict__ 
   const bool in = k < n;
   const int64_t kk = in ? k : 0;
   double2 s1 = make_double2(0, 0), s2 = make_double2(0, 0);
-  const double2* base = V + c * n + kk;
+  const TV* base = V + c * n + kk;
 #pragma unroll 4
   for (int64_t i = wv; i < j; i += 4) {
-    const double2 v = base[i * vstride];
+    const double2 v = ld2(base + i * vstride);
     s1 = cadd(s1, cmul(st.d1[i * nrhs + c], v));
     s2 = cadd(s2, cmul(st.coef[i * nrhs + c], v));
   }
@@ -372,15 +398,15 @@ __global__ void __launch_bounds__(256) dcgs_update_kernel(double2* __restrict__ 
   const double ig = 1.0 / st.gam[c];
   double q2 = 0;
   if (in) {
-    double2* qj = V + j * vstride + c * n + k;
-    const double2 qo = *qj;
+    TV* qj = V + j * vstride + c * n + k;
+    const double2 qo = ld2(qj);
     const double2 qn = cscale(make_double2(qo.x - s1.x, qo.y - s1.y), ig);
-    *qj = qn;
-    const double2 wo = w[c * n + k];
+    st2(qj, qn);
+    const double2 wo = ld2(w + c * n + k);
     const double2 cj = st.coef[j * nrhs + c];
     const double2 t = cadd(s2, cmul(cj, qn));
     const double2 wn = make_double2(wo.x * ig - t.x, wo.y * ig - t.y);
-    w[c * n + k] = wn;
+    st2(w + c * n + k, wn);
     q2 = wn.x * wn.x + wn.y * wn.y;
   }
   q2 = wave_sum(q2);
@@ -389,7 +415,8 @@ __global__ void __launch_bounds__(256) dcgs_update_kernel(double2* __restrict__ 
 
 // nu = sqrt(sum of the np partial sums of |w|^2); H[j+1][j] = nu and
 // q_{j+1} = w / nu (zero if nu == 0); only active right-hand sides.
-__global__ void normalize_kernel(const double2* __restrict__ w, double2* __restrict__ out, int64_t n,
+template <typename TV>
+__global__ void normalize_kernel(const TV* __restrict__ w, TV* __restrict__ out, int64_t n,
                                  const double* __restrict__ part, int np, GmresState st, int64_t m, int64_t j,
                                  int64_t nrhs) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
@@ -400,7 +427,7 @@ __global__ void normalize_kernel(const double2* __restrict__ w, double2* __restr
   if (blockIdx.x == 0 && threadIdx.x == 0) st.H[(j * (m + 1) + j + 1) * nrhs + c] = make_double2(nu, 0);
   if (k >= n) return;
   const double sc = nu > 0 ? 1.0 / nu : 0.0;
-  out[c * n + k] = cscale(w[c * n + k], sc);
+  st2(out + c * n + k, cscale(ld2(w + c * n + k), sc));
 }
 
 // y = H^{-1} g over the first kc[c] rows (upper triangular), in place in g;
@@ -429,14 +456,15 @@ __global__ void __launch_bounds__(256) backsolve_kernel(GmresState st, int64_t m
 }
 
 // x[c] += sum_{i < kc[c]} y[i][c] V[i][c]
-__global__ void x_update_kernel(GmresState st, const double2* __restrict__ V, int64_t vstride, double2* __restrict__ x,
+template <typename TV>
+__global__ void x_update_kernel(GmresState st, const TV* __restrict__ V, int64_t vstride, double2* __restrict__ x,
                                 int64_t n, int64_t nrhs) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
   if (k >= n) return;
   const int64_t kc = st.kc[c];
   double2 acc = x[c * n + k];
   for (int64_t i = 0; i < kc; ++i) {
-    const double2 a = st.g[i * nrhs + c], v = V[i * vstride + c * n + k];
+    const double2 a = st.g[i * nrhs + c], v = ld2(V + i * vstride + c * n + k);
     acc.x += a.x * v.x - a.y * v.y;
     acc.y += a.x * v.y + a.y * v.x;
   }
@@ -580,6 +608,55 @@ static void apply_op(const double2* A, int64_t lda, int64_t n, int64_t nrhs, con
   zgemm_batched(d, s);
 }
 
+// One GMRES cycle from the normalised residual in V[0]: up to mres Arnoldi
+// iterations (the matrix-vector products by mv.launch(j)), the last column,
+// the triangular solve and x += Q y.  total counts the iterations of all
+// cycles against max_iter.
+template <typename TV, typename MV>
+static void run_cycle(const MV& mv, TV* V, TV* w, int64_t vstride, int64_t n, int64_t nrhs, int64_t mres,
+                      int64_t max_iter, int64_t& total, GmresState gs, double* part, int np, PinnedFlags& flags,
+                      double2* x, hipStream_t s) {
+  const dim3 g4((unsigned)((nrhs + 3) / 4));
+  const double vb = (double)sizeof(TV);
+  const int check_every = 4;
+  auto all_done = [&](const int32_t* a) { return std::none_of(a, a + nrhs, [](int32_t v) { return v != 0; }); };
+  int pending = 0;  // flag copies queued in this cycle
+  int64_t jlast = -1;
+  for (int64_t j = 0; j < mres && total < max_iter; ++j) {
+    TV* Vn = V + (j + 1) * vstride;
+    mv.launch((size_t)j, s);  // w = A q_j
+    {
+      // work: bytes of q_0..q_j and w for every right-hand side
+      TimedLaunch tl(T_GMRES_DOTS, s, vb * (double)(j + 2) * (double)nrhs * (double)n);
+      hipLaunchKernelGGL(dots2_kernel<TV>, dim3((unsigned)(((j + 4) / 4 * nrhs + 3) / 4)), dim3(256), 0, s, V, vstride,
+                         w, n, nrhs, j, gs);
+    }
+    hipLaunchKernelGGL(column_kernel, g4, dim3(256), 0, s, gs, mres, j, nrhs, 1);
+    hipLaunchKernelGGL(coef_kernel, dim3((unsigned)(j + 1), (unsigned)((nrhs + 63) / 64)), dim3(256), 0, s, gs, mres, j,
+                       nrhs);
+    {
+      // work: bytes of q_0..q_{j-1} read, q_j and w read and written
+      TimedLaunch tl(T_GMRES_UPDATE, s, vb * (double)(j + 4) * (double)nrhs * (double)n);
+      hipLaunchKernelGGL(dcgs_update_kernel<TV>, dim3((unsigned)np, (unsigned)nrhs), dim3(256), 0, s, V, vstride, w, n,
+                         nrhs, j, gs, part);
+    }
+    hipLaunchKernelGGL(normalize_kernel<TV>, grid2(n, nrhs), dim3(256), 0, s, w, Vn, n, part, np, gs, mres, j, nrhs);
+    CBFM_HIP(hipGetLastError());
+    ++total;
+    jlast = j;
+    if ((j + 1) % check_every == 0) {
+      if (pending > 0 && all_done(flags.wait())) break;
+      flags.post(gs.active, s);
+      ++pending;
+    }
+  }
+  // the last column of the cycle, taken without the delayed correction
+  if (jlast >= 0) hipLaunchKernelGGL(column_kernel, g4, dim3(256), 0, s, gs, mres, jlast + 1, nrhs, 0);
+  hipLaunchKernelGGL(backsolve_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, mres, nrhs);
+  hipLaunchKernelGGL(x_update_kernel<TV>, grid2(n, nrhs), dim3(256), 0, s, gs, V, vstride, x, n, nrhs);
+  CBFM_HIP(hipGetLastError());
+}
+
 }  // namespace cbfm
 
 using namespace cbfm;
@@ -636,20 +713,41 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
       Aop = Ap.as<double2>();
       lda = n;
     }
-    // ---- GMRES state
-    Scratch V((mres + 1) * nrhs * n * sizeof(double2), s);
-    Scratch x(nrhs * n * sizeof(double2), s), u(nrhs * n * sizeof(double2), s);
+    // ---- GMRES state.  The plain form keeps the Krylov basis in double;
+    // the mixed form (inner_fp32) keeps it and the operator in float and
+    // refines: every cycle starts from the residual b - A x formed in
+    // double with the double operator, and stops once it has reduced that
+    // residual by inner_tol (or reached tol).
+    const bool f32 = prm->inner_fp32 != 0;
+    const double inner = f32 ? (prm->inner_tol > 0 ? prm->inner_tol : 1e-6) : 0.0;
+    const size_t vsz = f32 ? sizeof(float2) : sizeof(double2);
+    Scratch V((mres + 1) * nrhs * n * vsz, s);
+    Scratch x(nrhs * n * sizeof(double2), s), u(nrhs * n * vsz, s), r64(f32 ? nrhs * n * sizeof(double2) : 0, s);
+    Scratch A32(f32 ? n * n * sizeof(float2) : 0, s);
     const int np = (int)((n + 63) / 64);  // partial norm sums per vector (64-row blocks)
     const size_t hbytes = (size_t)nrhs * (mres + 1) * mres * sizeof(double2), cbytes = (size_t)nrhs * (mres + 1) * sizeof(double2);
     Scratch Rs(hbytes, s), Hs(hbytes, s), csb(nrhs * mres * sizeof(double2), s), snb(nrhs * mres * sizeof(double2), s),
         gb(cbytes, s), d1b(cbytes, s), d2b(cbytes, s), coefb(cbytes, s), abb(nrhs * sizeof(double2), s),
         dbl(5 * nrhs * sizeof(double), s), ints(3 * nrhs * sizeof(int32_t), s), part(nrhs * np * sizeof(double), s);
-    GmresState gs{Rs.as<double2>(),          Hs.as<double2>(),          csb.as<double2>(),          snb.as<double2>(),
-                  gb.as<double2>(),          d1b.as<double2>(),         d2b.as<double2>(),          coefb.as<double2>(),
-                  abb.as<double2>(),         dbl.as<double>(),          dbl.as<double>() + nrhs,    dbl.as<double>() + 2 * nrhs,
-                  dbl.as<double>() + 3 * nrhs, ints.as<int32_t>(),      ints.as<int32_t>() + nrhs,  ints.as<int32_t>() + 2 * nrhs};
+    GmresState gs{Rs.as<double2>(),
+                  Hs.as<double2>(),
+                  csb.as<double2>(),
+                  snb.as<double2>(),
+                  gb.as<double2>(),
+                  d1b.as<double2>(),
+                  d2b.as<double2>(),
+                  coefb.as<double2>(),
+                  abb.as<double2>(),
+                  dbl.as<double>(),
+                  dbl.as<double>() + nrhs,
+                  dbl.as<double>() + 2 * nrhs,
+                  dbl.as<double>() + 3 * nrhs,
+                  dbl.as<double>() + 4 * nrhs,
+                  ints.as<int32_t>(),
+                  ints.as<int32_t>() + nrhs,
+                  ints.as<int32_t>() + 2 * nrhs};
     const int64_t vstride = nrhs * n;
-    const dim3 g1((unsigned)((nrhs + 63) / 64)), b1(64), g4((unsigned)((nrhs + 3) / 4));
+    const dim3 g1((unsigned)((nrhs + 63) / 64)), b1(64);
     CBFM_HIP(hipMemsetAsync(x.p, 0, nrhs * n * sizeof(double2), s));
     CBFM_HIP(hipMemsetAsync(gs.its, 0, nrhs * sizeof(int32_t), s));
     hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, b.as<double2>(), n, gs.bnorm, nullptr);
@@ -661,22 +759,34 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
     // read one check later, so the host never waits for the device inside a
     // cycle; iterations queued after the last right-hand side converged do
     // nothing (every kernel skips inactive right-hand sides).
-    const int check_every = 4;
     PinnedFlags flags(nrhs);
     auto all_done = [&](const int32_t* a) {
       return std::none_of(a, a + nrhs, [](int32_t v) { return v != 0; });
     };
-    // u = A v_j for every Krylov index j, descriptors uploaded once
-    std::vector<std::vector<GemmDesc>> mv(mres);
-    for (int64_t j = 0; j < mres; ++j) {
-      GemmDesc d = gemm(Aop, lda, OP_N, V.as<double2>() + j * vstride, n, OP_T, u.as<double2>(), n, n, nrhs, n);
-      d.transC = 1;
-      mv[j].push_back(d);
+    // w = A q_j for every Krylov index j, descriptors uploaded once
+    std::vector<std::vector<GemmDesc>> mv(f32 ? 0 : mres);
+    std::vector<std::vector<GemmDescX>> mvx(f32 ? mres : 0);
+    if (f32) {
+      hipLaunchKernelGGL(to_float_kernel, grid2(n, n), dim3(256), 0, s, Aop, lda, A32.as<float2>(), n, n, n);
+      CBFM_HIP(hipGetLastError());
+      for (int64_t j = 0; j < mres; ++j) {
+        GemmDescX d = gemmx(A32.as<float2>(), 0, n, OP_N, V.as<float2>() + j * vstride, 0, n, OP_T, u.as<float2>(), 0, n,
+                            n, nrhs, n);
+        d.transC = 1;
+        mvx[j].push_back(d);
+      }
+    } else {
+      for (int64_t j = 0; j < mres; ++j) {
+        GemmDesc d = gemm(Aop, lda, OP_N, V.as<double2>() + j * vstride, n, OP_T, u.as<double2>(), n, n, nrhs, n);
+        d.transC = 1;
+        mv[j].push_back(d);
+      }
     }
     const GemmPlan matvec(mv, s);
+    const XGemmPlan matvec32(mvx, XG_FP32, s);
     for (;;) {
-      // r = b - A x  (x = 0 on the first cycle)
-      double2* r = u.as<double2>();
+      // r = b - A x in double  (x = 0 on the first cycle)
+      double2* r = f32 ? r64.as<double2>() : u.as<double2>();
       if (total == 0) {
         CBFM_HIP(hipMemcpyAsync(r, b.p, nrhs * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
       } else {
@@ -685,53 +795,24 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
                            nrhs * n);
       }
       hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, r, n, gs.nrm, nullptr);
-      hipLaunchKernelGGL(cycle_init_kernel, g1, b1, 0, s, gs, mres, nrhs, tol);
-      hipLaunchKernelGGL(scale_kernel, grid2(n, nrhs), dim3(256), 0, s, r, V.as<double2>(), n, gs.nrm);
+      hipLaunchKernelGGL(cycle_init_kernel, g1, b1, 0, s, gs, mres, nrhs, tol, inner);
+      if (f32)
+        hipLaunchKernelGGL(scale_kernel<float2>, grid2(n, nrhs), dim3(256), 0, s, r, V.as<float2>(), n, gs.nrm);
+      else
+        hipLaunchKernelGGL(scale_kernel<double2>, grid2(n, nrhs), dim3(256), 0, s, r, V.as<double2>(), n, gs.nrm);
       if (all_done(flags.sync_read(gs.active, s)) || total >= prm->max_iter) break;
-      int pending = 0;  // flag copies queued in this cycle
-      int64_t jlast = -1;
-      for (int64_t j = 0; j < mres && total < prm->max_iter; ++j) {
-        double2* Vn = V.as<double2>() + (j + 1) * vstride;
-        matvec.launch((size_t)j, s);  // u = A q_j
-        {
-          // work: bytes of q_0..q_j and w for every right-hand side
-          TimedLaunch tl(T_GMRES_DOTS, s, 16.0 * (double)(j + 2) * (double)nrhs * (double)n);
-          hipLaunchKernelGGL(dots2_kernel, dim3((unsigned)(((j + 4) / 4 * nrhs + 3) / 4)), dim3(256), 0, s,
-                             V.as<double2>(), vstride, u.as<double2>(), n, nrhs, j, gs);
-        }
-        hipLaunchKernelGGL(column_kernel, g4, dim3(256), 0, s, gs, mres, j, nrhs, tol, 1);
-        hipLaunchKernelGGL(coef_kernel, dim3((unsigned)(j + 1), (unsigned)((nrhs + 63) / 64)), dim3(256), 0, s, gs, mres,
-                           j, nrhs);
-        {
-          // work: bytes of q_0..q_{j-1} read, q_j and w read and written
-          TimedLaunch tl(T_GMRES_UPDATE, s, 16.0 * (double)(j + 4) * (double)nrhs * (double)n);
-          hipLaunchKernelGGL(dcgs_update_kernel, dim3((unsigned)np, (unsigned)nrhs), dim3(256), 0, s,
-                             V.as<double2>(), vstride, u.as<double2>(), n, nrhs, j, gs, part.as<double>());
-        }
-        hipLaunchKernelGGL(normalize_kernel, grid2(n, nrhs), dim3(256), 0, s, u.as<double2>(), Vn, n, part.as<double>(),
-                           np, gs, mres, j, nrhs);
-        CBFM_HIP(hipGetLastError());
-        ++total;
-        jlast = j;
-        if ((j + 1) % check_every == 0) {
-          if (pending > 0 && all_done(flags.wait())) break;
-          flags.post(gs.active, s);
-          ++pending;
-        }
-      }
-      // the last column of the cycle, taken without the delayed correction
-      if (jlast >= 0)
-        hipLaunchKernelGGL(column_kernel, g4, dim3(256), 0, s, gs, mres, jlast + 1, nrhs, tol, 0);
-      hipLaunchKernelGGL(backsolve_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, mres, nrhs);
-      hipLaunchKernelGGL(x_update_kernel, grid2(n, nrhs), dim3(256), 0, s, gs, V.as<double2>(), vstride, x.as<double2>(),
-                         n, nrhs);
-      CBFM_HIP(hipGetLastError());
+      if (f32)
+        run_cycle(matvec32, V.as<float2>(), u.as<float2>(), vstride, n, nrhs, mres, prm->max_iter, total, gs,
+                  part.as<double>(), np, flags, x.as<double2>(), s);
+      else
+        run_cycle(matvec, V.as<double2>(), u.as<double2>(), vstride, n, nrhs, mres, prm->max_iter, total, gs,
+                  part.as<double>(), np, flags, x.as<double2>(), s);
       if (total >= prm->max_iter) break;
     }
     CBFM_HIP(hipMemcpyAsync(its.data(), gs.its, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     // true relative residual of the preconditioned system
     {
-      double2* r = u.as<double2>();
+      double2* r = f32 ? r64.as<double2>() : u.as<double2>();
       apply_op(Aop, lda, n, nrhs, x.as<double2>(), r, s);
       hipLaunchKernelGGL(sub_from_kernel, dim3((unsigned)((nrhs * n + 255) / 256)), dim3(256), 0, s, b.as<double2>(), r,
                          nrhs * n);

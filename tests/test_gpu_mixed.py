@@ -1,0 +1,94 @@
+"""The precision form through the C ABI: FP32 fill with FP32 or BF16
+matrix-core projection (FP32 accumulation), and GMRES with float Krylov
+cycles refined against the double residual, checked against the FP64
+oracle (same imported CBFs)."""
+import numpy as np
+import pytest
+
+from test_gpu_cbf_solve import _gpu_handles, _oracle_cbf, _rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.mark.parametrize("name", ["c1", "cyl_small"])
+def test_mixed_projection_error(torch_cuda, name):
+    """Z_r from the float fill and FP32 matrix cores stays within 1e-4 of the
+    FP64 oracle, and so does split BF16; plain BF16 inputs (8-bit
+    significands) within 2e-2."""
+    O = _oracle_cbf(name)
+    w = O["P"]["w"]
+    cbfm, mesh, med, cbf = _gpu_handles(w, O)
+    n = cbf.n_cbf
+    print(f"mixed project {w.name} N_CBF={n}", flush=True)
+    Z = torch_cuda.zeros((n, n), dtype=torch_cuda.complex128, device="cuda")
+    cbfm.project(mesh, med, cbf, Z, cbfm.MIXED_FP32)
+    e32 = _rel(Z.cpu().numpy(), O["Zr"])
+    cbfm.project(mesh, med, cbf, Z, cbfm.MIXED_BF16)
+    e16 = _rel(Z.cpu().numpy(), O["Zr"])
+    cbfm.project(mesh, med, cbf, Z, cbfm.MIXED_BF16X3)
+    e3 = _rel(Z.cpu().numpy(), O["Zr"])
+    print(f"Z_r rel err: fp32 {e32:.2e}  bf16 {e16:.2e}  split bf16 {e3:.2e}")
+    assert e32 < 1e-4 and e3 < 1e-4
+    assert e16 < 2e-2
+
+
+def test_refined_solve_matches_fp64(torch_cuda):
+    """Float Krylov cycles refined against the double residual reach the
+    double solution of the same system (tol 1e-11)."""
+    from oracle import excitation
+    O = _oracle_cbf("cyl_small")
+    P = O["P"]
+    w, m = P["w"], P["m"]
+    cbfm, mesh, med, cbf = _gpu_handles(w, O)
+    n = cbf.n_cbf
+    Zr = torch_cuda.zeros((n, n), dtype=torch_cuda.complex128, device="cuda")
+    cbfm.project(mesh, med, cbf, Zr, cbfm.FP64)
+    jt = torch_cuda.zeros((len(w.inc), 2 * m.ne), dtype=torch_cuda.complex128, device="cuda")
+    print("refined solve", flush=True)
+    out = cbfm.solve(mesh, med, cbf, Zr, w.inc, tol=1e-11, max_iter=4 * n, restart=n, j_out=jt, inner_fp32=True)
+    print(out)
+    assert out["status"] == "OK" and np.all(out["relres"] < 1.1e-10)
+    vr = O["CJM"].conj().T @ excitation.rhs(m, w.inc, w.k0, w.eta0)
+    jref = O["CMJ"] @ np.linalg.solve(O["Zr"], vr)
+    err = _rel(jt.cpu().numpy().T, jref)
+    print("currents rel err", err)
+    assert err < 1e-8
+    # a loose inner tolerance only adds cycles
+    out2 = cbfm.solve(mesh, med, cbf, Zr, w.inc, tol=1e-11, max_iter=4 * n, restart=n, j_out=jt, inner_fp32=True,
+                      inner_tol=1e-2)
+    assert out2["status"] == "OK" and _rel(jt.cpu().numpy().T, jref) < 1e-8
+
+
+@pytest.mark.parametrize("name", ["c1", "cyl_small"])
+def test_mixed_end_to_end_rcs(torch_cuda, name):
+    """Float fill + FP32 matrix-core projection + refined float GMRES: the
+    monostatic RCS within 1e-4 of the FP64 oracle, and with split-BF16
+    projection too; with plain BF16 inputs the error is reported and
+    bounded by 5e-2."""
+    from oracle import excitation
+    O = _oracle_cbf(name)
+    P = O["P"]
+    w, m = P["w"], P["m"]
+    cbfm, mesh, med, cbf = _gpu_handles(w, O)
+    n = cbf.n_cbf
+    vr = O["CJM"].conj().T @ excitation.rhs(m, w.inc, w.k0, w.eta0)
+    jref = O["CMJ"] @ np.linalg.solve(O["Zr"], vr)
+    rcs_ref = excitation.monostatic_rcs(m, jref, w.inc, w.k0, w.eta0)
+    Z = torch_cuda.zeros((n, n), dtype=torch_cuda.complex128, device="cuda")
+    errs = {}
+    for prec in (cbfm.MIXED_FP32, cbfm.MIXED_BF16, cbfm.MIXED_BF16X3):
+        cbfm.project(mesh, med, cbf, Z, prec)
+        out = cbfm.solve(mesh, med, cbf, Z, w.inc, tol=1e-8, max_iter=4 * n, restart=n, inner_fp32=True)
+        assert out["status"] == "OK"
+        errs[prec] = np.max(np.abs(out["rcs"] - rcs_ref) / rcs_ref)
+    print(f"{w.name}: monostatic RCS rel err fp32 {errs[cbfm.MIXED_FP32]:.2e} bf16 {errs[cbfm.MIXED_BF16]:.2e} "
+          f"split bf16 {errs[cbfm.MIXED_BF16X3]:.2e}")
+    assert errs[cbfm.MIXED_FP32] < 1e-4 and errs[cbfm.MIXED_BF16X3] < 1e-4
+    assert errs[cbfm.MIXED_BF16] < 5e-2
