@@ -277,6 +277,8 @@ typedef struct {
                       /* b - A x formed in double (iterative refinement)   */
                       /* and stopped once it has reduced it by inner_tol   */
   double inner_tol;   /* mixed form only; 0 -> 1e-6                         */
+  int32_t use_graph;  /* 1: Arnoldi iterations in chunks of four captured   */
+                      /* once per cycle into a HIP graph and replayed      */
 } cbfm_solver_params;
 
 cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, const void* Zr_dev,

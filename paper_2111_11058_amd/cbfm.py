@@ -46,7 +46,8 @@ class CbfParams(C.Structure):
 
 class SolverParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32),
-                ("use_cmp", C.c_int32), ("inner_fp32", C.c_int32), ("inner_tol", C.c_double)]
+                ("use_cmp", C.c_int32), ("inner_fp32", C.c_int32), ("inner_tol", C.c_double),
+                ("use_graph", C.c_int32)]
 
 
 _lib = None
@@ -322,10 +323,11 @@ def cmp_apply(cbf: CBF, y, x, stream=None):
 
 def solve(mesh: Mesh, medium: Medium, cbf: CBF, Zr, inc, tol=1e-6, max_iter=1000, restart=100,
           use_cmp=True, j_out=None, dirs=None, ldz=None, stream=None, raise_noconv=False, inner_fp32=False,
-          inner_tol=0.0):
+          inner_tol=0.0, use_graph=False):
     """cbfm_solve.  Returns dict(iters, relres, rcs, status).  inner_fp32
     selects the mixed form (float Krylov cycles refined against the double
-    residual, each cycle reducing it by inner_tol)."""
+    residual, each cycle reducing it by inner_tol); use_graph replays the
+    Arnoldi iterations from a captured HIP graph."""
     import torch
     inc, pi = _host(inc, np.float64)
     inc = inc.reshape(-1, 6)
@@ -345,7 +347,7 @@ def solve(mesh: Mesh, medium: Medium, cbf: CBF, Zr, inc, tol=1e-6, max_iter=1000
         pd, nd = None, 0
         rcs = np.zeros(nrhs)
     prm = SolverParams(float(tol), int(max_iter), int(restart), int(bool(use_cmp)), int(bool(inner_fp32)),
-                       float(inner_tol))
+                       float(inner_tol), int(bool(use_graph)))
     code = lib().cbfm_solve(mesh.handle, C.byref(medium), cbf.handle, pz, ldz, pi, nrhs, C.byref(prm), pj,
                             iters.ctypes.data_as(C.c_void_p), relres.ctypes.data_as(C.c_void_p), pd, nd,
                             rcs.ctypes.data_as(C.c_void_p), _stream(stream))

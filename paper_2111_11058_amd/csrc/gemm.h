@@ -98,6 +98,8 @@ class XGemmPlan {
  public:
   XGemmPlan(const std::vector<std::vector<GemmDescX>>& groups, int mode, hipStream_t s);
   void launch(size_t g, hipStream_t s) const;
+  // device copy of group g's descriptors (kernels may repoint operands)
+  GemmDescX* desc(size_t g) const { return dev_.as<GemmDescX>() + first_[g]; }
 
  private:
   int mode_;
@@ -117,6 +119,8 @@ class GemmPlan {
  public:
   GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t s, bool tune = true);
   void launch(size_t g, hipStream_t s) const;
+  // device copy of group g's descriptors (kernels may repoint operands)
+  GemmDesc* desc(size_t g) const { return dev_.as<GemmDesc>() + first_[g]; }
 
  private:
   bool tune_;

@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <type_traits>
 
 #include "cbf.h"
 #include "gemm.h"
@@ -179,7 +181,8 @@ __global__ void cycle_init_kernel(GmresState st, int64_t m, int64_t nrhs, double
 template <typename TV>
 __global__ void __launch_bounds__(256) dots2_kernel(const TV* __restrict__ V, int64_t vstride,
                                                     const TV* __restrict__ w, int64_t n, int64_t nrhs, int64_t j,
-                                                    GmresState st) {
+                                                    GmresState st, const int64_t* __restrict__ jp) {
+  if (jp) j = *jp;  // iteration index from the device (graph replays)
   const int64_t id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t runs = (j + 4) / 4;
@@ -226,7 +229,8 @@ __global__ void __launch_bounds__(256) dots2_kernel(const TV* __restrict__ V, in
 // contiguous run of rotations, a scan over the lanes gives every run its
 // incoming a_i, and the runs are then replayed in parallel.
 __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs,
-                                                     int correct) {
+                                                     int correct, const int64_t* __restrict__ jp) {
+  if (jp) j = *jp;
   const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= nrhs || !st.active[c]) return;  // uniform over the wavefront
@@ -324,8 +328,11 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
 // as above.  One block per row l; lane = right-hand side (64 per block
 // row), the four wavefronts take every fourth column and are summed through
 // LDS in a fixed order.
-__global__ void __launch_bounds__(256) coef_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs) {
+__global__ void __launch_bounds__(256) coef_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs,
+                                                   const int64_t* __restrict__ jp) {
+  if (jp) j = *jp;
   const int64_t l = blockIdx.x;
+  if (l > j) return;  // graph replays launch the grid of the longest column
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t c = (int64_t)blockIdx.y * 64 + lane;
   const bool on = c < nrhs && st.active[c];
@@ -369,7 +376,9 @@ __global__ void __launch_bounds__(256) coef_kernel(GmresState st, int64_t m, int
 template <typename TV>
 __global__ void __launch_bounds__(256) dcgs_update_kernel(TV* __restrict__ V, int64_t vstride,
                                                           TV* __restrict__ w, int64_t n, int64_t nrhs, int64_t j,
-                                                          GmresState st, double* __restrict__ part) {
+                                                          GmresState st, double* __restrict__ part,
+                                                          const int64_t* __restrict__ jp) {
+  if (jp) j = *jp;
   const int64_t c = blockIdx.y;
   if (!st.active[c]) return;  // uniform over the block
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -416,9 +425,11 @@ __global__ void __launch_bounds__(256) dcgs_update_kernel(TV* __restrict__ V, in
 // nu = sqrt(sum of the np partial sums of |w|^2); H[j+1][j] = nu and
 // q_{j+1} = w / nu (zero if nu == 0); only active right-hand sides.
 template <typename TV>
-__global__ void normalize_kernel(const TV* __restrict__ w, TV* __restrict__ out, int64_t n,
+__global__ void normalize_kernel(const TV* __restrict__ w, TV* __restrict__ V, int64_t vstride, int64_t n,
                                  const double* __restrict__ part, int np, GmresState st, int64_t m, int64_t j,
-                                 int64_t nrhs) {
+                                 int64_t nrhs, const int64_t* __restrict__ jp) {
+  if (jp) j = *jp;
+  TV* out = V + (j + 1) * vstride;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
   if (!st.active[c]) return;
   double q = 0;
@@ -428,6 +439,16 @@ __global__ void normalize_kernel(const TV* __restrict__ w, TV* __restrict__ out,
   if (k >= n) return;
   const double sc = nu > 0 ? 1.0 / nu : 0.0;
   st2(out + c * n + k, cscale(ld2(w + c * n + k), sc));
+}
+
+// Device-side iteration counter of graph replays, and the matrix-vector
+// product's operand q_j taken from it.
+__global__ void counter_kernel(int64_t* __restrict__ jp, int64_t value, int add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *jp = add ? *jp + value : value;
+}
+template <typename D, typename TV>
+__global__ void point_matvec_kernel(D* __restrict__ desc, const TV* V, int64_t vstride, const int64_t* __restrict__ jp) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) desc->B = V + (*jp) * vstride;
 }
 
 // y = H^{-1} g over the first kc[c] rows (upper triangular), in place in g;
@@ -611,47 +632,106 @@ static void apply_op(const double2* A, int64_t lda, int64_t n, int64_t nrhs, con
 // One GMRES cycle from the normalised residual in V[0]: up to mres Arnoldi
 // iterations (the matrix-vector products by mv.launch(j)), the last column,
 // the triangular solve and x += Q y.  total counts the iterations of all
-// cycles against max_iter.
+// cycles against max_iter.  With a graph plan (dyn, its descriptor dyn_desc
+// and the device counter jdev), chunks of four iterations are captured once
+// into a HIP graph whose kernels read the iteration index from jdev, and
+// the graph is replayed; the remaining iterations run as plain launches.
 template <typename TV, typename MV>
-static void run_cycle(const MV& mv, TV* V, TV* w, int64_t vstride, int64_t n, int64_t nrhs, int64_t mres,
-                      int64_t max_iter, int64_t& total, GmresState gs, double* part, int np, PinnedFlags& flags,
-                      double2* x, hipStream_t s) {
+static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev, TV* V, TV* w, int64_t vstride,
+                      int64_t n, int64_t nrhs, int64_t mres, int64_t max_iter, int64_t& total, GmresState gs,
+                      double* part, int np, PinnedFlags& flags, double2* x, hipStream_t s) {
   const dim3 g4((unsigned)((nrhs + 3) / 4));
   const double vb = (double)sizeof(TV);
   const int check_every = 4;
   auto all_done = [&](const int32_t* a) { return std::none_of(a, a + nrhs, [](int32_t v) { return v != 0; }); };
-  int pending = 0;  // flag copies queued in this cycle
-  int64_t jlast = -1;
-  for (int64_t j = 0; j < mres && total < max_iter; ++j) {
-    TV* Vn = V + (j + 1) * vstride;
-    mv.launch((size_t)j, s);  // w = A q_j
+  // enqueue iteration j (jp == nullptr) or the iteration *jp (graph capture)
+  auto iteration = [&](int64_t j, const int64_t* jp, hipStream_t q) {
+    const int64_t jg = jp ? mres - 1 : j;  // grids cover the longest column
+    if (jp) {
+      using D = typename std::conditional<std::is_same<TV, double2>::value, GemmDesc, GemmDescX>::type;
+      hipLaunchKernelGGL((point_matvec_kernel<D, TV>), dim3(1), dim3(64), 0, q, static_cast<D*>(dyn_desc), V, vstride,
+                         jp);
+      dyn->launch(0, q);
+    } else {
+      mv.launch((size_t)j, q);  // w = A q_j
+    }
     {
       // work: bytes of q_0..q_j and w for every right-hand side
-      TimedLaunch tl(T_GMRES_DOTS, s, vb * (double)(j + 2) * (double)nrhs * (double)n);
-      hipLaunchKernelGGL(dots2_kernel<TV>, dim3((unsigned)(((j + 4) / 4 * nrhs + 3) / 4)), dim3(256), 0, s, V, vstride,
-                         w, n, nrhs, j, gs);
+      TimedLaunch tl(T_GMRES_DOTS, q, vb * (double)(j + 2) * (double)nrhs * (double)n);
+      hipLaunchKernelGGL(dots2_kernel<TV>, dim3((unsigned)(((jg + 4) / 4 * nrhs + 3) / 4)), dim3(256), 0, q, V,
+                         vstride, w, n, nrhs, j, gs, jp);
     }
-    hipLaunchKernelGGL(column_kernel, g4, dim3(256), 0, s, gs, mres, j, nrhs, 1);
-    hipLaunchKernelGGL(coef_kernel, dim3((unsigned)(j + 1), (unsigned)((nrhs + 63) / 64)), dim3(256), 0, s, gs, mres, j,
-                       nrhs);
+    hipLaunchKernelGGL(column_kernel, g4, dim3(256), 0, q, gs, mres, j, nrhs, 1, jp);
+    hipLaunchKernelGGL(coef_kernel, dim3((unsigned)(jg + 1), (unsigned)((nrhs + 63) / 64)), dim3(256), 0, q, gs, mres,
+                       j, nrhs, jp);
     {
       // work: bytes of q_0..q_{j-1} read, q_j and w read and written
-      TimedLaunch tl(T_GMRES_UPDATE, s, vb * (double)(j + 4) * (double)nrhs * (double)n);
-      hipLaunchKernelGGL(dcgs_update_kernel<TV>, dim3((unsigned)np, (unsigned)nrhs), dim3(256), 0, s, V, vstride, w, n,
-                         nrhs, j, gs, part);
+      TimedLaunch tl(T_GMRES_UPDATE, q, vb * (double)(j + 4) * (double)nrhs * (double)n);
+      hipLaunchKernelGGL(dcgs_update_kernel<TV>, dim3((unsigned)np, (unsigned)nrhs), dim3(256), 0, q, V, vstride, w, n,
+                         nrhs, j, gs, part, jp);
     }
-    hipLaunchKernelGGL(normalize_kernel<TV>, grid2(n, nrhs), dim3(256), 0, s, w, Vn, n, part, np, gs, mres, j, nrhs);
+    hipLaunchKernelGGL(normalize_kernel<TV>, grid2(n, nrhs), dim3(256), 0, q, w, V, vstride, n, part, np, gs, mres, j,
+                       nrhs, jp);
+    if (jp) hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, q, jdev, (int64_t)1, 1);
     CBFM_HIP(hipGetLastError());
+  };
+  int pending = 0;  // flag copies queued in this cycle
+  int64_t j = 0;
+  bool done = false;
+  auto check = [&]() {
+    if (pending > 0 && all_done(flags.wait())) return true;
+    flags.post(gs.active, s);
+    ++pending;
+    return false;
+  };
+  if (dyn && mres >= check_every && max_iter - total >= check_every) {
+    hipStream_t cs;
+    CBFM_HIP(hipStreamCreate(&cs));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      try {
+        for (int q = 0; q < check_every; ++q) iteration(0, jdev, cs);
+      } catch (...) {
+        (void)hipStreamEndCapture(cs, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cs);
+        throw;
+      }
+      e = hipStreamEndCapture(cs, &graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    CBFM_HIP(e);
+    hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, s, jdev, (int64_t)0, 0);
+    try {
+      while (j + check_every <= mres && total + check_every <= max_iter) {
+        CBFM_HIP(hipGraphLaunch(exec, s));
+        j += check_every;
+        total += check_every;
+        if (check()) {
+          done = true;
+          break;
+        }
+      }
+    } catch (...) {
+      (void)hipGraphExecDestroy(exec);
+      throw;
+    }
+    CBFM_HIP(hipGraphExecDestroy(exec));
+  }
+  for (; !done && j < mres && total < max_iter; ++j) {
+    iteration(j, nullptr, s);
     ++total;
-    jlast = j;
-    if ((j + 1) % check_every == 0) {
-      if (pending > 0 && all_done(flags.wait())) break;
-      flags.post(gs.active, s);
-      ++pending;
+    if ((j + 1) % check_every == 0 && check()) {
+      ++j;
+      break;
     }
   }
   // the last column of the cycle, taken without the delayed correction
-  if (jlast >= 0) hipLaunchKernelGGL(column_kernel, g4, dim3(256), 0, s, gs, mres, jlast + 1, nrhs, 0);
+  if (j > 0) hipLaunchKernelGGL(column_kernel, g4, dim3(256), 0, s, gs, mres, j, nrhs, 0, nullptr);
   hipLaunchKernelGGL(backsolve_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, mres, nrhs);
   hipLaunchKernelGGL(x_update_kernel<TV>, grid2(n, nrhs), dim3(256), 0, s, gs, V, vstride, x, n, nrhs);
   CBFM_HIP(hipGetLastError());
@@ -784,6 +864,13 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
     }
     const GemmPlan matvec(mv, s);
     const XGemmPlan matvec32(mvx, XG_FP32, s);
+    // graph replays: one matrix-vector descriptor repointed on the device
+    const bool graph = prm->use_graph != 0 && mres > 0;
+    std::unique_ptr<GemmPlan> dyn;
+    std::unique_ptr<XGemmPlan> dyn32;
+    Scratch jdev(graph ? sizeof(int64_t) : 0, s);
+    if (graph && f32) dyn32.reset(new XGemmPlan({mvx[0]}, XG_FP32, s));
+    if (graph && !f32) dyn.reset(new GemmPlan({mv[0]}, s, false));
     for (;;) {
       // r = b - A x in double  (x = 0 on the first cycle)
       double2* r = f32 ? r64.as<double2>() : u.as<double2>();
@@ -802,11 +889,13 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
         hipLaunchKernelGGL(scale_kernel<double2>, grid2(n, nrhs), dim3(256), 0, s, r, V.as<double2>(), n, gs.nrm);
       if (all_done(flags.sync_read(gs.active, s)) || total >= prm->max_iter) break;
       if (f32)
-        run_cycle(matvec32, V.as<float2>(), u.as<float2>(), vstride, n, nrhs, mres, prm->max_iter, total, gs,
-                  part.as<double>(), np, flags, x.as<double2>(), s);
+        run_cycle(matvec32, dyn32.get(), dyn32 ? dyn32->desc(0) : nullptr, jdev.as<int64_t>(), V.as<float2>(),
+                  u.as<float2>(), vstride, n, nrhs, mres, prm->max_iter, total, gs, part.as<double>(), np, flags,
+                  x.as<double2>(), s);
       else
-        run_cycle(matvec, V.as<double2>(), u.as<double2>(), vstride, n, nrhs, mres, prm->max_iter, total, gs,
-                  part.as<double>(), np, flags, x.as<double2>(), s);
+        run_cycle(matvec, dyn.get(), dyn ? dyn->desc(0) : nullptr, jdev.as<int64_t>(), V.as<double2>(),
+                  u.as<double2>(), vstride, n, nrhs, mres, prm->max_iter, total, gs, part.as<double>(), np, flags,
+                  x.as<double2>(), s);
       if (total >= prm->max_iter) break;
     }
     CBFM_HIP(hipMemcpyAsync(its.data(), gs.its, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));

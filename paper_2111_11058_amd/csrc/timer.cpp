@@ -39,6 +39,8 @@ void drain(Rec& r) {
 TimedLaunch::TimedLaunch(int id_, hipStream_t s_, double work_) : id(id_), s(s_), work(work_) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!(g_mask >> id & 1u)) return;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone) return;  // no events in graphs
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     e0 = e1 = nullptr;
     return;

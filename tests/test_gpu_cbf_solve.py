@@ -184,3 +184,34 @@ def test_single_sphere_worked_example_end_to_end(torch_cuda):
     print("restarted", d)
     assert d["status"] == "OK"
     assert _rel(jt.cpu().numpy().T, jref) < 1e-8
+
+
+def test_graph_replayed_solve_matches_eager(torch_cuda):
+    """Arnoldi chunks captured in a HIP graph and replayed (many replays per
+    solve, host reads of the convergence flags between them) give the same
+    currents as plain launches; two graph solves in a row, and the mixed form."""
+    from oracle import excitation
+    O = _oracle_cbf("cyl_small")
+    P = O["P"]
+    w, m = P["w"], P["m"]
+    cbfm, mesh, med, cbf = _gpu_handles(w, O)
+    n = cbf.n_cbf
+    Zr = torch_cuda.zeros((n, n), dtype=torch_cuda.complex128, device="cuda")
+    cbfm.project(mesh, med, cbf, Zr, cbfm.FP64)
+    nr, ne2 = len(w.inc), 2 * m.ne
+    j0 = torch_cuda.zeros((nr, ne2), dtype=torch_cuda.complex128, device="cuda")
+    e = cbfm.solve(mesh, med, cbf, Zr, w.inc, tol=1e-12, max_iter=n + 10, restart=n + 10, j_out=j0)
+    ref = j0.cpu().numpy()
+    for rep in range(2):
+        jg = torch_cuda.zeros((nr, ne2), dtype=torch_cuda.complex128, device="cuda")
+        g = cbfm.solve(mesh, med, cbf, Zr, w.inc, tol=1e-12, max_iter=n + 10, restart=n + 10, j_out=jg, use_graph=True)
+        print("graph solve", rep, g["iters"], e["iters"])
+        assert g["status"] == "OK" and np.array_equal(g["iters"], e["iters"])
+        assert _rel(jg.cpu().numpy(), ref) < 1e-13
+        _ = Zr.sum().item()  # eager work between the graph solves
+    # the mixed form: float cycles refined in double, one graph per cycle
+    jg = torch_cuda.zeros((nr, ne2), dtype=torch_cuda.complex128, device="cuda")
+    g = cbfm.solve(mesh, med, cbf, Zr, w.inc, tol=1e-11, max_iter=4 * n, restart=n, j_out=jg, use_graph=True,
+                   inner_fp32=True)
+    print("mixed graph solve", g)
+    assert g["status"] == "OK" and _rel(jg.cpu().numpy(), ref) < 1e-9
