@@ -287,6 +287,63 @@ cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, const vo
                        double* relres_host, const double* dirs_host, int64_t ndir,
                        double* rcs_host, void* stream);
 
+/* ------------------------------------------------------------- serving ---
+ * A request server for scattering solves of mixed size (the whole path of a
+ * request: mesh, CBF build, fill fused with the projection, CMP-GMRES and
+ * monostatic RCS, as the calls above).  `slots` worker threads, each with
+ * its own HIP stream on the current device, take requests in arrival order,
+ * first fit: a request is admitted when its estimated device footprint fits
+ * in what the budget leaves beside the requests running and the resident
+ * scatterers (which are evicted, least recently used first, while unused),
+ * or alone on an idle server.  Requests that arrive while others run are
+ * admitted as slots and memory free up, and their GPU work overlaps.
+ * Requests with the same nonzero scatterer_key share one resident mesh, CBF
+ * set and Z_r (built by the first; the caller guarantees that equal keys
+ * mean equal geometry, cells, medium, waves, delta_svd and precision).
+ * All inputs are copied at submission.                                     */
+typedef struct cbfm_server_s* cbfm_server;
+
+typedef struct {
+  const double* xyz_host;       /* nv x 3                                   */
+  int64_t nv;
+  const int32_t* tri_host;      /* nt x 3                                   */
+  int64_t nt;
+  const int32_t* edge_block;    /* per canonical edge, or NULL (one cell)   */
+  int32_t nblocks;
+  cbfm_medium medium;
+  const double* gen_host;       /* n_gen x 6 generating plane waves         */
+  int32_t n_gen;
+  double delta_svd;
+  int32_t precision;            /* projection precision (cbfm_precision)    */
+  const double* inc_host;       /* nrhs x 6 incidences                      */
+  int64_t nrhs;
+  double tol;                   /* GMRES relative residual                  */
+  int32_t max_iter;
+  int32_t restart;              /* 0: min(N_CBF, 400)                       */
+  uint64_t scatterer_key;       /* 0: nothing kept after the request        */
+} cbfm_request;
+
+/* Estimated peak device bytes of a request (CBF build, fill + projection
+   panels of at most 1 GiB unless one cell needs more, Z_r and the GMRES
+   workspace), as the server uses it for admission.                        */
+cbfm_status cbfm_request_footprint(const cbfm_request* req, int64_t* bytes);
+
+cbfm_status cbfm_server_create(int32_t slots, int64_t budget_bytes, cbfm_server* out);
+/* Queue a request; *ticket identifies it.  Never blocks on the GPU.        */
+cbfm_status cbfm_server_submit(cbfm_server srv, const cbfm_request* req, int64_t* ticket);
+/* Wait for a request and release it: rcs_host (nrhs monostatic sigma),
+   iters_host (nrhs), times_host (3: submitted, started, finished, seconds
+   on the server's clock); each may be NULL.  Returns the request's status
+   (its message through cbfm_last_error).                                  */
+cbfm_status cbfm_server_wait(cbfm_server srv, int64_t ticket, double* rcs_host, int32_t* iters_host,
+                             double* times_host);
+/* Peak device bytes admitted (running requests plus resident scatterers),
+   the most requests that ran at once, resident scatterers now.            */
+cbfm_status cbfm_server_stats(cbfm_server srv, int64_t* peak_bytes, int32_t* max_running,
+                              int32_t* resident);
+/* Waits for every queued request, stops the workers, frees residents.    */
+void cbfm_server_destroy(cbfm_server srv);
+
 #ifdef __cplusplus
 }
 #endif

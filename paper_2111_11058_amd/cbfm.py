@@ -67,6 +67,12 @@ def lib():
     sig = {
         "cbfm_last_error": (C.c_char_p, []),
         "cbfm_timer_enable": (_I32, [_I32]),
+        "cbfm_request_footprint": (_I32, [_P, C.POINTER(_I64)]),
+        "cbfm_server_create": (_I32, [_I32, _I64, C.POINTER(_P)]),
+        "cbfm_server_submit": (_I32, [_P, _P, C.POINTER(_I64)]),
+        "cbfm_server_wait": (_I32, [_P, _I64, _P, _P, _P]),
+        "cbfm_server_stats": (_I32, [_P, C.POINTER(_I64), C.POINTER(_I32), C.POINTER(_I32)]),
+        "cbfm_server_destroy": (None, [_P]),
         "cbfm_timer_read": (_I32, [C.c_char_p, C.POINTER(_I64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "cbfm_version": (_I32, []),
         "cbfm_mesh_load": (_I32, [_P, _I64, _P, _I64, _P, _I32, C.POINTER(_P)]),
@@ -354,3 +360,85 @@ def solve(mesh: Mesh, medium: Medium, cbf: CBF, Zr, inc, tol=1e-6, max_iter=1000
     if code != 0 and (code != -5 or raise_noconv):
         _check(code)
     return dict(iters=iters, relres=relres, rcs=rcs, status=STATUS.get(code, code))
+
+
+class Request(C.Structure):
+    """cbfm_request (see include/cbfm.h)."""
+    _fields_ = [("xyz_host", _P), ("nv", _I64), ("tri_host", _P), ("nt", _I64), ("edge_block", _P),
+                ("nblocks", _I32), ("medium", Medium), ("gen_host", _P), ("n_gen", _I32), ("delta_svd", C.c_double),
+                ("precision", _I32), ("inc_host", _P), ("nrhs", _I64), ("tol", C.c_double), ("max_iter", _I32),
+                ("restart", _I32), ("scatterer_key", C.c_uint64)]
+
+
+def make_request(V, T, edge_block, nblocks, medium, gen, delta_svd, inc, tol=1e-6, max_iter=0, restart=0,
+                 precision=FP64, key=0):
+    """A Request and the host arrays it points to (keep both alive until
+    the request is submitted; submission copies them)."""
+    V, pv = _host(V, np.float64)
+    T, pt = _host(T, np.int32)
+    gen, pg = _host(gen, np.float64)
+    inc, pi = _host(inc, np.float64)
+    keep = [V, T, gen, inc]
+    pe, nb = None, 1
+    if edge_block is not None:
+        eb, pe = _host(edge_block, np.int32)
+        keep.append(eb)
+        nb = int(nblocks)
+    r = Request(pv, V.size // 3, pt, T.size // 3, pe, nb, medium, pg, gen.size // 6, float(delta_svd), int(precision),
+                pi, inc.size // 6, float(tol), int(max_iter), int(restart), int(key))
+    return r, keep
+
+
+def request_footprint(req):
+    b = _I64()
+    _check(lib().cbfm_request_footprint(C.byref(req), C.byref(b)))
+    return b.value
+
+
+class Server:
+    """cbfm_server: continuous batching of scattering solves (slots worker
+    streams, admission by estimated device footprint within budget_bytes)."""
+
+    def __init__(self, slots=2, budget_bytes=None):
+        if budget_bytes is None:
+            import torch
+            free, _ = torch.cuda.mem_get_info()
+            budget_bytes = free // 2
+        h = _P()
+        _check(lib().cbfm_server_create(int(slots), int(budget_bytes), C.byref(h)))
+        self._h = h
+        self._nrhs = {}
+
+    def submit(self, req):
+        t = _I64()
+        _check(lib().cbfm_server_submit(self._h, C.byref(req), C.byref(t)))
+        self._nrhs[t.value] = req.nrhs
+        return t.value
+
+    def wait(self, ticket):
+        n = self._nrhs.pop(ticket)
+        rcs = np.zeros(n)
+        iters = np.zeros(n, np.int32)
+        times = np.zeros(3)
+        code = lib().cbfm_server_wait(self._h, int(ticket), rcs.ctypes.data_as(_P), iters.ctypes.data_as(_P),
+                                      times.ctypes.data_as(_P))
+        if code not in (0, -5):
+            _check(code)
+        return dict(rcs=rcs, iters=iters, t_submit=times[0], t_start=times[1], t_end=times[2],
+                    status=STATUS.get(code, code))
+
+    def stats(self):
+        pb, mr, res = _I64(), _I32(), _I32()
+        _check(lib().cbfm_server_stats(self._h, C.byref(pb), C.byref(mr), C.byref(res)))
+        return dict(peak_bytes=pb.value, max_running=mr.value, resident=res.value)
+
+    def close(self):
+        if self._h:
+            lib().cbfm_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

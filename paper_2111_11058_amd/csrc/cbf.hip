@@ -36,17 +36,19 @@ namespace cbfm {
 // ------------------------------------------------------------- rocSOLVER handle
 static std::mutex g_blas_mu;
 
+// One rocBLAS handle per (device, stream): a handle's workspace is then never
+// shared by work on two streams (concurrent requests of the server).
 rocblas_handle blas_handle(hipStream_t s) {
-  static std::map<int, rocblas_handle> handles;
+  static std::map<std::pair<int, hipStream_t>, rocblas_handle> handles;
   int dev = 0;
   CBFM_HIP(hipGetDevice(&dev));
-  auto it = handles.find(dev);
+  auto it = handles.find({dev, s});
   if (it == handles.end()) {
     rocblas_handle h;
     CBFM_REQUIRE(rocblas_create_handle(&h) == rocblas_status_success, CBFM_E_HIP, "rocblas_create_handle failed");
-    it = handles.emplace(dev, h).first;
+    CBFM_REQUIRE(rocblas_set_stream(h, s) == rocblas_status_success, CBFM_E_HIP, "rocblas_set_stream failed");
+    it = handles.emplace(std::make_pair(dev, s), h).first;
   }
-  CBFM_REQUIRE(rocblas_set_stream(it->second, s) == rocblas_status_success, CBFM_E_HIP, "rocblas_set_stream failed");
   return it->second;
 }
 

@@ -16,7 +16,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .blocks import octant_blocks, rcb_blocks
-from .meshes import cube, cylinder, icosphere
+from .meshes import cube, cylinder, geodesic, icosphere
 
 ETA0 = 376.730313668  # free-space wave impedance (ohm); passed to both sides
 
@@ -119,3 +119,70 @@ def small_cylinder(K=2, n_h=4, nblocks=4, eps_r=3.0 + 0j) -> Workload:
     V, T = cylinder(K, n_h, 0.3, 0.8)
     return Workload(f"cyl{len(T)}", V, T, rcb_blocks(V, T, nblocks), nblocks, eps_r, 1.0 + 0j,
                     random_incidences(3, 7), generating_set())
+
+
+# ---------------------------------------------------------------- serving
+@dataclass
+class ServeRequest:
+    t_arrival: float     # seconds after the stream starts
+    shape: str
+    unknowns: int
+    work: Workload
+
+
+def _serve_ladder():
+    """(shape, unknowns, mesh parameters) of the sizes a request may take:
+    sphere r 0.5 (icosphere-2, geodesic n = 5..11), cube edge 1 (n = 6..14
+    squares per face edge), cylinder r 0.5, h 2 (K = 3..6 rings, rows
+    keeping the side squares near unit aspect)."""
+    lad = {"sphere": [(960, ("ico", 2))] + [(60 * n * n, ("geo", n)) for n in range(5, 12)],
+           "cube": [(36 * n * n, ("cube", n)) for n in range(6, 15)],
+           "cylinder": []}
+    for K in range(3, 7):
+        nh = int(round(2.0 * 6 * K / np.pi))
+        lad["cylinder"].append((3 * (12 * K * nh + 12 * K * K), ("cyl", K, nh)))
+    return lad
+
+
+_SERVE_MESHES = {}
+
+
+def _serve_mesh(spec):
+    if spec not in _SERVE_MESHES:
+        if spec[0] == "ico":
+            V, T = icosphere(spec[1], 0.5)
+        elif spec[0] == "geo":
+            V, T = geodesic(spec[1], 0.5)
+        elif spec[0] == "cube":
+            V, T = cube(spec[1], 1.0)
+        else:
+            V, T = cylinder(spec[1], spec[2], 0.5, 2.0)
+        ne = 3 * len(T) // 2
+        nb = max(1, int(round(ne / 100.0)))
+        _SERVE_MESHES[spec] = (V, T, rcb_blocks(V, T, nb), nb)
+    return _SERVE_MESHES[spec]
+
+
+def serving_stream(n_requests: int = 512, seed: int = 2113, rate: float = 200.0, max_unknowns: float = 8000.0):
+    """Seeded request stream: Poisson arrivals at `rate` per second, shape
+    uniform over sphere / cube / cylinder, target unknowns uniform in
+    [960, max_unknowns] snapped to the nearest size of the shape's ladder,
+    eps_r uniform in [1.5, 6], 1-16 seeded incidences, RCB cells of about
+    100 edges, the Table-I generating waves."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+    lad = _serve_ladder()
+    out = []
+    for i in range(n_requests):
+        shape = ("sphere", "cube", "cylinder")[int(rng.integers(3))]
+        target = rng.uniform(960.0, max_unknowns)
+        eps = float(rng.uniform(1.5, 6.0))
+        nrhs = int(rng.integers(1, 17))
+        iseed = int(rng.integers(1 << 31))
+        opts = [(u, spec) for u, spec in lad[shape] if u <= max_unknowns] or lad[shape][:1]
+        u, spec = min(opts, key=lambda o: abs(o[0] - target))
+        V, T, eb, nb = _serve_mesh(spec)
+        w = Workload(f"{shape}{len(T)}_er{eps:.2f}", V, T, eb, nb, eps + 0j, 1.0 + 0j,
+                     random_incidences(nrhs, iseed), generating_set())
+        out.append(ServeRequest(float(t[i]), shape, u, w))
+    return out

@@ -80,6 +80,37 @@ def icosphere(level: int, radius: float = 1.0):
     return V, T.astype(np.int32)
 
 
+def geodesic(n: int, radius: float = 1.0):
+    """Icosahedron with every face split into an n x n triangular grid, the
+    grid points projected onto the sphere: 20 n^2 triangles (frequency-n
+    geodesic sphere).  Points shared by faces are merged exactly: each is
+    keyed by its integer barycentric weights on the icosahedron vertices."""
+    V0, T0 = icosphere(0, 1.0)
+    index, verts, tris = {}, [], []
+
+    def vid(a, b, c, i, j):
+        w = {}
+        for v, wt in ((a, n - i - j), (b, i), (c, j)):
+            if wt:
+                w[int(v)] = w.get(int(v), 0) + wt
+        key = tuple(sorted(w.items()))
+        if key not in index:
+            p = (V0[a] * (n - i - j) + V0[b] * i + V0[c] * j) / n
+            index[key] = len(verts)
+            verts.append(p / np.linalg.norm(p))
+        return index[key]
+
+    for a, b, c in T0:
+        for i in range(n):
+            for j in range(n - i):
+                tris.append((vid(a, b, c, i, j), vid(a, b, c, i + 1, j), vid(a, b, c, i, j + 1)))
+                if i + j + 1 < n:
+                    tris.append((vid(a, b, c, i + 1, j), vid(a, b, c, i + 1, j + 1), vid(a, b, c, i, j + 1)))
+    V = np.array(verts, dtype=np.float64) * radius
+    T = _orient_outward(V, np.array(tris, dtype=np.int64))
+    return V, T.astype(np.int32)
+
+
 def cube(n: int, edge: float = 1.0):
     """Cube [-edge/2, edge/2]^3; each face an n x n grid of squares, each square
     split along its face-local (i, j) -> (i+1, j+1) diagonal: 12 n^2 triangles.
