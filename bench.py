@@ -156,6 +156,68 @@ def rooflines(cbfm, step):
     return rows[dom], rows
 
 
+def serve(cbfm, n_requests, slots, budget, seed=2113, rate=200.0, tol=1e-6):
+    """Replay the seeded mixed-size request stream (Poisson arrivals at
+    `rate`/s) into a request server; latency = finish - submission on the
+    server's clock."""
+    from synth import configs
+    stream = configs.serving_stream(n_requests, seed=seed, rate=rate)
+    reqs = []
+    for r in stream:
+        w = r.work
+        med = cbfm.Medium.make(w.k0, w.eta0, w.eps_r, w.mu_r)
+        reqs.append(cbfm.make_request(w.V, w.T, w.edge_block, w.nblocks, med, w.gen, w.delta_svd, w.inc, tol=tol))
+    srv = cbfm.Server(slots=slots, budget_bytes=budget)
+    try:
+        tickets = []
+        t0 = time.perf_counter()
+        for r, (req, _) in zip(stream, reqs):
+            lag = r.t_arrival - (time.perf_counter() - t0)
+            if lag > 0:
+                time.sleep(lag)
+            tickets.append(srv.submit(req))
+        outs = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    finally:
+        srv.close()
+    lat = np.array([o["t_end"] - o["t_submit"] for o in outs])
+    queue = np.array([o["t_start"] - o["t_submit"] for o in outs])
+    nsolve = int(sum(len(o["rcs"]) for o in outs))
+    ok = sum(o["status"] == "OK" for o in outs)
+    status = {}
+    for o in outs:
+        status[o["status"]] = status.get(o["status"], 0) + 1
+    its = np.concatenate([o["iters"] for o in outs])
+    return {"requests": n_requests, "slots": slots, "budget_bytes": int(budget), "arrival_rate_per_s": rate,
+            "wall_s": wall, "requests_per_s": n_requests / wall, "solves_per_s": nsolve / wall,
+            "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
+                           "mean": float(lat.mean() * 1e3)},
+            "queue_wait_ms": {"p50": float(np.percentile(queue, 50) * 1e3), "p99": float(np.percentile(queue, 99) * 1e3)},
+            "status_ok": int(ok), "status": status, "gmres_iterations": {"mean": float(its.mean()), "max": int(its.max())},
+            "max_running": st["max_running"], "peak_admitted_bytes": st["peak_bytes"],
+            "unknowns": {"min": int(min(r.unknowns for r in stream)), "max": int(max(r.unknowns for r in stream))}}
+
+
+def serving_legs(cbfm, torch, n, slots):
+    """The serving leg under a generous budget (half the free device memory)
+    and a tight one (twice the largest request's estimated footprint)."""
+    from synth import configs
+    free, _ = torch.cuda.mem_get_info()
+    big = 0
+    for r in configs.serving_stream(n):
+        w = r.work
+        med = cbfm.Medium.make(w.k0, w.eta0, w.eps_r, w.mu_r)
+        req, keep = cbfm.make_request(w.V, w.T, w.edge_block, w.nblocks, med, w.gen, w.delta_svd, w.inc)
+        big = max(big, cbfm.request_footprint(req))
+    legs = {}
+    for name, budget in (("generous", free // 2), ("tight", min(free // 2, 2 * big))):
+        log(f"serving {name}: {n} requests, budget {budget / 2**30:.1f} GiB")
+        legs[name] = serve(cbfm, n, slots, budget)
+        log(f"serving {name}: {legs[name]}")
+    return legs
+
+
 def cpu_baseline(w, sample, seed=5):
     """The oracle's fill timed on a bounded, seeded sample of the workload's
     triangle pairs (regular and near pairs in the workload's proportion)."""
@@ -199,6 +261,10 @@ def main():
     ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the traffic summary from four rocprofv3 --pmc output folders (no GPU use)")
     ap.add_argument("--traffic-command", default="", help="command line recorded in the traffic summary")
+    ap.add_argument("--serve", type=int, default=32,
+                    help="requests of the serving leg (mixed-size stream, Poisson arrivals); 0 skips it")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving leg (both budgets)")
+    ap.add_argument("--serve-slots", type=int, default=4)
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(*args.write_traffic, args.traffic_command)
@@ -220,6 +286,9 @@ def main():
     from paper_2111_11058_amd import cbfm
     if not torch.cuda.is_available():
         raise SystemExit("no HIP device visible")
+    if args.serve_only:
+        print(json.dumps(serving_legs(cbfm, torch, args.serve or 512, args.serve_slots)), flush=True)
+        return
     w = workload(args.workload)
     log(f"bench: {w.name} nt={w.nt} cells={w.nblocks} nrhs={len(w.inc)}")
     mesh = cbfm.Mesh(w.V, w.T, w.edge_block, w.nblocks)
@@ -314,6 +383,9 @@ def main():
                            "rcs_max_rel_err_vs_fp64": float(np.max(np.abs(o["rcs"] - rcs64) / rcs64))}
             log(f"{name}: {forms[name]}")
         result["precision_forms"] = forms
+    if args.serve > 0:
+        log("serving")
+        result["serving"] = serving_legs(cbfm, torch, args.serve, args.serve_slots)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)

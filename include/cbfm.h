@@ -243,6 +243,17 @@ void cbfm_cbf_free(cbfm_cbf c);
 cbfm_status cbfm_project(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, int32_t precision,
                          void* Zr_dev, int64_t ldz, void* stream);
 
+/* cbfm_project_batch: Z_r of `count` scatterers of any sizes and media at
+ * once (as cbfm_project for each): the regular-pair fills of all of them run
+ * in one persistent launch over (scatterer, test triangle, source tile)
+ * work items, the projection GEMMs of all of them in two batched launches.
+ * Scatterers are grouped while their whole-Z scratch fits a quarter of the
+ * free device memory; one that does not fit goes through cbfm_project's
+ * panels.  meshes, media, cbfs, Zr, ldz: arrays of `count` entries.        */
+cbfm_status cbfm_project_batch(int32_t count, const cbfm_mesh* meshes, const cbfm_medium* media,
+                               const cbfm_cbf* cbfs, int32_t precision, void* const* Zr_dev,
+                               const int64_t* ldz, void* stream);
+
 /* ----------------------------------------------------------------- CMP ---
  * cbfm_cmp_apply: x = (G^CBF)^{-1} y with G^CBF = (C^JM)^H G_ffff C^MJ
  * (paper Sec. III-C, CBF Gram matrix and inner CBFM equation), exact
@@ -318,8 +329,8 @@ typedef struct {
   const double* inc_host;       /* nrhs x 6 incidences                      */
   int64_t nrhs;
   double tol;                   /* GMRES relative residual                  */
-  int32_t max_iter;
-  int32_t restart;              /* 0: min(N_CBF, 400)                       */
+  int32_t max_iter;             /* 0: 3000                                  */
+  int32_t restart;              /* 0: min(N_CBF, 1000)                      */
   uint64_t scatterer_key;       /* 0: nothing kept after the request        */
 } cbfm_request;
 

@@ -68,6 +68,7 @@ def lib():
         "cbfm_last_error": (C.c_char_p, []),
         "cbfm_timer_enable": (_I32, [_I32]),
         "cbfm_request_footprint": (_I32, [_P, C.POINTER(_I64)]),
+        "cbfm_project_batch": (_I32, [_I32, _P, _P, _P, _I32, _P, _P, _P]),
         "cbfm_server_create": (_I32, [_I32, _I64, C.POINTER(_P)]),
         "cbfm_server_submit": (_I32, [_P, _P, C.POINTER(_I64)]),
         "cbfm_server_wait": (_I32, [_P, _I64, _P, _P, _P]),
@@ -316,6 +317,19 @@ def project(mesh: Mesh, medium: Medium, cbf: CBF, out, precision=FP64, ldz=None,
     p = _dev(out, torch.complex128, n * ldz, "Zr")
     _check(lib().cbfm_project(mesh.handle, C.byref(medium), cbf.handle, precision, p, ldz, _stream(stream)))
     return out
+
+
+def project_batch(items, precision=FP64, stream=None):
+    """cbfm_project_batch over items = [(mesh, medium, cbf, Zr tensor), ...]
+    (Zr row-major n x n complex128, ldz = n)."""
+    import torch
+    k = len(items)
+    meshes = (_P * k)(*[it[0].handle for it in items])
+    media = (Medium * k)(*[it[1] for it in items])
+    cbfs = (_P * k)(*[it[2].handle for it in items])
+    zr = (_P * k)(*[_dev(it[3], torch.complex128, it[2].n_cbf ** 2, "Zr") for it in items])
+    ldz = (_I64 * k)(*[it[2].n_cbf for it in items])
+    _check(lib().cbfm_project_batch(k, meshes, media, cbfs, int(precision), zr, ldz, _stream(stream)))
 
 
 def cmp_apply(cbf: CBF, y, x, stream=None):

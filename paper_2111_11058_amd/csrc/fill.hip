@@ -22,6 +22,7 @@
 // the bounded remainders by the 7-point rule.  K of a coplanar pair is 0.
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -181,16 +182,13 @@ __device__ __forceinline__ float expo(float x) { return __expf(x); }
 // Two wavefronts per SIMD at least: the FP64 instance then fits in 256
 // VGPRs (one or two spilled outside the point loops), which hides the
 // latency of its dependent FP64 chains far better than one wavefront.
+// The 3 x 3 local blocks of the three output operators for test triangle P
+// and source triangle Q, written at o0 (row stride ldl, operator stride
+// op_stride).
 template <typename R, bool LOSSY>
-__global__ void __launch_bounds__(256, 2) fill_regular_kernel(
-    TriTab<R> tab, const int32_t* __restrict__ rowTris, const int32_t* __restrict__ colTris,
-    int64_t nct, FillConsts fc, cx<R>* __restrict__ out, int64_t op_stride, int64_t ldl) {
-  const int64_t i = blockIdx.y;
-  const int64_t jq = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (jq >= nct) return;
+__device__ __forceinline__ void regular_pair(const TriTab<R>& tab, int32_t P, int32_t Q, const FillConsts& fc,
+                                             cx<R>* __restrict__ o0, int64_t op_stride, int64_t ldl) {
   const int64_t nt = tab.nt;
-  const int32_t P = rowTris[i];
-  const int32_t Q = colTris[jq];
 
   const R d[3] = {(R)(tab.cen[0][P] - tab.cen[0][Q]), (R)(tab.cen[1][P] - tab.cen[1][Q]),
                   (R)(tab.cen[2][P] - tab.cen[2][Q])};
@@ -310,7 +308,6 @@ __global__ void __launch_bounds__(256, 2) fill_regular_kernel(
       qv[a][c] = tab.v[c][a * nt + Q];
     }
   }
-  cx<R>* o0 = out + (3 * i) * ldl + 3 * jq;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const R* p = pv[a];
@@ -363,6 +360,56 @@ __global__ void __launch_bounds__(256, 2) fill_regular_kernel(
         o0[(o + 1) * op_stride + a * ldl + b] = cx<R>{cab * re, cab * im};
       }
     }
+  }
+}
+
+template <typename R, bool LOSSY>
+__global__ void __launch_bounds__(256, 2) fill_regular_kernel(
+    TriTab<R> tab, const int32_t* __restrict__ rowTris, const int32_t* __restrict__ colTris,
+    int64_t nct, FillConsts fc, cx<R>* __restrict__ out, int64_t op_stride, int64_t ldl) {
+  const int64_t i = blockIdx.y;
+  const int64_t jq = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (jq >= nct) return;
+  regular_pair<R, LOSSY>(tab, rowTris[i], colTris[jq], fc, out + (3 * i) * ldl + 3 * jq, op_stride, ldl);
+}
+
+// Many fills (scatterers of any size, each with its own medium) in one
+// persistent launch: a work item is one row triangle of one job against 256
+// of its columns; blocks stride over the items of all jobs.
+template <typename R>
+struct FillJob {
+  TriTab<R> tab;
+  FillConsts fc;
+  const int32_t* rowTris;
+  const int32_t* colTris;
+  int64_t nct, op_stride, ldl;
+  cx<R>* out;
+  int32_t lossy;
+  int64_t item0;  // first work item of the job
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256, 2) fill_regular_batch_kernel(const FillJob<R>* __restrict__ jobs, int njobs,
+                                                                     int64_t total) {
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].item0 <= it)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const FillJob<R>& J = jobs[lo];
+    const int64_t local = it - J.item0, chunks = (J.nct + 255) / 256;
+    const int64_t i = local / chunks, jq = (local % chunks) * 256 + threadIdx.x;
+    if (jq >= J.nct) continue;
+    cx<R>* o0 = J.out + (3 * i) * J.ldl + 3 * jq;
+    if (J.lossy)
+      regular_pair<R, true>(J.tab, J.rowTris[i], J.colTris[jq], J.fc, o0, J.op_stride, J.ldl);
+    else
+      regular_pair<R, false>(J.tab, J.rowTris[i], J.colTris[jq], J.fc, o0, J.op_stride, J.ldl);
   }
 }
 
@@ -653,6 +700,65 @@ void fill_local(const cbfm_mesh_s* m, const Media& md, int precision, int layout
     near_stage(m, fc, near, nnear, static_cast<cx<double>*>(local), op_stride, ldl, s);
   else
     near_stage(m, fc, near, nnear, static_cast<cx<float>*>(local), op_stride, ldl, s);
+}
+
+void fill_near(const cbfm_mesh_s* m, const Media& md, int precision, int layout, const NearPair* near, int64_t nnear,
+               int64_t nrt, int64_t nct, void* local, hipStream_t s) {
+  const FillConsts fc = make_consts(md, layout);
+  const int64_t ldl = 3 * nct, op_stride = 3 * nrt * ldl;
+  TimedLaunch tn(T_FILL_NEAR, s, (double)nnear);  // work: near pairs
+  if (precision == CBFM_FP64)
+    near_stage(m, fc, near, nnear, static_cast<cx<double>*>(local), op_stride, ldl, s);
+  else
+    near_stage(m, fc, near, nnear, static_cast<cx<float>*>(local), op_stride, ldl, s);
+}
+
+template <typename R>
+static void batch_launch(const std::vector<FillBatchItem>& items, hipStream_t s) {
+  std::vector<FillJob<R>> jobs;
+  int64_t total = 0;
+  double pairs = 0;
+  for (const FillBatchItem& it : items) {
+    if (it.nrt == 0 || it.nct == 0) continue;
+    FillJob<R> j{};
+    if constexpr (std::is_same<R, double>::value)
+      j.tab = it.m->tab64();
+    else
+      j.tab = it.m->tab32();
+    j.fc = make_consts(it.md, it.layout);
+    j.rowTris = it.rowTris;
+    j.colTris = it.colTris;
+    j.nct = it.nct;
+    j.ldl = 3 * it.nct;
+    j.op_stride = 3 * it.nrt * j.ldl;
+    j.out = static_cast<cx<R>*>(it.local);
+    j.lossy = it.md.k2i != 0.0;
+    j.item0 = total;
+    total += it.nrt * ((it.nct + 255) / 256);
+    pairs += (double)it.nrt * (double)it.nct;
+    jobs.push_back(j);
+  }
+  if (jobs.empty()) return;
+  Scratch dev(jobs.size() * sizeof(FillJob<R>), s);
+  CBFM_HIP(hipMemcpyAsync(dev.p, jobs.data(), jobs.size() * sizeof(FillJob<R>), hipMemcpyHostToDevice, s));
+  int dev_id = 0, cus = 0;
+  CBFM_HIP(hipGetDevice(&dev_id));
+  CBFM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
+  const int64_t grid = std::min<int64_t>(total, (int64_t)8 * std::max(cus, 1));
+  {
+    TimedLaunch tl(T_FILL_REGULAR, s, pairs);  // work: triangle pairs
+    hipLaunchKernelGGL(fill_regular_batch_kernel<R>, dim3((unsigned)grid), dim3(256), 0, s, dev.as<FillJob<R>>(),
+                       (int)jobs.size(), total);
+    CBFM_HIP(hipGetLastError());
+  }
+  CBFM_HIP(hipStreamSynchronize(s));  // the job table is host memory of this frame
+}
+
+void fill_regular_batch(const std::vector<FillBatchItem>& items, int precision, hipStream_t s) {
+  if (precision == CBFM_FP64)
+    batch_launch<double>(items, s);
+  else
+    batch_launch<float>(items, s);
 }
 
 // ------------------------------------------------------------- assembly

@@ -189,6 +189,21 @@ Media make_media(const cbfm_medium* med);
 // Fill the triangle-local matrix for row triangles x column triangles into
 // `local` (3 ops x 3*nrt x 3*nct complex of the given precision, ops per
 // layout) and overwrite the near pairs.  Implemented in fill.hip.
+// One regular fill of many (mesh, medium, rows x columns) jobs in a single
+// persistent launch (the near pairs of each job are left to fill_near).
+struct FillBatchItem {
+  const cbfm_mesh_s* m;
+  Media md;
+  int layout;
+  const int32_t* rowTris;
+  int64_t nrt;
+  const int32_t* colTris;
+  int64_t nct;
+  void* local;
+};
+void fill_regular_batch(const std::vector<FillBatchItem>& items, int precision, hipStream_t s);
+void fill_near(const cbfm_mesh_s* m, const Media& md, int precision, int layout, const NearPair* near, int64_t nnear,
+               int64_t nrt, int64_t nct, void* local, hipStream_t s);
 void fill_local(const cbfm_mesh_s* m, const Media& md, int precision, int layout,
                 const int32_t* rowTris_dev, int64_t nrt, const int32_t* colTris_dev, int64_t nct,
                 const NearPair* near_dev, int64_t nnear, void* local, hipStream_t s);

@@ -12,6 +12,7 @@
 //   Z_r[cell a rows]  = C_a^H W_X[cell a rows, :]
 // so only one panel of Z exists at a time.
 #include <algorithm>
+#include <memory>
 #include <cstring>
 
 #include "cbf.h"
@@ -22,6 +23,81 @@ namespace cbfm {
 // Bytes of scratch a panel of `nrow` RWG rows touching `nrt` triangles needs.
 static size_t panel_bytes(int64_t nrt, int64_t nt, int64_t nrow, int64_t ne, int64_t NL, size_t esz) {
   return (size_t)27 * nrt * nt * esz + (size_t)3 * nrow * ne * 16 + (size_t)4 * nrow * NL * 16;
+}
+
+// Descriptors of the projection GEMMs of a panel holding the rows of cells
+// p0..p1-1: Zp = [K; TE; TH] rows of the panel (nrow x ne each, complex float
+// for the mixed forms, else double), W its four nrow x N_L products.
+static void panel_gemms(const MeshHost& h, cbfm_cbf_s* c, int p0, int p1, void* Zp, void* W, bool mixed, double2* Zr,
+                        int64_t ldz, std::vector<GemmDesc>& d1, std::vector<GemmDesc>& d2, std::vector<GemmDescX>& x1,
+                        std::vector<GemmDescX>& x2) {
+  const int nb = h.nblocks;
+  const int64_t ne = h.ne, NL = c->NL, r0 = h.cell_off[p0], nrow = h.cell_off[p1] - r0;
+  const size_t zs = mixed ? sizeof(float2) : sizeof(double2);
+  char* Zk = static_cast<char*>(Zp);
+  char* Zte = Zk + nrow * ne * zs;
+  char* Zth = Zte + nrow * ne * zs;
+  char* Wkm = static_cast<char*>(W);
+  char* Wkj = Wkm + nrow * NL * zs;
+  char* Wte = Wkj + nrow * NL * zs;
+  char* Wth = Wte + nrow * NL * zs;
+  for (int b = 0; b < nb; ++b) {
+    const int64_t Nb = h.cell_off[b + 1] - h.cell_off[b], cb0 = h.cell_off[b];
+    const double2* CMb = c->CM.as<double2>() + c->coff[b];
+    const double2* CJb = c->CJ.as<double2>() + c->coff[b];
+    const int64_t Lb = c->L[b], ob = c->off[b];
+    const struct {
+      char* Z;
+      const double2* C;
+      char* W;
+    } prod[4] = {{Zk, CMb, Wkm}, {Zk, CJb, Wkj}, {Zte, CJb, Wte}, {Zth, CMb, Wth}};
+    for (const auto& q : prod) {
+      if (mixed)
+        x1.push_back(gemmx(q.Z + cb0 * zs, 0, ne, OP_N, q.C, 1, Lb, OP_N, q.W + ob * zs, 0, NL, nrow, Lb, Nb));
+      else
+        d1.push_back(gemm(reinterpret_cast<const double2*>(q.Z) + cb0, ne, OP_N, q.C, Lb, OP_N,
+                          reinterpret_cast<double2*>(q.W) + ob, NL, nrow, Lb, Nb));
+    }
+  }
+  for (int a = p0; a < p1; ++a) {
+    const int64_t Na = h.cell_off[a + 1] - h.cell_off[a], ra = h.cell_off[a] - r0;
+    const double2* CMa = c->CM.as<double2>() + c->coff[a];
+    const double2* CJa = c->CJ.as<double2>() + c->coff[a];
+    const int64_t La = c->L[a], oa = c->off[a];
+    // Z_r blocks: [J rows][M cols] = C^J^H K C^M, [J][J] = -C^J^H TE C^J,
+    //             [M][M] = C^M^H TH C^M,         [M][J] = C^M^H K C^J
+    const struct {
+      const double2* C;
+      char* W;
+      double2* out;
+      double alpha;
+    } prod[4] = {{CJa, Wkm, Zr + oa * ldz, 1.0},
+                 {CJa, Wte, Zr + oa * ldz + NL, -1.0},
+                 {CMa, Wth, Zr + (NL + oa) * ldz, 1.0},
+                 {CMa, Wkj, Zr + (NL + oa) * ldz + NL, 1.0}};
+    for (const auto& q : prod) {
+      if (mixed)
+        x2.push_back(gemmx(q.C, 1, La, OP_C, q.W + ra * NL * zs, 0, NL, OP_N, q.out, 1, ldz, La, NL, Na,
+                           (float)q.alpha));
+      else
+        d2.push_back(gemm(q.C, La, OP_C, reinterpret_cast<const double2*>(q.W) + ra * NL, NL, OP_N, q.out, ldz, La, NL,
+                          Na, q.alpha));
+    }
+  }
+}
+
+// Both GEMM stages (each one batched launch; both synchronise the stream).
+static void launch_panel_gemms(int precision, std::vector<GemmDesc>& d1, std::vector<GemmDesc>& d2,
+                               std::vector<GemmDescX>& x1, std::vector<GemmDescX>& x2, hipStream_t s) {
+  const int mode = precision == CBFM_MIXED_BF16 ? XG_BF16 : precision == CBFM_MIXED_BF16X3 ? XG_BF16X3 : XG_FP32;
+  if (!x1.empty()) {
+    xgemm_batched(x1, mode, s);
+    xgemm_batched(x2, mode, s);
+  }
+  if (!d1.empty()) {
+    zgemm_batched(d1, s);
+    zgemm_batched(d2, s);
+  }
 }
 
 void project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int precision, double2* Zr, int64_t ldz,
@@ -111,77 +187,118 @@ void project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int preci
     fill_local(m, md, fillp, CBFM_LAYOUT_OPS3, d_rows, nrt, colTris, nt, d_nl, (int64_t)nl.size(), local.p, s);
     assemble(m, fillp, local.p, nrt, nt, d_re, nrow, colEdges, ne, d_pos, colPos, Zp.p, nrow * ne, ne, s,
              mixed ? 0 : 1);
-    if (mixed) {
-      const float2* Zk = Zp.as<float2>();
-      const float2* Zte = Zk + nrow * ne;
-      const float2* Zth = Zte + nrow * ne;
-      float2* Wkm = W.as<float2>();
-      float2* Wkj = Wkm + nrow * NL;
-      float2* Wte = Wkj + nrow * NL;
-      float2* Wth = Wte + nrow * NL;
-      std::vector<GemmDescX> x1, x2;
-      for (int b = 0; b < nb; ++b) {
-        const int64_t Nb = h.cell_off[b + 1] - h.cell_off[b], cb0 = h.cell_off[b];
-        const double2* CMb = c->CM.as<double2>() + c->coff[b];
-        const double2* CJb = c->CJ.as<double2>() + c->coff[b];
-        const int64_t Lb = c->L[b], ob = c->off[b];
-        x1.push_back(gemmx(Zk + cb0, 0, ne, OP_N, CMb, 1, Lb, OP_N, Wkm + ob, 0, NL, nrow, Lb, Nb));
-        x1.push_back(gemmx(Zk + cb0, 0, ne, OP_N, CJb, 1, Lb, OP_N, Wkj + ob, 0, NL, nrow, Lb, Nb));
-        x1.push_back(gemmx(Zte + cb0, 0, ne, OP_N, CJb, 1, Lb, OP_N, Wte + ob, 0, NL, nrow, Lb, Nb));
-        x1.push_back(gemmx(Zth + cb0, 0, ne, OP_N, CMb, 1, Lb, OP_N, Wth + ob, 0, NL, nrow, Lb, Nb));
-      }
-      for (int a = p0; a < p1; ++a) {
-        const int64_t Na = h.cell_off[a + 1] - h.cell_off[a], ra = h.cell_off[a] - r0;
-        const double2* CMa = c->CM.as<double2>() + c->coff[a];
-        const double2* CJa = c->CJ.as<double2>() + c->coff[a];
-        const int64_t La = c->L[a], oa = c->off[a];
-        x2.push_back(gemmx(CJa, 1, La, OP_C, Wkm + ra * NL, 0, NL, OP_N, Zr + oa * ldz, 1, ldz, La, NL, Na));
-        x2.push_back(gemmx(CJa, 1, La, OP_C, Wte + ra * NL, 0, NL, OP_N, Zr + oa * ldz + NL, 1, ldz, La, NL, Na, -1.0f));
-        x2.push_back(gemmx(CMa, 1, La, OP_C, Wth + ra * NL, 0, NL, OP_N, Zr + (NL + oa) * ldz, 1, ldz, La, NL, Na));
-        x2.push_back(gemmx(CMa, 1, La, OP_C, Wkj + ra * NL, 0, NL, OP_N, Zr + (NL + oa) * ldz + NL, 1, ldz, La, NL, Na));
-      }
-      const int mode = precision == CBFM_MIXED_BF16 ? XG_BF16 : precision == CBFM_MIXED_BF16X3 ? XG_BF16X3 : XG_FP32;
-      xgemm_batched(x1, mode, s);
-      xgemm_batched(x2, mode, s);
-      continue;  // xgemm_batched synchronised the stream
-    }
-    double2* Zk = Zp.as<double2>();
-    double2* Zte = Zk + nrow * ne;
-    double2* Zth = Zte + nrow * ne;
-    double2* Wkm = W.as<double2>();
-    double2* Wkj = Wkm + nrow * NL;
-    double2* Wte = Wkj + nrow * NL;
-    double2* Wth = Wte + nrow * NL;
     std::vector<GemmDesc> d1, d2;
-    for (int b = 0; b < nb; ++b) {
-      const int64_t Nb = h.cell_off[b + 1] - h.cell_off[b], cb0 = h.cell_off[b];
-      const double2* CMb = c->CM.as<double2>() + c->coff[b];
-      const double2* CJb = c->CJ.as<double2>() + c->coff[b];
-      const int64_t Lb = c->L[b], ob = c->off[b];
-      d1.push_back(gemm(Zk + cb0, ne, OP_N, CMb, Lb, OP_N, Wkm + ob, NL, nrow, Lb, Nb));
-      d1.push_back(gemm(Zk + cb0, ne, OP_N, CJb, Lb, OP_N, Wkj + ob, NL, nrow, Lb, Nb));
-      d1.push_back(gemm(Zte + cb0, ne, OP_N, CJb, Lb, OP_N, Wte + ob, NL, nrow, Lb, Nb));
-      d1.push_back(gemm(Zth + cb0, ne, OP_N, CMb, Lb, OP_N, Wth + ob, NL, nrow, Lb, Nb));
-    }
-    for (int a = p0; a < p1; ++a) {
-      const int64_t Na = h.cell_off[a + 1] - h.cell_off[a], ra = h.cell_off[a] - r0;
-      const double2* CMa = c->CM.as<double2>() + c->coff[a];
-      const double2* CJa = c->CJ.as<double2>() + c->coff[a];
-      const int64_t La = c->L[a], oa = c->off[a];
-      d2.push_back(gemm(CJa, La, OP_C, Wkm + ra * NL, NL, OP_N, Zr + oa * ldz, ldz, La, NL, Na));
-      d2.push_back(gemm(CJa, La, OP_C, Wte + ra * NL, NL, OP_N, Zr + oa * ldz + NL, ldz, La, NL, Na, -1.0));
-      d2.push_back(gemm(CMa, La, OP_C, Wth + ra * NL, NL, OP_N, Zr + (NL + oa) * ldz, ldz, La, NL, Na));
-      d2.push_back(gemm(CMa, La, OP_C, Wkj + ra * NL, NL, OP_N, Zr + (NL + oa) * ldz + NL, ldz, La, NL, Na));
-    }
-    zgemm_batched(d1, s);
-    zgemm_batched(d2, s);
+    std::vector<GemmDescX> x1, x2;
+    panel_gemms(h, c, p0, p1, Zp.p, W.p, mixed, Zr, ldz, d1, d2, x1, x2);
+    launch_panel_gemms(precision, d1, d2, x1, x2, s);
     CBFM_HIP(hipStreamSynchronize(s));  // host index staging of this panel
+  }
+}
+
+// Z_r of several scatterers, each taken as one panel of all its cells: the
+// regular fills of all of them in one persistent launch, then per scatterer
+// the near pairs and the assembly, then the projection GEMMs of all of them
+// in two batched launches.  Consecutive scatterers are grouped while their
+// scratch fits the budget; one that does not fit alone goes through the
+// panelled single-scatterer path.
+struct BatchEntry {
+  const cbfm_mesh_s* m;
+  Media md;
+  cbfm_cbf_s* c;
+  double2* Zr;
+  int64_t ldz;
+};
+
+void project_batch_dev(const std::vector<BatchEntry>& es, int precision, hipStream_t s, size_t budget) {
+  const bool mixed = precision == CBFM_MIXED_FP32 || precision == CBFM_MIXED_BF16 || precision == CBFM_MIXED_BF16X3;
+  const int fillp = precision == CBFM_FP64 ? CBFM_FP64 : CBFM_FP32;
+  const size_t esz = fillp == CBFM_FP64 ? 16 : 8;
+  auto full = [&](const BatchEntry& e) {
+    const MeshHost& h = e.m->h;
+    return panel_bytes(h.nt, h.nt, h.ne, h.ne, e.c->NL, esz);
+  };
+  struct Prep {
+    std::unique_ptr<Scratch> idx, local, Zp, W;
+    int32_t* iota;
+    NearPair* near;
+  };
+  size_t i = 0;
+  while (i < es.size()) {
+    size_t j = i, bytes = 0;
+    while (j < es.size() && (j == i || bytes + full(es[j]) <= budget)) bytes += full(es[j++]);
+    if (j == i + 1 && bytes > budget) {
+      project_dev(es[i].m, es[i].md, es[i].c, precision, es[i].Zr, es[i].ldz, s, budget);
+      i = j;
+      continue;
+    }
+    std::vector<std::unique_ptr<Prep>> preps;
+    std::vector<FillBatchItem> items;
+    for (size_t k = i; k < j; ++k) {
+      const BatchEntry& e = es[k];
+      const MeshHost& h = e.m->h;
+      auto p = std::make_unique<Prep>();
+      std::vector<int32_t> iota(h.nt);
+      for (int64_t t = 0; t < h.nt; ++t) iota[t] = (int32_t)t;
+      const size_t ib = 4 * iota.size() + sizeof(NearPair) * h.near.size();
+      p->idx.reset(new Scratch(ib, s));
+      CBFM_HIP(hipMemcpyAsync(p->idx->p, iota.data(), 4 * iota.size(), hipMemcpyHostToDevice, s));
+      if (!h.near.empty())
+        CBFM_HIP(hipMemcpyAsync(p->idx->as<char>() + 4 * iota.size(), h.near.data(), sizeof(NearPair) * h.near.size(),
+                                hipMemcpyHostToDevice, s));
+      p->iota = p->idx->as<int32_t>();
+      p->near = reinterpret_cast<NearPair*>(p->idx->as<char>() + 4 * iota.size());
+      const size_t zsz = mixed ? sizeof(float2) : sizeof(double2);
+      p->local.reset(new Scratch((size_t)27 * h.nt * h.nt * esz, s));
+      p->Zp.reset(new Scratch((size_t)3 * h.ne * h.ne * zsz, s));
+      p->W.reset(new Scratch((size_t)4 * h.ne * e.c->NL * zsz, s));
+      items.push_back({e.m, e.md, CBFM_LAYOUT_OPS3, p->iota, h.nt, p->iota, h.nt, p->local->p});
+      preps.push_back(std::move(p));
+    }
+    fill_regular_batch(items, fillp, s);
+    std::vector<GemmDesc> d1, d2;
+    std::vector<GemmDescX> x1, x2;
+    for (size_t k = i; k < j; ++k) {
+      const BatchEntry& e = es[k];
+      const MeshHost& h = e.m->h;
+      Prep& p = *preps[k - i];
+      fill_near(e.m, e.md, fillp, CBFM_LAYOUT_OPS3, p.near, (int64_t)h.near.size(), h.nt, h.nt, p.local->p, s);
+      assemble(e.m, fillp, p.local->p, h.nt, h.nt, e.m->perm.as<int32_t>(), h.ne, e.m->perm.as<int32_t>(), h.ne,
+               p.iota, p.iota, p.Zp->p, h.ne * h.ne, h.ne, s, mixed ? 0 : 1);
+      panel_gemms(h, e.c, 0, h.nblocks, p.Zp->p, p.W->p, mixed, e.Zr, e.ldz, d1, d2, x1, x2);
+    }
+    launch_panel_gemms(precision, d1, d2, x1, x2, s);
+    i = j;
   }
 }
 
 }  // namespace cbfm
 
 using namespace cbfm;
+
+extern "C" cbfm_status cbfm_project_batch(int32_t count, const cbfm_mesh* meshes, const cbfm_medium* media,
+                                          const cbfm_cbf* cbfs, int32_t precision, void* const* Zr, const int64_t* ldz,
+                                          void* stream) {
+  return guarded([&] {
+    CBFM_REQUIRE(count >= 0, CBFM_E_ARG, "negative count");
+    if (count == 0) return;
+    CBFM_REQUIRE(meshes && media && cbfs && Zr && ldz, CBFM_E_ARG, "null argument");
+    CBFM_REQUIRE(precision == CBFM_FP64 || precision == CBFM_FP32 || precision == CBFM_MIXED_FP32 ||
+                     precision == CBFM_MIXED_BF16 || precision == CBFM_MIXED_BF16X3,
+                 CBFM_E_ARG, "unknown precision");
+    std::vector<BatchEntry> es;
+    for (int32_t k = 0; k < count; ++k) {
+      CBFM_REQUIRE(meshes[k] && cbfs[k] && Zr[k], CBFM_E_ARG, "null entry " + std::to_string(k));
+      CBFM_REQUIRE(cbfs[k]->mesh == meshes[k], CBFM_E_STATE, "CBF set of entry " + std::to_string(k) + " belongs to another mesh");
+      CBFM_REQUIRE(ldz[k] >= 2 * cbfs[k]->NL, CBFM_E_ARG, "ldz < N_CBF in entry " + std::to_string(k));
+      CBFM_REQUIRE(meshes[k]->h.nt <= 65535, CBFM_E_ARG, "too many triangles for one assembly launch");
+      es.push_back({meshes[k], make_media(&media[k]), cbfs[k], static_cast<double2*>(Zr[k]), ldz[k]});
+    }
+    size_t fr = 0, tot = 0;
+    CBFM_HIP(hipMemGetInfo(&fr, &tot));
+    const size_t budget = std::min<size_t>(fr / 4, (size_t)32 << 30);
+    project_batch_dev(es, precision, static_cast<hipStream_t>(stream), budget);
+  });
+}
 
 extern "C" cbfm_status cbfm_project(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, int32_t precision, void* Zr,
                                     int64_t ldz, void* stream) {

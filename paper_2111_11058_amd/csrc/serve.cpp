@@ -87,7 +87,7 @@ std::pair<size_t, size_t> estimate(int64_t nt, const std::vector<int32_t>& eb, i
                        6 * nb * S * Nmax * z + 2 * nb * Nmax * Nmax * z + 2 * S * ne * z;
   const double cell_panel = 27 * 2 * Nmax * (double)nt * esz + 3 * Nmax * ne * z + 4 * Nmax * NL * z;
   const double panel = std::max<double>(cell_panel, (double)panel_budget);
-  const double m = restart > 0 ? std::min<double>(restart, n) : std::min<double>(n, 400);
+  const double m = restart > 0 ? std::min<double>(restart, n) : std::min<double>(n, 1000);
   const double solve = (m + 1) * nrhs * n * z + 2 * nrhs * (m + 1) * m * z + n * n * z + 8 * nrhs * std::max(n, 2 * ne) * z;
   const double resident = n * n * z + NL * NL * z + 2 * ne * S * z + 2048.0 * nt;
   return {(size_t)(std::max(build, panel) + solve), (size_t)resident};
@@ -212,8 +212,8 @@ void cbfm_server_s::run(Job* j, hipStream_t s) {
     }
     cbfm_solver_params sp{};
     sp.tol = j->tol;
-    sp.max_iter = j->max_iter > 0 ? j->max_iter : 2000;
-    sp.restart = j->restart > 0 ? j->restart : (int32_t)std::min<int64_t>(r->n, 400);
+    sp.max_iter = j->max_iter > 0 ? j->max_iter : 3000;
+    sp.restart = j->restart > 0 ? j->restart : (int32_t)std::min<int64_t>(r->n, 1000);
     sp.use_cmp = 1;
     j->rcs.assign(j->nrhs, 0.0);
     j->iters.assign(j->nrhs, 0);

@@ -215,3 +215,30 @@ def test_graph_replayed_solve_matches_eager(torch_cuda):
                    inner_fp32=True)
     print("mixed graph solve", g)
     assert g["status"] == "OK" and _rel(jg.cpu().numpy(), ref) < 1e-9
+
+
+def test_batched_projection_matches_single(torch_cuda):
+    """Several scatterers (own sizes and media) through one persistent fill
+    launch and batched GEMMs give each one's Z_r as cbfm_project does, and
+    the FP64 oracle's."""
+    from paper_2111_11058_amd import cbfm
+    names = ["c1", "cyl_small"]
+    Os = [_oracle_cbf(nm) for nm in names]
+    hs = [_gpu_handles(O["P"]["w"], O) for O in Os]
+    for prec, tol in ((cbfm.FP64, 1e-13), (cbfm.MIXED_FP32, 1e-5)):
+        items, singles = [], []
+        for (cb_, mesh, med, cbf), O in zip(hs, Os):
+            n = cbf.n_cbf
+            zb = torch_cuda.zeros((n, n), dtype=torch_cuda.complex128, device="cuda")
+            zs = torch_cuda.zeros((n, n), dtype=torch_cuda.complex128, device="cuda")
+            cbfm.project(mesh, med, cbf, zs, prec)
+            items.append((mesh, med, cbf, zb))
+            singles.append(zs)
+        print("batched projection", prec, flush=True)
+        cbfm.project_batch(items, prec)
+        for (mesh, med, cbf, zb), zs, O in zip(items, singles, Os):
+            e = _rel(zb.cpu().numpy(), zs.cpu().numpy())
+            print("batch vs single", e)
+            assert e < tol
+            if prec == cbfm.FP64:
+                assert _rel(zb.cpu().numpy(), O["Zr"]) < 1e-10
