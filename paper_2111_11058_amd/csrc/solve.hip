@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(256) dots2_kernel(const TV* __restrict__ V, in
   }
 }
 
-// Per right-hand side (one wavefront each): gamma and a^H b, then column
+// Per right-hand side (one single-wavefront block each): gamma and a^H b, then column
 // jc = j - 1 made final (corrected for the new q_j unless correct == 0, the
 // end of a cycle, when it is taken as it stands) and reduced by the Givens
 // rotations; the new rotation updates g and the convergence test.
@@ -228,10 +228,10 @@ __global__ void __launch_bounds__(256) dots2_kernel(const TV* __restrict__ V, in
 // follow an affine recurrence, so each lane composes the maps of a
 // contiguous run of rotations, a scan over the lanes gives every run its
 // incoming a_i, and the runs are then replayed in parallel.
-__global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs,
+__global__ void __launch_bounds__(64) column_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs,
                                                      int correct, const int64_t* __restrict__ jp) {
   if (jp) j = *jp;
-  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t c = (int64_t)blockIdx.x;
   const int lane = threadIdx.x & 63;
   if (c >= nrhs || !st.active[c]) return;  // uniform over the wavefront
   double gam = 1.0;
@@ -369,12 +369,13 @@ __global__ void __launch_bounds__(256) coef_kernel(GmresState st, int64_t m, int
 }
 
 // The update pass: q_j <- (q_j - sum_{i<j} a_i q_i) / gamma and w <- w / gamma
-// - sum_{i<j} c_i q_i - c_j q_j(new).  A block of four wavefronts takes 64
+// - sum_{i<j} c_i q_i - c_j q_j(new).  A block of eight wavefronts takes 64
 // consecutive rows of one right-hand side, wavefront v summing over the
-// basis vectors i = v mod 4; wavefront 0 combines the partial sums in a
-// fixed order and stores the row block's sum of |w|^2 in part.
+// basis vectors i = v mod 8 (more loads in flight per row); wavefront 0
+// combines the partial sums in a fixed order and stores the row block's sum
+// of |w|^2 in part.
 template <typename TV>
-__global__ void __launch_bounds__(256) dcgs_update_kernel(TV* __restrict__ V, int64_t vstride,
+__global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, int64_t vstride,
                                                           TV* __restrict__ w, int64_t n, int64_t nrhs, int64_t j,
                                                           GmresState st, double* __restrict__ part,
                                                           const int64_t* __restrict__ jp) {
@@ -388,19 +389,19 @@ __global__ void __launch_bounds__(256) dcgs_update_kernel(TV* __restrict__ V, in
   double2 s1 = make_double2(0, 0), s2 = make_double2(0, 0);
   const TV* base = V + c * n + kk;
 #pragma unroll 4
-  for (int64_t i = wv; i < j; i += 4) {
+  for (int64_t i = wv; i < j; i += 8) {
     const double2 v = ld2(base + i * vstride);
     s1 = cadd(s1, cmul(st.d1[i * nrhs + c], v));
     s2 = cadd(s2, cmul(st.coef[i * nrhs + c], v));
   }
-  __shared__ double2 sh[3][64][2];
+  __shared__ double2 sh[7][64][2];
   if (wv > 0) {
     sh[wv - 1][lane][0] = s1;
     sh[wv - 1][lane][1] = s2;
   }
   __syncthreads();
   if (wv > 0) return;
-  for (int t = 0; t < 3; ++t) {
+  for (int t = 0; t < 7; ++t) {
     s1 = cadd(s1, sh[t][lane][0]);
     s2 = cadd(s2, sh[t][lane][1]);
   }
@@ -661,13 +662,13 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
       hipLaunchKernelGGL(dots2_kernel<TV>, dim3((unsigned)(((jg + 4) / 4 * nrhs + 3) / 4)), dim3(256), 0, q, V,
                          vstride, w, n, nrhs, j, gs, jp);
     }
-    hipLaunchKernelGGL(column_kernel, g4, dim3(256), 0, q, gs, mres, j, nrhs, 1, jp);
+    hipLaunchKernelGGL(column_kernel, dim3((unsigned)nrhs), dim3(64), 0, q, gs, mres, j, nrhs, 1, jp);
     hipLaunchKernelGGL(coef_kernel, dim3((unsigned)(jg + 1), (unsigned)((nrhs + 63) / 64)), dim3(256), 0, q, gs, mres,
                        j, nrhs, jp);
     {
       // work: bytes of q_0..q_{j-1} read, q_j and w read and written
       TimedLaunch tl(T_GMRES_UPDATE, q, vb * (double)(j + 4) * (double)nrhs * (double)n);
-      hipLaunchKernelGGL(dcgs_update_kernel<TV>, dim3((unsigned)np, (unsigned)nrhs), dim3(256), 0, q, V, vstride, w, n,
+      hipLaunchKernelGGL(dcgs_update_kernel<TV>, dim3((unsigned)np, (unsigned)nrhs), dim3(512), 0, q, V, vstride, w, n,
                          nrhs, j, gs, part, jp);
     }
     hipLaunchKernelGGL(normalize_kernel<TV>, grid2(n, nrhs), dim3(256), 0, q, w, V, vstride, n, part, np, gs, mres, j,
@@ -731,7 +732,7 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
     }
   }
   // the last column of the cycle, taken without the delayed correction
-  if (j > 0) hipLaunchKernelGGL(column_kernel, g4, dim3(256), 0, s, gs, mres, j, nrhs, 0, nullptr);
+  if (j > 0) hipLaunchKernelGGL(column_kernel, dim3((unsigned)nrhs), dim3(64), 0, s, gs, mres, j, nrhs, 0, nullptr);
   hipLaunchKernelGGL(backsolve_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, mres, nrhs);
   hipLaunchKernelGGL(x_update_kernel<TV>, grid2(n, nrhs), dim3(256), 0, s, gs, V, vstride, x, n, nrhs);
   CBFM_HIP(hipGetLastError());
