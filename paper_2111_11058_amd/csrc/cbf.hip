@@ -590,19 +590,42 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
       maxloc = std::max(maxloc, cs[b].tris.size());
     }
     CBFM_HIP(hipMemcpyAsync(idx.p, host.data(), ibytes, hipMemcpyHostToDevice, s));
-    Scratch local((size_t)27 * maxloc * maxloc * sizeof(double2), s);
-    for (int b = 0; b < nb; ++b) {
-      const int Nb = (int)cs[b].edges.size();
-      const int64_t nt_b = cs[b].tris.size();
-      fill_local(m, md, CBFM_FP64, CBFM_LAYOUT_OPS3, ptr[b].tris, nt_b, ptr[b].tris, nt_b, ptr[b].near,
-                 (int64_t)cs[b].near.size(), local.p, s);
-      assemble(m, CBFM_FP64, local.p, nt_b, nt_b, ptr[b].edges, Nb, ptr[b].edges, Nb, ptr[b].pos, ptr[b].pos, ops.p,
-               (int64_t)Nb * Nb, Nb, s);
-      double2* Zb = Zpad.as<double2>() + (size_t)b * n * n;
-      hipLaunchKernelGGL(pack_zmm_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, ops.as<double2>(), Nb, n, Zb);
-      hipLaunchKernelGGL(pack_v_kernel, dim3((n + 255) / 256, S), dim3(256), 0, s, vgen.as<double2>(), h.ne,
-                         ptr[b].edges, Nb, n, Vpad.as<double2>() + (size_t)b * n * S);
-      CBFM_HIP(hipGetLastError());
+    // the cells' self blocks: regular pairs of a group of cells in one
+    // persistent launch (groups of at most 1 GiB of triangle-local scratch),
+    // then per cell the near pairs, the assembly and the packing
+    const size_t group_bytes = std::max<size_t>((size_t)1 << 30, (size_t)27 * maxloc * maxloc * sizeof(double2));
+    for (int g0 = 0; g0 < nb;) {
+      int g1 = g0;
+      size_t bytes = 0;
+      std::vector<size_t> loff;
+      while (g1 < nb) {
+        const size_t cb = (size_t)27 * cs[g1].tris.size() * cs[g1].tris.size() * sizeof(double2);
+        if (g1 > g0 && bytes + cb > group_bytes) break;
+        loff.push_back(bytes);
+        bytes += cb;
+        ++g1;
+      }
+      Scratch local(bytes, s);
+      std::vector<FillBatchItem> items;
+      for (int b = g0; b < g1; ++b) {
+        const int64_t nt_b = cs[b].tris.size();
+        items.push_back({m, md, CBFM_LAYOUT_OPS3, ptr[b].tris, nt_b, ptr[b].tris, nt_b, local.as<char>() + loff[b - g0]});
+      }
+      fill_regular_batch(items, CBFM_FP64, s);
+      for (int b = g0; b < g1; ++b) {
+        const int Nb = (int)cs[b].edges.size();
+        const int64_t nt_b = cs[b].tris.size();
+        void* lb = local.as<char>() + loff[b - g0];
+        fill_near(m, md, CBFM_FP64, CBFM_LAYOUT_OPS3, ptr[b].near, (int64_t)cs[b].near.size(), nt_b, nt_b, lb, s);
+        assemble(m, CBFM_FP64, lb, nt_b, nt_b, ptr[b].edges, Nb, ptr[b].edges, Nb, ptr[b].pos, ptr[b].pos, ops.p,
+                 (int64_t)Nb * Nb, Nb, s);
+        double2* Zb = Zpad.as<double2>() + (size_t)b * n * n;
+        hipLaunchKernelGGL(pack_zmm_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, ops.as<double2>(), Nb, n, Zb);
+        hipLaunchKernelGGL(pack_v_kernel, dim3((n + 255) / 256, S), dim3(256), 0, s, vgen.as<double2>(), h.ne,
+                           ptr[b].edges, Nb, n, Vpad.as<double2>() + (size_t)b * n * S);
+        CBFM_HIP(hipGetLastError());
+      }
+      g0 = g1;
     }
     // LU solves Z_mm J_m = V_m
     Scratch piv((size_t)nb * n * sizeof(rocblas_int), s);

@@ -83,7 +83,9 @@ std::pair<size_t, size_t> estimate(int64_t nt, const std::vector<int32_t>& eb, i
   }
   const double nb = (double)N.size(), n = 2.0 * NL, z = 16.0;
   const double esz = precision == CBFM_FP64 ? 16.0 : 8.0;
-  const double build = nb * 4 * Nmax * Nmax * z + nb * 2 * Nmax * S * z + 27 * 4 * Nmax * Nmax * z +
+  const double cell_local = 27 * 4 * Nmax * Nmax * z;  // one cell's triangle-local self block
+  const double build = nb * 4 * Nmax * Nmax * z + nb * 2 * Nmax * S * z +
+                       std::max(cell_local, std::min(nb * cell_local, (double)(1 << 30))) +
                        6 * nb * S * Nmax * z + 2 * nb * Nmax * Nmax * z + 2 * S * ne * z;
   const double cell_panel = 27 * 2 * Nmax * (double)nt * esz + 3 * Nmax * ne * z + 4 * Nmax * NL * z;
   const double panel = std::max<double>(cell_panel, (double)panel_budget);
