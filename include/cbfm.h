@@ -111,7 +111,8 @@ int32_t cbfm_version(void);
  *   0 "fill_regular"  triangle pairs      1 "fill_near"    near pairs
  *   2 "assemble"      (none, 0)           3 "gemm"         real flops
  *   4 "gmres_dots"    bytes of basis vectors the Arnoldi dot pass reads
- *   5 "gmres_update"  bytes the Arnoldi update pass reads and writes
+ *   5 "gmres_update"  bytes the Arnoldi update pass reads and writes (basis,
+ *                     w and the Hessenberg entries of p = H a)
  * (the GMRES figures count every right-hand side of the batch, also those
  * already converged, which the kernels skip).
  * cbfm_timer_enable(mask) clears all timers and times the families whose

@@ -5,10 +5,10 @@
 //
 // A wavefront computes a 16 x 16 tile of C with v_mfma_f64_16x16x4_f64
 // (real): for each group of 16 k it does 4 x 4 MFMAs, the four real
-// products Ar*Br, -Ai*Bi, Ar*Bi, Ai*Br.  Lane L holds A[L % 16][k] and
-// B[k][L % 16] for k = k0 + 4 (L / 16) + t, t = 0..3 (any assignment of the
-// 16 k values to (slot, step) works as long as A and B agree), which lets
-// each lane load 4 consecutive elements when op(A) is not transposed.
+// products Ar*Br, -Ai*Bi, Ar*Bi, Ai*Br.  In step t = 0..3 lane L holds
+// A[L % 16][k] and B[k][L % 16] for k = k0 + 4 t + L / 16 (any assignment
+// of the 16 k values to (slot, step) works as long as A and B agree); the
+// operands reach that layout through LDS (see zgemm_batched_kernel).
 // The accumulator element r of lane L is C[4 r + L / 16][L % 16] (measured
 // on gfx950 with indexed operands: rows are interleaved across the four
 // lane groups).
@@ -23,17 +23,18 @@ namespace cbfm {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ double2 ld_op(const double2* __restrict__ X, int64_t ld, int op, int64_t i, int64_t k,
-                                         int64_t rows, int64_t cols) {
-  // element op(X)[i][k]; rows x cols is the shape of op(X); zero outside.
-  // Branch-free: an out-of-range lane loads element (0, 0) and discards it.
-  const bool ok = i < rows && k < cols;
-  const int64_t ii = ok ? i : 0, kk = ok ? k : 0;
-  const int64_t idx = (op == OP_N || op == OP_R) ? ii * ld + kk : kk * ld + ii;
-  double2 v = X[idx];
-  v.x = ok ? v.x : 0.0;
-  v.y = ok ? ((op == OP_C || op == OP_R) ? -v.y : v.y) : 0.0;
-  return v;
+// Loads through a global-address-space pointer: the compiler then emits
+// global instead of flat loads.  Flat loads also count as LDS operations, so
+// with them in flight every LDS wait of the K loop would wait for memory.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_global(const double2* p) {
+  const d2v w = *(const __attribute__((address_space(1))) d2v*)p;
+  return make_double2(w.x, w.y);
+}
+__device__ __forceinline__ float2 ld_global(const float2* p) {
+  const f2v w = *(const __attribute__((address_space(1))) f2v*)p;
+  return make_float2(w.x, w.y);
 }
 
 __device__ __forceinline__ int64_t uniform64(int64_t x) {
@@ -46,16 +47,24 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) {
 // SPLITK > 1: the SPLITK wavefronts of a block share one tile, each taking
 // every SPLITK-th group of 16 k, and the partial tiles are summed through
 // LDS (few, deep tiles: more loads in flight per tile).
+// Operands go through LDS: each wavefront loads its 16 x 16 sub-tiles of
+// op(A) and op(B) along the operand's contiguous dimension (16 lanes x 16 B
+// = 256 B per row or column of memory), writes them to its own LDS region
+// and reads them back in the matrix-core layout.  Loading the matrix-core
+// layout straight from memory spreads every load instruction over 32 cache
+// lines and runs at about half the speed on the shapes of this library.
 template <int SPLITK>
 __global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK)
     zgemm_batched_kernel(const GemmDesc* __restrict__ desc, int ndesc, int64_t total_tiles) {
+  constexpr int NW = SPLITK == 1 ? 4 : SPLITK;  // wavefronts per block
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // wave-uniform tile and descriptor (readfirstlane makes the K loop a scalar
   // loop: the accumulators then stay in the matrix-core registers across it)
   const int64_t tile = SPLITK == 1 ? (int64_t)blockIdx.x * 4 + wave : (int64_t)blockIdx.x;
+  __shared__ double2 stage[NW][2][16][17];  // [wave][A, B][row of op(A) / column of op(B)][k], padded
   __shared__ double red[SPLITK == 1 ? 1 : (SPLITK - 1) * 64 * 8];
-  if (tile >= total_tiles) return;  // uniform per block when SPLITK == 4
+  if (tile >= total_tiles) return;  // uniform per block when SPLITK > 1
   // descriptor holding this tile (tile_start ascending)
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
@@ -80,46 +89,80 @@ __global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK)
   const int64_t t = tile - d.tile_start;
   const int64_t ntn = (d.N + 15) / 16;
   const int64_t m0 = (t / ntn) * 16, n0 = (t % ntn) * 16;
-  const int64_t ia = m0 + (lane & 15);  // row of op(A) this lane loads
-  const int64_t jb = n0 + (lane & 15);  // column of op(B) this lane loads
-  const int slot = lane >> 4;
+  const int slot = lane >> 4, li = lane & 15;
+  // which operand dimension is contiguous in memory
+  const bool a_k = d.opA == OP_N || d.opA == OP_R;  // A[i][k] at i lda + k
+  const bool b_k = d.opB == OP_T || d.opB == OP_C;  // B[k][j] at j ldb + k
   dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-  const int64_t kstep = 16 * SPLITK;
-  int64_t k0 = SPLITK == 1 ? 0 : 16 * wave;
-  double2 a[4], b[4];
-  if (k0 < d.K) {
+  // this wavefront's groups of 16 k: k0 = 16 (wave + SPLITK g), g < ng
+  const int64_t kfirst = SPLITK == 1 ? 0 : 16 * wave, kstep = 16 * SPLITK;
+  const int64_t ng = kfirst < d.K ? (d.K - kfirst + kstep - 1) / kstep : 0;
+  double2 ga[4], gb[4];
+  // Lane (slot, li), load q: line 4 q + slot of the operand, element li
+  // along it, i.e. op(A)[m0 + ar][k + ak] and op(B)[k + bk][n0 + bc] for the
+  // group starting at k.  Each load walks its line of memory with a fixed
+  // element step per group; off* is its element offset and n* the number of
+  // groups it stays inside the matrix (loads past it read element 0 and
+  // are replaced by zero).
+  const int64_t sAk = a_k ? 1 : d.lda, sAi = a_k ? d.lda : 1;
+  const int64_t sBk = b_k ? 1 : d.ldb, sBj = b_k ? d.ldb : 1;
+  const double sgA = (d.opA == OP_C || d.opA == OP_R) ? -1.0 : 1.0;
+  const double sgB = (d.opB == OP_C || d.opB == OP_R) ? -1.0 : 1.0;
+  const int64_t stA = kstep * sAk, stB = kstep * sBk;
+  int ar[4], ak[4], bk[4], bc[4];
+  int64_t offA[4], offB[4], nA[4], nB[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int64_t k = k0 + 4 * slot + s;
-      a[s] = ld_op(d.A, d.lda, d.opA, ia, k, d.M, d.K);
-      b[s] = ld_op(d.B, d.ldb, d.opB, k, jb, d.K, d.N);
-    }
+  for (int q = 0; q < 4; ++q) {
+    const int r = 4 * q + slot;
+    ar[q] = a_k ? r : li;
+    ak[q] = a_k ? li : r;
+    bk[q] = b_k ? li : r;
+    bc[q] = b_k ? r : li;
+    const int64_t i = m0 + ar[q], ka = kfirst + ak[q], j = n0 + bc[q], kb = kfirst + bk[q];
+    nA[q] = i < d.M && ka < d.K ? (d.K - ka + kstep - 1) / kstep : 0;
+    nB[q] = j < d.N && kb < d.K ? (d.K - kb + kstep - 1) / kstep : 0;
+    offA[q] = nA[q] > 0 ? i * sAi + ka * sAk : 0;
+    offB[q] = nB[q] > 0 ? j * sBj + kb * sBk : 0;
   }
-  for (; k0 < d.K; k0 += kstep) {
-    // prefetch the next group while the matrix cores work on this one
-    double2 an[4], bn[4];
-    const int64_t k1 = k0 + kstep;
-    if (k1 < d.K) {
+  auto gload = [&](int64_t g) {  // group g; called for g = 0, 1, 2, ... in order
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int64_t k = k1 + 4 * slot + s;
-        an[s] = ld_op(d.A, d.lda, d.opA, ia, k, d.M, d.K);
-        bn[s] = ld_op(d.B, d.ldb, d.opB, k, jb, d.K, d.N);
-      }
+    for (int q = 0; q < 4; ++q) {
+      const bool oa = g < nA[q], ob = g < nB[q];
+      const double2 va = ld_global(d.A + (oa ? offA[q] : 0));
+      const double2 vb = ld_global(d.B + (ob ? offB[q] : 0));
+      ga[q] = oa ? make_double2(va.x, sgA * va.y) : make_double2(0, 0);
+      gb[q] = ob ? make_double2(vb.x, sgB * vb.y) : make_double2(0, 0);
+      offA[q] += stA;
+      offB[q] += stB;
     }
+  };
+  double2(*sa)[17] = stage[wave][0];
+  double2(*sb)[17] = stage[wave][1];
+  if (ng > 0) gload(0);
+  for (int64_t g = 0; g < ng; ++g) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sa[ar[q]][ak[q]] = ga[q];
+      sb[bc[q]][bk[q]] = gb[q];
+    }
+    // the next group's loads go out before the matrix cores take this one
+    if (g + 1 < ng) gload(g + 1);
+    // LDS operations of a wavefront complete in order: a compiler barrier
+    // keeps the reads after the writes (and the next writes after the reads)
+    __builtin_amdgcn_wave_barrier();
+    double2 a[4], b[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {  // step s takes k = 4 s + slot
+      a[s] = sa[li][4 * s + slot];
+      b[s] = sb[li][4 * s + slot];
+    }
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].x, b[s].x, cr, 0, 0, 0);
       cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[s].y, b[s].y, cr, 0, 0, 0);
       ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].x, b[s].y, ci, 0, 0, 0);
       ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].y, b[s].x, ci, 0, 0, 0);
-    }
-    if (k1 < d.K) {
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        a[s] = an[s];
-        b[s] = bn[s];
-      }
     }
   }
   if (SPLITK > 1) {
@@ -154,7 +197,7 @@ __global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK)
       double2 v = make_double2(d.alpha_re * xr - d.alpha_im * xi, d.alpha_re * xi + d.alpha_im * xr);
       double2* p = d.transC ? d.C + col * d.ldc + row : d.C + row * d.ldc + col;
       if (d.accumulate) {
-        const double2 o = *p;
+        const double2 o = ld_global(p);
         v.x += o.x;
         v.y += o.y;
       }
@@ -173,30 +216,16 @@ __global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK)
 typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ float2 ldx(const void* __restrict__ X, int is64, int64_t ld, int op, int64_t i, int64_t k,
-                                      int64_t rows, int64_t cols) {
-  const bool ok = i < rows && k < cols;
-  const int64_t ii = ok ? i : 0, kk = ok ? k : 0;
-  const int64_t idx = (op == OP_N || op == OP_R) ? ii * ld + kk : kk * ld + ii;
-  float2 v;
-  if (is64) {
-    const double2 d = static_cast<const double2*>(X)[idx];
-    v = make_float2((float)d.x, (float)d.y);
-  } else {
-    v = static_cast<const float2*>(X)[idx];
-  }
-  v.x = ok ? v.x : 0.0f;
-  v.y = ok ? ((op == OP_C || op == OP_R) ? -v.y : v.y) : 0.0f;
-  return v;
-}
-
 template <int MODE, int SPLITK>
 __global__ void __launch_bounds__(256) xgemm_batched_kernel(const GemmDescX* __restrict__ desc, int ndesc,
                                                             int64_t total_tiles) {
   constexpr int KG = MODE == XG_FP32 ? 16 : 32;  // k per step of a wavefront
+  constexpr int NW = SPLITK == 1 ? 4 : SPLITK;   // wavefronts per block
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t tile = SPLITK == 1 ? (int64_t)blockIdx.x * 4 + wave : (int64_t)blockIdx.x;
+  // operands staged through LDS as in zgemm_batched_kernel, as complex float
+  __shared__ float2 stage[NW][2][16][KG + 1];
   __shared__ float red[SPLITK == 1 ? 1 : (SPLITK - 1) * 64 * 8];
   if (tile >= total_tiles) return;  // uniform per block when SPLITK > 1
   int lo = 0, hi = ndesc - 1;
@@ -223,18 +252,92 @@ __global__ void __launch_bounds__(256) xgemm_batched_kernel(const GemmDescX* __r
   const int64_t t = tile - d.tile_start;
   const int64_t ntn = (d.N + 15) / 16;
   const int64_t m0 = (t / ntn) * 16, n0 = (t % ntn) * 16;
-  const int64_t ia = m0 + (lane & 15), jb = n0 + (lane & 15);
-  const int slot = lane >> 4;
+  const int slot = lane >> 4, li = lane & 15;
+  const bool a_k = d.opA == OP_N || d.opA == OP_R;  // A[i][k] at i lda + k
+  const bool b_k = d.opB == OP_T || d.opB == OP_C;  // B[k][j] at j ldb + k
+  // lane (slot, li), load q: line 4 q + slot of the operand, element li
+  // along it, walked with a fixed element step per step of k as in
+  // zgemm_batched_kernel; operands of complex double are rounded to float
+  const int64_t kfirst = SPLITK == 1 ? 0 : (int64_t)KG * wave, kstep = (int64_t)KG * SPLITK;
+  const int64_t sAk = a_k ? 1 : d.lda, sAi = a_k ? d.lda : 1;
+  const int64_t sBk = b_k ? 1 : d.ldb, sBj = b_k ? d.ldb : 1;
+  const float sgA = (d.opA == OP_C || d.opA == OP_R) ? -1.0f : 1.0f;
+  const float sgB = (d.opB == OP_C || d.opB == OP_R) ? -1.0f : 1.0f;
+  int ar[4], ak[4], bk[4], bc[4];
+  int64_t offA[4], offB[4], kA[4], kB[4];
+  bool rA[4], rB[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = 4 * q + slot;
+    ar[q] = a_k ? r : li;
+    ak[q] = a_k ? li : r;
+    bk[q] = b_k ? li : r;
+    bc[q] = b_k ? r : li;
+    const int64_t i = m0 + ar[q], j = n0 + bc[q];
+    rA[q] = i < d.M;
+    rB[q] = j < d.N;
+    kA[q] = kfirst + ak[q];
+    kB[q] = kfirst + bk[q];
+    offA[q] = rA[q] ? i * sAi + kA[q] * sAk : 0;
+    offB[q] = rB[q] ? j * sBj + kB[q] * sBk : 0;
+  }
+  float2(*sa)[KG + 1] = stage[wave][0];
+  float2(*sb)[KG + 1] = stage[wave][1];
   flt4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-  for (int64_t k0 = SPLITK == 1 ? 0 : (int64_t)KG * wave; k0 < d.K; k0 += (int64_t)KG * SPLITK) {
+  for (int64_t k0 = kfirst; k0 < d.K; k0 += kstep) {
+    // half h: k from k0 + 16 h
+#pragma unroll
+    for (int h = 0; h < KG / 16; ++h) {
+      float2 va[4], vb[4];
+      bool oa[4], ob[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        oa[q] = rA[q] && kA[q] + 16 * h < d.K;
+        ob[q] = rB[q] && kB[q] + 16 * h < d.K;
+      }
+      if (d.a64) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double2 w = ld_global(static_cast<const double2*>(d.A) + (oa[q] ? offA[q] + 16 * h * sAk : 0));
+          va[q] = make_float2((float)w.x, (float)w.y);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) va[q] = ld_global(static_cast<const float2*>(d.A) + (oa[q] ? offA[q] + 16 * h * sAk : 0));
+      }
+      if (d.b64) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double2 w = ld_global(static_cast<const double2*>(d.B) + (ob[q] ? offB[q] + 16 * h * sBk : 0));
+          vb[q] = make_float2((float)w.x, (float)w.y);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) vb[q] = ld_global(static_cast<const float2*>(d.B) + (ob[q] ? offB[q] + 16 * h * sBk : 0));
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        sa[ar[q]][16 * h + ak[q]] = oa[q] ? make_float2(va[q].x, sgA * va[q].y) : make_float2(0.0f, 0.0f);
+        sb[bc[q]][16 * h + bk[q]] = ob[q] ? make_float2(vb[q].x, sgB * vb[q].y) : make_float2(0.0f, 0.0f);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      kA[q] += kstep;
+      kB[q] += kstep;
+      offA[q] += kstep * sAk;
+      offB[q] += kstep * sBk;
+    }
+    // LDS operations of a wavefront complete in order
+    __builtin_amdgcn_wave_barrier();
     if constexpr (MODE == XG_FP32) {
       float2 a[4], b[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t k = k0 + 4 * slot + q;
-        a[q] = ldx(d.A, d.a64, d.lda, d.opA, ia, k, d.M, d.K);
-        b[q] = ldx(d.B, d.b64, d.ldb, d.opB, k, jb, d.K, d.N);
+      for (int q = 0; q < 4; ++q) {  // step q takes k = 4 q + slot
+        a[q] = sa[li][4 * q + slot];
+        b[q] = sb[li][4 * q + slot];
       }
+      __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q].x, b[q].x, cr, 0, 0, 0);
@@ -245,16 +348,16 @@ __global__ void __launch_bounds__(256) xgemm_batched_kernel(const GemmDescX* __r
     } else if constexpr (MODE == XG_BF16) {
       bf16x8 ar, ai, an, br, bi;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int64_t k = k0 + 8 * slot + q;
-        const float2 a = ldx(d.A, d.a64, d.lda, d.opA, ia, k, d.M, d.K);
-        const float2 b = ldx(d.B, d.b64, d.ldb, d.opB, k, jb, d.K, d.N);
+      for (int q = 0; q < 8; ++q) {  // slot takes k = 8 slot + q
+        const float2 a = sa[li][8 * slot + q];
+        const float2 b = sb[li][8 * slot + q];
         ar[q] = (__bf16)a.x;
         ai[q] = (__bf16)a.y;
         an[q] = (__bf16)(-a.y);
         br[q] = (__bf16)b.x;
         bi[q] = (__bf16)b.y;
       }
+      __builtin_amdgcn_wave_barrier();
       cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br, cr, 0, 0, 0);
       cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(an, bi, cr, 0, 0, 0);
       ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, bi, ci, 0, 0, 0);
@@ -265,9 +368,8 @@ __global__ void __launch_bounds__(256) xgemm_batched_kernel(const GemmDescX* __r
       bf16x8 arh, arl, aih, ail, anh, anl, brh, brl, bih, bil;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int64_t k = k0 + 8 * slot + q;
-        const float2 a = ldx(d.A, d.a64, d.lda, d.opA, ia, k, d.M, d.K);
-        const float2 b = ldx(d.B, d.b64, d.ldb, d.opB, k, jb, d.K, d.N);
+        const float2 a = sa[li][8 * slot + q];
+        const float2 b = sb[li][8 * slot + q];
         arh[q] = (__bf16)a.x;
         arl[q] = (__bf16)(a.x - (float)arh[q]);
         aih[q] = (__bf16)a.y;
@@ -279,6 +381,7 @@ __global__ void __launch_bounds__(256) xgemm_batched_kernel(const GemmDescX* __r
         bih[q] = (__bf16)b.y;
         bil[q] = (__bf16)(b.y - (float)bih[q]);
       }
+      __builtin_amdgcn_wave_barrier();
 #define XG_SPLIT3(acc, xh, xl, yh, yl)                                  \
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, yh, acc, 0, 0, 0); \
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yl, acc, 0, 0, 0); \
@@ -419,8 +522,7 @@ static int64_t number_tiles(const std::vector<GemmDesc>& in, std::vector<GemmDes
 }
 
 // Launch shapes: four tiles per block (one per wavefront), or one tile per
-// block with K split over 4 or 8 wavefronts (16 would need more registers
-// than a 1024-thread block leaves a lane).
+// block with K split over 4 or 8 wavefronts.
 enum { GV_TILE4 = 0, GV_SPLIT4, GV_SPLIT8, GV_COUNT };
 
 static void launch_variant(int v, const GemmDesc* dev, int count, int64_t tiles, hipStream_t s) {

@@ -90,7 +90,10 @@ std::pair<size_t, size_t> estimate(int64_t nt, const std::vector<int32_t>& eb, i
   const double cell_panel = 27 * 2 * Nmax * (double)nt * esz + 3 * Nmax * ne * z + 4 * Nmax * NL * z;
   const double panel = std::max<double>(cell_panel, (double)panel_budget);
   const double m = restart > 0 ? std::min<double>(restart, n) : std::min<double>(n, 1000);
-  const double solve = (m + 1) * nrhs * n * z + 2 * nrhs * (m + 1) * m * z + n * n * z + 8 * nrhs * std::max(n, 2 * ne) * z;
+  // Krylov basis, H and R, the operator, vectors, and the per-column
+  // arrays (g, cs, sn and the two dot products)
+  const double solve = (m + 1) * nrhs * n * z + 2 * nrhs * (m + 1) * m * z + n * n * z +
+                       8 * nrhs * std::max(n, 2 * ne) * z + 5 * nrhs * (m + 1) * z;
   const double resident = n * n * z + NL * NL * z + 2 * ne * S * z + 2048.0 * nt;
   return {(size_t)(std::max(build, panel) + solve), (size_t)resident};
 }

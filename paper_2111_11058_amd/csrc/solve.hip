@@ -136,7 +136,8 @@ __global__ void sub_from_kernel(const double2* __restrict__ b, double2* __restri
 //       H[l][j-1] += H[j][j-1] a_l (l < j),  H[j][j-1] *= gamma
 //   A q_j(new) = (w - A Q a) / gamma with A Q a = Q_{j+1} p, p = H a, so
 //   h_l = (b_l - p_l) / gamma (l < j), h_j = ((beta - a^H b) / gamma - p_j) / gamma
-//   w <- w / gamma - sum_{l <= j} c_l q_l,  c_l = p_l / gamma + h_l
+//   w <- w / gamma - sum_{l <= j} c_l q_l,  c_l = p_l / gamma + h_l, that is
+//   c_l = b_l / gamma (l < j) and c_j = (beta - a^H b) / gamma^2
 //   H[l][j] = h_l, H[j+1][j] = ||w||, q_{j+1} = w / ||w||
 // Column j-1 is final after the correction, so the Givens rotations and the
 // convergence test run one iteration behind the matrix-vector product.
@@ -148,7 +149,6 @@ struct GmresState {
   double2* g;       // [i * nrhs + c], i <= m
   double2* d1;      // [i * nrhs + c]: a_i, alpha at i = j
   double2* d2;      // [i * nrhs + c]: b_i, beta at i = j
-  double2* coef;    // [i * nrhs + c]: c_i
   double2* ab;      // [c] a^H b
   double* gam;      // [c] gamma
   double* nrm;      // [c]
@@ -176,17 +176,19 @@ __global__ void cycle_init_kernel(GmresState st, int64_t m, int64_t nrhs, double
   st.kc[c] = 0;
 }
 
-// d1[i] = q_i^H q_j and d2[i] = q_i^H w for i <= j: one wavefront per
-// right-hand side and run of four basis vectors, four per block.
+// d1[i] = q_i^H q_j and d2[i] = q_i^H w for i <= j: one block of four
+// wavefronts per right-hand side and run of four basis vectors; the
+// threads take every 256th row, the loads of all four vectors of a row go
+// out together, and the wavefronts are summed through LDS in a fixed order.
 template <typename TV>
 __global__ void __launch_bounds__(256) dots2_kernel(const TV* __restrict__ V, int64_t vstride,
                                                     const TV* __restrict__ w, int64_t n, int64_t nrhs, int64_t j,
                                                     GmresState st, const int64_t* __restrict__ jp) {
   if (jp) j = *jp;  // iteration index from the device (graph replays)
-  const int64_t id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
+  const int64_t id = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t runs = (j + 4) / 4;
-  if (id >= runs * nrhs) return;
+  if (id >= runs * nrhs) return;  // uniform over the block
   const int64_t run = id / nrhs, c = id % nrhs;
   if (!st.active[c]) return;
   const int64_t i0 = run * 4;
@@ -197,86 +199,163 @@ __global__ void __launch_bounds__(256) dots2_kernel(const TV* __restrict__ V, in
   double2 s1[4], s2[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) s1[t] = s2[t] = make_double2(0, 0);
-  for (int64_t k = lane; k < n; k += 64) {
+  for (int64_t k = threadIdx.x; k < n; k += 256) {
     const double2 x = ld2(qj + k), y = ld2(wc + k);
+    double2 v[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (t < cnt) {
-        const double2 v = ld2(qi + t * vstride + k);
-        s1[t] = cadd(s1[t], cconjmul(v, x));
-        s2[t] = cadd(s2[t], cconjmul(v, y));
-      }
+    for (int t = 0; t < 4; ++t) v[t] = ld2(qi + (t < cnt ? t : 0) * vstride + k);  // vectors past j: discarded
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      s1[t] = cadd(s1[t], cconjmul(v[t], x));
+      s2[t] = cadd(s2[t], cconjmul(v[t], y));
+    }
   }
+  __shared__ double sh[4][4][4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    if (t >= cnt) break;
-    const double2 r1 = make_double2(wave_sum(s1[t].x), wave_sum(s1[t].y));
-    const double2 r2 = make_double2(wave_sum(s2[t].x), wave_sum(s2[t].y));
+    const double r0 = wave_sum(s1[t].x), r1 = wave_sum(s1[t].y), r2 = wave_sum(s2[t].x), r3 = wave_sum(s2[t].y);
     if (lane == 0) {
-      st.d1[(i0 + t) * nrhs + c] = r1;
-      st.d2[(i0 + t) * nrhs + c] = r2;
+      sh[wv][t][0] = r0;
+      sh[wv][t][1] = r1;
+      sh[wv][t][2] = r2;
+      sh[wv][t][3] = r3;
     }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < cnt) {
+    double r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = (sh[0][t][q] + sh[1][t][q]) + (sh[2][t][q] + sh[3][t][q]);
+    st.d1[(i0 + t) * nrhs + c] = make_double2(r[0], r[1]);
+    st.d2[(i0 + t) * nrhs + c] = make_double2(r[2], r[3]);
   }
 }
 
-// Per right-hand side (one single-wavefront block each): gamma and a^H b, then column
-// jc = j - 1 made final (corrected for the new q_j unless correct == 0, the
-// end of a cycle, when it is taken as it stands) and reduced by the Givens
-// rotations; the new rotation updates g and the convergence test.
+// Per right-hand side (one block of 256 threads each): gamma and a^H b,
+// then column jc = j - 1 made final (corrected for the new q_j unless
+// correct == 0, the end of a cycle, when it is taken as it stands) and
+// reduced by the Givens rotations; the new rotation updates g and the
+// convergence test.
 // Rotation i maps (a_i, h_{i+1}) to (c_i a_i + s_i h_{i+1}, a_{i+1}) with
 // a_{i+1} = -conj(s_i) a_i + conj(c_i) h_{i+1}, a_0 = h_0: the carried a_i
-// follow an affine recurrence, so each lane composes the maps of a
-// contiguous run of rotations, a scan over the lanes gives every run its
-// incoming a_i, and the runs are then replayed in parallel.
-__global__ void __launch_bounds__(64) column_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs,
-                                                     int correct, const int64_t* __restrict__ jp) {
+// follow an affine recurrence, so each thread composes the maps of a
+// contiguous run of rotations (at most four up to 1024 columns), a scan over
+// the block gives every run its incoming a_i, and the runs are then replayed
+// in parallel.  The kernel is bound by memory latency: every load a thread
+// needs is issued before its first wait (up to 1024 columns), so it waits
+// on memory about once instead of once per step.
+__global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs,
+                                                      int correct, const int64_t* __restrict__ jp) {
   if (jp) j = *jp;
   const int64_t c = (int64_t)blockIdx.x;
-  const int lane = threadIdx.x & 63;
-  if (c >= nrhs || !st.active[c]) return;  // uniform over the wavefront
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  if (c >= nrhs) return;
+  const double2* d1 = st.d1;
+  const double2* d2 = st.d2;
+  __shared__ double red[4][3];
+  __shared__ double2 tot[4][2];     // (P, Q) of each wavefront's runs
+  __shared__ double2 incl[256][2];  // (P, Q) of runs 0..t
+  __shared__ double2 afin;
+  constexpr int KR = 4;
+  const int64_t jc = j > 0 ? j - 1 : 0, col = jc * (m + 1);
+  const int64_t K = (jc + 255) / 256;
+  const int64_t i0 = std::min<int64_t>(jc, t * K), i1 = std::min<int64_t>(jc, i0 + K);
+  // ---- loads (indices clamped to valid entries; the unused ones discarded)
+  double2 da[KR], db[KR];  // a_l, b_l of iteration j for l = t + 256 u
+#pragma unroll
+  for (int u = 0; u < KR; ++u) {
+    const int64_t l = t + 256 * u < j ? t + 256 * u : 0;
+    da[u] = d1[l * nrhs + c];
+    db[u] = d2[l * nrhs + c];
+  }
+  const double alpha = d1[j * nrhs + c].x;
+  const double2 hs = st.H[(col + jc + 1) * nrhs + c];  // H[jc+1][jc], real
+  const double2 h0 = st.H[col * nrhs + c], a00 = d1[c], gj = st.g[jc * nrhs + c];
+  const double tgt = st.tgt[c], bnorm = st.bnorm[c];
+  double2 sv[KR], cv[KR], bv[KR];  // first KR rotations of this thread's run
+#pragma unroll
+  for (int u = 0; u < KR; ++u) {
+    const int64_t i = std::max<int64_t>(0, std::min<int64_t>(i0 + u, i1 - 1));
+    sv[u] = st.sn[i * nrhs + c];
+    cv[u] = st.cs[i * nrhs + c];
+    bv[u] = st.H[(col + i + 1) * nrhs + c];
+    if (correct) bv[u] = cadd(bv[u], cmul(hs, d1[(i + 1) * nrhs + c]));
+  }
+  // (the loads above are issued for converged right-hand sides too: the
+  // test comes after them so that it does not delay them)
+  if (!st.active[c]) return;  // uniform over the block
+  // ---- gamma and a^H b
   double gam = 1.0;
   bool breakdown = false;
   if (correct) {
     double aa = 0;
     double2 ab = make_double2(0, 0);
-    for (int64_t l = lane; l < j; l += 64) {
-      const double2 a = st.d1[l * nrhs + c];
+#pragma unroll
+    for (int u = 0; u < KR; ++u)
+      if (t + 256 * u < j) {
+        aa += da[u].x * da[u].x + da[u].y * da[u].y;
+        ab = cadd(ab, cconjmul(da[u], db[u]));
+      }
+    for (int64_t l = t + 256 * KR; l < j; l += 256) {
+      const double2 a = d1[l * nrhs + c];
       aa += a.x * a.x + a.y * a.y;
-      ab = cadd(ab, cconjmul(a, st.d2[l * nrhs + c]));
+      ab = cadd(ab, cconjmul(a, d2[l * nrhs + c]));
     }
     aa = wave_sum(aa);
     ab = make_double2(wave_sum(ab.x), wave_sum(ab.y));
-    const double alpha = st.d1[j * nrhs + c].x;
+    if (lane == 0) {
+      red[wv][0] = aa;
+      red[wv][1] = ab.x;
+      red[wv][2] = ab.y;
+    }
+    __syncthreads();
+    aa = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+    ab = make_double2((red[0][1] + red[1][1]) + (red[2][1] + red[3][1]),
+                      (red[0][2] + red[1][2]) + (red[2][2] + red[3][2]));
     const double g2 = alpha - aa;
     // q_j nearly inside the span of q_0..q_{j-1}: the Krylov space is
     // (numerically) invariant, taken as a breakdown
     breakdown = !(g2 > 0.25 * alpha);
     gam = breakdown ? 1.0 : sqrt(g2);
-    if (lane == 0) {
+    if (t == 0) {
       st.gam[c] = gam;
       st.ab[c] = ab;
     }
   }
   if (j == 0) return;
-  const int64_t jc = j - 1, col = jc * (m + 1);
-  const double2 hs = st.H[(col + jc + 1) * nrhs + c];  // H[jc+1][jc], real
-  auto corrected = [&](int64_t l) {  // H[l][jc] for the final basis, l <= jc
-    double2 h = st.H[(col + l) * nrhs + c];
-    if (correct) h = cadd(h, cmul(hs, st.d1[l * nrhs + c]));
-    return h;
-  };
   const double hsub = correct ? (breakdown ? 0.0 : hs.x * gam) : hs.x;
-  const int64_t K = (jc + 63) / 64;
-  const int64_t i0 = std::min<int64_t>(jc, lane * K), i1 = std::min<int64_t>(jc, i0 + K);
+  // ---- compose the maps of this thread's run
   double2 P = make_double2(1, 0), Q = make_double2(0, 0);
-  for (int64_t i = i0; i < i1; ++i) {
-    const double2 sn = st.sn[i * nrhs + c], cs = st.cs[i * nrhs + c], b = corrected(i + 1);
-    if (correct) st.H[(col + i + 1) * nrhs + c] = b;
-    const double2 Pi = make_double2(-sn.x, sn.y);  // -conj(s_i)
-    Q = cadd(cmul(Pi, Q), cmul(make_double2(cs.x, -cs.y), b));
-    P = cmul(Pi, P);
+  for (int64_t ib = i0; ib < i1; ib += KR) {
+    double2 s2[KR], c2[KR], b2[KR];
+#pragma unroll
+    for (int u = 0; u < KR; ++u) {
+      s2[u] = sv[u];
+      c2[u] = cv[u];
+      b2[u] = bv[u];
+    }
+    if (ib != i0) {  // past the first KR rotations (more than 1024 columns)
+#pragma unroll
+      for (int u = 0; u < KR; ++u) {
+        const int64_t i = std::min<int64_t>(ib + u, i1 - 1);
+        s2[u] = st.sn[i * nrhs + c];
+        c2[u] = st.cs[i * nrhs + c];
+        b2[u] = st.H[(col + i + 1) * nrhs + c];
+        if (correct) b2[u] = cadd(b2[u], cmul(hs, d1[(i + 1) * nrhs + c]));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < KR; ++u) {
+      if (ib + u >= i1) break;
+      if (correct) st.H[(col + ib + u + 1) * nrhs + c] = b2[u];
+      const double2 Pi = make_double2(-s2[u].x, s2[u].y);  // -conj(s_i)
+      Q = cadd(cmul(Pi, Q), cmul(make_double2(c2[u].x, -c2[u].y), b2[u]));
+      P = cmul(Pi, P);
+    }
   }
-  // inclusive scan: after it, (P, Q) maps a_0 to the carry leaving this run
+  // ---- inclusive scan over the wavefront, then over the wavefronts in
+  // order: afterwards (P, Q) maps a_0 to the carry leaving run t
   for (int off = 1; off < 64; off <<= 1) {
     const double2 Po = make_double2(__shfl_up(P.x, off, 64), __shfl_up(P.y, off, 64));
     const double2 Qo = make_double2(__shfl_up(Q.x, off, 64), __shfl_up(Q.y, off, 64));
@@ -285,19 +364,53 @@ __global__ void __launch_bounds__(64) column_kernel(GmresState st, int64_t m, in
       P = cmul(P, Po);
     }
   }
-  const double2 a0 = corrected(0);
-  const double2 Pe = make_double2(__shfl_up(P.x, 1, 64), __shfl_up(P.y, 1, 64));
-  const double2 Qe = make_double2(__shfl_up(Q.x, 1, 64), __shfl_up(Q.y, 1, 64));
-  double2 a = lane == 0 ? a0 : cadd(cmul(Pe, a0), Qe);
-  for (int64_t i = i0; i < i1; ++i) {
-    // this lane stored the final H[i+1][jc] above (or it was final already)
-    const double2 sn = st.sn[i * nrhs + c], cs = st.cs[i * nrhs + c], b = st.H[(col + i + 1) * nrhs + c];
-    st.R[(col + i) * nrhs + c] = cadd(cmul(cs, a), cmul(sn, b));
-    a = cadd(cmul(make_double2(-sn.x, sn.y), a), cmul(make_double2(cs.x, -cs.y), b));
+  if (lane == 63) {
+    tot[wv][0] = P;
+    tot[wv][1] = Q;
   }
-  const int last = jc == 0 ? 0 : (int)((jc - 1) / K);  // lane that ends with a_jc
-  a = make_double2(__shfl(a.x, last, 64), __shfl(a.y, last, 64));
-  if (lane != 0) return;
+  __syncthreads();
+  double2 Pp = make_double2(1, 0), Qp = make_double2(0, 0);
+  for (int v = 0; v < wv; ++v) {
+    Qp = cadd(cmul(tot[v][0], Qp), tot[v][1]);
+    Pp = cmul(tot[v][0], Pp);
+  }
+  Q = cadd(cmul(P, Qp), Q);
+  P = cmul(P, Pp);
+  incl[t][0] = P;
+  incl[t][1] = Q;
+  __syncthreads();
+  const double2 a0 = correct ? cadd(h0, cmul(hs, a00)) : h0;
+  double2 a = t == 0 ? a0 : cadd(cmul(incl[t - 1][0], a0), incl[t - 1][1]);
+  // ---- replay the run: rotated column entries
+  for (int64_t ib = i0; ib < i1; ib += KR) {
+    double2 s2[KR], c2[KR], b2[KR];
+#pragma unroll
+    for (int u = 0; u < KR; ++u) {
+      s2[u] = sv[u];
+      c2[u] = cv[u];
+      b2[u] = bv[u];
+    }
+    if (ib != i0) {  // this thread stored the final H[i+1][jc] above
+#pragma unroll
+      for (int u = 0; u < KR; ++u) {
+        const int64_t i = std::min<int64_t>(ib + u, i1 - 1);
+        s2[u] = st.sn[i * nrhs + c];
+        c2[u] = st.cs[i * nrhs + c];
+        b2[u] = st.H[(col + i + 1) * nrhs + c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < KR; ++u) {
+      if (ib + u >= i1) break;
+      st.R[(col + ib + u) * nrhs + c] = cadd(cmul(c2[u], a), cmul(s2[u], b2[u]));
+      a = cadd(cmul(make_double2(-s2[u].x, s2[u].y), a), cmul(make_double2(c2[u].x, -c2[u].y), b2[u]));
+    }
+  }
+  const int last = jc == 0 ? 0 : (int)((jc - 1) / K);  // thread that ends with a_jc
+  if (t == last) afin = a;
+  __syncthreads();
+  if (t != 0) return;
+  a = afin;
   if (correct) {
     st.H[col * nrhs + c] = a0;
     st.H[(col + jc + 1) * nrhs + c] = make_double2(hsub, 0);
@@ -311,116 +424,146 @@ __global__ void __launch_bounds__(64) column_kernel(GmresState st, int64_t m, in
   st.cs[jc * nrhs + c] = cc;
   st.sn[jc * nrhs + c] = ss;
   st.R[(col + jc) * nrhs + c] = make_double2(den, 0);
-  const double2 gj = st.g[jc * nrhs + c];
   // g[jc+1] = -conj(s) g[jc];  g[jc] = c g[jc]
   const double2 gn = make_double2(-(ss.x * gj.x + ss.y * gj.y), -(ss.x * gj.y - ss.y * gj.x));
   st.g[(jc + 1) * nrhs + c] = gn;
   st.g[jc * nrhs + c] = cmul(cc, gj);
   const double ra = sqrt(gn.x * gn.x + gn.y * gn.y);
-  st.res[c] = ra / st.bnorm[c];
+  st.res[c] = ra / bnorm;
   st.kc[c] = (int32_t)(jc + 1);
   st.its[c] += 1;
-  if (ra <= st.tgt[c] || den == 0.0 || breakdown) st.active[c] = 0;
+  if (ra <= tgt || den == 0.0 || breakdown) st.active[c] = 0;
 }
 
-// Column j of H and the update coefficients: p_l = sum_i H[l][i] a_i over
-// the final columns i < j (upper Hessenberg: i >= l - 1), then h_l and c_l
-// as above.  One block per row l; lane = right-hand side (64 per block
-// row), the four wavefronts take every fourth column and are summed through
-// LDS in a fixed order.
-__global__ void __launch_bounds__(256) coef_kernel(GmresState st, int64_t m, int64_t j, int64_t nrhs,
-                                                   const int64_t* __restrict__ jp) {
-  if (jp) j = *jp;
-  const int64_t l = blockIdx.x;
-  if (l > j) return;  // graph replays launch the grid of the longest column
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t c = (int64_t)blockIdx.y * 64 + lane;
-  const bool on = c < nrhs && st.active[c];
-  double2 p0 = make_double2(0, 0), p1 = p0;
-  if (on) {
-    const int64_t lo = l > 0 ? l - 1 : 0;
-    const double2* Hl = st.H + l * nrhs + c;  // column i at Hl[i * (m + 1) * nrhs]
-    const double2* a = st.d1 + c;
-    const int64_t cs = (m + 1) * nrhs;
-    int64_t i = lo + wv;
-    for (; i + 4 < j; i += 8) {
-      p0 = cadd(p0, cmul(Hl[i * cs], a[i * nrhs]));
-      p1 = cadd(p1, cmul(Hl[(i + 4) * cs], a[(i + 4) * nrhs]));
-    }
-    if (i < j) p0 = cadd(p0, cmul(Hl[i * cs], a[i * nrhs]));
-    p0 = cadd(p0, p1);
-  }
-  __shared__ double2 sh[3][64];
-  if (wv > 0) sh[wv - 1][lane] = p0;
-  __syncthreads();
-  if (wv > 0 || !on) return;
-  const double2 p = cadd(cadd(p0, sh[0][lane]), cadd(sh[1][lane], sh[2][lane]));
-  const double ig = 1.0 / st.gam[c];
-  const double2 b = st.d2[l * nrhs + c];
-  double2 h;
-  if (l < j) {
-    h = cscale(make_double2(b.x - p.x, b.y - p.y), ig);
-  } else {
-    const double2 ab = st.ab[c];
-    h = cscale(make_double2((b.x - ab.x) * ig - p.x, (b.y - ab.y) * ig - p.y), ig);
-  }
-  st.H[(j * (m + 1) + l) * nrhs + c] = h;
-  st.coef[l * nrhs + c] = cadd(cscale(p, ig), h);
-}
-
-// The update pass: q_j <- (q_j - sum_{i<j} a_i q_i) / gamma and w <- w / gamma
-// - sum_{i<j} c_i q_i - c_j q_j(new).  A block of eight wavefronts takes 64
-// consecutive rows of one right-hand side, wavefront v summing over the
-// basis vectors i = v mod 8 (more loads in flight per row); wavefront 0
-// combines the partial sums in a fixed order and stores the row block's sum
-// of |w|^2 in part.
+// The update pass, with column j of H computed beside it.  With
+// p_l = sum_i H[l][i] a_i over the final columns i < j (upper Hessenberg:
+// i >= l - 1), h_l = (b_l - p_l) / gamma, h_j = ((beta - a^H b) / gamma -
+// p_j) / gamma and c_l = p_l / gamma + h_l, the update coefficients reduce
+// to c_l = b_l / gamma (l < j) and c_j = (beta - a^H b) / gamma^2, so the
+// update does not wait for p:
+//   q_j <- (q_j - sum_{i<j} a_i q_i) / gamma
+//   w   <- (w - sum_{i<j} b_i q_i) / gamma - c_j q_j(new)
+// Blocks [0, nhb): row l = b / g of column j (g = blocks of 64 right-hand
+// sides, lane = right-hand side); the eight wavefronts take every eighth
+// column, four columns in flight each, and are summed in a fixed order.
+// They come first in the grid so that their chains of loads start early
+// and overlap the streaming of the update blocks.  (Cutting the rows into
+// parts summed later, or running them on a second stream, measured slower.)
+// Blocks [nhb, nhb + np nrhs): eight wavefronts take 128 consecutive rows
+// (two per lane) of one right-hand side, wavefront v summing over the basis
+// vectors i = v mod 8; wavefront 0 combines the partial sums in a fixed
+// order and stores the row block's sum of |w|^2 in part.
 template <typename TV>
 __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, int64_t vstride,
-                                                          TV* __restrict__ w, int64_t n, int64_t nrhs, int64_t j,
-                                                          GmresState st, double* __restrict__ part,
-                                                          const int64_t* __restrict__ jp) {
+                                                          TV* __restrict__ w, int64_t n, int64_t nrhs, int64_t m,
+                                                          int64_t j, int64_t nhb, int np, GmresState st,
+                                                          double* __restrict__ part, const int64_t* __restrict__ jp) {
   if (jp) j = *jp;
-  const int64_t c = blockIdx.y;
-  if (!st.active[c]) return;  // uniform over the block
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t k = (int64_t)blockIdx.x * 64 + lane;
-  const bool in = k < n;
-  const int64_t kk = in ? k : 0;
-  double2 s1 = make_double2(0, 0), s2 = make_double2(0, 0);
-  const TV* base = V + c * n + kk;
-#pragma unroll 4
-  for (int64_t i = wv; i < j; i += 8) {
-    const double2 v = ld2(base + i * vstride);
-    s1 = cadd(s1, cmul(st.d1[i * nrhs + c], v));
-    s2 = cadd(s2, cmul(st.coef[i * nrhs + c], v));
+  const int64_t blk = blockIdx.x;
+  if (blk < nhb) {
+    __shared__ double2 shp[7][64];
+    const int64_t ng = (nrhs + 63) / 64;
+    const int64_t l = blk / ng, c = (blk % ng) * 64 + lane;
+    if (l > j) return;  // graph replays launch the rows of the longest column
+    const bool on = c < nrhs && st.active[c];
+    const int64_t cc = on ? c : 0;  // idle lanes read valid entries and discard them
+    const int64_t lo = l > 0 ? l - 1 : 0;
+    const int64_t cs = (m + 1) * nrhs;
+    const double2* Hl = st.H + l * nrhs + cc;  // column i at Hl[i * cs]
+    const double2* a = st.d1 + cc;
+    double2 acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = make_double2(0, 0);
+    for (int64_t ib = lo + wv; ib < j; ib += 32) {
+      double2 hv[4], av[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = ib + 8 * u < j ? ib + 8 * u : ib;
+        hv[u] = Hl[i * cs];
+        av[u] = a[i * nrhs];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = ib + 8 * u < j ? cadd(acc[u], cmul(hv[u], av[u])) : acc[u];
+    }
+    double2 p = cadd(cadd(acc[0], acc[1]), cadd(acc[2], acc[3]));
+    if (wv > 0) shp[wv - 1][lane] = p;
+    __syncthreads();
+    if (wv > 0 || !on) return;
+    for (int v = 0; v < 7; ++v) p = cadd(p, shp[v][lane]);
+    const double ig = 1.0 / st.gam[c];
+    const double2 b = st.d2[l * nrhs + c];
+    double2 h;
+    if (l < j) {
+      h = cscale(make_double2(b.x - p.x, b.y - p.y), ig);
+    } else {
+      const double2 ab = st.ab[c];
+      h = cscale(make_double2((b.x - ab.x) * ig - p.x, (b.y - ab.y) * ig - p.y), ig);
+    }
+    st.H[(j * (m + 1) + l) * nrhs + c] = h;
+    return;
   }
-  __shared__ double2 sh[7][64][2];
+  constexpr int RPL = 2;  // rows per lane
+  const int64_t u0 = blk - nhb;
+  const int64_t c = u0 / np, rb = u0 % np;
+  if (c >= nrhs || !st.active[c]) return;  // uniform over the block
+  const double2* d1 = st.d1;
+  const double2* d2 = st.d2;
+  double2 s1[RPL], s2[RPL];
+  int64_t kk[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    s1[r] = s2[r] = make_double2(0, 0);
+    const int64_t k = (rb * RPL + r) * 64 + lane;
+    kk[r] = k < n ? k : 0;  // rows past n: a valid row, discarded
+  }
+  const TV* base = V + c * n;
+  for (int64_t i = wv; i < j; i += 8) {
+    const double2 a = d1[i * nrhs + c], b = d2[i * nrhs + c];
+    double2 v[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) v[r] = ld2(base + i * vstride + kk[r]);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      s1[r] = cadd(s1[r], cmul(a, v[r]));
+      s2[r] = cadd(s2[r], cmul(b, v[r]));
+    }
+  }
+  __shared__ double2 sh[7][RPL][64][2];
   if (wv > 0) {
-    sh[wv - 1][lane][0] = s1;
-    sh[wv - 1][lane][1] = s2;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      sh[wv - 1][r][lane][0] = s1[r];
+      sh[wv - 1][r][lane][1] = s2[r];
+    }
   }
   __syncthreads();
   if (wv > 0) return;
-  for (int t = 0; t < 7; ++t) {
-    s1 = cadd(s1, sh[t][lane][0]);
-    s2 = cadd(s2, sh[t][lane][1]);
-  }
   const double ig = 1.0 / st.gam[c];
+  const double2 beta = d2[j * nrhs + c], ab = st.ab[c];
+  const double2 cj = cscale(make_double2(beta.x - ab.x, beta.y - ab.y), ig * ig);
   double q2 = 0;
-  if (in) {
-    TV* qj = V + j * vstride + c * n + k;
-    const double2 qo = ld2(qj);
-    const double2 qn = cscale(make_double2(qo.x - s1.x, qo.y - s1.y), ig);
-    st2(qj, qn);
-    const double2 wo = ld2(w + c * n + k);
-    const double2 cj = st.coef[j * nrhs + c];
-    const double2 t = cadd(s2, cmul(cj, qn));
-    const double2 wn = make_double2(wo.x * ig - t.x, wo.y * ig - t.y);
-    st2(w + c * n + k, wn);
-    q2 = wn.x * wn.x + wn.y * wn.y;
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    for (int t = 0; t < 7; ++t) {
+      s1[r] = cadd(s1[r], sh[t][r][lane][0]);
+      s2[r] = cadd(s2[r], sh[t][r][lane][1]);
+    }
+    const int64_t k = (rb * RPL + r) * 64 + lane;
+    if (k < n) {
+      TV* qj = V + j * vstride + c * n + k;
+      const double2 qo = ld2(qj);
+      const double2 qn = cscale(make_double2(qo.x - s1[r].x, qo.y - s1[r].y), ig);
+      st2(qj, qn);
+      const double2 wo = ld2(w + c * n + k);
+      const double2 t = cmul(cj, qn);
+      const double2 wn = make_double2((wo.x - s2[r].x) * ig - t.x, (wo.y - s2[r].y) * ig - t.y);
+      st2(w + c * n + k, wn);
+      q2 += wn.x * wn.x + wn.y * wn.y;
+    }
   }
   q2 = wave_sum(q2);
-  if (lane == 0) part[c * gridDim.x + blockIdx.x] = q2;
+  if (lane == 0) part[c * np + rb] = q2;
 }
 
 // nu = sqrt(sum of the np partial sums of |w|^2); H[j+1][j] = nu and
@@ -641,9 +784,9 @@ template <typename TV, typename MV>
 static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev, TV* V, TV* w, int64_t vstride,
                       int64_t n, int64_t nrhs, int64_t mres, int64_t max_iter, int64_t& total, GmresState gs,
                       double* part, int np, PinnedFlags& flags, double2* x, hipStream_t s) {
-  const dim3 g4((unsigned)((nrhs + 3) / 4));
   const double vb = (double)sizeof(TV);
   const int check_every = 4;
+  const int64_t ng = (nrhs + 63) / 64;
   auto all_done = [&](const int32_t* a) { return std::none_of(a, a + nrhs, [](int32_t v) { return v != 0; }); };
   // enqueue iteration j (jp == nullptr) or the iteration *jp (graph capture)
   auto iteration = [&](int64_t j, const int64_t* jp, hipStream_t q) {
@@ -659,17 +802,18 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
     {
       // work: bytes of q_0..q_j and w for every right-hand side
       TimedLaunch tl(T_GMRES_DOTS, q, vb * (double)(j + 2) * (double)nrhs * (double)n);
-      hipLaunchKernelGGL(dots2_kernel<TV>, dim3((unsigned)(((jg + 4) / 4 * nrhs + 3) / 4)), dim3(256), 0, q, V,
-                         vstride, w, n, nrhs, j, gs, jp);
+      hipLaunchKernelGGL(dots2_kernel<TV>, dim3((unsigned)((jg + 4) / 4 * nrhs)), dim3(256), 0, q, V, vstride, w, n,
+                         nrhs, j, gs, jp);
     }
-    hipLaunchKernelGGL(column_kernel, dim3((unsigned)nrhs), dim3(64), 0, q, gs, mres, j, nrhs, 1, jp);
-    hipLaunchKernelGGL(coef_kernel, dim3((unsigned)(jg + 1), (unsigned)((nrhs + 63) / 64)), dim3(256), 0, q, gs, mres,
-                       j, nrhs, jp);
+    hipLaunchKernelGGL(column_kernel, dim3((unsigned)nrhs), dim3(256), 0, q, gs, mres, j, nrhs, 1, jp);
     {
-      // work: bytes of q_0..q_{j-1} read, q_j and w read and written
-      TimedLaunch tl(T_GMRES_UPDATE, q, vb * (double)(j + 4) * (double)nrhs * (double)n);
-      hipLaunchKernelGGL(dcgs_update_kernel<TV>, dim3((unsigned)np, (unsigned)nrhs), dim3(512), 0, q, V, vstride, w, n,
-                         nrhs, j, gs, part, jp);
+      // work: bytes of q_0..q_{j-1} read, q_j and w read and written, and
+      // the j + j (j + 1) / 2 entries of H read for p = H a
+      const double hr = (double)j + 0.5 * (double)j * (double)(j + 1);
+      TimedLaunch tl(T_GMRES_UPDATE, q, (vb * (double)(j + 4) * (double)n + 16.0 * hr) * (double)nrhs);
+      const int64_t nhb = (jg + 1) * ng;
+      hipLaunchKernelGGL(dcgs_update_kernel<TV>, dim3((unsigned)(nhb + (int64_t)np * nrhs)), dim3(512), 0, q, V,
+                         vstride, w, n, nrhs, mres, j, nhb, np, gs, part, jp);
     }
     hipLaunchKernelGGL(normalize_kernel<TV>, grid2(n, nrhs), dim3(256), 0, q, w, V, vstride, n, part, np, gs, mres, j,
                        nrhs, jp);
@@ -732,7 +876,7 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
     }
   }
   // the last column of the cycle, taken without the delayed correction
-  if (j > 0) hipLaunchKernelGGL(column_kernel, dim3((unsigned)nrhs), dim3(64), 0, s, gs, mres, j, nrhs, 0, nullptr);
+  if (j > 0) hipLaunchKernelGGL(column_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, mres, j, nrhs, 0, nullptr);
   hipLaunchKernelGGL(backsolve_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, mres, nrhs);
   hipLaunchKernelGGL(x_update_kernel<TV>, grid2(n, nrhs), dim3(256), 0, s, gs, V, vstride, x, n, nrhs);
   CBFM_HIP(hipGetLastError());
@@ -805,10 +949,10 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
     Scratch V((mres + 1) * nrhs * n * vsz, s);
     Scratch x(nrhs * n * sizeof(double2), s), u(nrhs * n * vsz, s), r64(f32 ? nrhs * n * sizeof(double2) : 0, s);
     Scratch A32(f32 ? n * n * sizeof(float2) : 0, s);
-    const int np = (int)((n + 63) / 64);  // partial norm sums per vector (64-row blocks)
+    const int np = (int)((n + 127) / 128);  // partial norm sums per vector (128-row blocks)
     const size_t hbytes = (size_t)nrhs * (mres + 1) * mres * sizeof(double2), cbytes = (size_t)nrhs * (mres + 1) * sizeof(double2);
     Scratch Rs(hbytes, s), Hs(hbytes, s), csb(nrhs * mres * sizeof(double2), s), snb(nrhs * mres * sizeof(double2), s),
-        gb(cbytes, s), d1b(cbytes, s), d2b(cbytes, s), coefb(cbytes, s), abb(nrhs * sizeof(double2), s),
+        gb(cbytes, s), d1b(cbytes, s), d2b(cbytes, s), abb(nrhs * sizeof(double2), s),
         dbl(5 * nrhs * sizeof(double), s), ints(3 * nrhs * sizeof(int32_t), s), part(nrhs * np * sizeof(double), s);
     GmresState gs{Rs.as<double2>(),
                   Hs.as<double2>(),
@@ -817,7 +961,6 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
                   gb.as<double2>(),
                   d1b.as<double2>(),
                   d2b.as<double2>(),
-                  coefb.as<double2>(),
                   abb.as<double2>(),
                   dbl.as<double>(),
                   dbl.as<double>() + nrhs,
