@@ -144,8 +144,8 @@ __global__ void sub_from_kernel(const double2* __restrict__ b, double2* __restri
 struct GmresState {
   double2* R;       // rotated Hessenberg (upper triangular): column j, row i at [(j * (m + 1) + i) * nrhs + c]
   double2* H;       // Hessenberg matrix of the final basis, same layout
-  double2* cs;      // [i * nrhs + c]
-  double2* sn;      // [i * nrhs + c]
+  double2* cs;      // [c * m + i]
+  double2* sn;      // [c * m + i]
   double2* g;       // [i * nrhs + c], i <= m
   double2* d1;      // [i * nrhs + c]: a_i, alpha at i = j
   double2* d2;      // [i * nrhs + c]: b_i, beta at i = j
@@ -158,6 +158,12 @@ struct GmresState {
   int32_t* active;  // [c]
   int32_t* kc;      // [c] Krylov dimension reached in this cycle
   int32_t* its;     // [c] iterations spent (all cycles)
+  // per right-hand side contiguous copies for the column step (one block
+  // per right-hand side reads them along i): [c * (m + 1) + i]
+  double2* d1t;     // a_i, alpha
+  double2* d2t;     // b_i, beta
+  double2* hc;      // the newest column of H (rows 0..j+1)
+  int64_t ms;       // m + 1
 };
 
 // Start a cycle: g = beta e1, active = beta/bnorm > tol, kc = 0; the cycle
@@ -227,8 +233,11 @@ __global__ void __launch_bounds__(256) dots2_kernel(const TV* __restrict__ V, in
     double r[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) r[q] = (sh[0][t][q] + sh[1][t][q]) + (sh[2][t][q] + sh[3][t][q]);
-    st.d1[(i0 + t) * nrhs + c] = make_double2(r[0], r[1]);
-    st.d2[(i0 + t) * nrhs + c] = make_double2(r[2], r[3]);
+    const double2 v1 = make_double2(r[0], r[1]), v2 = make_double2(r[2], r[3]);
+    st.d1[(i0 + t) * nrhs + c] = v1;
+    st.d2[(i0 + t) * nrhs + c] = v2;
+    st.d1t[c * st.ms + i0 + t] = v1;
+    st.d2t[c * st.ms + i0 + t] = v2;
   }
 }
 
@@ -251,8 +260,12 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
   const int64_t c = (int64_t)blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   if (c >= nrhs) return;
-  const double2* d1 = st.d1;
-  const double2* d2 = st.d2;
+  // this right-hand side's contiguous vectors
+  const double2* d1 = st.d1t + c * st.ms;
+  const double2* d2 = st.d2t + c * st.ms;
+  const double2* hcol = st.hc + c * st.ms;
+  double2* sn = st.sn + c * m;
+  double2* cs = st.cs + c * m;
   __shared__ double red[4][3];
   __shared__ double2 tot[4][2];     // (P, Q) of each wavefront's runs
   __shared__ double2 incl[256][2];  // (P, Q) of runs 0..t
@@ -266,21 +279,21 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
 #pragma unroll
   for (int u = 0; u < KR; ++u) {
     const int64_t l = t + 256 * u < j ? t + 256 * u : 0;
-    da[u] = d1[l * nrhs + c];
-    db[u] = d2[l * nrhs + c];
+    da[u] = d1[l];
+    db[u] = d2[l];
   }
-  const double alpha = d1[j * nrhs + c].x;
-  const double2 hs = st.H[(col + jc + 1) * nrhs + c];  // H[jc+1][jc], real
-  const double2 h0 = st.H[col * nrhs + c], a00 = d1[c], gj = st.g[jc * nrhs + c];
+  const double alpha = d1[j].x;
+  const double2 hs = hcol[jc + 1];  // H[jc+1][jc], real
+  const double2 h0 = hcol[0], a00 = d1[0], gj = st.g[jc * nrhs + c];
   const double tgt = st.tgt[c], bnorm = st.bnorm[c];
   double2 sv[KR], cv[KR], bv[KR];  // first KR rotations of this thread's run
 #pragma unroll
   for (int u = 0; u < KR; ++u) {
     const int64_t i = std::max<int64_t>(0, std::min<int64_t>(i0 + u, i1 - 1));
-    sv[u] = st.sn[i * nrhs + c];
-    cv[u] = st.cs[i * nrhs + c];
-    bv[u] = st.H[(col + i + 1) * nrhs + c];
-    if (correct) bv[u] = cadd(bv[u], cmul(hs, d1[(i + 1) * nrhs + c]));
+    sv[u] = sn[i];
+    cv[u] = cs[i];
+    bv[u] = hcol[i + 1];
+    if (correct) bv[u] = cadd(bv[u], cmul(hs, d1[i + 1]));
   }
   // (the loads above are issued for converged right-hand sides too: the
   // test comes after them so that it does not delay them)
@@ -298,9 +311,9 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
         ab = cadd(ab, cconjmul(da[u], db[u]));
       }
     for (int64_t l = t + 256 * KR; l < j; l += 256) {
-      const double2 a = d1[l * nrhs + c];
+      const double2 a = d1[l];
       aa += a.x * a.x + a.y * a.y;
-      ab = cadd(ab, cconjmul(a, d2[l * nrhs + c]));
+      ab = cadd(ab, cconjmul(a, d2[l]));
     }
     aa = wave_sum(aa);
     ab = make_double2(wave_sum(ab.x), wave_sum(ab.y));
@@ -339,10 +352,10 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
 #pragma unroll
       for (int u = 0; u < KR; ++u) {
         const int64_t i = std::min<int64_t>(ib + u, i1 - 1);
-        s2[u] = st.sn[i * nrhs + c];
-        c2[u] = st.cs[i * nrhs + c];
-        b2[u] = st.H[(col + i + 1) * nrhs + c];
-        if (correct) b2[u] = cadd(b2[u], cmul(hs, d1[(i + 1) * nrhs + c]));
+        s2[u] = sn[i];
+        c2[u] = cs[i];
+        b2[u] = hcol[i + 1];
+        if (correct) b2[u] = cadd(b2[u], cmul(hs, d1[i + 1]));
       }
     }
 #pragma unroll
@@ -394,8 +407,8 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
 #pragma unroll
       for (int u = 0; u < KR; ++u) {
         const int64_t i = std::min<int64_t>(ib + u, i1 - 1);
-        s2[u] = st.sn[i * nrhs + c];
-        c2[u] = st.cs[i * nrhs + c];
+        s2[u] = sn[i];
+        c2[u] = cs[i];
         b2[u] = st.H[(col + i + 1) * nrhs + c];
       }
     }
@@ -421,8 +434,8 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
     cc = make_double2(a.x / den, -a.y / den);  // conj(a)/den
     ss = make_double2(hsub / den, 0.0);        // conj(h)/den, h real
   }
-  st.cs[jc * nrhs + c] = cc;
-  st.sn[jc * nrhs + c] = ss;
+  cs[jc] = cc;
+  sn[jc] = ss;
   st.R[(col + jc) * nrhs + c] = make_double2(den, 0);
   // g[jc+1] = -conj(s) g[jc];  g[jc] = c g[jc]
   const double2 gn = make_double2(-(ss.x * gj.x + ss.y * gj.y), -(ss.x * gj.y - ss.y * gj.x));
@@ -501,6 +514,7 @@ __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, in
       h = cscale(make_double2((b.x - ab.x) * ig - p.x, (b.y - ab.y) * ig - p.y), ig);
     }
     st.H[(j * (m + 1) + l) * nrhs + c] = h;
+    st.hc[c * st.ms + l] = h;
     return;
   }
   constexpr int RPL = 2;  // rows per lane
@@ -579,7 +593,10 @@ __global__ void normalize_kernel(const TV* __restrict__ w, TV* __restrict__ V, i
   double q = 0;
   for (int b = 0; b < np; ++b) q += part[c * np + b];
   const double nu = sqrt(q);
-  if (blockIdx.x == 0 && threadIdx.x == 0) st.H[(j * (m + 1) + j + 1) * nrhs + c] = make_double2(nu, 0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st.H[(j * (m + 1) + j + 1) * nrhs + c] = make_double2(nu, 0);
+    st.hc[c * st.ms + j + 1] = make_double2(nu, 0);
+  }
   if (k >= n) return;
   const double sc = nu > 0 ? 1.0 / nu : 0.0;
   st2(out + c * n + k, cscale(ld2(w + c * n + k), sc));
@@ -595,45 +612,104 @@ __global__ void point_matvec_kernel(D* __restrict__ desc, const TV* V, int64_t v
   if (threadIdx.x == 0 && blockIdx.x == 0) desc->B = V + (*jp) * vstride;
 }
 
-// y = H^{-1} g over the first kc[c] rows (upper triangular), in place in g;
-// one block per right-hand side, column-oriented back substitution.
+// y = R^{-1} g over the first kc[c] rows (R upper triangular), in place in
+// g; one block per right-hand side.  Blocked back substitution: the
+// triangle of the lowest 32 unsolved rows is copied to LDS and solved by one
+// wavefront (the solved value broadcast across the lanes), then every row
+// above it is updated by the block with all 32 loads of a row issued
+// together, so the block waits on memory about twice per 32 rows instead of
+// once per row.
 __global__ void __launch_bounds__(256) backsolve_kernel(GmresState st, int64_t m, int64_t nrhs) {
+  constexpr int BS = 32;
   const int64_t c = blockIdx.x;
   const int64_t k = st.kc[c];
-  __shared__ double2 yi;
-  for (int64_t i = k - 1; i >= 0; --i) {
-    if (threadIdx.x == 0) {
-      const double2 s = st.g[i * nrhs + c], d = st.R[(i * (m + 1) + i) * nrhs + c];
-      const double dd = d.x * d.x + d.y * d.y;
-      yi = dd > 0 ? make_double2((s.x * d.x + s.y * d.y) / dd, (s.y * d.x - s.x * d.y) / dd) : make_double2(0, 0);
-      st.g[i * nrhs + c] = yi;
+  __shared__ double2 T[BS][BS + 1];  // T[r][q] = R[b0 + r][b0 + q], q >= r
+  __shared__ double2 yb[BS];         // solved values of the block
+  const int tid = threadIdx.x;
+  for (int64_t b1 = k; b1 > 0; b1 -= BS) {
+    const int64_t b0 = b1 > BS ? b1 - BS : 0;
+    const int nb = (int)(b1 - b0);
+    for (int e = tid; e < nb * nb; e += 256) {
+      const int r = e / nb, q = e % nb;
+      if (q >= r) T[r][q] = st.R[((b0 + q) * (m + 1) + b0 + r) * nrhs + c];
     }
     __syncthreads();
-    const double2 y = yi;
-    for (int64_t t = threadIdx.x; t < i; t += blockDim.x) {
-      const double2 h = st.R[(i * (m + 1) + t) * nrhs + c];
+    if (tid < 64) {
+      const int lane = tid;
+      double2 yl = lane < nb ? st.g[(b0 + lane) * nrhs + c] : make_double2(0, 0);
+      for (int q = nb - 1; q >= 0; --q) {
+        if (lane == q) {
+          const double2 d = T[q][q];
+          const double dd = d.x * d.x + d.y * d.y;
+          yl = dd > 0 ? make_double2((yl.x * d.x + yl.y * d.y) / dd, (yl.y * d.x - yl.x * d.y) / dd)
+                      : make_double2(0, 0);
+        }
+        const double2 yq = make_double2(__shfl(yl.x, q, 64), __shfl(yl.y, q, 64));
+        if (lane < q) yl = make_double2(yl.x - (T[lane][q].x * yq.x - T[lane][q].y * yq.y),
+                                        yl.y - (T[lane][q].x * yq.y + T[lane][q].y * yq.x));
+      }
+      if (lane < nb) {
+        yb[lane] = yl;
+        st.g[(b0 + lane) * nrhs + c] = yl;
+      }
+    }
+    __syncthreads();
+    for (int64_t t = tid; t < b0; t += 256) {
+      double2 h[BS];
+#pragma unroll
+      for (int q = 0; q < BS; ++q) h[q] = st.R[((b0 + (q < nb ? q : 0)) * (m + 1) + t) * nrhs + c];
+      double2 acc = make_double2(0, 0);
+#pragma unroll
+      for (int q = 0; q < BS; ++q)
+        if (q < nb) acc = cadd(acc, cmul(h[q], yb[q]));
       double2* gt = st.g + t * nrhs + c;
-      gt->x -= h.x * y.x - h.y * y.y;
-      gt->y -= h.x * y.y + h.y * y.x;
+      *gt = make_double2(gt->x - acc.x, gt->y - acc.y);
     }
     __syncthreads();
   }
 }
 
-// x[c] += sum_{i < kc[c]} y[i][c] V[i][c]
+// x[c] += sum_{i < kc[c]} y[i][c] V[i][c]: a block of eight wavefronts takes
+// 128 consecutive rows (two per lane) of one right-hand side, wavefront v
+// summing over the basis vectors i = v mod 8, combined in a fixed order.
 template <typename TV>
-__global__ void x_update_kernel(GmresState st, const TV* __restrict__ V, int64_t vstride, double2* __restrict__ x,
-                                int64_t n, int64_t nrhs) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
-  if (k >= n) return;
+__global__ void __launch_bounds__(512) x_update_kernel(GmresState st, const TV* __restrict__ V, int64_t vstride,
+                                                       double2* __restrict__ x, int64_t n, int64_t nrhs, int np) {
+  constexpr int RPL = 2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t c = blockIdx.x / np, rb = blockIdx.x % np;
+  if (c >= nrhs) return;
   const int64_t kc = st.kc[c];
-  double2 acc = x[c * n + k];
-  for (int64_t i = 0; i < kc; ++i) {
-    const double2 a = st.g[i * nrhs + c], v = ld2(V + i * vstride + c * n + k);
-    acc.x += a.x * v.x - a.y * v.y;
-    acc.y += a.x * v.y + a.y * v.x;
+  double2 acc[RPL];
+  int64_t kk[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    acc[r] = make_double2(0, 0);
+    const int64_t k = (rb * RPL + r) * 64 + lane;
+    kk[r] = k < n ? k : 0;  // rows past n: a valid row, discarded
   }
-  x[c * n + k] = acc;
+  const TV* base = V + c * n;
+  for (int64_t i = wv; i < kc; i += 8) {
+    const double2 a = st.g[i * nrhs + c];
+    double2 v[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) v[r] = ld2(base + i * vstride + kk[r]);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) acc[r] = cadd(acc[r], cmul(a, v[r]));
+  }
+  __shared__ double2 sh[7][RPL][64];
+  if (wv > 0) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) sh[wv - 1][r][lane] = acc[r];
+  }
+  __syncthreads();
+  if (wv > 0) return;
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    for (int t = 0; t < 7; ++t) acc[r] = cadd(acc[r], sh[t][r][lane]);
+    const int64_t k = (rb * RPL + r) * 64 + lane;
+    if (k < n) x[c * n + k] = cadd(x[c * n + k], acc[r]);
+  }
 }
 
 // ------------------------------------------------------------- far field
@@ -878,7 +954,8 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
   // the last column of the cycle, taken without the delayed correction
   if (j > 0) hipLaunchKernelGGL(column_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, mres, j, nrhs, 0, nullptr);
   hipLaunchKernelGGL(backsolve_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, mres, nrhs);
-  hipLaunchKernelGGL(x_update_kernel<TV>, grid2(n, nrhs), dim3(256), 0, s, gs, V, vstride, x, n, nrhs);
+  hipLaunchKernelGGL(x_update_kernel<TV>, dim3((unsigned)((int64_t)np * nrhs)), dim3(512), 0, s, gs, V, vstride, x, n, nrhs,
+                     np);
   CBFM_HIP(hipGetLastError());
 }
 
@@ -952,8 +1029,9 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
     const int np = (int)((n + 127) / 128);  // partial norm sums per vector (128-row blocks)
     const size_t hbytes = (size_t)nrhs * (mres + 1) * mres * sizeof(double2), cbytes = (size_t)nrhs * (mres + 1) * sizeof(double2);
     Scratch Rs(hbytes, s), Hs(hbytes, s), csb(nrhs * mres * sizeof(double2), s), snb(nrhs * mres * sizeof(double2), s),
-        gb(cbytes, s), d1b(cbytes, s), d2b(cbytes, s), abb(nrhs * sizeof(double2), s),
-        dbl(5 * nrhs * sizeof(double), s), ints(3 * nrhs * sizeof(int32_t), s), part(nrhs * np * sizeof(double), s);
+        gb(cbytes, s), d1b(cbytes, s), d2b(cbytes, s), d1t(cbytes, s), d2t(cbytes, s), hcb(cbytes, s),
+        abb(nrhs * sizeof(double2), s), dbl(5 * nrhs * sizeof(double), s), ints(3 * nrhs * sizeof(int32_t), s),
+        part(nrhs * np * sizeof(double), s);
     GmresState gs{Rs.as<double2>(),
                   Hs.as<double2>(),
                   csb.as<double2>(),
@@ -969,7 +1047,11 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
                   dbl.as<double>() + 4 * nrhs,
                   ints.as<int32_t>(),
                   ints.as<int32_t>() + nrhs,
-                  ints.as<int32_t>() + 2 * nrhs};
+                  ints.as<int32_t>() + 2 * nrhs,
+                  d1t.as<double2>(),
+                  d2t.as<double2>(),
+                  hcb.as<double2>(),
+                  mres + 1};
     const int64_t vstride = nrhs * n;
     const dim3 g1((unsigned)((nrhs + 63) / 64)), b1(64);
     CBFM_HIP(hipMemsetAsync(x.p, 0, nrhs * n * sizeof(double2), s));
