@@ -143,7 +143,7 @@ __global__ void sub_from_kernel(const double2* __restrict__ b, double2* __restri
 // convergence test run one iteration behind the matrix-vector product.
 struct GmresState {
   double2* R;       // rotated Hessenberg (upper triangular): column j, row i at [(j * (m + 1) + i) * nrhs + c]
-  double2* H;       // Hessenberg matrix of the final basis, same layout
+  double2* H;       // Hessenberg matrix of the final basis, by rows: row l, column i at [(l * m + i) * nrhs + c]
   double2* cs;      // [c * m + i]
   double2* sn;      // [c * m + i]
   double2* g;       // [i * nrhs + c], i <= m
@@ -361,7 +361,7 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
 #pragma unroll
     for (int u = 0; u < KR; ++u) {
       if (ib + u >= i1) break;
-      if (correct) st.H[(col + ib + u + 1) * nrhs + c] = b2[u];
+      if (correct) st.H[((ib + u + 1) * m + jc) * nrhs + c] = b2[u];
       const double2 Pi = make_double2(-s2[u].x, s2[u].y);  // -conj(s_i)
       Q = cadd(cmul(Pi, Q), cmul(make_double2(c2[u].x, -c2[u].y), b2[u]));
       P = cmul(Pi, P);
@@ -409,7 +409,7 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
         const int64_t i = std::min<int64_t>(ib + u, i1 - 1);
         s2[u] = sn[i];
         c2[u] = cs[i];
-        b2[u] = st.H[(col + i + 1) * nrhs + c];
+        b2[u] = st.H[((i + 1) * m + jc) * nrhs + c];
       }
     }
 #pragma unroll
@@ -425,8 +425,8 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
   if (t != 0) return;
   a = afin;
   if (correct) {
-    st.H[col * nrhs + c] = a0;
-    st.H[(col + jc + 1) * nrhs + c] = make_double2(hsub, 0);
+    st.H[jc * nrhs + c] = a0;
+    st.H[((jc + 1) * m + jc) * nrhs + c] = make_double2(hsub, 0);
   }
   const double den = sqrt(a.x * a.x + a.y * a.y + hsub * hsub);
   double2 cc = make_double2(1, 0), ss = make_double2(0, 0);
@@ -456,34 +456,35 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
 // update does not wait for p:
 //   q_j <- (q_j - sum_{i<j} a_i q_i) / gamma
 //   w   <- (w - sum_{i<j} b_i q_i) / gamma - c_j q_j(new)
-// Blocks [0, nhb): row l = b / g of column j (g = blocks of 64 right-hand
-// sides, lane = right-hand side); the eight wavefronts take every eighth
-// column, four columns in flight each, and are summed in a fixed order.
-// They come first in the grid so that their chains of loads start early
-// and overlap the streaming of the update blocks.  (Cutting the rows into
-// parts summed later, or running them on a second stream, measured slower.)
-// Blocks [nhb, nhb + np nrhs): eight wavefronts take 128 consecutive rows
-// (two per lane) of one right-hand side, wavefront v summing over the basis
-// vectors i = v mod 8; wavefront 0 combines the partial sums in a fixed
-// order and stores the row block's sum of |w|^2 in part.
+// Blocks [0, np nrhs): eight wavefronts take 128 consecutive rows (two per
+// lane) of one right-hand side, wavefront v summing over the basis vectors
+// i = v mod 8; wavefront 0 combines the partial sums in a fixed order and
+// stores the row block's sum of |w|^2 in part.
+// Blocks from np nrhs on: row l of column j, for 64 right-hand
+// sides (lane = right-hand side); the eight wavefronts take every eighth
+// column of the row (contiguous in H), four columns in flight each, summed
+// in a fixed order.  These latency-bound blocks come last, where they fill
+// the tail of the streaming; placed first they held CUs the update blocks
+// needed, and cutting the rows into parts or running them as a separate
+// launch or stream measured slower too.
 template <typename TV>
 __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, int64_t vstride,
                                                           TV* __restrict__ w, int64_t n, int64_t nrhs, int64_t m,
-                                                          int64_t j, int64_t nhb, int np, GmresState st,
+                                                          int64_t j, int np, GmresState st,
                                                           double* __restrict__ part, const int64_t* __restrict__ jp) {
   if (jp) j = *jp;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t blk = blockIdx.x;
-  if (blk < nhb) {
+  const int64_t nub = (int64_t)np * nrhs;  // update blocks
+  if ((int64_t)blockIdx.x >= nub) {
     __shared__ double2 shp[7][64];
+    const int64_t hb = (int64_t)blockIdx.x - nub;
     const int64_t ng = (nrhs + 63) / 64;
-    const int64_t l = blk / ng, c = (blk % ng) * 64 + lane;
+    const int64_t l = hb / ng, c = (hb % ng) * 64 + lane;
     if (l > j) return;  // graph replays launch the rows of the longest column
     const bool on = c < nrhs && st.active[c];
     const int64_t cc = on ? c : 0;  // idle lanes read valid entries and discard them
     const int64_t lo = l > 0 ? l - 1 : 0;
-    const int64_t cs = (m + 1) * nrhs;
-    const double2* Hl = st.H + l * nrhs + cc;  // column i at Hl[i * cs]
+    const double2* Hl = st.H + l * m * nrhs + cc;  // column i at Hl[i * nrhs]: the row is contiguous
     const double2* a = st.d1 + cc;
     double2 acc[4];
 #pragma unroll
@@ -493,7 +494,7 @@ __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, in
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int64_t i = ib + 8 * u < j ? ib + 8 * u : ib;
-        hv[u] = Hl[i * cs];
+        hv[u] = Hl[i * nrhs];
         av[u] = a[i * nrhs];
       }
 #pragma unroll
@@ -513,13 +514,12 @@ __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, in
       const double2 ab = st.ab[c];
       h = cscale(make_double2((b.x - ab.x) * ig - p.x, (b.y - ab.y) * ig - p.y), ig);
     }
-    st.H[(j * (m + 1) + l) * nrhs + c] = h;
+    st.H[(l * m + j) * nrhs + c] = h;
     st.hc[c * st.ms + l] = h;
     return;
   }
   constexpr int RPL = 2;  // rows per lane
-  const int64_t u0 = blk - nhb;
-  const int64_t c = u0 / np, rb = u0 % np;
+  const int64_t c = (int64_t)blockIdx.x / np, rb = (int64_t)blockIdx.x % np;
   if (c >= nrhs || !st.active[c]) return;  // uniform over the block
   const double2* d1 = st.d1;
   const double2* d2 = st.d2;
@@ -594,7 +594,7 @@ __global__ void normalize_kernel(const TV* __restrict__ w, TV* __restrict__ V, i
   for (int b = 0; b < np; ++b) q += part[c * np + b];
   const double nu = sqrt(q);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st.H[(j * (m + 1) + j + 1) * nrhs + c] = make_double2(nu, 0);
+    st.H[((j + 1) * m + j) * nrhs + c] = make_double2(nu, 0);
     st.hc[c * st.ms + j + 1] = make_double2(nu, 0);
   }
   if (k >= n) return;
@@ -889,7 +889,7 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
       TimedLaunch tl(T_GMRES_UPDATE, q, (vb * (double)(j + 4) * (double)n + 16.0 * hr) * (double)nrhs);
       const int64_t nhb = (jg + 1) * ng;
       hipLaunchKernelGGL(dcgs_update_kernel<TV>, dim3((unsigned)(nhb + (int64_t)np * nrhs)), dim3(512), 0, q, V,
-                         vstride, w, n, nrhs, mres, j, nhb, np, gs, part, jp);
+                         vstride, w, n, nrhs, mres, j, np, gs, part, jp);
     }
     hipLaunchKernelGGL(normalize_kernel<TV>, grid2(n, nrhs), dim3(256), 0, q, w, V, vstride, n, part, np, gs, mres, j,
                        nrhs, jp);
