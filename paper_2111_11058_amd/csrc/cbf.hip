@@ -24,6 +24,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -511,21 +512,36 @@ struct CellSupport {
   std::vector<NearPair> near;
 };
 
-static CellSupport support(const MeshHost& h, const std::vector<int32_t>& edges) {
-  CellSupport cs;
-  cs.edges = edges;
-  cs.pos.assign(h.nt, -1);
-  for (int32_t e : edges) {
-    cs.pos[h.tplus[e]] = 0;
-    cs.pos[h.tminus[e]] = 0;
-  }
-  for (int64_t t = 0; t < h.nt; ++t)
-    if (cs.pos[t] == 0) {
-      cs.pos[t] = (int32_t)cs.tris.size();
-      cs.tris.push_back((int32_t)t);
+// The supports of all cells, with each cell's near pairs in the order of
+// the mesh's near list (one pass over the list: a triangle lies in the
+// supports of at most the three cells of its edges).
+static std::vector<CellSupport> supports(const MeshHost& h, int nb) {
+  std::vector<CellSupport> cs(nb);
+  std::vector<std::array<int32_t, 3>> tcell(h.nt, {-1, -1, -1});
+  for (int b = 0; b < nb; ++b) {
+    CellSupport& c = cs[b];
+    c.edges = cell_edges(h, b);
+    c.pos.assign(h.nt, -1);
+    for (int32_t e : c.edges) {
+      c.pos[h.tplus[e]] = 0;
+      c.pos[h.tminus[e]] = 0;
     }
+    for (int64_t t = 0; t < h.nt; ++t)
+      if (c.pos[t] == 0) {
+        c.pos[t] = (int32_t)c.tris.size();
+        c.tris.push_back((int32_t)t);
+        for (int32_t& x : tcell[t])
+          if (x < 0) {
+            x = b;
+            break;
+          }
+      }
+  }
   for (const NearPair& q : h.near)
-    if (cs.pos[q.p] >= 0 && cs.pos[q.q] >= 0) cs.near.push_back({q.p, q.q, cs.pos[q.p], cs.pos[q.q], q.coplanar, 0});
+    for (int32_t b : tcell[q.p]) {
+      if (b < 0) break;
+      if (cs[b].pos[q.q] >= 0) cs[b].near.push_back({q.p, q.q, cs[b].pos[q.p], cs[b].pos[q.q], q.coplanar, 0});
+    }
   return cs;
 }
 
@@ -561,12 +577,10 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
     Scratch Vpad((size_t)nb * n * S * sizeof(double2), s);
     Scratch ops((size_t)3 * Nmax * Nmax * sizeof(double2), s);
     // index staging for every cell, uploaded once
-    std::vector<CellSupport> cs(nb);
+    std::vector<CellSupport> cs = supports(h, nb);
     size_t ibytes = 0;
-    for (int b = 0; b < nb; ++b) {
-      cs[b] = support(h, cell_edges(h, b));
+    for (int b = 0; b < nb; ++b)
       ibytes += 4 * (cs[b].tris.size() + cs[b].pos.size() + cs[b].edges.size()) + sizeof(NearPair) * cs[b].near.size();
-    }
     std::vector<char> host(ibytes);
     Scratch idx(ibytes, s);
     size_t o = 0;
