@@ -81,12 +81,24 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
-// Stream-ordered scratch released at scope exit (hipFreeAsync on the stream).
+// Large scratch blocks (scratch.cpp): device allocations kept after use and
+// handed out again, ordered on the stream by an event.
+constexpr size_t kBigScratch = (size_t)256 << 20;
+void* big_alloc(size_t bytes, hipStream_t s);
+void big_release(void* p, size_t bytes, hipStream_t s);
+
+// Stream-ordered scratch released at scope exit: hipMallocAsync /
+// hipFreeAsync on the stream, or the large-block cache from kBigScratch up.
 struct Scratch {
   void* p = nullptr;
   hipStream_t s = nullptr;
-  Scratch(size_t bytes, hipStream_t stream) : s(stream) {
+  size_t n = 0;
+  Scratch(size_t bytes, hipStream_t stream) : s(stream), n(bytes) {
     if (bytes == 0) return;
+    if (bytes >= kBigScratch) {
+      p = big_alloc(bytes, stream);
+      return;
+    }
     hipError_t e = hipMallocAsync(&p, bytes, stream);
     if (e != hipSuccess) {
       p = nullptr;
@@ -94,7 +106,11 @@ struct Scratch {
     }
   }
   ~Scratch() {
-    if (p) (void)hipFreeAsync(p, s);
+    if (!p) return;
+    if (n >= kBigScratch)
+      big_release(p, n, s);
+    else
+      (void)hipFreeAsync(p, s);
   }
   Scratch(const Scratch&) = delete;
   Scratch& operator=(const Scratch&) = delete;
