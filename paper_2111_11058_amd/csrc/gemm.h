@@ -125,7 +125,7 @@ class GemmPlan {
  private:
   bool tune_;
   Scratch dev_;
-  std::vector<int64_t> first_, count_, tiles_;
+  std::vector<int64_t> first_, count_, tiles_, m_, n_;
   std::vector<double> flops_;
   std::vector<int> variant_;
 };

@@ -37,6 +37,11 @@ __device__ __forceinline__ float2 ld_global(const float2* p) {
   return make_float2(w.x, w.y);
 }
 
+// Loads outside an operand read this zero instead (the address is chosen,
+// never the value: a value chosen after an unconditional load lets the
+// compiler move the load under a branch, one wait per load).
+__device__ double2 g_zero2[1];
+
 __device__ __forceinline__ int64_t uniform64(int64_t x) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(x & 0xffffffff));
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
@@ -47,23 +52,29 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) {
 // SPLITK > 1: the SPLITK wavefronts of a block share one tile, each taking
 // every SPLITK-th group of 16 k, and the partial tiles are summed through
 // LDS (few, deep tiles: more loads in flight per tile).
+// CT > 1 (one descriptor only): a tile is 16 rows by CT adjacent 16-column
+// blocks, so a wavefront loads each part of op(A) once for CT column blocks
+// (a matrix times a few vectors reads the matrix once instead of CT times).
 // Operands go through LDS: each wavefront loads its 16 x 16 sub-tiles of
 // op(A) and op(B) along the operand's contiguous dimension (16 lanes x 16 B
 // = 256 B per row or column of memory), writes them to its own LDS region
 // and reads them back in the matrix-core layout.  Loading the matrix-core
 // layout straight from memory spreads every load instruction over 32 cache
 // lines and runs at about half the speed on the shapes of this library.
-template <int SPLITK>
+template <int SPLITK, int CT>
 __global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK)
     zgemm_batched_kernel(const GemmDesc* __restrict__ desc, int ndesc, int64_t total_tiles) {
   constexpr int NW = SPLITK == 1 ? 4 : SPLITK;  // wavefronts per block
+  constexpr int NS = 1 + CT;                    // staged sub-tiles per wavefront: A, then B per column block
+  constexpr int STAGE = NW * NS * 16 * 17;      // double2, rows padded to 17
+  constexpr int RED = SPLITK == 1 ? 0 : (SPLITK - 1) * 64 * 4 * CT;  // double2: partial tiles of waves 1..
+  // the split-K partial sums reuse the staging memory after the K loop
+  __shared__ double2 smem[STAGE > RED ? STAGE : RED];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // wave-uniform tile and descriptor (readfirstlane makes the K loop a scalar
   // loop: the accumulators then stay in the matrix-core registers across it)
   const int64_t tile = SPLITK == 1 ? (int64_t)blockIdx.x * 4 + wave : (int64_t)blockIdx.x;
-  __shared__ double2 stage[NW][2][16][17];  // [wave][A, B][row of op(A) / column of op(B)][k], padded
-  __shared__ double red[SPLITK == 1 ? 1 : (SPLITK - 1) * 64 * 8];
   if (tile >= total_tiles) return;  // uniform per block when SPLITK > 1
   // descriptor holding this tile (tile_start ascending)
   int lo = 0, hi = ndesc - 1;
@@ -86,31 +97,32 @@ __global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK)
   d.tile_start = uniform64(d.tile_start);
   d.opA = __builtin_amdgcn_readfirstlane(d.opA);
   d.opB = __builtin_amdgcn_readfirstlane(d.opB);
-  const int64_t t = tile - d.tile_start;
-  const int64_t ntn = (d.N + 15) / 16;
-  const int64_t m0 = (t / ntn) * 16, n0 = (t % ntn) * 16;
+  const int64_t t = tile - (CT == 1 ? d.tile_start : 0);
+  const int64_t ntn = (d.N + 16 * CT - 1) / (16 * CT);
+  const int64_t m0 = (t / ntn) * 16, n0 = (t % ntn) * 16 * CT;
   const int slot = lane >> 4, li = lane & 15;
   // which operand dimension is contiguous in memory
   const bool a_k = d.opA == OP_N || d.opA == OP_R;  // A[i][k] at i lda + k
   const bool b_k = d.opB == OP_T || d.opB == OP_C;  // B[k][j] at j ldb + k
-  dbl4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+  dbl4 cr[CT], ci[CT];
+#pragma unroll
+  for (int u = 0; u < CT; ++u) cr[u] = ci[u] = dbl4{0, 0, 0, 0};
   // this wavefront's groups of 16 k: k0 = 16 (wave + SPLITK g), g < ng
   const int64_t kfirst = SPLITK == 1 ? 0 : 16 * wave, kstep = 16 * SPLITK;
   const int64_t ng = kfirst < d.K ? (d.K - kfirst + kstep - 1) / kstep : 0;
-  double2 ga[4], gb[4];
+  double2 ga[4], gb[CT][4];
   // Lane (slot, li), load q: line 4 q + slot of the operand, element li
-  // along it, i.e. op(A)[m0 + ar][k + ak] and op(B)[k + bk][n0 + bc] for the
-  // group starting at k.  Each load walks its line of memory with a fixed
-  // element step per group; off* is its element offset and n* the number of
-  // groups it stays inside the matrix (loads past it read element 0 and
-  // are replaced by zero).
+  // along it, i.e. op(A)[m0 + ar][k + ak] and op(B)[k + bk][n0 + 16 u + bc]
+  // for the group starting at k.  Each load walks its line of memory with a
+  // fixed element step per group; off* is its element offset and n* the
+  // number of groups it stays inside the matrix (loads past it read zero).
   const int64_t sAk = a_k ? 1 : d.lda, sAi = a_k ? d.lda : 1;
   const int64_t sBk = b_k ? 1 : d.ldb, sBj = b_k ? d.ldb : 1;
   const double sgA = (d.opA == OP_C || d.opA == OP_R) ? -1.0 : 1.0;
   const double sgB = (d.opB == OP_C || d.opB == OP_R) ? -1.0 : 1.0;
   const int64_t stA = kstep * sAk, stB = kstep * sBk;
   int ar[4], ak[4], bk[4], bc[4];
-  int64_t offA[4], offB[4], nA[4], nB[4];
+  int64_t offA[4], nA[4], offB[CT][4], nB[CT][4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int r = 4 * q + slot;
@@ -118,90 +130,112 @@ __global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK)
     ak[q] = a_k ? li : r;
     bk[q] = b_k ? li : r;
     bc[q] = b_k ? r : li;
-    const int64_t i = m0 + ar[q], ka = kfirst + ak[q], j = n0 + bc[q], kb = kfirst + bk[q];
+    const int64_t i = m0 + ar[q], ka = kfirst + ak[q], kb = kfirst + bk[q];
     nA[q] = i < d.M && ka < d.K ? (d.K - ka + kstep - 1) / kstep : 0;
-    nB[q] = j < d.N && kb < d.K ? (d.K - kb + kstep - 1) / kstep : 0;
     offA[q] = nA[q] > 0 ? i * sAi + ka * sAk : 0;
-    offB[q] = nB[q] > 0 ? j * sBj + kb * sBk : 0;
+#pragma unroll
+    for (int u = 0; u < CT; ++u) {
+      const int64_t j = n0 + 16 * u + bc[q];
+      nB[u][q] = j < d.N && kb < d.K ? (d.K - kb + kstep - 1) / kstep : 0;
+      offB[u][q] = nB[u][q] > 0 ? j * sBj + kb * sBk : 0;
+    }
   }
   auto gload = [&](int64_t g) {  // group g; called for g = 0, 1, 2, ... in order
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const bool oa = g < nA[q], ob = g < nB[q];
-      const double2 va = ld_global(d.A + (oa ? offA[q] : 0));
-      const double2 vb = ld_global(d.B + (ob ? offB[q] : 0));
-      ga[q] = oa ? make_double2(va.x, sgA * va.y) : make_double2(0, 0);
-      gb[q] = ob ? make_double2(vb.x, sgB * vb.y) : make_double2(0, 0);
+      ga[q] = ld_global(g < nA[q] ? d.A + offA[q] : g_zero2);
       offA[q] += stA;
-      offB[q] += stB;
+#pragma unroll
+      for (int u = 0; u < CT; ++u) {
+        gb[u][q] = ld_global(g < nB[u][q] ? d.B + offB[u][q] : g_zero2);
+        offB[u][q] += stB;
+      }
     }
   };
-  double2(*sa)[17] = stage[wave][0];
-  double2(*sb)[17] = stage[wave][1];
+  // this wavefront's staging: sub-tile 0 = op(A) rows x k, 1 + u = op(B) columns of block u x k
+  double2(*st)[16][17] = reinterpret_cast<double2(*)[16][17]>(smem + (size_t)wave * NS * 16 * 17);
   if (ng > 0) gload(0);
   for (int64_t g = 0; g < ng; ++g) {
+    // (the conjugation sign is applied here, where the loads are waited on)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      sa[ar[q]][ak[q]] = ga[q];
-      sb[bc[q]][bk[q]] = gb[q];
+      st[0][ar[q]][ak[q]] = make_double2(ga[q].x, sgA * ga[q].y);
+#pragma unroll
+      for (int u = 0; u < CT; ++u) st[1 + u][bc[q]][bk[q]] = make_double2(gb[u][q].x, sgB * gb[u][q].y);
     }
     // the next group's loads go out before the matrix cores take this one
-    if (g + 1 < ng) gload(g + 1);
+    // (unconditionally: past the last group they read zeros, and a
+    // conditional load would leave register copies that wait on it)
+    gload(g + 1);
     // LDS operations of a wavefront complete in order: a compiler barrier
     // keeps the reads after the writes (and the next writes after the reads)
     __builtin_amdgcn_wave_barrier();
-    double2 a[4], b[4];
+    double2 a[4], b[CT][4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {  // step s takes k = 4 s + slot
-      a[s] = sa[li][4 * s + slot];
-      b[s] = sb[li][4 * s + slot];
+      a[s] = st[0][li][4 * s + slot];
+#pragma unroll
+      for (int u = 0; u < CT; ++u) b[u][s] = st[1 + u][li][4 * s + slot];
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].x, b[s].x, cr, 0, 0, 0);
-      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[s].y, b[s].y, cr, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].x, b[s].y, ci, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].y, b[s].x, ci, 0, 0, 0);
+    for (int u = 0; u < CT; ++u) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        cr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].x, b[u][s].x, cr[u], 0, 0, 0);
+        cr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[s].y, b[u][s].y, cr[u], 0, 0, 0);
+        ci[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].x, b[u][s].y, ci[u], 0, 0, 0);
+        ci[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].y, b[u][s].x, ci[u], 0, 0, 0);
+      }
     }
   }
   if (SPLITK > 1) {
-    // waves 1..SPLITK-1 hand their partial tiles to wave 0
+    // waves 1..SPLITK-1 hand their partial tiles to wave 0 (through the
+    // staging memory: every wavefront has left the K loop first)
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(smem);
     if (wave > 0) {
-      double* r = red + ((wave - 1) * 64 + lane) * 8;
+      double* r = red + ((wave - 1) * 64 + lane) * 8 * CT;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        r[q] = cr[q];
-        r[4 + q] = ci[q];
-      }
+      for (int u = 0; u < CT; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          r[8 * u + q] = cr[u][q];
+          r[8 * u + 4 + q] = ci[u][q];
+        }
     }
     __syncthreads();
     if (wave > 0) return;
 #pragma unroll
     for (int w = 0; w < SPLITK - 1; ++w) {
-      const double* r = red + (w * 64 + lane) * 8;
+      const double* r = red + (w * 64 + lane) * 8 * CT;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        cr[q] += r[q];
-        ci[q] += r[4 + q];
-      }
+      for (int u = 0; u < CT; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          cr[u][q] += r[8 * u + q];
+          ci[u][q] += r[8 * u + 4 + q];
+        }
     }
   }
-  const int64_t col = n0 + (lane & 15);
-  if (col >= d.N) return;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int64_t row = m0 + 4 * r + slot;
-    if (row < d.M) {
-      const double xr = cr[r], xi = ci[r];
-      double2 v = make_double2(d.alpha_re * xr - d.alpha_im * xi, d.alpha_re * xi + d.alpha_im * xr);
-      double2* p = d.transC ? d.C + col * d.ldc + row : d.C + row * d.ldc + col;
-      if (d.accumulate) {
-        const double2 o = ld_global(p);
-        v.x += o.x;
-        v.y += o.y;
+  for (int u = 0; u < CT; ++u) {
+    const int64_t col = n0 + 16 * u + (lane & 15);
+    if (col >= d.N) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = m0 + 4 * r + slot;
+      if (row < d.M) {
+        const double xr = cr[u][r], xi = ci[u][r];
+        double2 v = make_double2(d.alpha_re * xr - d.alpha_im * xi, d.alpha_re * xi + d.alpha_im * xr);
+        double2* p = d.transC ? d.C + col * d.ldc + row : d.C + row * d.ldc + col;
+        if (d.accumulate) {
+          const double2 o = ld_global(p);
+          v.x += o.x;
+          v.y += o.y;
+        }
+        *p = v;
       }
-      *p = v;
     }
   }
 }
@@ -522,21 +556,36 @@ static int64_t number_tiles(const std::vector<GemmDesc>& in, std::vector<GemmDes
 }
 
 // Launch shapes: four tiles per block (one per wavefront), or one tile per
-// block with K split over 4 or 8 wavefronts.
-enum { GV_TILE4 = 0, GV_SPLIT4, GV_SPLIT8, GV_COUNT };
+// block with K split over 4 or 8 wavefronts; for a single product also
+// tiles of 2 or 4 adjacent 16-column blocks with K split over 4 wavefronts
+// (op(A) read once for them; with 8 wavefronts they would spill).
+enum { GV_TILE4 = 0, GV_SPLIT4, GV_SPLIT8, GV_WIDE2_S4, GV_WIDE4_S4, GV_COUNT };
 
-static void launch_variant(int v, const GemmDesc* dev, int count, int64_t tiles, hipStream_t s) {
+static bool single_only(int v) { return v >= GV_WIDE2_S4; }
+
+// tiles: 16 x 16 tiles of the group; M, N: the sizes of its product when it
+// has one (the wide shapes number their own tiles)
+static void launch_variant(int v, const GemmDesc* dev, int count, int64_t tiles, int64_t M, int64_t N,
+                           hipStream_t s) {
   const dim3 one((unsigned)tiles);
+  auto wide = [&](int ct) { return ((M + 15) / 16) * ((N + 16 * ct - 1) / (16 * ct)); };
+  CBFM_REQUIRE(!single_only(v) || count == 1, CBFM_E_ARG, "wide GEMM tiles need a single product");
   switch (v) {
     case GV_TILE4:
-      hipLaunchKernelGGL(zgemm_batched_kernel<1>, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, dev, count,
+      hipLaunchKernelGGL((zgemm_batched_kernel<1, 1>), dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, dev, count,
                          tiles);
       break;
     case GV_SPLIT4:
-      hipLaunchKernelGGL(zgemm_batched_kernel<4>, one, dim3(256), 0, s, dev, count, tiles);
+      hipLaunchKernelGGL((zgemm_batched_kernel<4, 1>), one, dim3(256), 0, s, dev, count, tiles);
+      break;
+    case GV_SPLIT8:
+      hipLaunchKernelGGL((zgemm_batched_kernel<8, 1>), one, dim3(512), 0, s, dev, count, tiles);
+      break;
+    case GV_WIDE2_S4:
+      hipLaunchKernelGGL((zgemm_batched_kernel<4, 2>), dim3((unsigned)wide(2)), dim3(256), 0, s, dev, count, wide(2));
       break;
     default:
-      hipLaunchKernelGGL(zgemm_batched_kernel<8>, one, dim3(512), 0, s, dev, count, tiles);
+      hipLaunchKernelGGL((zgemm_batched_kernel<4, 4>), dim3((unsigned)wide(4)), dim3(256), 0, s, dev, count, wide(4));
       break;
   }
   CBFM_HIP(hipGetLastError());
@@ -570,9 +619,10 @@ static int choose(const GemmKey& k) {
   return k.tiles < 4096 ? GV_SPLIT4 : GV_TILE4;
 }
 
-static void launch_descs(const GemmDesc* dev, int count, int64_t tiles, double flops, int variant, hipStream_t s) {
+static void launch_descs(const GemmDesc* dev, int count, int64_t tiles, int64_t M, int64_t N, double flops,
+                         int variant, hipStream_t s) {
   TimedLaunch tl(T_GEMM, s, flops);
-  launch_variant(variant, dev, count, tiles, s);
+  launch_variant(variant, dev, count, tiles, M, N, s);
 }
 
 // Elements spanned by an operand or the result of a descriptor.
@@ -614,9 +664,10 @@ static void tune_group(const GemmKey& key, const GemmDesc* dev, int count, int64
   float best_ms = 0;
   try {
     for (int v = 0; v < GV_COUNT; ++v) {
-      launch_variant(v, dev, count, tiles, s);
+      if (single_only(v) && count != 1) continue;
+      launch_variant(v, dev, count, tiles, key.M, key.N, s);
       CBFM_HIP(hipEventRecord(e0, s));
-      for (int r = 0; r < 3; ++r) launch_variant(v, dev, count, tiles, s);
+      for (int r = 0; r < 3; ++r) launch_variant(v, dev, count, tiles, key.M, key.N, s);
       CBFM_HIP(hipEventRecord(e1, s));
       CBFM_HIP(hipEventSynchronize(e1));
       float ms = 0;
@@ -645,8 +696,8 @@ void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s) {
   if (live.empty()) return;
   Scratch dev(live.size() * sizeof(GemmDesc), s);
   CBFM_HIP(hipMemcpyAsync(dev.p, live.data(), live.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
-  launch_descs(dev.as<GemmDesc>(), (int)live.size(), tiles, flops, choose(key_of(live.data(), (int)live.size(), tiles)),
-               s);
+  launch_descs(dev.as<GemmDesc>(), (int)live.size(), tiles, live[0].M, live[0].N, flops,
+               choose(key_of(live.data(), (int)live.size(), tiles)), s);
   // the descriptor staging buffer is host memory of this frame
   CBFM_HIP(hipStreamSynchronize(s));
 }
@@ -671,6 +722,8 @@ GemmPlan::GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t
     CBFM_HIP(hipStreamSynchronize(s));  // `all` is host memory of this frame
   }
   for (size_t g = 0; g < groups.size(); ++g) {
+    m_.push_back(count_[g] > 0 ? all[first_[g]].M : 0);
+    n_.push_back(count_[g] > 0 ? all[first_[g]].N : 0);
     if (count_[g] == 0) {
       variant_.push_back(GV_TILE4);
       continue;
@@ -684,7 +737,7 @@ GemmPlan::GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t
 void GemmPlan::launch(size_t g, hipStream_t s) const {
   CBFM_REQUIRE(g < tiles_.size(), CBFM_E_ARG, "GEMM plan group out of range");
   if (count_[g] == 0) return;
-  launch_descs(dev_.as<GemmDesc>() + first_[g], (int)count_[g], tiles_[g], flops_[g], variant_[g], s);
+  launch_descs(dev_.as<GemmDesc>() + first_[g], (int)count_[g], tiles_[g], m_[g], n_[g], flops_[g], variant_[g], s);
 }
 
 }  // namespace cbfm
