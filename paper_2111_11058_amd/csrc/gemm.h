@@ -106,6 +106,7 @@ class XGemmPlan {
   Scratch dev_;
   std::vector<int64_t> first_, count_, tiles_;
   std::vector<double> flops_;
+  std::vector<int> types_;  // operand element types of each group
 };
 
 // Groups of GEMMs whose descriptors are uploaded to the device once (one

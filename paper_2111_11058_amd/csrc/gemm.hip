@@ -42,6 +42,19 @@ __device__ __forceinline__ float2 ld_global(const float2* p) {
 // compiler move the load under a branch, one wait per load).
 __device__ double2 g_zero2[1];
 
+// 8 bytes (a complex float) loaded from global memory into a double's bits
+__device__ __forceinline__ double ld_global8(const void* p) {
+  return *(const __attribute__((address_space(1))) double*)p;
+}
+__device__ __forceinline__ float2 bits_to_float2(double x) {
+  union {
+    double d;
+    float f[2];
+  } u;
+  u.d = x;
+  return make_float2(u.f[0], u.f[1]);
+}
+
 __device__ __forceinline__ int64_t uniform64(int64_t x) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(x & 0xffffffff));
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
@@ -250,7 +263,7 @@ __global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK)
 typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-template <int MODE, int SPLITK>
+template <int MODE, int SPLITK, bool A64, bool B64>
 __global__ void __launch_bounds__(256) xgemm_batched_kernel(const GemmDescX* __restrict__ desc, int ndesc,
                                                             int64_t total_tiles) {
   constexpr int KG = MODE == XG_FP32 ? 16 : 32;  // k per step of a wavefront
@@ -281,8 +294,6 @@ __global__ void __launch_bounds__(256) xgemm_batched_kernel(const GemmDescX* __r
   d.tile_start = uniform64(d.tile_start);
   d.opA = __builtin_amdgcn_readfirstlane(d.opA);
   d.opB = __builtin_amdgcn_readfirstlane(d.opB);
-  d.a64 = __builtin_amdgcn_readfirstlane(d.a64);
-  d.b64 = __builtin_amdgcn_readfirstlane(d.b64);
   const int64_t t = tile - d.tile_start;
   const int64_t ntn = (d.N + 15) / 16;
   const int64_t m0 = (t / ntn) * 16, n0 = (t % ntn) * 16;
@@ -318,42 +329,46 @@ __global__ void __launch_bounds__(256) xgemm_batched_kernel(const GemmDescX* __r
   float2(*sa)[KG + 1] = stage[wave][0];
   float2(*sb)[KG + 1] = stage[wave][1];
   flt4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-  for (int64_t k0 = kfirst; k0 < d.K; k0 += kstep) {
-    // half h: k from k0 + 16 h
+  // raw operand values of one step (half h, load q): a complex double, or
+  // the 8 bytes of a complex float in .x.  The next step's loads go out
+  // before this one's matrix-core work; loads outside an operand read zero
+  // (the address is chosen, not the value, as in zgemm_batched_kernel), and
+  // the conversion and the conjugation sign are applied at the LDS store.
+  double2 ra[KG / 16][4], rb[KG / 16][4];
+  auto gload = [&]() {  // the step at the running offsets, which it advances
+    if constexpr (A64) {
 #pragma unroll
-    for (int h = 0; h < KG / 16; ++h) {
-      float2 va[4], vb[4];
-      bool oa[4], ob[4];
+      for (int h = 0; h < KG / 16; ++h)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        oa[q] = rA[q] && kA[q] + 16 * h < d.K;
-        ob[q] = rB[q] && kB[q] + 16 * h < d.K;
-      }
-      if (d.a64) {
+        for (int q = 0; q < 4; ++q)
+          ra[h][q] = ld_global(rA[q] && kA[q] + 16 * h < d.K
+                                   ? static_cast<const double2*>(d.A) + offA[q] + 16 * h * sAk
+                                   : g_zero2);
+    } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double2 w = ld_global(static_cast<const double2*>(d.A) + (oa[q] ? offA[q] + 16 * h * sAk : 0));
-          va[q] = make_float2((float)w.x, (float)w.y);
-        }
-      } else {
+      for (int h = 0; h < KG / 16; ++h)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) va[q] = ld_global(static_cast<const float2*>(d.A) + (oa[q] ? offA[q] + 16 * h * sAk : 0));
-      }
-      if (d.b64) {
+        for (int q = 0; q < 4; ++q)
+          ra[h][q].x = ld_global8(rA[q] && kA[q] + 16 * h < d.K
+                                      ? (const void*)(static_cast<const float2*>(d.A) + offA[q] + 16 * h * sAk)
+                                      : (const void*)g_zero2);
+    }
+    if constexpr (B64) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double2 w = ld_global(static_cast<const double2*>(d.B) + (ob[q] ? offB[q] + 16 * h * sBk : 0));
-          vb[q] = make_float2((float)w.x, (float)w.y);
-        }
-      } else {
+      for (int h = 0; h < KG / 16; ++h)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) vb[q] = ld_global(static_cast<const float2*>(d.B) + (ob[q] ? offB[q] + 16 * h * sBk : 0));
-      }
+        for (int q = 0; q < 4; ++q)
+          rb[h][q] = ld_global(rB[q] && kB[q] + 16 * h < d.K
+                                   ? static_cast<const double2*>(d.B) + offB[q] + 16 * h * sBk
+                                   : g_zero2);
+    } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        sa[ar[q]][16 * h + ak[q]] = oa[q] ? make_float2(va[q].x, sgA * va[q].y) : make_float2(0.0f, 0.0f);
-        sb[bc[q]][16 * h + bk[q]] = ob[q] ? make_float2(vb[q].x, sgB * vb[q].y) : make_float2(0.0f, 0.0f);
-      }
+      for (int h = 0; h < KG / 16; ++h)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          rb[h][q].x = ld_global8(rB[q] && kB[q] + 16 * h < d.K
+                                      ? (const void*)(static_cast<const float2*>(d.B) + offB[q] + 16 * h * sBk)
+                                      : (const void*)g_zero2);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -362,6 +377,19 @@ __global__ void __launch_bounds__(256) xgemm_batched_kernel(const GemmDescX* __r
       offA[q] += kstep * sAk;
       offB[q] += kstep * sBk;
     }
+  };
+  if (kfirst < d.K) gload();
+  for (int64_t k0 = kfirst; k0 < d.K; k0 += kstep) {
+#pragma unroll
+    for (int h = 0; h < KG / 16; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float2 va = A64 ? make_float2((float)ra[h][q].x, (float)ra[h][q].y) : bits_to_float2(ra[h][q].x);
+        const float2 vb = B64 ? make_float2((float)rb[h][q].x, (float)rb[h][q].y) : bits_to_float2(rb[h][q].x);
+        sa[ar[q]][16 * h + ak[q]] = make_float2(va.x, sgA * va.y);
+        sb[bc[q]][16 * h + bk[q]] = make_float2(vb.x, sgB * vb.y);
+      }
+    gload();  // the next step (zeros past the end)
     // LDS operations of a wavefront complete in order
     __builtin_amdgcn_wave_barrier();
     if constexpr (MODE == XG_FP32) {
@@ -478,26 +506,53 @@ static int64_t number_tiles_x(const std::vector<GemmDescX>& in, std::vector<Gemm
   return tiles;
 }
 
-static void launch_x(const GemmDescX* dd, int n, int64_t tiles, double flops, int mode, hipStream_t s) {
-  TimedLaunch tl(T_GEMM, s, flops);
+// Element types of a group's operands (bit 1: A is complex double, bit 0:
+// B is); every product of one launch has the same pair, which the kernel
+// takes as template arguments so that its loads carry no run-time choice.
+static int operand_types(const std::vector<GemmDescX>& g) {
+  if (g.empty()) return 0;
+  const int ab = (g[0].a64 ? 2 : 0) | (g[0].b64 ? 1 : 0);
+  for (const GemmDescX& d : g)
+    CBFM_REQUIRE(((d.a64 ? 2 : 0) | (d.b64 ? 1 : 0)) == ab, CBFM_E_ARG,
+                 "mixed operand element types in one batched GEMM launch");
+  return ab;
+}
+
+template <int MODE, int SPLITK>
+static void launch_x_types(const GemmDescX* dd, int n, int64_t tiles, int ab, dim3 g, hipStream_t s) {
+  switch (ab) {
+    case 0:
+      hipLaunchKernelGGL((xgemm_batched_kernel<MODE, SPLITK, false, false>), g, dim3(256), 0, s, dd, n, tiles);
+      break;
+    case 1:
+      hipLaunchKernelGGL((xgemm_batched_kernel<MODE, SPLITK, false, true>), g, dim3(256), 0, s, dd, n, tiles);
+      break;
+    case 2:
+      hipLaunchKernelGGL((xgemm_batched_kernel<MODE, SPLITK, true, false>), g, dim3(256), 0, s, dd, n, tiles);
+      break;
+    default:
+      hipLaunchKernelGGL((xgemm_batched_kernel<MODE, SPLITK, true, true>), g, dim3(256), 0, s, dd, n, tiles);
+  }
+}
+
+template <int MODE>
+static void launch_x_mode(const GemmDescX* dd, int n, int64_t tiles, int ab, hipStream_t s) {
   const bool few = tiles < 4096;
   const dim3 g(few ? (unsigned)tiles : (unsigned)((tiles + 3) / 4));
-  if (mode == XG_BF16) {
-    if (few)
-      hipLaunchKernelGGL((xgemm_batched_kernel<XG_BF16, 4>), g, dim3(256), 0, s, dd, n, tiles);
-    else
-      hipLaunchKernelGGL((xgemm_batched_kernel<XG_BF16, 1>), g, dim3(256), 0, s, dd, n, tiles);
-  } else if (mode == XG_BF16X3) {
-    if (few)
-      hipLaunchKernelGGL((xgemm_batched_kernel<XG_BF16X3, 4>), g, dim3(256), 0, s, dd, n, tiles);
-    else
-      hipLaunchKernelGGL((xgemm_batched_kernel<XG_BF16X3, 1>), g, dim3(256), 0, s, dd, n, tiles);
-  } else {
-    if (few)
-      hipLaunchKernelGGL((xgemm_batched_kernel<XG_FP32, 4>), g, dim3(256), 0, s, dd, n, tiles);
-    else
-      hipLaunchKernelGGL((xgemm_batched_kernel<XG_FP32, 1>), g, dim3(256), 0, s, dd, n, tiles);
-  }
+  if (few)
+    launch_x_types<MODE, 4>(dd, n, tiles, ab, g, s);
+  else
+    launch_x_types<MODE, 1>(dd, n, tiles, ab, g, s);
+}
+
+static void launch_x(const GemmDescX* dd, int n, int64_t tiles, double flops, int mode, int ab, hipStream_t s) {
+  TimedLaunch tl(T_GEMM, s, flops);
+  if (mode == XG_BF16)
+    launch_x_mode<XG_BF16>(dd, n, tiles, ab, s);
+  else if (mode == XG_BF16X3)
+    launch_x_mode<XG_BF16X3>(dd, n, tiles, ab, s);
+  else
+    launch_x_mode<XG_FP32>(dd, n, tiles, ab, s);
   CBFM_HIP(hipGetLastError());
 }
 
@@ -507,9 +562,10 @@ void xgemm_batched(std::vector<GemmDescX>& descs, int mode, hipStream_t s) {
   double flops = 0;
   const int64_t tiles = number_tiles_x(descs, live, &flops);
   if (live.empty()) return;
+  const int ab = operand_types(live);
   Scratch dev(live.size() * sizeof(GemmDescX), s);
   CBFM_HIP(hipMemcpyAsync(dev.p, live.data(), live.size() * sizeof(GemmDescX), hipMemcpyHostToDevice, s));
-  launch_x(dev.as<GemmDescX>(), (int)live.size(), tiles, flops, mode, s);
+  launch_x(dev.as<GemmDescX>(), (int)live.size(), tiles, flops, mode, ab, s);
   CBFM_HIP(hipStreamSynchronize(s));  // the descriptor staging buffer is host memory of this frame
 }
 
@@ -527,6 +583,7 @@ XGemmPlan::XGemmPlan(const std::vector<std::vector<GemmDescX>>& groups, int mode
     tiles_.push_back(number_tiles_x(g, all, &f));
     flops_.push_back(f);
     count_.push_back((int64_t)all.size() - first_.back());
+    types_.push_back(operand_types(std::vector<GemmDescX>(all.begin() + first_.back(), all.end())));
   }
   if (!all.empty()) {
     CBFM_HIP(hipMemcpyAsync(dev_.p, all.data(), all.size() * sizeof(GemmDescX), hipMemcpyHostToDevice, s));
@@ -537,7 +594,7 @@ XGemmPlan::XGemmPlan(const std::vector<std::vector<GemmDescX>>& groups, int mode
 void XGemmPlan::launch(size_t g, hipStream_t s) const {
   CBFM_REQUIRE(g < tiles_.size(), CBFM_E_ARG, "GEMM plan group out of range");
   if (count_[g] == 0) return;
-  launch_x(dev_.as<GemmDescX>() + first_[g], (int)count_[g], tiles_[g], flops_[g], mode_, s);
+  launch_x(dev_.as<GemmDescX>() + first_[g], (int)count_[g], tiles_[g], flops_[g], mode_, types_[g], s);
 }
 
 // Tile offsets of a group of descriptors (empty products dropped); returns
