@@ -81,36 +81,24 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
-// Large scratch blocks (scratch.cpp): device allocations kept after use and
-// handed out again, ordered on the stream by an event.
+// Scratch allocation (scratch.cpp): device blocks kept after use and handed
+// out again, reuse ordered on the stream by an event; blocks from
+// kBigScratch up are matched by size rather than by power-of-two class.
 constexpr size_t kBigScratch = (size_t)256 << 20;
-void* big_alloc(size_t bytes, hipStream_t s);
-void big_release(void* p, size_t bytes, hipStream_t s);
+void* scratch_alloc(size_t bytes, hipStream_t s);
+void scratch_release(void* p, size_t bytes, hipStream_t s);
+size_t scratch_cached_bytes();  // bytes held by the cache on the current device
 
-// Stream-ordered scratch released at scope exit: hipMallocAsync /
-// hipFreeAsync on the stream, or the large-block cache from kBigScratch up.
+// Stream-ordered scratch released at scope exit.
 struct Scratch {
   void* p = nullptr;
   hipStream_t s = nullptr;
   size_t n = 0;
   Scratch(size_t bytes, hipStream_t stream) : s(stream), n(bytes) {
-    if (bytes == 0) return;
-    if (bytes >= kBigScratch) {
-      p = big_alloc(bytes, stream);
-      return;
-    }
-    hipError_t e = hipMallocAsync(&p, bytes, stream);
-    if (e != hipSuccess) {
-      p = nullptr;
-      throw Error{CBFM_E_NOMEM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed"};
-    }
+    if (bytes > 0) p = scratch_alloc(bytes, stream);
   }
   ~Scratch() {
-    if (!p) return;
-    if (n >= kBigScratch)
-      big_release(p, n, s);
-    else
-      (void)hipFreeAsync(p, s);
+    if (p) scratch_release(p, n, s);
   }
   Scratch(const Scratch&) = delete;
   Scratch& operator=(const Scratch&) = delete;

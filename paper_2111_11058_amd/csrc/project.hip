@@ -295,6 +295,7 @@ extern "C" cbfm_status cbfm_project_batch(int32_t count, const cbfm_mesh* meshes
     }
     size_t fr = 0, tot = 0;
     CBFM_HIP(hipMemGetInfo(&fr, &tot));
+    fr += scratch_cached_bytes();  // cached scratch is free for this call's panels
     const size_t budget = std::min<size_t>(fr / 4, (size_t)32 << 30);
     project_batch_dev(es, precision, static_cast<hipStream_t>(stream), budget);
   });
@@ -313,6 +314,7 @@ extern "C" cbfm_status cbfm_project(cbfm_mesh m, const cbfm_medium* med, cbfm_cb
     // scratch budget per panel: a quarter of the free device memory, at most 32 GiB
     size_t fr = 0, tot = 0;
     CBFM_HIP(hipMemGetInfo(&fr, &tot));
+    fr += scratch_cached_bytes();  // cached scratch is free for this call's panels
     const size_t budget = std::min<size_t>(fr / 4, (size_t)32 << 30);
     project_dev(m, md, c, precision, static_cast<double2*>(Zr), ldz, static_cast<hipStream_t>(stream), budget);
   });

@@ -1,17 +1,25 @@
-// Cache of large device scratch blocks.
+// Cache of device scratch blocks.
 //
-// Freeing and re-mapping multi-gigabyte stream-ordered allocations
-// (hipMallocAsync / hipFreeAsync) costs tens to hundreds of milliseconds
-// each on this runtime once the pool has been used, which dominated the
-// panelled projection of large meshes (panels of tens of GB).  Blocks of at
-// least kBigScratch bytes therefore come from plain device allocations that
-// are kept after use and handed out again.  A released block carries an
-// event recorded on the releasing stream; the next user's stream waits on
-// it, so reuse is ordered after every operation queued before the release.
-// If an allocation fails, the cached blocks of that device are freed (after
-// their events complete) and the allocation is retried; the blocks cached
-// per device are capped at kCacheCap bytes (the oldest are freed first).
+// On this runtime the stream-ordered allocator (hipMallocAsync /
+// hipFreeAsync) costs from about a hundred microseconds to a few
+// milliseconds per call, whatever the size and the pool's release threshold,
+// and multi-gigabyte blocks far more; with some ninety scratch blocks per
+// CBF build, projection and solve, that host time left the device idle for
+// a sixth of a small problem's step.  Every scratch block therefore comes
+// from plain device allocations that are kept after use and handed out
+// again:
+//  * blocks below kBigScratch are rounded up to a power of two and reused
+//    for requests of the same class; larger ones are reused for requests of
+//    at least half their size;
+//  * a released block carries an event recorded on the releasing stream, and
+//    the next user's stream waits on it, so reuse is ordered after every
+//    operation queued before the release, on any stream;
+//  * the bytes cached per device are capped at kCacheCap (the oldest blocks
+//    are freed first), and if an allocation fails, the device's cached blocks
+//    are freed (after their events complete) and the allocation is retried.
+#include <cstdint>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -21,6 +29,14 @@ namespace cbfm {
 namespace {
 
 constexpr size_t kCacheCap = (size_t)64 << 30;
+constexpr size_t kMinBlock = 512;
+
+size_t block_size(size_t bytes) {
+  if (bytes >= kBigScratch) return bytes;
+  size_t b = kMinBlock;
+  while (b < bytes) b <<= 1;
+  return b;
+}
 
 struct Block {
   void* p;
@@ -31,13 +47,47 @@ struct Block {
 
 struct Cache {
   std::mutex mu;
-  std::vector<Block> free;
+  std::vector<Block> free;                         // in release order
+  std::vector<std::pair<int, hipEvent_t>> events;  // spare events and their devices
 };
 
 // never destroyed: the runtime may be torn down before static destructors run
 Cache& cache() {
   static Cache* c = new Cache;
   return *c;
+}
+
+hipEvent_t take_event(int dev) {
+  {
+    std::lock_guard<std::mutex> lk(cache().mu);
+    auto& ev = cache().events;
+    for (size_t i = ev.size(); i-- > 0;)
+      if (ev[i].first == dev) {
+        const hipEvent_t e = ev[i].second;
+        ev[i] = ev.back();
+        ev.pop_back();
+        return e;
+      }
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+// (call with the cache lock held)
+void spare_event(int dev, hipEvent_t e) { cache().events.push_back({dev, e}); }
+
+void free_blocks(std::vector<Block>& drop) {
+  for (Block& b : drop) {
+    (void)hipEventSynchronize(b.ready);
+    (void)hipFree(b.p);
+    std::lock_guard<std::mutex> lk(cache().mu);
+    spare_event(b.dev, b.ready);
+  }
+  drop.clear();
 }
 
 void trim(int dev) {
@@ -48,63 +98,70 @@ void trim(int dev) {
     for (size_t i = 0; i < f.size();) {
       if (f[i].dev == dev) {
         drop.push_back(f[i]);
-        f[i] = f.back();
-        f.pop_back();
+        f.erase(f.begin() + (ptrdiff_t)i);
       } else {
         ++i;
       }
     }
   }
-  for (Block& b : drop) {
-    (void)hipEventSynchronize(b.ready);
-    (void)hipEventDestroy(b.ready);
-    (void)hipFree(b.p);
-  }
+  free_blocks(drop);
 }
 
 }  // namespace
 
-void* big_alloc(size_t bytes, hipStream_t s) {
+void* scratch_alloc(size_t bytes, hipStream_t s) {
   int dev = 0;
   CBFM_HIP(hipGetDevice(&dev));
+  const size_t want = block_size(bytes);
+  const bool big = want >= kBigScratch;
   {
-    std::lock_guard<std::mutex> lk(cache().mu);
+    std::unique_lock<std::mutex> lk(cache().mu);
     auto& f = cache().free;
-    // the smallest cached block that fits and wastes at most half of itself
+    // a block of the same class; for large requests the smallest cached
+    // block that fits and wastes at most half of itself
     size_t best = f.size();
-    for (size_t i = 0; i < f.size(); ++i)
-      if (f[i].dev == dev && f[i].bytes >= bytes && f[i].bytes <= 2 * bytes &&
-          (best == f.size() || f[i].bytes < f[best].bytes))
+    for (size_t i = 0; i < f.size(); ++i) {
+      if (f[i].dev != dev) continue;
+      if (!big) {
+        if (f[i].bytes == want) {
+          best = i;
+          break;
+        }
+      } else if (f[i].bytes >= want && f[i].bytes <= 2 * want && (best == f.size() || f[i].bytes < f[best].bytes)) {
         best = i;
+      }
+    }
     if (best < f.size()) {
       const Block b = f[best];
       f.erase(f.begin() + (ptrdiff_t)best);  // (keeps the release order)
-      const hipError_t e = hipStreamWaitEvent(s, b.ready, 0);
-      (void)hipEventDestroy(b.ready);
-      if (e != hipSuccess) {
-        (void)hipDeviceSynchronize();  // keep the ordering before handing the block out
+      lk.unlock();
+      if (hipStreamWaitEvent(s, b.ready, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipEventSynchronize(b.ready);  // keep the ordering before handing the block out
       }
+      lk.lock();
+      spare_event(dev, b.ready);  // re-recording later leaves the queued wait as it was
       return b.p;
     }
   }
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) {
+  if (hipMalloc(&p, want) != hipSuccess) {
     (void)hipGetLastError();
     trim(dev);
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+    if (hipMalloc(&p, want) != hipSuccess) {
       (void)hipGetLastError();
-      throw Error{CBFM_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+      throw Error{CBFM_E_NOMEM, "device allocation of " + std::to_string(want) + " bytes failed"};
     }
   }
   return p;
 }
 
-void big_release(void* p, size_t bytes, hipStream_t s) {
+void scratch_release(void* p, size_t bytes, hipStream_t s) {
   int dev = 0;
   hipEvent_t ev = nullptr;
-  if (hipGetDevice(&dev) != hipSuccess || hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventRecord(ev, s) != hipSuccess) {
+  if (hipGetDevice(&dev) != hipSuccess || (ev = take_event(dev)) == nullptr || hipEventRecord(ev, s) != hipSuccess) {
     // no way to order a later reuse: wait for the stream, then free
+    (void)hipGetLastError();
     if (ev) (void)hipEventDestroy(ev);
     (void)hipStreamSynchronize(s);
     (void)hipFree(p);
@@ -114,7 +171,7 @@ void big_release(void* p, size_t bytes, hipStream_t s) {
   {
     std::lock_guard<std::mutex> lk(cache().mu);
     auto& f = cache().free;
-    f.push_back({p, bytes, dev, ev});
+    f.push_back({p, block_size(bytes), dev, ev});
     size_t held = 0;
     for (const Block& b : f)
       if (b.dev == dev) held += b.bytes;
@@ -129,11 +186,20 @@ void big_release(void* p, size_t bytes, hipStream_t s) {
       }
     }
   }
-  for (Block& b : drop) {
-    (void)hipEventSynchronize(b.ready);
-    (void)hipEventDestroy(b.ready);
-    (void)hipFree(b.p);
+  free_blocks(drop);
+}
+
+size_t scratch_cached_bytes() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
   }
+  std::lock_guard<std::mutex> lk(cache().mu);
+  size_t held = 0;
+  for (const Block& b : cache().free)
+    if (b.dev == dev) held += b.bytes;
+  return held;
 }
 
 }  // namespace cbfm
