@@ -201,8 +201,9 @@ cbfm_status cbfm_rhs(cbfm_mesh m, const cbfm_medium* med, const double* inc_host
  * generating waves (LU), G'_m = (J^M)^H G_m J^J, SVD, keep sigma_i/sigma_1 >=
  * delta_svd (at most max_L if max_L > 0).  FP64 throughout.
  * Synchronises the stream (the kept counts L_m are host data).
- * Returns CBFM_E_ARG for n_gen outside [1, 4096], CBFM_E_RANK if a cell's
- * Z_mm is singular or a cell keeps no CBF.                                 */
+ * Returns CBFM_E_ARG for n_gen outside [1, 4096] or a mesh of more than
+ * 32767 cells or 32767 RWGs in one cell, CBFM_E_RANK if a cell's Z_mm is
+ * singular or a cell keeps no CBF.                                         */
 typedef struct {
   const double* gen_host; /* n_gen x 6 (k, p) generating plane waves */
   int32_t n_gen;

@@ -83,63 +83,95 @@ __device__ double gram_entry(int e, int f, const int32_t* tplus, const int32_t* 
   return g;
 }
 
-// Dense cell Gram G_m (N x N complex, row-major) for canonical edge list `ed`.
-__global__ void cell_gram_kernel(const int32_t* __restrict__ ed, int N, const int32_t* tplus, const int32_t* tminus,
-                                 const int32_t* aplus, const int32_t* aminus, const int32_t* tri_edge,
-                                 const int32_t* tri_sign, const double* length, double2* __restrict__ G) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
-  if (c >= N) return;
-  G[(int64_t)r * N + c] =
-      make_double2(gram_entry(ed[r], ed[c], tplus, tminus, aplus, aminus, tri_edge, tri_sign, length), 0.0);
+// One cell of the batched per-cell launches: where its triangle-local blocks
+// start in the local buffer of its group, and its support.
+struct CellJob {
+  int64_t loff;          // elements into the local buffer of the cell's group
+  int32_t nt, N;         // support triangles, RWGs of the cell
+  const int32_t* edges;  // the cell's RWGs (canonical edges)
+  const int32_t* pos;    // mesh triangle -> position in the cell's support list
+};
+
+// Dense cell Grams G_m (N x N complex, row-major, cell b at b Nmax^2) of
+// every cell's RWGs (blockIdx.z = cell).
+__global__ void cell_gram_kernel(const CellJob* __restrict__ cells, int Nmax, const int32_t* tplus,
+                                 const int32_t* tminus, const int32_t* aplus, const int32_t* aminus,
+                                 const int32_t* tri_edge, const int32_t* tri_sign, const double* length,
+                                 double2* __restrict__ G) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y, b = blockIdx.z;
+  const CellJob cj = cells[b];
+  if (c >= cj.N || r >= cj.N) return;
+  G[(int64_t)b * Nmax * Nmax + (int64_t)r * cj.N + c] = make_double2(
+      gram_entry(cj.edges[r], cj.edges[c], tplus, tminus, aplus, aminus, tri_edge, tri_sign, length), 0.0);
 }
 
-// Pack the cell block of [[K, -TE], [TH, K]] (from 3 x N x N row-major) into
-// a column-major n x n matrix with identity padding.
-__global__ void pack_zmm_kernel(const double2* __restrict__ ops, int N, int n, double2* __restrict__ Z) {
+// Self blocks of a group of cells (blockIdx.z: cell cell0 + z): the cell's
+// [[K, -TE], [TH, K]] as a column-major n x n matrix with identity padding,
+// each RWG entry the sum over the two triangles of either RWG of the
+// triangle-local entries (local blocks [K, TE, TH], each 3 nt x 3 nt
+// row-major; signs and lengths are inside them).
+__global__ void cell_zmm_kernel(const double2* __restrict__ local, const CellJob* __restrict__ jobs, int cell0,
+                                const int32_t* __restrict__ tplus, const int32_t* __restrict__ tminus,
+                                const int32_t* __restrict__ aplus, const int32_t* __restrict__ aminus, int n,
+                                double2* __restrict__ Zpad) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
   if (r >= n) return;
+  const int b = cell0 + (int)blockIdx.z;
+  const CellJob jb = jobs[b];
+  const int N = jb.N;
   double2 v = make_double2(r == c ? 1.0 : 0.0, 0.0);
   if (r < 2 * N && c < 2 * N) {
     const int br = r / N, bc = c / N, rr = r % N, cc = c % N;
-    const int64_t NN = (int64_t)N * N;
-    // [[K, -TE], [TH, K]] with ops = [K, TE, TH]
     const int op = (br == bc) ? 0 : (br == 0 ? 1 : 2);
-    v = ops[op * NN + (int64_t)rr * N + cc];
-    if (br == 0 && bc == 1) {
-      v.x = -v.x;
-      v.y = -v.y;
-    }
+    const int64_t ldl = 3 * (int64_t)jb.nt, op_stride = ldl * ldl;
+    const int32_t em = jb.edges[rr], en = jb.edges[cc];
+    const int64_t ri[2] = {3 * (int64_t)jb.pos[tplus[em]] + aplus[em], 3 * (int64_t)jb.pos[tminus[em]] + aminus[em]};
+    const int64_t ci[2] = {3 * (int64_t)jb.pos[tplus[en]] + aplus[en], 3 * (int64_t)jb.pos[tminus[en]] + aminus[en]};
+    const double2* L = local + jb.loff + op * op_stride;
+    double re = 0, im = 0;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const double2 e = L[ri[x] * ldl + ci[y]];
+        re += e.x;
+        im += e.y;
+      }
+    v = (br == 0 && bc == 1) ? make_double2(-re, -im) : make_double2(re, im);
   }
-  Z[(int64_t)c * n + r] = v;
+  Zpad[(int64_t)b * n * n + (int64_t)c * n + r] = v;
 }
 
-// Pack the generating right-hand sides of a cell: column c of the n x s
-// column-major block is [v^E(edges); v^H(edges); 0].
-__global__ void pack_v_kernel(const double2* __restrict__ v, int64_t ne, const int32_t* __restrict__ ed, int N,
-                              int n, double2* __restrict__ out) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+// The generating right-hand sides of every cell (blockIdx.z: cell): column c
+// of the cell's n x S column-major block is [v^E(edges); v^H(edges); 0].
+__global__ void cell_v_kernel(const double2* __restrict__ v, int64_t ne, const CellJob* __restrict__ jobs, int n,
+                              int S, double2* __restrict__ Vpad) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y, b = blockIdx.z;
   if (r >= n) return;
+  const CellJob jb = jobs[b];
   double2 x = make_double2(0.0, 0.0);
-  if (r < N)
-    x = v[(int64_t)c * 2 * ne + ed[r]];
-  else if (r < 2 * N)
-    x = v[(int64_t)c * 2 * ne + ne + ed[r - N]];
-  out[(int64_t)c * n + r] = x;
+  if (r < jb.N)
+    x = v[(int64_t)c * 2 * ne + jb.edges[r]];
+  else if (r < 2 * jb.N)
+    x = v[(int64_t)c * 2 * ne + ne + jb.edges[r - jb.N]];
+  Vpad[((int64_t)b * S + c) * n + r] = x;
 }
 
-// From a cell's solved currents J = [J^M; J^J] (column-major n x S, the
-// magnetic rows first), write (J^M)^H and (J^J)^H as column-major S x Nmax
-// matrices (blockIdx.z picks which), zero beyond the cell's N columns.
-__global__ void pack_jh_kernel(const double2* __restrict__ J, int n, int S, int N, int Nmax,
+// From every cell's solved currents J = [J^M; J^J] (column-major n x S per
+// cell, the magnetic rows first), write (J^M)^H and (J^J)^H as column-major
+// S x Nmax matrices (blockIdx.z = 2 cell + which), zero beyond the cell's N
+// columns.
+__global__ void pack_jh_kernel(const double2* __restrict__ J, int n, int S, const int32_t* __restrict__ Ns, int Nmax,
                                double2* __restrict__ out) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y, w = blockIdx.z;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y, b = blockIdx.z >> 1, w = blockIdx.z & 1;
   if (r >= S) return;
+  const int N = Ns[b];
   double2 x = make_double2(0.0, 0.0);
   if (c < N) {
-    x = J[(int64_t)r * n + w * N + c];
+    x = J[((int64_t)b * S + r) * n + w * N + c];
     x.y = -x.y;
   }
-  out[(int64_t)w * S * Nmax + (int64_t)c * S + r] = x;
+  out[((int64_t)(2 * b + w) * Nmax + c) * S + r] = x;
 }
 
 __device__ inline double wave_sum(double x) {
@@ -567,6 +599,7 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
     int Nmax = 0;
     for (int b = 0; b < nb; ++b) Nmax = std::max<int>(Nmax, (int)(h.cell_off[b + 1] - h.cell_off[b]));
     const int n = 2 * Nmax;
+    CBFM_REQUIRE(nb <= 32767 && n <= 65535, CBFM_E_ARG, "above 32767 cells or 32767 RWGs in one cell");
     // generating right-hand sides on all edges
     Scratch vgen((size_t)S * 2 * h.ne * sizeof(double2), s);
     Scratch dinc((size_t)S * 6 * sizeof(double), s);
@@ -575,72 +608,92 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
     // per-cell Z_mm (padded, column-major) and V_m
     Scratch Zpad((size_t)nb * n * n * sizeof(double2), s);
     Scratch Vpad((size_t)nb * n * S * sizeof(double2), s);
-    Scratch ops((size_t)3 * Nmax * Nmax * sizeof(double2), s);
-    // index staging for every cell, uploaded once
     std::vector<CellSupport> cs = supports(h, nb);
-    size_t ibytes = 0;
-    for (int b = 0; b < nb; ++b)
-      ibytes += 4 * (cs[b].tris.size() + cs[b].pos.size() + cs[b].edges.size()) + sizeof(NearPair) * cs[b].near.size();
+    // groups of cells whose triangle-local blocks fit in at most 1 GiB (or
+    // one cell), filled together; each cell's blocks at loff[b] elements
+    size_t maxloc = 0;
+    for (int b = 0; b < nb; ++b) maxloc = std::max(maxloc, cs[b].tris.size());
+    const size_t group_bytes = std::max<size_t>((size_t)1 << 30, (size_t)27 * maxloc * maxloc * sizeof(double2));
+    std::vector<int> gstart{0};
+    std::vector<size_t> gbytes;
+    std::vector<int64_t> loff(nb);
+    {
+      size_t bytes = 0;
+      for (int b = 0; b < nb; ++b) {
+        const size_t cb = (size_t)27 * cs[b].tris.size() * cs[b].tris.size() * sizeof(double2);
+        if (b > gstart.back() && bytes + cb > group_bytes) {
+          gbytes.push_back(bytes);
+          gstart.push_back(b);
+          bytes = 0;
+        }
+        loff[b] = (int64_t)(bytes / sizeof(double2));
+        bytes += cb;
+      }
+      gbytes.push_back(bytes);
+      gstart.push_back(nb);
+    }
+    // index staging for every cell, uploaded once: support lists, the near
+    // pairs of all cells in one array (each tagged with its cell), and the
+    // per-cell tables of the batched launches
+    std::vector<int64_t> noff(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) noff[b + 1] = noff[b] + (int64_t)cs[b].near.size();
+    auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
+    size_t ibytes = al(sizeof(NearPair) * noff[nb]) + al(sizeof(CellJob) * nb) + al(sizeof(NearOut) * nb);
+    for (int b = 0; b < nb; ++b) ibytes += al(4 * cs[b].tris.size()) + al(4 * cs[b].pos.size()) + al(4 * cs[b].edges.size());
     std::vector<char> host(ibytes);
     Scratch idx(ibytes, s);
     size_t o = 0;
-    struct Ptrs {
-      int32_t *tris, *pos, *edges;
-      NearPair* near;
-    };
-    std::vector<Ptrs> ptr(nb);
     auto put = [&](const void* src, size_t bytes) {
-      std::memcpy(host.data() + o, src, bytes);
+      if (bytes) std::memcpy(host.data() + o, src, bytes);
       void* d = idx.as<char>() + o;
-      o += bytes;
+      o += al(bytes);
       return d;
     };
-    size_t maxloc = 0;
+    std::vector<const int32_t*> dtris(nb);
+    std::vector<CellJob> jobs(nb);
+    std::vector<NearOut> nouts(nb);
     for (int b = 0; b < nb; ++b) {
-      ptr[b].tris = (int32_t*)put(cs[b].tris.data(), 4 * cs[b].tris.size());
-      ptr[b].pos = (int32_t*)put(cs[b].pos.data(), 4 * cs[b].pos.size());
-      ptr[b].edges = (int32_t*)put(cs[b].edges.data(), 4 * cs[b].edges.size());
-      ptr[b].near = (NearPair*)put(cs[b].near.data(), sizeof(NearPair) * cs[b].near.size());
-      maxloc = std::max(maxloc, cs[b].tris.size());
+      const int64_t nt_b = (int64_t)cs[b].tris.size();
+      dtris[b] = (const int32_t*)put(cs[b].tris.data(), 4 * cs[b].tris.size());
+      jobs[b].pos = (const int32_t*)put(cs[b].pos.data(), 4 * cs[b].pos.size());
+      jobs[b].edges = (const int32_t*)put(cs[b].edges.data(), 4 * cs[b].edges.size());
+      jobs[b].loff = loff[b];
+      jobs[b].nt = (int32_t)nt_b;
+      jobs[b].N = (int32_t)cs[b].edges.size();
+      nouts[b] = {loff[b], 9 * nt_b * nt_b, 3 * nt_b};
+      for (NearPair& q : cs[b].near) q.pad = b;
     }
+    NearPair* dnear = (NearPair*)(idx.as<char>() + o);
+    for (int b = 0; b < nb; ++b) {
+      std::memcpy(host.data() + o, cs[b].near.data(), sizeof(NearPair) * cs[b].near.size());
+      o += sizeof(NearPair) * cs[b].near.size();
+    }
+    o = al(o);
+    const CellJob* djobs = (const CellJob*)put(jobs.data(), sizeof(CellJob) * nb);
+    const NearOut* douts = (const NearOut*)put(nouts.data(), sizeof(NearOut) * nb);
+    CBFM_REQUIRE(o == ibytes, CBFM_E_HIP, "cell index staging size mismatch");
     CBFM_HIP(hipMemcpyAsync(idx.p, host.data(), ibytes, hipMemcpyHostToDevice, s));
-    // the cells' self blocks: regular pairs of a group of cells in one
-    // persistent launch (groups of at most 1 GiB of triangle-local scratch),
-    // then per cell the near pairs, the assembly and the packing
-    const size_t group_bytes = std::max<size_t>((size_t)1 << 30, (size_t)27 * maxloc * maxloc * sizeof(double2));
-    for (int g0 = 0; g0 < nb;) {
-      int g1 = g0;
-      size_t bytes = 0;
-      std::vector<size_t> loff;
-      while (g1 < nb) {
-        const size_t cb = (size_t)27 * cs[g1].tris.size() * cs[g1].tris.size() * sizeof(double2);
-        if (g1 > g0 && bytes + cb > group_bytes) break;
-        loff.push_back(bytes);
-        bytes += cb;
-        ++g1;
-      }
-      Scratch local(bytes, s);
+    // the cells' self blocks, a group at a time: regular pairs in one
+    // persistent launch, the near pairs of all the group's cells in one
+    // launch pair, then assembly and packing of every cell in one launch
+    for (size_t g = 0; g + 1 < gstart.size(); ++g) {
+      const int g0 = gstart[g], g1 = gstart[g + 1];
+      Scratch local(gbytes[g], s);
       std::vector<FillBatchItem> items;
       for (int b = g0; b < g1; ++b) {
         const int64_t nt_b = cs[b].tris.size();
-        items.push_back({m, md, CBFM_LAYOUT_OPS3, ptr[b].tris, nt_b, ptr[b].tris, nt_b, local.as<char>() + loff[b - g0]});
+        items.push_back({m, md, CBFM_LAYOUT_OPS3, dtris[b], nt_b, dtris[b], nt_b, local.as<double2>() + loff[b]});
       }
       fill_regular_batch(items, CBFM_FP64, s);
-      for (int b = g0; b < g1; ++b) {
-        const int Nb = (int)cs[b].edges.size();
-        const int64_t nt_b = cs[b].tris.size();
-        void* lb = local.as<char>() + loff[b - g0];
-        fill_near(m, md, CBFM_FP64, CBFM_LAYOUT_OPS3, ptr[b].near, (int64_t)cs[b].near.size(), nt_b, nt_b, lb, s);
-        assemble(m, CBFM_FP64, lb, nt_b, nt_b, ptr[b].edges, Nb, ptr[b].edges, Nb, ptr[b].pos, ptr[b].pos, ops.p,
-                 (int64_t)Nb * Nb, Nb, s);
-        double2* Zb = Zpad.as<double2>() + (size_t)b * n * n;
-        hipLaunchKernelGGL(pack_zmm_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, ops.as<double2>(), Nb, n, Zb);
-        hipLaunchKernelGGL(pack_v_kernel, dim3((n + 255) / 256, S), dim3(256), 0, s, vgen.as<double2>(), h.ne,
-                           ptr[b].edges, Nb, n, Vpad.as<double2>() + (size_t)b * n * S);
-        CBFM_HIP(hipGetLastError());
-      }
-      g0 = g1;
+      fill_near_batch(m, md, CBFM_LAYOUT_OPS3, dnear + noff[g0], noff[g1] - noff[g0], douts + g0, g0, local.p, s);
+      hipLaunchKernelGGL(cell_zmm_kernel, dim3((n + 255) / 256, n, g1 - g0), dim3(256), 0, s, local.as<double2>(),
+                         djobs, g0, m->tplus.as<int32_t>(), m->tminus.as<int32_t>(), m->aplus.as<int32_t>(),
+                         m->aminus.as<int32_t>(), n, Zpad.as<double2>());
+      CBFM_HIP(hipGetLastError());
     }
+    hipLaunchKernelGGL(cell_v_kernel, dim3((n + 255) / 256, S, nb), dim3(256), 0, s, vgen.as<double2>(), h.ne, djobs,
+                       n, S, Vpad.as<double2>());
+    CBFM_HIP(hipGetLastError());
     // LU solves Z_mm J_m = V_m
     Scratch piv((size_t)nb * n * sizeof(rocblas_int), s);
     Scratch info((size_t)nb * sizeof(rocblas_int), s);
@@ -665,11 +718,8 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
     Scratch dN((size_t)nb * sizeof(int32_t), s);
     CBFM_HIP(hipMemcpyAsync(dN.p, hN.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, s));
     Scratch QA((size_t)nb * 2 * S * Nmax * sizeof(double2), s);
-    for (int b = 0; b < nb; ++b) {
-      hipLaunchKernelGGL(pack_jh_kernel, dim3((S + 255) / 256, Nmax, 2), dim3(256), 0, s,
-                         Vpad.as<double2>() + (size_t)b * n * S, n, S, hN[b], Nmax,
-                         QA.as<double2>() + (size_t)b * 2 * S * Nmax);
-    }
+    hipLaunchKernelGGL(pack_jh_kernel, dim3((S + 255) / 256, Nmax, 2 * nb), dim3(256), 0, s, Vpad.as<double2>(), n,
+                       S, dN.as<int32_t>(), Nmax, QA.as<double2>());
     Scratch Rf((size_t)nb * 2 * rk * Nmax * sizeof(double2), s);  // per cell R_M, then R_J
     hipLaunchKernelGGL(cell_qr_kernel, dim3(2 * nb), dim3(1024), (size_t)S * sizeof(double2), s, QA.as<double2>(), S,
                        Nmax, dN.as<int32_t>(), rk, Rf.as<double2>());
@@ -679,15 +729,14 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
     Scratch Gm((size_t)nb * Nmax * Nmax * sizeof(double2), s);
     Scratch T2((size_t)nb * Nmax * rk * sizeof(double2), s);
     Scratch core((size_t)nb * rk * rk * sizeof(double2), s);
+    hipLaunchKernelGGL(cell_gram_kernel, dim3((Nmax + 255) / 256, Nmax, nb), dim3(256), 0, s, djobs, Nmax,
+                       m->tplus.as<int32_t>(), m->tminus.as<int32_t>(), m->aplus.as<int32_t>(), m->aminus.as<int32_t>(),
+                       m->tri_edge.as<int32_t>(), m->tri_sign.as<int32_t>(), m->length.as<double>(), Gm.as<double2>());
     std::vector<GemmDesc> d1, d2;
     for (int b = 0; b < nb; ++b) {
       const int Nb = hN[b];
       const double2* R = Rf.as<double2>() + (size_t)b * 2 * rk * Nmax;
       double2* G = Gm.as<double2>() + (size_t)b * Nmax * Nmax;
-      hipLaunchKernelGGL(cell_gram_kernel, dim3((Nb + 255) / 256, Nb), dim3(256), 0, s, ptr[b].edges, Nb,
-                         m->tplus.as<int32_t>(), m->tminus.as<int32_t>(), m->aplus.as<int32_t>(),
-                         m->aminus.as<int32_t>(), m->tri_edge.as<int32_t>(), m->tri_sign.as<int32_t>(),
-                         m->length.as<double>(), G);
       double2* t2 = T2.as<double2>() + (size_t)b * Nmax * rk;
       d1.push_back(gemm(G, Nb, OP_N, R, Nmax, OP_T, t2, rk, Nb, rk, Nb));
       d2.push_back(gemm(R + (size_t)rk * Nmax, Nmax, OP_R, t2, rk, OP_N, core.as<double2>() + (size_t)b * rk * rk, rk,

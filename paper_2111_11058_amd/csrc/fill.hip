@@ -593,10 +593,17 @@ __global__ void __launch_bounds__(64) near_outer_kernel(const double* __restrict
                                                         const double* __restrict__ cl64, int64_t nt,
                                                         const NearPair* __restrict__ near, int64_t nnear, FillConsts fc,
                                                         const cd* __restrict__ buf, cx<R>* __restrict__ out,
-                                                        int64_t op_stride, int64_t ldl) {
+                                                        int64_t op_stride, int64_t ldl,
+                                                        const NearOut* __restrict__ outs, int cell0) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nnear) return;
   const NearPair np = near[t];
+  if (outs) {  // batched: the pair's own block
+    const NearOut ob = outs[np.pad - cell0];
+    out += ob.off;
+    op_stride = ob.op_stride;
+    ldl = ob.ldl;
+  }
   const int P = np.p, Q = np.q;
   double vp[3][3], vq[3][3], ca[3], cb[3];
   for (int a = 0; a < 3; ++a) {
@@ -653,7 +660,7 @@ __global__ void __launch_bounds__(64) near_outer_kernel(const double* __restrict
 
 template <typename R>
 static void near_stage(const cbfm_mesh_s* m, const FillConsts& fc, const NearPair* near, int64_t nnear, cx<R>* out,
-                       int64_t op_stride, int64_t ldl, hipStream_t s) {
+                       int64_t op_stride, int64_t ldl, hipStream_t s, const NearOut* outs = nullptr, int cell0 = 0) {
   if (nnear == 0) return;
   Scratch buf((size_t)nnear * 7 * NEAR_VALS * sizeof(cd), s);
   hipLaunchKernelGGL(near_inner_kernel, dim3((unsigned)((nnear * 7 + 63) / 64)), dim3(64), 0, s, m->tri_xyz.as<double>(),
@@ -661,7 +668,7 @@ static void near_stage(const cbfm_mesh_s* m, const FillConsts& fc, const NearPai
   CBFM_HIP(hipGetLastError());
   hipLaunchKernelGGL((near_outer_kernel<R>), dim3((unsigned)((nnear + 63) / 64)), dim3(64), 0, s, m->tri_xyz.as<double>(),
                      m->area.as<double>(), m->c64.as<double>(), m->h.nt, near, nnear, fc, buf.as<cd>(), out, op_stride,
-                     ldl);
+                     ldl, outs, cell0);
   CBFM_HIP(hipGetLastError());
 }
 
@@ -711,6 +718,13 @@ void fill_near(const cbfm_mesh_s* m, const Media& md, int precision, int layout,
     near_stage(m, fc, near, nnear, static_cast<cx<double>*>(local), op_stride, ldl, s);
   else
     near_stage(m, fc, near, nnear, static_cast<cx<float>*>(local), op_stride, ldl, s);
+}
+
+void fill_near_batch(const cbfm_mesh_s* m, const Media& md, int layout, const NearPair* near, int64_t nnear,
+                     const NearOut* outs, int cell0, void* local, hipStream_t s) {
+  const FillConsts fc = make_consts(md, layout);
+  TimedLaunch tn(T_FILL_NEAR, s, (double)nnear);  // work: near pairs
+  near_stage(m, fc, near, nnear, static_cast<cx<double>*>(local), 0, 0, s, outs, cell0);
 }
 
 template <typename R>

@@ -509,11 +509,11 @@ static int64_t number_tiles_x(const std::vector<GemmDescX>& in, std::vector<Gemm
 // Element types of a group's operands (bit 1: A is complex double, bit 0:
 // B is); every product of one launch has the same pair, which the kernel
 // takes as template arguments so that its loads carry no run-time choice.
-static int operand_types(const std::vector<GemmDescX>& g) {
-  if (g.empty()) return 0;
+static int operand_types(const GemmDescX* g, size_t count) {
+  if (count == 0) return 0;
   const int ab = (g[0].a64 ? 2 : 0) | (g[0].b64 ? 1 : 0);
-  for (const GemmDescX& d : g)
-    CBFM_REQUIRE(((d.a64 ? 2 : 0) | (d.b64 ? 1 : 0)) == ab, CBFM_E_ARG,
+  for (size_t i = 0; i < count; ++i)
+    CBFM_REQUIRE(((g[i].a64 ? 2 : 0) | (g[i].b64 ? 1 : 0)) == ab, CBFM_E_ARG,
                  "mixed operand element types in one batched GEMM launch");
   return ab;
 }
@@ -562,7 +562,7 @@ void xgemm_batched(std::vector<GemmDescX>& descs, int mode, hipStream_t s) {
   double flops = 0;
   const int64_t tiles = number_tiles_x(descs, live, &flops);
   if (live.empty()) return;
-  const int ab = operand_types(live);
+  const int ab = operand_types(live.data(), live.size());
   Scratch dev(live.size() * sizeof(GemmDescX), s);
   CBFM_HIP(hipMemcpyAsync(dev.p, live.data(), live.size() * sizeof(GemmDescX), hipMemcpyHostToDevice, s));
   launch_x(dev.as<GemmDescX>(), (int)live.size(), tiles, flops, mode, ab, s);
@@ -583,7 +583,7 @@ XGemmPlan::XGemmPlan(const std::vector<std::vector<GemmDescX>>& groups, int mode
     tiles_.push_back(number_tiles_x(g, all, &f));
     flops_.push_back(f);
     count_.push_back((int64_t)all.size() - first_.back());
-    types_.push_back(operand_types(std::vector<GemmDescX>(all.begin() + first_.back(), all.end())));
+    types_.push_back(operand_types(all.data() + first_.back(), (size_t)count_.back()));
   }
   if (!all.empty()) {
     CBFM_HIP(hipMemcpyAsync(dev_.p, all.data(), all.size() * sizeof(GemmDescX), hipMemcpyHostToDevice, s));
@@ -660,9 +660,7 @@ struct GemmKey {
 static std::mutex g_tune_mu;
 static std::map<GemmKey, int> g_tuned;  // launch shape measured fastest, per shape class
 
-static GemmKey key_of(const GemmDesc* d, int count, int64_t tiles) {
-  int dev = 0;
-  CBFM_HIP(hipGetDevice(&dev));
+static GemmKey key_of(int dev, const GemmDesc* d, int count, int64_t tiles) {
   int64_t K = 0;
   for (int i = 0; i < count; ++i) K = std::max(K, d[i].K);
   return GemmKey{dev, count, d[0].opA, d[0].opB, tiles, d[0].M, d[0].N, K};
@@ -753,8 +751,10 @@ void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s) {
   if (live.empty()) return;
   Scratch dev(live.size() * sizeof(GemmDesc), s);
   CBFM_HIP(hipMemcpyAsync(dev.p, live.data(), live.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
+  int d = 0;
+  CBFM_HIP(hipGetDevice(&d));
   launch_descs(dev.as<GemmDesc>(), (int)live.size(), tiles, live[0].M, live[0].N, flops,
-               choose(key_of(live.data(), (int)live.size(), tiles)), s);
+               choose(key_of(d, live.data(), (int)live.size(), tiles)), s);
   // the descriptor staging buffer is host memory of this frame
   CBFM_HIP(hipStreamSynchronize(s));
 }
@@ -778,6 +778,10 @@ GemmPlan::GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t
     CBFM_HIP(hipMemcpyAsync(dev_.p, all.data(), all.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
     CBFM_HIP(hipStreamSynchronize(s));  // `all` is host memory of this frame
   }
+  int dev = 0;
+  CBFM_HIP(hipGetDevice(&dev));
+  GemmKey last{-1, 0, 0, 0, 0, 0, 0, 0};  // groups of one shape class (such as the
+  int last_variant = GV_TILE4;             // per-Krylov-index matvecs) share one choice
   for (size_t g = 0; g < groups.size(); ++g) {
     m_.push_back(count_[g] > 0 ? all[first_[g]].M : 0);
     n_.push_back(count_[g] > 0 ? all[first_[g]].N : 0);
@@ -785,9 +789,15 @@ GemmPlan::GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t
       variant_.push_back(GV_TILE4);
       continue;
     }
-    const GemmKey k = key_of(all.data() + first_[g], (int)count_[g], tiles_[g]);
+    const GemmKey k = key_of(dev, all.data() + first_[g], (int)count_[g], tiles_[g]);
+    if (last.dev >= 0 && !(k < last) && !(last < k)) {
+      variant_.push_back(last_variant);
+      continue;
+    }
     if (tune_ && rerunnable(groups[g])) tune_group(k, dev_.as<GemmDesc>() + first_[g], (int)count_[g], tiles_[g], s);
-    variant_.push_back(choose(k));
+    last = k;
+    last_variant = choose(k);
+    variant_.push_back(last_variant);
   }
 }
 

@@ -122,7 +122,7 @@ struct NearPair {
   int32_t p, q;     // triangles
   int32_t i, j;     // positions in the row / column triangle lists
   int32_t coplanar; // K of the pair is zero
-  int32_t pad;
+  int32_t pad;      // batched near-pair launches: the block the pair belongs to
 };
 
 struct MeshHost {
@@ -208,6 +208,14 @@ struct FillBatchItem {
 void fill_regular_batch(const std::vector<FillBatchItem>& items, int precision, hipStream_t s);
 void fill_near(const cbfm_mesh_s* m, const Media& md, int precision, int layout, const NearPair* near, int64_t nnear,
                int64_t nrt, int64_t nct, void* local, hipStream_t s);
+// The near pairs of several FP64 local blocks in one launch pair: pair t
+// (device arrays) writes into block outs[near[t].pad - cell0], which starts
+// outs[...].off elements into `local`.
+struct NearOut {
+  int64_t off, op_stride, ldl;
+};
+void fill_near_batch(const cbfm_mesh_s* m, const Media& md, int layout, const NearPair* near, int64_t nnear,
+                     const NearOut* outs, int cell0, void* local, hipStream_t s);
 void fill_local(const cbfm_mesh_s* m, const Media& md, int precision, int layout,
                 const int32_t* rowTris_dev, int64_t nrt, const int32_t* colTris_dev, int64_t nct,
                 const NearPair* near_dev, int64_t nnear, void* local, hipStream_t s);
