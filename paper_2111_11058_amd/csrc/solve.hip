@@ -142,7 +142,8 @@ __global__ void sub_from_kernel(const double2* __restrict__ b, double2* __restri
 // Column j-1 is final after the correction, so the Givens rotations and the
 // convergence test run one iteration behind the matrix-vector product.
 struct GmresState {
-  double2* R;       // rotated Hessenberg (upper triangular): column j, row i at [(j * (m + 1) + i) * nrhs + c]
+  double2* R;       // rotated Hessenberg (upper triangular), per right-hand side: column j, row i at
+                    // [c * (m + 1) * m + j * (m + 1) + i]
   double2* H;       // Hessenberg matrix of the final basis, by rows: row l, column i at [(l * m + i) * nrhs + c]
   double2* cs;      // [c * m + i]
   double2* sn;      // [c * m + i]
@@ -415,7 +416,7 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
 #pragma unroll
     for (int u = 0; u < KR; ++u) {
       if (ib + u >= i1) break;
-      st.R[(col + ib + u) * nrhs + c] = cadd(cmul(c2[u], a), cmul(s2[u], b2[u]));
+      st.R[c * (m + 1) * m + col + ib + u] = cadd(cmul(c2[u], a), cmul(s2[u], b2[u]));
       a = cadd(cmul(make_double2(-s2[u].x, s2[u].y), a), cmul(make_double2(c2[u].x, -c2[u].y), b2[u]));
     }
   }
@@ -436,7 +437,7 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
   }
   cs[jc] = cc;
   sn[jc] = ss;
-  st.R[(col + jc) * nrhs + c] = make_double2(den, 0);
+  st.R[c * (m + 1) * m + col + jc] = make_double2(den, 0);
   // g[jc+1] = -conj(s) g[jc];  g[jc] = c g[jc]
   const double2 gn = make_double2(-(ss.x * gj.x + ss.y * gj.y), -(ss.x * gj.y - ss.y * gj.x));
   st.g[(jc + 1) * nrhs + c] = gn;
@@ -626,12 +627,13 @@ __global__ void __launch_bounds__(256) backsolve_kernel(GmresState st, int64_t m
   __shared__ double2 T[BS][BS + 1];  // T[r][q] = R[b0 + r][b0 + q], q >= r
   __shared__ double2 yb[BS];         // solved values of the block
   const int tid = threadIdx.x;
+  const double2* Rc = st.R + c * (m + 1) * m;  // this right-hand side's R, column-major
   for (int64_t b1 = k; b1 > 0; b1 -= BS) {
     const int64_t b0 = b1 > BS ? b1 - BS : 0;
     const int nb = (int)(b1 - b0);
     for (int e = tid; e < nb * nb; e += 256) {
-      const int r = e / nb, q = e % nb;
-      if (q >= r) T[r][q] = st.R[((b0 + q) * (m + 1) + b0 + r) * nrhs + c];
+      const int q = e / nb, r = e % nb;  // consecutive threads: consecutive rows of column q
+      if (q >= r) T[r][q] = Rc[(b0 + q) * (m + 1) + b0 + r];
     }
     __syncthreads();
     if (tid < 64) {
@@ -657,7 +659,7 @@ __global__ void __launch_bounds__(256) backsolve_kernel(GmresState st, int64_t m
     for (int64_t t = tid; t < b0; t += 256) {
       double2 h[BS];
 #pragma unroll
-      for (int q = 0; q < BS; ++q) h[q] = st.R[((b0 + (q < nb ? q : 0)) * (m + 1) + t) * nrhs + c];
+      for (int q = 0; q < BS; ++q) h[q] = Rc[(b0 + (q < nb ? q : 0)) * (m + 1) + t];
       double2 acc = make_double2(0, 0);
 #pragma unroll
       for (int q = 0; q < BS; ++q)
@@ -689,7 +691,23 @@ __global__ void __launch_bounds__(512) x_update_kernel(GmresState st, const TV* 
     kk[r] = k < n ? k : 0;  // rows past n: a valid row, discarded
   }
   const TV* base = V + c * n;
-  for (int64_t i = wv; i < kc; i += 8) {
+  int64_t i = wv;
+  // four basis vectors at a time: their loads go out together (the sums
+  // still take the vectors in order)
+  for (; i + 24 < kc; i += 32) {
+    double2 a[4], v[4][RPL];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = st.g[(i + 8 * u) * nrhs + c];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) v[u][r] = ld2(base + (i + 8 * u) * vstride + kk[r]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) acc[r] = cadd(acc[r], cmul(a[u], v[u][r]));
+  }
+  for (; i < kc; i += 8) {
     const double2 a = st.g[i * nrhs + c];
     double2 v[RPL];
 #pragma unroll
