@@ -480,7 +480,13 @@ __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, in
     __shared__ double2 shp[7][64];
     const int64_t hb = (int64_t)blockIdx.x - nub;
     const int64_t ng = (nrhs + 63) / 64;
-    const int64_t l = hb / ng, c = (hb % ng) * 64 + lane;
+    // lanes: cw right-hand sides (a power of two, at least nrhs when nrhs <
+    // 64) times 64 / cw column offsets, so that few right-hand sides still
+    // fill the wavefront; with 64 or more, one column offset per lane group
+    int cw = 64;
+    while (cw > 1 && cw / 2 >= nrhs) cw >>= 1;
+    const int sub = 64 / cw, lc = lane & (cw - 1), li = lane / cw;
+    const int64_t l = hb / ng, c = (hb % ng) * 64 + lc;
     if (l > j) return;  // graph replays launch the rows of the longest column
     const bool on = c < nrhs && st.active[c];
     const int64_t cc = on ? c : 0;  // idle lanes read valid entries and discard them
@@ -490,21 +496,24 @@ __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, in
     double2 acc[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[u] = make_double2(0, 0);
-    for (int64_t ib = lo + wv; ib < j; ib += 32) {
+    const int64_t istep = 8 * (int64_t)sub;  // column stride of one unrolled load
+    for (int64_t ib = lo + wv * sub + li; ib < j; ib += 4 * istep) {
       double2 hv[4], av[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int64_t i = ib + 8 * u < j ? ib + 8 * u : ib;
+        const int64_t i = ib + istep * u < j ? ib + istep * u : ib;
         hv[u] = Hl[i * nrhs];
         av[u] = a[i * nrhs];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] = ib + 8 * u < j ? cadd(acc[u], cmul(hv[u], av[u])) : acc[u];
+      for (int u = 0; u < 4; ++u) acc[u] = ib + istep * u < j ? cadd(acc[u], cmul(hv[u], av[u])) : acc[u];
     }
     double2 p = cadd(cadd(acc[0], acc[1]), cadd(acc[2], acc[3]));
+    for (int off = cw; off < 64; off <<= 1)  // the column offsets of one right-hand side
+      p = make_double2(p.x + __shfl_xor(p.x, off, 64), p.y + __shfl_xor(p.y, off, 64));
     if (wv > 0) shp[wv - 1][lane] = p;
     __syncthreads();
-    if (wv > 0 || !on) return;
+    if (wv > 0 || !on || li != 0) return;
     for (int v = 0; v < 7; ++v) p = cadd(p, shp[v][lane]);
     const double ig = 1.0 / st.gam[c];
     const double2 b = st.d2[l * nrhs + c];
@@ -533,7 +542,27 @@ __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, in
     kk[r] = k < n ? k : 0;  // rows past n: a valid row, discarded
   }
   const TV* base = V + c * n;
-  for (int64_t i = wv; i < j; i += 8) {
+  int64_t i = wv;
+  // four basis vectors at a time: their loads go out together (the sums
+  // still take the vectors in order)
+  for (; i + 24 < j; i += 32) {
+    double2 a[4], b[4], v[4][RPL];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = d1[(i + 8 * u) * nrhs + c];
+      b[u] = d2[(i + 8 * u) * nrhs + c];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) v[u][r] = ld2(base + (i + 8 * u) * vstride + kk[r]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        s1[r] = cadd(s1[r], cmul(a[u], v[u][r]));
+        s2[r] = cadd(s2[r], cmul(b[u], v[u][r]));
+      }
+  }
+  for (; i < j; i += 8) {
     const double2 a = d1[i * nrhs + c], b = d2[i * nrhs + c];
     double2 v[RPL];
 #pragma unroll
