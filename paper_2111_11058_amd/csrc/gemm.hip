@@ -623,13 +623,71 @@ static int64_t number_tiles(const std::vector<GemmDesc>& in, std::vector<GemmDes
   return tiles;
 }
 
+// A single matrix-vector product (N = 1, rows of op(A) contiguous: op N or
+// conj) on the vector units: the tiled kernels would pad the one column to
+// 16 and spend sixteen times the matrix-core work.  One wavefront per row,
+// lanes along the row, four loads in flight per lane, the row sum by a
+// butterfly; alpha and accumulation as in the tiled kernel.
+__global__ void __launch_bounds__(256) zgemv_kernel(const GemmDesc* __restrict__ desc) {
+  const int lane = threadIdx.x & 63;
+  GemmDesc d = desc[0];
+  d.M = uniform64(d.M);
+  d.K = uniform64(d.K);
+  d.lda = uniform64(d.lda);
+  d.ldb = uniform64(d.ldb);
+  d.ldc = uniform64(d.ldc);
+  d.opA = __builtin_amdgcn_readfirstlane(d.opA);
+  d.opB = __builtin_amdgcn_readfirstlane(d.opB);
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= d.M) return;  // uniform over the wavefront
+  const double sgA = d.opA == OP_R ? -1.0 : 1.0;
+  const double sgB = (d.opB == OP_C || d.opB == OP_R) ? -1.0 : 1.0;
+  const int64_t sx = (d.opB == OP_T || d.opB == OP_C) ? 1 : d.ldb;  // x_k = B[k sx]
+  const double2* ar = d.A + row * d.lda;
+  double re = 0, im = 0;
+  for (int64_t k0 = lane; k0 < d.K; k0 += 256) {
+    double2 a[4], x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = k0 + 64 * u;
+      a[u] = ld_global(k < d.K ? ar + k : g_zero2);
+      x[u] = ld_global(k < d.K ? d.B + k * sx : g_zero2);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double ax = a[u].x, ay = sgA * a[u].y, xx = x[u].x, xy = sgB * x[u].y;
+      re += ax * xx - ay * xy;
+      im += ax * xy + ay * xx;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  if (lane == 0) {
+    double2 v = make_double2(d.alpha_re * re - d.alpha_im * im, d.alpha_re * im + d.alpha_im * re);
+    double2* p = d.transC ? d.C + row : d.C + row * d.ldc;  // column 0
+    if (d.accumulate) {
+      const double2 o = ld_global(p);
+      v.x += o.x;
+      v.y += o.y;
+    }
+    *p = v;
+  }
+}
+
 // Launch shapes: four tiles per block (one per wavefront), or one tile per
 // block with K split over 4 or 8 wavefronts; for a single product also
 // tiles of 2 or 4 adjacent 16-column blocks with K split over 4 wavefronts
-// (op(A) read once for them; with 8 wavefronts they would spill).
-enum { GV_TILE4 = 0, GV_SPLIT4, GV_SPLIT8, GV_WIDE2_S4, GV_WIDE4_S4, GV_COUNT };
+// (op(A) read once for them; with 8 wavefronts they would spill), and for a
+// single matrix-vector product the vector-unit kernel.
+enum { GV_TILE4 = 0, GV_SPLIT4, GV_SPLIT8, GV_WIDE2_S4, GV_WIDE4_S4, GV_GEMV, GV_COUNT };
 
 static bool single_only(int v) { return v >= GV_WIDE2_S4; }
+
+// The vector-unit kernel takes one column with op(A) rows contiguous.
+static bool gemv_shape(int64_t N, int opA) { return N == 1 && (opA == OP_N || opA == OP_R); }
 
 // tiles: 16 x 16 tiles of the group; M, N: the sizes of its product when it
 // has one (the wide shapes number their own tiles)
@@ -639,6 +697,9 @@ static void launch_variant(int v, const GemmDesc* dev, int count, int64_t tiles,
   auto wide = [&](int ct) { return ((M + 15) / 16) * ((N + 16 * ct - 1) / (16 * ct)); };
   CBFM_REQUIRE(!single_only(v) || count == 1, CBFM_E_ARG, "wide GEMM tiles need a single product");
   switch (v) {
+    case GV_GEMV:
+      hipLaunchKernelGGL(zgemv_kernel, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, s, dev);
+      break;
     case GV_TILE4:
       hipLaunchKernelGGL((zgemm_batched_kernel<1, 1>), dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, dev, count,
                          tiles);
@@ -731,6 +792,7 @@ static void tune_group(const GemmKey& key, const GemmDesc* dev, int count, int64
   try {
     for (int v = 0; v < GV_COUNT; ++v) {
       if (single_only(v) && count != 1) continue;
+      if (v == GV_GEMV && !gemv_shape(key.N, key.opA)) continue;
       launch_variant(v, dev, count, tiles, key.M, key.N, s);
       CBFM_HIP(hipEventRecord(e0, s));
       for (int r = 0; r < 3; ++r) launch_variant(v, dev, count, tiles, key.M, key.N, s);
