@@ -187,7 +187,7 @@ __global__ void cycle_init_kernel(GmresState st, int64_t m, int64_t nrhs, double
 // wavefronts per right-hand side and run of four basis vectors; the
 // threads take every 256th row, the loads of all four vectors of a row go
 // out together, and the wavefronts are summed through LDS in a fixed order.
-template <typename TV>
+template <typename TV, bool UNR>
 __global__ void __launch_bounds__(256) dots2_kernel(const TV* __restrict__ V, int64_t vstride,
                                                     const TV* __restrict__ w, int64_t n, int64_t nrhs, int64_t j,
                                                     GmresState st, const int64_t* __restrict__ jp) {
@@ -206,7 +206,28 @@ __global__ void __launch_bounds__(256) dots2_kernel(const TV* __restrict__ V, in
   double2 s1[4], s2[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) s1[t] = s2[t] = make_double2(0, 0);
-  for (int64_t k = threadIdx.x; k < n; k += 256) {
+  int64_t k = threadIdx.x;
+  // UNR: four rows per lane at a time, their loads issued together (the
+  // sums still take the rows in order), for long vectors and few blocks;
+  // it needs more registers, which would cost occupancy otherwise
+  for (; UNR && k + 768 < n; k += 1024) {
+    double2 x[4], y[4], v[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[u] = ld2(qj + k + 256 * u);
+      y[u] = ld2(wc + k + 256 * u);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) v[u][t] = ld2(qi + (t < cnt ? t : 0) * vstride + k + 256 * u);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        s1[t] = cadd(s1[t], cconjmul(v[u][t], x[u]));
+        s2[t] = cadd(s2[t], cconjmul(v[u][t], y[u]));
+      }
+  }
+  for (; k < n; k += 256) {
     const double2 x = ld2(qj + k), y = ld2(wc + k);
     double2 v[4];
 #pragma unroll
@@ -925,8 +946,12 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
     {
       // work: bytes of q_0..q_j and w for every right-hand side
       TimedLaunch tl(T_GMRES_DOTS, q, vb * (double)(j + 2) * (double)nrhs * (double)n);
-      hipLaunchKernelGGL(dots2_kernel<TV>, dim3((unsigned)((jg + 4) / 4 * nrhs)), dim3(256), 0, q, V, vstride, w, n,
-                         nrhs, j, gs, jp);
+      if (n >= 2048 && nrhs < 16)
+        hipLaunchKernelGGL((dots2_kernel<TV, true>), dim3((unsigned)((jg + 4) / 4 * nrhs)), dim3(256), 0, q, V,
+                           vstride, w, n, nrhs, j, gs, jp);
+      else
+        hipLaunchKernelGGL((dots2_kernel<TV, false>), dim3((unsigned)((jg + 4) / 4 * nrhs)), dim3(256), 0, q, V,
+                           vstride, w, n, nrhs, j, gs, jp);
     }
     hipLaunchKernelGGL(column_kernel, dim3((unsigned)nrhs), dim3(256), 0, q, gs, mres, j, nrhs, 1, jp);
     {
