@@ -165,7 +165,45 @@ struct GmresState {
   double2* d2t;     // b_i, beta
   double2* hc;      // the newest column of H (rows 0..j+1)
   int64_t ms;       // m + 1
+  // few right-hand sides: the update pass splits the basis range of each
+  // 128-row block over `split` blocks, which leave their sums (128 rows x
+  // the two sums) in ws at [((c np + rb) split + part) 256 + 128 s + 64 r +
+  // lane]; dcgs_finish_kernel adds them in part order and completes the
+  // update
+  int split;
+  double2* ws;
 };
+
+// The end of the update of 128 rows of one right-hand side (one wavefront,
+// RPL = 2 rows per lane) once s1 = sum a_l q_l and s2 = sum b_l q_l are
+// known: q_j <- (q_j - s1) / gamma, w <- (w - s2) / gamma - c_j q_j, and
+// the partial sum of |w|^2 of these rows.
+template <typename TV>
+__device__ inline void finish_rows(TV* V, int64_t vstride, TV* w, int64_t n, int64_t nrhs, int64_t j, int64_t c,
+                                   int64_t rb, int np, const GmresState& st, const double2 (&s1)[2],
+                                   const double2 (&s2)[2], double* part, int lane) {
+  const double ig = 1.0 / st.gam[c];
+  const double2 beta = st.d2[j * nrhs + c], ab = st.ab[c];
+  const double2 cj = cscale(make_double2(beta.x - ab.x, beta.y - ab.y), ig * ig);
+  double q2 = 0;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int64_t k = (rb * 2 + r) * 64 + lane;
+    if (k < n) {
+      TV* qj = V + j * vstride + c * n + k;
+      const double2 qo = ld2(qj);
+      const double2 qn = cscale(make_double2(qo.x - s1[r].x, qo.y - s1[r].y), ig);
+      st2(qj, qn);
+      const double2 wo = ld2(w + c * n + k);
+      const double2 t = cmul(cj, qn);
+      const double2 wn = make_double2((wo.x - s2[r].x) * ig - t.x, (wo.y - s2[r].y) * ig - t.y);
+      st2(w + c * n + k, wn);
+      q2 += wn.x * wn.x + wn.y * wn.y;
+    }
+  }
+  q2 = wave_sum(q2);
+  if (lane == 0) part[c * np + rb] = q2;
+}
 
 // Start a cycle: g = beta e1, active = beta/bnorm > tol, kc = 0; the cycle
 // stops at the residual norm max(tol bnorm, inner beta) (inner = 0: at tol;
@@ -496,7 +534,8 @@ __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, in
                                                           double* __restrict__ part, const int64_t* __restrict__ jp) {
   if (jp) j = *jp;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t nub = (int64_t)np * nrhs;  // update blocks
+  const int S = st.split;
+  const int64_t nub = (int64_t)np * nrhs * S;  // update blocks
   if ((int64_t)blockIdx.x >= nub) {
     __shared__ double2 shp[7][64];
     const int64_t hb = (int64_t)blockIdx.x - nub;
@@ -549,8 +588,9 @@ __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, in
     st.hc[c * st.ms + l] = h;
     return;
   }
-  constexpr int RPL = 2;  // rows per lane
-  const int64_t c = (int64_t)blockIdx.x / np, rb = (int64_t)blockIdx.x % np;
+  constexpr int RPL = 2;  // rows per lane (finish_rows takes two)
+  const int part_id = (int)(blockIdx.x % S);
+  const int64_t c = (int64_t)(blockIdx.x / S) / np, rb = (int64_t)(blockIdx.x / S) % np;
   if (c >= nrhs || !st.active[c]) return;  // uniform over the block
   const double2* d1 = st.d1;
   const double2* d2 = st.d2;
@@ -563,17 +603,19 @@ __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, in
     kk[r] = k < n ? k : 0;  // rows past n: a valid row, discarded
   }
   const TV* base = V + c * n;
-  int64_t i = wv;
+  // this block's basis vectors: i = 8 (part + S t) + wavefront
+  const int64_t istep = 8 * (int64_t)S;
+  int64_t i = wv + 8 * (int64_t)part_id;
   // four basis vectors at a time: their loads go out together (the sums
   // still take the vectors in order)
-  for (; i + 24 < j; i += 32) {
+  for (; i + 3 * istep < j; i += 4 * istep) {
     double2 a[4], b[4], v[4][RPL];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      a[u] = d1[(i + 8 * u) * nrhs + c];
-      b[u] = d2[(i + 8 * u) * nrhs + c];
+      a[u] = d1[(i + istep * u) * nrhs + c];
+      b[u] = d2[(i + istep * u) * nrhs + c];
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) v[u][r] = ld2(base + (i + 8 * u) * vstride + kk[r]);
+      for (int r = 0; r < RPL; ++r) v[u][r] = ld2(base + (i + istep * u) * vstride + kk[r]);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -583,7 +625,7 @@ __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, in
         s2[r] = cadd(s2[r], cmul(b[u], v[u][r]));
       }
   }
-  for (; i < j; i += 8) {
+  for (; i < j; i += istep) {
     const double2 a = d1[i * nrhs + c], b = d2[i * nrhs + c];
     double2 v[RPL];
 #pragma unroll
@@ -604,31 +646,46 @@ __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, in
   }
   __syncthreads();
   if (wv > 0) return;
-  const double ig = 1.0 / st.gam[c];
-  const double2 beta = d2[j * nrhs + c], ab = st.ab[c];
-  const double2 cj = cscale(make_double2(beta.x - ab.x, beta.y - ab.y), ig * ig);
-  double q2 = 0;
 #pragma unroll
-  for (int r = 0; r < RPL; ++r) {
+  for (int r = 0; r < RPL; ++r)
     for (int t = 0; t < 7; ++t) {
       s1[r] = cadd(s1[r], sh[t][r][lane][0]);
       s2[r] = cadd(s2[r], sh[t][r][lane][1]);
     }
-    const int64_t k = (rb * RPL + r) * 64 + lane;
-    if (k < n) {
-      TV* qj = V + j * vstride + c * n + k;
-      const double2 qo = ld2(qj);
-      const double2 qn = cscale(make_double2(qo.x - s1[r].x, qo.y - s1[r].y), ig);
-      st2(qj, qn);
-      const double2 wo = ld2(w + c * n + k);
-      const double2 t = cmul(cj, qn);
-      const double2 wn = make_double2((wo.x - s2[r].x) * ig - t.x, (wo.y - s2[r].y) * ig - t.y);
-      st2(w + c * n + k, wn);
-      q2 += wn.x * wn.x + wn.y * wn.y;
+  if (S > 1) {  // dcgs_finish_kernel completes the update
+    double2* mine = st.ws + (((c * np + rb) * S) + part_id) * 256;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      mine[64 * r + lane] = s1[r];
+      mine[128 + 64 * r + lane] = s2[r];
+    }
+    return;
+  }
+  finish_rows(V, vstride, w, n, nrhs, j, c, rb, np, st, s1, s2, part, lane);
+}
+
+// The update of a split pass: one wavefront per 128-row block of a
+// right-hand side adds the parts' sums in part order and completes it.
+template <typename TV>
+__global__ void __launch_bounds__(64) dcgs_finish_kernel(TV* __restrict__ V, int64_t vstride, TV* __restrict__ w,
+                                                          int64_t n, int64_t nrhs, int64_t j, int np, GmresState st,
+                                                          double* __restrict__ part, const int64_t* __restrict__ jp) {
+  if (jp) j = *jp;
+  const int lane = threadIdx.x;
+  const int64_t c = (int64_t)blockIdx.x / np, rb = (int64_t)blockIdx.x % np;
+  if (c >= nrhs || !st.active[c]) return;
+  const int S = st.split;
+  const double2* sums = st.ws + (c * np + rb) * S * 256;
+  double2 s1[2], s2[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    s1[r] = s2[r] = make_double2(0, 0);
+    for (int q = 0; q < S; ++q) {
+      s1[r] = cadd(s1[r], sums[q * 256 + 64 * r + lane]);
+      s2[r] = cadd(s2[r], sums[q * 256 + 128 + 64 * r + lane]);
     }
   }
-  q2 = wave_sum(q2);
-  if (lane == 0) part[c * np + rb] = q2;
+  finish_rows(V, vstride, w, n, nrhs, j, c, rb, np, st, s1, s2, part, lane);
 }
 
 // nu = sqrt(sum of the np partial sums of |w|^2); H[j+1][j] = nu and
@@ -960,8 +1017,11 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
       const double hr = (double)j + 0.5 * (double)j * (double)(j + 1);
       TimedLaunch tl(T_GMRES_UPDATE, q, (vb * (double)(j + 4) * (double)n + 16.0 * hr) * (double)nrhs);
       const int64_t nhb = (jg + 1) * ng;
-      hipLaunchKernelGGL(dcgs_update_kernel<TV>, dim3((unsigned)(nhb + (int64_t)np * nrhs)), dim3(512), 0, q, V,
-                         vstride, w, n, nrhs, mres, j, np, gs, part, jp);
+      hipLaunchKernelGGL(dcgs_update_kernel<TV>, dim3((unsigned)(nhb + (int64_t)np * nrhs * gs.split)), dim3(512), 0,
+                         q, V, vstride, w, n, nrhs, mres, j, np, gs, part, jp);
+      if (gs.split > 1)
+        hipLaunchKernelGGL(dcgs_finish_kernel<TV>, dim3((unsigned)((int64_t)np * nrhs)), dim3(64), 0, q, V, vstride, w,
+                           n, nrhs, j, np, gs, part, jp);
     }
     hipLaunchKernelGGL(normalize_kernel<TV>, grid2(n, nrhs), dim3(256), 0, q, w, V, vstride, n, part, np, gs, mres, j,
                        nrhs, jp);
@@ -1104,6 +1164,10 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
         gb(cbytes, s), d1b(cbytes, s), d2b(cbytes, s), d1t(cbytes, s), d2t(cbytes, s), hcb(cbytes, s),
         abb(nrhs * sizeof(double2), s), dbl(5 * nrhs * sizeof(double), s), ints(3 * nrhs * sizeof(int32_t), s),
         part(nrhs * np * sizeof(double), s);
+    // few 128-row update blocks (a single right-hand side): the basis range
+    // of each is split over up to 8 blocks, so that about 256 blocks stream
+    const int split = nrhs == 1 && np < 64 ? (int)std::min<int64_t>(8, (256 + np - 1) / np) : 1;
+    Scratch wsb(split > 1 ? (size_t)nrhs * np * split * 256 * sizeof(double2) : 0, s);
     GmresState gs{Rs.as<double2>(),
                   Hs.as<double2>(),
                   csb.as<double2>(),
@@ -1123,7 +1187,9 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
                   d1t.as<double2>(),
                   d2t.as<double2>(),
                   hcb.as<double2>(),
-                  mres + 1};
+                  mres + 1,
+                  split,
+                  wsb.as<double2>()};
     const int64_t vstride = nrhs * n;
     const dim3 g1((unsigned)((nrhs + 63) / 64)), b1(64);
     CBFM_HIP(hipMemsetAsync(x.p, 0, nrhs * n * sizeof(double2), s));
