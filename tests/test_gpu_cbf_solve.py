@@ -209,6 +209,17 @@ def test_graph_replayed_solve_matches_eager(torch_cuda):
         assert g["status"] == "OK" and np.array_equal(g["iters"], e["iters"])
         assert _rel(jg.cpu().numpy(), ref) < 1e-13
         _ = Zr.sum().item()  # eager work between the graph solves
+    # a single right-hand side (its own update-pass split and matrix-vector
+    # kernel), eager and replayed, against the first column of the batch
+    inc1 = np.ascontiguousarray(w.inc[:1])
+    j1 = torch_cuda.zeros((1, ne2), dtype=torch_cuda.complex128, device="cuda")
+    e1 = cbfm.solve(mesh, med, cbf, Zr, inc1, tol=1e-12, max_iter=n + 10, restart=n + 10, j_out=j1)
+    assert e1["status"] == "OK" and _rel(j1.cpu().numpy(), ref[:1]) < 1e-9
+    j1g = torch_cuda.zeros((1, ne2), dtype=torch_cuda.complex128, device="cuda")
+    g1 = cbfm.solve(mesh, med, cbf, Zr, inc1, tol=1e-12, max_iter=n + 10, restart=n + 10, j_out=j1g, use_graph=True)
+    print("single graph solve", g1["iters"], e1["iters"])
+    assert g1["status"] == "OK" and np.array_equal(g1["iters"], e1["iters"])
+    assert _rel(j1g.cpu().numpy(), j1.cpu().numpy()) < 1e-13
     # the mixed form: float cycles refined in double, one graph per cycle
     jg = torch_cuda.zeros((nr, ne2), dtype=torch_cuda.complex128, device="cuda")
     g = cbfm.solve(mesh, med, cbf, Zr, w.inc, tol=1e-11, max_iter=4 * n, restart=n, j_out=jg, use_graph=True,
