@@ -516,14 +516,17 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
 // update does not wait for p:
 //   q_j <- (q_j - sum_{i<j} a_i q_i) / gamma
 //   w   <- (w - sum_{i<j} b_i q_i) / gamma - c_j q_j(new)
-// Blocks [0, np nrhs): eight wavefronts take 128 consecutive rows (two per
-// lane) of one right-hand side, wavefront v summing over the basis vectors
-// i = v mod 8; wavefront 0 combines the partial sums in a fixed order and
-// stores the row block's sum of |w|^2 in part.
-// Blocks from np nrhs on: row l of column j, for 64 right-hand
-// sides (lane = right-hand side); the eight wavefronts take every eighth
-// column of the row (contiguous in H), four columns in flight each, summed
-// in a fixed order.  These latency-bound blocks come last, where they fill
+// Blocks [0, np nrhs split): eight wavefronts take 128 consecutive rows (two
+// per lane) of one right-hand side, wavefront v summing over the basis
+// vectors i = v mod 8 (with split > 1, part p of the row block over those
+// with i / 8 = p mod split); wavefront 0 combines the partial sums in a
+// fixed order and completes the update, storing the row block's sum of
+// |w|^2 in part (with split > 1, dcgs_finish_kernel does this).
+// Blocks from np nrhs split on: row l of column j; the lanes take up to 64
+// right-hand sides and, when there are fewer, several column offsets each
+// (added by a butterfly); the eight wavefronts take interleaved columns of
+// the row (contiguous in H), four columns in flight each, summed in a fixed
+// order.  These latency-bound blocks come last, where they fill
 // the tail of the streaming; placed first they held CUs the update blocks
 // needed, and cutting the rows into parts or running them as a separate
 // launch or stream measured slower too.
