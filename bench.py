@@ -72,6 +72,8 @@ def workload(name):
         return configs.sphere_c3()
     if name == "cylinder19968":
         return configs.cylinder_c5()
+    if name == "sphere_array4x4x2":
+        return configs.sphere_array()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -256,7 +258,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cube1728", choices=["cube1728", "sphere320", "sphere5120", "cylinder19968"])
+    ap.add_argument("--workload", default="cube1728", choices=["cube1728", "sphere320", "sphere5120", "cylinder19968",
+                                                                "sphere_array4x4x2"])
     ap.add_argument("--cpu-sample", type=int, default=250000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the precision-form legs (FP32 fill, mixed FP32 and split-BF16)")
@@ -301,7 +304,7 @@ def main():
     state = {}
 
     def step(precision, inner_fp32=False):
-        cb = cbfm.build_cbf(mesh, med, w.gen, w.delta_svd)
+        cb = cbfm.build_cbf(mesh, med, w.gen, w.delta_svd, max_L=w.extra.get("max_L", 0))
         n = cb.n_cbf
         Zr = state.get(n)
         if Zr is None:
@@ -362,6 +365,15 @@ def main():
         "roofline_kernels": roofs,
         "flop_per_pair": FLOP_PER_PAIR,
     }
+    if w.extra.get("max_L"):
+        # the paper's comparison on its array: the same CBFs solved without
+        # the CMP (the K-diagonal CBFM without G^CBF), full GMRES up to 1000
+        # iterations
+        nc = state[cb.n_cbf]
+        o = cbfm.solve(mesh, med, cb, nc, w.inc, use_cmp=False, max_iter=1000, restart=1000, **solver)
+        result["without_cmp"] = {"gmres_iterations_max": int(o["iters"].max()), "status": o["status"],
+                                 "relres_max": float(o["relres"].max())}
+        log(f"without CMP: {result['without_cmp']}")
     if not args.no_fp32:
         # the precision forms on the same workload: FP32 regular fill with the
         # FP64 projection and solve; and the mixed forms (FP32 fill, FP32 or

@@ -16,7 +16,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .blocks import octant_blocks, rcb_blocks
-from .meshes import cube, cylinder, geodesic, icosphere
+from .meshes import cube, cylinder, edges_canonical, geodesic, icosphere
 
 ETA0 = 376.730313668  # free-space wave impedance (ohm); passed to both sides
 
@@ -113,6 +113,30 @@ def cylinder_c5() -> Workload:
     inc = np.concatenate([-r, t], axis=1)
     return Workload("cylinder19968_er3", V, T, rcb_blocks(V, T, 96), 96, 3.0 + 0j, 1.0 + 0j,
                     inc, generating_set())
+
+
+def sphere_array(nx: int = 4, ny: int = 4, nz: int = 2, pitch: float = 0.5, eps_r: complex = 3.0 + 0j) -> Workload:
+    """The paper's sphere array (Sec. IV-A, 4 x 4 x 2 spheres): copies of the
+    single-cell sphere (radius lambda/6, 320 triangles, 960 unknowns) at a
+    centre pitch of lambda/2 along x, y and z, centred on the origin; one
+    cell per sphere; one theta-polarised wave travelling along -z (x
+    polarisation); the Table I generating waves.  The paper keeps 70 CBFs per
+    current per cell (the singular-value groups l = 1..5): ``extra["max_L"]``
+    and ``delta_svd = 0``."""
+    V0, T0 = icosphere(2, 1.0 / 6.0)
+    Vs, Ts = [], []
+    for ix in range(nx):
+        for iy in range(ny):
+            for iz in range(nz):
+                off = pitch * np.array([ix - (nx - 1) / 2, iy - (ny - 1) / 2, iz - (nz - 1) / 2])
+                Ts.append(T0 + len(V0) * len(Vs))
+                Vs.append(V0 + off)
+    V, T = np.concatenate(Vs), np.concatenate(Ts).astype(T0.dtype)
+    # an edge's cell is the sphere of its vertices
+    blocks = (edges_canonical(T)[:, 0] // len(V0)).astype(np.int32)
+    return Workload(f"sphere_array{nx}x{ny}x{nz}_er{eps_r.real:g}", V, T, blocks, nx * ny * nz, eps_r, 1.0 + 0j,
+                    np.array([[0, 0, -1, 1, 0, 0]], dtype=np.float64), generating_set(), delta_svd=0.0,
+                    extra={"max_L": 70})
 
 
 def small_cylinder(K=2, n_h=4, nblocks=4, eps_r=3.0 + 0j) -> Workload:
