@@ -16,6 +16,9 @@ struct cbfm_cbf_s {
   cbfm::DevBuf CM, CJ;         // per cell N_b x L_b row-major double2, cell after cell
   std::vector<double> sigma;   // kept singular values, cell after cell
   cbfm::DevBuf d_L, d_off, d_coff, d_cell_off, d_edge_block;
+  // no triangle carries RWGs of two cells (disjoint bodies, one or more per
+  // cell): the RWG Gram couples no two cells and B is block-diagonal by cell
+  bool blockdiag = false;
   // B^{-1} for B = (C^M)^H G C^J (row-major), formed on first use
   std::mutex mu;
   bool factored = false;

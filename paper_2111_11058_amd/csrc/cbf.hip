@@ -449,6 +449,15 @@ void cbf_finish(cbfm_cbf_s* c) {
     c->coff[b + 1] = c->coff[b] + (h.cell_off[b + 1] - h.cell_off[b]) * (int64_t)c->L[b];
   }
   c->NL = c->off[h.nblocks];
+  std::vector<int32_t> tcell(h.nt, -1);
+  c->blockdiag = true;
+  for (int64_t e = 0; e < h.ne && c->blockdiag; ++e)
+    for (const int32_t t : {h.tplus[e], h.tminus[e]}) {
+      if (tcell[t] < 0)
+        tcell[t] = h.edge_block[e];
+      else if (tcell[t] != h.edge_block[e])
+        c->blockdiag = false;
+    }
   c->d_L.upload(c->L);
   c->d_off.upload(c->off);
   c->d_coff.upload(c->coff);
@@ -456,9 +465,28 @@ void cbf_finish(cbfm_cbf_s* c) {
   c->d_edge_block.upload(h.edge_block);
 }
 
+// Diagonal blocks of a block-diagonal B (row-major NL x NL, cell a at rows
+// and columns off[a] .. off[a] + L[a]) to or from a stack of Lmax x Lmax
+// row-major blocks padded with the identity (blockIdx.z = cell).
+__global__ void cmp_blocks_kernel(double2* __restrict__ B, int64_t NL, const int64_t* __restrict__ off,
+                                  const int32_t* __restrict__ L, int Lmax, double2* __restrict__ P, int to_stack) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y, a = blockIdx.z;
+  if (j >= Lmax) return;
+  const int La = L[a];
+  double2* p = P + ((int64_t)a * Lmax + i) * Lmax + j;
+  const bool in = i < La && j < La;
+  double2* b = B + (off[a] + (in ? i : 0)) * NL + off[a] + (in ? j : 0);
+  if (to_stack)
+    *p = in ? *b : make_double2(i == j ? 1.0 : 0.0, 0.0);
+  else if (in)
+    *b = *p;
+}
+
 // B^{-1} for B = (C^M)^H G C^J.  rocSOLVER works column-major, so it sees
 // M = B^T; LU + inversion of M leaves M^{-1} = (B^{-1})^T in column-major
-// order, i.e. B^{-1} in the row-major layout used here.
+// order, i.e. B^{-1} in the row-major layout used here.  A block-diagonal B
+// is inverted block by block (one batched call; the blocks off the diagonal
+// are exact zeros and stay so).
 static void cmp_factor(cbfm_cbf_s* c, hipStream_t s) {
   const cbfm_mesh_s* m = c->mesh;
   const MeshHost& h = m->h;
@@ -479,6 +507,36 @@ static void cmp_factor(cbfm_cbf_s* c, hipStream_t s) {
                       OP_N, c->Binv.as<double2>() + c->off[a] * NL, NL, c->L[a], NL, Na));
   }
   zgemm_batched(ds, s);
+  if (c->blockdiag) {
+    const int nb = h.nblocks;
+    const int Lmax = *std::max_element(c->L.begin(), c->L.end());
+    Scratch P((size_t)nb * Lmax * Lmax * sizeof(double2), s), ipiv((size_t)nb * Lmax * sizeof(rocblas_int), s),
+        info((size_t)2 * nb * sizeof(rocblas_int), s);
+    const dim3 g((unsigned)((Lmax + 63) / 64), (unsigned)Lmax, (unsigned)nb);
+    hipLaunchKernelGGL(cmp_blocks_kernel, g, dim3(64), 0, s, c->Binv.as<double2>(), NL, c->d_off.as<int64_t>(),
+                       c->d_L.as<int32_t>(), Lmax, P.as<double2>(), 1);
+    CBFM_HIP(hipGetLastError());
+    {
+      std::lock_guard<std::mutex> lk(blas_mutex());
+      rocblas_handle bh = blas_handle(s);
+      const rocblas_stride sA = (rocblas_stride)Lmax * Lmax, sP = Lmax;
+      CBFM_RS(rocsolver_zgetrf_strided_batched(bh, Lmax, Lmax, (rocblas_double_complex*)P.p, Lmax, sA,
+                                               ipiv.as<rocblas_int>(), sP, info.as<rocblas_int>(), nb));
+      CBFM_RS(rocsolver_zgetri_strided_batched(bh, Lmax, (rocblas_double_complex*)P.p, Lmax, sA,
+                                               ipiv.as<rocblas_int>(), sP, info.as<rocblas_int>() + nb, nb));
+    }
+    hipLaunchKernelGGL(cmp_blocks_kernel, g, dim3(64), 0, s, c->Binv.as<double2>(), NL, c->d_off.as<int64_t>(),
+                       c->d_L.as<int32_t>(), Lmax, P.as<double2>(), 0);
+    CBFM_HIP(hipGetLastError());
+    std::vector<rocblas_int> hinfo(2 * nb);
+    CBFM_HIP(hipMemcpyAsync(hinfo.data(), info.p, hinfo.size() * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+    CBFM_HIP(hipStreamSynchronize(s));
+    for (int a = 0; a < 2 * nb; ++a)
+      CBFM_REQUIRE(hinfo[a] == 0, CBFM_E_RANK,
+                   "G^CBF is singular (cell " + std::to_string(a % nb) + ", zero pivot " + std::to_string(hinfo[a]) + ")");
+    c->factored = true;
+    return;
+  }
   Scratch ipiv(NL * sizeof(rocblas_int), s);
   Scratch info(2 * sizeof(rocblas_int), s);
   {

@@ -1144,8 +1144,18 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
     Scratch Ap(use_cmp ? n * n * sizeof(double2) : 0, s);
     if (use_cmp) {
       const double2* Bi = cmp_inverse(c, s);
-      std::vector<GemmDesc> ds{gemm(Zr, ldz, OP_N, Bi, NL, OP_C, Ap.as<double2>(), n, n, NL, NL, -1.0),
-                               gemm(Zr + NL, ldz, OP_N, Bi, NL, OP_N, Ap.as<double2>() + NL, n, n, NL, NL)};
+      std::vector<GemmDesc> ds;
+      if (c->blockdiag) {  // B^{-1} block-diagonal: each cell's columns take its own block
+        for (int a = 0; a < h.nblocks; ++a) {
+          const int64_t o = c->off[a], La = c->L[a];
+          const double2* Ba = Bi + o * NL + o;
+          ds.push_back(gemm(Zr + o, ldz, OP_N, Ba, NL, OP_C, Ap.as<double2>() + o, n, n, La, La, -1.0));
+          ds.push_back(gemm(Zr + NL + o, ldz, OP_N, Ba, NL, OP_N, Ap.as<double2>() + NL + o, n, n, La, La));
+        }
+      } else {
+        ds.push_back(gemm(Zr, ldz, OP_N, Bi, NL, OP_C, Ap.as<double2>(), n, n, NL, NL, -1.0));
+        ds.push_back(gemm(Zr + NL, ldz, OP_N, Bi, NL, OP_N, Ap.as<double2>() + NL, n, n, NL, NL));
+      }
       zgemm_batched(ds, s);
       Aop = Ap.as<double2>();
       lda = n;
