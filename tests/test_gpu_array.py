@@ -58,3 +58,29 @@ def test_array_cells_share_cbf_spans(array_run):
         for m in range(1, len(C)):
             x, *_ = np.linalg.lstsq(C0, C[m], rcond=None)
             assert np.linalg.norm(C[m] - C0 @ x) < 1e-8 * np.linalg.norm(C[m]), m
+
+
+def test_array_permittivity_sweep():
+    """Iterations to 1e-4 against eps_r (Sec. IV-A): with the CMP they grow
+    with eps_r, and they are a small fraction of those of the K-diagonal CBFM
+    without it (the paper: 1/5 at eps_r = 6 to 1/70 at eps_r = 1)."""
+    import torch
+    from paper_2111_11058_amd import cbfm
+    from synth import configs
+    its, ratios = [], []
+    for er in (1.0, 3.0, 6.0):
+        w = configs.sphere_array(eps_r=er + 0j)
+        print(f"sphere array eps_r {er}", flush=True)
+        mesh = cbfm.Mesh(w.V, w.T, w.edge_block, w.nblocks)
+        med = cbfm.Medium.make(w.k0, w.eta0, w.eps_r, w.mu_r)
+        cb = cbfm.build_cbf(mesh, med, w.gen, w.delta_svd, max_L=w.extra["max_L"])
+        Zr = torch.zeros((cb.n_cbf, cb.n_cbf), dtype=torch.complex128, device="cuda")
+        cbfm.project(mesh, med, cb, Zr, cbfm.FP64)
+        a = cbfm.solve(mesh, med, cb, Zr, w.inc, tol=1e-4, max_iter=3000, restart=3000, use_cmp=True)
+        b = cbfm.solve(mesh, med, cb, Zr, w.inc, tol=1e-4, max_iter=3000, restart=3000, use_cmp=False)
+        assert a["status"] == "OK" and b["status"] == "OK"
+        its.append(int(a["iters"][0]))
+        ratios.append(b["iters"][0] / a["iters"][0])
+    print("iterations with CMP", its, "reduction", ratios)
+    assert its[0] < its[1] < its[2]
+    assert ratios[0] > ratios[1] > ratios[2] >= 5 and ratios[0] >= 70
