@@ -115,15 +115,17 @@ def cylinder_c5() -> Workload:
                     inc, generating_set())
 
 
-def sphere_array(nx: int = 4, ny: int = 4, nz: int = 2, pitch: float = 0.5, eps_r: complex = 3.0 + 0j) -> Workload:
+def sphere_array(nx: int = 4, ny: int = 4, nz: int = 2, pitch: float = 0.5, eps_r: complex = 3.0 + 0j,
+                 level: int = 2) -> Workload:
     """The paper's sphere array (Sec. IV-A, 4 x 4 x 2 spheres): copies of the
     single-cell sphere (radius lambda/6, 320 triangles, 960 unknowns) at a
     centre pitch of lambda/2 along x, y and z, centred on the origin; one
     cell per sphere; one theta-polarised wave travelling along -z (x
     polarisation); the Table I generating waves.  The paper keeps 70 CBFs per
     current per cell (the singular-value groups l = 1..5): ``extra["max_L"]``
-    and ``delta_svd = 0``."""
-    V0, T0 = icosphere(2, 1.0 / 6.0)
+    and ``delta_svd = 0``.  ``level`` < 2 gives coarser spheres (level 1: 80
+    triangles) for tests small enough for the oracle."""
+    V0, T0 = icosphere(level, 1.0 / 6.0)
     Vs, Ts = [], []
     for ix in range(nx):
         for iy in range(ny):

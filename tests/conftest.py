@@ -32,6 +32,8 @@ def oracle_problem(name):
         w = configs.sphere_c1()
     elif name == "cyl_small":
         w = configs.small_cylinder()
+    elif name == "array2":
+        w = configs.sphere_array(2, 1, 1, level=1)
     else:
         raise KeyError(name)
     m = mesh.build(w.V, w.T)

@@ -89,6 +89,36 @@ def test_cmp_apply_parity(torch_cuda):
     assert _rel(yt.cpu().numpy(), ref) < 1e-10
 
 
+def test_disjoint_cells_block_cmp_parity(torch_cuda):
+    """Two disjoint spheres, one per cell: no triangle carries RWGs of both
+    cells, so G^CBF is block-diagonal and the library inverts it block by
+    block and forms the preconditioned operator per cell.  The CMP apply and
+    the CMP-preconditioned solve against the oracle's dense G^CBF and LU."""
+    from oracle import excitation
+    O = _oracle_cbf("array2")
+    P = O["P"]
+    w, m = P["w"], P["m"]
+    cbfm, mesh, med, cbf = _gpu_handles(w, O)
+    n = cbf.n_cbf
+    NL = n // 2
+    assert np.allclose(O["Gc"][:NL, :NL][:cbf.L[0], cbf.L[0]:], 0.0)  # the oracle's B couples no cells
+    rng = np.random.default_rng(12)
+    y = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    yt = torch_cuda.tensor(y, dtype=torch_cuda.complex128, device="cuda")
+    xt = torch_cuda.empty_like(yt)
+    cbfm.cmp_apply(cbf, yt, xt)
+    assert _rel(xt.cpu().numpy(), np.linalg.solve(O["Gc"], y.T).T) < 1e-10
+    Zr = torch_cuda.zeros((n, n), dtype=torch_cuda.complex128, device="cuda")
+    cbfm.project(mesh, med, cbf, Zr, cbfm.FP64)
+    jt = torch_cuda.zeros((len(w.inc), 2 * m.ne), dtype=torch_cuda.complex128, device="cuda")
+    out = cbfm.solve(mesh, med, cbf, Zr, w.inc, tol=1e-12, max_iter=n + 10, restart=n + 10, use_cmp=True, j_out=jt)
+    assert out["status"] == "OK"
+    jref = O["CMJ"] @ np.linalg.solve(O["Zr"], O["vr"])
+    assert _rel(jt.cpu().numpy().T, jref) < 1e-9
+    rcs_ref = excitation.monostatic_rcs(m, jref, w.inc, w.k0, w.eta0)
+    assert np.max(np.abs(out["rcs"] - rcs_ref) / rcs_ref) < 1e-9
+
+
 @pytest.mark.parametrize("name", ["c1", "cyl_small"])
 def test_build_cbf_invariants(torch_cuda, name):
     """CBFs are unique only up to unitary mixing inside degenerate singular
