@@ -530,14 +530,14 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
 // the tail of the streaming; placed first they held CUs the update blocks
 // needed, and cutting the rows into parts or running them as a separate
 // launch or stream measured slower too.
-template <typename TV>
+template <typename TV, bool SPLIT>
 __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, int64_t vstride,
                                                           TV* __restrict__ w, int64_t n, int64_t nrhs, int64_t m,
                                                           int64_t j, int np, GmresState st,
                                                           double* __restrict__ part, const int64_t* __restrict__ jp) {
   if (jp) j = *jp;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int S = st.split;
+  const int S = SPLIT ? st.split : 1;
   const int64_t nub = (int64_t)np * nrhs * S;  // update blocks
   if ((int64_t)blockIdx.x >= nub) {
     __shared__ double2 shp[7][64];
@@ -655,7 +655,7 @@ __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, in
       s1[r] = cadd(s1[r], sh[t][r][lane][0]);
       s2[r] = cadd(s2[r], sh[t][r][lane][1]);
     }
-  if (S > 1) {  // dcgs_finish_kernel completes the update
+  if (SPLIT) {  // dcgs_finish_kernel completes the update
     double2* mine = st.ws + (((c * np + rb) * S) + part_id) * 256;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
@@ -1020,11 +1020,15 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
       const double hr = (double)j + 0.5 * (double)j * (double)(j + 1);
       TimedLaunch tl(T_GMRES_UPDATE, q, (vb * (double)(j + 4) * (double)n + 16.0 * hr) * (double)nrhs);
       const int64_t nhb = (jg + 1) * ng;
-      hipLaunchKernelGGL(dcgs_update_kernel<TV>, dim3((unsigned)(nhb + (int64_t)np * nrhs * gs.split)), dim3(512), 0,
-                         q, V, vstride, w, n, nrhs, mres, j, np, gs, part, jp);
-      if (gs.split > 1)
+      if (gs.split > 1) {
+        hipLaunchKernelGGL((dcgs_update_kernel<TV, true>), dim3((unsigned)(nhb + (int64_t)np * nrhs * gs.split)),
+                           dim3(512), 0, q, V, vstride, w, n, nrhs, mres, j, np, gs, part, jp);
         hipLaunchKernelGGL(dcgs_finish_kernel<TV>, dim3((unsigned)((int64_t)np * nrhs)), dim3(64), 0, q, V, vstride, w,
                            n, nrhs, j, np, gs, part, jp);
+      } else {
+        hipLaunchKernelGGL((dcgs_update_kernel<TV, false>), dim3((unsigned)(nhb + (int64_t)np * nrhs)), dim3(512), 0,
+                           q, V, vstride, w, n, nrhs, mres, j, np, gs, part, jp);
+      }
     }
     hipLaunchKernelGGL(normalize_kernel<TV>, grid2(n, nrhs), dim3(256), 0, q, w, V, vstride, n, part, np, gs, mres, j,
                        nrhs, jp);
