@@ -19,6 +19,10 @@ struct cbfm_cbf_s {
   // no triangle carries RWGs of two cells (disjoint bodies, one or more per
   // cell): the RWG Gram couples no two cells and B is block-diagonal by cell
   bool blockdiag = false;
+  // built on a mesh of translated copies of cell 0: every cell holds cell
+  // 0's CBFs (they span the same spaces), so a block of Z_r depends only on
+  // the offset of its two cells
+  bool shared = false;
   // B^{-1} for B = (C^M)^H G C^J (row-major), formed on first use
   std::mutex mu;
   bool factored = false;

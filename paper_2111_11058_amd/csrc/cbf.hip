@@ -844,6 +844,18 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
         c->L[b] = L;
         c->sigma.insert(c->sigma.end(), sb, sb + L);
       }
+      // translated copies of one cell: the plane waves on cell b are those on
+      // cell 0 times one phase per wave, so its currents are cell 0's times
+      // a diagonal phase matrix and its CBFs span cell 0's spaces; every
+      // cell takes cell 0's (count, singular values and vectors)
+      if (m->translated) {
+        c->shared = true;
+        c->sigma.resize((size_t)c->L[0] * nb);
+        for (int b = 1; b < nb; ++b) {
+          c->L[b] = c->L[0];
+          std::copy(c->sigma.begin(), c->sigma.begin() + c->L[0], c->sigma.begin() + (size_t)b * c->L[0]);
+        }
+      }
       cbf_finish(c);
       c->CM.alloc(std::max<int64_t>(1, c->coff[nb]) * sizeof(double2));
       c->CJ.alloc(std::max<int64_t>(1, c->coff[nb]) * sizeof(double2));
@@ -863,6 +875,15 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
       }
       zgemm_batched(d3, s);
       zgemm_batched(d4, s);
+      if (c->shared) {
+        const size_t blk = (size_t)(c->coff[1] - c->coff[0]) * sizeof(double2);
+        for (int b = 1; b < nb; ++b) {
+          CBFM_HIP(hipMemcpyAsync(c->CM.as<double2>() + c->coff[b], c->CM.as<double2>(), blk,
+                                  hipMemcpyDeviceToDevice, s));
+          CBFM_HIP(hipMemcpyAsync(c->CJ.as<double2>() + c->coff[b], c->CJ.as<double2>(), blk,
+                                  hipMemcpyDeviceToDevice, s));
+        }
+      }
     } catch (...) {
       delete c;
       throw;

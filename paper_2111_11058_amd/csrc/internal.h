@@ -149,6 +149,12 @@ struct MeshHost {
 
 struct cbfm_mesh_s {
   cbfm::MeshHost h;
+  // every cell a translated copy of cell 0 (the same RWGs in the same order
+  // on triangles shifted by shift[b]), with no triangle carrying RWGs of
+  // two cells; found at load (find_translates in mesh.cpp)
+  bool translated = false;
+  std::vector<double> shift;   // nblocks * 3
+  std::vector<int32_t> tcell;  // triangle -> its cell (translated meshes)
   // device tables
   cbfm::DevBuf q64, v64, c64, q32, v32, c32, cen;   // SoA geometry
   cbfm::DevBuf tri_edge, tri_sign, tplus, tminus, aplus, aminus, length, area;

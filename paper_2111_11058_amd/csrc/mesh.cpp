@@ -319,6 +319,57 @@ const char* cbfm_last_error(void) { return cbfm::g_last_error.c_str(); }
 
 int32_t cbfm_version(void) { return 1; }
 
+// Whether every cell is cell 0 moved by one vector: equal RWG counts, and
+// RWG i of cell b (cell order) lies on triangles whose vertices, in their
+// stored order, are those of RWG i of cell 0 plus the shift, with the same
+// free vertices; and no triangle carries RWGs of two cells.  Coordinates
+// must agree within 1e-9 of the mesh extent.
+static void find_translates(cbfm_mesh_s* m) {
+  const MeshHost& h = m->h;
+  const int nb = h.nblocks;
+  m->translated = false;
+  if (nb < 2 || h.ne == 0) return;
+  const int64_t N0 = h.cell_off[1] - h.cell_off[0];
+  for (int b = 1; b < nb; ++b)
+    if (h.cell_off[b + 1] - h.cell_off[b] != N0) return;
+  std::vector<int32_t> tcell(h.nt, -1);
+  for (int b = 0; b < nb; ++b)
+    for (int64_t i = h.cell_off[b]; i < h.cell_off[b + 1]; ++i) {
+      const int e = h.perm[i];
+      for (const int32_t t : {h.tplus[e], h.tminus[e]}) {
+        if (tcell[t] >= 0 && tcell[t] != b) return;
+        tcell[t] = b;
+      }
+    }
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t v = 0; v < h.nv; ++v)
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = std::min(lo[c], h.V[v * 3 + c]);
+      hi[c] = std::max(hi[c], h.V[v * 3 + c]);
+    }
+  const double tol = 1e-9 * std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+  const double* V = h.V.data();
+  auto vtx = [&](int32_t t, int a) { return V + 3 * (int64_t)h.T[3 * (int64_t)t + a]; };
+  std::vector<double> shift((size_t)nb * 3, 0.0);
+  const int e00 = h.perm[h.cell_off[0]];
+  for (int b = 1; b < nb; ++b) {
+    const int eb0 = h.perm[h.cell_off[b]];
+    double* d = &shift[(size_t)b * 3];
+    for (int c = 0; c < 3; ++c) d[c] = vtx(h.tplus[eb0], 0)[c] - vtx(h.tplus[e00], 0)[c];
+    for (int64_t i = 0; i < N0; ++i) {
+      const int e0 = h.perm[h.cell_off[0] + i], eb = h.perm[h.cell_off[b] + i];
+      if (h.aplus[e0] != h.aplus[eb] || h.aminus[e0] != h.aminus[eb]) return;
+      for (const auto& tt : {std::make_pair(h.tplus[e0], h.tplus[eb]), std::make_pair(h.tminus[e0], h.tminus[eb])})
+        for (int a = 0; a < 3; ++a)
+          for (int c = 0; c < 3; ++c)
+            if (std::abs(vtx(tt.second, a)[c] - vtx(tt.first, a)[c] - d[c]) > tol) return;
+    }
+  }
+  m->translated = true;
+  m->shift = std::move(shift);
+  m->tcell = std::move(tcell);
+}
+
 cbfm_status cbfm_mesh_load(const double* xyz, int64_t nv, const int32_t* tri, int64_t nt,
                            const int32_t* edge_block, int32_t nblocks, cbfm_mesh* out) {
   return guarded([&] {
@@ -328,6 +379,7 @@ cbfm_status cbfm_mesh_load(const double* xyz, int64_t nv, const int32_t* tri, in
     try {
       MeshHost& h = m->h;
       analyze_host(h, xyz, nv, tri, nt, edge_block, nblocks);
+      find_translates(m);
       upload(m);
     } catch (...) {
       delete m;

@@ -12,8 +12,11 @@
 //   Z_r[cell a rows]  = C_a^H W_X[cell a rows, :]
 // so only one panel of Z exists at a time.
 #include <algorithm>
-#include <memory>
+#include <array>
+#include <cmath>
 #include <cstring>
+#include <map>
+#include <memory>
 
 #include "cbf.h"
 #include "gemm.h"
@@ -195,6 +198,144 @@ void project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int preci
   }
 }
 
+// Copy the reduced block of each offset to every cell pair with that
+// offset (blockIdx.x = pair a nb + b, blockIdx.y = quadrant: J-M, J-J, M-M,
+// M-J).  Zd holds per offset the four L x L row-major quadrants.
+__global__ void scatter_offsets_kernel(const double2* __restrict__ Zd, const int32_t* __restrict__ pair_k, int nb,
+                                       int64_t L, int64_t NL, double2* __restrict__ Zr, int64_t ldz) {
+  const int64_t p = blockIdx.x;
+  const int q = blockIdx.y;
+  const int64_t a = p / nb, b = p % nb, k = pair_k[p];
+  const double2* src = Zd + (k * 4 + q) * L * L;
+  const int64_t r0 = (q >= 2 ? NL : 0) + a * L, c0 = (q == 1 || q == 3 ? NL : 0) + b * L;
+  for (int64_t e = threadIdx.x; e < L * L; e += blockDim.x) {
+    const int64_t i = e / L, j = e % L;
+    Zr[(r0 + i) * ldz + c0 + j] = src[e];
+  }
+}
+
+// Z_r on a mesh of translated copies of cell 0 whose cells share cell 0's
+// CBFs (FP64): the block of cells (a, b) is C_0^H Z_ab C_0 and Z_ab depends
+// only on the offset of b from a, so each distinct offset is filled
+// (regular pairs in one persistent launch, near pairs batched, assembly)
+// and projected once, for a representative pair, and copied to the pairs
+// that share it.  Offsets are grouped while their scratch fits the budget.
+static void project_translated(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, double2* Zr, int64_t ldz,
+                               hipStream_t s, size_t budget) {
+  const MeshHost& h = m->h;
+  const int nb = h.nblocks;
+  const int64_t N0 = h.cell_off[1] - h.cell_off[0], L = c->L[0], NL = c->NL;
+  // distinct offsets (coordinates rounded to 1e-7 of the mesh extent) and
+  // the first pair of each
+  double ext = 0;
+  for (int b = 0; b < nb; ++b)
+    for (int x = 0; x < 3; ++x) ext = std::max(ext, std::abs(m->shift[(size_t)b * 3 + x]));
+  const double unit = std::max(ext, 1e-300) * 1e-7;
+  std::map<std::array<int64_t, 3>, int32_t> kof;
+  std::vector<std::pair<int, int>> rep;
+  std::vector<int32_t> pair_k((size_t)nb * nb);
+  for (int a = 0; a < nb; ++a)
+    for (int b = 0; b < nb; ++b) {
+      std::array<int64_t, 3> key;
+      for (int x = 0; x < 3; ++x)
+        key[x] = std::llround((m->shift[(size_t)b * 3 + x] - m->shift[(size_t)a * 3 + x]) / unit);
+      auto it = kof.find(key);
+      if (it == kof.end()) {
+        it = kof.emplace(key, (int32_t)rep.size()).first;
+        rep.push_back({a, b});
+      }
+      pair_k[(size_t)a * nb + b] = it->second;
+    }
+  const int K = (int)rep.size();
+  // each cell's support triangles (ascending) and every triangle's position
+  // in its cell's support (one cell per triangle)
+  std::vector<std::vector<int32_t>> tris(nb);
+  std::vector<int32_t> tpos(h.nt, -1);
+  for (int64_t t = 0; t < h.nt; ++t) {
+    const int b = m->tcell[t];
+    if (b < 0) continue;
+    tpos[t] = (int32_t)tris[b].size();
+    tris[b].push_back((int32_t)t);
+  }
+  const int64_t nt0 = (int64_t)tris[0].size();
+  for (int b = 0; b < nb; ++b) CBFM_REQUIRE((int64_t)tris[b].size() == nt0, CBFM_E_STATE, "translated cells differ");
+  // near pairs of each representative pair, tagged with its offset
+  std::vector<int32_t> krep((size_t)nb * nb, -1);
+  for (int k = 0; k < K; ++k) krep[(size_t)rep[k].first * nb + rep[k].second] = k;
+  std::vector<std::vector<NearPair>> near(K);
+  for (const NearPair& q : h.near) {
+    const int a = m->tcell[q.p], b = m->tcell[q.q];
+    if (a < 0 || b < 0) continue;
+    const int k = krep[(size_t)a * nb + b];
+    if (k >= 0) near[k].push_back({q.p, q.q, tpos[q.p], tpos[q.q], q.coplanar, k});
+  }
+  // device tables: supports (cell after cell), positions, near pairs,
+  // offset of every pair
+  std::vector<int32_t> alltris;
+  for (int b = 0; b < nb; ++b) alltris.insert(alltris.end(), tris[b].begin(), tris[b].end());
+  std::vector<int64_t> noff(K + 1, 0);
+  for (int k = 0; k < K; ++k) noff[k + 1] = noff[k] + (int64_t)near[k].size();
+  std::vector<NearPair> allnear;
+  allnear.reserve(noff[K]);
+  for (int k = 0; k < K; ++k) allnear.insert(allnear.end(), near[k].begin(), near[k].end());
+  Scratch dtris(alltris.size() * sizeof(int32_t), s), dpos(tpos.size() * sizeof(int32_t), s),
+      dnear(std::max<size_t>(1, allnear.size()) * sizeof(NearPair), s), dpk(pair_k.size() * sizeof(int32_t), s);
+  CBFM_HIP(hipMemcpyAsync(dtris.p, alltris.data(), alltris.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  CBFM_HIP(hipMemcpyAsync(dpos.p, tpos.data(), tpos.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  if (!allnear.empty())
+    CBFM_HIP(hipMemcpyAsync(dnear.p, allnear.data(), allnear.size() * sizeof(NearPair), hipMemcpyHostToDevice, s));
+  CBFM_HIP(hipMemcpyAsync(dpk.p, pair_k.data(), pair_k.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  // reduced blocks of every offset: four L x L quadrants
+  Scratch Zd((size_t)K * 4 * L * L * sizeof(double2), s);
+  const double2* CM0 = c->CM.as<double2>();
+  const double2* CJ0 = c->CJ.as<double2>();
+  const size_t loc = (size_t)27 * nt0 * nt0, zb = (size_t)3 * N0 * N0, wb = (size_t)4 * N0 * L;
+  const size_t per = (loc + zb + wb) * sizeof(double2);
+  const int G = (int)std::max<size_t>(1, std::min<size_t>((size_t)K, budget / per));
+  for (int k0 = 0; k0 < K; k0 += G) {
+    const int k1 = std::min(K, k0 + G), ng = k1 - k0;
+    Scratch local((size_t)ng * loc * sizeof(double2), s), Zb((size_t)ng * zb * sizeof(double2), s),
+        W((size_t)ng * wb * sizeof(double2), s), outs((size_t)ng * sizeof(NearOut), s);
+    std::vector<FillBatchItem> items;
+    std::vector<NearOut> hout(ng);
+    for (int k = k0; k < k1; ++k) {
+      const int a = rep[k].first, b = rep[k].second;
+      items.push_back({m, md, CBFM_LAYOUT_OPS3, dtris.as<int32_t>() + (size_t)a * nt0, nt0,
+                       dtris.as<int32_t>() + (size_t)b * nt0, nt0, local.as<double2>() + (size_t)(k - k0) * loc});
+      hout[k - k0] = {(int64_t)((size_t)(k - k0) * loc), 9 * nt0 * nt0, 3 * nt0};
+    }
+    CBFM_HIP(hipMemcpyAsync(outs.p, hout.data(), hout.size() * sizeof(NearOut), hipMemcpyHostToDevice, s));
+    fill_regular_batch(items, CBFM_FP64, s);  // (synchronises: the near-out table has arrived)
+    fill_near_batch(m, md, CBFM_LAYOUT_OPS3, dnear.as<NearPair>() + noff[k0], noff[k1] - noff[k0],
+                    outs.as<NearOut>(), k0, local.p, s);
+    std::vector<GemmDesc> d1, d2;
+    for (int k = k0; k < k1; ++k) {
+      const int a = rep[k].first, b = rep[k].second;
+      double2* Zk = Zb.as<double2>() + (size_t)(k - k0) * zb;  // K, TE, TH: N0 x N0 each
+      assemble(m, CBFM_FP64, local.as<double2>() + (size_t)(k - k0) * loc, nt0, nt0, m->perm.as<int32_t>() + h.cell_off[a],
+               N0, m->perm.as<int32_t>() + h.cell_off[b], N0, dpos.as<int32_t>(), dpos.as<int32_t>(), Zk, N0 * N0, N0,
+               s, 1);
+      double2* Wk = W.as<double2>() + (size_t)(k - k0) * wb;  // K C^M, K C^J, TE C^J, TH C^M: N0 x L each
+      const double2* Zop[4] = {Zk, Zk, Zk + N0 * N0, Zk + 2 * N0 * N0};
+      const double2* Cop[4] = {CM0, CJ0, CJ0, CM0};
+      for (int u = 0; u < 4; ++u) d1.push_back(gemm(Zop[u], N0, OP_N, Cop[u], L, OP_N, Wk + u * N0 * L, L, N0, L, N0));
+      // quadrants: J-M = C^J^H K C^M, J-J = -C^J^H TE C^J, M-M = C^M^H TH C^M, M-J = C^M^H K C^J
+      double2* Dk = Zd.as<double2>() + (size_t)k * 4 * L * L;
+      const double2* Cq[4] = {CJ0, CJ0, CM0, CM0};
+      const int wq[4] = {0, 2, 3, 1};
+      const double al[4] = {1.0, -1.0, 1.0, 1.0};
+      for (int u = 0; u < 4; ++u)
+        d2.push_back(gemm(Cq[u], L, OP_C, Wk + wq[u] * N0 * L, L, OP_N, Dk + u * L * L, L, L, L, N0, al[u]));
+    }
+    zgemm_batched(d1, s);
+    zgemm_batched(d2, s);
+  }
+  CBFM_REQUIRE((int64_t)nb * nb <= 0x7fffffff, CBFM_E_ARG, "too many cell pairs");
+  hipLaunchKernelGGL(scatter_offsets_kernel, dim3((unsigned)((int64_t)nb * nb), 4), dim3(256), 0, s, Zd.as<double2>(),
+                     dpk.as<int32_t>(), nb, L, NL, Zr, ldz);
+  CBFM_HIP(hipGetLastError());
+}
+
 // Z_r of several scatterers, each taken as one panel of all its cells: the
 // regular fills of all of them in one persistent launch, then per scatterer
 // the near pairs and the assembly, then the projection GEMMs of all of them
@@ -316,6 +457,9 @@ extern "C" cbfm_status cbfm_project(cbfm_mesh m, const cbfm_medium* med, cbfm_cb
     CBFM_HIP(hipMemGetInfo(&fr, &tot));
     fr += scratch_cached_bytes();  // cached scratch is free for this call's panels
     const size_t budget = std::min<size_t>(fr / 4, (size_t)32 << 30);
-    project_dev(m, md, c, precision, static_cast<double2*>(Zr), ldz, static_cast<hipStream_t>(stream), budget);
+    if (m->translated && c->shared && precision == CBFM_FP64)
+      project_translated(m, md, c, static_cast<double2*>(Zr), ldz, static_cast<hipStream_t>(stream), budget);
+    else
+      project_dev(m, md, c, precision, static_cast<double2*>(Zr), ldz, static_cast<hipStream_t>(stream), budget);
   });
 }

@@ -119,6 +119,36 @@ def test_disjoint_cells_block_cmp_parity(torch_cuda):
     assert np.max(np.abs(out["rcs"] - rcs_ref) / rcs_ref) < 1e-9
 
 
+def test_translated_cells_share_cbfs_and_offset_blocks(torch_cuda):
+    """Two translated copies of one sphere: the GPU build gives both cells
+    cell 0's CBFs (they span the same spaces), and the projection fills one
+    block per cell offset (three here) and copies it to the pairs sharing
+    that offset; against the oracle's dense projection with the same CBFs."""
+    from oracle import cbf as ocbf, reduced
+    from paper_2111_11058_amd import cbfm
+    O = _oracle_cbf("array2")
+    P = O["P"]
+    w, m = P["w"], P["m"]
+    mesh = cbfm.Mesh(w.V, w.T, w.edge_block, w.nblocks)
+    med = cbfm.Medium.make(w.k0, w.eta0, w.eps_r, w.mu_r)
+    cb = cbfm.build_cbf(mesh, med, w.gen, 1e-3)
+    CM, CJ = cb.export()
+    assert np.array_equal(cb.L, [cb.L[0]] * 2) and np.array_equal(CM[0], CM[1]) and np.array_equal(CJ[0], CJ[1])
+    for c, ix in enumerate(O["cb"].cells):  # still dual CBFs of each cell: (C^M)^H G C^J = Sigma
+        D = CM[c].conj().T @ O["G"][np.ix_(ix, ix)] @ CJ[c]
+        assert np.abs(D - np.diag(np.diag(D))).max() < 1e-9 * np.abs(D).max()
+    n = cb.n_cbf
+    Zr = torch_cuda.zeros((n, n + 2), dtype=torch_cuda.complex128, device="cuda")
+    cbfm.project(mesh, med, cb, Zr, cbfm.FP64, ldz=n + 2)
+    L = int(cb.L[0])
+    sets = ocbf.CBFSet(O["cb"].cells, CM, CJ, [cb.sigma[:L], cb.sigma[L:]], O["cb"].sigma_all)
+    CJM, CMJ = reduced.cbf_matrices(sets, m.ne)
+    ref = reduced.project(P["Z"], CJM, CMJ)
+    err = _rel(Zr.cpu().numpy()[:, :n], ref)
+    print("translated projection rel err", err)
+    assert err < 1e-10
+
+
 @pytest.mark.parametrize("name", ["c1", "cyl_small"])
 def test_build_cbf_invariants(torch_cuda, name):
     """CBFs are unique only up to unitary mixing inside degenerate singular
