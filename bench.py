@@ -74,6 +74,8 @@ def workload(name):
         return configs.cylinder_c5()
     if name == "sphere_array4x4x2":
         return configs.sphere_array()
+    if name == "sphere_array8x16x2":
+        return configs.sphere_array(8, 16, 2)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -259,7 +261,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cube1728", choices=["cube1728", "sphere320", "sphere5120", "cylinder19968",
-                                                                "sphere_array4x4x2"])
+                                                                "sphere_array4x4x2", "sphere_array8x16x2"])
     ap.add_argument("--cpu-sample", type=int, default=250000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the precision-form legs (FP32 fill, mixed FP32 and split-BF16)")
@@ -374,17 +376,19 @@ def main():
         result["without_cmp"] = {"gmres_iterations_max": int(o["iters"].max()), "status": o["status"],
                                  "relres_max": float(o["relres"].max())}
         log(f"without CMP: {result['without_cmp']}")
-        # iterations to 1e-4 against eps_r, with and without the CMP
+        # iterations to 1e-4 against eps_r, with and without the CMP (the
+        # paper's figure for the 4 x 4 x 2 array)
         sweep = {}
-        for er in (1.0, 2.0, 3.0, 4.0, 5.0, 6.0):
+        for er in ((1.0, 2.0, 3.0, 4.0, 5.0, 6.0) if args.workload == "sphere_array4x4x2" else ()):
             med_e = cbfm.Medium.make(w.k0, w.eta0, er + 0j, w.mu_r)
             cb_e = cbfm.build_cbf(mesh, med_e, w.gen, w.delta_svd, max_L=w.extra["max_L"])
             cbfm.project(mesh, med_e, cb_e, nc, cbfm.FP64)
             a = cbfm.solve(mesh, med_e, cb_e, nc, w.inc, tol=1e-4, max_iter=3000, restart=3000, use_cmp=True)
             b = cbfm.solve(mesh, med_e, cb_e, nc, w.inc, tol=1e-4, max_iter=3000, restart=3000, use_cmp=False)
             sweep[f"{er:g}"] = {"with_cmp": int(a["iters"].max()), "without_cmp": int(b["iters"].max())}
-        result["eps_r_sweep_tol_1e-4"] = sweep
-        log(f"eps_r sweep: {sweep}")
+        if sweep:
+            result["eps_r_sweep_tol_1e-4"] = sweep
+            log(f"eps_r sweep: {sweep}")
     if not args.no_fp32:
         # the precision forms on the same workload: FP32 regular fill with the
         # FP64 projection and solve; and the mixed forms (FP32 fill, FP32 or

@@ -435,6 +435,39 @@ __global__ void gram_times_cj_kernel(const int32_t* __restrict__ perm, const int
   GC[m * NL + col] = acc;
 }
 
+// The same product for a block-diagonal B, kept per cell: GCc at coff[a]
+// holds G_aa C^J_a (N_a x L_a row-major; no RWG's Gram row reaches another
+// cell).  One block per RWG row m (internal order), lanes over its cell's
+// columns.
+__global__ void gram_times_cj_cell_kernel(const int32_t* __restrict__ perm, const int32_t* __restrict__ iperm,
+                                          const int32_t* __restrict__ edge_block, const int64_t* __restrict__ cell_off,
+                                          const int32_t* __restrict__ L, const int64_t* __restrict__ coff,
+                                          const double2* __restrict__ CJ, int64_t ne, const int32_t* tplus,
+                                          const int32_t* tminus, const int32_t* aplus, const int32_t* aminus,
+                                          const int32_t* tri_edge, const int32_t* tri_sign, const double* length,
+                                          double2* __restrict__ GCc) {
+  const int64_t m = blockIdx.x;
+  if (m >= ne) return;
+  const int e = perm[m], a = edge_block[e], La = L[a];
+  const int64_t r = m - cell_off[a];
+  for (int j = threadIdx.x; j < La; j += blockDim.x) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int side = 0; side < 2; ++side) {
+      const int t = side ? tminus[e] : tplus[e];
+      const int ai = side ? aminus[e] : aplus[e];
+      for (int db = 1; db <= 2; ++db) {
+        const int b = (ai + db) % 3;
+        const int f = tri_edge[t * 3 + b];
+        const double g = (db == 1 ? 1.0 : -1.0) * length[e] * length[f] / 6.0 * tri_sign[t * 3 + ai] * tri_sign[t * 3 + b];
+        const double2 c = CJ[coff[a] + (iperm[f] - cell_off[a]) * La + j];
+        acc.x += g * c.x;
+        acc.y += g * c.y;
+      }
+    }
+    GCc[coff[a] + r * La + j] = acc;
+  }
+}
+
 // ------------------------------------------------------------- host helpers
 static std::vector<int32_t> cell_edges(const MeshHost& h, int b) {
   return std::vector<int32_t>(h.perm.begin() + h.cell_off[b], h.perm.begin() + h.cell_off[b + 1]);
@@ -482,6 +515,41 @@ __global__ void cmp_blocks_kernel(double2* __restrict__ B, int64_t NL, const int
     *b = *p;
 }
 
+// Invert the diagonal blocks of a block-diagonal B in place (one batched
+// LU and inversion, blocks padded with the identity to the largest); the
+// blocks off the diagonal are zeros and stay so.
+static void invert_blocks(cbfm_cbf_s* c, hipStream_t s) {
+  const MeshHost& h = c->mesh->h;
+  const int64_t NL = c->NL;
+  const int nb = h.nblocks;
+  const int Lmax = *std::max_element(c->L.begin(), c->L.end());
+  Scratch P((size_t)nb * Lmax * Lmax * sizeof(double2), s), ipiv((size_t)nb * Lmax * sizeof(rocblas_int), s),
+      info((size_t)2 * nb * sizeof(rocblas_int), s);
+  const dim3 g((unsigned)((Lmax + 63) / 64), (unsigned)Lmax, (unsigned)nb);
+  hipLaunchKernelGGL(cmp_blocks_kernel, g, dim3(64), 0, s, c->Binv.as<double2>(), NL, c->d_off.as<int64_t>(),
+                     c->d_L.as<int32_t>(), Lmax, P.as<double2>(), 1);
+  CBFM_HIP(hipGetLastError());
+  {
+    std::lock_guard<std::mutex> lk(blas_mutex());
+    rocblas_handle bh = blas_handle(s);
+    const rocblas_stride sA = (rocblas_stride)Lmax * Lmax, sP = Lmax;
+    CBFM_RS(rocsolver_zgetrf_strided_batched(bh, Lmax, Lmax, (rocblas_double_complex*)P.p, Lmax, sA,
+                                             ipiv.as<rocblas_int>(), sP, info.as<rocblas_int>(), nb));
+    CBFM_RS(rocsolver_zgetri_strided_batched(bh, Lmax, (rocblas_double_complex*)P.p, Lmax, sA,
+                                             ipiv.as<rocblas_int>(), sP, info.as<rocblas_int>() + nb, nb));
+  }
+  hipLaunchKernelGGL(cmp_blocks_kernel, g, dim3(64), 0, s, c->Binv.as<double2>(), NL, c->d_off.as<int64_t>(),
+                     c->d_L.as<int32_t>(), Lmax, P.as<double2>(), 0);
+  CBFM_HIP(hipGetLastError());
+  std::vector<rocblas_int> hinfo(2 * nb);
+  CBFM_HIP(hipMemcpyAsync(hinfo.data(), info.p, hinfo.size() * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+  CBFM_HIP(hipStreamSynchronize(s));
+  for (int a = 0; a < 2 * nb; ++a)
+    CBFM_REQUIRE(hinfo[a] == 0, CBFM_E_RANK,
+                 "G^CBF is singular (cell " + std::to_string(a % nb) + ", zero pivot " + std::to_string(hinfo[a]) + ")");
+  c->factored = true;
+}
+
 // B^{-1} for B = (C^M)^H G C^J.  rocSOLVER works column-major, so it sees
 // M = B^T; LU + inversion of M leaves M^{-1} = (B^{-1})^T in column-major
 // order, i.e. B^{-1} in the row-major layout used here.  A block-diagonal B
@@ -491,6 +559,29 @@ static void cmp_factor(cbfm_cbf_s* c, hipStream_t s) {
   const cbfm_mesh_s* m = c->mesh;
   const MeshHost& h = m->h;
   const int64_t NL = c->NL, ne = h.ne;
+  if (c->blockdiag) {
+    // B_a = (C^M_a)^H G_aa C^J_a per cell into the zeroed B
+    const int nb = h.nblocks;
+    Scratch GCc((size_t)std::max<int64_t>(1, c->coff[nb]) * sizeof(double2), s);
+    hipLaunchKernelGGL(gram_times_cj_cell_kernel, dim3((unsigned)ne), dim3(64), 0, s, m->perm.as<int32_t>(),
+                       m->iperm.as<int32_t>(), c->d_edge_block.as<int32_t>(), c->d_cell_off.as<int64_t>(),
+                       c->d_L.as<int32_t>(), c->d_coff.as<int64_t>(), c->CJ.as<double2>(), ne, m->tplus.as<int32_t>(),
+                       m->tminus.as<int32_t>(), m->aplus.as<int32_t>(), m->aminus.as<int32_t>(),
+                       m->tri_edge.as<int32_t>(), m->tri_sign.as<int32_t>(), m->length.as<double>(), GCc.as<double2>());
+    CBFM_HIP(hipGetLastError());
+    c->Binv.alloc(NL * NL * sizeof(double2));
+    CBFM_HIP(hipMemsetAsync(c->Binv.p, 0, NL * NL * sizeof(double2), s));
+    std::vector<GemmDesc> ds;
+    for (int a = 0; a < nb; ++a) {
+      const int64_t Na = h.cell_off[a + 1] - h.cell_off[a], La = c->L[a];
+      ds.push_back(gemm(c->CM.as<double2>() + c->coff[a], La, OP_C, GCc.as<double2>() + c->coff[a], La, OP_N,
+                        c->Binv.as<double2>() + c->off[a] * NL + c->off[a], NL, La, La, Na));
+    }
+    zgemm_batched(ds, s);
+    invert_blocks(c, s);
+    return;
+  }
+  CBFM_REQUIRE(ne <= 65535, CBFM_E_ARG, "G^CBF coupling cells: at most 65535 RWGs");
   Scratch GC(ne * NL * sizeof(double2), s);
   dim3 grid((unsigned)((NL + 255) / 256), (unsigned)ne);
   hipLaunchKernelGGL(gram_times_cj_kernel, grid, dim3(256), 0, s, m->perm.as<int32_t>(), m->iperm.as<int32_t>(),
@@ -507,36 +598,6 @@ static void cmp_factor(cbfm_cbf_s* c, hipStream_t s) {
                       OP_N, c->Binv.as<double2>() + c->off[a] * NL, NL, c->L[a], NL, Na));
   }
   zgemm_batched(ds, s);
-  if (c->blockdiag) {
-    const int nb = h.nblocks;
-    const int Lmax = *std::max_element(c->L.begin(), c->L.end());
-    Scratch P((size_t)nb * Lmax * Lmax * sizeof(double2), s), ipiv((size_t)nb * Lmax * sizeof(rocblas_int), s),
-        info((size_t)2 * nb * sizeof(rocblas_int), s);
-    const dim3 g((unsigned)((Lmax + 63) / 64), (unsigned)Lmax, (unsigned)nb);
-    hipLaunchKernelGGL(cmp_blocks_kernel, g, dim3(64), 0, s, c->Binv.as<double2>(), NL, c->d_off.as<int64_t>(),
-                       c->d_L.as<int32_t>(), Lmax, P.as<double2>(), 1);
-    CBFM_HIP(hipGetLastError());
-    {
-      std::lock_guard<std::mutex> lk(blas_mutex());
-      rocblas_handle bh = blas_handle(s);
-      const rocblas_stride sA = (rocblas_stride)Lmax * Lmax, sP = Lmax;
-      CBFM_RS(rocsolver_zgetrf_strided_batched(bh, Lmax, Lmax, (rocblas_double_complex*)P.p, Lmax, sA,
-                                               ipiv.as<rocblas_int>(), sP, info.as<rocblas_int>(), nb));
-      CBFM_RS(rocsolver_zgetri_strided_batched(bh, Lmax, (rocblas_double_complex*)P.p, Lmax, sA,
-                                               ipiv.as<rocblas_int>(), sP, info.as<rocblas_int>() + nb, nb));
-    }
-    hipLaunchKernelGGL(cmp_blocks_kernel, g, dim3(64), 0, s, c->Binv.as<double2>(), NL, c->d_off.as<int64_t>(),
-                       c->d_L.as<int32_t>(), Lmax, P.as<double2>(), 0);
-    CBFM_HIP(hipGetLastError());
-    std::vector<rocblas_int> hinfo(2 * nb);
-    CBFM_HIP(hipMemcpyAsync(hinfo.data(), info.p, hinfo.size() * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
-    CBFM_HIP(hipStreamSynchronize(s));
-    for (int a = 0; a < 2 * nb; ++a)
-      CBFM_REQUIRE(hinfo[a] == 0, CBFM_E_RANK,
-                   "G^CBF is singular (cell " + std::to_string(a % nb) + ", zero pivot " + std::to_string(hinfo[a]) + ")");
-    c->factored = true;
-    return;
-  }
   Scratch ipiv(NL * sizeof(rocblas_int), s);
   Scratch info(2 * sizeof(rocblas_int), s);
   {
