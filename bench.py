@@ -76,6 +76,8 @@ def workload(name):
         return configs.sphere_array()
     if name == "sphere_array8x16x2":
         return configs.sphere_array(8, 16, 2)
+    if name == "cube_array8x2x2":
+        return configs.cube_array(6)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -261,7 +263,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cube1728", choices=["cube1728", "sphere320", "sphere5120", "cylinder19968",
-                                                                "sphere_array4x4x2", "sphere_array8x16x2"])
+                                                                "sphere_array4x4x2", "sphere_array8x16x2",
+                                                                "cube_array8x2x2"])
     ap.add_argument("--cpu-sample", type=int, default=250000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the precision-form legs (FP32 fill, mixed FP32 and split-BF16)")

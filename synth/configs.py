@@ -141,6 +141,38 @@ def sphere_array(nx: int = 4, ny: int = 4, nz: int = 2, pitch: float = 0.5, eps_
                     extra={"max_L": 70})
 
 
+# Table II (cube array): (dtheta, N_theta, dphi, N_phi) of the generating
+# waves and the singular-value group l kept, per condition 1..6
+CUBE_ARRAY_CONDITIONS = {1: (30.0, 12, 30.0, 6, 4), 2: (30.0, 12, 30.0, 6, 5), 3: (30.0, 12, 30.0, 6, 6),
+                         4: (10.0, 36, 10.0, 18, 4), 5: (10.0, 36, 10.0, 18, 5), 6: (10.0, 36, 10.0, 18, 6)}
+
+
+def cube_array(condition: int = 6, nx: int = 8, ny: int = 2, nz: int = 2, pitch: float = 0.5,
+               eps_r: complex = 3.0 + 0j) -> Workload:
+    """The paper's cube array (Sec. IV-B): 8 x 2 x 2 cubes of edge 0.4
+    lambda (12 mm at lambda = 30 mm) meshed with 6 x 6 squares per face (432
+    triangles, 1296 unknowns each) at a centre pitch of lambda/2, one cell per
+    cube, eps_r 3, one theta-polarised wave along -z.  The generating waves
+    and the CBFs kept per current follow Table II: groups l = 1..L of sizes
+    2 (2 l + 1), i.e. 48, 70 or 96 CBFs for L = 4, 5, 6."""
+    dth, nth, dph, nph, lmax = CUBE_ARRAY_CONDITIONS[condition]
+    V0, T0 = cube(6, 0.4)
+    Vs, Ts = [], []
+    for ix in range(nx):
+        for iy in range(ny):
+            for iz in range(nz):
+                off = pitch * np.array([ix - (nx - 1) / 2, iy - (ny - 1) / 2, iz - (nz - 1) / 2])
+                Ts.append(T0 + len(V0) * len(Vs))
+                Vs.append(V0 + off)
+    V, T = np.concatenate(Vs), np.concatenate(Ts).astype(T0.dtype)
+    blocks = (edges_canonical(T)[:, 0] // len(V0)).astype(np.int32)
+    gen = generating_set(0.0, dth, nth, 0.0, dph, nph)
+    max_L = sum(2 * (2 * l + 1) for l in range(1, lmax + 1))
+    return Workload(f"cube_array{nx}x{ny}x{nz}_cond{condition}", V, T, blocks, nx * ny * nz, eps_r, 1.0 + 0j,
+                    np.array([[0, 0, -1, 1, 0, 0]], dtype=np.float64), gen, delta_svd=0.0,
+                    extra={"max_L": max_L})
+
+
 def small_cylinder(K=2, n_h=4, nblocks=4, eps_r=3.0 + 0j) -> Workload:
     V, T = cylinder(K, n_h, 0.3, 0.8)
     return Workload(f"cyl{len(T)}", V, T, rcb_blocks(V, T, nblocks), nblocks, eps_r, 1.0 + 0j,
