@@ -138,6 +138,11 @@ cbfm_status cbfm_timer_read(const char* name, int64_t* launches, double* total_m
  * with opposite directions, a triangle is degenerate, the enclosed volume is
  * not positive, or a cell is empty.  Uploads the tables to the current
  * device (synchronous).  The handle is freed with cbfm_mesh_free.
+ * Arrays: the load also notes whether every cell is cell 0 moved by one
+ * vector (equal RWG counts; RWG i of each cell, in cell order, on triangles
+ * whose vertices in stored order are cell 0's plus the shift, within 1e-9 of
+ * the mesh extent; no triangle carrying RWGs of two cells), which
+ * cbfm_build_cbf and cbfm_project use (paper Sec. IV-A: identical cells).
  */
 cbfm_status cbfm_mesh_load(const double* xyz_host, int64_t nv, const int32_t* tri_host,
                            int64_t nt, const int32_t* edge_block_host, int32_t nblocks,
@@ -201,6 +206,9 @@ cbfm_status cbfm_rhs(cbfm_mesh m, const cbfm_medium* med, const double* inc_host
  * generating waves (LU), G'_m = (J^M)^H G_m J^J, SVD, keep sigma_i/sigma_1 >=
  * delta_svd (at most max_L if max_L > 0).  FP64 throughout.
  * Synchronises the stream (the kept counts L_m are host data).
+ * On a mesh of translated copies of one cell (see cbfm_mesh_load) the
+ * waves on each cell are those on cell 0 times one phase per wave, so every
+ * cell receives cell 0's count, singular values and CBFs (the same spaces).
  * Returns CBFM_E_ARG for n_gen outside [1, 4096] or a mesh of more than
  * 32767 cells or 32767 RWGs in one cell, CBFM_E_RANK if a cell's Z_mm is
  * singular or a cell keeps no CBF.                                         */
@@ -240,7 +248,10 @@ void cbfm_cbf_free(cbfm_cbf c);
  * (fill as in cbfm_fill_pmchwt, projection in double) or the mixed forms
  * CBFM_MIXED_FP32 / CBFM_MIXED_BF16 / CBFM_MIXED_BF16X3 (float fill, float
  * panel, FP32, BF16 or split-BF16 matrix-core projection with FP32
- * accumulation; Z_r still stored double).
+ * accumulation; Z_r still stored double).  With CBFs built on a mesh of
+ * translated copies of one cell (FP64), the block of two cells depends only
+ * on their offset: one block is filled and projected per distinct offset
+ * and copied to the pairs sharing it.
  *   Zr_dev  N_CBF x N_CBF double2, row-major, ldz >= N_CBF                 */
 cbfm_status cbfm_project(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, int32_t precision,
                          void* Zr_dev, int64_t ldz, void* stream);
