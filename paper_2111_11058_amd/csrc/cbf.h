@@ -1,8 +1,6 @@
 // CBF handle and the Calderon preconditioner (see cbf.hip).
 #pragma once
 
-#include <rocblas/rocblas.h>
-
 #include <mutex>
 
 #include "internal.h"
@@ -31,8 +29,6 @@ struct cbfm_cbf_s {
 
 namespace cbfm {
 
-rocblas_handle blas_handle(hipStream_t s);
-std::mutex& blas_mutex();
 // x <- (G^CBF)^{-1} x in place, nrhs vectors of length 2 NL
 void cmp_apply_dev(cbfm_cbf_s* c, int64_t nrhs, double2* x, hipStream_t s);
 // B^{-1} (NL x NL, row-major), formed on first use

@@ -21,7 +21,6 @@
 //
 // G^CBF = blkdiag(A, B) with B = (C^M)^H G C^J and A = (C^J)^H G C^M =
 // -B^H (G real antisymmetric), so one inverse of B serves both halves.
-#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <array>
@@ -31,36 +30,9 @@
 
 #include "cbf.h"
 #include "gemm.h"
+#include "gj.h"
 
 namespace cbfm {
-
-// ------------------------------------------------------------- rocSOLVER handle
-static std::mutex g_blas_mu;
-
-// One rocBLAS handle per (device, stream): a handle's workspace is then never
-// shared by work on two streams (concurrent requests of the server).
-rocblas_handle blas_handle(hipStream_t s) {
-  static std::map<std::pair<int, hipStream_t>, rocblas_handle> handles;
-  int dev = 0;
-  CBFM_HIP(hipGetDevice(&dev));
-  auto it = handles.find({dev, s});
-  if (it == handles.end()) {
-    rocblas_handle h;
-    CBFM_REQUIRE(rocblas_create_handle(&h) == rocblas_status_success, CBFM_E_HIP, "rocblas_create_handle failed");
-    CBFM_REQUIRE(rocblas_set_stream(h, s) == rocblas_status_success, CBFM_E_HIP, "rocblas_set_stream failed");
-    it = handles.emplace(std::make_pair(dev, s), h).first;
-  }
-  return it->second;
-}
-
-std::mutex& blas_mutex() { return g_blas_mu; }
-
-#define CBFM_RS(call)                                                                                  \
-  do {                                                                                                 \
-    rocblas_status st_ = (call);                                                                       \
-    CBFM_REQUIRE(st_ == rocblas_status_success, CBFM_E_HIP,                                            \
-                 std::string(#call) + ": rocblas status " + std::to_string((int)st_));                 \
-  } while (0)
 
 // ------------------------------------------------------------- kernels
 // Gram entry G[e, f] of two canonical edges (closed form above).
@@ -106,16 +78,17 @@ __global__ void cell_gram_kernel(const CellJob* __restrict__ cells, int Nmax, co
 }
 
 // Self blocks of a group of cells (blockIdx.z: cell cell0 + z): the cell's
-// [[K, -TE], [TH, K]] as a column-major n x n matrix with identity padding,
-// each RWG entry the sum over the two triangles of either RWG of the
-// triangle-local entries (local blocks [K, TE, TH], each 3 nt x 3 nt
-// row-major; signs and lengths are inside them).
+// [[K, -TE], [TH, K]] as the first n columns of the row-major n x ld
+// augmented system [Z_mm | V_m], with identity padding, each RWG entry the
+// sum over the two triangles of either RWG of the triangle-local entries
+// (local blocks [K, TE, TH], each 3 nt x 3 nt row-major; signs and lengths
+// are inside them).
 __global__ void cell_zmm_kernel(const double2* __restrict__ local, const CellJob* __restrict__ jobs, int cell0,
                                 const int32_t* __restrict__ tplus, const int32_t* __restrict__ tminus,
                                 const int32_t* __restrict__ aplus, const int32_t* __restrict__ aminus, int n,
-                                double2* __restrict__ Zpad) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
-  if (r >= n) return;
+                                int ld, double2* __restrict__ Aug) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+  if (c >= n) return;
   const int b = cell0 + (int)blockIdx.z;
   const CellJob jb = jobs[b];
   const int N = jb.N;
@@ -139,26 +112,27 @@ __global__ void cell_zmm_kernel(const double2* __restrict__ local, const CellJob
       }
     v = (br == 0 && bc == 1) ? make_double2(-re, -im) : make_double2(re, im);
   }
-  Zpad[(int64_t)b * n * n + (int64_t)c * n + r] = v;
+  Aug[(int64_t)b * n * ld + (int64_t)r * ld + c] = v;
 }
 
-// The generating right-hand sides of every cell (blockIdx.z: cell): column c
-// of the cell's n x S column-major block is [v^E(edges); v^H(edges); 0].
+// The generating right-hand sides of every cell (blockIdx.z: cell): column
+// n + c of the cell's row-major n x (n + S) augmented system is
+// [v^E(edges); v^H(edges); 0] of wave c.
 __global__ void cell_v_kernel(const double2* __restrict__ v, int64_t ne, const CellJob* __restrict__ jobs, int n,
-                              int S, double2* __restrict__ Vpad) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y, b = blockIdx.z;
-  if (r >= n) return;
+                              int S, double2* __restrict__ Aug) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y, b = blockIdx.z;
+  if (c >= S) return;
   const CellJob jb = jobs[b];
   double2 x = make_double2(0.0, 0.0);
   if (r < jb.N)
     x = v[(int64_t)c * 2 * ne + jb.edges[r]];
   else if (r < 2 * jb.N)
     x = v[(int64_t)c * 2 * ne + ne + jb.edges[r - jb.N]];
-  Vpad[((int64_t)b * S + c) * n + r] = x;
+  Aug[((int64_t)b * n + r) * (n + S) + n + c] = x;
 }
 
-// From every cell's solved currents J = [J^M; J^J] (column-major n x S per
-// cell, the magnetic rows first), write (J^M)^H and (J^J)^H as column-major
+// From every cell's solved currents J = [J^M; J^J] (columns n .. n + S - 1
+// of the row-major n x (n + S) augmented system, the magnetic rows first), write (J^M)^H and (J^J)^H as column-major
 // S x Nmax matrices (blockIdx.z = 2 cell + which), zero beyond the cell's N
 // columns.
 __global__ void pack_jh_kernel(const double2* __restrict__ J, int n, int S, const int32_t* __restrict__ Ns, int Nmax,
@@ -168,7 +142,7 @@ __global__ void pack_jh_kernel(const double2* __restrict__ J, int n, int S, cons
   const int N = Ns[b];
   double2 x = make_double2(0.0, 0.0);
   if (c < N) {
-    x = J[((int64_t)b * S + r) * n + w * N + c];
+    x = J[((int64_t)b * n + w * N + c) * (n + S) + n + r];
     x.y = -x.y;
   }
   out[((int64_t)(2 * b + w) * Nmax + c) * S + r] = x;
@@ -516,45 +490,29 @@ __global__ void cmp_blocks_kernel(double2* __restrict__ B, int64_t NL, const int
 }
 
 // Invert the diagonal blocks of a block-diagonal B in place (one batched
-// LU and inversion, blocks padded with the identity to the largest); the
-// blocks off the diagonal are zeros and stay so.
+// Gauss-Jordan inversion, blocks padded with the identity to the largest);
+// the blocks off the diagonal are zeros and stay so.
 static void invert_blocks(cbfm_cbf_s* c, hipStream_t s) {
   const MeshHost& h = c->mesh->h;
   const int64_t NL = c->NL;
   const int nb = h.nblocks;
   const int Lmax = *std::max_element(c->L.begin(), c->L.end());
-  Scratch P((size_t)nb * Lmax * Lmax * sizeof(double2), s), ipiv((size_t)nb * Lmax * sizeof(rocblas_int), s),
-      info((size_t)2 * nb * sizeof(rocblas_int), s);
+  Scratch P((size_t)nb * Lmax * Lmax * sizeof(double2), s);
   const dim3 g((unsigned)((Lmax + 63) / 64), (unsigned)Lmax, (unsigned)nb);
   hipLaunchKernelGGL(cmp_blocks_kernel, g, dim3(64), 0, s, c->Binv.as<double2>(), NL, c->d_off.as<int64_t>(),
                      c->d_L.as<int32_t>(), Lmax, P.as<double2>(), 1);
   CBFM_HIP(hipGetLastError());
-  {
-    std::lock_guard<std::mutex> lk(blas_mutex());
-    rocblas_handle bh = blas_handle(s);
-    const rocblas_stride sA = (rocblas_stride)Lmax * Lmax, sP = Lmax;
-    CBFM_RS(rocsolver_zgetrf_strided_batched(bh, Lmax, Lmax, (rocblas_double_complex*)P.p, Lmax, sA,
-                                             ipiv.as<rocblas_int>(), sP, info.as<rocblas_int>(), nb));
-    CBFM_RS(rocsolver_zgetri_strided_batched(bh, Lmax, (rocblas_double_complex*)P.p, Lmax, sA,
-                                             ipiv.as<rocblas_int>(), sP, info.as<rocblas_int>() + nb, nb));
-  }
+  gj_inverse_batched(P.as<double2>(), (int64_t)Lmax * Lmax, Lmax, nb, "G^CBF block of cell", s);
   hipLaunchKernelGGL(cmp_blocks_kernel, g, dim3(64), 0, s, c->Binv.as<double2>(), NL, c->d_off.as<int64_t>(),
                      c->d_L.as<int32_t>(), Lmax, P.as<double2>(), 0);
   CBFM_HIP(hipGetLastError());
-  std::vector<rocblas_int> hinfo(2 * nb);
-  CBFM_HIP(hipMemcpyAsync(hinfo.data(), info.p, hinfo.size() * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
-  CBFM_HIP(hipStreamSynchronize(s));
-  for (int a = 0; a < 2 * nb; ++a)
-    CBFM_REQUIRE(hinfo[a] == 0, CBFM_E_RANK,
-                 "G^CBF is singular (cell " + std::to_string(a % nb) + ", zero pivot " + std::to_string(hinfo[a]) + ")");
   c->factored = true;
 }
 
-// B^{-1} for B = (C^M)^H G C^J.  rocSOLVER works column-major, so it sees
-// M = B^T; LU + inversion of M leaves M^{-1} = (B^{-1})^T in column-major
-// order, i.e. B^{-1} in the row-major layout used here.  A block-diagonal B
-// is inverted block by block (one batched call; the blocks off the diagonal
-// are exact zeros and stay so).
+// B^{-1} for B = (C^M)^H G C^J (row-major, inverted in place by blocked
+// Gauss-Jordan elimination).  A block-diagonal B is inverted block by block
+// (one batched call; the blocks off the diagonal are exact zeros and stay
+// so).
 static void cmp_factor(cbfm_cbf_s* c, hipStream_t s) {
   const cbfm_mesh_s* m = c->mesh;
   const MeshHost& h = m->h;
@@ -598,21 +556,8 @@ static void cmp_factor(cbfm_cbf_s* c, hipStream_t s) {
                       OP_N, c->Binv.as<double2>() + c->off[a] * NL, NL, c->L[a], NL, Na));
   }
   zgemm_batched(ds, s);
-  Scratch ipiv(NL * sizeof(rocblas_int), s);
-  Scratch info(2 * sizeof(rocblas_int), s);
-  {
-    std::lock_guard<std::mutex> lk(blas_mutex());
-    rocblas_handle bh = blas_handle(s);
-    CBFM_RS(rocsolver_zgetrf(bh, (rocblas_int)NL, (rocblas_int)NL, (rocblas_double_complex*)c->Binv.p,
-                             (rocblas_int)NL, ipiv.as<rocblas_int>(), info.as<rocblas_int>()));
-    CBFM_RS(rocsolver_zgetri(bh, (rocblas_int)NL, (rocblas_double_complex*)c->Binv.p, (rocblas_int)NL,
-                             ipiv.as<rocblas_int>(), info.as<rocblas_int>() + 1));
-  }
-  rocblas_int hinfo[2] = {0, 0};
-  CBFM_HIP(hipMemcpyAsync(hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost, s));
-  CBFM_HIP(hipStreamSynchronize(s));
-  CBFM_REQUIRE(hinfo[0] == 0 && hinfo[1] == 0, CBFM_E_RANK,
-               "G^CBF is singular (zero pivot " + std::to_string(hinfo[0]) + ")");
+  CBFM_REQUIRE(NL <= 65535, CBFM_E_ARG, "G^CBF coupling cells: at most 65535 CBFs per current");
+  gj_inverse_batched(c->Binv.as<double2>(), NL * NL, (int)NL, 1, "G^CBF", s);
   c->factored = true;
 }
 
@@ -724,9 +669,9 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
     Scratch dinc((size_t)S * 6 * sizeof(double), s);
     CBFM_HIP(hipMemcpyAsync(dinc.p, prm->gen_host, (size_t)S * 6 * sizeof(double), hipMemcpyHostToDevice, s));
     rhs_launch(m, md, med->eta0, dinc.as<double>(), S, vgen.p, s);
-    // per-cell Z_mm (padded, column-major) and V_m
-    Scratch Zpad((size_t)nb * n * n * sizeof(double2), s);
-    Scratch Vpad((size_t)nb * n * S * sizeof(double2), s);
+    // per cell the augmented system [Z_mm | V_m] (padded, row-major n x (n + S))
+    const int ldz = n + S;
+    Scratch Aug((size_t)nb * n * ldz * sizeof(double2), s);
     std::vector<CellSupport> cs = supports(h, nb);
     // groups of cells whose triangle-local blocks fit in at most 1 GiB (or
     // one cell), filled together; each cell's blocks at loff[b] elements
@@ -807,29 +752,16 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
       fill_near_batch(m, md, CBFM_LAYOUT_OPS3, dnear + noff[g0], noff[g1] - noff[g0], douts + g0, g0, local.p, s);
       hipLaunchKernelGGL(cell_zmm_kernel, dim3((n + 255) / 256, n, g1 - g0), dim3(256), 0, s, local.as<double2>(),
                          djobs, g0, m->tplus.as<int32_t>(), m->tminus.as<int32_t>(), m->aplus.as<int32_t>(),
-                         m->aminus.as<int32_t>(), n, Zpad.as<double2>());
+                         m->aminus.as<int32_t>(), n, ldz, Aug.as<double2>());
       CBFM_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(cell_v_kernel, dim3((n + 255) / 256, S, nb), dim3(256), 0, s, vgen.as<double2>(), h.ne, djobs,
-                       n, S, Vpad.as<double2>());
+    hipLaunchKernelGGL(cell_v_kernel, dim3((S + 255) / 256, n, nb), dim3(256), 0, s, vgen.as<double2>(), h.ne, djobs,
+                       n, S, Aug.as<double2>());
     CBFM_HIP(hipGetLastError());
-    // LU solves Z_mm J_m = V_m
-    Scratch piv((size_t)nb * n * sizeof(rocblas_int), s);
-    Scratch info((size_t)nb * sizeof(rocblas_int), s);
-    {
-      std::lock_guard<std::mutex> lk(blas_mutex());
-      rocblas_handle bh = blas_handle(s);
-      CBFM_RS(rocsolver_zgetrf_strided_batched(bh, n, n, (rocblas_double_complex*)Zpad.p, n, (rocblas_stride)n * n,
-                                               piv.as<rocblas_int>(), n, info.as<rocblas_int>(), nb));
-      CBFM_RS(rocsolver_zgetrs_strided_batched(bh, rocblas_operation_none, n, S, (rocblas_double_complex*)Zpad.p, n,
-                                               (rocblas_stride)n * n, piv.as<rocblas_int>(), n,
-                                               (rocblas_double_complex*)Vpad.p, n, (rocblas_stride)n * S, nb));
-    }
-    std::vector<rocblas_int> hinfo(nb);
-    CBFM_HIP(hipMemcpyAsync(hinfo.data(), info.p, nb * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
-    CBFM_HIP(hipStreamSynchronize(s));
-    for (int b = 0; b < nb; ++b)
-      CBFM_REQUIRE(hinfo[b] == 0, CBFM_E_RANK, "cell " + std::to_string(b) + ": Z_mm is singular");
+    // Z_mm J_m = V_m for every cell (Gauss-Jordan on the augmented systems)
+    gj_solve_batched(Aug.as<double2>(), (int64_t)n * ldz, ldz, n, ldz, nb, "Z_mm of cell", s);
+    Scratch info((size_t)nb * sizeof(int32_t), s);  // per cell: the Jacobi SVD ran out of sweeps
+    std::vector<int32_t> hinfo(nb);
     // QR of (J^M)^H and (J^J)^H (column-major S x Nmax, zero-padded): R only
     const int rk = std::min(S, Nmax);
     std::vector<int32_t> hN(nb);
@@ -837,7 +769,7 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
     Scratch dN((size_t)nb * sizeof(int32_t), s);
     CBFM_HIP(hipMemcpyAsync(dN.p, hN.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, s));
     Scratch QA((size_t)nb * 2 * S * Nmax * sizeof(double2), s);
-    hipLaunchKernelGGL(pack_jh_kernel, dim3((S + 255) / 256, Nmax, 2 * nb), dim3(256), 0, s, Vpad.as<double2>(), n,
+    hipLaunchKernelGGL(pack_jh_kernel, dim3((S + 255) / 256, Nmax, 2 * nb), dim3(256), 0, s, Aug.as<double2>(), n,
                        S, dN.as<int32_t>(), Nmax, QA.as<double2>());
     Scratch Rf((size_t)nb * 2 * rk * Nmax * sizeof(double2), s);  // per cell R_M, then R_J
     hipLaunchKernelGGL(cell_qr_kernel, dim3(2 * nb), dim3(1024), (size_t)S * sizeof(double2), s, QA.as<double2>(), S,
@@ -887,7 +819,7 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
     }
     std::vector<double> hs((size_t)nb * rk);
     CBFM_HIP(hipMemcpyAsync(hs.data(), sv.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    CBFM_HIP(hipMemcpyAsync(hinfo.data(), info.p, nb * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+    CBFM_HIP(hipMemcpyAsync(hinfo.data(), info.p, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     CBFM_HIP(hipStreamSynchronize(s));
     for (int b = 0; b < nb; ++b)
       CBFM_REQUIRE(hinfo[b] == 0, CBFM_E_HIP, "cell " + std::to_string(b) + ": Jacobi SVD did not converge");

@@ -89,6 +89,52 @@ def test_cmp_apply_parity(torch_cuda):
     assert _rel(yt.cpu().numpy(), ref) < 1e-10
 
 
+def test_cmp_apply_parity_two_pivot_rounds(torch_cuda):
+    """c1 with delta_SVD = 1e-5 keeps 290 CBFs per current, so B (order 290,
+    cells coupled) is inverted over panels whose first pivot rows come from
+    two groups of 256 rows and a second tournament round."""
+    O = _oracle_cbf("c1", delta=1e-5)
+    w = O["P"]["w"]
+    cbfm, mesh, med, cbf = _gpu_handles(w, O)
+    n = cbf.n_cbf
+    assert n // 2 == 290
+    rng = np.random.default_rng(13)
+    y = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    yt = torch_cuda.tensor(y, dtype=torch_cuda.complex128, device="cuda")
+    xt = torch_cuda.empty_like(yt)
+    cbfm.cmp_apply(cbf, yt, xt)
+    x = xt.cpu().numpy()
+    Gc = O["Gc"]
+    back = np.linalg.norm(x @ Gc.T - y) / (np.linalg.norm(Gc, 2) * np.linalg.norm(x))
+    fwd = _rel(x, np.linalg.solve(Gc, y.T).T)
+    cond = np.linalg.cond(Gc)
+    print("cmp backward", back, "forward", fwd, "cond", cond)
+    assert back < 1e-14 and fwd < 1e-14 * cond
+
+
+def test_build_cbf_one_cell_order_960(torch_cuda):
+    """The whole c1 body as one cell: its isolated system has order 960 (the
+    first panels' pivot rows come from four groups of 256 rows and a second
+    round) with 144 right-hand sides; kept count, singular values and the
+    duality relation as the oracle's."""
+    from oracle import cbf
+    from paper_2111_11058_amd import cbfm
+    P = oracle_problem("c1")
+    w, m = P["w"], P["m"]
+    eb = np.zeros(m.ne, dtype=np.int32)
+    ref = cbf.build(m, P["Kc"], P["TE"], P["TH"], eb, w.gen, w.k0, w.eta0, 1e-3)
+    mesh = cbfm.Mesh(w.V, w.T, eb, 1)
+    med = cbfm.Medium.make(w.k0, w.eta0, w.eps_r, w.mu_r)
+    print("build_cbf c1 as one cell", flush=True)
+    cb = cbfm.build_cbf(mesh, med, w.gen, 1e-3)
+    assert np.array_equal(cb.L, ref.L)
+    s = ref.sigma[0]
+    assert np.max(np.abs(cb.sigma - s)) < 1e-10 * s[0]
+    CM, CJ = cb.export()
+    G = cbf.rwg_gram(m)[np.ix_(ref.cells[0], ref.cells[0])]
+    assert np.abs(CM[0].conj().T @ G @ CJ[0] - np.diag(s)).max() < 1e-9 * s[0]
+
+
 def test_disjoint_cells_block_cmp_parity(torch_cuda):
     """Two disjoint spheres, one per cell: no triangle carries RWGs of both
     cells, so G^CBF is block-diagonal and the library inverts it block by
