@@ -54,7 +54,17 @@ __device__ inline double2 gj_recip(double2 p) {
   const double d = p.x * p.x + p.y * p.y;
   return make_double2(p.x / d, -p.y / d);
 }
-__device__ inline bool gj_better(double k1, int w1, double k0, int w0) { return k1 > k0 || (k1 == k0 && w1 < w0); }
+// Pivot key of a row: |re| + |im| rounded to float (a positive value stays
+// positive) in the high word, the complement of the thread in the low word,
+// so that the largest key is the largest entry and, among equals, the lowest
+// thread; 0 for a thread without a candidate row.
+__device__ inline uint64_t gj_key(bool alive, double2 z, int t) {
+  if (!alive) return 0;
+  const double m = gj_cabs1(z);
+  uint32_t hi = 0;
+  if (m > 0.0) hi = __float_as_uint((float)m) | 1u;  // (NaN counts as zero)
+  return ((uint64_t)hi << 32) | (uint32_t)~t;
+}
 
 struct SelectArgs {
   const double2* A;
@@ -80,9 +90,17 @@ __global__ void __launch_bounds__(kGroup) gj_select_kernel(SelectArgs p) {
   double2* Pc = p.Pcol + (int64_t)b * p.n * kW;
   const int k = p.k, w = p.w;
   if (p.cand_in == nullptr && g >= p.nsel_groups) {
+    // (every load is issued before the first store: a load-store chain per
+    // entry would wait on memory 32 times in a row)
     const int r = (g - p.nsel_groups) * kGroup + t;
-    if (r < k)
-      for (int j = 0; j < w; ++j) Pc[(int64_t)r * kW + j] = Ab[(int64_t)r * p.ld + k + j];
+    if (r < k) {
+      double2 v[kW];
+#pragma unroll
+      for (int j = 0; j < kW; ++j) v[j] = j < w ? Ab[(int64_t)r * p.ld + k + j] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < kW; ++j)
+        if (j < w) Pc[(int64_t)r * kW + j] = v[j];
+    }
     return;
   }
   int row = -1;
@@ -106,8 +124,7 @@ __global__ void __launch_bounds__(kGroup) gj_select_kernel(SelectArgs p) {
         if (j < w) Pc[(int64_t)row * kW + j] = a[j];
     }
   }
-  __shared__ double s_key[kGroup / 64];
-  __shared__ int s_who[kGroup / 64];
+  __shared__ uint64_t s_key[kGroup / 64];
   __shared__ double2 s_prow[kW];
   __shared__ int s_sel[kW];
   bool alive = row >= 0;
@@ -117,30 +134,18 @@ __global__ void __launch_bounds__(kGroup) gj_select_kernel(SelectArgs p) {
 #pragma unroll
   for (int c = 0; c < kW; ++c) {
     if (c < w && nsel == c) {  // (uniform: stops at the first column with no row left)
-      double key = alive ? gj_cabs1(a[c]) : -1.0;
-      if (alive && !(key >= 0.0)) key = 0.0;  // a NaN entry counts as zero
-      int who = t;
+      uint64_t key = gj_key(alive, a[c], t);
       for (int off = 32; off > 0; off >>= 1) {
-        const double ok = __shfl_xor(key, off, 64);
-        const int ow = __shfl_xor(who, off, 64);
-        if (gj_better(ok, ow, key, who)) {
-          key = ok;
-          who = ow;
-        }
+        const uint64_t o = __shfl_xor(key, off, 64);
+        key = o > key ? o : key;
       }
-      if (lane == 0) {
-        s_key[wave] = key;
-        s_who[wave] = who;
-      }
+      if (lane == 0) s_key[wave] = key;
       __syncthreads();
-      double bk = s_key[0];
-      int bw = s_who[0];
-      for (int q = 1; q < kGroup / 64; ++q)
-        if (gj_better(s_key[q], s_who[q], bk, bw)) {
-          bk = s_key[q];
-          bw = s_who[q];
-        }
-      if (bk >= 0.0) {
+      uint64_t best = s_key[0];
+      for (int q = 1; q < kGroup / 64; ++q) best = s_key[q] > best ? s_key[q] : best;
+      const int bw = (int)~(uint32_t)best;
+      const bool nonzero = (best >> 32) != 0;
+      if (best != 0) {
         if (t == bw) {
 #pragma unroll
           for (int j = c; j < kW; ++j) s_prow[j] = a[j];
@@ -149,7 +154,7 @@ __global__ void __launch_bounds__(kGroup) gj_select_kernel(SelectArgs p) {
         }
         __syncthreads();
         nsel = c + 1;
-        if (bk > 0.0) {
+        if (nonzero) {
           if (alive) {
             const double2 l = gj_mul(a[c], gj_recip(s_prow[c]));
 #pragma unroll
@@ -245,9 +250,17 @@ __global__ void __launch_bounds__(kGroup) gj_select_kernel(SelectArgs p) {
     if (t < nd) ra[s_dd[t]] = v2;
   }
   // panel entries of the displaced positions: the rows that now sit there
-  for (int e = t; e < nd * kW; e += kGroup) {
-    const int d = e / kW, j = e % kW;
-    if (j < w) Pc[(int64_t)s_dd[d] * kW + j] = Ab[(int64_t)s_ds[d] * p.ld + k + j];
+  constexpr int kDU = kW * kW / kGroup;
+  double2 dv[kDU];
+#pragma unroll
+  for (int u = 0; u < kDU; ++u) {
+    const int e = t + kGroup * u, d = e / kW, j = e % kW;
+    dv[u] = d < nd && j < w ? Ab[(int64_t)s_ds[d] * p.ld + k + j] : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int u = 0; u < kDU; ++u) {
+    const int e = t + kGroup * u, d = e / kW, j = e % kW;
+    if (d < nd && j < w) Pc[(int64_t)s_dd[d] * kW + j] = dv[u];
   }
 }
 
