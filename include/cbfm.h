@@ -65,9 +65,10 @@ typedef enum {
   CBFM_E_ARG = -1,     /* invalid argument (null pointer, size, range)      */
   CBFM_E_MESH = -2,    /* not a closed, consistently oriented 2-manifold    */
   CBFM_E_NOMEM = -3,   /* device or host allocation failed                  */
-  CBFM_E_HIP = -4,     /* a HIP / rocSOLVER call failed                     */
+  CBFM_E_HIP = -4,     /* a HIP call failed                                 */
   CBFM_E_NOCONV = -5,  /* GMRES reached max_iter; outputs hold the iterate  */
-  CBFM_E_RANK = -6,    /* a cell kept no CBF (L_m = 0)                      */
+  CBFM_E_RANK = -6,    /* a cell kept no CBF (L_m = 0), or a matrix to be
+                          solved or inverted has no nonzero pivot          */
   CBFM_E_STATE = -7    /* handles of different meshes mixed                 */
 } cbfm_status;
 
@@ -203,7 +204,9 @@ cbfm_status cbfm_rhs(cbfm_mesh m, const cbfm_medium* med, const double* inc_host
  * cbfm_build_cbf: primary CBFs with dual orthogonalisation (paper Sec.
  * III-A eq. of the primary CBFs, Sec. III-B eqs. of G_m, G'_m, the SVD and
  * C^M = J^M U_L, C^J = J^J V_L): per cell, Z_mm J_m = V_m for the n_gen
- * generating waves (LU), G'_m = (J^M)^H G_m J^J, SVD, keep sigma_i/sigma_1 >=
+ * generating waves (Gauss-Jordan elimination, pivot rows chosen by partial
+ * pivoting in a tournament over row groups, all cells in one batch),
+ * G'_m = (J^M)^H G_m J^J, SVD, keep sigma_i/sigma_1 >=
  * delta_svd (at most max_L if max_L > 0).  FP64 throughout.
  * Synchronises the stream (the kept counts L_m are host data).
  * On a mesh of translated copies of one cell (see cbfm_mesh_load) the
@@ -269,8 +272,11 @@ cbfm_status cbfm_project_batch(int32_t count, const cbfm_mesh* meshes, const cbf
 
 /* ----------------------------------------------------------------- CMP ---
  * cbfm_cmp_apply: x = (G^CBF)^{-1} y with G^CBF = (C^JM)^H G_ffff C^MJ
- * (paper Sec. III-C, CBF Gram matrix and inner CBFM equation), exact
- * (LU factors kept in the cbfm_cbf handle, formed on first use).
+ * (paper Sec. III-C, CBF Gram matrix and inner CBFM equation), exact:
+ * G^CBF = blkdiag(-B^H, B) with B = (C^M)^H G C^J, and B^{-1} is formed on
+ * first use by in-place Gauss-Jordan elimination (cell by cell when no
+ * triangle carries RWGs of two cells) and kept in the cbfm_cbf handle.
+ * Returns CBFM_E_RANK if B has no nonzero pivot.
  *   y_dev, x_dev  nrhs x N_CBF double2, vector after vector (may alias)    */
 cbfm_status cbfm_cmp_apply(cbfm_cbf c, int64_t nrhs, const void* y_dev, void* x_dev,
                            void* stream);
