@@ -112,6 +112,26 @@ def test_cmp_apply_parity_two_pivot_rounds(torch_cuda):
     assert back < 1e-14 and fwd < 1e-14 * cond
 
 
+@pytest.mark.parametrize("name", ["cyl_small", "array2"])
+def test_cmp_singular_b_reports_rank(torch_cuda, name):
+    """With the magnetic CBFs set to zero, B = (C^M)^H G C^J is zero: the
+    Gauss-Jordan inverse (dense for the coupled cylinder cells, block by
+    block for the two disjoint spheres) finds no nonzero pivot and
+    cmp_apply returns E_RANK; every kernel still runs to its end."""
+    from paper_2111_11058_amd import cbfm
+    O = _oracle_cbf(name)
+    w = O["P"]["w"]
+    mesh = cbfm.Mesh(w.V, w.T, w.edge_block, w.nblocks)
+    cbf = cbfm.cbf_import(mesh, [np.zeros_like(c) for c in O["cb"].CM], O["cb"].CJ, O["cb"].sigma)
+    n = cbf.n_cbf
+    y = torch_cuda.ones((1, n), dtype=torch_cuda.complex128, device="cuda")
+    x = torch_cuda.empty_like(y)
+    with pytest.raises(cbfm.CBFMError) as e:
+        cbfm.cmp_apply(cbf, y, x)
+    print(e.value)
+    assert e.value.code == -6 and "singular" in str(e.value)
+
+
 def test_build_cbf_one_cell_order_960(torch_cuda):
     """The whole c1 body as one cell: its isolated system has order 960 (the
     first panels' pivot rows come from four groups of 256 rows and a second
