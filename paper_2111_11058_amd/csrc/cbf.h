@@ -25,6 +25,18 @@ struct cbfm_cbf_s {
   std::mutex mu;
   bool factored = false;
   cbfm::DevBuf Binv;
+  // after a CBF build, B^{-1} is formed on a side stream that overlaps the
+  // caller's next work (the projection): `done` marks its end and dinfo
+  // (ninfo entries, one per inverted block) its pivot checks, read at the
+  // first use
+  bool pending = false;
+  hipEvent_t done = nullptr;
+  cbfm::DevBuf dinfo;
+  int ninfo = 0;
+  cbfm_cbf_s() = default;
+  cbfm_cbf_s(const cbfm_cbf_s&) = delete;
+  cbfm_cbf_s& operator=(const cbfm_cbf_s&) = delete;
+  ~cbfm_cbf_s();  // waits for `done`
 };
 
 namespace cbfm {

@@ -491,8 +491,9 @@ __global__ void cmp_blocks_kernel(double2* __restrict__ B, int64_t NL, const int
 
 // Invert the diagonal blocks of a block-diagonal B in place (one batched
 // Gauss-Jordan inversion, blocks padded with the identity to the largest);
-// the blocks off the diagonal are zeros and stay so.
-static void invert_blocks(cbfm_cbf_s* c, hipStream_t s) {
+// the blocks off the diagonal are zeros and stay so.  async: the pivot
+// checks are left in c->dinfo, nothing is waited for.
+static void invert_blocks(cbfm_cbf_s* c, hipStream_t s, bool async) {
   const MeshHost& h = c->mesh->h;
   const int64_t NL = c->NL;
   const int nb = h.nblocks;
@@ -502,18 +503,24 @@ static void invert_blocks(cbfm_cbf_s* c, hipStream_t s) {
   hipLaunchKernelGGL(cmp_blocks_kernel, g, dim3(64), 0, s, c->Binv.as<double2>(), NL, c->d_off.as<int64_t>(),
                      c->d_L.as<int32_t>(), Lmax, P.as<double2>(), 1);
   CBFM_HIP(hipGetLastError());
-  gj_inverse_batched(P.as<double2>(), (int64_t)Lmax * Lmax, Lmax, nb, "G^CBF block of cell", s);
+  if (async) {
+    c->dinfo.alloc((size_t)nb * sizeof(int32_t));
+    c->ninfo = nb;
+    gj_inverse_batched_async(P.as<double2>(), (int64_t)Lmax * Lmax, Lmax, nb, c->dinfo.as<int32_t>(), s);
+  } else {
+    gj_inverse_batched(P.as<double2>(), (int64_t)Lmax * Lmax, Lmax, nb, "G^CBF block of cell", s);
+  }
   hipLaunchKernelGGL(cmp_blocks_kernel, g, dim3(64), 0, s, c->Binv.as<double2>(), NL, c->d_off.as<int64_t>(),
                      c->d_L.as<int32_t>(), Lmax, P.as<double2>(), 0);
   CBFM_HIP(hipGetLastError());
-  c->factored = true;
 }
 
 // B^{-1} for B = (C^M)^H G C^J (row-major, inverted in place by blocked
 // Gauss-Jordan elimination).  A block-diagonal B is inverted block by block
 // (one batched call; the blocks off the diagonal are exact zeros and stay
-// so).
-static void cmp_factor(cbfm_cbf_s* c, hipStream_t s) {
+// so).  async: enqueue only, the pivot checks left in c->dinfo (the caller
+// marks the result pending); else checked, and c->factored set.
+static void cmp_factor(cbfm_cbf_s* c, hipStream_t s, bool async = false) {
   const cbfm_mesh_s* m = c->mesh;
   const MeshHost& h = m->h;
   const int64_t NL = c->NL, ne = h.ne;
@@ -536,7 +543,8 @@ static void cmp_factor(cbfm_cbf_s* c, hipStream_t s) {
                         c->Binv.as<double2>() + c->off[a] * NL + c->off[a], NL, La, La, Na));
     }
     zgemm_batched(ds, s);
-    invert_blocks(c, s);
+    invert_blocks(c, s, async);
+    if (!async) c->factored = true;
     return;
   }
   CBFM_REQUIRE(ne <= 65535, CBFM_E_ARG, "G^CBF coupling cells: at most 65535 RWGs");
@@ -557,12 +565,66 @@ static void cmp_factor(cbfm_cbf_s* c, hipStream_t s) {
   }
   zgemm_batched(ds, s);
   CBFM_REQUIRE(NL <= 65535, CBFM_E_ARG, "G^CBF coupling cells: at most 65535 CBFs per current");
+  if (async) {
+    c->dinfo.alloc(sizeof(int32_t));
+    c->ninfo = 1;
+    gj_inverse_batched_async(c->Binv.as<double2>(), NL * NL, (int)NL, 1, c->dinfo.as<int32_t>(), s);
+    return;
+  }
   gj_inverse_batched(c->Binv.as<double2>(), NL * NL, (int)NL, 1, "G^CBF", s);
   c->factored = true;
 }
 
+// A side stream per device and host thread (default priority) for work that
+// overlaps the caller's stream.  Non-blocking: a blocking stream would
+// synchronise with the legacy default stream that callers often use, and the
+// overlap would be lost; the ordering is explicit (events) both ways.
+static hipStream_t side_stream() {
+  static thread_local std::map<int, hipStream_t> streams;
+  int dev = 0;
+  CBFM_HIP(hipGetDevice(&dev));
+  auto it = streams.find(dev);
+  if (it == streams.end()) {
+    hipStream_t st = nullptr;
+    CBFM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    it = streams.emplace(dev, st).first;
+  }
+  return it->second;
+}
+
+// Start B^{-1} on the side stream after the work queued so far on s (the
+// CBF build), so that it overlaps what the caller queues next; the first
+// cmp_inverse waits for it and checks its pivots.  On any failure here the
+// handle is left unfactored and cmp_inverse forms B^{-1} itself.
+static void cmp_factor_async(cbfm_cbf_s* c, hipStream_t s) {
+  hipStream_t side = nullptr;
+  try {
+    side = side_stream();
+    hipEvent_t start = nullptr;
+    CBFM_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    const hipError_t e1 = hipEventRecord(start, s), e2 = e1 == hipSuccess ? hipStreamWaitEvent(side, start, 0) : e1;
+    (void)hipEventDestroy(start);  // (released once the wait is done)
+    CBFM_HIP(e2);
+    if (!c->done) CBFM_HIP(hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
+    cmp_factor(c, side, true);
+    CBFM_HIP(hipEventRecord(c->done, side));
+    c->pending = true;
+  } catch (...) {
+    if (side) (void)hipStreamSynchronize(side);
+    (void)hipGetLastError();
+    c->pending = false;
+    c->factored = false;
+  }
+}
+
 const double2* cmp_inverse(cbfm_cbf_s* c, hipStream_t s) {
   std::lock_guard<std::mutex> lk(c->mu);
+  if (c->pending) {
+    c->pending = false;
+    CBFM_HIP(hipStreamWaitEvent(s, c->done, 0));
+    gj_check(c->dinfo.as<int32_t>(), c->ninfo, c->blockdiag ? "G^CBF block of cell" : "G^CBF", s);
+    c->factored = true;
+  }
   if (!c->factored) cmp_factor(c, s);
   return c->Binv.as<double2>();
 }
@@ -644,6 +706,13 @@ static std::vector<CellSupport> supports(const MeshHost& h, int nb) {
 }  // namespace cbfm
 
 using namespace cbfm;
+
+cbfm_cbf_s::~cbfm_cbf_s() {
+  if (done) {
+    (void)hipEventSynchronize(done);
+    (void)hipEventDestroy(done);
+  }
+}
 
 extern "C" {
 
@@ -877,6 +946,7 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
                                   hipMemcpyDeviceToDevice, s));
         }
       }
+      cmp_factor_async(c, s);
     } catch (...) {
       delete c;
       throw;

@@ -350,10 +350,20 @@ __global__ void gj_gather_kernel(const double2* __restrict__ in, double2* __rest
   out[row + j] = in[row + src[(int64_t)b * n + j]];
 }
 
-// The elimination itself; returns every matrix's info (0: no zero pivot)
-// and, for an inversion, the input row each position holds at the end.
-std::vector<int32_t> eliminate(double2* A, int64_t strideA, int64_t ld, int n, int ncols, int nmat, bool inverse,
-                               std::vector<int32_t>* rowat_host, hipStream_t s) {
+// src_b[rowat_b[q]] = q: the position that holds each input row.
+__global__ void gj_src_kernel(const int32_t* __restrict__ rowat, int32_t* __restrict__ src, int n, int64_t total) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const int64_t b = e / n;
+  src[b * n + rowat[e]] = (int32_t)(e - b * n);
+}
+
+// The elimination, enqueued on s with no host wait: info_dev (nmat entries)
+// receives 0 or 1 + the first column without a nonzero pivot.  An inversion
+// ends with the column gather.  Every scratch buffer is released in stream
+// order.
+void eliminate(double2* A, int64_t strideA, int64_t ld, int n, int ncols, int nmat, bool inverse, int32_t* info_dev,
+               hipStream_t s) {
   CBFM_REQUIRE(n >= 1 && n <= 65535 && nmat >= 1 && nmat <= 65535, CBFM_E_ARG,
                "Gauss-Jordan: order in [1, 65535] and at most 65535 matrices");
   CBFM_REQUIRE(ncols >= n && ld >= ncols && strideA >= (int64_t)(n - 1) * ld + ncols, CBFM_E_ARG,
@@ -364,9 +374,9 @@ std::vector<int32_t> eliminate(double2* A, int64_t strideA, int64_t ld, int n, i
   Scratch pcol((size_t)nmat * n * kW * sizeof(double2), s), dinv((size_t)nmat * kW * kW * sizeof(double2), s),
       swaps((size_t)nmat * kSwapInts * sizeof(int32_t), s),
       rowat(inverse ? (size_t)nmat * n * sizeof(int32_t) : 0, s),
-      info((size_t)nmat * sizeof(int32_t), s), cand0((size_t)nmat * cstride * sizeof(int32_t), s),
+      cand0((size_t)nmat * cstride * sizeof(int32_t), s),
       cand1((size_t)nmat * cstride * sizeof(int32_t), s);
-  CBFM_HIP(hipMemsetAsync(info.p, 0, (size_t)nmat * sizeof(int32_t), s));
+  CBFM_HIP(hipMemsetAsync(info_dev, 0, (size_t)nmat * sizeof(int32_t), s));
   if (inverse) {
     const int64_t total = (int64_t)nmat * n;
     hipLaunchKernelGGL(gj_iota_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, rowat.as<int32_t>(), n,
@@ -415,7 +425,7 @@ std::vector<int32_t> eliminate(double2* A, int64_t strideA, int64_t ld, int n, i
     a.Dinv = dinv.as<double2>();
     a.swaps = swaps.as<int32_t>();
     a.rowat = inverse ? rowat.as<int32_t>() : nullptr;
-    a.info = info.as<int32_t>();
+    a.info = info_dev;
     int G = (n - k + kGroup - 1) / kGroup, cur = 0;
     a.cand_in = nullptr;
     a.cand_len = 0;
@@ -454,53 +464,48 @@ std::vector<int32_t> eliminate(double2* A, int64_t strideA, int64_t ld, int n, i
     }
     plan.launch((size_t)st, s);
   }
-  std::vector<int32_t> hinfo(nmat);
-  CBFM_HIP(hipMemcpyAsync(hinfo.data(), info.p, (size_t)nmat * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  if (rowat_host) {
-    rowat_host->resize((size_t)nmat * n);
-    CBFM_HIP(hipMemcpyAsync(rowat_host->data(), rowat.p, (size_t)nmat * n * sizeof(int32_t), hipMemcpyDeviceToHost,
-                            s));
-  }
-  CBFM_HIP(hipStreamSynchronize(s));
-  return hinfo;
-}
-
-void check_info(const std::vector<int32_t>& info, const char* what) {
-  for (size_t b = 0; b < info.size(); ++b)
-    CBFM_REQUIRE(info[b] == 0, CBFM_E_RANK,
-                 std::string(what) + (info.size() > 1 ? " " + std::to_string(b) : std::string()) +
-                     " is singular (no nonzero pivot in column " + std::to_string(info[b] - 1) + ")");
+  if (!inverse) return;
+  // column j of the inverse sits at the position that holds input row j
+  const int64_t total = (int64_t)nmat * n;
+  Scratch src((size_t)total * sizeof(int32_t), s), tmp((size_t)nmat * strideA * sizeof(double2), s);
+  CBFM_HIP(hipMemsetAsync(src.p, 0, (size_t)total * sizeof(int32_t), s));
+  hipLaunchKernelGGL(gj_src_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, rowat.as<int32_t>(),
+                     src.as<int32_t>(), n, total);
+  hipLaunchKernelGGL(gj_gather_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)n, (unsigned)nmat), dim3(256), 0,
+                     s, A, tmp.as<double2>(), src.as<int32_t>(), n, strideA);
+  CBFM_HIP(hipGetLastError());
+  CBFM_HIP(hipMemcpyAsync(A, tmp.p, (size_t)nmat * strideA * sizeof(double2), hipMemcpyDeviceToDevice, s));
 }
 
 }  // namespace
 
-void gj_inverse_batched(double2* A, int64_t strideA, int n, int nmat, const char* what, hipStream_t s) {
+void gj_check(const int32_t* info_dev, int nmat, const char* what, hipStream_t s) {
+  std::vector<int32_t> info(nmat);
+  CBFM_HIP(hipMemcpyAsync(info.data(), info_dev, (size_t)nmat * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  CBFM_HIP(hipStreamSynchronize(s));
+  for (int b = 0; b < nmat; ++b)
+    CBFM_REQUIRE(info[b] == 0, CBFM_E_RANK,
+                 std::string(what) + (nmat > 1 ? " " + std::to_string(b) : std::string()) +
+                     " is singular (no nonzero pivot in column " + std::to_string(info[b] - 1) + ")");
+}
+
+void gj_inverse_batched_async(double2* A, int64_t strideA, int n, int nmat, int32_t* info_dev, hipStream_t s) {
   CBFM_REQUIRE(strideA == (int64_t)n * n, CBFM_E_ARG, "Gauss-Jordan inversion: matrices must be packed");
-  std::vector<int32_t> rowat;
-  check_info(eliminate(A, strideA, n, n, n, nmat, true, &rowat, s), what);
-  // column j of the inverse sits at the position that holds input row j
-  std::vector<int32_t> src((size_t)nmat * n, -1);
-  for (int b = 0; b < nmat; ++b) {
-    int32_t* sb = src.data() + (size_t)b * n;
-    const int32_t* rb = rowat.data() + (size_t)b * n;
-    for (int q = 0; q < n; ++q) {
-      CBFM_REQUIRE(rb[q] >= 0 && rb[q] < n && sb[rb[q]] < 0, CBFM_E_HIP, "Gauss-Jordan: row map is not a permutation");
-      sb[rb[q]] = q;
-    }
-  }
-  Scratch dsrc(src.size() * sizeof(int32_t), s), tmp((size_t)nmat * strideA * sizeof(double2), s);
-  CBFM_HIP(hipMemcpyAsync(dsrc.p, src.data(), src.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(gj_gather_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)n, (unsigned)nmat), dim3(256), 0,
-                     s, A, tmp.as<double2>(), dsrc.as<int32_t>(), n, strideA);
-  CBFM_HIP(hipGetLastError());
-  CBFM_HIP(hipMemcpyAsync(A, tmp.p, (size_t)nmat * strideA * sizeof(double2), hipMemcpyDeviceToDevice, s));
-  CBFM_HIP(hipStreamSynchronize(s));  // `src` is host memory of this frame
+  eliminate(A, strideA, n, n, n, nmat, true, info_dev, s);
+}
+
+void gj_inverse_batched(double2* A, int64_t strideA, int n, int nmat, const char* what, hipStream_t s) {
+  Scratch info((size_t)std::max(1, nmat) * sizeof(int32_t), s);
+  gj_inverse_batched_async(A, strideA, n, nmat, info.as<int32_t>(), s);
+  gj_check(info.as<int32_t>(), nmat, what, s);
 }
 
 void gj_solve_batched(double2* A, int64_t strideA, int64_t ld, int n, int ncols, int nmat, const char* what,
                       hipStream_t s) {
   CBFM_REQUIRE(ncols > n, CBFM_E_ARG, "Gauss-Jordan solve: no right-hand side");
-  check_info(eliminate(A, strideA, ld, n, ncols, nmat, false, nullptr, s), what);
+  Scratch info((size_t)std::max(1, nmat) * sizeof(int32_t), s);
+  eliminate(A, strideA, ld, n, ncols, nmat, false, info.as<int32_t>(), s);
+  gj_check(info.as<int32_t>(), nmat, what, s);
 }
 
 }  // namespace cbfm

@@ -14,6 +14,11 @@
 //  * a released block carries an event recorded on the releasing stream, and
 //    the next user's stream waits on it, so reuse is ordered after every
 //    operation queued before the release, on any stream;
+//  * among the cached blocks that fit, one released on the requesting stream
+//    (stream order alone makes it free) or one whose event has completed is
+//    taken first; a block still in use on another stream is taken only if a
+//    new allocation fails, so that work on two streams (the CMP inverse
+//    formed beside the projection) does not serialise through the cache;
 //  * the bytes cached per device are capped at kCacheCap (the oldest blocks
 //    are freed first), and if an allocation fails, the device's cached blocks
 //    are freed (after their events complete) and the allocation is retried.
@@ -43,6 +48,7 @@ struct Block {
   size_t bytes;
   int dev;
   hipEvent_t ready;
+  hipStream_t stream;  // the releasing stream
 };
 
 struct Cache {
@@ -114,44 +120,57 @@ void* scratch_alloc(size_t bytes, hipStream_t s) {
   CBFM_HIP(hipGetDevice(&dev));
   const size_t want = block_size(bytes);
   const bool big = want >= kBigScratch;
+  auto fits = [&](const Block& b) {
+    return b.dev == dev && (big ? b.bytes >= want && b.bytes <= 2 * want : b.bytes == want);
+  };
+  // take cached block i (lock held on entry, released on return)
+  auto take = [&](std::unique_lock<std::mutex>& lk, size_t i) {
+    const Block b = cache().free[i];
+    cache().free.erase(cache().free.begin() + (ptrdiff_t)i);  // (keeps the release order)
+    lk.unlock();
+    // (also on the releasing stream: a stream handle may name a new stream
+    // once the old one is destroyed)
+    if (hipStreamWaitEvent(s, b.ready, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipEventSynchronize(b.ready);  // keep the ordering before handing the block out
+    }
+    lk.lock();
+    spare_event(dev, b.ready);  // re-recording later leaves a queued wait as it was
+    return b.p;
+  };
+  size_t busy = SIZE_MAX;  // a fitting block still in use on another stream
   {
     std::unique_lock<std::mutex> lk(cache().mu);
     auto& f = cache().free;
-    // a block of the same class; for large requests the smallest cached
-    // block that fits and wastes at most half of itself
-    size_t best = f.size();
+    // the smallest fitting block that is free to use now: released on this
+    // stream, or its release event completed
+    size_t best = SIZE_MAX;
     for (size_t i = 0; i < f.size(); ++i) {
-      if (f[i].dev != dev) continue;
-      if (!big) {
-        if (f[i].bytes == want) {
-          best = i;
-          break;
-        }
-      } else if (f[i].bytes >= want && f[i].bytes <= 2 * want && (best == f.size() || f[i].bytes < f[best].bytes)) {
-        best = i;
+      if (!fits(f[i])) continue;
+      const bool now = f[i].stream == s || hipEventQuery(f[i].ready) == hipSuccess;
+      if (!now) {
+        (void)hipGetLastError();  // (hipErrorNotReady)
+        if (busy == SIZE_MAX || f[i].bytes < f[busy].bytes) busy = i;
+        continue;
       }
+      if (best == SIZE_MAX || f[i].bytes < f[best].bytes) best = i;
+      if (!big) break;
     }
-    if (best < f.size()) {
-      const Block b = f[best];
-      f.erase(f.begin() + (ptrdiff_t)best);  // (keeps the release order)
-      lk.unlock();
-      if (hipStreamWaitEvent(s, b.ready, 0) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipEventSynchronize(b.ready);  // keep the ordering before handing the block out
-      }
-      lk.lock();
-      spare_event(dev, b.ready);  // re-recording later leaves the queued wait as it was
-      return b.p;
-    }
+    if (best != SIZE_MAX) return take(lk, best);
   }
   void* p = nullptr;
+  if (hipMalloc(&p, want) == hipSuccess) return p;
+  (void)hipGetLastError();
+  if (busy != SIZE_MAX) {  // wait for a block in use rather than fail
+    std::unique_lock<std::mutex> lk(cache().mu);
+    auto& f = cache().free;
+    for (size_t i = 0; i < f.size(); ++i)
+      if (fits(f[i])) return take(lk, i);
+  }
+  trim(dev);
   if (hipMalloc(&p, want) != hipSuccess) {
     (void)hipGetLastError();
-    trim(dev);
-    if (hipMalloc(&p, want) != hipSuccess) {
-      (void)hipGetLastError();
-      throw Error{CBFM_E_NOMEM, "device allocation of " + std::to_string(want) + " bytes failed"};
-    }
+    throw Error{CBFM_E_NOMEM, "device allocation of " + std::to_string(want) + " bytes failed"};
   }
   return p;
 }
@@ -171,7 +190,7 @@ void scratch_release(void* p, size_t bytes, hipStream_t s) {
   {
     std::lock_guard<std::mutex> lk(cache().mu);
     auto& f = cache().free;
-    f.push_back({p, block_size(bytes), dev, ev});
+    f.push_back({p, block_size(bytes), dev, ev, s});
     size_t held = 0;
     for (const Block& b : f)
       if (b.dev == dev) held += b.bytes;
