@@ -316,7 +316,9 @@ def main():
             Zr = state[n] = torch.empty((n, n), dtype=torch.complex128, device="cuda")
         t0 = time.perf_counter()
         cbfm.project(mesh, med, cb, Zr, precision)
-        torch.cuda.synchronize()
+        # (the caller's stream only: the CMP inverse that the CBF build left
+        # on the library's side stream may still run beside the projection)
+        torch.cuda.current_stream().synchronize()
         t1 = time.perf_counter()
         # full (unrestarted) GMRES while the Krylov basis of all right-hand
         # sides stays small, else cycles of 1000

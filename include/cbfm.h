@@ -212,6 +212,10 @@ cbfm_status cbfm_rhs(cbfm_mesh m, const cbfm_medium* med, const double* inc_host
  * On a mesh of translated copies of one cell (see cbfm_mesh_load) the
  * waves on each cell are those on cell 0 times one phase per wave, so every
  * cell receives cell 0's count, singular values and CBFs (the same spaces).
+ * Before returning, the CMP inverse of the new set (see cbfm_cmp_apply) is
+ * queued on a library-owned side stream that waits for the build's work on
+ * `stream`, so that it runs beside what the caller queues next; its first
+ * use waits for it, and cbfm_cbf_free waits for it before freeing.
  * Returns CBFM_E_ARG for n_gen outside [1, 4096] or a mesh of more than
  * 32767 cells or 32767 RWGs in one cell, CBFM_E_RANK if a cell's Z_mm is
  * singular or a cell keeps no CBF.                                         */

@@ -30,17 +30,21 @@ struct cbfm_cbf_s {
   // (ninfo entries, one per inverted block) its pivot checks, read at the
   // first use
   bool pending = false;
-  hipEvent_t done = nullptr;
+  hipEvent_t start = nullptr, done = nullptr;
   cbfm::DevBuf dinfo;
   int ninfo = 0;
   cbfm_cbf_s() = default;
   cbfm_cbf_s(const cbfm_cbf_s&) = delete;
   cbfm_cbf_s& operator=(const cbfm_cbf_s&) = delete;
-  ~cbfm_cbf_s();  // waits for `done`
+  ~cbfm_cbf_s();  // waits for both events
 };
 
 namespace cbfm {
 
+// Whether CBF builds on the calling thread queue the CMP inverse on a side
+// stream (the default) or leave it to the first use (serving workers, whose
+// requests already overlap one another).
+void async_cmp_on_this_thread(bool on);
 // x <- (G^CBF)^{-1} x in place, nrhs vectors of length 2 NL
 void cmp_apply_dev(cbfm_cbf_s* c, int64_t nrhs, double2* x, hipStream_t s);
 // B^{-1} (NL x NL, row-major), formed on first use

@@ -587,10 +587,14 @@ static hipStream_t side_stream() {
   if (it == streams.end()) {
     hipStream_t st = nullptr;
     CBFM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    scratch_side_stream(st);
     it = streams.emplace(dev, st).first;
   }
   return it->second;
 }
+
+static thread_local bool t_async_cmp = true;
+void async_cmp_on_this_thread(bool on) { t_async_cmp = on; }
 
 // Start B^{-1} on the side stream after the work queued so far on s (the
 // CBF build), so that it overlaps what the caller queues next; the first
@@ -600,12 +604,12 @@ static void cmp_factor_async(cbfm_cbf_s* c, hipStream_t s) {
   hipStream_t side = nullptr;
   try {
     side = side_stream();
-    hipEvent_t start = nullptr;
-    CBFM_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
-    const hipError_t e1 = hipEventRecord(start, s), e2 = e1 == hipSuccess ? hipStreamWaitEvent(side, start, 0) : e1;
-    (void)hipEventDestroy(start);  // (released once the wait is done)
-    CBFM_HIP(e2);
+    // (both events live as long as the handle: none is destroyed while a
+    // wait on it may still be queued)
+    if (!c->start) CBFM_HIP(hipEventCreateWithFlags(&c->start, hipEventDisableTiming));
     if (!c->done) CBFM_HIP(hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
+    CBFM_HIP(hipEventRecord(c->start, s));
+    CBFM_HIP(hipStreamWaitEvent(side, c->start, 0));
     cmp_factor(c, side, true);
     CBFM_HIP(hipEventRecord(c->done, side));
     c->pending = true;
@@ -711,6 +715,10 @@ cbfm_cbf_s::~cbfm_cbf_s() {
   if (done) {
     (void)hipEventSynchronize(done);
     (void)hipEventDestroy(done);
+  }
+  if (start) {
+    (void)hipEventSynchronize(start);
+    (void)hipEventDestroy(start);
   }
 }
 
@@ -946,7 +954,7 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
                                   hipMemcpyDeviceToDevice, s));
         }
       }
-      cmp_factor_async(c, s);
+      if (t_async_cmp) cmp_factor_async(c, s);
     } catch (...) {
       delete c;
       throw;

@@ -15,13 +15,17 @@
 //    the next user's stream waits on it, so reuse is ordered after every
 //    operation queued before the release, on any stream;
 //  * among the cached blocks that fit, one released on the requesting stream
-//    (stream order alone makes it free) or one whose event has completed is
-//    taken first; a block still in use on another stream is taken only if a
-//    new allocation fails, so that work on two streams (the CMP inverse
-//    formed beside the projection) does not serialise through the cache;
+//    is taken first (stream order already puts it after its last use), then
+//    one released on another stream.  A block released on a library side
+//    stream is taken by another stream only if a new allocation fails, so
+//    that the CMP inverse formed there does not hold back the caller's
+//    projection through the cache.  (Choices go by the releasing stream
+//    alone: the cache queries no event, since an event recorded on a stream
+//    that has since been destroyed is only ever waited on);
 //  * the bytes cached per device are capped at kCacheCap (the oldest blocks
 //    are freed first), and if an allocation fails, the device's cached blocks
 //    are freed (after their events complete) and the allocation is retried.
+#include <algorithm>
 #include <cstdint>
 #include <mutex>
 #include <utility>
@@ -53,6 +57,7 @@ struct Block {
 
 struct Cache {
   std::mutex mu;
+  std::vector<hipStream_t> side;                   // library side streams
   std::vector<Block> free;                         // in release order
   std::vector<std::pair<int, hipEvent_t>> events;  // spare events and their devices
 };
@@ -138,25 +143,21 @@ void* scratch_alloc(size_t bytes, hipStream_t s) {
     spare_event(dev, b.ready);  // re-recording later leaves a queued wait as it was
     return b.p;
   };
-  size_t busy = SIZE_MAX;  // a fitting block still in use on another stream
+  size_t busy = SIZE_MAX;  // a fitting block released on a side stream
   {
     std::unique_lock<std::mutex> lk(cache().mu);
     auto& f = cache().free;
-    // the smallest fitting block that is free to use now: released on this
-    // stream, or its release event completed
-    size_t best = SIZE_MAX;
+    const auto& side = cache().side;
+    size_t same = SIZE_MAX, other = SIZE_MAX;
     for (size_t i = 0; i < f.size(); ++i) {
       if (!fits(f[i])) continue;
-      const bool now = f[i].stream == s || hipEventQuery(f[i].ready) == hipSuccess;
-      if (!now) {
-        (void)hipGetLastError();  // (hipErrorNotReady)
-        if (busy == SIZE_MAX || f[i].bytes < f[busy].bytes) busy = i;
-        continue;
-      }
-      if (best == SIZE_MAX || f[i].bytes < f[best].bytes) best = i;
-      if (!big) break;
+      size_t& slot = f[i].stream == s ? same
+                     : std::find(side.begin(), side.end(), f[i].stream) != side.end() ? busy
+                                                                                         : other;
+      if (slot == SIZE_MAX || f[i].bytes < f[slot].bytes) slot = i;
     }
-    if (best != SIZE_MAX) return take(lk, best);
+    if (same != SIZE_MAX) return take(lk, same);
+    if (other != SIZE_MAX) return take(lk, other);
   }
   void* p = nullptr;
   if (hipMalloc(&p, want) == hipSuccess) return p;
@@ -206,6 +207,11 @@ void scratch_release(void* p, size_t bytes, hipStream_t s) {
     }
   }
   free_blocks(drop);
+}
+
+void scratch_side_stream(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(cache().mu);
+  cache().side.push_back(s);
 }
 
 size_t scratch_cached_bytes() {

@@ -238,6 +238,7 @@ void cbfm_server_s::run(Job* j, hipStream_t s) {
 void cbfm_server_s::worker() {
   hipStream_t s = nullptr;
   const bool ok = hipSetDevice(device) == hipSuccess && hipStreamCreate(&s) == hipSuccess;
+  cbfm::async_cmp_on_this_thread(false);  // requests overlap one another already
   for (;;) {
     Job* j = nullptr;
     {
