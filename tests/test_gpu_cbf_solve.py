@@ -132,6 +132,37 @@ def test_cmp_singular_b_reports_rank(torch_cuda, name):
     assert e.value.code == -6 and "singular" in str(e.value)
 
 
+def test_cmp_inverse_formed_beside_the_projection(torch_cuda):
+    """cbfm_build_cbf leaves the CMP inverse on the library's side stream,
+    where it runs beside what is queued next (here the projection);
+    cmp_apply waits for it.  Checked against G^CBF that the oracle forms
+    from the exported CBFs (backward error)."""
+    from oracle import cbf as ocbf, reduced
+    from paper_2111_11058_amd import cbfm
+    O = _oracle_cbf("c1")
+    P = O["P"]
+    w, m = P["w"], P["m"]
+    mesh = cbfm.Mesh(w.V, w.T, w.edge_block, w.nblocks)
+    med = cbfm.Medium.make(w.k0, w.eta0, w.eps_r, w.mu_r)
+    cb = cbfm.build_cbf(mesh, med, w.gen, 1e-3)
+    n = cb.n_cbf
+    Zr = torch_cuda.zeros((n, n), dtype=torch_cuda.complex128, device="cuda")
+    cbfm.project(mesh, med, cb, Zr, cbfm.FP64)
+    CM, CJ = cb.export()
+    got = ocbf.CBFSet(O["cb"].cells, CM, CJ, O["cb"].sigma, O["cb"].sigma_all)
+    CJM, CMJ = reduced.cbf_matrices(got, m.ne)
+    Gc = reduced.gram_cbf(O["G"], CJM, CMJ)
+    rng = np.random.default_rng(14)
+    y = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    yt = torch_cuda.tensor(y, dtype=torch_cuda.complex128, device="cuda")
+    xt = torch_cuda.empty_like(yt)
+    cbfm.cmp_apply(cb, yt, xt)
+    x = xt.cpu().numpy()
+    back = np.linalg.norm(x @ Gc.T - y) / (np.linalg.norm(Gc, 2) * np.linalg.norm(x))
+    print("cmp after build: backward error", back)
+    assert back < 1e-14
+
+
 def test_build_cbf_one_cell_order_960(torch_cuda):
     """The whole c1 body as one cell: its isolated system has order 960 (the
     first panels' pivot rows come from four groups of 256 rows and a second
