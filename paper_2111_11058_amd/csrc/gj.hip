@@ -70,7 +70,7 @@ struct SelectArgs {
   const double2* A;
   int64_t strideA, ld;
   int n, k, w;
-  const int32_t* cand_in;  // this round's candidate rows (null: the rows k .. n - 1)
+  const int32_t* cand_in;  // candidate rows of this tournament stage (null: the rows k .. n - 1)
   int cand_len;            // entries of cand_in per matrix (-1 marks an empty slot)
   int nsel_groups;         // blocks that select; at the first round the blocks
                            // after them copy the panel entries of rows 0 .. k - 1
