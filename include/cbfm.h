@@ -158,6 +158,9 @@ cbfm_status cbfm_mesh_info(cbfm_mesh m, int64_t* ne, int64_t* nt, int32_t* nbloc
    cell of each edge (int32, host), or NULL. */
 cbfm_status cbfm_mesh_edges(cbfm_mesh m, int32_t* edge_vertices_host, int32_t* edge_block_host);
 
+/* Frees the mesh.  Every cbfm_cbf built on or imported for it must be freed
+   first: a CBF handle reads the mesh's tables, also from the library's side
+   stream while the CMP inverse that cbfm_build_cbf queued is running. */
 void cbfm_mesh_free(cbfm_mesh m);
 
 /* cbfm_mesh_analyze: the host-side part of cbfm_mesh_load only (validation,
