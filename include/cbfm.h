@@ -235,7 +235,9 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
 /* cbfm_cbf_import: wrap given CBFs (for parity checks with an external
    computation).  L_host: per-cell counts; CM_host / CJ_host: cell after cell,
    each N_m x L_m row-major double2 with rows in canonical edge order of the
-   cell's edges; sigma_host: sum(L) doubles (cell after cell).              */
+   cell's edges; sigma_host: sum(L) doubles (cell after cell).  On a mesh of
+   translated copies of one cell, CBFs identical (bit for bit) in every cell
+   are shared as those of cbfm_build_cbf (projection by cell offsets).      */
 cbfm_status cbfm_cbf_import(cbfm_mesh m, const int32_t* L_host, const void* CM_host,
                             const void* CJ_host, const double* sigma_host, void* stream,
                             cbfm_cbf* out);
@@ -265,6 +267,17 @@ void cbfm_cbf_free(cbfm_cbf c);
  *   Zr_dev  N_CBF x N_CBF double2, row-major, ldz >= N_CBF                 */
 cbfm_status cbfm_project(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, int32_t precision,
                          void* Zr_dev, int64_t ldz, void* stream);
+
+/* cbfm_project_ex: cbfm_project with an explicit scratch budget for the row
+ * panels (paper Sec. III-C, outer CBFM equation; the same Z_r).  Cells are
+ * grouped into panels of consecutive cells whose fill and projection
+ * scratch fits panel_bytes (a panel always holds at least one cell; on a
+ * mesh of translated cells, groups of cell offsets).  panel_bytes = 0 takes
+ * the default of cbfm_project: a quarter of the free device memory, at most
+ * 32 GiB.  npanels_host (or NULL) receives the number of panels used.     */
+cbfm_status cbfm_project_ex(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, int32_t precision,
+                            void* Zr_dev, int64_t ldz, int64_t panel_bytes, int32_t* npanels_host,
+                            void* stream);
 
 /* cbfm_project_batch: Z_r of `count` scatterers of any sizes and media at
  * once (as cbfm_project for each): the regular-pair fills of all of them run
@@ -303,7 +316,10 @@ cbfm_status cbfm_cmp_apply(cbfm_cbf c, int64_t nrhs, const void* y_dev, void* x_
  *              total bistatic sigma; NULL -> monostatic co-polarised sigma
  *              (direction -k, component along p), rcs_host nrhs
  *   use_cmp    1: right preconditioner (G^CBF)^{-1}; 0: none (y = j_CBF)
- * Synchronises the stream.  CBFM_E_NOCONV if some RHS did not reach tol.  */
+ * Synchronises the stream.  CBFM_E_NOCONV if, for some RHS, the relative
+ * residual of the preconditioned system recomputed in double at the end
+ * (relres_host) exceeds tol; every cycle starts from that true residual, so
+ * this happens only when max_iter is reached.                             */
 typedef struct {
   double tol;
   int32_t max_iter;   /* Arnoldi iterations over all cycles                */

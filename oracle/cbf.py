@@ -40,6 +40,23 @@ def rwg_gram(m: RWGMesh):
     return G
 
 
+def rwg_gram_sparse(m: RWGMesh):
+    """The RWG Gram of ``rwg_gram`` as a scipy CSR matrix (the same local
+    3 x 3 integrals summed over each triangle's RWGs; nonzero only between
+    RWGs that share a triangle), for meshes whose dense Gram is too large."""
+    import scipy.sparse
+    pts = qd.points(m.xyz)
+    s = m.tri_sign.astype(np.float64)
+    L = m.length[m.tri_edge]
+    coef = s * L / (2.0 * m.area[:, None])
+    f = coef[:, None, :, None] * (pts[:, :, None, :] - m.xyz[:, None, :, :])   # (nt,7,3,3)
+    nf = np.cross(m.normal[:, None, None, :], f)
+    loc = np.einsum("q,t,tqai,tqbi->tab", qd.WEIGHTS, m.area, nf, f)          # (nt,3,3)
+    ii = np.broadcast_to(m.tri_edge[:, :, None], loc.shape)
+    jj = np.broadcast_to(m.tri_edge[:, None, :], loc.shape)
+    return scipy.sparse.coo_matrix((loc.ravel(), (ii.ravel(), jj.ravel())), shape=(m.ne, m.ne)).tocsr()
+
+
 @dataclass
 class CBFSet:
     cells: list            # per cell: sorted edge ids
@@ -89,6 +106,28 @@ def build(m: RWGMesh, Kop, TE, TH, edge_block, gen, k0, eta0, delta_svd=1e-3):
         ix = np.nonzero(edge_block == c)[0]
         JM, JJ = primary_currents(m, Kop, TE, TH, ix, gen, k0, eta0, V)
         cm, cj, s, S = dual_cbfs(JM, JJ, G[np.ix_(ix, ix)], delta_svd)
+        cells.append(ix)
+        CM.append(cm)
+        CJ.append(cj)
+        sig.append(s)
+        sall.append(S)
+    return CBFSet(cells, CM, CJ, sig, sall)
+
+
+def dual_from_currents(m: RWGMesh, edge_block, currents, delta_svd, G=None):
+    """Dual CBFs of every cell from given current coefficient sets
+    ``currents`` = [(J^M_m, J^J_m), ...] (N_m x s each, cell by cell): the
+    same orthogonalisation as ``build`` (G'_m, SVD, truncation) applied to
+    currents that come from elsewhere (IPCBF solutions, or seeded test
+    inputs)."""
+    edge_block = np.asarray(edge_block)
+    if G is None:
+        G = rwg_gram_sparse(m)
+    cells, CM, CJ, sig, sall = [], [], [], [], []
+    for c, (JM, JJ) in enumerate(currents):
+        ix = np.nonzero(edge_block == c)[0]
+        Gm = G[np.ix_(ix, ix)] if isinstance(G, np.ndarray) else G[ix][:, ix].toarray()
+        cm, cj, s, S = dual_cbfs(JM, JJ, Gm, delta_svd)
         cells.append(ix)
         CM.append(cm)
         CJ.append(cj)

@@ -226,3 +226,48 @@ def fill_rows(m: RWGMesh, k, rows, chunk=4096):
                 # Y[i, q, ap, b] -> column tri_edge[q, b]
                 np.add.at(X[r], m.tri_edge.ravel(), Y[i, :, ap, :].ravel())
     return out
+
+
+def fill_block(m: RWGMesh, k, rows, cols, chunk=4096, near=None):
+    """Rows ``rows`` and columns ``cols`` (RWG ids) of K (=K1+K2), T1, T2,
+    each (len(rows), len(cols)), from the triangle pairs that carry them
+    only: every entry is the sum over the two triangles of the test RWG and
+    the two of the trial RWG of the pair blocks defined above (same far and
+    near rules), so a sub-block of a large mesh costs only its own pairs.
+    ``near``: the mesh's near-pair array if already at hand."""
+    rows, cols = np.asarray(rows), np.asarray(cols)
+    rt = np.unique(np.concatenate([m.tplus[rows], m.tminus[rows]]))
+    ct = np.unique(np.concatenate([m.tplus[cols], m.tminus[cols]]))
+    near_set = set(map(tuple, (near_pairs(m) if near is None else near).tolist()))
+    K = np.zeros((len(rt), len(ct), 3, 3), dtype=np.complex128)
+    T = np.zeros((2, len(rt), len(ct), 3, 3), dtype=np.complex128)
+    PP, QQ, II, JJ = [], [], [], []
+    for i, p in enumerate(rt.tolist()):
+        for j, q in enumerate(ct.tolist()):
+            if (p, q) in near_set:
+                Kc, Tc = near_local(m, k, p, q)
+                K[i, j] = Kc
+                T[:, i, j] = Tc
+            else:
+                PP.append(p)
+                QQ.append(q)
+                II.append(i)
+                JJ.append(j)
+    PP, QQ, II, JJ = map(np.asarray, (PP, QQ, II, JJ))
+    for s in range(0, len(PP), chunk):
+        Kc, Tc = regular_local(m, k, PP[s:s + chunk], QQ[s:s + chunk])
+        K[II[s:s + chunk], JJ[s:s + chunk]] = Kc
+        T[:, II[s:s + chunk], JJ[s:s + chunk]] = Tc
+    rpos = {int(t): i for i, t in enumerate(rt)}
+    cpos = {int(t): j for j, t in enumerate(ct)}
+    out = [np.zeros((len(rows), len(cols)), dtype=np.complex128) for _ in range(3)]
+    for r, e in enumerate(rows.tolist()):
+        for tp, ap in ((m.tplus[e], m.aplus[e]), (m.tminus[e], m.aminus[e])):
+            i = rpos[int(tp)]
+            for c, f in enumerate(cols.tolist()):
+                for tq, bq in ((m.tplus[f], m.aplus[f]), (m.tminus[f], m.aminus[f])):
+                    j = cpos[int(tq)]
+                    out[0][r, c] += K[i, j, ap, bq]
+                    out[1][r, c] += T[0, i, j, ap, bq]
+                    out[2][r, c] += T[1, i, j, ap, bq]
+    return out

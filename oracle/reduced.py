@@ -52,6 +52,41 @@ def gram_cbf(G, CJM, CMJ):
     return CJM.conj().T @ Gff @ CMJ
 
 
+def gram_b(G, cb: CBFSet):
+    """B = (C^M)^H G C^J (sum L x sum L) built cell pair by cell pair from a
+    dense or scipy-sparse RWG Gram G.  Since G is real antisymmetric,
+    G^CBF = blkdiag((C^J)^H G C^M, (C^M)^H G C^J) = blkdiag(-B^H, B)."""
+    Ls = cb.L
+    off = np.concatenate([[0], np.cumsum(Ls)])
+    B = np.zeros((off[-1], off[-1]), dtype=np.complex128)
+    for a, ia in enumerate(cb.cells):
+        Ga = G[ia] if isinstance(G, np.ndarray) else G[ia].toarray()
+        for b, ib in enumerate(cb.cells):
+            Gab = Ga[:, ib]
+            if np.any(Gab):
+                B[off[a]:off[a + 1], off[b]:off[b + 1]] = cb.CM[a].conj().T @ Gab @ cb.CJ[b]
+    return B
+
+
+def cmp_solve(B, y):
+    """x = (G^CBF)^{-1} y for G^CBF = blkdiag(-B^H, B), columns of y of
+    length 2 sum L (inner CBFM equation, solved exactly by LU)."""
+    NL = B.shape[0]
+    y = np.asarray(y)
+    x = np.empty_like(y, dtype=np.complex128)
+    x[:NL] = np.linalg.solve(-B.conj().T, y[:NL])
+    x[NL:] = np.linalg.solve(B, y[NL:])
+    return x
+
+
+def project_block(Kab, TEab, THab, CMa, CJa, CMb, CJb):
+    """Block (cell a rows, cell b columns) of Z_r = (C^JM)^H Z C^MJ from the
+    cell-pair blocks of K, TE, TH: the four quadrants
+    [[(C^J_a)^H K C^M_b, -(C^J_a)^H TE C^J_b], [(C^M_a)^H TH C^M_b, (C^M_a)^H K C^J_b]]."""
+    return np.block([[CJa.conj().T @ Kab @ CMb, -(CJa.conj().T @ TEab @ CJb)],
+                     [CMa.conj().T @ THab @ CMb, CMa.conj().T @ Kab @ CJb]])
+
+
 def gmres(matvec, b, tol=1e-12, restart=100, max_iter=1000):
     """Restarted GMRES(restart) for one right-hand side.  Returns
     (x, iterations, relative residual history)."""

@@ -90,6 +90,7 @@ def lib():
         "cbfm_cbf_export": (_I32, [_P, _P, _P]),
         "cbfm_cbf_free": (None, [_P]),
         "cbfm_project": (_I32, [_P, C.POINTER(Medium), _P, _I32, _P, _I64, _P]),
+        "cbfm_project_ex": (_I32, [_P, C.POINTER(Medium), _P, _I32, _P, _I64, _I64, C.POINTER(_I32), _P]),
         "cbfm_cmp_apply": (_I32, [_P, _I64, _P, _P, _P]),
         "cbfm_solve": (_I32, [_P, C.POINTER(Medium), _P, _P, _I64, _P, _I64, C.POINTER(SolverParams), _P,
                               _P, _P, _P, _I64, _P, _P]),
@@ -310,13 +311,20 @@ def cbf_import(mesh: Mesh, CM_cells, CJ_cells, sigma_cells, stream=None) -> CBF:
     return CBF(h, mesh)
 
 
-def project(mesh: Mesh, medium: Medium, cbf: CBF, out, precision=FP64, ldz=None, stream=None):
+def project(mesh: Mesh, medium: Medium, cbf: CBF, out, precision=FP64, ldz=None, stream=None, panel_bytes=None):
+    """cbfm_project into ``out`` (n x ldz complex128); with ``panel_bytes``
+    cbfm_project_ex with that panel budget, returning the panel count."""
     import torch
     n = cbf.n_cbf
     ldz = n if ldz is None else ldz
     p = _dev(out, torch.complex128, n * ldz, "Zr")
-    _check(lib().cbfm_project(mesh.handle, C.byref(medium), cbf.handle, precision, p, ldz, _stream(stream)))
-    return out
+    if panel_bytes is None:
+        _check(lib().cbfm_project(mesh.handle, C.byref(medium), cbf.handle, precision, p, ldz, _stream(stream)))
+        return out
+    npan = _I32()
+    _check(lib().cbfm_project_ex(mesh.handle, C.byref(medium), cbf.handle, precision, p, ldz, int(panel_bytes),
+                                 C.byref(npan), _stream(stream)))
+    return npan.value
 
 
 def project_batch(items, precision=FP64, stream=None):

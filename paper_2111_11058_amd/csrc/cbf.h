@@ -50,7 +50,8 @@ void cmp_apply_dev(cbfm_cbf_s* c, int64_t nrhs, double2* x, hipStream_t s);
 // B^{-1} (NL x NL, row-major), formed on first use
 const double2* cmp_inverse(cbfm_cbf_s* c, hipStream_t s);
 // Z_r of cbfm_project with an explicit scratch budget for the row panels
-void project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int precision, double2* Zr, int64_t ldz,
-                 hipStream_t s, size_t budget);
+// (returns the number of row panels)
+int project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int precision, double2* Zr, int64_t ldz,
+                hipStream_t s, size_t budget);
 
 }  // namespace cbfm

@@ -985,6 +985,18 @@ cbfm_status cbfm_cbf_import(cbfm_mesh m, const int32_t* L, const void* CM, const
       CBFM_HIP(hipMemcpy(c->CM.p, CM, bytes, hipMemcpyHostToDevice));
       CBFM_HIP(hipMemcpy(c->CJ.p, CJ, bytes, hipMemcpyHostToDevice));
       (void)stream;
+      // on a mesh of translated copies of cell 0, CBFs equal to cell 0's in
+      // every cell are shared (the projection then goes by cell offsets)
+      if (m->translated) {
+        const int nb = h.nblocks;
+        const size_t blk = (size_t)(c->coff[1] - c->coff[0]) * sizeof(double2);
+        bool same = true;
+        for (int b = 1; b < nb && same; ++b)
+          same = c->L[b] == c->L[0] &&
+                 std::memcmp((const char*)CM + c->coff[b] * sizeof(double2), CM, blk) == 0 &&
+                 std::memcmp((const char*)CJ + c->coff[b] * sizeof(double2), CJ, blk) == 0;
+        c->shared = same;
+      }
     } catch (...) {
       delete c;
       throw;

@@ -88,6 +88,9 @@ constexpr size_t kBigScratch = (size_t)256 << 20;
 void* scratch_alloc(size_t bytes, hipStream_t s);
 void scratch_release(void* p, size_t bytes, hipStream_t s);
 size_t scratch_cached_bytes();  // bytes held by the cache on the current device
+// Before destroying stream s: synchronise it, then call this, so that the
+// cache drops every reference to s and to the events recorded on it.
+void scratch_forget_stream(hipStream_t s);
 // Marks s as a library side stream: a cached block it released and still
 // uses is not waited for by another stream while a new block can be had.
 void scratch_side_stream(hipStream_t s);

@@ -103,8 +103,8 @@ static void launch_panel_gemms(int precision, std::vector<GemmDesc>& d1, std::ve
   }
 }
 
-void project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int precision, double2* Zr, int64_t ldz,
-                 hipStream_t s, size_t budget) {
+int project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int precision, double2* Zr, int64_t ldz,
+                hipStream_t s, size_t budget) {
   const MeshHost& h = m->h;
   const int nb = h.nblocks;
   const int64_t ne = h.ne, nt = h.nt, NL = c->NL;
@@ -196,6 +196,7 @@ void project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int preci
     launch_panel_gemms(precision, d1, d2, x1, x2, s);
     CBFM_HIP(hipStreamSynchronize(s));  // host index staging of this panel
   }
+  return (int)panels.size();
 }
 
 // Copy the reduced block of each offset to every cell pair with that
@@ -220,8 +221,8 @@ __global__ void scatter_offsets_kernel(const double2* __restrict__ Zd, const int
 // (regular pairs in one persistent launch, near pairs batched, assembly)
 // and projected once, for a representative pair, and copied to the pairs
 // that share it.  Offsets are grouped while their scratch fits the budget.
-static void project_translated(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, double2* Zr, int64_t ldz,
-                               hipStream_t s, size_t budget) {
+static int project_translated(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, double2* Zr, int64_t ldz,
+                              hipStream_t s, size_t budget) {
   const MeshHost& h = m->h;
   const int nb = h.nblocks;
   const int64_t N0 = h.cell_off[1] - h.cell_off[0], L = c->L[0], NL = c->NL;
@@ -292,7 +293,8 @@ static void project_translated(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s
   const size_t loc = (size_t)27 * nt0 * nt0, zb = (size_t)3 * N0 * N0, wb = (size_t)4 * N0 * L;
   const size_t per = (loc + zb + wb) * sizeof(double2);
   const int G = (int)std::max<size_t>(1, std::min<size_t>((size_t)K, budget / per));
-  for (int k0 = 0; k0 < K; k0 += G) {
+  int groups = 0;
+  for (int k0 = 0; k0 < K; k0 += G, ++groups) {
     const int k1 = std::min(K, k0 + G), ng = k1 - k0;
     Scratch local((size_t)ng * loc * sizeof(double2), s), Zb((size_t)ng * zb * sizeof(double2), s),
         W((size_t)ng * wb * sizeof(double2), s), outs((size_t)ng * sizeof(NearOut), s);
@@ -334,6 +336,7 @@ static void project_translated(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s
   hipLaunchKernelGGL(scatter_offsets_kernel, dim3((unsigned)((int64_t)nb * nb), 4), dim3(256), 0, s, Zd.as<double2>(),
                      dpk.as<int32_t>(), nb, L, NL, Zr, ldz);
   CBFM_HIP(hipGetLastError());
+  return groups;
 }
 
 // Z_r of several scatterers, each taken as one panel of all its cells: the
@@ -442,8 +445,8 @@ extern "C" cbfm_status cbfm_project_batch(int32_t count, const cbfm_mesh* meshes
   });
 }
 
-extern "C" cbfm_status cbfm_project(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, int32_t precision, void* Zr,
-                                    int64_t ldz, void* stream) {
+extern "C" cbfm_status cbfm_project_ex(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, int32_t precision, void* Zr,
+                                       int64_t ldz, int64_t panel_bytes, int32_t* npanels, void* stream) {
   return guarded([&] {
     CBFM_REQUIRE(m && c && Zr, CBFM_E_ARG, "null argument");
     CBFM_REQUIRE(c->mesh == m, CBFM_E_STATE, "CBF set belongs to another mesh");
@@ -451,15 +454,26 @@ extern "C" cbfm_status cbfm_project(cbfm_mesh m, const cbfm_medium* med, cbfm_cb
                      precision == CBFM_MIXED_BF16 || precision == CBFM_MIXED_BF16X3,
                  CBFM_E_ARG, "unknown precision");
     CBFM_REQUIRE(ldz >= 2 * c->NL, CBFM_E_ARG, "ldz < N_CBF");
+    CBFM_REQUIRE(panel_bytes >= 0, CBFM_E_ARG, "negative panel budget");
     const Media md = make_media(med);
-    // scratch budget per panel: a quarter of the free device memory, at most 32 GiB
-    size_t fr = 0, tot = 0;
-    CBFM_HIP(hipMemGetInfo(&fr, &tot));
-    fr += scratch_cached_bytes();  // cached scratch is free for this call's panels
-    const size_t budget = std::min<size_t>(fr / 4, (size_t)32 << 30);
+    size_t budget = (size_t)panel_bytes;
+    if (budget == 0) {
+      // scratch budget per panel: a quarter of the free device memory, at most 32 GiB
+      size_t fr = 0, tot = 0;
+      CBFM_HIP(hipMemGetInfo(&fr, &tot));
+      fr += scratch_cached_bytes();  // cached scratch is free for this call's panels
+      budget = std::min<size_t>(fr / 4, (size_t)32 << 30);
+    }
+    int np = 0;
     if (m->translated && c->shared && precision == CBFM_FP64)
-      project_translated(m, md, c, static_cast<double2*>(Zr), ldz, static_cast<hipStream_t>(stream), budget);
+      np = project_translated(m, md, c, static_cast<double2*>(Zr), ldz, static_cast<hipStream_t>(stream), budget);
     else
-      project_dev(m, md, c, precision, static_cast<double2*>(Zr), ldz, static_cast<hipStream_t>(stream), budget);
+      np = project_dev(m, md, c, precision, static_cast<double2*>(Zr), ldz, static_cast<hipStream_t>(stream), budget);
+    if (npanels) *npanels = np;
   });
+}
+
+extern "C" cbfm_status cbfm_project(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, int32_t precision, void* Zr,
+                                    int64_t ldz, void* stream) {
+  return cbfm_project_ex(m, med, c, precision, Zr, ldz, 0, nullptr, stream);
 }

@@ -14,14 +14,19 @@
 //  * a released block carries an event recorded on the releasing stream, and
 //    the next user's stream waits on it, so reuse is ordered after every
 //    operation queued before the release, on any stream;
+//  * before a stream is destroyed, its owner synchronises it and calls
+//    scratch_forget_stream: the blocks it released are then complete, their
+//    events are destroyed and they are tagged with no stream, so the cache
+//    never waits on, synchronises or compares the handle or an event of a
+//    destroyed stream (a new stream may reuse the handle value);
 //  * among the cached blocks that fit, one released on the requesting stream
 //    is taken first (stream order already puts it after its last use), then
 //    one released on another stream.  A block released on a library side
 //    stream is taken by another stream only if a new allocation fails, so
 //    that the CMP inverse formed there does not hold back the caller's
 //    projection through the cache.  (Choices go by the releasing stream
-//    alone: the cache queries no event, since an event recorded on a stream
-//    that has since been destroyed is only ever waited on);
+//    alone; the cache queries no event.)  A block whose stream was
+//    forgotten counts as released on the requesting stream;
 //  * the bytes cached per device are capped at kCacheCap (the oldest blocks
 //    are freed first), and if an allocation fails, the device's cached blocks
 //    are freed (after their events complete) and the allocation is retried.
@@ -51,8 +56,9 @@ struct Block {
   void* p;
   size_t bytes;
   int dev;
-  hipEvent_t ready;
-  hipStream_t stream;  // the releasing stream
+  hipEvent_t ready;    // recorded at the release; nullptr: known complete
+  hipStream_t stream;  // the releasing stream; nullptr once forgotten
+  bool forgotten;      // the releasing stream was destroyed (see scratch_forget_stream)
 };
 
 struct Cache {
@@ -93,10 +99,12 @@ void spare_event(int dev, hipEvent_t e) { cache().events.push_back({dev, e}); }
 
 void free_blocks(std::vector<Block>& drop) {
   for (Block& b : drop) {
-    (void)hipEventSynchronize(b.ready);
+    if (b.ready) (void)hipEventSynchronize(b.ready);
     (void)hipFree(b.p);
-    std::lock_guard<std::mutex> lk(cache().mu);
-    spare_event(b.dev, b.ready);
+    if (b.ready) {
+      std::lock_guard<std::mutex> lk(cache().mu);
+      spare_event(b.dev, b.ready);
+    }
   }
   drop.clear();
 }
@@ -133,14 +141,14 @@ void* scratch_alloc(size_t bytes, hipStream_t s) {
     const Block b = cache().free[i];
     cache().free.erase(cache().free.begin() + (ptrdiff_t)i);  // (keeps the release order)
     lk.unlock();
-    // (also on the releasing stream: a stream handle may name a new stream
-    // once the old one is destroyed)
-    if (hipStreamWaitEvent(s, b.ready, 0) != hipSuccess) {
-      (void)hipGetLastError();
-      (void)hipEventSynchronize(b.ready);  // keep the ordering before handing the block out
+    if (b.ready) {
+      if (hipStreamWaitEvent(s, b.ready, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipEventSynchronize(b.ready);  // keep the ordering before handing the block out
+      }
     }
     lk.lock();
-    spare_event(dev, b.ready);  // re-recording later leaves a queued wait as it was
+    if (b.ready) spare_event(dev, b.ready);  // re-recording later leaves a queued wait as it was
     return b.p;
   };
   size_t busy = SIZE_MAX;  // a fitting block released on a side stream
@@ -151,7 +159,7 @@ void* scratch_alloc(size_t bytes, hipStream_t s) {
     size_t same = SIZE_MAX, other = SIZE_MAX;
     for (size_t i = 0; i < f.size(); ++i) {
       if (!fits(f[i])) continue;
-      size_t& slot = f[i].stream == s ? same
+      size_t& slot = f[i].forgotten || f[i].stream == s ? same
                      : std::find(side.begin(), side.end(), f[i].stream) != side.end() ? busy
                                                                                          : other;
       if (slot == SIZE_MAX || f[i].bytes < f[slot].bytes) slot = i;
@@ -191,7 +199,7 @@ void scratch_release(void* p, size_t bytes, hipStream_t s) {
   {
     std::lock_guard<std::mutex> lk(cache().mu);
     auto& f = cache().free;
-    f.push_back({p, block_size(bytes), dev, ev, s});
+    f.push_back({p, block_size(bytes), dev, ev, s, false});
     size_t held = 0;
     for (const Block& b : f)
       if (b.dev == dev) held += b.bytes;
@@ -207,6 +215,22 @@ void scratch_release(void* p, size_t bytes, hipStream_t s) {
     }
   }
   free_blocks(drop);
+}
+
+void scratch_forget_stream(hipStream_t s) {
+  std::vector<hipEvent_t> done;
+  {
+    std::lock_guard<std::mutex> lk(cache().mu);
+    for (Block& b : cache().free)
+      if (!b.forgotten && b.stream == s) {
+        if (b.ready) done.push_back(b.ready);
+        b.ready = nullptr;
+        b.stream = nullptr;
+        b.forgotten = true;
+      }
+  }
+  // the caller synchronised s: these events are complete and never used again
+  for (hipEvent_t e : done) (void)hipEventDestroy(e);
 }
 
 void scratch_side_stream(hipStream_t s) {

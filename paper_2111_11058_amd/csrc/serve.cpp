@@ -140,7 +140,9 @@ struct cbfm_server_s {
     for (auto it = queue.begin(); it != queue.end(); ++it) {
       Job* j = *it;
       const bool shared = j->key != 0 && residents.count(j->key);
-      const size_t need = j->transient + (j->key != 0 && !shared ? j->resident : 0);
+      // a keyless request holds its own mesh, CBFs and Z_r while it runs; a
+      // keyed one adds them unless its key is already resident
+      const size_t need = j->transient + (j->key == 0 || !shared ? j->resident : 0);
       if (!make_room(need) && running > 0) continue;
       queue.erase(it);
       in_use += j->transient;
@@ -276,7 +278,12 @@ void cbfm_server_s::worker() {
     cv_done.notify_all();
     cv_work.notify_all();
   }
-  if (s) (void)hipStreamDestroy(s);
+  if (s) {
+    // the scratch cache must not keep this stream's handle or events
+    (void)hipStreamSynchronize(s);
+    scratch_forget_stream(s);
+    (void)hipStreamDestroy(s);
+  }
 }
 
 extern "C" {

@@ -1056,6 +1056,8 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
       } catch (...) {
         (void)hipStreamEndCapture(cs, &graph);
         if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamSynchronize(cs);
+        scratch_forget_stream(cs);
         (void)hipStreamDestroy(cs);
         throw;
       }
@@ -1063,6 +1065,8 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamSynchronize(cs);
+    scratch_forget_stream(cs);
     (void)hipStreamDestroy(cs);
     CBFM_HIP(e);
     hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, s, jdev, (int64_t)0, 0);
@@ -1293,7 +1297,7 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
       CBFM_HIP(hipStreamSynchronize(s));
       for (int64_t q = 0; q < nrhs; ++q) {
         res[q] = bn[q] > 0 ? rn[q] / bn[q] : 0.0;
-        if (res[q] > tol * 10.0) noconv = CBFM_E_NOCONV;
+        if (res[q] > tol) noconv = CBFM_E_NOCONV;
       }
     }
     // j_CBF = G^{-1} x ; j = C^MJ j_CBF

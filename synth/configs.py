@@ -60,6 +60,26 @@ def random_incidences(n: int, seed: int) -> np.ndarray:
     return np.concatenate([-d, th], axis=1)
 
 
+def random_complex(shape, seed: int) -> np.ndarray:
+    """Seeded complex normal entries (real and imaginary parts N(0, 1/2)):
+    stand-in coefficient sets for tests that need matrices of a given shape
+    and no particular physics (imported CBFs, current sets, perturbations)."""
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2.0)
+
+
+def random_cell_sets(sizes, cols: int, seed: int):
+    """One (N_m x cols) pair of seeded complex normal matrices per cell size
+    N_m in ``sizes`` (cell after cell, one seed for all)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in sizes:
+        a = (rng.standard_normal((n, cols)) + 1j * rng.standard_normal((n, cols))) / np.sqrt(2.0)
+        b = (rng.standard_normal((n, cols)) + 1j * rng.standard_normal((n, cols))) / np.sqrt(2.0)
+        out.append((a, b))
+    return out
+
+
 @dataclass
 class Workload:
     name: str

@@ -32,6 +32,8 @@ def oracle_problem(name):
         w = configs.sphere_c1()
     elif name == "cyl_small":
         w = configs.small_cylinder()
+    elif name == "cyl_lossy":
+        w = configs.small_cylinder(eps_r=4.0 - 0.1j)
     elif name == "array2":
         w = configs.sphere_array(2, 1, 1, level=1)
     else:

@@ -103,3 +103,26 @@ def test_served_rcs_matches_oracle(torch_cuda):
     err = np.max(np.abs(out["rcs"] - ref) / ref)
     print("served vs oracle RCS", err)
     assert out["status"] == "OK" and err < 1e-8
+
+
+def test_admission_keeps_within_budget(torch_cuda):
+    """A budget for about two requests at a time: keyless requests hold their
+    own mesh, CBFs and Z_r while they run, so admission counts them, and the
+    admitted peak never exceeds the budget while several requests run."""
+    from paper_2111_11058_amd import cbfm
+    from synth import configs
+    stream = configs.serving_stream(8, seed=9, max_unknowns=2200)
+    built = [_req(cbfm, r.work) for r in stream]
+    fps = [cbfm.request_footprint(req) for req, _ in built]
+    budget = int(2.2 * max(fps))
+    srv = cbfm.Server(slots=4, budget_bytes=budget)
+    try:
+        print(f"admission: 8 requests, budget {budget / 2**30:.2f} GiB", flush=True)
+        tickets = [srv.submit(req) for req, _ in built]
+        outs = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    finally:
+        srv.close()
+    print(st)
+    assert all(o["status"] == "OK" for o in outs)
+    assert st["peak_bytes"] <= budget

@@ -350,3 +350,50 @@ def test_gmres_equals_lu_and_cbf_invariance():
     # same span: projector onto span(CM1) reproduces CM2
     Qm, _ = np.linalg.qr(CM1)
     assert np.linalg.norm(CM2 - Qm @ (Qm.conj().T @ CM2)) < 1e-8 * np.linalg.norm(CM2)
+
+
+# ------------------------------------------------------- block forms of the oracle
+def test_block_forms_equal_the_dense_definitions():
+    """The block routines that let large meshes be sampled cheaply agree with
+    the dense definitions on the c1 sphere: fill_block with the sub-block of
+    fill_ops (ragged row and column sets, near and far pairs), the sparse
+    RWG Gram with the dense one, G^CBF = blkdiag(-B^H, B) from the cell-pair
+    form of B (G real antisymmetric), cmp_solve with a dense solve of G^CBF,
+    and project_block with the blocks of the dense projection."""
+    P = oracle_problem("c1")
+    m, w = P["m"], P["w"]
+    rows = np.array([0, 5, 77, 200, 479])
+    cols = np.array([3, 4, 150, 151, 300, 478])
+    got = fill.fill_block(m, P["k"], rows, cols)
+    for X, R_ in zip(got, (P["Kop"], P["T1"], P["T2"])):
+        ref = R_[np.ix_(rows, cols)]
+        assert np.abs(X - ref).max() <= 1e-13 * np.abs(ref).max()
+    G = cbf.rwg_gram(m)
+    Gs = cbf.rwg_gram_sparse(m)
+    assert np.abs(Gs.toarray() - G).max() <= 1e-15 * np.abs(G).max()
+    cb = cbf.build(m, P["Kc"], P["TE"], P["TH"], w.edge_block, w.gen, w.k0, w.eta0, 1e-3)
+    CJM, CMJ = reduced.cbf_matrices(cb, m.ne)
+    Gc = reduced.gram_cbf(G, CJM, CMJ)
+    B = reduced.gram_b(Gs, cb)
+    NL = B.shape[0]
+    assert np.abs(Gc[NL:, NL:] - B).max() <= 1e-13 * np.abs(B).max()
+    assert np.abs(Gc[:NL, :NL] + B.conj().T).max() <= 1e-13 * np.abs(B).max()
+    assert np.abs(Gc[:NL, NL:]).max() == 0 and np.abs(Gc[NL:, :NL]).max() == 0
+    y = configs.random_complex((2 * NL, 2), 3)
+    assert np.linalg.norm(reduced.cmp_solve(B, y) - np.linalg.solve(Gc, y)) <= 1e-12 * np.linalg.norm(
+        np.linalg.solve(Gc, y))
+    Zr = reduced.project(P["Z"], CJM, CMJ)
+    off = np.concatenate([[0], np.cumsum(cb.L)])
+    for a, b in ((0, 0), (2, 5)):
+        ia, ib = cb.cells[a], cb.cells[b]
+        blk = reduced.project_block(P["Kc"][np.ix_(ia, ib)], P["TE"][np.ix_(ia, ib)], P["TH"][np.ix_(ia, ib)],
+                                    cb.CM[a], cb.CJ[a], cb.CM[b], cb.CJ[b])
+        ra = np.r_[off[a]:off[a + 1], NL + off[a]:NL + off[a + 1]]
+        cbix = np.r_[off[b]:off[b + 1], NL + off[b]:NL + off[b + 1]]
+        ref = Zr[np.ix_(ra, cbix)]
+        assert np.abs(blk - ref).max() <= 1e-12 * np.abs(ref).max()
+    # dual CBFs from given currents: the primary currents reproduce build()
+    cur = [cbf.primary_currents(m, P["Kc"], P["TE"], P["TH"], ix, w.gen, w.k0, w.eta0) for ix in cb.cells]
+    cb2 = cbf.dual_from_currents(m, w.edge_block, cur, 1e-3)
+    for s1, s2 in zip(cb.sigma, cb2.sigma):
+        assert len(s1) == len(s2) and np.abs(s1 - s2).max() <= 1e-12 * s1[0]
