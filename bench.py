@@ -9,17 +9,20 @@ right-preconditioned GMRES solve of every incidence to its monostatic RCS
 (cbfm_solve).  The mesh is loaded and resident on the device before the
 timed region.
 
-Workload (default): dielectric cube, edge 1 wavelength, eps_r 2.5, 12 x 12
-squares per face (1,728 triangles, 2,592 RWGs, 5,184 unknowns), 27 cells,
-64 seeded incidences, CBFs from the 144 Table-I plane waves, delta_SVD 1e-3.
+Workload (default): dielectric cylinder r 1, h 6 wavelengths, eps_r 3,
+19,968 triangles (29,952 RWGs, 59,904 unknowns), 96 cells, 32 monostatic
+incidences, CBFs from the 144 Table-I plane waves, delta_SVD 1e-3, regular
+pairs filled in FP32 (near pairs, CBF build, projection and solve in FP64).
+The FP64 form of the same step runs beside it.
 
 value = logical triangle pair-evaluations (N_tri^2 per step) per second of
 the whole step.  After the timed steps one more step runs with the library's
-event timers on; the roofline entry is for the kernel family with the most
-GPU time in it (algorithmic work per launch over the average launch
-duration), and roofline_kernels lists every timed family.  HBM traffic per
-launch comes from the committed counter summary when the kernel's source is
-unchanged since it was measured, else it is null.
+event timers on, the projection and the solve timed separately; the roofline
+entry is for the kernel family with the most GPU time in that step
+(algorithmic work per launch over the average launch duration) and
+roofline_kernels lists every timed family.  HBM traffic per launch comes
+from the committed counter summary when the kernel's source is unchanged
+since it was measured, else it is null.
 """
 from __future__ import annotations
 
@@ -27,6 +30,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -37,24 +41,46 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PMCHWT fill+projection pair-evals/s; solves/s with p50/p99 latency"
 
-# Algorithmic FP64 flops of one regular triangle pair in the fill kernel
-# (FMA = 2 flops; square roots, reciprocals, sines/cosines not counted):
+# Algorithmic flops of one regular triangle pair in the fill kernel, the
+# same count in FP64 and FP32 (FMA = 2 flops; square roots, reciprocals,
+# sines/cosines and exponentials not counted):
 #   49 point pairs x 73 (distance 12, Green's functions of both media 24,
 #   inner accumulations 40 -- less 3 for the folded weight products)
 #   + 7 outer points x 190 (T moments 84, K moments 106)
 #   + 9 local pairs x 110 (K 38, two media X_i 36, two output operators 36)
 FLOP_PER_PAIR = 49 * 73 + 7 * 190 + 9 * 110
 PEAK_FP64_VALU = 78.6e12
+PEAK_FP32_VALU = 157.3e12       # published vector FP32 (packed FP32 issue)
+PEAK_FP32_VALU_UNPACKED = 78.6e12  # one FP32 FMA per lane per clock (packed forms not used here)
 PEAK_FP64_MFMA = 78.6e12
+PEAK_FP32_MFMA = 157.3e12
 PEAK_HBM = 8.0e12
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cube1728.txt")
+
+WORKLOADS = ["cylinder19968", "cube1728", "sphere320", "sphere5120", "sphere_array4x4x2", "sphere_array8x16x2",
+             "cube_array8x2x2"]
+
+
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
+
 
 # timer family -> (kernel, bound, peak, unit, scale of the timer's work unit)
 FAMILIES = {
     "fill_regular": ("fill_regular_kernel<double>", "alu", PEAK_FP64_VALU, "TFLOP/s", FLOP_PER_PAIR),
+    "fill_regular_f32": ("fill_regular_kernel<float>", "alu", PEAK_FP32_VALU, "TFLOP/s", FLOP_PER_PAIR),
     "gemm": ("zgemm_batched_kernel", "mfma", PEAK_FP64_MFMA, "TFLOP/s", 1.0),
+    "xgemm": ("xgemm_batched_kernel", "mfma", PEAK_FP32_MFMA, "TFLOP/s", 1.0),
     "gmres_dots": ("dots2_kernel", "hbm", PEAK_HBM, "GB/s", 1.0),
     "gmres_update": ("dcgs_update_kernel", "hbm", PEAK_HBM, "GB/s", 1.0),
+}
+# timer family -> (substring of the kernel symbol, source file), for the
+# counter summaries
+FAMILY_SOURCES = {
+    "fill_regular": ("fill_regular_kernel<double", "paper_2111_11058_amd/csrc/fill.hip"),
+    "fill_regular_f32": ("fill_regular_kernel<float", "paper_2111_11058_amd/csrc/fill.hip"),
+    "gemm": ("zgemm_batched_kernel", "paper_2111_11058_amd/csrc/gemm.hip"),
+    "gmres_dots": ("dots2_kernel", "paper_2111_11058_amd/csrc/solve.hip"),
+    "gmres_update": ("dcgs_update_kernel", "paper_2111_11058_amd/csrc/solve.hip"),
 }
 
 
@@ -81,14 +107,15 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def measured_traffic():
+def measured_traffic(workload_name):
     """Per-kernel HBM bytes per launch from the committed counter summary,
     kept only where the kernel's source file still has the hash recorded
     with the measurement."""
     out = {}
-    if not os.path.exists(TRAFFIC_FILE):
+    path = traffic_file(workload_name)
+    if not os.path.exists(path):
         return out
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if not line.startswith("kernel="):
             continue
         f = dict(kv.split("=", 1) for kv in line.split())
@@ -98,16 +125,7 @@ def measured_traffic():
     return out
 
 
-# timer family -> (substring of the kernel symbol, source file)
-FAMILY_SOURCES = {
-    "fill_regular": ("fill_regular_kernel<double", "paper_2111_11058_amd/csrc/fill.hip"),
-    "gemm": ("zgemm_batched_kernel", "paper_2111_11058_amd/csrc/gemm.hip"),
-    "gmres_dots": ("dots2_kernel", "paper_2111_11058_amd/csrc/solve.hip"),
-    "gmres_update": ("dcgs_update_kernel", "paper_2111_11058_amd/csrc/solve.hip"),
-}
-
-
-def write_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, cmd):
+def write_traffic(workload_name, fetch_dir, write_dir, cfetch_dir, cwrite_dir, cmd):
     """Turn four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE of this
     benchmark, then of the 1 GiB copy) into the traffic summary: per kernel
     family the mean KiB per dispatch, scaled so that the copy reads and
@@ -125,7 +143,7 @@ def write_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, cmd):
     gib_kib = float(1 << 20)
     fs = gib_kib / np.mean(per_dispatch(cfetch_dir, "__amd_rocclr_copyBuffer"))
     ws = gib_kib / np.mean(per_dispatch(cwrite_dir, "__amd_rocclr_copyBuffer"))
-    lines = ["# HBM traffic per dispatch, cube1728 bench step (FP64), from rocprofv3 --pmc",
+    lines = [f"# HBM traffic per dispatch, {workload_name} bench step, from rocprofv3 --pmc",
              f"# command: {cmd}",
              f"# calibration: a 1 GiB device copy reads {1 / fs:.4f} GiB by FETCH_SIZE and writes "
              f"{1 / ws:.4f} GiB by WRITE_SIZE; scales fetch x{fs:.4f}, write x{ws:.4f}"]
@@ -138,17 +156,13 @@ def write_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, cmd):
         b = (fk * fs + wk * ws) * 1024.0
         lines.append(f"kernel={fam} symbol={sub.split('<')[0]} source={src} sha256={sha} dispatches={len(f)} "
                      f"fetch_kib={fk:.1f} write_kib={wk:.1f} bytes_per_dispatch={b:.0f}")
-    with open(TRAFFIC_FILE, "w") as fh:
+    with open(traffic_file(workload_name), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 
-def rooflines(cbfm, step):
-    """One step with every timer family on: achieved rate of each family
-    against its peak; the dominant family is the one with the most time."""
-    cbfm.timer_enable(list(FAMILIES))
-    step()
-    traffic = measured_traffic()
+def read_families(cbfm, traffic, phase):
+    """Achieved rate of every timed family since the last timer_enable."""
     rows = {}
     for fam, (kernel, bound, peak, unit, scale) in FAMILIES.items():
         n, ms, work = cbfm.timer_read(fam, with_work=True)
@@ -158,12 +172,38 @@ def rooflines(cbfm, step):
         avg_s = ms * 1e-3 / n
         ach = per_launch / avg_s
         div = 1e12 if unit == "TFLOP/s" else 1e9
-        rows[fam] = {"bound": bound, "achieved": ach / div, "peak": peak / div, "unit": unit, "frac": ach / peak,
-                     "traffic": traffic.get(fam), "kernel": kernel, "launches": n, "avg_launch_ms": ms / n,
-                     "total_ms": ms, "work_per_launch": per_launch}
-    cbfm.timer_enable(None)
+        row = {"bound": bound, "achieved": ach / div, "peak": peak / div, "unit": unit, "frac": ach / peak,
+               "traffic": traffic.get(fam), "kernel": kernel, "phase": phase, "launches": n,
+               "avg_launch_ms": ms / n, "total_ms": ms, "work_per_launch": per_launch}
+        if fam == "fill_regular_f32":
+            row["frac_of_unpacked_fp32"] = ach / PEAK_FP32_VALU_UNPACKED
+        rows[fam] = row
+    return rows
+
+
+def rooflines(cbfm, run_phases, traffic, prefix=""):
+    """One step with the timers on, the projection and the solve timed
+    apart (run_phases calls project() and solve() in turn, each given a
+    callback that switches the timers on for that phase)."""
+    rows = {}
+    names = {"project": {"fill_regular": "fill_regular_fp64", "fill_regular_f32": "fill_regular_f32",
+                         "gemm": "projection_gemm_fp64", "xgemm": "projection_gemm_xf32"},
+             "solve": {"gemm": "gmres_matvec_gemm", "xgemm": "gmres_matvec_xgemm", "gmres_dots": "gmres_dots",
+                       "gmres_update": "gmres_update"}}
+
+    def timed(phase):
+        cbfm.timer_enable(list(cbfm.TIMERS))
+
+        def done():
+            for fam, row in read_families(cbfm, traffic, phase).items():
+                if fam in names[phase]:
+                    rows[prefix + names[phase][fam]] = row
+            cbfm.timer_enable(None)
+        return done
+
+    run_phases(timed)
     dom = max(rows, key=lambda k: rows[k]["total_ms"])
-    return rows[dom], rows
+    return dict(rows[dom], family=dom), rows
 
 
 def serve(cbfm, n_requests, slots, budget, seed=2113, rate=200.0, tol=1e-6):
@@ -206,6 +246,7 @@ def serve(cbfm, n_requests, slots, budget, seed=2113, rate=200.0, tol=1e-6):
             "queue_wait_ms": {"p50": float(np.percentile(queue, 50) * 1e3), "p99": float(np.percentile(queue, 99) * 1e3)},
             "status_ok": int(ok), "status": status, "gmres_iterations": {"mean": float(its.mean()), "max": int(its.max())},
             "max_running": st["max_running"], "peak_admitted_bytes": st["peak_bytes"],
+            "peak_within_budget": bool(st["peak_bytes"] <= budget),
             "unknowns": {"min": int(min(r.unknowns for r in stream)), "max": int(max(r.unknowns for r in stream))}}
 
 
@@ -228,33 +269,85 @@ def serving_legs(cbfm, torch, n, slots):
     return legs
 
 
-def cpu_baseline(w, sample, seed=5):
-    """The oracle's fill timed on a bounded, seeded sample of the workload's
-    triangle pairs (regular and near pairs in the workload's proportion)."""
+# ----------------------------------------------------------------- CPU oracle
+def _oracle_fill_chunk(args):
+    """Oracle FP64 fill of a list of (P, Q) pairs (worker of the pool)."""
+    name, P, Q, near = args
     from oracle import fill, mesh as om
+    w = workload(name)
     m = om.build(w.V, w.T)
     k, _ = fill.media(w.k0, w.eta0, w.eps_r, w.mu_r)
-    near = om.near_pairs(m)
-    frac = len(near) / m.nt ** 2
-    rng = np.random.default_rng(seed)
-    n_near = max(1, int(round(sample * frac)))
-    n_reg = sample - n_near
-    isn = set(map(tuple, near.tolist()))
-    P = rng.integers(0, m.nt, n_reg * 2)
-    Q = rng.integers(0, m.nt, n_reg * 2)
-    keep = np.array([(p, q) not in isn for p, q in zip(P.tolist(), Q.tolist())])
-    P, Q = P[keep][:n_reg], Q[keep][:n_reg]
-    pick = near[rng.choice(len(near), n_near, replace=False)]
     t0 = time.perf_counter()
     for s in range(0, len(P), 4096):
         fill.regular_local(m, k, P[s:s + 4096], Q[s:s + 4096])
-    for p, q in pick:
+    for p, q in near:
         fill.near_local(m, k, int(p), int(q))
-    dt = time.perf_counter() - t0
-    return {"value": (n_reg + n_near) / dt, "unit": "pair-evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle FP64 fill of {n_reg} regular + {n_near} near triangle pairs "
-                      f"(seeded, of {m.nt ** 2} in the workload), {dt:.1f} s on one core; "
-                      f"projection, CBF build and solve not included"}
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(name, sample, cores, seed=5):
+    """The oracle timed on the host cores: its FP64 fill on bounded seeded
+    samples of the workload's triangle pairs (regular and near pairs in the
+    workload's proportion), on one core and on `cores` worker processes,
+    and its end-to-end CBFM path (fill, CBF build, projection, G^CBF,
+    LU solve, RCS) on the 320-triangle sphere.  Never touches the GPU."""
+    import multiprocessing as mp
+    from oracle import fill, mesh as om
+    w = workload(name)
+    m = om.build(w.V, w.T)
+    log("cpu baseline: near pairs")
+    near = om.near_pairs(m)
+    frac = len(near) / m.nt ** 2
+    rng = np.random.default_rng(seed)
+
+    def draw(n):
+        n_near = max(1, int(round(n * frac)))
+        n_reg = n - n_near
+        isn = set(map(tuple, near.tolist()))
+        P = rng.integers(0, m.nt, n_reg * 2)
+        Q = rng.integers(0, m.nt, n_reg * 2)
+        keep = np.array([(p, q) not in isn for p, q in zip(P.tolist(), Q.tolist())])
+        return P[keep][:n_reg], Q[keep][:n_reg], near[rng.choice(len(near), n_near, replace=False)]
+
+    P, Q, nr = draw(sample)
+    log(f"cpu baseline: one core, {sample} pairs")
+    t1 = _oracle_fill_chunk((name, P, Q, nr))
+    one = {"value": sample / t1, "unit": "pair-evals/s", "cores": 1, "seconds": t1, "pairs": sample}
+    # all cores: `cores` workers, each a sample of the same size
+    chunks = [draw(sample) for _ in range(cores)]
+    log(f"cpu baseline: {cores} workers x {sample} pairs")
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_fill_chunk, [(name, a, b, c) for a, b, c in chunks])
+    tall = time.perf_counter() - t0
+    allc = {"value": cores * sample / tall, "unit": "pair-evals/s", "cores": cores, "seconds": tall,
+            "pairs": cores * sample}
+    # end to end on the 320-triangle sphere (the oracle's whole CBFM path)
+    from oracle import cbf, excitation, reduced
+    ws = workload("sphere320")
+    log("cpu baseline: oracle end to end, sphere320")
+    t0 = time.perf_counter()
+    ms = om.build(ws.V, ws.T)
+    k, eta = fill.media(ws.k0, ws.eta0, ws.eps_r, ws.mu_r)
+    Kc, TE, TH = fill.combine(*fill.fill_ops(ms, k), eta)
+    cb = cbf.build(ms, Kc, TE, TH, ws.edge_block, ws.gen, ws.k0, ws.eta0, ws.delta_svd)
+    CJM, CMJ = reduced.cbf_matrices(cb, ms.ne)
+    Zr = reduced.project(fill.assemble_Z(Kc, TE, TH), CJM, CMJ)
+    Gc = reduced.gram_cbf(cbf.rwg_gram(ms), CJM, CMJ)
+    vr = CJM.conj().T @ excitation.rhs(ms, ws.inc, ws.k0, ws.eta0)
+    jc = np.linalg.solve(Gc, np.linalg.solve(Zr @ np.linalg.inv(Gc), vr))
+    excitation.monostatic_rcs(ms, CMJ @ jc, ws.inc, ws.k0, ws.eta0)
+    te = time.perf_counter() - t0
+    e2e = {"workload": "sphere320 (320 triangles, 960 unknowns, 8 cells, 1 incidence, 144 generating waves)",
+           "seconds": te, "solves_per_s": len(ws.inc) / te, "pair_evals_per_s": ms.nt ** 2 / te}
+    return {"value": allc["value"], "unit": "pair-evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle FP64 fill of seeded samples of the {name} triangle pairs (regular and near pairs "
+                      f"in the workload's proportion): {cores} worker processes x {sample} pairs in {tall:.1f} s; "
+                      f"one core: {sample} pairs in {t1:.1f} s; the end-to-end oracle CBFM path on sphere320 in "
+                      f"{te:.1f} s (single process)",
+            "one_core": one, "all_cores": allc, "end_to_end": e2e,
+            "host": {"cpu_count": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}}
 
 
 def main():
@@ -262,12 +355,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cube1728", choices=["cube1728", "sphere320", "sphere5120", "cylinder19968",
-                                                                "sphere_array4x4x2", "sphere_array8x16x2",
-                                                                "cube_array8x2x2"])
-    ap.add_argument("--cpu-sample", type=int, default=250000)
+    ap.add_argument("--workload", default="cylinder19968", choices=WORKLOADS)
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
+                    help="fill precision of the timed step (default: fp32 for cylinder19968, else fp64)")
+    ap.add_argument("--cpu-sample", type=int, default=60000)
+    ap.add_argument("--cpu-cores", type=int, default=0, help="oracle worker processes (0: the host's, at most 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the precision-form legs (FP32 fill, mixed FP32 and split-BF16)")
+    ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--no-fp32", action="store_true", help="skip the precision-form legs")
+    ap.add_argument("--fp64-steps", type=int, default=0, help="steps of the FP64 leg (0: half of --steps, at least 1)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for the HBM byte counters)")
     ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -278,8 +374,12 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg (both budgets)")
     ap.add_argument("--serve-slots", type=int, default=4)
     args = ap.parse_args()
+    cores = args.cpu_cores or min(16, len(os.sched_getaffinity(0)))
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline(args.workload, args.cpu_sample, cores)), flush=True)
+        return
     if args.write_traffic:
-        write_traffic(*args.write_traffic, args.traffic_command)
+        write_traffic(args.workload, *args.write_traffic, args.traffic_command)
         return
     if args.copy_calibration:
         import torch
@@ -302,40 +402,50 @@ def main():
         print(json.dumps(serving_legs(cbfm, torch, args.serve or 512, args.serve_slots)), flush=True)
         return
     w = workload(args.workload)
-    log(f"bench: {w.name} nt={w.nt} cells={w.nblocks} nrhs={len(w.inc)}")
+    prec_name = args.precision or ("fp32" if args.workload == "cylinder19968" else "fp64")
+    PREC = cbfm.FP32 if prec_name == "fp32" else cbfm.FP64
+    log(f"bench: {w.name} nt={w.nt} cells={w.nblocks} nrhs={len(w.inc)} fill {prec_name}")
     mesh = cbfm.Mesh(w.V, w.T, w.edge_block, w.nblocks)
     med = cbfm.Medium.make(w.k0, w.eta0, w.eps_r, w.mu_r)
     solver = dict(tol=1e-6)
     state = {}
+    traffic = measured_traffic(args.workload)
 
-    def step(precision, inner_fp32=False):
+    def step(precision, inner_fp32=False, timed=None):
         cb = cbfm.build_cbf(mesh, med, w.gen, w.delta_svd, max_L=w.extra.get("max_L", 0))
         n = cb.n_cbf
         Zr = state.get(n)
         if Zr is None:
             Zr = state[n] = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+        done = timed("project") if timed else None
         t0 = time.perf_counter()
         cbfm.project(mesh, med, cb, Zr, precision)
         # (the caller's stream only: the CMP inverse that the CBF build left
         # on the library's side stream may still run beside the projection)
         torch.cuda.current_stream().synchronize()
         t1 = time.perf_counter()
+        if done:
+            done()
         # full (unrestarted) GMRES while the Krylov basis of all right-hand
         # sides stays small, else cycles of 1000
         m = n if n * n * len(w.inc) * 16 * 3 < 8 << 30 else 1000
+        done = timed("solve") if timed else None
+        t2 = time.perf_counter()
         out = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, max_iter=(3 if inner_fp32 else 1) * max(n, 3000),
                          restart=m, inner_fp32=inner_fp32, **solver)
-        t2 = time.perf_counter()
-        return cb, out, t1 - t0, t2 - t1
+        t3 = time.perf_counter()
+        if done:
+            done()
+        return cb, out, t1 - t0, t3 - t2
 
     for i in range(args.warmup):
         log(f"warmup {i}")
-        step(cbfm.FP64)
+        step(PREC)
     torch.cuda.synchronize()
     proj_t, solve_t, iters = [], [], []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        cb, out, tp, ts = step(cbfm.FP64)
+        cb, out, tp, ts = step(PREC)
         proj_t.append(tp)
         solve_t.append(ts)
         iters.append(out["iters"])
@@ -344,7 +454,7 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     nt = w.nt
-    roof, roofs = rooflines(cbfm, lambda: step(cbfm.FP64))
+    roof, roofs = rooflines(cbfm, lambda timed: step(PREC, timed=timed), traffic)
     nrhs = len(w.inc)
     lat = np.array(solve_t)
     result = {
@@ -358,20 +468,45 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32-fill/f64" if PREC == cbfm.FP32 else "f64",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {nt} triangles, {3 * nt // 2} RWGs, {3 * nt} unknowns, "
                                f"{w.nblocks} cells, {nrhs} incidences, {len(w.gen)} generating waves",
-                   "n_cbf": int(cb.n_cbf), "solver": solver},
+                   "fill_precision": prec_name, "n_cbf": int(cb.n_cbf), "solver": solver},
         "fill_projection_pair_evals_per_s": nt * nt / float(np.median(proj_t)),
         "solves_per_s": nrhs * args.steps / float(lat.sum()),
+        "solves_per_s_end_to_end": nrhs * args.steps / total,
         "solve_batch_latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                                    "p99": float(np.percentile(lat, 99) * 1e3)},
         "gmres_iterations": {"mean": float(np.mean(iters)), "max": int(np.max(iters))},
+        "gmres_relres_max": float(out["relres"].max()),
         "roofline": roof,
         "roofline_kernels": roofs,
         "flop_per_pair": FLOP_PER_PAIR,
     }
+    rcs_ref = out["rcs"]
+    if PREC != cbfm.FP64 or args.fp64_steps:
+        # the plain FP64 form of the same step beside the timed one
+        k = args.fp64_steps or max(1, args.steps // 2)
+        step(cbfm.FP64)
+        tp_l, ts_l = [], []
+        torch.cuda.synchronize()
+        tt = time.perf_counter()
+        for _ in range(k):
+            _, o64, tp, ts = step(cbfm.FP64)
+            tp_l.append(tp)
+            ts_l.append(ts)
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - tt
+        _, r64 = rooflines(cbfm, lambda timed: step(cbfm.FP64, timed=timed), traffic)
+        rcs_ref = o64["rcs"]
+        result["fp64_leg"] = {"steps": k, "value": nt * nt * k / tt, "ms_per_step": tt / k * 1e3,
+                              "fill_projection_pair_evals_per_s": nt * nt / float(np.median(tp_l)),
+                              "solves_per_s": nrhs * k / float(np.sum(ts_l)),
+                              "gmres_iterations_max": int(o64["iters"].max()), "status": o64["status"],
+                              "rcs_max_rel_err_of_timed_step": float(np.max(np.abs(out["rcs"] - rcs_ref) / rcs_ref)),
+                              "roofline_kernels": r64}
+        log(f"fp64 leg: {result['fp64_leg']}")
     if w.extra.get("max_L"):
         # the paper's comparison on its array: the same CBFs solved without
         # the CMP (the K-diagonal CBFM without G^CBF), full GMRES up to 1000
@@ -381,8 +516,6 @@ def main():
         result["without_cmp"] = {"gmres_iterations_max": int(o["iters"].max()), "status": o["status"],
                                  "relres_max": float(o["relres"].max())}
         log(f"without CMP: {result['without_cmp']}")
-        # iterations to 1e-4 against eps_r, with and without the CMP (the
-        # paper's figure for the 4 x 4 x 2 array)
         sweep = {}
         for er in ((1.0, 2.0, 3.0, 4.0, 5.0, 6.0) if args.workload == "sphere_array4x4x2" else ()):
             med_e = cbfm.Medium.make(w.k0, w.eta0, er + 0j, w.mu_r)
@@ -395,38 +528,46 @@ def main():
             result["eps_r_sweep_tol_1e-4"] = sweep
             log(f"eps_r sweep: {sweep}")
     if not args.no_fp32:
-        # the precision forms on the same workload: FP32 regular fill with the
-        # FP64 projection and solve; and the mixed forms (FP32 fill, FP32 or
-        # split-BF16 matrix-core projection, float GMRES cycles refined
-        # against the double residual).  CBF build, near pairs, the SVD and
-        # the refinement residual stay FP64.  RCS error against this run's
-        # FP64 step.
-        rcs64 = out["rcs"]
+        # the precision forms on the same workload: the mixed forms (FP32
+        # fill, FP32 or split-BF16 matrix-core projection, float GMRES cycles
+        # refined against the double residual), and the FP32 fill alone when
+        # the timed step is FP64.  CBF build, near pairs, the SVD and the
+        # refinement residual stay FP64.  RCS error against the FP64 step.
         forms = {}
-        for name, prec, inner in (("fp32_fill", cbfm.FP32, False), ("mixed_fp32", cbfm.MIXED_FP32, True),
-                                  ("mixed_bf16x3", cbfm.MIXED_BF16X3, True)):
+        legs = [("mixed_fp32", cbfm.MIXED_FP32, True), ("mixed_bf16x3", cbfm.MIXED_BF16X3, True)]
+        if PREC == cbfm.FP64:
+            legs.insert(0, ("fp32_fill", cbfm.FP32, False))
+        for name, prec, inner in legs:
             step(prec, inner)
             tp_l, ts_l, tt = [], [], time.perf_counter()
-            k = max(1, args.steps // 2)
+            k = max(1, args.steps // 4)
             for _ in range(k):
                 _, o, tp, ts = step(prec, inner)
                 tp_l.append(tp)
                 ts_l.append(ts)
             torch.cuda.synchronize()
             tt = time.perf_counter() - tt
-            forms[name] = {"value": nt * nt * k / tt, "ms_per_step": tt / k * 1e3,
+            forms[name] = {"steps": k, "value": nt * nt * k / tt, "ms_per_step": tt / k * 1e3,
                            "fill_projection_pair_evals_per_s": nt * nt / float(np.median(tp_l)),
                            "solves_per_s": nrhs * k / float(np.sum(ts_l)),
                            "gmres_iterations_max": int(o["iters"].max()), "status": o["status"],
-                           "rcs_max_rel_err_vs_fp64": float(np.max(np.abs(o["rcs"] - rcs64) / rcs64))}
+                           "rcs_max_rel_err_vs_fp64": float(np.max(np.abs(o["rcs"] - rcs_ref) / rcs_ref))}
             log(f"{name}: {forms[name]}")
         result["precision_forms"] = forms
     if args.serve > 0:
         log("serving")
         result["serving"] = serving_legs(cbfm, torch, args.serve, args.serve_slots)
     if not args.no_cpu_baseline:
+        # in a child process that never touches the GPU (its worker pool forks)
         log("cpu baseline (oracle)")
-        result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--workload",
+                            args.workload, "--cpu-sample", str(args.cpu_sample), "--cpu-cores", str(cores)],
+                           capture_output=True, text=True)
+        sys.stderr.write(r.stderr)
+        if r.returncode == 0:
+            result["cpu_baseline"] = json.loads(r.stdout.strip().splitlines()[-1])
+        else:
+            result["cpu_baseline"] = None
     print(json.dumps(result), flush=True)
 
 

@@ -114,6 +114,9 @@ int32_t cbfm_version(void);
  *   4 "gmres_dots"    bytes of basis vectors the Arnoldi dot pass reads
  *   5 "gmres_update"  bytes the Arnoldi update pass reads and writes (basis,
  *                     w and the Hessenberg entries of p = H a)
+ *   6 "fill_regular_f32"  triangle pairs of the regular fill in float
+ *   7 "xgemm"         real flops of the FP32 / BF16 matrix-core GEMMs
+ * ("fill_regular" and "gemm" then count the double-precision launches.)
  * (the GMRES figures count every right-hand side of the batch, also those
  * already converged, which the kernels skip).
  * cbfm_timer_enable(mask) clears all timers and times the families whose

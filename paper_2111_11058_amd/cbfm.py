@@ -134,7 +134,7 @@ def _host(a, dtype):
     return a, a.ctypes.data_as(C.c_void_p)
 
 
-TIMERS = ("fill_regular", "fill_near", "assemble", "gemm", "gmres_dots", "gmres_update")
+TIMERS = ("fill_regular", "fill_near", "assemble", "gemm", "gmres_dots", "gmres_update", "fill_regular_f32", "xgemm")
 
 
 def timer_enable(names=TIMERS):

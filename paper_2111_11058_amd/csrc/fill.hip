@@ -681,7 +681,8 @@ void fill_local(const cbfm_mesh_s* m, const Media& md, int precision, int layout
   CBFM_REQUIRE(nrt <= 65535, CBFM_E_ARG, "too many row triangles for one launch");
   dim3 grid((unsigned)((nct + 255) / 256), (unsigned)nrt);
   {
-  TimedLaunch tl(T_FILL_REGULAR, s, (double)nrt * (double)nct);  // work: triangle pairs
+  TimedLaunch tl(precision == CBFM_FP64 ? T_FILL_REGULAR : T_FILL_REGULAR_F32, s,
+                 (double)nrt * (double)nct);  // work: triangle pairs
   if (precision == CBFM_FP64) {
     auto* out = static_cast<cx<double>*>(local);
     if (lossy)
@@ -760,7 +761,8 @@ static void batch_launch(const std::vector<FillBatchItem>& items, hipStream_t s)
   CBFM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
   const int64_t grid = std::min<int64_t>(total, (int64_t)8 * std::max(cus, 1));
   {
-    TimedLaunch tl(T_FILL_REGULAR, s, pairs);  // work: triangle pairs
+    TimedLaunch tl(std::is_same<R, double>::value ? T_FILL_REGULAR : T_FILL_REGULAR_F32, s,
+                   pairs);  // work: triangle pairs
     hipLaunchKernelGGL(fill_regular_batch_kernel<R>, dim3((unsigned)grid), dim3(256), 0, s, dev.as<FillJob<R>>(),
                        (int)jobs.size(), total);
     CBFM_HIP(hipGetLastError());

@@ -557,7 +557,7 @@ static void launch_x_mode(const GemmDescX* dd, int n, int64_t tiles, int ab, hip
 }
 
 static void launch_x(const GemmDescX* dd, int n, int64_t tiles, double flops, int mode, int ab, hipStream_t s) {
-  TimedLaunch tl(T_GEMM, s, flops);
+  TimedLaunch tl(T_XGEMM, s, flops);
   if (mode == XG_BF16)
     launch_x_mode<XG_BF16>(dd, n, tiles, ab, s);
   else if (mode == XG_BF16X3)

@@ -183,7 +183,9 @@ enum TimerId {
   T_GEMM = 3,
   T_GMRES_DOTS = 4,
   T_GMRES_UPDATE = 5,
-  T_COUNT = 6
+  T_FILL_REGULAR_F32 = 6,  // the regular fill in float
+  T_XGEMM = 7,             // GEMMs on the FP32 / BF16 matrix cores
+  T_COUNT = 8
 };
 struct TimedLaunch {
   TimedLaunch(int id, hipStream_t s, double work = 0.0);

@@ -48,12 +48,20 @@ def test_multipanel_projection_parity(torch_cuda, name):
     w = O["P"]["w"]
     cbfm, mesh, med, cbf = _gpu_handles(w, O)
     n = cbf.n_cbf
-    # a budget of about two and a half cells' panels (FP64 triangle-local
-    # rows of a cell against every triangle dominate)
-    ne, nt, nb = mesh.ne, mesh.nt, mesh.nblocks
-    cell_rows = ne / nb
-    two_half = int(2.5 * (27 * 2 * cell_rows * nt * 16 + 3 * cell_rows * ne * 16 + 4 * cell_rows * n / 2 * 16))
-    for budget in (1, two_half):
+    # one cell per panel (budget 1 byte), then a budget halved from the
+    # whole-mesh scratch until three or more panels form (some holding
+    # several cells)
+    nb = mesh.nblocks
+    budgets = [1]
+    Z = torch_cuda.full((n, n), complex(np.nan, np.nan), dtype=torch_cuda.complex128, device="cuda")
+    b = 64 << 20
+    while b > 1 << 16:
+        if cbfm.project(mesh, med, cbf, Z, cbfm.FP64, panel_bytes=b) >= 3:
+            budgets.append(b)
+            break
+        b //= 2
+    assert len(budgets) == 2
+    for budget in budgets:
         Z = torch_cuda.full((n, n), complex(np.nan, np.nan), dtype=torch_cuda.complex128, device="cuda")
         print(f"multi-panel projection {w.name} budget {budget}", flush=True)
         np_ = cbfm.project(mesh, med, cbf, Z, cbfm.FP64, panel_bytes=budget)
