@@ -358,7 +358,7 @@ def main():
     ap.add_argument("--workload", default="cylinder19968", choices=WORKLOADS)
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="fill precision of the timed step (default: fp32 for cylinder19968, else fp64)")
-    ap.add_argument("--cpu-sample", type=int, default=60000)
+    ap.add_argument("--cpu-sample", type=int, default=300000)
     ap.add_argument("--cpu-cores", type=int, default=0, help="oracle worker processes (0: the host's, at most 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)

@@ -397,3 +397,99 @@ def test_block_forms_equal_the_dense_definitions():
     cb2 = cbf.dual_from_currents(m, w.edge_block, cur, 1e-3)
     for s1, s2 in zip(cb.sigma, cb2.sigma):
         assert len(s1) == len(s2) and np.abs(s1 - s2).max() <= 1e-12 * s1[0]
+
+
+# ------------------------------------------------ MoM arrangement, IPCBF, T-diagonal
+def test_mom_arrangement_gmres_equals_lu():
+    """GMRES on Z_t D^{-1} (the MoM arrangement with the diagonal
+    preconditioner) to 1e-12 reaches the LU solution of Z, reordered, and
+    needs fewer iterations than GMRES on Z_t itself; the residual history
+    falls below each looser allowance at the reported iteration."""
+    from oracle import mom
+    P = oracle_problem("c1")
+    Zt = mom.mom_t_matrix(P["Kc"], P["TE"], P["TH"])
+    ne = P["m"].ne
+    # the arrangement is Z with its two column blocks swapped
+    assert np.array_equal(Zt[:, :ne], P["Z"][:, ne:]) and np.array_equal(Zt[:, ne:], P["Z"][:, :ne])
+    ref = np.linalg.solve(P["Z"], P["v"])
+    j, its, hists = mom.mom_t_solve(Zt, P["v"], 1e-12, 2 * ne, 2 * ne)
+    assert np.linalg.norm(j - ref) <= 1e-9 * np.linalg.norm(ref)
+    _, its_plain, _ = reduced.gmres(lambda y: Zt @ y, P["v"][:, 0], 1e-6, 2 * ne, 2 * ne)
+    _, its_diag, _ = mom.mom_t_solve(Zt, P["v"], 1e-6, 2 * ne, 2 * ne)
+    assert its_diag[0] < its_plain
+    j2, its2, _ = mom.mom_t_solve(Zt, P["v"], 1e-2, 2 * ne, 2 * ne)
+    res = np.linalg.norm(P["v"] - P["Z"] @ j2) / np.linalg.norm(P["v"])
+    assert res <= 1e-2 and abs(res - hists[0][its2[0]]) <= 1e-8
+
+
+def test_ipcbf_limits_and_invariances():
+    """IPCBF currents (Sec. III-A, GMRES version): (1) as delta_r -> 0 they
+    are the MoM solutions of the generating waves restricted to each cell;
+    (2) with delta_SVD = 0 the CBFM on those CBFs reproduces the MoM
+    solution of a generating incidence (it lies in the CBF span); (3) the
+    kept singular values do not depend on the order of the waves; (4) at a
+    loose delta_r every wave's residual is within delta_r."""
+    from oracle import mom
+    P = oracle_problem("cyl_small")
+    w, m = P["w"], P["m"]
+    ne = m.ne
+    Zt = mom.mom_t_matrix(P["Kc"], P["TE"], P["TH"])
+    gen = w.gen[::12][:10]
+    Vg = excitation.rhs(m, gen, w.k0, w.eta0)
+    cur, its = mom.ipcbf_currents(Zt, Vg, w.edge_block, 1e-12, max_iter=2 * ne)
+    exact = np.linalg.solve(P["Z"], Vg)
+    for c in range(w.nblocks):
+        ix = np.nonzero(w.edge_block == c)[0]
+        JM, JJ = cur[c]
+        assert np.linalg.norm(JM - exact[:ne][ix]) <= 1e-9 * np.linalg.norm(exact[:ne][ix])
+        assert np.linalg.norm(JJ - exact[ne:][ix]) <= 1e-9 * np.linalg.norm(exact[ne:][ix])
+    cb = cbf.dual_from_currents(m, w.edge_block, cur, 0.0, G=cbf.rwg_gram(m))
+    CJM, CMJ = reduced.cbf_matrices(cb, ne)
+    Zr = reduced.project(P["Z"], CJM, CMJ)
+    jc = CMJ @ np.linalg.solve(Zr, CJM.conj().T @ Vg[:, [3]])
+    assert np.linalg.norm(jc[:, 0] - exact[:, 3]) <= 1e-7 * np.linalg.norm(exact[:, 3])
+    perm = np.random.default_rng(4).permutation(len(gen))
+    cur2, _ = mom.ipcbf_currents(Zt, Vg[:, perm], w.edge_block, 1e-12, max_iter=2 * ne)
+    cb2 = cbf.dual_from_currents(m, w.edge_block, cur2, 0.0, G=cbf.rwg_gram(m))
+    for s1, s2 in zip(cb.sigma, cb2.sigma):
+        assert np.abs(np.sort(s1) - np.sort(s2)).max() <= 1e-9 * s1.max()
+    curl, itl = mom.ipcbf_currents(Zt, Vg, w.edge_block, 1e-2, max_iter=2 * ne)
+    J = np.zeros((2 * ne, len(gen)), complex)
+    for c in range(w.nblocks):
+        ix = np.nonzero(w.edge_block == c)[0]
+        J[ix], J[ne + ix] = curl[c]
+    res = np.linalg.norm(Vg - P["Z"] @ J, axis=0) / np.linalg.norm(Vg, axis=0)
+    assert np.all(res <= 1e-2) and max(itl) < min(its)
+
+
+def test_t_diagonal_cbfm_is_the_column_swapped_reduced_matrix():
+    """(C^JM)^H Z_t C^JM equals Z_r = (C^JM)^H Z C^MJ with its two column
+    halves swapped, so the T-diagonal CBFM reaches the same currents as the
+    K-diagonal one (GMRES 1e-12 against LU)."""
+    from oracle import mom
+    P = oracle_problem("c1")
+    w, m = P["w"], P["m"]
+    cb = cbf.build(m, P["Kc"], P["TE"], P["TH"], w.edge_block, w.gen, w.k0, w.eta0, 1e-3)
+    CJM, CMJ = reduced.cbf_matrices(cb, m.ne)
+    Zr = reduced.project(P["Z"], CJM, CMJ)
+    Zt = mom.mom_t_matrix(P["Kc"], P["TE"], P["TH"])
+    Ztr = mom.t_diagonal_operator(Zt, CJM)
+    NL = Zr.shape[0] // 2
+    sw = np.r_[NL:2 * NL, 0:NL]
+    assert np.abs(Ztr - Zr[:, sw]).max() <= 1e-12 * np.abs(Zr).max()
+    vr = CJM.conj().T @ P["v"][:, 0]
+    y, it, _ = reduced.gmres(lambda u: Ztr @ u, vr, 1e-12, 2 * NL, 2 * NL)
+    j_t = CJM @ y
+    j = np.concatenate([j_t[m.ne:], j_t[:m.ne]])
+    jref = CMJ @ np.linalg.solve(Zr, vr)
+    assert np.linalg.norm(j - jref) <= 1e-9 * np.linalg.norm(jref)
+
+
+def test_rmse_closed_forms():
+    """RMSE (Sec. IV-A): a constant offset delta over a range R gives
+    10 log10(delta / R); a scaled error scales inside the log."""
+    from oracle import mom
+    sm = np.linspace(1.0, 5.0, 31)
+    assert abs(mom.rmse_db(sm + 0.04, sm) - 10 * np.log10(0.01)) < 1e-12
+    e = np.sin(np.arange(31.0))
+    assert abs(mom.rmse_db(sm + 2 * e, sm) - mom.rmse_db(sm + e, sm) - 10 * np.log10(2)) < 1e-12
