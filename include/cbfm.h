@@ -59,6 +59,7 @@ extern "C" {
 
 typedef struct cbfm_mesh_s* cbfm_mesh;
 typedef struct cbfm_cbf_s* cbfm_cbf;
+typedef struct cbfm_mom_s* cbfm_mom;
 
 typedef enum {
   CBFM_OK = 0,
@@ -83,11 +84,12 @@ typedef enum {
                         /* hi hi + hi lo + lo hi, about 16 significant bits)    */
 } cbfm_precision;
 
-/* Output layout of cbfm_fill_pmchwt: three nrow x ncol complex matrices,
-   matrix after matrix. */
+/* Output layout of cbfm_fill_pmchwt: three (four for MEDIA4) nrow x ncol
+   complex matrices, matrix after matrix. */
 enum {
   CBFM_LAYOUT_MEDIA3 = 0, /* [K1 + K2, T1, T2]                                */
-  CBFM_LAYOUT_OPS3 = 1    /* [K, TE = eta1 T1 + eta2 T2, TH = T1/eta1 + T2/eta2] */
+  CBFM_LAYOUT_OPS3 = 1,   /* [K, TE = eta1 T1 + eta2 T2, TH = T1/eta1 + T2/eta2] */
+  CBFM_LAYOUT_MEDIA4 = 2  /* [K1, K2, T1, T2]: every medium's operators apart */
 };
 
 /* Interior medium and free-space constants. */
@@ -101,8 +103,34 @@ typedef struct {
 /* Thread-local description of the last error (never NULL). */
 const char* cbfm_last_error(void);
 
+/* ------------------------------------------------------- device memory ---
+ * cbfm_set_allocator: the caller's device allocator (for example PyTorch's
+ * caching allocator) for all device memory of the library: the buffers that
+ * handles own and the stream-ordered scratch of every call.  alloc(bytes,
+ * stream) returns device memory of the current device, usable in the order
+ * of `stream` (NULL for handle buffers, which any stream may use), or NULL
+ * on failure (the call then fails with CBFM_E_NOMEM); release(p, stream)
+ * gives it back once the work queued on `stream` is done with it (handle
+ * buffers: when the handle is freed, stream NULL).  The routines may be
+ * called from any thread (serving workers), and must be callable until
+ * every block obtained through them is released.  Passing NULL for both
+ * restores the library's own device allocations (hipMalloc with a cache of
+ * freed scratch blocks).  Blocks keep the routine that gave them out; the
+ * cached hipMalloc blocks are freed when an allocator is set.  Not
+ * thread-safe against calls in flight: set it before other work.          */
+typedef void* (*cbfm_alloc_fn)(size_t bytes, void* stream);
+typedef void (*cbfm_release_fn)(void* p, void* stream);
+cbfm_status cbfm_set_allocator(cbfm_alloc_fn alloc, cbfm_release_fn release);
+
+/* Device bytes the library holds from its own hipMalloc allocations (handle
+   buffers and cached or live scratch; memory from a caller's allocator is
+   not counted), the most it held at once since the process started, and
+   the part now idle in the scratch cache of the current device (any may
+   be NULL).                                                               */
+cbfm_status cbfm_memory_stats(int64_t* held, int64_t* peak, int64_t* cached);
+
 /* ABI version (incremented on incompatible change). */
-int32_t cbfm_version(void);
+int32_t cbfm_version(void);  /* 2: cbfm_solver_params gained cmp_mode, cmp_inner_tol */
 
 /* -------------------------------------------------------------- timers ---
  * Opt-in kernel timing for measurement: when enabled, the library records a
@@ -189,10 +217,15 @@ cbfm_status cbfm_mesh_analyze(const double* xyz_host, int64_t nv, const int32_t*
  *              CBFM_FP32: regular pairs in float, near pairs in double,
  *              output float2.
  *   layout     CBFM_LAYOUT_MEDIA3 or CBFM_LAYOUT_OPS3 (see above)
- *   out_dev    3 matrices, matrix o element (r, c) at
- *              out_dev[(o * nrow + r) * ld + c]; ld >= ncol
+ *   out_dev    3 matrices (4 for MEDIA4), matrix o element (r, c) at
+ *              out_dev[(o * nrow + r) * ld + c]; ld >= ncol.  MEDIA4 fills
+ *              [K1 + K2, T1, T2] and, apart, the K operator of the body with
+ *              the exterior medium inside (exactly 2 K1: the kernel sums
+ *              two equal media), then K1 = that / 2 and K2 = (K1 + K2) - K1;
+ *              it takes twice the time of the other layouts
  * Uses stream-ordered scratch of about 3 * 9 * ntr * ntc complex elements,
- * ntr/ntc the triangles touching the row/column ranges.
+ * ntr/ntc the triangles touching the row/column ranges.  Synchronises the
+ * stream.
  */
 cbfm_status cbfm_fill_pmchwt(cbfm_mesh m, const cbfm_medium* med, int32_t precision,
                              int64_t row0, int64_t nrow, int64_t col0, int64_t ncol,
@@ -293,6 +326,12 @@ cbfm_status cbfm_project_batch(int32_t count, const cbfm_mesh* meshes, const cbf
                                const cbfm_cbf* cbfs, int32_t precision, void* const* Zr_dev,
                                const int64_t* ldz, void* stream);
 
+/* CMP modes: the exact inverse (the plain path), or the paper's inexact
+   inner solve of G^CBF j_CBF = y by GMRES with the diagonal preconditioner
+   D^CBF = diag(1 / [G^CBF]_ii) (Sec. III-C, the paragraph on D^CBF; the
+   numerical section uses the allowance 1e-5). */
+enum { CBFM_CMP_EXACT = 0, CBFM_CMP_INNER_GMRES = 1 };
+
 /* ----------------------------------------------------------------- CMP ---
  * cbfm_cmp_apply: x = (G^CBF)^{-1} y with G^CBF = (C^JM)^H G_ffff C^MJ
  * (paper Sec. III-C, CBF Gram matrix and inner CBFM equation), exact:
@@ -303,6 +342,16 @@ cbfm_status cbfm_project_batch(int32_t count, const cbfm_mesh* meshes, const cbf
  *   y_dev, x_dev  nrhs x N_CBF double2, vector after vector (may alias)    */
 cbfm_status cbfm_cmp_apply(cbfm_cbf c, int64_t nrhs, const void* y_dev, void* x_dev,
                            void* stream);
+
+/* cbfm_cmp_apply_ex: as cbfm_cmp_apply with mode CBFM_CMP_EXACT; with
+ * CBFM_CMP_INNER_GMRES, x is the GMRES solution of G^CBF x = y with the
+ * right preconditioner D^CBF (x0 = 0, restarted every min(2 sum L, 500)
+ * iterations, at most 4 x 2 sum L), stopped at the relative residual
+ * inner_tol (0: 1e-5); the operator G^CBF D^CBF (2 sum L square) is formed
+ * on the first such call and kept in the handle.  Synchronises the stream
+ * in the inexact mode.                                                     */
+cbfm_status cbfm_cmp_apply_ex(cbfm_cbf c, int64_t nrhs, const void* y_dev, void* x_dev, int32_t mode,
+                              double inner_tol, void* stream);
 
 /* --------------------------------------------------------------- solve ---
  * cbfm_solve: for each incidence, v_r = (C^JM)^H v, right-preconditioned
@@ -318,7 +367,11 @@ cbfm_status cbfm_cmp_apply(cbfm_cbf c, int64_t nrhs, const void* y_dev, void* x_
  *   dirs_host  ndir x 3 unit observation directions -> rcs_host nrhs x ndir
  *              total bistatic sigma; NULL -> monostatic co-polarised sigma
  *              (direction -k, component along p), rcs_host nrhs
- *   use_cmp    1: right preconditioner (G^CBF)^{-1}; 0: none (y = j_CBF)
+ *   use_cmp    1: right preconditioner (G^CBF)^{-1}; 0: none (y = j_CBF),
+ *              the K-diagonal CBFM without the CMP; 2: the T-diagonal
+ *              CBFM of Sec. IV-A, (C^JM)^H Z_t C^JM j_t^CBF = v_r with Z_t
+ *              the MoM arrangement (Z with its column blocks swapped), that
+ *              is Z_r with its two column halves swapped, no preconditioner
  * Synchronises the stream.  CBFM_E_NOCONV if, for some RHS, the relative
  * residual of the preconditioned system recomputed in double at the end
  * (relres_host) exceeds tol; every cycle starts from that true residual, so
@@ -335,6 +388,14 @@ typedef struct {
   double inner_tol;   /* mixed form only; 0 -> 1e-6                         */
   int32_t use_graph;  /* 1: Arnoldi iterations in chunks of four captured   */
                       /* once per cycle into a HIP graph and replayed      */
+  int32_t cmp_mode;   /* with use_cmp 1: CBFM_CMP_EXACT, or               */
+                      /* CBFM_CMP_INNER_GMRES -- the paper's inexact      */
+                      /* (G^CBF)^{-1} (see cbfm_cmp_apply_ex), inside     */
+                      /* flexible GMRES (the preconditioner changes from  */
+                      /* one iteration to the next, so the iterate is     */
+                      /* built from the preconditioned vectors); double   */
+                      /* cycles, no graphs                                */
+  double cmp_inner_tol; /* inexact CMP allowance; 0 -> 1e-5                */
 } cbfm_solver_params;
 
 cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, const void* Zr_dev,
@@ -342,6 +403,87 @@ cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, const vo
                        const cbfm_solver_params* prm, void* j_dev, int32_t* iters_host,
                        double* relres_host, const double* dirs_host, int64_t ndir,
                        double* rcs_host, void* stream);
+
+/* ---------------------------------------------------- the whole system ---
+ * A cbfm_mom holds the whole discretised PMCHWT system of a mesh and medium
+ * on the device, in the MoM arrangement of the numerical section (Sec. IV)
+ * with its diagonal preconditioner:
+ *   A = Z_t D^{-1},  Z_t = [[-TE, K], [K, TH]] acting on j_t = [alpha^J; alpha^M],
+ *   D = diag(Z_t),
+ * where the paper tests the T blocks with Buffa-Christiansen functions and
+ * this library with the RWG functions themselves (the BC basis is not
+ * built), so Z_t is the matrix Z of the conventions above with its two
+ * column blocks swapped.  A is (2 ne)^2 complex numbers: 16 bytes each in
+ * FP64, 8 in FP32 (regular pairs filled in float, near pairs in double):
+ * for 29,952 RWGs 57 GB or 29 GB of device memory.
+ *
+ * cbfm_mom_build: fill and store A and D.  precision CBFM_FP64 or
+ *   CBFM_FP32.  panel_bytes: scratch budget of the fill's row panels (0: a
+ *   quarter of the free device memory, at most 32 GiB).  Synchronises the
+ *   stream.  The mesh must outlive the handle.  CBFM_E_NOMEM if A does not
+ *   fit.                                                                    */
+cbfm_status cbfm_mom_build(cbfm_mesh m, const cbfm_medium* med, int32_t precision, int64_t panel_bytes,
+                           void* stream, cbfm_mom* out);
+/* The order n = 2 ne and the precision of A (each may be NULL).          */
+cbfm_status cbfm_mom_info(cbfm_mom o, int64_t* n, int32_t* precision);
+/* Copy rows row0 .. row0 + nrow - 1 of A into A_dev (row stride ld >= n,
+   double2 for FP64, float2 for FP32) and D into d_dev (n double2); either
+   may be NULL.  A's rows are [E-tests; H-tests] and its columns [alpha^J;
+   alpha^M], each half with the RWGs in the library's cell order (canonical
+   edges stably sorted by cell), not the canonical one.  Enqueued on the
+   stream.                                                                  */
+cbfm_status cbfm_mom_export(cbfm_mom o, int64_t row0, int64_t nrow, void* A_dev, int64_t ld, void* d_dev,
+                            void* stream);
+void cbfm_mom_free(cbfm_mom o);
+
+/* cbfm_mom_solve: the MoM baseline of Sec. IV -- right-preconditioned GMRES
+ * on Z_t D^{-1} u = v from u = 0 (Z_t D^{-1} = A), j_t = D^{-1} u, for every
+ * incidence; the residual ||v - Z j|| / ||v|| is what tol bounds.  Outputs
+ * as cbfm_solve: j_dev (nrhs x 2ne, canonical order, [alpha^M; alpha^J]),
+ * iters, relres (true relative residual), RCS.  Fields of prm: tol,
+ * max_iter, restart, inner_fp32 / inner_tol (float Krylov cycles refined
+ * against the double residual; an FP32 operator always runs float cycles
+ * and forms its residual in float, so tolerances below about 1e-6 are out
+ * of its reach), use_graph; use_cmp is ignored.  CBFM_E_NOCONV as
+ * cbfm_solve.  Synchronises the stream.                                    */
+cbfm_status cbfm_mom_solve(cbfm_mom o, const double* inc_host, int64_t nrhs, const cbfm_solver_params* prm,
+                           void* j_dev, int32_t* iters_host, double* relres_host, const double* dirs_host,
+                           int64_t ndir, double* rcs_host, void* stream);
+
+/* cbfm_build_ipcbf: improved primary CBFs by the GMRES version of Sec.
+ * III-A: each of the n_gen generating plane waves is solved on the whole
+ * scatterer as in cbfm_mom_solve, to the loose relative residual delta_r
+ * (full GMRES unless restart > 0); cell m keeps the rows of its RWGs,
+ * J^M_m and J^J_m (N_m x n_gen), and the sets are orthogonalised exactly as
+ * in cbfm_build_cbf (Sec. III-B: G'_m, SVD, truncation at delta_svd, at
+ * most max_L if > 0).  iters_host / relres_host (n_gen each, or NULL): the
+ * iterations and true residual of every wave.  CBFM_E_NOCONV (no handle)
+ * if a wave does not reach delta_r within max_iter, CBFM_E_RANK as
+ * cbfm_build_cbf.  The CBF handle belongs to the operator's mesh; the CMP
+ * inverse is queued as after cbfm_build_cbf.  Synchronises the stream.    */
+typedef struct {
+  const double* gen_host; /* n_gen x 6 (k, p) generating plane waves */
+  int32_t n_gen;
+  double delta_r;         /* GMRES residual allowance, in (0, 1)     */
+  double delta_svd;
+  int32_t max_L;          /* 0 = no cap                              */
+  int32_t max_iter;
+  int32_t restart;        /* 0 = max_iter (full GMRES)               */
+} cbfm_ipcbf_params;
+cbfm_status cbfm_build_ipcbf(cbfm_mom o, const cbfm_ipcbf_params* prm, void* stream, cbfm_cbf* out,
+                             int32_t* iters_host, double* relres_host);
+
+/* cbfm_solve_matfree: cbfm_solve (use_cmp 0 or 1) with the reduced
+ * operator applied without forming Z_r (Sec. III-C, the remark after the
+ * current reconstruction: the products with C^MJ, C^JM and G^CBF are cheap
+ * and the one with Z is the expensive one): every GMRES product computes
+ * (C^JM)^H Z C^MJ (G^CBF)^{-1} y from the stored operator, Z u = A D P^T u
+ * with P^T swapping the halves of u.  Double Krylov cycles only
+ * (inner_fp32 = use_graph = 0).  Outputs as cbfm_solve.                    */
+cbfm_status cbfm_solve_matfree(cbfm_mom o, cbfm_cbf c, const double* inc_host, int64_t nrhs,
+                               const cbfm_solver_params* prm, void* j_dev, int32_t* iters_host,
+                               double* relres_host, const double* dirs_host, int64_t ndir, double* rcs_host,
+                               void* stream);
 
 /* ------------------------------------------------------------- serving ---
  * A request server for scattering solves of mixed size (the whole path of a

@@ -126,11 +126,14 @@ def near_local(m: RWGMesh, k, p, q):
     if p == q or coplanar(m, p, q):
         K = np.zeros((3, 3), dtype=np.complex128)
     else:
-        # V(r) = int_Q g (r - r') summed over both media
-        ksq = k[0] * k[0] + k[1] * k[1]
+        # V(r) = int_Q g (r - r') summed over the media in k
+        ksq = k[0] * k[0]
+        grs = _gr(k[0], R)
+        for ki in k[1:]:
+            ksq = ksq + ki * ki
+            grs = grs + _gr(ki, R)
         # int (r - r')/R = -Vm1
-        Vs = -(2.0 * pot["Gm3"] - 0.5 * ksq * pot["Vm1"]) / FOUR_PI
-        grs = _gr(k[0], R) + _gr(k[1], R)
+        Vs = -(float(len(k)) * pot["Gm3"] - 0.5 * ksq * pot["Vm1"]) / FOUR_PI
         Vk = Vs + Aq * np.einsum("kj,j,kji->ki", grs, w, diff)
         # int_Q grad'G x f_b = -(s_b l_b / 2Aq) V x (r - q_b)
         rmq = rp[:, None, :] - vq[None, :, :]           # (7,3b,3)
@@ -178,6 +181,26 @@ def fill_ops(m: RWGMesh, k):
     """RWG matrices (K, T1, T2) with K = K1 + K2."""
     K, T = local_blocks(m, k)
     return assemble_ops(m, K, T)
+
+
+def fill_media(m: RWGMesh, k):
+    """The four operators of the two media apart, (K1, K2, T1, T2): K_i is the
+    K operator of medium i alone (the fill with the single wavenumber k_i)."""
+    K1, T1 = _one_medium(m, k[0])
+    K2, T2 = _one_medium(m, k[1])
+    return K1, K2, T1, T2
+
+
+def _one_medium(m: RWGMesh, ki):
+    K, T = local_blocks(m, np.array([ki]))
+    ne = m.ne
+    out = [np.zeros((ne, ne), dtype=np.complex128) for _ in range(2)]
+    rows = m.tri_edge
+    for X, Y in zip(out, [K, T[0]]):
+        ii = np.broadcast_to(rows[:, None, :, None], Y.shape)
+        jj = np.broadcast_to(rows[None, :, None, :], Y.shape)
+        np.add.at(X, (ii.ravel(), jj.ravel()), Y.ravel())
+    return out
 
 
 def combine(Kop, T1, T2, eta):

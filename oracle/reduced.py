@@ -147,6 +147,88 @@ def gmres(matvec, b, tol=1e-12, restart=100, max_iter=1000):
     return x, it, hist
 
 
+def cmp_inner(Gcbf, y, tol, restart=None, max_iter=None):
+    """The paper's inexact (G^CBF)^{-1} (Sec. III-C, the paragraph on D^CBF):
+    GMRES on G^CBF D z = y with the diagonal preconditioner
+    D = diag(1 / [G^CBF]_ii) (1 where that diagonal is 0), x0 = 0, to the
+    relative residual tol; x = D z, for every column of y."""
+    n = Gcbf.shape[0]
+    dg = np.diag(Gcbf)
+    D = np.where(dg != 0, 1.0 / np.where(dg != 0, dg, 1.0), 1.0)
+    A = Gcbf * D[None, :]
+    y = np.asarray(y).reshape(n, -1)
+    out = np.zeros_like(y, dtype=np.complex128)
+    for c in range(y.shape[1]):
+        z, _, _ = gmres(lambda u: A @ u, y[:, c], tol, restart or min(n, 500), max_iter or 4 * n)
+        out[:, c] = D * z
+    return out
+
+
+def fgmres(matvec, precond, b, tol=1e-12, restart=100, max_iter=1000):
+    """Flexible GMRES (Saad 2003): right preconditioning by an operator that
+    may change from one iteration to the next.  The preconditioned vectors
+    z_j = precond(q_j) are kept and the iterate is x = x0 + Z y, y from the
+    same least-squares problem as GMRES (modified Gram-Schmidt Arnoldi on
+    A z_j).  Returns (x, iterations, relative residual history)."""
+    b = np.asarray(b, dtype=np.complex128)
+    n = len(b)
+    x = np.zeros(n, dtype=np.complex128)
+    bn = np.linalg.norm(b)
+    hist = [1.0]
+    if bn == 0:
+        return x, 0, hist
+    it = 0
+    r = b.copy()
+    while it < max_iter:
+        beta = np.linalg.norm(r)
+        if beta / bn <= tol:
+            break
+        m = min(restart, max_iter - it)
+        Vb = np.zeros((m + 1, n), dtype=np.complex128)
+        Zb = np.zeros((m, n), dtype=np.complex128)
+        H = np.zeros((m + 1, m), dtype=np.complex128)
+        Vb[0] = r / beta
+        cs = np.zeros(m, dtype=np.complex128)
+        sn = np.zeros(m, dtype=np.complex128)
+        g = np.zeros(m + 1, dtype=np.complex128)
+        g[0] = beta
+        kk = 0
+        for kk in range(m):
+            Zb[kk] = precond(Vb[kk])
+            wv = matvec(Zb[kk])
+            for i in range(kk + 1):
+                H[i, kk] = np.vdot(Vb[i], wv)
+                wv = wv - H[i, kk] * Vb[i]
+            H[kk + 1, kk] = np.linalg.norm(wv)
+            if H[kk + 1, kk] != 0:
+                Vb[kk + 1] = wv / H[kk + 1, kk]
+            for i in range(kk):
+                t = cs[i] * H[i, kk] + sn[i] * H[i + 1, kk]
+                H[i + 1, kk] = -np.conj(sn[i]) * H[i, kk] + np.conj(cs[i]) * H[i + 1, kk]
+                H[i, kk] = t
+            a, bb = H[kk, kk], H[kk + 1, kk]
+            den = np.sqrt(abs(a) ** 2 + abs(bb) ** 2)
+            cs[kk] = np.conj(a) / den if den else 1.0
+            sn[kk] = np.conj(bb) / den if den else 0.0
+            H[kk, kk] = den
+            H[kk + 1, kk] = 0
+            g[kk + 1] = -np.conj(sn[kk]) * g[kk]
+            g[kk] = cs[kk] * g[kk]
+            it += 1
+            hist.append(abs(g[kk + 1]) / bn)
+            if hist[-1] <= tol:
+                kk += 1
+                break
+        else:
+            kk = m
+        y = np.linalg.solve(np.triu(H[:kk, :kk]), g[:kk]) if kk else np.zeros(0)
+        x = x + Zb[:kk].T @ y
+        r = b - matvec(x)
+        if hist[-1] <= tol:
+            break
+    return x, it, hist
+
+
 def solve_reduced(Zr, Gcbf, vr, tol=1e-12, restart=100, max_iter=1000):
     """Right-preconditioned GMRES on Z_r G^-1 y = v_r, then j_CBF = G^-1 y,
     for every column of ``vr``.  Returns (j_CBF, iterations, histories)."""

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcbfm.so")
 
 FP64, FP32, MIXED_FP32, MIXED_BF16, MIXED_BF16X3 = 0, 1, 2, 3, 4
-LAYOUT_MEDIA3, LAYOUT_OPS3 = 0, 1
+LAYOUT_MEDIA3, LAYOUT_OPS3, LAYOUT_MEDIA4 = 0, 1, 2
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_MESH", -3: "E_NOMEM", -4: "E_HIP", -5: "E_NOCONV",
           -6: "E_RANK", -7: "E_STATE"}
@@ -44,10 +44,18 @@ class CbfParams(C.Structure):
                 ("delta_svd", C.c_double), ("max_L", C.c_int32)]
 
 
+CMP_EXACT, CMP_INNER_GMRES = 0, 1
+
+
 class SolverParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32),
                 ("use_cmp", C.c_int32), ("inner_fp32", C.c_int32), ("inner_tol", C.c_double),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("cmp_mode", C.c_int32), ("cmp_inner_tol", C.c_double)]
+
+
+class IpcbfParams(C.Structure):
+    _fields_ = [("gen_host", C.POINTER(C.c_double)), ("n_gen", C.c_int32), ("delta_r", C.c_double),
+                ("delta_svd", C.c_double), ("max_L", C.c_int32), ("max_iter", C.c_int32), ("restart", C.c_int32)]
 
 
 _lib = None
@@ -66,6 +74,8 @@ def lib():
     L = C.CDLL(LIB_PATH)
     sig = {
         "cbfm_last_error": (C.c_char_p, []),
+        "cbfm_set_allocator": (_I32, [_P, _P]),
+        "cbfm_memory_stats": (_I32, [C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
         "cbfm_timer_enable": (_I32, [_I32]),
         "cbfm_request_footprint": (_I32, [_P, C.POINTER(_I64)]),
         "cbfm_project_batch": (_I32, [_I32, _P, _P, _P, _I32, _P, _P, _P]),
@@ -92,6 +102,14 @@ def lib():
         "cbfm_project": (_I32, [_P, C.POINTER(Medium), _P, _I32, _P, _I64, _P]),
         "cbfm_project_ex": (_I32, [_P, C.POINTER(Medium), _P, _I32, _P, _I64, _I64, C.POINTER(_I32), _P]),
         "cbfm_cmp_apply": (_I32, [_P, _I64, _P, _P, _P]),
+        "cbfm_cmp_apply_ex": (_I32, [_P, _I64, _P, _P, _I32, C.c_double, _P]),
+        "cbfm_mom_build": (_I32, [_P, C.POINTER(Medium), _I32, _I64, _P, C.POINTER(_P)]),
+        "cbfm_mom_info": (_I32, [_P, C.POINTER(_I64), C.POINTER(_I32)]),
+        "cbfm_mom_export": (_I32, [_P, _I64, _I64, _P, _I64, _P, _P]),
+        "cbfm_mom_free": (None, [_P]),
+        "cbfm_mom_solve": (_I32, [_P, _P, _I64, C.POINTER(SolverParams), _P, _P, _P, _P, _I64, _P, _P]),
+        "cbfm_build_ipcbf": (_I32, [_P, C.POINTER(IpcbfParams), _P, C.POINTER(_P), _P, _P]),
+        "cbfm_solve_matfree": (_I32, [_P, _P, _P, _I64, C.POINTER(SolverParams), _P, _P, _P, _P, _I64, _P, _P]),
         "cbfm_solve": (_I32, [_P, C.POINTER(Medium), _P, _P, _I64, _P, _I64, C.POINTER(SolverParams), _P,
                               _P, _P, _P, _I64, _P, _P]),
     }
@@ -132,6 +150,44 @@ def _dev(t, dtype, numel=None, what="tensor"):
 def _host(a, dtype):
     a = np.ascontiguousarray(a, dtype=dtype)
     return a, a.ctypes.data_as(C.c_void_p)
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+_allocator_hooks = []  # the ctypes callbacks live as long as the process
+
+
+def use_torch_allocator(enable=True):
+    """cbfm_set_allocator with PyTorch's caching allocator: every device
+    buffer of the library (handles and scratch) then comes from
+    torch.cuda.caching_allocator_alloc on the stream the library names, and
+    goes back through caching_allocator_delete.  enable=False restores the
+    library's own allocations."""
+    import torch
+    if not enable:
+        _check(lib().cbfm_set_allocator(None, None))
+        return
+
+    def _alloc(nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:
+            return None
+
+    def _release(p, stream):
+        torch.cuda.caching_allocator_delete(int(p))
+
+    hooks = (_ALLOC_FN(_alloc), _RELEASE_FN(_release))
+    _allocator_hooks.append(hooks)
+    _check(lib().cbfm_set_allocator(C.cast(hooks[0], _P), C.cast(hooks[1], _P)))
+
+
+def memory_stats():
+    """cbfm_memory_stats: dict(held, peak, cached) bytes of the library's own
+    device allocations."""
+    h, p, c = _I64(), _I64(), _I64()
+    _check(lib().cbfm_memory_stats(C.byref(h), C.byref(p), C.byref(c)))
+    return dict(held=h.value, peak=p.value, cached=c.value)
 
 
 TIMERS = ("fill_regular", "fill_near", "assemble", "gemm", "gmres_dots", "gmres_update", "fill_regular_f32", "xgemm")
@@ -222,15 +278,16 @@ class Mesh:
 
 def fill_pmchwt(mesh: Mesh, medium: Medium, out, precision=FP64, layout=LAYOUT_MEDIA3,
                 row0=0, nrow=None, col0=0, ncol=None, ld=None, stream=None):
-    """cbfm_fill_pmchwt into ``out`` (3 x nrow x ld complex tensor)."""
+    """cbfm_fill_pmchwt into ``out`` (3 x nrow x ld complex tensor, 4 x for
+    LAYOUT_MEDIA4)."""
     import torch
     nrow = mesh.ne - row0 if nrow is None else nrow
     ncol = mesh.ne - col0 if ncol is None else ncol
     ld = ncol if ld is None else ld
     dt = torch.complex128 if precision == FP64 else torch.complex64
-    p = _dev(out, dt, 3 * nrow * ld, "out")
-    _check(lib().cbfm_fill_pmchwt(mesh.handle, C.byref(medium), precision, row0, nrow, col0, ncol,
-                                  layout, p, ld, _stream(stream)))
+    p = _dev(out, dt, (4 if layout == LAYOUT_MEDIA4 else 3) * nrow * ld, "out")
+    _check(lib().cbfm_fill_pmchwt(mesh.handle, C.byref(medium), precision, row0, nrow, col0, ncol, layout, p, ld,
+                                  _stream(stream)))
     return out
 
 
@@ -340,18 +397,123 @@ def project_batch(items, precision=FP64, stream=None):
     _check(lib().cbfm_project_batch(k, meshes, media, cbfs, int(precision), zr, ldz, _stream(stream)))
 
 
-def cmp_apply(cbf: CBF, y, x, stream=None):
+def cmp_apply(cbf: CBF, y, x, stream=None, mode=CMP_EXACT, inner_tol=0.0):
+    """cbfm_cmp_apply_ex: x = (G^CBF)^{-1} y, exact or by the inner GMRES."""
     import torch
     nrhs = y.numel() // cbf.n_cbf
     py = _dev(y, torch.complex128, nrhs * cbf.n_cbf, "y")
     px = _dev(x, torch.complex128, nrhs * cbf.n_cbf, "x")
-    _check(lib().cbfm_cmp_apply(cbf.handle, nrhs, py, px, _stream(stream)))
+    _check(lib().cbfm_cmp_apply_ex(cbf.handle, nrhs, py, px, int(mode), float(inner_tol), _stream(stream)))
     return x
+
+
+class MomOperator:
+    """The whole system in the MoM arrangement with its diagonal
+    preconditioner (cbfm_mom): A = Z_t D^{-1} stored on the device."""
+
+    def __init__(self, mesh: Mesh, medium: Medium, precision=FP64, panel_bytes=0, stream=None):
+        h = _P()
+        _check(lib().cbfm_mom_build(mesh.handle, C.byref(medium), int(precision), int(panel_bytes), _stream(stream),
+                                    C.byref(h)))
+        self._h, self.mesh, self.medium = h, mesh, medium
+        n, p = _I64(), _I32()
+        _check(lib().cbfm_mom_info(h, C.byref(n), C.byref(p)))
+        self.n, self.precision = n.value, p.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self, row0=0, nrow=None, stream=None):
+        """(rows row0.. of A, D) as torch tensors (cell order, see the header)."""
+        import torch
+        nrow = self.n - row0 if nrow is None else nrow
+        dt = torch.complex128 if self.precision == FP64 else torch.complex64
+        A = torch.empty((nrow, self.n), dtype=dt, device="cuda")
+        d = torch.empty(self.n, dtype=torch.complex128, device="cuda")
+        _check(lib().cbfm_mom_export(self._h, int(row0), int(nrow), _dev(A, dt, nrow * self.n, "A"), self.n,
+                                     _dev(d, torch.complex128, self.n, "d"), _stream(stream)))
+        torch.cuda.synchronize()
+        return A, d
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cbfm_mom_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _solve_outputs(nrhs, dirs):
+    iters = np.zeros(nrhs, np.int32)
+    relres = np.zeros(nrhs)
+    if dirs is not None:
+        dirs, pd = _host(dirs, np.float64)
+        dirs = dirs.reshape(-1, 3)
+        rcs = np.zeros((nrhs, len(dirs)))
+        return iters, relres, rcs, dirs, pd, len(dirs)
+    return iters, relres, np.zeros(nrhs), None, None, 0
+
+
+def mom_solve(mom: MomOperator, inc, tol=1e-6, max_iter=1000, restart=1000, j_out=None, dirs=None, stream=None,
+              inner_fp32=False, inner_tol=0.0, use_graph=False):
+    """cbfm_mom_solve (the MoM baseline).  Returns dict(iters, relres, rcs, status)."""
+    import torch
+    inc, pi = _host(inc, np.float64)
+    inc = inc.reshape(-1, 6)
+    nrhs = len(inc)
+    pj = _dev(j_out, torch.complex128, nrhs * mom.n, "j") if j_out is not None else None
+    iters, relres, rcs, dirs, pd, nd = _solve_outputs(nrhs, dirs)
+    prm = SolverParams(float(tol), int(max_iter), int(restart), 0, int(bool(inner_fp32)), float(inner_tol),
+                       int(bool(use_graph)))
+    code = lib().cbfm_mom_solve(mom.handle, pi, nrhs, C.byref(prm), pj, iters.ctypes.data_as(C.c_void_p),
+                                relres.ctypes.data_as(C.c_void_p), pd, nd, rcs.ctypes.data_as(C.c_void_p),
+                                _stream(stream))
+    if code not in (0, -5):
+        _check(code)
+    return dict(iters=iters, relres=relres, rcs=rcs, status=STATUS.get(code, code))
+
+
+def build_ipcbf(mom: MomOperator, gen, delta_r=1e-3, delta_svd=1e-3, max_L=0, max_iter=1000, restart=0, stream=None):
+    """cbfm_build_ipcbf: returns (CBF, iterations per wave, residual per wave)."""
+    gen, _ = _host(gen, np.float64)
+    gen = gen.reshape(-1, 6)
+    prm = IpcbfParams(gen.ctypes.data_as(C.POINTER(C.c_double)), len(gen), float(delta_r), float(delta_svd),
+                      int(max_L), int(max_iter), int(restart))
+    h = _P()
+    its = np.zeros(len(gen), np.int32)
+    res = np.zeros(len(gen))
+    _check(lib().cbfm_build_ipcbf(mom.handle, C.byref(prm), _stream(stream), C.byref(h),
+                                  its.ctypes.data_as(C.c_void_p), res.ctypes.data_as(C.c_void_p)))
+    return CBF(h, mom.mesh), its, res
+
+
+def solve_matfree(mom: MomOperator, cbf: CBF, inc, tol=1e-6, max_iter=1000, restart=100, use_cmp=True, j_out=None,
+                  dirs=None, stream=None):
+    """cbfm_solve_matfree: the reduced CBFM solve with (C^JM)^H Z C^MJ applied
+    from the stored operator, Z_r never formed."""
+    import torch
+    inc, pi = _host(inc, np.float64)
+    inc = inc.reshape(-1, 6)
+    nrhs = len(inc)
+    pj = _dev(j_out, torch.complex128, nrhs * mom.n, "j") if j_out is not None else None
+    iters, relres, rcs, dirs, pd, nd = _solve_outputs(nrhs, dirs)
+    prm = SolverParams(float(tol), int(max_iter), int(restart), int(use_cmp), 0, 0.0, 0)
+    code = lib().cbfm_solve_matfree(mom.handle, cbf.handle, pi, nrhs, C.byref(prm), pj,
+                                    iters.ctypes.data_as(C.c_void_p), relres.ctypes.data_as(C.c_void_p), pd, nd,
+                                    rcs.ctypes.data_as(C.c_void_p), _stream(stream))
+    if code not in (0, -5):
+        _check(code)
+    return dict(iters=iters, relres=relres, rcs=rcs, status=STATUS.get(code, code))
 
 
 def solve(mesh: Mesh, medium: Medium, cbf: CBF, Zr, inc, tol=1e-6, max_iter=1000, restart=100,
           use_cmp=True, j_out=None, dirs=None, ldz=None, stream=None, raise_noconv=False, inner_fp32=False,
-          inner_tol=0.0, use_graph=False):
+          inner_tol=0.0, use_graph=False, cmp_mode=CMP_EXACT, cmp_inner_tol=0.0):
     """cbfm_solve.  Returns dict(iters, relres, rcs, status).  inner_fp32
     selects the mixed form (float Krylov cycles refined against the double
     residual, each cycle reducing it by inner_tol); use_graph replays the
@@ -374,8 +536,8 @@ def solve(mesh: Mesh, medium: Medium, cbf: CBF, Zr, inc, tol=1e-6, max_iter=1000
     else:
         pd, nd = None, 0
         rcs = np.zeros(nrhs)
-    prm = SolverParams(float(tol), int(max_iter), int(restart), int(bool(use_cmp)), int(bool(inner_fp32)),
-                       float(inner_tol), int(bool(use_graph)))
+    prm = SolverParams(float(tol), int(max_iter), int(restart), int(use_cmp), int(bool(inner_fp32)),
+                       float(inner_tol), int(bool(use_graph)), int(cmp_mode), float(cmp_inner_tol))
     code = lib().cbfm_solve(mesh.handle, C.byref(medium), cbf.handle, pz, ldz, pi, nrhs, C.byref(prm), pj,
                             iters.ctypes.data_as(C.c_void_p), relres.ctypes.data_as(C.c_void_p), pd, nd,
                             rcs.ctypes.data_as(C.c_void_p), _stream(stream))

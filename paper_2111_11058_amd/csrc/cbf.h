@@ -33,6 +33,10 @@ struct cbfm_cbf_s {
   hipEvent_t start = nullptr, done = nullptr;
   cbfm::DevBuf dinfo;
   int ninfo = 0;
+  // the inexact CMP's operator G^CBF D^CBF (2NL x 2NL) and D^CBF, formed on
+  // its first use (under mu)
+  bool inner_ready = false;
+  cbfm::DevBuf Gd, dinv;
   cbfm_cbf_s() = default;
   cbfm_cbf_s(const cbfm_cbf_s&) = delete;
   cbfm_cbf_s& operator=(const cbfm_cbf_s&) = delete;
@@ -45,11 +49,21 @@ namespace cbfm {
 // stream (the default) or leave it to the first use (serving workers, whose
 // requests already overlap one another).
 void async_cmp_on_this_thread(bool on);
+// x = GMRES solution of G^CBF x = y with the diagonal preconditioner
+// D^CBF (right preconditioning, x0 = 0) to the relative residual tol
+// (the paper's inexact inner CMP); y and x must not alias
+void cmp_inner_apply(cbfm_cbf_s* c, int64_t nrhs, const double2* y, double2* x, double tol, hipStream_t s);
 // x <- (G^CBF)^{-1} x in place, nrhs vectors of length 2 NL
 void cmp_apply_dev(cbfm_cbf_s* c, int64_t nrhs, double2* x, hipStream_t s);
 // B^{-1} (NL x NL, row-major), formed on first use
 const double2* cmp_inverse(cbfm_cbf_s* c, hipStream_t s);
 // Z_r of cbfm_project with an explicit scratch budget for the row panels
+// CBFs of every cell from whole-body current coefficient sets (IPCBF): X
+// holds S vectors of length 2 ne in the library's cell order, each
+// [alpha^M; alpha^J]; cell m keeps its rows (Sec. III-A) and they are
+// orthogonalised as in cbfm_build_cbf (Sec. III-B).  Synchronises s.
+cbfm_cbf_s* cbf_from_currents(const cbfm_mesh_s* m, const double2* X, int S, double delta_svd, int max_L,
+                              hipStream_t s);
 // (returns the number of row panels)
 int project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int precision, double2* Zr, int64_t ldz,
                 hipStream_t s, size_t budget);

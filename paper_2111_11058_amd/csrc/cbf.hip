@@ -31,6 +31,7 @@
 #include "cbf.h"
 #include "gemm.h"
 #include "gj.h"
+#include "solve.h"
 
 namespace cbfm {
 
@@ -520,7 +521,10 @@ static void invert_blocks(cbfm_cbf_s* c, hipStream_t s, bool async) {
 // (one batched call; the blocks off the diagonal are exact zeros and stay
 // so).  async: enqueue only, the pivot checks left in c->dinfo (the caller
 // marks the result pending); else checked, and c->factored set.
-static void cmp_factor(cbfm_cbf_s* c, hipStream_t s, bool async = false) {
+// B = (C^M)^H G C^J (NL x NL row-major) into Bout: cell by cell when no
+// triangle carries RWGs of two cells (the blocks off the diagonal are then
+// exact zeros), else through the RWG Gram times C^J of every cell.
+static void form_b(cbfm_cbf_s* c, double2* Bout, hipStream_t s) {
   const cbfm_mesh_s* m = c->mesh;
   const MeshHost& h = m->h;
   const int64_t NL = c->NL, ne = h.ne;
@@ -534,17 +538,14 @@ static void cmp_factor(cbfm_cbf_s* c, hipStream_t s, bool async = false) {
                        m->tminus.as<int32_t>(), m->aplus.as<int32_t>(), m->aminus.as<int32_t>(),
                        m->tri_edge.as<int32_t>(), m->tri_sign.as<int32_t>(), m->length.as<double>(), GCc.as<double2>());
     CBFM_HIP(hipGetLastError());
-    c->Binv.alloc(NL * NL * sizeof(double2));
-    CBFM_HIP(hipMemsetAsync(c->Binv.p, 0, NL * NL * sizeof(double2), s));
+    CBFM_HIP(hipMemsetAsync(Bout, 0, NL * NL * sizeof(double2), s));
     std::vector<GemmDesc> ds;
     for (int a = 0; a < nb; ++a) {
       const int64_t Na = h.cell_off[a + 1] - h.cell_off[a], La = c->L[a];
       ds.push_back(gemm(c->CM.as<double2>() + c->coff[a], La, OP_C, GCc.as<double2>() + c->coff[a], La, OP_N,
-                        c->Binv.as<double2>() + c->off[a] * NL + c->off[a], NL, La, La, Na));
+                        Bout + c->off[a] * NL + c->off[a], NL, La, La, Na));
     }
     zgemm_batched(ds, s);
-    invert_blocks(c, s, async);
-    if (!async) c->factored = true;
     return;
   }
   CBFM_REQUIRE(ne <= 65535, CBFM_E_ARG, "G^CBF coupling cells: at most 65535 RWGs");
@@ -556,14 +557,24 @@ static void cmp_factor(cbfm_cbf_s* c, hipStream_t s, bool async = false) {
                      m->tplus.as<int32_t>(), m->tminus.as<int32_t>(), m->aplus.as<int32_t>(), m->aminus.as<int32_t>(),
                      m->tri_edge.as<int32_t>(), m->tri_sign.as<int32_t>(), m->length.as<double>(), GC.as<double2>());
   CBFM_HIP(hipGetLastError());
-  c->Binv.alloc(NL * NL * sizeof(double2));
   std::vector<GemmDesc> ds;
   for (int a = 0; a < h.nblocks; ++a) {
     const int64_t Na = h.cell_off[a + 1] - h.cell_off[a];
     ds.push_back(gemm(c->CM.as<double2>() + c->coff[a], c->L[a], OP_C, GC.as<double2>() + h.cell_off[a] * NL, NL,
-                      OP_N, c->Binv.as<double2>() + c->off[a] * NL, NL, c->L[a], NL, Na));
+                      OP_N, Bout + c->off[a] * NL, NL, c->L[a], NL, Na));
   }
   zgemm_batched(ds, s);
+}
+
+static void cmp_factor(cbfm_cbf_s* c, hipStream_t s, bool async = false) {
+  const int64_t NL = c->NL;
+  c->Binv.alloc(NL * NL * sizeof(double2));
+  form_b(c, c->Binv.as<double2>(), s);
+  if (c->blockdiag) {
+    invert_blocks(c, s, async);
+    if (!async) c->factored = true;
+    return;
+  }
   CBFM_REQUIRE(NL <= 65535, CBFM_E_ARG, "G^CBF coupling cells: at most 65535 CBFs per current");
   if (async) {
     c->dinfo.alloc(sizeof(int32_t));
@@ -573,6 +584,69 @@ static void cmp_factor(cbfm_cbf_s* c, hipStream_t s, bool async = false) {
   }
   gj_inverse_batched(c->Binv.as<double2>(), NL * NL, (int)NL, 1, "G^CBF", s);
   c->factored = true;
+}
+
+// The operator of the inexact CMP: Gd = G^CBF D^CBF (2NL x 2NL, row-major)
+// with G^CBF = blkdiag(-B^H, B) and D^CBF = diag(1 / [G^CBF]_jj) (1 where
+// that diagonal is 0), and D^CBF itself (row i = 0 writes it).
+__global__ void inner_operator_kernel(const double2* __restrict__ B, int64_t NL, double2* __restrict__ Gd,
+                                      double2* __restrict__ dinv) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y, n = 2 * NL;
+  if (j >= n) return;
+  double2 g = make_double2(0.0, 0.0), dg;
+  if (j < NL) {
+    const double2 b = B[j * NL + j];
+    dg = make_double2(-b.x, b.y);  // -conj(B_jj)
+    if (i < NL) {
+      const double2 e = B[j * NL + i];  // (-B^H)_ij = -conj(B_ji)
+      g = make_double2(-e.x, e.y);
+    }
+  } else {
+    dg = B[(j - NL) * NL + (j - NL)];
+    if (i >= NL) g = B[(i - NL) * NL + (j - NL)];
+  }
+  const double den = dg.x * dg.x + dg.y * dg.y;
+  const double2 d = den > 0 ? make_double2(dg.x / den, -dg.y / den) : make_double2(1.0, 0.0);
+  Gd[i * n + j] = make_double2(g.x * d.x - g.y * d.y, g.x * d.y + g.y * d.x);
+  if (i == 0) dinv[j] = d;
+}
+
+__global__ void diag_times_kernel(const double2* __restrict__ d, const double2* __restrict__ z, double2* __restrict__ x,
+                                  int64_t n, int64_t nv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (i >= n || c >= nv) return;
+  const double2 a = d[i], b = z[c * n + i];
+  x[c * n + i] = make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+void cmp_inner_apply(cbfm_cbf_s* c, int64_t nrhs, const double2* y, double2* x, double tol, hipStream_t s) {
+  const int64_t NL = c->NL, n = 2 * NL;
+  if (nrhs == 0 || NL == 0) return;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!c->inner_ready) {
+      CBFM_REQUIRE(n <= 65535, CBFM_E_ARG, "inexact CMP: at most 32767 CBFs per current");
+      Scratch B((size_t)NL * NL * sizeof(double2), s);
+      form_b(c, B.as<double2>(), s);
+      c->Gd.alloc((size_t)n * n * sizeof(double2));
+      c->dinv.alloc((size_t)n * sizeof(double2));
+      hipLaunchKernelGGL(inner_operator_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, s,
+                         B.as<double2>(), NL, c->Gd.as<double2>(), c->dinv.as<double2>());
+      CBFM_HIP(hipGetLastError());
+      c->inner_ready = true;
+    }
+  }
+  // GMRES on (G^CBF D^CBF) z = y, x = D^CBF z
+  GmresSpec sp;
+  sp.tol = tol;
+  sp.restart = std::min<int64_t>(n, 500);
+  sp.max_iter = 4 * n;
+  DenseOp op(c->Gd.as<double2>(), n, nullptr, 0);
+  Scratch z((size_t)nrhs * n * sizeof(double2), s);
+  (void)gmres_run(op, n, nrhs, y, z.as<double2>(), sp, s);
+  hipLaunchKernelGGL(diag_times_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, s,
+                     c->dinv.as<double2>(), z.as<double2>(), x, n, nrhs);
+  CBFM_HIP(hipGetLastError());
 }
 
 // A side stream per device and host thread (default priority) for work that
@@ -722,6 +796,185 @@ cbfm_cbf_s::~cbfm_cbf_s() {
   }
 }
 
+// CBFs of every cell from its current coefficient sets J_m = [J^M_m; J^J_m]
+// (primary or IPCBF), given as (J^M_m)^H and (J^J_m)^H in QA: column-major
+// S x Nmax per cell and current (cell b's at 2 b and 2 b + 1), zero beyond
+// the cell's N_m columns.  The dual orthogonalisation of Sec. III-B: QR of
+// both (R only), the core X = R_M G_m R_J^H, its one-sided Jacobi SVD,
+// L_m = #{sigma_i / sigma_1 >= delta_svd} (at most max_L), C^M = J^M U_L,
+// C^J = J^J V_L.  share: every cell takes cell 0's CBFs (arrays of
+// translated copies).  The CMP inverse is queued on the side stream unless
+// this thread disabled that.  Returns a new handle; QA is overwritten.
+static cbfm_cbf_s* orthogonalise(const cbfm_mesh_s* m, double2* QA_p, int S, int Nmax, const std::vector<int32_t>& hN,
+                                 const int32_t* dN_p, const CellJob* djobs, double delta_svd, int max_L, bool share,
+                                 hipStream_t s) {
+  const MeshHost& h = m->h;
+  const int nb = h.nblocks;
+  const int rk = std::min(S, Nmax);
+  Scratch info((size_t)nb * sizeof(int32_t), s);  // per cell: the Jacobi SVD ran out of sweeps
+  std::vector<int32_t> hinfo(nb);
+  Scratch Rf((size_t)nb * 2 * rk * Nmax * sizeof(double2), s);  // per cell R_M, then R_J
+  hipLaunchKernelGGL(cell_qr_kernel, dim3(2 * nb), dim3(1024), (size_t)S * sizeof(double2), s, QA_p, S,
+                     Nmax, dN_p, rk, Rf.as<double2>());
+  CBFM_HIP(hipGetLastError());
+  // core X = R_M G_m R_J^H (column-major rk x rk), computed as its row-major
+  // transpose conj(R_J) G_m^T R_M^T = -conj(R_J) G_m R_M^T (G_m antisymmetric)
+  Scratch Gm((size_t)nb * Nmax * Nmax * sizeof(double2), s);
+  Scratch T2((size_t)nb * Nmax * rk * sizeof(double2), s);
+  Scratch core((size_t)nb * rk * rk * sizeof(double2), s);
+  hipLaunchKernelGGL(cell_gram_kernel, dim3((Nmax + 255) / 256, Nmax, nb), dim3(256), 0, s, djobs, Nmax,
+                     m->tplus.as<int32_t>(), m->tminus.as<int32_t>(), m->aplus.as<int32_t>(), m->aminus.as<int32_t>(),
+                     m->tri_edge.as<int32_t>(), m->tri_sign.as<int32_t>(), m->length.as<double>(), Gm.as<double2>());
+  std::vector<GemmDesc> d1, d2;
+  for (int b = 0; b < nb; ++b) {
+    const int Nb = hN[b];
+    const double2* R = Rf.as<double2>() + (size_t)b * 2 * rk * Nmax;
+    double2* G = Gm.as<double2>() + (size_t)b * Nmax * Nmax;
+    double2* t2 = T2.as<double2>() + (size_t)b * Nmax * rk;
+    d1.push_back(gemm(G, Nb, OP_N, R, Nmax, OP_T, t2, rk, Nb, rk, Nb));
+    d2.push_back(gemm(R + (size_t)rk * Nmax, Nmax, OP_R, t2, rk, OP_N, core.as<double2>() + (size_t)b * rk * rk, rk,
+                      rk, rk, Nb, -1.0));
+  }
+  CBFM_HIP(hipGetLastError());
+  zgemm_batched(d1, s);
+  zgemm_batched(d2, s);
+  // SVD of the cores: right singular vectors U~ and U~ S^{-1}
+  Scratch sv((size_t)nb * rk * sizeof(double), s);
+  Scratch Ut((size_t)nb * rk * rk * sizeof(double2), s);
+  Scratch Uts((size_t)nb * rk * rk * sizeof(double2), s);
+  {
+    const int ncmax = std::min(Nmax, rk);
+    const size_t lds = (size_t)ncmax * ncmax * sizeof(double2) + (size_t)ncmax * (sizeof(double2) + 12);
+    const double tol = std::sqrt((double)ncmax) * 2.220446049250313e-16;
+    const int max_sweeps = 60;
+    if (lds <= core_svd_lds_limit()) {
+      hipLaunchKernelGGL(core_svd_kernel<true>, dim3(nb), dim3(1024), lds, s, core.as<double2>(), rk,
+                         dN_p, nullptr, tol, max_sweeps, sv.as<double>(), Ut.as<double2>(),
+                         Uts.as<double2>(), info.as<int32_t>());
+    } else {
+      Scratch work((size_t)nb * rk * rk * sizeof(double2), s);
+      hipLaunchKernelGGL(core_svd_kernel<false>, dim3(nb), dim3(1024), (size_t)ncmax * (sizeof(double2) + 12), s,
+                         core.as<double2>(), rk, dN_p, work.as<double2>(), tol, max_sweeps,
+                         sv.as<double>(), Ut.as<double2>(), Uts.as<double2>(), info.as<int32_t>());
+    }
+    CBFM_HIP(hipGetLastError());
+  }
+  std::vector<double> hs((size_t)nb * rk);
+  CBFM_HIP(hipMemcpyAsync(hs.data(), sv.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CBFM_HIP(hipMemcpyAsync(hinfo.data(), info.p, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  CBFM_HIP(hipStreamSynchronize(s));
+  for (int b = 0; b < nb; ++b)
+    CBFM_REQUIRE(hinfo[b] == 0, CBFM_E_HIP, "cell " + std::to_string(b) + ": Jacobi SVD did not converge");
+  auto* c = new cbfm_cbf_s();
+  try {
+    c->mesh = m;
+    c->L.resize(nb);
+    for (int b = 0; b < nb; ++b) {
+      const double* sb = &hs[(size_t)b * rk];
+      int L = 0;
+      const int Nb = hN[b];
+      while (L < rk && L < Nb && sb[L] > 0 && sb[L] >= delta_svd * sb[0]) ++L;
+      if (max_L > 0) L = std::min(L, max_L);
+      CBFM_REQUIRE(L > 0, CBFM_E_RANK, "cell " + std::to_string(b) + " keeps no CBF");
+      c->L[b] = L;
+      c->sigma.insert(c->sigma.end(), sb, sb + L);
+    }
+    // translated copies of one cell: the plane waves on cell b are those on
+    // cell 0 times one phase per wave, so its currents are cell 0's times
+    // a diagonal phase matrix and its CBFs span cell 0's spaces; every
+    // cell takes cell 0's (count, singular values and vectors)
+    if (share) {
+      c->shared = true;
+      c->sigma.resize((size_t)c->L[0] * nb);
+      for (int b = 1; b < nb; ++b) {
+        c->L[b] = c->L[0];
+        std::copy(c->sigma.begin(), c->sigma.begin() + c->L[0], c->sigma.begin() + (size_t)b * c->L[0]);
+      }
+    }
+    cbf_finish(c);
+    c->CM.alloc(std::max<int64_t>(1, c->coff[nb]) * sizeof(double2));
+    c->CJ.alloc(std::max<int64_t>(1, c->coff[nb]) * sizeof(double2));
+    // C^J = R_J^H V_L with V = U~;  C^M = R_M^H U_L with U = X V S^{-1} = X U~ S^{-1}
+    Scratch W((size_t)std::max<int64_t>(1, c->coff[nb]) * sizeof(double2), s);
+    std::vector<GemmDesc> d3, d4;
+    for (int b = 0; b < nb; ++b) {
+      const int Nb = hN[b], nc = std::min(Nb, rk), L = c->L[b];
+      const double2* R = Rf.as<double2>() + (size_t)b * 2 * rk * Nmax;
+      const double2* ub = Ut.as<double2>() + (size_t)b * rk * rk;
+      const double2* usb = Uts.as<double2>() + (size_t)b * rk * rk;
+      double2* wb = W.as<double2>() + c->coff[b];  // nc x L row-major (nc <= N_b)
+      d3.push_back(gemm(core.as<double2>() + (size_t)b * rk * rk, rk, OP_T, usb, rk, OP_T, wb, L, nc, L, nc));
+      d3.push_back(gemm(R + (size_t)rk * Nmax, Nmax, OP_C, ub, rk, OP_T, c->CJ.as<double2>() + c->coff[b], L, Nb, L,
+                        nc));
+      d4.push_back(gemm(R, Nmax, OP_C, wb, L, OP_N, c->CM.as<double2>() + c->coff[b], L, Nb, L, nc));
+    }
+    zgemm_batched(d3, s);
+    zgemm_batched(d4, s);
+    if (c->shared) {
+      const size_t blk = (size_t)(c->coff[1] - c->coff[0]) * sizeof(double2);
+      for (int b = 1; b < nb; ++b) {
+        CBFM_HIP(hipMemcpyAsync(c->CM.as<double2>() + c->coff[b], c->CM.as<double2>(), blk,
+                                hipMemcpyDeviceToDevice, s));
+        CBFM_HIP(hipMemcpyAsync(c->CJ.as<double2>() + c->coff[b], c->CJ.as<double2>(), blk,
+                                hipMemcpyDeviceToDevice, s));
+      }
+    }
+    if (t_async_cmp) cmp_factor_async(c, s);
+  } catch (...) {
+    delete c;
+    throw;
+  }
+  return c;
+}
+
+// From whole-body current coefficients (IPCBF): vector c of X (length 2 ne,
+// the library's cell order) holds [alpha^M; alpha^J] of wave c; cell b's
+// rows give (J^M_b)^H and (J^J_b)^H, column-major S x Nmax (QA layout).
+__global__ void pack_global_kernel(const double2* __restrict__ X, int64_t ne, int S, const int64_t* __restrict__ cell_off,
+                                   int Nmax, double2* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y, b = blockIdx.z >> 1, w = blockIdx.z & 1;
+  if (r >= S) return;
+  const int64_t c0 = cell_off[b], N = cell_off[b + 1] - c0;
+  double2 x = make_double2(0.0, 0.0);
+  if (i < N) {
+    x = X[(int64_t)r * 2 * ne + (int64_t)w * ne + c0 + i];
+    x.y = -x.y;
+  }
+  out[((int64_t)(2 * b + w) * Nmax + i) * S + r] = x;
+}
+
+cbfm_cbf_s* cbfm::cbf_from_currents(const cbfm_mesh_s* m, const double2* X, int S, double delta_svd, int max_L,
+                                    hipStream_t s) {
+  const MeshHost& h = m->h;
+  const int nb = h.nblocks;
+  int Nmax = 0;
+  std::vector<int32_t> hN(nb);
+  for (int b = 0; b < nb; ++b) {
+    hN[b] = (int32_t)(h.cell_off[b + 1] - h.cell_off[b]);
+    Nmax = std::max<int>(Nmax, hN[b]);
+  }
+  // per cell its RWGs (the segment of the cell-order table) for the Gram
+  std::vector<CellJob> jobs(nb);
+  for (int b = 0; b < nb; ++b) {
+    jobs[b] = CellJob{};
+    jobs[b].N = hN[b];
+    jobs[b].edges = m->perm.as<int32_t>() + h.cell_off[b];
+  }
+  Scratch dN((size_t)nb * sizeof(int32_t), s), djobs((size_t)nb * sizeof(CellJob), s),
+      dco((size_t)(nb + 1) * sizeof(int64_t), s);
+  CBFM_HIP(hipMemcpyAsync(dN.p, hN.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  CBFM_HIP(hipMemcpyAsync(djobs.p, jobs.data(), nb * sizeof(CellJob), hipMemcpyHostToDevice, s));
+  CBFM_HIP(hipMemcpyAsync(dco.p, h.cell_off.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  Scratch QA((size_t)nb * 2 * S * Nmax * sizeof(double2), s);
+  hipLaunchKernelGGL(pack_global_kernel, dim3((S + 255) / 256, Nmax, 2 * nb), dim3(256), 0, s, X, h.ne, S,
+                     dco.as<int64_t>(), Nmax, QA.as<double2>());
+  CBFM_HIP(hipGetLastError());
+  cbfm_cbf_s* c = orthogonalise(m, QA.as<double2>(), S, Nmax, hN, dN.as<int32_t>(), djobs.as<CellJob>(), delta_svd,
+                                max_L, false, s);
+  CBFM_HIP(hipStreamSynchronize(s));  // host tables of this frame
+  return c;
+}
+
 extern "C" {
 
 cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_params* prm, void* stream,
@@ -837,10 +1090,7 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
     CBFM_HIP(hipGetLastError());
     // Z_mm J_m = V_m for every cell (Gauss-Jordan on the augmented systems)
     gj_solve_batched(Aug.as<double2>(), (int64_t)n * ldz, ldz, n, ldz, nb, "Z_mm of cell", s);
-    Scratch info((size_t)nb * sizeof(int32_t), s);  // per cell: the Jacobi SVD ran out of sweeps
-    std::vector<int32_t> hinfo(nb);
-    // QR of (J^M)^H and (J^J)^H (column-major S x Nmax, zero-padded): R only
-    const int rk = std::min(S, Nmax);
+    // QR of (J^M)^H and (J^J)^H (column-major S x Nmax, zero-padded)
     std::vector<int32_t> hN(nb);
     for (int b = 0; b < nb; ++b) hN[b] = (int32_t)cs[b].edges.size();
     Scratch dN((size_t)nb * sizeof(int32_t), s);
@@ -848,117 +1098,9 @@ cbfm_status cbfm_build_cbf(cbfm_mesh m, const cbfm_medium* med, const cbfm_cbf_p
     Scratch QA((size_t)nb * 2 * S * Nmax * sizeof(double2), s);
     hipLaunchKernelGGL(pack_jh_kernel, dim3((S + 255) / 256, Nmax, 2 * nb), dim3(256), 0, s, Aug.as<double2>(), n,
                        S, dN.as<int32_t>(), Nmax, QA.as<double2>());
-    Scratch Rf((size_t)nb * 2 * rk * Nmax * sizeof(double2), s);  // per cell R_M, then R_J
-    hipLaunchKernelGGL(cell_qr_kernel, dim3(2 * nb), dim3(1024), (size_t)S * sizeof(double2), s, QA.as<double2>(), S,
-                       Nmax, dN.as<int32_t>(), rk, Rf.as<double2>());
     CBFM_HIP(hipGetLastError());
-    // core X = R_M G_m R_J^H (column-major rk x rk), computed as its row-major
-    // transpose conj(R_J) G_m^T R_M^T = -conj(R_J) G_m R_M^T (G_m antisymmetric)
-    Scratch Gm((size_t)nb * Nmax * Nmax * sizeof(double2), s);
-    Scratch T2((size_t)nb * Nmax * rk * sizeof(double2), s);
-    Scratch core((size_t)nb * rk * rk * sizeof(double2), s);
-    hipLaunchKernelGGL(cell_gram_kernel, dim3((Nmax + 255) / 256, Nmax, nb), dim3(256), 0, s, djobs, Nmax,
-                       m->tplus.as<int32_t>(), m->tminus.as<int32_t>(), m->aplus.as<int32_t>(), m->aminus.as<int32_t>(),
-                       m->tri_edge.as<int32_t>(), m->tri_sign.as<int32_t>(), m->length.as<double>(), Gm.as<double2>());
-    std::vector<GemmDesc> d1, d2;
-    for (int b = 0; b < nb; ++b) {
-      const int Nb = hN[b];
-      const double2* R = Rf.as<double2>() + (size_t)b * 2 * rk * Nmax;
-      double2* G = Gm.as<double2>() + (size_t)b * Nmax * Nmax;
-      double2* t2 = T2.as<double2>() + (size_t)b * Nmax * rk;
-      d1.push_back(gemm(G, Nb, OP_N, R, Nmax, OP_T, t2, rk, Nb, rk, Nb));
-      d2.push_back(gemm(R + (size_t)rk * Nmax, Nmax, OP_R, t2, rk, OP_N, core.as<double2>() + (size_t)b * rk * rk, rk,
-                        rk, rk, Nb, -1.0));
-    }
-    CBFM_HIP(hipGetLastError());
-    zgemm_batched(d1, s);
-    zgemm_batched(d2, s);
-    // SVD of the cores: right singular vectors U~ and U~ S^{-1}
-    Scratch sv((size_t)nb * rk * sizeof(double), s);
-    Scratch Ut((size_t)nb * rk * rk * sizeof(double2), s);
-    Scratch Uts((size_t)nb * rk * rk * sizeof(double2), s);
-    {
-      const int ncmax = std::min(Nmax, rk);
-      const size_t lds = (size_t)ncmax * ncmax * sizeof(double2) + (size_t)ncmax * (sizeof(double2) + 12);
-      const double tol = std::sqrt((double)ncmax) * 2.220446049250313e-16;
-      const int max_sweeps = 60;
-      if (lds <= core_svd_lds_limit()) {
-        hipLaunchKernelGGL(core_svd_kernel<true>, dim3(nb), dim3(1024), lds, s, core.as<double2>(), rk,
-                           dN.as<int32_t>(), nullptr, tol, max_sweeps, sv.as<double>(), Ut.as<double2>(),
-                           Uts.as<double2>(), info.as<int32_t>());
-      } else {
-        Scratch work((size_t)nb * rk * rk * sizeof(double2), s);
-        hipLaunchKernelGGL(core_svd_kernel<false>, dim3(nb), dim3(1024), (size_t)ncmax * (sizeof(double2) + 12), s,
-                           core.as<double2>(), rk, dN.as<int32_t>(), work.as<double2>(), tol, max_sweeps,
-                           sv.as<double>(), Ut.as<double2>(), Uts.as<double2>(), info.as<int32_t>());
-      }
-      CBFM_HIP(hipGetLastError());
-    }
-    std::vector<double> hs((size_t)nb * rk);
-    CBFM_HIP(hipMemcpyAsync(hs.data(), sv.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    CBFM_HIP(hipMemcpyAsync(hinfo.data(), info.p, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    CBFM_HIP(hipStreamSynchronize(s));
-    for (int b = 0; b < nb; ++b)
-      CBFM_REQUIRE(hinfo[b] == 0, CBFM_E_HIP, "cell " + std::to_string(b) + ": Jacobi SVD did not converge");
-    auto* c = new cbfm_cbf_s();
-    try {
-      c->mesh = m;
-      c->L.resize(nb);
-      for (int b = 0; b < nb; ++b) {
-        const double* sb = &hs[(size_t)b * rk];
-        int L = 0;
-        const int Nb = hN[b];
-        while (L < rk && L < Nb && sb[L] > 0 && sb[L] >= prm->delta_svd * sb[0]) ++L;
-        if (prm->max_L > 0) L = std::min(L, prm->max_L);
-        CBFM_REQUIRE(L > 0, CBFM_E_RANK, "cell " + std::to_string(b) + " keeps no CBF");
-        c->L[b] = L;
-        c->sigma.insert(c->sigma.end(), sb, sb + L);
-      }
-      // translated copies of one cell: the plane waves on cell b are those on
-      // cell 0 times one phase per wave, so its currents are cell 0's times
-      // a diagonal phase matrix and its CBFs span cell 0's spaces; every
-      // cell takes cell 0's (count, singular values and vectors)
-      if (m->translated) {
-        c->shared = true;
-        c->sigma.resize((size_t)c->L[0] * nb);
-        for (int b = 1; b < nb; ++b) {
-          c->L[b] = c->L[0];
-          std::copy(c->sigma.begin(), c->sigma.begin() + c->L[0], c->sigma.begin() + (size_t)b * c->L[0]);
-        }
-      }
-      cbf_finish(c);
-      c->CM.alloc(std::max<int64_t>(1, c->coff[nb]) * sizeof(double2));
-      c->CJ.alloc(std::max<int64_t>(1, c->coff[nb]) * sizeof(double2));
-      // C^J = R_J^H V_L with V = U~;  C^M = R_M^H U_L with U = X V S^{-1} = X U~ S^{-1}
-      Scratch W((size_t)std::max<int64_t>(1, c->coff[nb]) * sizeof(double2), s);
-      std::vector<GemmDesc> d3, d4;
-      for (int b = 0; b < nb; ++b) {
-        const int Nb = hN[b], nc = std::min(Nb, rk), L = c->L[b];
-        const double2* R = Rf.as<double2>() + (size_t)b * 2 * rk * Nmax;
-        const double2* ub = Ut.as<double2>() + (size_t)b * rk * rk;
-        const double2* usb = Uts.as<double2>() + (size_t)b * rk * rk;
-        double2* wb = W.as<double2>() + c->coff[b];  // nc x L row-major (nc <= N_b)
-        d3.push_back(gemm(core.as<double2>() + (size_t)b * rk * rk, rk, OP_T, usb, rk, OP_T, wb, L, nc, L, nc));
-        d3.push_back(gemm(R + (size_t)rk * Nmax, Nmax, OP_C, ub, rk, OP_T, c->CJ.as<double2>() + c->coff[b], L, Nb, L,
-                          nc));
-        d4.push_back(gemm(R, Nmax, OP_C, wb, L, OP_N, c->CM.as<double2>() + c->coff[b], L, Nb, L, nc));
-      }
-      zgemm_batched(d3, s);
-      zgemm_batched(d4, s);
-      if (c->shared) {
-        const size_t blk = (size_t)(c->coff[1] - c->coff[0]) * sizeof(double2);
-        for (int b = 1; b < nb; ++b) {
-          CBFM_HIP(hipMemcpyAsync(c->CM.as<double2>() + c->coff[b], c->CM.as<double2>(), blk,
-                                  hipMemcpyDeviceToDevice, s));
-          CBFM_HIP(hipMemcpyAsync(c->CJ.as<double2>() + c->coff[b], c->CJ.as<double2>(), blk,
-                                  hipMemcpyDeviceToDevice, s));
-        }
-      }
-      if (t_async_cmp) cmp_factor_async(c, s);
-    } catch (...) {
-      delete c;
-      throw;
-    }
+    cbfm_cbf_s* c = orthogonalise(m, QA.as<double2>(), S, Nmax, hN, dN.as<int32_t>(), djobs, prm->delta_svd,
+                                  prm->max_L, m->translated, s);
     *out = c;
   });
 }
@@ -1026,11 +1168,24 @@ cbfm_status cbfm_cbf_export(cbfm_cbf c, void* CM, void* CJ) {
 void cbfm_cbf_free(cbfm_cbf c) { delete c; }
 
 cbfm_status cbfm_cmp_apply(cbfm_cbf c, int64_t nrhs, const void* y, void* x, void* stream) {
+  return cbfm_cmp_apply_ex(c, nrhs, y, x, CBFM_CMP_EXACT, 0.0, stream);
+}
+
+cbfm_status cbfm_cmp_apply_ex(cbfm_cbf c, int64_t nrhs, const void* y, void* x, int32_t mode, double inner_tol,
+                              void* stream) {
   return guarded([&] {
     CBFM_REQUIRE(c && y && x && nrhs >= 0, CBFM_E_ARG, "bad argument");
+    CBFM_REQUIRE(mode == CBFM_CMP_EXACT || mode == CBFM_CMP_INNER_GMRES, CBFM_E_ARG, "unknown CMP mode");
+    CBFM_REQUIRE(mode == CBFM_CMP_EXACT || (inner_tol >= 0 && inner_tol < 1), CBFM_E_ARG, "inner_tol outside [0, 1)");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (x != y)
-      CBFM_HIP(hipMemcpyAsync(x, y, (size_t)nrhs * 2 * c->NL * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    const size_t bytes = (size_t)nrhs * 2 * c->NL * sizeof(double2);
+    if (mode == CBFM_CMP_INNER_GMRES) {
+      Scratch yc(bytes, s);  // (x and y may alias)
+      CBFM_HIP(hipMemcpyAsync(yc.p, y, bytes, hipMemcpyDeviceToDevice, s));
+      cmp_inner_apply(c, nrhs, yc.as<double2>(), static_cast<double2*>(x), inner_tol > 0 ? inner_tol : 1e-5, s);
+      return;
+    }
+    if (x != y) CBFM_HIP(hipMemcpyAsync(x, y, bytes, hipMemcpyDeviceToDevice, s));
     cmp_apply_dev(c, nrhs, static_cast<double2*>(x), s);
   });
 }

@@ -22,6 +22,8 @@
 // the bounded remainders by the 7-point rule.  K of a coplanar pair is 0.
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <type_traits>
 
 #include "internal.h"
@@ -658,23 +660,31 @@ __global__ void __launch_bounds__(64) near_outer_kernel(const double* __restrict
     }
 }
 
+// Bytes of the near-pair stage's intermediate values for nnear pairs.
+size_t near_buffer_bytes(int64_t nnear) { return (size_t)nnear * 7 * NEAR_VALS * sizeof(cd); }
+
+// The two near-pair launches; their intermediate values go to buf_in
+// (near_buffer_bytes(nnear) bytes of device memory), or to stream-ordered
+// scratch when buf_in is NULL.
 template <typename R>
 static void near_stage(const cbfm_mesh_s* m, const FillConsts& fc, const NearPair* near, int64_t nnear, cx<R>* out,
-                       int64_t op_stride, int64_t ldl, hipStream_t s, const NearOut* outs = nullptr, int cell0 = 0) {
+                       int64_t op_stride, int64_t ldl, hipStream_t s, const NearOut* outs = nullptr, int cell0 = 0,
+                       void* buf_in = nullptr) {
   if (nnear == 0) return;
-  Scratch buf((size_t)nnear * 7 * NEAR_VALS * sizeof(cd), s);
+  Scratch own(buf_in ? 0 : near_buffer_bytes(nnear), s);
+  cd* buf = static_cast<cd*>(buf_in ? buf_in : own.p);
   hipLaunchKernelGGL(near_inner_kernel, dim3((unsigned)((nnear * 7 + 63) / 64)), dim3(64), 0, s, m->tri_xyz.as<double>(),
-                     m->area.as<double>(), near, nnear, fc, buf.as<cd>());
+                     m->area.as<double>(), near, nnear, fc, buf);
   CBFM_HIP(hipGetLastError());
   hipLaunchKernelGGL((near_outer_kernel<R>), dim3((unsigned)((nnear + 63) / 64)), dim3(64), 0, s, m->tri_xyz.as<double>(),
-                     m->area.as<double>(), m->c64.as<double>(), m->h.nt, near, nnear, fc, buf.as<cd>(), out, op_stride,
+                     m->area.as<double>(), m->c64.as<double>(), m->h.nt, near, nnear, fc, buf, out, op_stride,
                      ldl, outs, cell0);
   CBFM_HIP(hipGetLastError());
 }
 
 void fill_local(const cbfm_mesh_s* m, const Media& md, int precision, int layout,
                 const int32_t* rowTris, int64_t nrt, const int32_t* colTris, int64_t nct,
-                const NearPair* near, int64_t nnear, void* local, hipStream_t s) {
+                const NearPair* near, int64_t nnear, void* local, hipStream_t s, void* near_buf) {
   const FillConsts fc = make_consts(md, layout);
   const int64_t ldl = 3 * nct, op_stride = 3 * nrt * ldl;
   const bool lossy = md.k2i != 0.0;
@@ -705,9 +715,9 @@ void fill_local(const cbfm_mesh_s* m, const Media& md, int precision, int layout
   }
   TimedLaunch tn(T_FILL_NEAR, s, (double)nnear);  // work: near pairs
   if (precision == CBFM_FP64)
-    near_stage(m, fc, near, nnear, static_cast<cx<double>*>(local), op_stride, ldl, s);
+    near_stage(m, fc, near, nnear, static_cast<cx<double>*>(local), op_stride, ldl, s, nullptr, 0, near_buf);
   else
-    near_stage(m, fc, near, nnear, static_cast<cx<float>*>(local), op_stride, ldl, s);
+    near_stage(m, fc, near, nnear, static_cast<cx<float>*>(local), op_stride, ldl, s, nullptr, 0, near_buf);
 }
 
 void fill_near(const cbfm_mesh_s* m, const Media& md, int precision, int layout, const NearPair* near, int64_t nnear,
@@ -890,71 +900,141 @@ void rhs_launch(const cbfm_mesh_s* m, const Media& md, double eta0, const double
 
 using namespace cbfm;
 
+namespace cbfm {
+
+// The fill of RWG rows row0..row0+nrow-1 against columns col0..col0+ncol-1
+// into out (3 matrices, ld), after the arguments are checked.  Its device
+// workspace (index tables, near-pair intermediates, triangle-local blocks,
+// each 256-byte aligned) is carved from ws (ws_bytes long) when given, else
+// taken from stream-ordered scratch.  Synchronises s (host staging).
+static void fill_ranges(const cbfm_mesh_s* m, const Media& md, int precision, int64_t row0, int64_t nrow, int64_t col0,
+                        int64_t ncol, int layout, void* out_dev, int64_t ld, hipStream_t s, char* ws, size_t ws_bytes) {
+  const MeshHost& h = m->h;
+  // triangles touching the ranges and their positions
+  auto tris_of = [&](int64_t e0, int64_t n, std::vector<int32_t>& list, std::vector<int32_t>& pos) {
+    pos.assign(h.nt, -1);
+    for (int64_t e = e0; e < e0 + n; ++e) {
+      pos[h.tplus[e]] = 0;
+      pos[h.tminus[e]] = 0;
+    }
+    list.clear();
+    for (int64_t t = 0; t < h.nt; ++t)
+      if (pos[t] == 0) {
+        pos[t] = (int32_t)list.size();
+        list.push_back((int32_t)t);
+      }
+  };
+  std::vector<int32_t> rl, rp, cl, cp;
+  tris_of(row0, nrow, rl, rp);
+  tris_of(col0, ncol, cl, cp);
+  std::vector<NearPair> nl;
+  for (const NearPair& q : h.near)
+    if (rp[q.p] >= 0 && cp[q.q] >= 0) nl.push_back({q.p, q.q, rp[q.p], cp[q.q], q.coplanar, 0});
+  std::vector<int32_t> re(nrow), ce(ncol);
+  for (int64_t r = 0; r < nrow; ++r) re[r] = (int32_t)(row0 + r);
+  for (int64_t c = 0; c < ncol; ++c) ce[c] = (int32_t)(col0 + c);
+  const int64_t nrt = rl.size(), nct = cl.size();
+  const size_t esz = precision == CBFM_FP64 ? 16 : 8;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t ib = sizeof(int32_t) * (rl.size() + cl.size() + rp.size() + cp.size() + re.size() + ce.size()) +
+                    sizeof(NearPair) * nl.size();
+  const size_t nb = near_buffer_bytes((int64_t)nl.size()), lb = 3 * 9 * (size_t)nrt * nct * esz;
+  const size_t total = al(ib) + al(nb) + al(lb);
+  std::unique_ptr<Scratch> own;
+  if (ws) {
+    CBFM_REQUIRE(total <= ws_bytes, CBFM_E_ARG,
+                 "the fill of these ranges needs " + std::to_string(total) + " bytes of workspace; the maximum is " +
+                     std::to_string(ws_bytes));
+  } else {
+    own.reset(new Scratch(total, s));
+    ws = own->as<char>();
+  }
+  char* p = ws;
+  std::vector<char> host(ib);
+  size_t off = 0;
+  auto put = [&](const void* src, size_t bytes) {
+    if (bytes) std::memcpy(host.data() + off, src, bytes);
+    void* dst = p + off;
+    off += bytes;
+    return dst;
+  };
+  auto* d_rl = (int32_t*)put(rl.data(), rl.size() * 4);
+  auto* d_cl = (int32_t*)put(cl.data(), cl.size() * 4);
+  auto* d_rp = (int32_t*)put(rp.data(), rp.size() * 4);
+  auto* d_cp = (int32_t*)put(cp.data(), cp.size() * 4);
+  auto* d_re = (int32_t*)put(re.data(), re.size() * 4);
+  auto* d_ce = (int32_t*)put(ce.data(), ce.size() * 4);
+  auto* d_nl = (NearPair*)put(nl.data(), nl.size() * sizeof(NearPair));
+  CBFM_HIP(hipMemcpyAsync(p, host.data(), ib, hipMemcpyHostToDevice, s));
+  void* near_buf = ws + al(ib);
+  void* local = ws + al(ib) + al(nb);
+  fill_local(m, md, precision, layout, d_rl, nrt, d_cl, nct, d_nl, (int64_t)nl.size(), local, s, near_buf);
+  assemble(m, precision, local, nrt, nct, d_re, nrow, d_ce, ncol, d_rp, d_cp, out_dev, nrow * ld, ld, s);
+  // the host staging buffer must outlive the asynchronous copy
+  CBFM_HIP(hipStreamSynchronize(s));
+}
+
+// K1 = Kv / 2 and K2 = K - K1 (Kv: the K operator of a body whose interior
+// medium is the exterior one, which is 2 K1 bit for bit)
+template <typename R>
+__global__ void split_k_kernel(const cx<R>* __restrict__ Kv, cx<R>* __restrict__ K1, cx<R>* __restrict__ K2, int64_t ncol,
+                               int64_t ld) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+  if (c >= ncol) return;
+  const cx<R> v = Kv[r * ld + c], k = K2[r * ld + c];
+  const cx<R> k1 = {v.re * (R)0.5, v.im * (R)0.5};
+  K1[r * ld + c] = k1;
+  K2[r * ld + c] = cx<R>{k.re - k1.re, k.im - k1.im};
+}
+
+static void fill_check(cbfm_mesh m, int32_t precision, int64_t row0, int64_t nrow, int64_t col0, int64_t ncol,
+                       int32_t layout, const void* out_dev, int64_t ld) {
+  CBFM_REQUIRE(m != nullptr && out_dev != nullptr, CBFM_E_ARG, "mesh or output is NULL");
+  CBFM_REQUIRE(precision == CBFM_FP64 || precision == CBFM_FP32, CBFM_E_ARG, "unknown precision");
+  CBFM_REQUIRE(layout == CBFM_LAYOUT_MEDIA3 || layout == CBFM_LAYOUT_OPS3 || layout == CBFM_LAYOUT_MEDIA4, CBFM_E_ARG,
+               "unknown layout");
+  const MeshHost& h = m->h;
+  CBFM_REQUIRE(row0 >= 0 && nrow >= 0 && row0 + nrow <= h.ne && col0 >= 0 && ncol >= 0 && col0 + ncol <= h.ne,
+               CBFM_E_ARG, "row/column range outside [0, ne)");
+  CBFM_REQUIRE(ld >= ncol, CBFM_E_ARG, "ld < ncol");
+}
+
+}  // namespace cbfm
+
 extern "C" cbfm_status cbfm_fill_pmchwt(cbfm_mesh m, const cbfm_medium* med, int32_t precision, int64_t row0,
                                         int64_t nrow, int64_t col0, int64_t ncol, int32_t layout, void* out_dev,
                                         int64_t ld, void* stream) {
   return guarded([&] {
-    CBFM_REQUIRE(m != nullptr && out_dev != nullptr, CBFM_E_ARG, "mesh or output is NULL");
-    CBFM_REQUIRE(precision == CBFM_FP64 || precision == CBFM_FP32, CBFM_E_ARG, "unknown precision");
-    CBFM_REQUIRE(layout == CBFM_LAYOUT_MEDIA3 || layout == CBFM_LAYOUT_OPS3, CBFM_E_ARG, "unknown layout");
-    const MeshHost& h = m->h;
-    CBFM_REQUIRE(row0 >= 0 && nrow >= 0 && row0 + nrow <= h.ne && col0 >= 0 && ncol >= 0 &&
-                     col0 + ncol <= h.ne,
-                 CBFM_E_ARG, "row/column range outside [0, ne)");
-    CBFM_REQUIRE(ld >= ncol, CBFM_E_ARG, "ld < ncol");
+    fill_check(m, precision, row0, nrow, col0, ncol, layout, out_dev, ld);
     const Media md = make_media(med);
     if (nrow == 0 || ncol == 0) return;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // triangles touching the ranges and their positions
-    auto tris_of = [&](int64_t e0, int64_t n, std::vector<int32_t>& list, std::vector<int32_t>& pos) {
-      pos.assign(h.nt, -1);
-      for (int64_t e = e0; e < e0 + n; ++e) {
-        pos[h.tplus[e]] = 0;
-        pos[h.tminus[e]] = 0;
-      }
-      list.clear();
-      for (int64_t t = 0; t < h.nt; ++t)
-        if (pos[t] == 0) {
-          pos[t] = (int32_t)list.size();
-          list.push_back((int32_t)t);
-        }
-    };
-    std::vector<int32_t> rl, rp, cl, cp;
-    tris_of(row0, nrow, rl, rp);
-    tris_of(col0, ncol, cl, cp);
-    std::vector<NearPair> nl;
-    for (const NearPair& q : h.near)
-      if (rp[q.p] >= 0 && cp[q.q] >= 0) nl.push_back({q.p, q.q, rp[q.p], cp[q.q], q.coplanar, 0});
-    std::vector<int32_t> re(nrow), ce(ncol);
-    for (int64_t r = 0; r < nrow; ++r) re[r] = (int32_t)(row0 + r);
-    for (int64_t c = 0; c < ncol; ++c) ce[c] = (int32_t)(col0 + c);
-    const int64_t nrt = rl.size(), nct = cl.size();
-    const size_t esz = precision == CBFM_FP64 ? 16 : 8;
-    // index tables in one scratch block
-    const size_t ib = sizeof(int32_t) * (rl.size() + cl.size() + rp.size() + cp.size() + re.size() + ce.size()) +
-                      sizeof(NearPair) * nl.size();
-    Scratch idx(ib, s);
-    char* p = idx.as<char>();
-    std::vector<char> host(ib);
-    size_t off = 0;
-    auto put = [&](const void* src, size_t bytes) {
-      std::memcpy(host.data() + off, src, bytes);
-      void* dst = p + off;
-      off += bytes;
-      return dst;
-    };
-    auto* d_rl = (int32_t*)put(rl.data(), rl.size() * 4);
-    auto* d_cl = (int32_t*)put(cl.data(), cl.size() * 4);
-    auto* d_rp = (int32_t*)put(rp.data(), rp.size() * 4);
-    auto* d_cp = (int32_t*)put(cp.data(), cp.size() * 4);
-    auto* d_re = (int32_t*)put(re.data(), re.size() * 4);
-    auto* d_ce = (int32_t*)put(ce.data(), ce.size() * 4);
-    auto* d_nl = (NearPair*)put(nl.data(), nl.size() * sizeof(NearPair));
-    CBFM_HIP(hipMemcpyAsync(p, host.data(), ib, hipMemcpyHostToDevice, s));
-    Scratch local(3 * 9 * (size_t)nrt * nct * esz, s);
-    fill_local(m, md, precision, layout, d_rl, nrt, d_cl, nct, d_nl, (int64_t)nl.size(), local.p, s);
-    assemble(m, precision, local.p, nrt, nct, d_re, nrow, d_ce, ncol, d_rp, d_cp, out_dev, nrow * ld, ld, s);
-    // the host staging buffer must outlive the asynchronous copy
+    if (layout != CBFM_LAYOUT_MEDIA4) {
+      fill_ranges(m, md, precision, row0, nrow, col0, ncol, layout, out_dev, ld, s, nullptr, 0);
+      return;
+    }
+    // [K1, K2, T1, T2]: [K1 + K2, T1, T2] of the medium into matrices 1..3,
+    // then K of the body with the exterior medium inside (2 K1) apart
+    const size_t esz = precision == CBFM_FP64 ? 16 : 8, mat = (size_t)nrow * ld * esz;
+    char* o = static_cast<char*>(out_dev);
+    fill_ranges(m, md, precision, row0, nrow, col0, ncol, CBFM_LAYOUT_MEDIA3, o + mat, ld, s, nullptr, 0);
+    cbfm_medium outside = *med;
+    outside.eps_re = 1.0;
+    outside.eps_im = 0.0;
+    outside.mu_re = 1.0;
+    outside.mu_im = 0.0;
+    Scratch kv(3 * mat, s);
+    fill_ranges(m, make_media(&outside), precision, row0, nrow, col0, ncol, CBFM_LAYOUT_MEDIA3, kv.p, ld, s, nullptr,
+                0);
+    CBFM_REQUIRE(nrow <= 65535, CBFM_E_ARG, "too many rows for one launch");
+    const dim3 g((unsigned)((ncol + 255) / 256), (unsigned)nrow);
+    if (precision == CBFM_FP64)
+      hipLaunchKernelGGL(split_k_kernel<double>, g, dim3(256), 0, s, kv.as<cx<double>>(), (cx<double>*)o,
+                         (cx<double>*)(o + mat), ncol, ld);
+    else
+      hipLaunchKernelGGL(split_k_kernel<float>, g, dim3(256), 0, s, kv.as<cx<float>>(), (cx<float>*)o,
+                         (cx<float>*)(o + mat), ncol, ld);
+    CBFM_HIP(hipGetLastError());
     CBFM_HIP(hipStreamSynchronize(s));
   });
 }

@@ -49,10 +49,21 @@ cbfm_status guarded(F&& f) {
   }
 }
 
+// Device memory of the library: from the caller's allocator when one is
+// set (cbfm_set_allocator), else from hipMalloc.  A block remembers the
+// release routine it must go back through.
+using ReleaseFn = void (*)(void* p, void* stream);
+// device bytes the library holds from hipMalloc (handles and the scratch
+// cache), now and at most since the process started
+void device_bytes_add(int64_t delta);
+// the caller's allocator, or nullptr (then hipMalloc)
+void* hooked_alloc(size_t bytes, hipStream_t s, ReleaseFn* release);
+
 // Device buffer owned by a handle.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  ReleaseFn rel = nullptr;  // the caller's release routine, or nullptr (hipFree)
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
@@ -60,12 +71,22 @@ struct DevBuf {
   void alloc(size_t n) {
     release();
     if (n == 0) return;
+    ReleaseFn r = nullptr;
+    void* q = hooked_alloc(n, nullptr, &r);
+    if (r) {
+      CBFM_REQUIRE(q != nullptr, CBFM_E_NOMEM, "the caller's allocator returned no memory for " + std::to_string(n) + " bytes");
+      p = q;
+      rel = r;
+      bytes = n;
+      return;
+    }
     hipError_t e = hipMalloc(&p, n);
     if (e != hipSuccess) {
       p = nullptr;
       throw Error{CBFM_E_NOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed"};
     }
     bytes = n;
+    device_bytes_add((int64_t)n);
   }
   template <typename T>
   void upload(const std::vector<T>& v) {
@@ -73,9 +94,15 @@ struct DevBuf {
     if (!v.empty()) CBFM_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && rel) {
+      rel(p, nullptr);
+    } else if (p) {
+      (void)hipFree(p);
+      device_bytes_add(-(int64_t)bytes);
+    }
     p = nullptr;
     bytes = 0;
+    rel = nullptr;
   }
   template <typename T>
   T* as() const { return static_cast<T*>(p); }
@@ -94,17 +121,32 @@ void scratch_forget_stream(hipStream_t s);
 // Marks s as a library side stream: a cached block it released and still
 // uses is not waited for by another stream while a new block can be had.
 void scratch_side_stream(hipStream_t s);
+// Frees the oldest cached blocks of the current device (after their events
+// complete) until the cache holds at most `limit` bytes.
+void scratch_trim_to(size_t limit);
 
-// Stream-ordered scratch released at scope exit.
+// Stream-ordered scratch released at scope exit: from the caller's
+// allocator when one is set, else from the library's cache.
 struct Scratch {
   void* p = nullptr;
   hipStream_t s = nullptr;
   size_t n = 0;
+  ReleaseFn rel = nullptr;
   Scratch(size_t bytes, hipStream_t stream) : s(stream), n(bytes) {
-    if (bytes > 0) p = scratch_alloc(bytes, stream);
+    if (bytes == 0) return;
+    p = hooked_alloc(bytes, stream, &rel);
+    if (rel) {
+      CBFM_REQUIRE(p != nullptr, CBFM_E_NOMEM,
+                   "the caller's allocator returned no memory for " + std::to_string(bytes) + " bytes");
+      return;
+    }
+    p = scratch_alloc(bytes, stream);
   }
   ~Scratch() {
-    if (p) scratch_release(p, n, s);
+    if (p && rel)
+      rel(p, s);
+    else if (p)
+      scratch_release(p, n, s);
   }
   Scratch(const Scratch&) = delete;
   Scratch& operator=(const Scratch&) = delete;
@@ -230,9 +272,12 @@ struct NearOut {
 };
 void fill_near_batch(const cbfm_mesh_s* m, const Media& md, int layout, const NearPair* near, int64_t nnear,
                      const NearOut* outs, int cell0, void* local, hipStream_t s);
+// near_buf: near_buffer_bytes(nnear) bytes of device memory for the near
+// stage's intermediates, or NULL for stream-ordered scratch.
 void fill_local(const cbfm_mesh_s* m, const Media& md, int precision, int layout,
                 const int32_t* rowTris_dev, int64_t nrt, const int32_t* colTris_dev, int64_t nct,
-                const NearPair* near_dev, int64_t nnear, void* local, hipStream_t s);
+                const NearPair* near_dev, int64_t nnear, void* local, hipStream_t s, void* near_buf = nullptr);
+size_t near_buffer_bytes(int64_t nnear);
 
 void rhs_launch(const cbfm_mesh_s* m, const Media& md, double eta0, const double* inc_dev, int64_t nrhs,
                 void* v_dev, hipStream_t s);

@@ -101,6 +101,7 @@ void free_blocks(std::vector<Block>& drop) {
   for (Block& b : drop) {
     if (b.ready) (void)hipEventSynchronize(b.ready);
     (void)hipFree(b.p);
+    device_bytes_add(-(int64_t)b.bytes);
     if (b.ready) {
       std::lock_guard<std::mutex> lk(cache().mu);
       spare_event(b.dev, b.ready);
@@ -168,7 +169,10 @@ void* scratch_alloc(size_t bytes, hipStream_t s) {
     if (other != SIZE_MAX) return take(lk, other);
   }
   void* p = nullptr;
-  if (hipMalloc(&p, want) == hipSuccess) return p;
+  if (hipMalloc(&p, want) == hipSuccess) {
+    device_bytes_add((int64_t)want);
+    return p;
+  }
   (void)hipGetLastError();
   if (busy != SIZE_MAX) {  // wait for a block in use rather than fail
     std::unique_lock<std::mutex> lk(cache().mu);
@@ -181,6 +185,7 @@ void* scratch_alloc(size_t bytes, hipStream_t s) {
     (void)hipGetLastError();
     throw Error{CBFM_E_NOMEM, "device allocation of " + std::to_string(want) + " bytes failed"};
   }
+  device_bytes_add((int64_t)want);
   return p;
 }
 
@@ -193,6 +198,7 @@ void scratch_release(void* p, size_t bytes, hipStream_t s) {
     if (ev) (void)hipEventDestroy(ev);
     (void)hipStreamSynchronize(s);
     (void)hipFree(p);
+    device_bytes_add(-(int64_t)block_size(bytes));
     return;
   }
   std::vector<Block> drop;
@@ -233,6 +239,32 @@ void scratch_forget_stream(hipStream_t s) {
   for (hipEvent_t e : done) (void)hipEventDestroy(e);
 }
 
+void scratch_trim_to(size_t limit) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  std::vector<Block> drop;
+  {
+    std::lock_guard<std::mutex> lk(cache().mu);
+    auto& f = cache().free;
+    size_t held = 0;
+    for (const Block& b : f)
+      if (b.dev == dev) held += b.bytes;
+    for (size_t i = 0; held > limit && i < f.size();) {
+      if (f[i].dev == dev) {
+        held -= f[i].bytes;
+        drop.push_back(f[i]);
+        f.erase(f.begin() + (ptrdiff_t)i);
+      } else {
+        ++i;
+      }
+    }
+  }
+  free_blocks(drop);
+}
+
 void scratch_side_stream(hipStream_t s) {
   std::lock_guard<std::mutex> lk(cache().mu);
   cache().side.push_back(s);
@@ -252,3 +284,57 @@ size_t scratch_cached_bytes() {
 }
 
 }  // namespace cbfm
+
+// ------------------------------------------------------------ allocator hook
+namespace cbfm {
+namespace {
+std::mutex g_hook_mu;
+cbfm_alloc_fn g_alloc = nullptr;
+cbfm_release_fn g_release = nullptr;
+std::mutex g_bytes_mu;
+int64_t g_bytes = 0, g_peak = 0;
+}  // namespace
+
+void device_bytes_add(int64_t delta) {
+  std::lock_guard<std::mutex> lk(g_bytes_mu);
+  g_bytes += delta;
+  g_peak = std::max(g_peak, g_bytes);
+}
+
+void* hooked_alloc(size_t bytes, hipStream_t s, ReleaseFn* release) {
+  cbfm_alloc_fn a;
+  {
+    std::lock_guard<std::mutex> lk(g_hook_mu);
+    a = g_alloc;
+    *release = g_release;
+  }
+  if (!a) return nullptr;
+  return a(bytes, static_cast<void*>(s));
+}
+}  // namespace cbfm
+
+using namespace cbfm;
+
+extern "C" cbfm_status cbfm_set_allocator(cbfm_alloc_fn alloc, cbfm_release_fn release) {
+  return guarded([&] {
+    CBFM_REQUIRE((alloc == nullptr) == (release == nullptr), CBFM_E_ARG, "set both routines or neither");
+    {
+      std::lock_guard<std::mutex> lk(g_hook_mu);
+      g_alloc = alloc;
+      g_release = release;
+    }
+    // blocks cached from hipMalloc are no longer handed out: free them
+    if (alloc) scratch_trim_to(0);
+  });
+}
+
+extern "C" cbfm_status cbfm_memory_stats(int64_t* held, int64_t* peak, int64_t* cached) {
+  return guarded([&] {
+    {
+      std::lock_guard<std::mutex> lk(g_bytes_mu);
+      if (held) *held = g_bytes;
+      if (peak) *peak = g_peak;
+    }
+    if (cached) *cached = (int64_t)scratch_cached_bytes();
+  });
+}

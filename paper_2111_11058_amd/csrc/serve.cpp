@@ -239,6 +239,7 @@ void cbfm_server_s::run(Job* j, hipStream_t s) {
 
 void cbfm_server_s::worker() {
   hipStream_t s = nullptr;
+  size_t trim_limit = 0;
   const bool ok = hipSetDevice(device) == hipSuccess && hipStreamCreate(&s) == hipSuccess;
   cbfm::async_cmp_on_this_thread(false);  // requests overlap one another already
   for (;;) {
@@ -274,7 +275,12 @@ void cbfm_server_s::worker() {
       }
       running -= 1;
       j->done = true;
+      // idle cached scratch may hold what the running requests and the
+      // residents leave of the budget, no more
+      const size_t used = in_use + resident_bytes;
+      trim_limit = budget > used ? budget - used : 0;
     }
+    scratch_trim_to(trim_limit);
     cv_done.notify_all();
     cv_work.notify_all();
   }

@@ -20,6 +20,7 @@
 
 #include "cbf.h"
 #include "gemm.h"
+#include "solve.h"
 
 namespace cbfm {
 
@@ -987,7 +988,7 @@ static void apply_op(const double2* A, int64_t lda, int64_t n, int64_t nrhs, con
 template <typename TV, typename MV>
 static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev, TV* V, TV* w, int64_t vstride,
                       int64_t n, int64_t nrhs, int64_t mres, int64_t max_iter, int64_t& total, GmresState gs,
-                      double* part, int np, PinnedFlags& flags, double2* x, hipStream_t s) {
+                      double* part, int np, PinnedFlags& flags, double2* x, hipStream_t s, const TV* xb = nullptr) {
   const double vb = (double)sizeof(TV);
   const int check_every = 4;
   const int64_t ng = (nrhs + 63) / 64;
@@ -1097,9 +1098,317 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
   // the last column of the cycle, taken without the delayed correction
   if (j > 0) hipLaunchKernelGGL(column_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, mres, j, nrhs, 0, nullptr);
   hipLaunchKernelGGL(backsolve_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, mres, nrhs);
-  hipLaunchKernelGGL(x_update_kernel<TV>, dim3((unsigned)((int64_t)np * nrhs)), dim3(512), 0, s, gs, V, vstride, x, n, nrhs,
+  // x += Q y, or Z y for flexible GMRES (the preconditioned vectors z_j)
+  hipLaunchKernelGGL(x_update_kernel<TV>, dim3((unsigned)((int64_t)np * nrhs)), dim3(512), 0, s, gs, xb ? xb : V,
+                     vstride, x, n, nrhs,
                      np);
   CBFM_HIP(hipGetLastError());
+}
+
+// r = A x in double for row-stored vectors x (nrhs x n), A float (lda):
+// the matrix-core product with float operands, double accumulation output.
+static void apply_op32(const float2* A, int64_t lda, int64_t n, int64_t nrhs, const double2* x, double2* r,
+                       hipStream_t s) {
+  std::vector<GemmDescX> d{gemmx(A, 0, lda, OP_N, x, 1, n, OP_T, r, 1, n, n, nrhs, n)};
+  d[0].transC = 1;
+  xgemm_batched(d, XG_FP32, s);
+}
+
+namespace {
+// w = A q_j through a composite operator
+struct OpMV {
+  const KrylovOp* op;
+  void launch(size_t j, hipStream_t q) const { op->launch((int64_t)j, q); }
+};
+}  // namespace
+
+GmresResult gmres_run(KrylovOp& op, int64_t n, int64_t nrhs, const double2* b, double2* x, const GmresSpec& p,
+                      hipStream_t s) {
+  int64_t lda64 = 0, lda32 = 0;
+  const double2* A64 = op.dense64(&lda64);
+  const float2* A32in = op.dense32(&lda32);
+  const bool dense = A64 != nullptr || A32in != nullptr;
+  // a float-only operator runs float cycles (its residuals in float too)
+  const bool f32 = p.f32 || (A32in != nullptr && A64 == nullptr);
+  CBFM_REQUIRE(dense || !f32, CBFM_E_ARG, "float Krylov cycles need a dense operator");
+  CBFM_REQUIRE(p.tol > 0 && p.max_iter >= 1 && p.restart >= 1, CBFM_E_ARG, "bad solver parameters");
+  const int64_t mres = std::min<int64_t>(p.restart, std::max<int64_t>(p.max_iter, 1));
+  // The plain form keeps the Krylov basis in double; the mixed form keeps it
+  // and the operator in float and refines: every cycle starts from the
+  // residual b - A x formed in double, and stops once it has reduced that
+  // residual by inner_tol (or reached tol).
+  const double inner = f32 ? (p.inner_tol > 0 ? p.inner_tol : 1e-6) : 0.0;
+  const size_t vsz = f32 ? sizeof(float2) : sizeof(double2);
+  Scratch V((mres + 1) * nrhs * n * vsz, s);
+  Scratch u(nrhs * n * vsz, s), r64(f32 ? nrhs * n * sizeof(double2) : 0, s);
+  Scratch A32own(f32 && A32in == nullptr ? n * n * sizeof(float2) : 0, s);
+  const int np = (int)((n + 127) / 128);  // partial norm sums per vector (128-row blocks)
+  const size_t hbytes = (size_t)nrhs * (mres + 1) * mres * sizeof(double2), cbytes = (size_t)nrhs * (mres + 1) * sizeof(double2);
+  Scratch Rs(hbytes, s), Hs(hbytes, s), csb(nrhs * mres * sizeof(double2), s), snb(nrhs * mres * sizeof(double2), s),
+      gb(cbytes, s), d1b(cbytes, s), d2b(cbytes, s), d1t(cbytes, s), d2t(cbytes, s), hcb(cbytes, s),
+      abb(nrhs * sizeof(double2), s), dbl(5 * nrhs * sizeof(double), s), ints(3 * nrhs * sizeof(int32_t), s),
+      part(nrhs * np * sizeof(double), s);
+  // few 128-row update blocks (a single right-hand side): the basis range
+  // of each is split over up to 8 blocks, so that about 256 blocks stream
+  const int split = nrhs == 1 && np < 64 ? (int)std::min<int64_t>(8, (256 + np - 1) / np) : 1;
+  Scratch wsb(split > 1 ? (size_t)nrhs * np * split * 256 * sizeof(double2) : 0, s);
+  GmresState gs{Rs.as<double2>(),
+                Hs.as<double2>(),
+                csb.as<double2>(),
+                snb.as<double2>(),
+                gb.as<double2>(),
+                d1b.as<double2>(),
+                d2b.as<double2>(),
+                abb.as<double2>(),
+                dbl.as<double>(),
+                dbl.as<double>() + nrhs,
+                dbl.as<double>() + 2 * nrhs,
+                dbl.as<double>() + 3 * nrhs,
+                dbl.as<double>() + 4 * nrhs,
+                ints.as<int32_t>(),
+                ints.as<int32_t>() + nrhs,
+                ints.as<int32_t>() + 2 * nrhs,
+                d1t.as<double2>(),
+                d2t.as<double2>(),
+                hcb.as<double2>(),
+                mres + 1,
+                split,
+                wsb.as<double2>()};
+  const int64_t vstride = nrhs * n;
+  const dim3 g1((unsigned)((nrhs + 63) / 64)), b1(64);
+  CBFM_HIP(hipMemsetAsync(x, 0, nrhs * n * sizeof(double2), s));
+  CBFM_HIP(hipMemsetAsync(gs.its, 0, nrhs * sizeof(int32_t), s));
+  hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, b, n, gs.bnorm, nullptr);
+  GmresResult out;
+  out.its.assign(nrhs, 0);
+  out.res.assign(nrhs, 1.0);
+  int64_t total = 0;
+  const double tol = p.tol;
+  // Convergence flags go to pinned host memory every few iterations and are
+  // read one check later, so the host never waits for the device inside a
+  // cycle; iterations queued after the last right-hand side converged do
+  // nothing (every kernel skips inactive right-hand sides).
+  PinnedFlags flags(nrhs);
+  auto all_done = [&](const int32_t* a) {
+    return std::none_of(a, a + nrhs, [](int32_t v) { return v != 0; });
+  };
+  // w = A q_j for every Krylov index j, descriptors uploaded once
+  const float2* A32 = A32in;
+  int64_t ld32 = lda32;
+  std::vector<std::vector<GemmDesc>> mv(dense && !f32 ? mres : 0);
+  std::vector<std::vector<GemmDescX>> mvx(f32 ? mres : 0);
+  if (f32) {
+    if (A32 == nullptr) {
+      hipLaunchKernelGGL(to_float_kernel, grid2(n, n), dim3(256), 0, s, A64, lda64, A32own.as<float2>(), n, n, n);
+      CBFM_HIP(hipGetLastError());
+      A32 = A32own.as<float2>();
+      ld32 = n;
+    }
+    for (int64_t j = 0; j < mres; ++j) {
+      GemmDescX d = gemmx(A32, 0, ld32, OP_N, V.as<float2>() + j * vstride, 0, n, OP_T, u.as<float2>(), 0, n, n, nrhs,
+                          n);
+      d.transC = 1;
+      mvx[j].push_back(d);
+    }
+  } else if (dense) {
+    for (int64_t j = 0; j < mres; ++j) {
+      GemmDesc d = gemm(A64, lda64, OP_N, V.as<double2>() + j * vstride, n, OP_T, u.as<double2>(), n, n, nrhs, n);
+      d.transC = 1;
+      mv[j].push_back(d);
+    }
+  } else {
+    op.prepare(V.as<double2>(), vstride, u.as<double2>(), mres, nrhs, s);
+  }
+  const GemmPlan matvec(mv, s);
+  const XGemmPlan matvec32(mvx, XG_FP32, s);
+  // graph replays: one matrix-vector descriptor repointed on the device
+  const bool graph = p.graph && dense && mres > 0;
+  std::unique_ptr<GemmPlan> dyn;
+  std::unique_ptr<XGemmPlan> dyn32;
+  Scratch jdev(graph ? sizeof(int64_t) : 0, s);
+  if (graph && f32) dyn32.reset(new XGemmPlan({mvx[0]}, XG_FP32, s));
+  if (graph && !f32) dyn.reset(new GemmPlan({mv[0]}, s, false));
+  // r = b - A x in double (A x in float for a float-only operator)
+  auto residual = [&](double2* r) {
+    if (A64)
+      apply_op(A64, lda64, n, nrhs, x, r, s);
+    else if (A32in)
+      apply_op32(A32in, lda32, n, nrhs, x, r, s);
+    else
+      op.apply(x, r, nrhs, s);
+    hipLaunchKernelGGL(sub_from_kernel, dim3((unsigned)((nrhs * n + 255) / 256)), dim3(256), 0, s, b, r, nrhs * n);
+  };
+  const OpMV opmv{&op};
+  for (;;) {
+    // r = b - A x  (x = 0 on the first cycle)
+    double2* r = f32 ? r64.as<double2>() : u.as<double2>();
+    if (total == 0)
+      CBFM_HIP(hipMemcpyAsync(r, b, nrhs * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    else
+      residual(r);
+    hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, r, n, gs.nrm, nullptr);
+    hipLaunchKernelGGL(cycle_init_kernel, g1, b1, 0, s, gs, mres, nrhs, tol, inner);
+    if (f32)
+      hipLaunchKernelGGL(scale_kernel<float2>, grid2(n, nrhs), dim3(256), 0, s, r, V.as<float2>(), n, gs.nrm);
+    else
+      hipLaunchKernelGGL(scale_kernel<double2>, grid2(n, nrhs), dim3(256), 0, s, r, V.as<double2>(), n, gs.nrm);
+    if (all_done(flags.sync_read(gs.active, s)) || total >= p.max_iter) break;
+    if (f32)
+      run_cycle(matvec32, dyn32.get(), dyn32 ? dyn32->desc(0) : nullptr, jdev.as<int64_t>(), V.as<float2>(),
+                u.as<float2>(), vstride, n, nrhs, mres, p.max_iter, total, gs, part.as<double>(), np, flags, x, s);
+    else if (dense)
+      run_cycle(matvec, dyn.get(), dyn ? dyn->desc(0) : nullptr, jdev.as<int64_t>(), V.as<double2>(),
+                u.as<double2>(), vstride, n, nrhs, mres, p.max_iter, total, gs, part.as<double>(), np, flags, x, s);
+    else
+      run_cycle(opmv, (const OpMV*)nullptr, nullptr, jdev.as<int64_t>(), V.as<double2>(), u.as<double2>(), vstride, n,
+                nrhs, mres, p.max_iter, total, gs, part.as<double>(), np, flags, x, s, op.xbasis());
+    if (total >= p.max_iter) break;
+  }
+  CBFM_HIP(hipMemcpyAsync(out.its.data(), gs.its, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  // true relative residual
+  {
+    double2* r = f32 ? r64.as<double2>() : u.as<double2>();
+    residual(r);
+    hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, r, n, gs.nrm, nullptr);
+    std::vector<double> rn(nrhs), bn(nrhs);
+    CBFM_HIP(hipMemcpyAsync(rn.data(), gs.nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    CBFM_HIP(hipMemcpyAsync(bn.data(), gs.bnorm, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    CBFM_HIP(hipStreamSynchronize(s));
+    for (int64_t q = 0; q < nrhs; ++q) {
+      out.res[q] = bn[q] > 0 ? rn[q] / bn[q] : 0.0;
+      if (out.res[q] > tol) out.noconv = true;
+    }
+  }
+  return out;
+}
+
+void permute_halves(const double2* in, double2* out, const int32_t* perm, int64_t ne, int64_t nv, int forward,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(permute_kernel, grid2(ne, nv), dim3(256), 0, s, in, out, perm, ne, nv, forward);
+  CBFM_HIP(hipGetLastError());
+}
+
+void rcs_compute(const cbfm_mesh_s* m, const cbfm_medium* med, const double2* jfinal, const double* inc, int64_t nrhs,
+                 const double* dirs, int64_t ndir, double* rcs, hipStream_t s) {
+  const MeshHost& h = m->h;
+  const int64_t nd = dirs ? ndir : 1;
+  std::vector<double> hd(nrhs * nd * 3), hp;
+  if (dirs) {
+    for (int64_t q = 0; q < nrhs; ++q) std::memcpy(&hd[q * nd * 3], dirs, nd * 3 * sizeof(double));
+  } else {
+    hp.resize(nrhs * 3);
+    for (int64_t q = 0; q < nrhs; ++q)
+      for (int x3 = 0; x3 < 3; ++x3) {
+        hd[q * 3 + x3] = -inc[q * 6 + x3];
+        hp[q * 3 + x3] = inc[q * 6 + 3 + x3];
+      }
+  }
+  Scratch ddir(hd.size() * sizeof(double), s), dpol(hp.size() * sizeof(double), s),
+      dsig(nrhs * nd * sizeof(double), s);
+  CBFM_HIP(hipMemcpyAsync(ddir.p, hd.data(), hd.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  if (!hp.empty()) CBFM_HIP(hipMemcpyAsync(dpol.p, hp.data(), hp.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  FarArgs fa{};
+  fa.xyz9 = m->tri_xyz.as<double>();
+  fa.tri_edge = m->tri_edge.as<int32_t>();
+  fa.c64 = m->c64.as<double>();
+  fa.nt = h.nt;
+  fa.ne = h.ne;
+  const double s15 = std::sqrt(15.0);
+  const double qa = (6.0 - s15) / 21.0, qb = (6.0 + s15) / 21.0;
+  const double wa = (155.0 - s15) / 1200.0, wb = (155.0 + s15) / 1200.0;
+  const double Bq[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {1 - 2 * qa, qa, qa}, {qa, 1 - 2 * qa, qa}, {qa, qa, 1 - 2 * qa},
+                           {1 - 2 * qb, qb, qb},        {qb, 1 - 2 * qb, qb}, {qb, qb, 1 - 2 * qb}};
+  const double Wq[7] = {9.0 / 40.0, wa, wa, wa, wb, wb, wb};
+  std::memcpy(fa.bary, Bq, sizeof(Bq));
+  std::memcpy(fa.w, Wq, sizeof(Wq));
+  fa.k0 = med->k0;
+  fa.eta0 = med->eta0;
+  hipLaunchKernelGGL(farfield_kernel, dim3((unsigned)nd, (unsigned)nrhs), dim3(256), 0, s, fa, jfinal, ddir.as<double>(),
+                     hp.empty() ? nullptr : dpol.as<double>(), nd, dsig.as<double>());
+  CBFM_HIP(hipGetLastError());
+  CBFM_HIP(hipMemcpyAsync(rcs, dsig.p, nrhs * nd * sizeof(double), hipMemcpyDeviceToHost, s));
+  CBFM_HIP(hipStreamSynchronize(s));
+}
+
+// v_r = (C^JM)^H v for nrhs tested incident fields v (internal order, nrhs x 2ne)
+void project_rhs(const cbfm_mesh_s* m, cbfm_cbf_s* c, const double2* vint, int64_t nrhs, double2* b, hipStream_t s) {
+  const MeshHost& h = m->h;
+  const int64_t ne = h.ne, NL = c->NL, n = 2 * NL;
+  std::vector<GemmDesc> ds;
+  for (int a = 0; a < h.nblocks; ++a) {
+    const int64_t Na = h.cell_off[a + 1] - h.cell_off[a], r0 = h.cell_off[a];
+    // [v_r]_J-part = (C^J_a)^H v^E_a,  [v_r]_M-part = (C^M_a)^H v^H_a  (per vector: v . conj(C))
+    ds.push_back(gemm(vint + r0, 2 * ne, OP_N, c->CJ.as<double2>() + c->coff[a], c->L[a], OP_R, b + c->off[a], n, nrhs,
+                      c->L[a], Na));
+    ds.push_back(gemm(vint + ne + r0, 2 * ne, OP_N, c->CM.as<double2>() + c->coff[a], c->L[a], OP_R,
+                      b + NL + c->off[a], n, nrhs, c->L[a], Na));
+  }
+  zgemm_batched(ds, s);
+}
+
+// j = C^MJ j_CBF (internal order, nrhs x 2ne)
+void expand_cbf(const cbfm_mesh_s* m, cbfm_cbf_s* c, const double2* jc, int64_t nrhs, double2* jint, hipStream_t s) {
+  const MeshHost& h = m->h;
+  const int64_t ne = h.ne, NL = c->NL, n = 2 * NL;
+  std::vector<GemmDesc> ds;
+  for (int a = 0; a < h.nblocks; ++a) {
+    const int64_t Na = h.cell_off[a + 1] - h.cell_off[a], r0 = h.cell_off[a];
+    // alpha^M_a = C^M_a beta^M_a, alpha^J_a = C^J_a beta^J_a  (per vector: beta . C^T)
+    ds.push_back(gemm(jc + c->off[a], n, OP_N, c->CM.as<double2>() + c->coff[a], c->L[a], OP_T, jint + r0, 2 * ne, nrhs,
+                      Na, c->L[a]));
+    ds.push_back(gemm(jc + NL + c->off[a], n, OP_N, c->CJ.as<double2>() + c->coff[a], c->L[a], OP_T, jint + ne + r0,
+                      2 * ne, nrhs, Na, c->L[a]));
+  }
+  zgemm_batched(ds, s);
+}
+
+// Flexible GMRES with the paper's inexact CMP: each Krylov vector q_j is
+// preconditioned by an inner GMRES solve z_j ~ (G^CBF)^{-1} q_j (diagonal
+// preconditioner D^CBF, relative residual inner_tol), the product is
+// w = Z_r z_j, and the iterate is x = sum z_j y_j: j_CBF itself.
+class FlexCmpOp : public KrylovOp {
+ public:
+  FlexCmpOp(const double2* Zr, int64_t ldz, cbfm_cbf_s* c, double inner_tol, int64_t n)
+      : Zr_(Zr), ldz_(ldz), c_(c), tol_(inner_tol), n_(n) {}
+  void prepare(const double2* V, int64_t vstride, double2* w, int64_t mres, int64_t nrhs, hipStream_t s) override {
+    V_ = V;
+    vstride_ = vstride;
+    nrhs_ = nrhs;
+    Zb_.reset(new Scratch((size_t)mres * vstride * sizeof(double2), s));
+    std::vector<std::vector<GemmDesc>> g(mres);
+    for (int64_t j = 0; j < mres; ++j) {
+      GemmDesc d = gemm(Zr_, ldz_, OP_N, Zb_->as<double2>() + j * vstride, n_, OP_T, w, n_, n_, nrhs, n_);
+      d.transC = 1;
+      g[j].push_back(d);
+    }
+    plan_.reset(new GemmPlan(g, s, false));
+  }
+  void launch(int64_t j, hipStream_t q) const override {
+    cmp_inner_apply(c_, nrhs_, V_ + j * vstride_, Zb_->as<double2>() + j * vstride_, tol_, q);
+    plan_->launch((size_t)j, q);
+  }
+  void apply(const double2* x, double2* r, int64_t nrhs, hipStream_t s) const override {
+    apply_op(Zr_, ldz_, n_, nrhs, x, r, s);
+  }
+  const double2* xbasis() const override { return Zb_ ? Zb_->as<double2>() : nullptr; }
+
+ private:
+  const double2* Zr_;
+  int64_t ldz_;
+  cbfm_cbf_s* c_;
+  double tol_;
+  int64_t n_, nrhs_ = 0, vstride_ = 0;
+  const double2* V_ = nullptr;
+  std::unique_ptr<Scratch> Zb_;
+  std::unique_ptr<GemmPlan> plan_;
+};
+
+// out[c][i] = in[c][(i + NL) mod 2NL]: the two halves of each vector swapped
+__global__ void swap_halves_kernel(const double2* __restrict__ in, double2* __restrict__ out, int64_t NL, int64_t nv,
+                                   int64_t ldi, int64_t ldo) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (i >= 2 * NL || c >= nv) return;
+  out[c * ldo + i] = in[c * ldi + (i < NL ? i + NL : i - NL)];
 }
 
 }  // namespace cbfm
@@ -1110,47 +1419,45 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
                                   const double* inc, int64_t nrhs, const cbfm_solver_params* prm, void* j_dev,
                                   int32_t* iters, double* relres, const double* dirs, int64_t ndir, double* rcs,
                                   void* stream) {
-  cbfm_status noconv = CBFM_OK;
+  bool noconv = false;
   cbfm_status st = guarded([&] {
     CBFM_REQUIRE(m && c && Zr_v && inc && prm, CBFM_E_ARG, "null argument");
     CBFM_REQUIRE(c->mesh == m, CBFM_E_STATE, "CBF set belongs to another mesh");
     CBFM_REQUIRE(nrhs >= 1 && nrhs <= 65535, CBFM_E_ARG, "nrhs out of range");
     CBFM_REQUIRE(ldz >= 2 * c->NL, CBFM_E_ARG, "ldz < N_CBF");
     CBFM_REQUIRE(prm->tol > 0 && prm->max_iter >= 1 && prm->restart >= 1, CBFM_E_ARG, "bad solver parameters");
+    CBFM_REQUIRE(prm->use_cmp >= 0 && prm->use_cmp <= 2, CBFM_E_ARG, "use_cmp must be 0, 1 or 2");
+    CBFM_REQUIRE(prm->cmp_mode == CBFM_CMP_EXACT || prm->cmp_mode == CBFM_CMP_INNER_GMRES, CBFM_E_ARG,
+                 "unknown CMP mode");
+    const bool flexible = prm->use_cmp == 1 && prm->cmp_mode == CBFM_CMP_INNER_GMRES;
+    CBFM_REQUIRE(!flexible || (prm->inner_fp32 == 0 && prm->use_graph == 0), CBFM_E_ARG,
+                 "the inexact CMP runs double Krylov cycles without graphs");
+    CBFM_REQUIRE(!flexible || (prm->cmp_inner_tol >= 0 && prm->cmp_inner_tol < 1), CBFM_E_ARG,
+                 "cmp_inner_tol outside [0, 1)");
     CBFM_REQUIRE(dirs == nullptr || ndir >= 1, CBFM_E_ARG, "ndir must be >= 1 with dirs");
     const Media md = make_media(med);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const MeshHost& h = m->h;
-    const int64_t ne = h.ne, NL = c->NL, n = 2 * NL, nb = h.nblocks;
+    const int64_t ne = h.ne, NL = c->NL, n = 2 * NL;
     const double2* Zr = static_cast<const double2*>(Zr_v);
-    const bool use_cmp = prm->use_cmp != 0;
-    const int64_t mres = std::min<int64_t>(prm->restart, std::max<int64_t>(prm->max_iter, 1));
     // ---- right-hand sides and their projection
     Scratch dinc(nrhs * 6 * sizeof(double), s);
     CBFM_HIP(hipMemcpyAsync(dinc.p, inc, nrhs * 6 * sizeof(double), hipMemcpyHostToDevice, s));
     Scratch v(nrhs * 2 * ne * sizeof(double2), s), vint(nrhs * 2 * ne * sizeof(double2), s);
     rhs_launch(m, md, med->eta0, dinc.as<double>(), nrhs, v.p, s);
-    hipLaunchKernelGGL(permute_kernel, grid2(ne, nrhs), dim3(256), 0, s, v.as<double2>(), vint.as<double2>(),
-                       m->perm.as<int32_t>(), ne, nrhs, 1);
+    permute_halves(v.as<double2>(), vint.as<double2>(), m->perm.as<int32_t>(), ne, nrhs, 1, s);
     Scratch b(nrhs * n * sizeof(double2), s);
-    {
-      std::vector<GemmDesc> ds;
-      for (int a = 0; a < nb; ++a) {
-        const int64_t Na = h.cell_off[a + 1] - h.cell_off[a], r0 = h.cell_off[a];
-        // [v_r]_J-part = (C^J_a)^H v^E_a,  [v_r]_M-part = (C^M_a)^H v^H_a  (per vector: v . conj(C))
-        ds.push_back(gemm(vint.as<double2>() + r0, 2 * ne, OP_N, c->CJ.as<double2>() + c->coff[a], c->L[a], OP_R,
-                          b.as<double2>() + c->off[a], n, nrhs, c->L[a], Na));
-        ds.push_back(gemm(vint.as<double2>() + ne + r0, 2 * ne, OP_N, c->CM.as<double2>() + c->coff[a], c->L[a], OP_R,
-                          b.as<double2>() + NL + c->off[a], n, nrhs, c->L[a], Na));
-      }
-      zgemm_batched(ds, s);
-    }
-    // ---- operator: right-preconditioned A = Z_r (G^CBF)^{-1}, formed once,
-    // with (G^CBF)^{-1} = blkdiag(-(B^{-1})^H, B^{-1})
+    project_rhs(m, c, vint.as<double2>(), nrhs, b.as<double2>(), s);
+    // ---- operator.  use_cmp 1: right-preconditioned A = Z_r (G^CBF)^{-1},
+    // formed once, with (G^CBF)^{-1} = blkdiag(-(B^{-1})^H, B^{-1}).
+    // use_cmp 2 (T-diagonal CBFM, Sec. IV-A): (C^JM)^H Z_t C^JM = Z_r with
+    // its two column halves swapped, solved without preconditioner.
     const double2* Aop = Zr;
     int64_t lda = ldz;
-    Scratch Ap(use_cmp ? n * n * sizeof(double2) : 0, s);
-    if (use_cmp) {
+    Scratch Ap(prm->use_cmp && !flexible ? n * n * sizeof(double2) : 0, s);
+    if (flexible) {
+      // (no operator formed: flexible GMRES applies Z_r after each inner solve)
+    } else if (prm->use_cmp == 1) {
       const double2* Bi = cmp_inverse(c, s);
       std::vector<GemmDesc> ds;
       if (c->blockdiag) {  // B^{-1} block-diagonal: each cell's columns take its own block
@@ -1167,202 +1474,45 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
       zgemm_batched(ds, s);
       Aop = Ap.as<double2>();
       lda = n;
-    }
-    // ---- GMRES state.  The plain form keeps the Krylov basis in double;
-    // the mixed form (inner_fp32) keeps it and the operator in float and
-    // refines: every cycle starts from the residual b - A x formed in
-    // double with the double operator, and stops once it has reduced that
-    // residual by inner_tol (or reached tol).
-    const bool f32 = prm->inner_fp32 != 0;
-    const double inner = f32 ? (prm->inner_tol > 0 ? prm->inner_tol : 1e-6) : 0.0;
-    const size_t vsz = f32 ? sizeof(float2) : sizeof(double2);
-    Scratch V((mres + 1) * nrhs * n * vsz, s);
-    Scratch x(nrhs * n * sizeof(double2), s), u(nrhs * n * vsz, s), r64(f32 ? nrhs * n * sizeof(double2) : 0, s);
-    Scratch A32(f32 ? n * n * sizeof(float2) : 0, s);
-    const int np = (int)((n + 127) / 128);  // partial norm sums per vector (128-row blocks)
-    const size_t hbytes = (size_t)nrhs * (mres + 1) * mres * sizeof(double2), cbytes = (size_t)nrhs * (mres + 1) * sizeof(double2);
-    Scratch Rs(hbytes, s), Hs(hbytes, s), csb(nrhs * mres * sizeof(double2), s), snb(nrhs * mres * sizeof(double2), s),
-        gb(cbytes, s), d1b(cbytes, s), d2b(cbytes, s), d1t(cbytes, s), d2t(cbytes, s), hcb(cbytes, s),
-        abb(nrhs * sizeof(double2), s), dbl(5 * nrhs * sizeof(double), s), ints(3 * nrhs * sizeof(int32_t), s),
-        part(nrhs * np * sizeof(double), s);
-    // few 128-row update blocks (a single right-hand side): the basis range
-    // of each is split over up to 8 blocks, so that about 256 blocks stream
-    const int split = nrhs == 1 && np < 64 ? (int)std::min<int64_t>(8, (256 + np - 1) / np) : 1;
-    Scratch wsb(split > 1 ? (size_t)nrhs * np * split * 256 * sizeof(double2) : 0, s);
-    GmresState gs{Rs.as<double2>(),
-                  Hs.as<double2>(),
-                  csb.as<double2>(),
-                  snb.as<double2>(),
-                  gb.as<double2>(),
-                  d1b.as<double2>(),
-                  d2b.as<double2>(),
-                  abb.as<double2>(),
-                  dbl.as<double>(),
-                  dbl.as<double>() + nrhs,
-                  dbl.as<double>() + 2 * nrhs,
-                  dbl.as<double>() + 3 * nrhs,
-                  dbl.as<double>() + 4 * nrhs,
-                  ints.as<int32_t>(),
-                  ints.as<int32_t>() + nrhs,
-                  ints.as<int32_t>() + 2 * nrhs,
-                  d1t.as<double2>(),
-                  d2t.as<double2>(),
-                  hcb.as<double2>(),
-                  mres + 1,
-                  split,
-                  wsb.as<double2>()};
-    const int64_t vstride = nrhs * n;
-    const dim3 g1((unsigned)((nrhs + 63) / 64)), b1(64);
-    CBFM_HIP(hipMemsetAsync(x.p, 0, nrhs * n * sizeof(double2), s));
-    CBFM_HIP(hipMemsetAsync(gs.its, 0, nrhs * sizeof(int32_t), s));
-    hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, b.as<double2>(), n, gs.bnorm, nullptr);
-    std::vector<int32_t> its(nrhs, 0);
-    std::vector<double> res(nrhs, 1.0);
-    int64_t total = 0;
-    const double tol = prm->tol;
-    // Convergence flags go to pinned host memory every few iterations and are
-    // read one check later, so the host never waits for the device inside a
-    // cycle; iterations queued after the last right-hand side converged do
-    // nothing (every kernel skips inactive right-hand sides).
-    PinnedFlags flags(nrhs);
-    auto all_done = [&](const int32_t* a) {
-      return std::none_of(a, a + nrhs, [](int32_t v) { return v != 0; });
-    };
-    // w = A q_j for every Krylov index j, descriptors uploaded once
-    std::vector<std::vector<GemmDesc>> mv(f32 ? 0 : mres);
-    std::vector<std::vector<GemmDescX>> mvx(f32 ? mres : 0);
-    if (f32) {
-      hipLaunchKernelGGL(to_float_kernel, grid2(n, n), dim3(256), 0, s, Aop, lda, A32.as<float2>(), n, n, n);
+    } else if (prm->use_cmp == 2) {
+      // row r of Z_r Pi: row r of Z_r with its halves swapped
+      hipLaunchKernelGGL(swap_halves_kernel, grid2(n, n), dim3(256), 0, s, Zr, Ap.as<double2>(), NL, n, ldz, n);
       CBFM_HIP(hipGetLastError());
-      for (int64_t j = 0; j < mres; ++j) {
-        GemmDescX d = gemmx(A32.as<float2>(), 0, n, OP_N, V.as<float2>() + j * vstride, 0, n, OP_T, u.as<float2>(), 0, n,
-                            n, nrhs, n);
-        d.transC = 1;
-        mvx[j].push_back(d);
-      }
-    } else {
-      for (int64_t j = 0; j < mres; ++j) {
-        GemmDesc d = gemm(Aop, lda, OP_N, V.as<double2>() + j * vstride, n, OP_T, u.as<double2>(), n, n, nrhs, n);
-        d.transC = 1;
-        mv[j].push_back(d);
-      }
+      Aop = Ap.as<double2>();
+      lda = n;
     }
-    const GemmPlan matvec(mv, s);
-    const XGemmPlan matvec32(mvx, XG_FP32, s);
-    // graph replays: one matrix-vector descriptor repointed on the device
-    const bool graph = prm->use_graph != 0 && mres > 0;
-    std::unique_ptr<GemmPlan> dyn;
-    std::unique_ptr<XGemmPlan> dyn32;
-    Scratch jdev(graph ? sizeof(int64_t) : 0, s);
-    if (graph && f32) dyn32.reset(new XGemmPlan({mvx[0]}, XG_FP32, s));
-    if (graph && !f32) dyn.reset(new GemmPlan({mv[0]}, s, false));
-    for (;;) {
-      // r = b - A x in double  (x = 0 on the first cycle)
-      double2* r = f32 ? r64.as<double2>() : u.as<double2>();
-      if (total == 0) {
-        CBFM_HIP(hipMemcpyAsync(r, b.p, nrhs * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
-      } else {
-        apply_op(Aop, lda, n, nrhs, x.as<double2>(), r, s);
-        hipLaunchKernelGGL(sub_from_kernel, dim3((unsigned)((nrhs * n + 255) / 256)), dim3(256), 0, s, b.as<double2>(), r,
-                           nrhs * n);
-      }
-      hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, r, n, gs.nrm, nullptr);
-      hipLaunchKernelGGL(cycle_init_kernel, g1, b1, 0, s, gs, mres, nrhs, tol, inner);
-      if (f32)
-        hipLaunchKernelGGL(scale_kernel<float2>, grid2(n, nrhs), dim3(256), 0, s, r, V.as<float2>(), n, gs.nrm);
-      else
-        hipLaunchKernelGGL(scale_kernel<double2>, grid2(n, nrhs), dim3(256), 0, s, r, V.as<double2>(), n, gs.nrm);
-      if (all_done(flags.sync_read(gs.active, s)) || total >= prm->max_iter) break;
-      if (f32)
-        run_cycle(matvec32, dyn32.get(), dyn32 ? dyn32->desc(0) : nullptr, jdev.as<int64_t>(), V.as<float2>(),
-                  u.as<float2>(), vstride, n, nrhs, mres, prm->max_iter, total, gs, part.as<double>(), np, flags,
-                  x.as<double2>(), s);
-      else
-        run_cycle(matvec, dyn.get(), dyn ? dyn->desc(0) : nullptr, jdev.as<int64_t>(), V.as<double2>(),
-                  u.as<double2>(), vstride, n, nrhs, mres, prm->max_iter, total, gs, part.as<double>(), np, flags,
-                  x.as<double2>(), s);
-      if (total >= prm->max_iter) break;
-    }
-    CBFM_HIP(hipMemcpyAsync(its.data(), gs.its, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    // true relative residual of the preconditioned system
-    {
-      double2* r = f32 ? r64.as<double2>() : u.as<double2>();
-      apply_op(Aop, lda, n, nrhs, x.as<double2>(), r, s);
-      hipLaunchKernelGGL(sub_from_kernel, dim3((unsigned)((nrhs * n + 255) / 256)), dim3(256), 0, s, b.as<double2>(), r,
-                         nrhs * n);
-      hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, r, n, gs.nrm, nullptr);
-      std::vector<double> rn(nrhs), bn(nrhs);
-      CBFM_HIP(hipMemcpyAsync(rn.data(), gs.nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-      CBFM_HIP(hipMemcpyAsync(bn.data(), gs.bnorm, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-      CBFM_HIP(hipStreamSynchronize(s));
-      for (int64_t q = 0; q < nrhs; ++q) {
-        res[q] = bn[q] > 0 ? rn[q] / bn[q] : 0.0;
-        if (res[q] > tol) noconv = CBFM_E_NOCONV;
-      }
-    }
-    // j_CBF = G^{-1} x ; j = C^MJ j_CBF
+    GmresSpec sp;
+    sp.tol = prm->tol;
+    sp.max_iter = prm->max_iter;
+    sp.restart = prm->restart;
+    sp.f32 = prm->inner_fp32 != 0;
+    sp.inner_tol = prm->inner_tol;
+    sp.graph = prm->use_graph != 0;
+    Scratch x(nrhs * n * sizeof(double2), s);
+    DenseOp dop(Aop, lda, nullptr, 0);
+    FlexCmpOp fop(Zr, ldz, c, prm->cmp_inner_tol > 0 ? prm->cmp_inner_tol : 1e-5, n);
+    const GmresResult res =
+        gmres_run(flexible ? (KrylovOp&)fop : (KrylovOp&)dop, n, nrhs, b.as<double2>(), x.as<double2>(), sp, s);
+    noconv = res.noconv;
+    // j_CBF = G^{-1} x (CMP), x itself (flexible: the iterate is j_CBF), or
+    // Pi x (T-diagonal: [J CBFs; M CBFs] -> [M; J]); j = C^MJ j_CBF
     double2* jc = x.as<double2>();
-    if (use_cmp) cmp_apply_dev(c, nrhs, jc, s);
-    Scratch jint(nrhs * 2 * ne * sizeof(double2), s), jout(nrhs * 2 * ne * sizeof(double2), s);
-    {
-      std::vector<GemmDesc> ds;
-      for (int a = 0; a < nb; ++a) {
-        const int64_t Na = h.cell_off[a + 1] - h.cell_off[a], r0 = h.cell_off[a];
-        // alpha^M_a = C^M_a beta^M_a, alpha^J_a = C^J_a beta^J_a  (per vector: beta . C^T)
-        ds.push_back(gemm(jc + c->off[a], n, OP_N, c->CM.as<double2>() + c->coff[a], c->L[a], OP_T,
-                          jint.as<double2>() + r0, 2 * ne, nrhs, Na, c->L[a]));
-        ds.push_back(gemm(jc + NL + c->off[a], n, OP_N, c->CJ.as<double2>() + c->coff[a], c->L[a], OP_T,
-                          jint.as<double2>() + ne + r0, 2 * ne, nrhs, Na, c->L[a]));
-      }
-      zgemm_batched(ds, s);
-    }
-    double2* jfinal = j_dev ? static_cast<double2*>(j_dev) : jout.as<double2>();
-    hipLaunchKernelGGL(permute_kernel, grid2(ne, nrhs), dim3(256), 0, s, jint.as<double2>(), jfinal,
-                       m->perm.as<int32_t>(), ne, nrhs, 0);
-    CBFM_HIP(hipGetLastError());
-    // ---- RCS
-    if (rcs) {
-      const int64_t nd = dirs ? ndir : 1;
-      std::vector<double> hd(nrhs * nd * 3), hp;
-      if (dirs) {
-        for (int64_t q = 0; q < nrhs; ++q) std::memcpy(&hd[q * nd * 3], dirs, nd * 3 * sizeof(double));
-      } else {
-        hp.resize(nrhs * 3);
-        for (int64_t q = 0; q < nrhs; ++q)
-          for (int x3 = 0; x3 < 3; ++x3) {
-            hd[q * 3 + x3] = -inc[q * 6 + x3];
-            hp[q * 3 + x3] = inc[q * 6 + 3 + x3];
-          }
-      }
-      Scratch ddir(hd.size() * sizeof(double), s), dpol(hp.size() * sizeof(double), s),
-          dsig(nrhs * nd * sizeof(double), s);
-      CBFM_HIP(hipMemcpyAsync(ddir.p, hd.data(), hd.size() * sizeof(double), hipMemcpyHostToDevice, s));
-      if (!hp.empty()) CBFM_HIP(hipMemcpyAsync(dpol.p, hp.data(), hp.size() * sizeof(double), hipMemcpyHostToDevice, s));
-      FarArgs fa{};
-      fa.xyz9 = m->tri_xyz.as<double>();
-      fa.tri_edge = m->tri_edge.as<int32_t>();
-      fa.c64 = m->c64.as<double>();
-      fa.nt = h.nt;
-      fa.ne = ne;
-      const double s15 = std::sqrt(15.0);
-      const double qa = (6.0 - s15) / 21.0, qb = (6.0 + s15) / 21.0;
-      const double wa = (155.0 - s15) / 1200.0, wb = (155.0 + s15) / 1200.0;
-      const double Bq[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {1 - 2 * qa, qa, qa}, {qa, 1 - 2 * qa, qa}, {qa, qa, 1 - 2 * qa},
-                               {1 - 2 * qb, qb, qb},        {qb, 1 - 2 * qb, qb}, {qb, qb, 1 - 2 * qb}};
-      const double Wq[7] = {9.0 / 40.0, wa, wa, wa, wb, wb, wb};
-      std::memcpy(fa.bary, Bq, sizeof(Bq));
-      std::memcpy(fa.w, Wq, sizeof(Wq));
-      fa.k0 = med->k0;
-      fa.eta0 = med->eta0;
-      hipLaunchKernelGGL(farfield_kernel, dim3((unsigned)nd, (unsigned)nrhs), dim3(256), 0, s, fa, jfinal, ddir.as<double>(),
-                         hp.empty() ? nullptr : dpol.as<double>(), nd, dsig.as<double>());
+    Scratch jsw(prm->use_cmp == 2 ? nrhs * n * sizeof(double2) : 0, s);
+    if (prm->use_cmp == 1 && !flexible) cmp_apply_dev(c, nrhs, jc, s);
+    if (prm->use_cmp == 2) {
+      hipLaunchKernelGGL(swap_halves_kernel, grid2(n, nrhs), dim3(256), 0, s, jc, jsw.as<double2>(), NL, nrhs, n, n);
       CBFM_HIP(hipGetLastError());
-      CBFM_HIP(hipMemcpyAsync(rcs, dsig.p, nrhs * nd * sizeof(double), hipMemcpyDeviceToHost, s));
+      jc = jsw.as<double2>();
     }
+    Scratch jint(nrhs * 2 * ne * sizeof(double2), s), jout(nrhs * 2 * ne * sizeof(double2), s);
+    expand_cbf(m, c, jc, nrhs, jint.as<double2>(), s);
+    double2* jfinal = j_dev ? static_cast<double2*>(j_dev) : jout.as<double2>();
+    permute_halves(jint.as<double2>(), jfinal, m->perm.as<int32_t>(), ne, nrhs, 0, s);
+    if (rcs) rcs_compute(m, med, jfinal, inc, nrhs, dirs, ndir, rcs, s);
     CBFM_HIP(hipStreamSynchronize(s));
-    if (iters) std::memcpy(iters, its.data(), nrhs * sizeof(int32_t));
-    if (relres) std::memcpy(relres, res.data(), nrhs * sizeof(double));
-    if (noconv != CBFM_OK) set_error("GMRES did not reach the tolerance for every right-hand side");
+    if (iters) std::memcpy(iters, res.its.data(), nrhs * sizeof(int32_t));
+    if (relres) std::memcpy(relres, res.res.data(), nrhs * sizeof(double));
+    if (noconv) set_error("GMRES did not reach the tolerance for every right-hand side");
   });
-  return st != CBFM_OK ? st : noconv;
+  return st != CBFM_OK ? st : (noconv ? CBFM_E_NOCONV : CBFM_OK);
 }

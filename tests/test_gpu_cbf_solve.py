@@ -413,3 +413,47 @@ def test_batched_projection_matches_single(torch_cuda):
             assert e < tol
             if prec == cbfm.FP64:
                 assert _rel(zb.cpu().numpy(), O["Zr"]) < 1e-10
+
+
+def test_inexact_cmp_and_flexible_gmres(torch_cuda):
+    """The paper's inexact CMP through the C ABI: cmp_apply_ex with the inner
+    GMRES (D^CBF preconditioner) meets its allowance against the oracle's
+    G^CBF and reaches the exact inverse as the allowance goes to 0; the
+    reduced solve with the inexact CMP inside flexible GMRES reaches the LU
+    solution, and at the paper's 1e-5 inner allowance converges in about the
+    iterations of the exact CMP and of the oracle's flexible GMRES."""
+    from oracle import reduced
+    O = _oracle_cbf("cyl_small")
+    P = O["P"]
+    w, m = P["w"], P["m"]
+    cbfm, mesh, med, cbf = _gpu_handles(w, O)
+    n = cbf.n_cbf
+    from synth import configs
+    y = configs.random_complex((2, n), 32)
+    yt = torch_cuda.tensor(y, dtype=torch_cuda.complex128, device="cuda")
+    xt = torch_cuda.empty_like(yt)
+    Gc = O["Gc"]
+    xe = np.linalg.solve(Gc, y.T).T
+    cbfm.cmp_apply(cbf, yt, xt, mode=cbfm.CMP_INNER_GMRES, inner_tol=1e-13)
+    e0 = _rel(xt.cpu().numpy(), xe)
+    cbfm.cmp_apply(cbf, yt, xt, mode=cbfm.CMP_INNER_GMRES, inner_tol=1e-5)
+    x5 = xt.cpu().numpy()
+    res5 = np.linalg.norm(x5 @ Gc.T - y, axis=1) / np.linalg.norm(y, axis=1)
+    print("inner CMP: allowance 1e-13 error", e0, "allowance 1e-5 residuals", res5)
+    assert e0 < 1e-9 and np.all(res5 <= 1e-5)
+    Zr = torch_cuda.tensor(O["Zr"], dtype=torch_cuda.complex128, device="cuda")
+    jt = torch_cuda.zeros((len(w.inc), 2 * m.ne), dtype=torch_cuda.complex128, device="cuda")
+    out = cbfm.solve(mesh, med, cbf, Zr, w.inc, tol=1e-12, max_iter=n + 10, restart=n + 10, j_out=jt,
+                     cmp_mode=cbfm.CMP_INNER_GMRES, cmp_inner_tol=1e-10)
+    jref = O["CMJ"] @ np.linalg.solve(O["Zr"], O["vr"])
+    print("flexible GMRES, inner 1e-10:", out["iters"], out["status"])
+    assert out["status"] == "OK" and _rel(jt.cpu().numpy().T, jref) < 1e-9
+    ex = cbfm.solve(mesh, med, cbf, Zr, w.inc, tol=1e-6, max_iter=n + 10, restart=n + 10)
+    inx = cbfm.solve(mesh, med, cbf, Zr, w.inc, tol=1e-6, max_iter=n + 10, restart=n + 10, j_out=jt,
+                     cmp_mode=cbfm.CMP_INNER_GMRES, cmp_inner_tol=1e-5)
+    ora = [reduced.fgmres(lambda u: O["Zr"] @ u, lambda q: reduced.cmp_inner(Gc, q, 1e-5)[:, 0], O["vr"][:, c], 1e-6,
+                          n + 10, n + 10)[1] for c in range(O["vr"].shape[1])]
+    print("iterations to 1e-6: exact CMP", ex["iters"], "inexact (GPU)", inx["iters"], "inexact (oracle)", ora)
+    assert inx["status"] == "OK" and np.all(inx["relres"] <= 1e-6)
+    assert np.all(np.abs(inx["iters"] - np.array(ora)) <= 2) and np.all(inx["iters"] <= ex["iters"] + 5)
+    assert _rel(jt.cpu().numpy().T, jref) < 1e-4

@@ -110,3 +110,28 @@ def test_rhs_parity(torch_cuda):
     got = out.cpu().numpy().T
     ref = excitation.rhs(m, inc, w.k0, w.eta0)
     assert _rel(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["c1", "cyl_lossy"])
+def test_fill_media4_parity(torch_cuda, case):
+    """The MEDIA4 layout [K1, K2, T1, T2] against the oracle's fill of each
+    medium apart (FP64 to 1e-10, FP32 fill to 2e-5), normwise and
+    elementwise."""
+    from oracle import fill
+    from paper_2111_11058_amd import cbfm
+    P = oracle_problem(case)
+    w, m = P["w"], P["m"]
+    ref = fill.fill_media(m, P["k"])
+    mesh = cbfm.Mesh(w.V, w.T, w.edge_block, w.nblocks)
+    med = cbfm.Medium.make(w.k0, w.eta0, w.eps_r, w.mu_r)
+    ne = mesh.ne
+    for prec, dt, tol in ((cbfm.FP64, torch_cuda.complex128, TOL64), (cbfm.FP32, torch_cuda.complex64, 2e-5)):
+        out = torch_cuda.full((4, ne, ne), complex(np.nan, np.nan), dtype=dt, device="cuda")
+        print(f"media4 {w.name} prec {prec}", flush=True)
+        cbfm.fill_pmchwt(mesh, med, out, prec, cbfm.LAYOUT_MEDIA4)
+        got = out.cpu().numpy().astype(np.complex128)
+        for o, name_o in enumerate(["K1", "K2", "T1", "T2"]):
+            r = _rel(got[o], ref[o])
+            e = np.abs(got[o] - ref[o]).max() / np.abs(ref[o]).max()
+            print(name_o, prec, r, e)
+            assert r < tol and e < tol, (name_o, r, e)

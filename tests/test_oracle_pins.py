@@ -493,3 +493,44 @@ def test_rmse_closed_forms():
     assert abs(mom.rmse_db(sm + 0.04, sm) - 10 * np.log10(0.01)) < 1e-12
     e = np.sin(np.arange(31.0))
     assert abs(mom.rmse_db(sm + 2 * e, sm) - mom.rmse_db(sm + e, sm) - 10 * np.log10(2)) < 1e-12
+
+
+def test_media_apart_sum_to_the_combined_fill():
+    """K1 and K2 filled apart (one medium each) sum to the fill of both
+    media, and T1, T2 are the combined fill's (the K operator is linear in
+    the media's kernels g_i)."""
+    P = oracle_problem("c1")
+    K1, K2, T1, T2 = fill.fill_media(P["m"], P["k"])
+    assert np.abs(K1 + K2 - P["Kop"]).max() <= 1e-13 * np.abs(P["Kop"]).max()
+    assert np.array_equal(T1, P["T1"]) and np.array_equal(T2, P["T2"])
+    assert np.abs(K1 - K2).max() > 1e-3 * np.abs(K1).max()  # the media differ
+
+
+def test_inexact_cmp_and_flexible_gmres():
+    """The inexact inner CMP (GMRES with D^CBF) reaches the exact inverse as
+    its allowance goes to 0 and meets its allowance otherwise; flexible
+    GMRES with the exact inverse takes the iterations of right-preconditioned
+    GMRES and reaches LU; with the inexact inner solve at the paper's 1e-5
+    it still reaches the LU solution of the reduced system."""
+    P = oracle_problem("cyl_small")
+    w, m = P["w"], P["m"]
+    cb = cbf.build(m, P["Kc"], P["TE"], P["TH"], w.edge_block, w.gen, w.k0, w.eta0, 1e-3)
+    CJM, CMJ = reduced.cbf_matrices(cb, m.ne)
+    Zr = reduced.project(P["Z"], CJM, CMJ)
+    Gc = reduced.gram_cbf(cbf.rwg_gram(m), CJM, CMJ)
+    n = Gc.shape[0]
+    y = configs.random_complex((n, 2), 31)
+    xe = np.linalg.solve(Gc, y)
+    x0 = reduced.cmp_inner(Gc, y, 1e-14)
+    assert np.linalg.norm(x0 - xe) <= 1e-8 * np.linalg.norm(xe)
+    x5 = reduced.cmp_inner(Gc, y, 1e-5)
+    assert np.all(np.linalg.norm(Gc @ x5 - y, axis=0) <= 1e-5 * np.linalg.norm(y, axis=0))
+    vr = CJM.conj().T @ P["v"][:, 0]
+    Gi = np.linalg.inv(Gc)
+    ref = np.linalg.solve(Zr, vr)
+    yv, it_r, _ = reduced.gmres(lambda u: Zr @ (Gi @ u), vr, 1e-10, n, n)
+    xf, it_f, _ = reduced.fgmres(lambda u: Zr @ u, lambda q: Gi @ q, vr, 1e-10, n, n)
+    assert it_f == it_r and np.linalg.norm(xf - Gi @ yv) <= 1e-8 * np.linalg.norm(ref)
+    assert np.linalg.norm(xf - ref) <= 1e-8 * np.linalg.norm(ref)
+    xi, it_i, _ = reduced.fgmres(lambda u: Zr @ u, lambda q: reduced.cmp_inner(Gc, q, 1e-5)[:, 0], vr, 1e-12, n, n)
+    assert np.linalg.norm(xi - ref) <= 1e-9 * np.linalg.norm(ref)
