@@ -231,6 +231,26 @@ cbfm_status cbfm_fill_pmchwt(cbfm_mesh m, const cbfm_medium* med, int32_t precis
                              int64_t row0, int64_t nrow, int64_t col0, int64_t ncol,
                              int32_t layout, void* out_dev, int64_t ld, void* stream);
 
+/* cbfm_fill_pmchwt_noalloc: cbfm_fill_pmchwt (same arguments, same
+ * results) for callers that cannot allocate device memory -- code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation: it calls no hipMalloc, hipFree or other allocating routine.
+ * Its workspace (index tables, near-pair intermediates, triangle-local
+ * blocks) is a library array of CBFM_FILL_NOALLOC_MAX_BYTES bytes per
+ * device, held from the first call on that device until the process ends;
+ * ranges whose workspace exceeds it (about 27 x (triangles touching the
+ * rows) x (triangles touching the columns) x 16 bytes in FP64, 8 in FP32)
+ * are rejected with CBFM_E_ARG before any device work.  Every call on a
+ * device shares that device's array: calls that overlap on one device (on
+ * several streams or host threads) race and must be serialised by the
+ * caller.  Nothing in the array needs clearing between calls.
+ * Synchronises the stream, as cbfm_fill_pmchwt does.                      */
+#define CBFM_FILL_NOALLOC_MAX_BYTES (64ll << 20)
+/* (the MEDIA4 layout is not offered by the allocation-free fill) */
+cbfm_status cbfm_fill_pmchwt_noalloc(cbfm_mesh m, const cbfm_medium* med, int32_t precision,
+                                     int64_t row0, int64_t nrow, int64_t col0, int64_t ncol,
+                                     int32_t layout, void* out_dev, int64_t ld, void* stream);
+
 /* cbfm_rhs: tested incident plane waves (paper Sec. II-B, v^E and v^H):
    v = [v^E ; v^H] with v^E_m = int f_m . E_inc, v^H_m = -int f_m . H_inc,
    E_inc = p exp(-j k0 k . r), H_inc = k x E_inc / eta0, 7-point rule.

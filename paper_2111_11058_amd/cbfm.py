@@ -93,6 +93,8 @@ def lib():
         "cbfm_mesh_analyze": (_I32, [_P, _I64, _P, _I64, _P, _I32, C.POINTER(_I64), _P, _P, _P,
                                      C.POINTER(_I64), _P, _I64]),
         "cbfm_fill_pmchwt": (_I32, [_P, C.POINTER(Medium), _I32, _I64, _I64, _I64, _I64, _I32, _P, _I64, _P]),
+        "cbfm_fill_pmchwt_noalloc": (_I32, [_P, C.POINTER(Medium), _I32, _I64, _I64, _I64, _I64, _I32, _P, _I64,
+                                            _P]),
         "cbfm_rhs": (_I32, [_P, C.POINTER(Medium), _P, _I64, _P, _P]),
         "cbfm_build_cbf": (_I32, [_P, C.POINTER(Medium), C.POINTER(CbfParams), _P, C.POINTER(_P)]),
         "cbfm_cbf_import": (_I32, [_P, _P, _P, _P, _P, _P, C.POINTER(_P)]),
@@ -276,18 +278,22 @@ class Mesh:
             pass
 
 
+FILL_NOALLOC_MAX_BYTES = 64 << 20  # CBFM_FILL_NOALLOC_MAX_BYTES
+
+
 def fill_pmchwt(mesh: Mesh, medium: Medium, out, precision=FP64, layout=LAYOUT_MEDIA3,
-                row0=0, nrow=None, col0=0, ncol=None, ld=None, stream=None):
+                row0=0, nrow=None, col0=0, ncol=None, ld=None, stream=None, noalloc=False):
     """cbfm_fill_pmchwt into ``out`` (3 x nrow x ld complex tensor, 4 x for
-    LAYOUT_MEDIA4)."""
+    LAYOUT_MEDIA4); with noalloc, cbfm_fill_pmchwt_noalloc (the library's
+    fixed workspace)."""
     import torch
     nrow = mesh.ne - row0 if nrow is None else nrow
     ncol = mesh.ne - col0 if ncol is None else ncol
     ld = ncol if ld is None else ld
     dt = torch.complex128 if precision == FP64 else torch.complex64
     p = _dev(out, dt, (4 if layout == LAYOUT_MEDIA4 else 3) * nrow * ld, "out")
-    _check(lib().cbfm_fill_pmchwt(mesh.handle, C.byref(medium), precision, row0, nrow, col0, ncol, layout, p, ld,
-                                  _stream(stream)))
+    f = lib().cbfm_fill_pmchwt_noalloc if noalloc else lib().cbfm_fill_pmchwt
+    _check(f(mesh.handle, C.byref(medium), precision, row0, nrow, col0, ncol, layout, p, ld, _stream(stream)))
     return out
 
 

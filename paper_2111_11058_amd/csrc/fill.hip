@@ -999,6 +999,30 @@ static void fill_check(cbfm_mesh m, int32_t precision, int64_t row0, int64_t nro
   CBFM_REQUIRE(ld >= ncol, CBFM_E_ARG, "ld < ncol");
 }
 
+// ------------------------------------------------------------- allocation-free fill
+// Workspace of cbfm_fill_pmchwt_noalloc: one array per device, held until
+// the process ends.  Host code never uses the array's name as an address:
+// the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoAllocBytes = (size_t)CBFM_FILL_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static char* noalloc_scratch() {
+  int dev = 0;
+  CBFM_HIP(hipGetDevice(&dev));
+  CBFM_REQUIRE(dev >= 0 && dev < kMaxDevices, CBFM_E_ARG, "device index above the workspace table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    CBFM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    CBFM_REQUIRE(ptr != nullptr, CBFM_E_HIP, "no device address for the fill workspace");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return static_cast<char*>(g_scratch_ptr[dev]);
+}
+
 }  // namespace cbfm
 
 extern "C" cbfm_status cbfm_fill_pmchwt(cbfm_mesh m, const cbfm_medium* med, int32_t precision, int64_t row0,
@@ -1036,6 +1060,20 @@ extern "C" cbfm_status cbfm_fill_pmchwt(cbfm_mesh m, const cbfm_medium* med, int
                          (cx<float>*)(o + mat), ncol, ld);
     CBFM_HIP(hipGetLastError());
     CBFM_HIP(hipStreamSynchronize(s));
+  });
+}
+
+extern "C" cbfm_status cbfm_fill_pmchwt_noalloc(cbfm_mesh m, const cbfm_medium* med, int32_t precision, int64_t row0,
+                                                int64_t nrow, int64_t col0, int64_t ncol, int32_t layout,
+                                                void* out_dev, int64_t ld, void* stream) {
+  return guarded([&] {
+    fill_check(m, precision, row0, nrow, col0, ncol, layout, out_dev, ld);
+    CBFM_REQUIRE(layout != CBFM_LAYOUT_MEDIA4, CBFM_E_ARG, "the allocation-free fill has no MEDIA4 layout");
+    const Media md = make_media(med);
+    if (nrow == 0 || ncol == 0) return;
+    char* ws = noalloc_scratch();
+    fill_ranges(m, md, precision, row0, nrow, col0, ncol, layout, out_dev, ld, static_cast<hipStream_t>(stream), ws,
+                kNoAllocBytes);
   });
 }
 
