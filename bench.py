@@ -350,6 +350,92 @@ def cpu_baseline(name, sample, cores, seed=5):
             "host": {"cpu_count": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}}
 
 
+def rmse_db(sig_c, sig_m):
+    """RMSE of the CBFM RCS against the MoM RCS over the observation angles
+    (linear sigma; 10 log10 of the rms difference over the MoM range)."""
+    sig_c, sig_m = np.asarray(sig_c, float), np.asarray(sig_m, float)
+    return float(10.0 * np.log10(np.sqrt(np.mean((sig_c - sig_m) ** 2)) / (sig_m.max() - sig_m.min())))
+
+
+def plane_incidences(theta_deg):
+    """Monostatic theta-polarised incidences from the directions theta
+    (degrees), phi = 0: arrival direction r(theta, 0), k = -r, p = theta-hat."""
+    from synth import configs
+    th = np.deg2rad(np.asarray(theta_deg, float))
+    r, t, _ = configs.sph_dir(th, np.zeros_like(th))
+    return np.concatenate([-r, t], axis=1)
+
+
+def ipcbf_leg(cbfm, torch, w, mesh, med, prec, primary_rcs, primary_its, primary_ms, solver, delta_r=1e-2):
+    """IPCBF (the GMRES version of Sec. III-A) on the bench workload, with the
+    paper's cylinder conditions: s = 10 theta-polarised generating waves in
+    the phi = 0 plane (theta_s = 0, 5 degree steps), delta_svd 1e-3; then
+    the same projection and CMP solve of the bench incidences (all in that
+    plane).  Step time = FP32 operator fill + IPCBF GMRES + orthogonalisation
+    + projection + solve.  RCS against an FP64 MoM solve (the stored FP64
+    operator, GMRES to 1e-6) as RMSE (Sec. IV-A) beside the primary CBFs'."""
+    gen = plane_incidences(np.arange(10) * 5.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = cbfm.MomOperator(mesh, med, cbfm.FP32)
+    t1 = time.perf_counter()
+    cb, its, res = cbfm.build_ipcbf(op, gen, delta_r=delta_r, delta_svd=1e-3, max_iter=1000)
+    t2 = time.perf_counter()
+    op.close()
+    n = cb.n_cbf
+    Zr = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    cbfm.project(mesh, med, cb, Zr, prec)
+    torch.cuda.current_stream().synchronize()
+    t3 = time.perf_counter()
+    out = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, max_iter=3000, restart=min(n, 1000), **solver)
+    t4 = time.perf_counter()
+    leg = {"generating_waves": len(gen), "delta_r": delta_r, "delta_svd": 1e-3, "n_cbf": int(n),
+           "ipcbf_gmres_iterations": [int(i) for i in its], "ipcbf_residual_max": float(res.max()),
+           "gmres_iterations": {"mean": float(out["iters"].mean()), "max": int(out["iters"].max())},
+           "status": out["status"], "ms": {"operator_fill_fp32": (t1 - t0) * 1e3, "ipcbf_gmres_and_svd": (t2 - t1) * 1e3,
+                                           "projection": (t3 - t2) * 1e3, "solve": (t4 - t3) * 1e3,
+                                           "step": (t4 - t0) * 1e3},
+           "primary_cbfs": {"gmres_iterations_max": int(primary_its), "ms_per_step": primary_ms}}
+    del Zr
+    # MoM reference (FP64 operator)
+    t5 = time.perf_counter()
+    op64 = cbfm.MomOperator(mesh, med, cbfm.FP64)
+    mom = cbfm.mom_solve(op64, w.inc, tol=1e-6, max_iter=3000, restart=1000)
+    t6 = time.perf_counter()
+    op64.close()
+    leg["mom_fp64"] = {"gmres_iterations_max": int(mom["iters"].max()), "status": mom["status"],
+                       "ms": (t6 - t5) * 1e3}
+    leg["rmse_db_vs_mom"] = {"ipcbf": rmse_db(out["rcs"], mom["rcs"]), "primary": rmse_db(primary_rcs, mom["rcs"])}
+    return leg
+
+
+def mom_leg(cbfm, torch, w, mesh, med, cb, Zr, solver):
+    """The paper's comparison on its arrays (Sec. IV-A, IV-B): iterations to
+    1e-6 of the MoM (its arrangement with the diagonal preconditioner, on the
+    stored FP64 operator), the K-diagonal CBFM without the CMP, the
+    T-diagonal CBFM and the CBFM with the CMP, for the theta-polarised wave
+    along -z; and the RMSE of the CBFM RCS against the MoM RCS over
+    0 <= theta <= 30 degrees, 1 degree steps, phi = 0 (both to 1e-4)."""
+    op = cbfm.MomOperator(mesh, med, cbfm.FP64)
+    inc = w.inc
+    n = cb.n_cbf
+    t0 = time.perf_counter()
+    mom = cbfm.mom_solve(op, inc, tol=1e-6, max_iter=1000, restart=1000)
+    t1 = time.perf_counter()
+    legs = {"mom": {"iterations": int(mom["iters"].max()), "status": mom["status"],
+                    "relres": float(mom["relres"].max()), "ms": (t1 - t0) * 1e3}}
+    for name, uc in (("cbfm_cmp", 1), ("cbfm_k_diagonal_no_cmp", 0), ("cbfm_t_diagonal", 2)):
+        o = cbfm.solve(mesh, med, cb, Zr, inc, tol=1e-6, max_iter=1000, restart=1000, use_cmp=uc)
+        legs[name] = {"iterations": int(o["iters"].max()), "status": o["status"], "relres": float(o["relres"].max())}
+    incs = plane_incidences(np.arange(31) * 1.0)
+    a = cbfm.mom_solve(op, incs, tol=1e-4, max_iter=2000, restart=1000)
+    b = cbfm.solve(mesh, med, cb, Zr, incs, tol=1e-4, max_iter=2000, restart=min(n, 1000), use_cmp=True)
+    op.close()
+    legs["rmse_db"] = rmse_db(b["rcs"], a["rcs"])
+    legs["rcs_directions"] = "0..30 deg, 1 deg, phi 0, theta-hat, monostatic, both solves to 1e-4"
+    return legs
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -373,6 +459,8 @@ def main():
                     help="requests of the serving leg (mixed-size stream, Poisson arrivals); 0 skips it")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg (both budgets)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--no-ipcbf", action="store_true", help="skip the IPCBF leg of the cylinder workload")
+    ap.add_argument("--mom", action="store_true", help="array workloads: the MoM, K-/T-diagonal and RMSE leg")
     args = ap.parse_args()
     cores = args.cpu_cores or min(16, len(os.sched_getaffinity(0)))
     if args.cpu_baseline_only:
@@ -507,6 +595,15 @@ def main():
                               "rcs_max_rel_err_of_timed_step": float(np.max(np.abs(out["rcs"] - rcs_ref) / rcs_ref)),
                               "roofline_kernels": r64}
         log(f"fp64 leg: {result['fp64_leg']}")
+    if args.workload == "cylinder19968" and not args.no_ipcbf:
+        log("ipcbf leg")
+        result["ipcbf"] = ipcbf_leg(cbfm, torch, w, mesh, med, PREC, out["rcs"], int(out["iters"].max()),
+                                    result["ms_per_step"], solver)
+        log(f"ipcbf: {result['ipcbf']}")
+    if w.extra.get("max_L") and args.mom:
+        log("mom leg")
+        result["mom_comparison"] = mom_leg(cbfm, torch, w, mesh, med, cb, state[cb.n_cbf], solver)
+        log(f"mom: {result['mom_comparison']}")
     if w.extra.get("max_L"):
         # the paper's comparison on its array: the same CBFs solved without
         # the CMP (the K-diagonal CBFM without G^CBF), full GMRES up to 1000
