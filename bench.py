@@ -161,6 +161,120 @@ def write_traffic(workload_name, fetch_dir, write_dir, cfetch_dir, cwrite_dir, c
     print("\n".join(lines))
 
 
+# counter passes (one rocprofv3 --pmc run each; at most 8 SQ and 2 GRBM)
+COUNTER_PASSES = {
+    "valu_a": ["SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_TRANS_F64",
+               "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_TRANS_F32"],
+    "valu_b": ["SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_VALU_INT32", "SQ_INSTS_VALU_INT64",
+               "SQ_INSTS_VALU_CVT", "SQ_INSTS_SALU", "SQ_WAVES", "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE"],
+    "mfma": ["SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_XF32",
+             "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_INSTS_VALU_MFMA_F64", "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE"],
+}
+COUNTER_KERNELS = {  # label -> (symbol substring, source)
+    "fill_regular_fp64": ("fill_regular_kernel<double, false>", "paper_2111_11058_amd/csrc/fill.hip"),
+    "fill_regular_f32": ("fill_regular_kernel<float, false>", "paper_2111_11058_amd/csrc/fill.hip"),
+    "zgemm": ("zgemm_batched_kernel", "paper_2111_11058_amd/csrc/gemm.hip"),
+    "xgemm": ("xgemm_batched_kernel", "paper_2111_11058_amd/csrc/gemm.hip"),
+}
+N_SIMD = 256 * 4
+N_XCD = 8
+
+
+def write_counters(workload_name, stats_dir, dirs, cmd):
+    """Per-dispatch VALU and MFMA counters of the fill and GEMM kernels from
+    the rocprofv3 --pmc passes in COUNTER_PASSES (folders ``dirs``, in that
+    order) and the kernel durations of a --kernel-trace --stats run of the
+    same command (``stats_dir``): issued FP64/FP32 VALU flops per dispatch
+    (64 lanes x (2 FMA + ADD + MUL) instructions; full wavefronts),
+    VALU-issue and MFMA-busy fractions, written to
+    profiles/valu_mfma_counters_<workload>.txt."""
+    import csv
+    from collections import defaultdict
+
+    def groups(d):
+        """(kernel label, grid size) -> {counter: [per-dispatch values]}"""
+        per = defaultdict(lambda: defaultdict(float))
+        key = {}
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            for lab, (sub, _) in COUNTER_KERNELS.items():
+                if sub in r["Kernel_Name"]:
+                    did = r["Dispatch_Id"]
+                    key[did] = (lab, int(r["Grid_Size"]))
+                    per[did][r["Counter_Name"]] += float(r["Counter_Value"])
+        out = defaultdict(lambda: defaultdict(list))
+        for did, vals in per.items():
+            for c, v in vals.items():
+                out[key[did]][c].append(v)
+        return out
+
+    def durations(d):
+        """(kernel label, grid size) -> mean duration in ns (kernel trace)"""
+        acc = defaultdict(list)
+        for r in csv.DictReader(open(os.path.join(d, "run_kernel_trace.csv"))):
+            for lab, (sub, _) in COUNTER_KERNELS.items():
+                if sub in r["Kernel_Name"]:
+                    g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+                    acc[(lab, g)].append(float(r["End_Timestamp"]) - float(r["Start_Timestamp"]))
+        return {k: float(np.mean(v)) for k, v in acc.items()}
+
+    merged = defaultdict(dict)
+    for d in dirs:
+        for k, cs in groups(d).items():
+            for c, v in cs.items():
+                merged[k][c] = float(np.mean(v))
+                merged[k]["dispatches"] = len(v)
+    dur = durations(stats_dir)
+    lines = [f"# VALU and MFMA counters per dispatch, {workload_name} bench step, from rocprofv3 --pmc",
+             f"# command: {cmd}",
+             "# passes: " + "; ".join(f"{p}: {' '.join(c)}" for p, c in COUNTER_PASSES.items()),
+             "# issued_fp64_tflops = 64 (2 FMA_F64 + ADD_F64 + MUL_F64) / duration (likewise FP32);"
+             " valu_issue = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs);"
+             " mfma_busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs);"
+             " mfma_f64_tflops = 512 MOPS_F64 / duration; durations from the kernel trace of the same command"]
+    for src in sorted({src for _, src in COUNTER_KERNELS.values()}):
+        lines.append(f"# source {src} sha256={hashlib.sha256(open(os.path.join(ROOT, src), 'rb').read()).hexdigest()}")
+    small = defaultdict(lambda: [0, 0])
+    for (lab, grid), c in sorted(merged.items()):
+        ns = dur.get((lab, grid))
+        if not lab.startswith("fill") and (ns or 0) < 1e6 and c.get("dispatches", 0) < 100:
+            small[lab][0] += 1  # short, rare launches (Gauss-Jordan steps, CBF-build GEMMs)
+            small[lab][1] += c.get("dispatches", 0)
+            continue
+        sub, src = COUNTER_KERNELS[lab]
+        f64 = 64.0 * (2 * c.get("SQ_INSTS_VALU_FMA_F64", 0) + c.get("SQ_INSTS_VALU_ADD_F64", 0)
+                      + c.get("SQ_INSTS_VALU_MUL_F64", 0))
+        f32 = 64.0 * (2 * c.get("SQ_INSTS_VALU_FMA_F32", 0) + c.get("SQ_INSTS_VALU_ADD_F32", 0)
+                      + c.get("SQ_INSTS_VALU_MUL_F32", 0))
+        parts = [f"kernel={lab} grid={grid} dispatches={c.get('dispatches', 0)}"]
+        if ns:
+            parts.append(f"duration_us={ns / 1e3:.1f}")
+        if f64 or f32:
+            parts.append(f"fp64_valu_flop={f64:.4g} fp32_valu_flop={f32:.4g}")
+            if ns:
+                parts.append(f"issued_fp64_tflops={f64 / ns / 1e3:.2f} issued_fp32_tflops={f32 / ns / 1e3:.2f}")
+            parts.append(f"trans_f64={c.get('SQ_INSTS_VALU_TRANS_F64', 0):.4g} "
+                         f"trans_f32={c.get('SQ_INSTS_VALU_TRANS_F32', 0):.4g}")
+        gui = c.get("GRBM_GUI_ACTIVE")
+        if gui:
+            gui /= N_XCD  # the counter is summed over the XCDs; each runs for the whole dispatch
+        if "SQ_INSTS_VALU" in c and gui:
+            parts.append(f"valu_insts={c['SQ_INSTS_VALU']:.4g} valu_issue={4 * c['SQ_INSTS_VALU'] / (N_SIMD * gui):.3f} "
+                         f"int32={c.get('SQ_INSTS_VALU_INT32', 0):.4g} cvt={c.get('SQ_INSTS_VALU_CVT', 0):.4g} "
+                         f"salu={c.get('SQ_INSTS_SALU', 0):.4g} gui_cycles={gui:.4g}")
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in c and gui:
+            m64 = 512.0 * c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0)
+            parts.append(f"mfma_busy={c['SQ_VALU_MFMA_BUSY_CYCLES'] / (N_SIMD * gui):.3f} mfma_f64_flop={m64:.4g}")
+            if ns:
+                parts.append(f"mfma_f64_tflops={m64 / ns / 1e3:.2f}")
+        lines.append(" ".join(parts))
+    for lab, (g, n) in small.items():
+        lines.append(f"# {lab}: {g} further launch shapes ({n} dispatches) under 1 ms and under 100 dispatches each")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"valu_mfma_counters_{workload_name}.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def read_families(cbfm, traffic, phase):
     """Achieved rate of every timed family since the last timer_enable."""
     rows = {}
@@ -366,7 +480,8 @@ def plane_incidences(theta_deg):
     return np.concatenate([-r, t], axis=1)
 
 
-def ipcbf_leg(cbfm, torch, w, mesh, med, prec, primary_rcs, primary_its, primary_ms, solver, delta_r=1e-2):
+def ipcbf_leg(cbfm, torch, w, mesh, med, prec, primary_rcs, primary_its, primary_ms, solver, delta_r=1e-2,
+              gen=None):
     """IPCBF (the GMRES version of Sec. III-A) on the bench workload, with the
     paper's cylinder conditions: s = 10 theta-polarised generating waves in
     the phi = 0 plane (theta_s = 0, 5 degree steps), delta_svd 1e-3; then
@@ -374,7 +489,7 @@ def ipcbf_leg(cbfm, torch, w, mesh, med, prec, primary_rcs, primary_its, primary
     plane).  Step time = FP32 operator fill + IPCBF GMRES + orthogonalisation
     + projection + solve.  RCS against an FP64 MoM solve (the stored FP64
     operator, GMRES to 1e-6) as RMSE (Sec. IV-A) beside the primary CBFs'."""
-    gen = plane_incidences(np.arange(10) * 5.0)
+    gen = plane_incidences(np.arange(10) * 5.0) if gen is None else gen
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     op = cbfm.MomOperator(mesh, med, cbfm.FP32)
@@ -455,11 +570,16 @@ def main():
     ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the traffic summary from four rocprofv3 --pmc output folders (no GPU use)")
     ap.add_argument("--traffic-command", default="", help="command line recorded in the traffic summary")
+    ap.add_argument("--write-counters", nargs=4, metavar=("STATS", "VALU_A", "VALU_B", "MFMA"),
+                    help="write the VALU/MFMA counter summary from a --kernel-trace --stats folder and three "
+                         "rocprofv3 --pmc folders (no GPU use)")
     ap.add_argument("--serve", type=int, default=32,
                     help="requests of the serving leg (mixed-size stream, Poisson arrivals); 0 skips it")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg (both budgets)")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--no-ipcbf", action="store_true", help="skip the IPCBF leg of the cylinder workload")
+    ap.add_argument("--ipcbf", action="store_true",
+                    help="other workloads: the IPCBF leg with the Table-I generating waves")
     ap.add_argument("--mom", action="store_true", help="array workloads: the MoM, K-/T-diagonal and RMSE leg")
     args = ap.parse_args()
     cores = args.cpu_cores or min(16, len(os.sched_getaffinity(0)))
@@ -468,6 +588,9 @@ def main():
         return
     if args.write_traffic:
         write_traffic(args.workload, *args.write_traffic, args.traffic_command)
+        return
+    if args.write_counters:
+        write_counters(args.workload, args.write_counters[0], args.write_counters[1:], args.traffic_command)
         return
     if args.copy_calibration:
         import torch
@@ -595,10 +718,13 @@ def main():
                               "rcs_max_rel_err_of_timed_step": float(np.max(np.abs(out["rcs"] - rcs_ref) / rcs_ref)),
                               "roofline_kernels": r64}
         log(f"fp64 leg: {result['fp64_leg']}")
-    if args.workload == "cylinder19968" and not args.no_ipcbf:
+    if (args.workload == "cylinder19968" and not args.no_ipcbf) or args.ipcbf:
+        # the cylinder: the paper's in-plane generating waves (its incidences
+        # lie in that plane); otherwise the Table-I waves of the primary CBFs
         log("ipcbf leg")
         result["ipcbf"] = ipcbf_leg(cbfm, torch, w, mesh, med, PREC, out["rcs"], int(out["iters"].max()),
-                                    result["ms_per_step"], solver)
+                                    result["ms_per_step"], solver,
+                                    gen=None if args.workload == "cylinder19968" else w.gen)
         log(f"ipcbf: {result['ipcbf']}")
     if w.extra.get("max_L") and args.mom:
         log("mom leg")

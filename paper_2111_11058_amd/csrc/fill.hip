@@ -32,6 +32,8 @@ namespace cbfm {
 
 struct FillConsts {
   double w[7];
+  double wq[7][7];            // w_k w_l / (4 pi): point-pair weights of the regular rule
+  float wqf[7][7];
   double bary[7][3];
   double k1, k2r, k2i;
   double rev1, rev2;          // k / (2 pi): phase in revolutions (FP32 path)
@@ -76,6 +78,10 @@ static FillConsts make_consts(const Media& md, int layout) {
   for (int k = 0; k < 7; ++k) {
     fc.w[k] = W[k];
     for (int i = 0; i < 3; ++i) fc.bary[k][i] = B[k][i];
+    for (int l = 0; l < 7; ++l) {
+      fc.wq[k][l] = W[k] * W[l] * (0.25 / M_PI);
+      fc.wqf[k][l] = (float)fc.wq[k][l];
+    }
   }
   fc.k1 = md.k1;
   fc.k2r = md.k2r;
@@ -123,41 +129,40 @@ static FillConsts make_consts(const Media& md, int layout) {
 
 // ------------------------------------------------------------- phase helpers
 // sin and cos of 2 pi x, x in revolutions: x = n / 2 + f with n = rint(2 x),
-// |f| <= 1/4 (the subtraction loses at most an ulp of 1/4), theta = 2 pi f
-// in [-pi/2, pi/2], Taylor series of sin to theta^21 / 21! and of cos to
-// theta^22 / 22! (remainders below 2e-18 there); a half turn only flips
+// |f| <= 1/4 (the subtraction is exact), then with u = f^2
+//   sin(2 pi f) = f S(u),  cos(2 pi f) = C(u),
+// S and C polynomials of degree 8 in u on [0, 1/16]: near-minimax fits
+// (Chebyshev interpolation of sin(2 pi sqrt u) / sqrt u and
+// cos(2 pi sqrt u) at 9 nodes, computed in 50-digit arithmetic; fit error
+// 1.3e-18 and 3.9e-18, under a quarter ulp of the results, so that the
+// Horner evaluation in FP64 stays within an ulp).  A half turn only flips
 // both signs, applied to the sign bits.  The phases here are small
 // multiples of 2 pi (k R over a scatterer), where this reduction is exact
-// enough.
+// enough.  17 FMAs, 3 products and a rint for the pair of values.
 __device__ __forceinline__ void sincos_rev(double x, double& s, double& c) {
   const double q = rint(2.0 * x);
   const double f = fma(-0.5, q, x);
   const int flip = ((int)q & 1) << 31;
-  const double t = f * 6.283185307179586;
-  const double t2 = t * t;
-  double ps = -1.0 / 51090942171709440000.0;  // -1/21!
-  ps = fma(ps, t2, 1.0 / 121645100408832000.0);
-  ps = fma(ps, t2, -1.0 / 355687428096000.0);
-  ps = fma(ps, t2, 1.0 / 1307674368000.0);
-  ps = fma(ps, t2, -1.0 / 6227020800.0);
-  ps = fma(ps, t2, 1.0 / 39916800.0);
-  ps = fma(ps, t2, -1.0 / 362880.0);
-  ps = fma(ps, t2, 1.0 / 5040.0);
-  ps = fma(ps, t2, -1.0 / 120.0);
-  ps = fma(ps, t2, 1.0 / 6.0);
-  const double sn = fma(-(ps * t2), t, t);
-  double pc = 1.0 / 1124000727777607680000.0;  // 1/22!
-  pc = fma(pc, t2, -1.0 / 2432902008176640000.0);
-  pc = fma(pc, t2, 1.0 / 6402373705728000.0);
-  pc = fma(pc, t2, -1.0 / 20922789888000.0);
-  pc = fma(pc, t2, 1.0 / 87178291200.0);
-  pc = fma(pc, t2, -1.0 / 479001600.0);
-  pc = fma(pc, t2, 1.0 / 3628800.0);
-  pc = fma(pc, t2, -1.0 / 40320.0);
-  pc = fma(pc, t2, 1.0 / 720.0);
-  pc = fma(pc, t2, -1.0 / 24.0);
-  pc = fma(pc, t2, 0.5);
-  const double cs = fma(-pc, t2, 1.0);
+  const double u = f * f;
+  double ps = 0.10089695501646812;
+  ps = fma(ps, u, -0.71773379214134536);
+  ps = fma(ps, u, 3.8199280942271643);
+  ps = fma(ps, u, -15.094641676117901);
+  ps = fma(ps, u, 42.058693925428685);
+  ps = fma(ps, u, -76.705859752824921);
+  ps = fma(ps, u, 81.605249276073621);
+  ps = fma(ps, u, -41.341702240399755);
+  ps = fma(ps, u, 6.2831853071795862);
+  const double sn = f * ps;
+  double pc = 0.2719458494999813;
+  pc = fma(pc, u, -1.7132184107005932);
+  pc = fma(pc, u, 7.9034624920850973);
+  pc = fma(pc, u, -26.426254066690255);
+  pc = fma(pc, u, 60.244641313160407);
+  pc = fma(pc, u, -85.456817205980613);
+  pc = fma(pc, u, 64.939394022663947);
+  pc = fma(pc, u, -19.739208802178705);
+  const double cs = fma(pc, u, 1.0);
   s = __hiloint2double(__double2hiint(sn) ^ flip, __double2loint(sn));
   c = __hiloint2double(__double2hiint(cs) ^ flip, __double2loint(cs));
 }
@@ -181,45 +186,50 @@ __device__ __forceinline__ double expo(double x) { return exp(x); }
 __device__ __forceinline__ float expo(float x) { return __expf(x); }
 
 // ------------------------------------------------------------- regular kernel
-// Two wavefronts per SIMD at least: the FP64 instance then fits in 256
-// VGPRs (one or two spilled outside the point loops), which hides the
-// latency of its dependent FP64 chains far better than one wavefront.
+__device__ __forceinline__ double pair_weight(const FillConsts& fc, int k, int l, double) { return fc.wq[k][l]; }
+__device__ __forceinline__ float pair_weight(const FillConsts& fc, int k, int l, float) { return fc.wqf[k][l]; }
+
 // The 3 x 3 local blocks of the three output operators for test triangle P
 // and source triangle Q, written at o0 (row stride ldl, operator stride
-// op_stride).
+// op_stride).  P is the same on every lane of the wavefront (one row
+// triangle per block): its quadrature points are read into scalar
+// registers, and the loop over them is the inner one.  The outer loop runs
+// over the lane's own source points r~'_l, so that only one of them (and
+// e_l = d - r~'_l, with X = r~_k + e_l) is held per lane.  Per source point
+// the inner sums over the test points are
+//   A0 = S_k G,  B0 = S_k g,  B1 = S_k g r~_k,
+// and the moments follow from them and the lane's vectors:
+//   S_k g X = B1 + e_l B0,   S_k g X x r~' = (S_k g X) x r~',
+//   S_k g r~ x X = B1 x e_l, S_k g r~.(X x r~') = B1.(e_l x r~')
+// (r~ x r~ = 0 and r~.(r~ x r~') = 0 drop out exactly); Ir and Irr take
+// the test point itself and are summed in the inner loop.
 template <typename R, bool LOSSY>
 __device__ __forceinline__ void regular_pair(const TriTab<R>& tab, int32_t P, int32_t Q, const FillConsts& fc,
                                              cx<R>* __restrict__ o0, int64_t op_stride, int64_t ldl) {
   const int64_t nt = tab.nt;
+  P = __builtin_amdgcn_readfirstlane(P);
 
   const R d[3] = {(R)(tab.cen[0][P] - tab.cen[0][Q]), (R)(tab.cen[1][P] - tab.cen[1][Q]),
                   (R)(tab.cen[2][P] - tab.cen[2][Q])};
-  R rq[7][3];
-#pragma unroll
-  for (int l = 0; l < 7; ++l)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) rq[l][c] = tab.q[c][l * nt + Q];
-
   const R k1 = (R)fc.k1, k2r = (R)fc.k2r, k2i = (R)fc.k2i;
   const R rev1 = (R)fc.rev1, rev2 = (R)fc.rev2;
-  const R inv4pi = (R)(0.25 / M_PI);
 
   cx<R> I0[2] = {}, Ir[2][3] = {}, Irq[2][3] = {}, Irr[2] = {};
   cx<R> S0 = {}, SA[3] = {}, SB[3] = {}, SC[3] = {};
 
 #pragma unroll 1
-  for (int k = 0; k < 7; ++k) {
-    const R rk[3] = {tab.q[0][k * nt + P], tab.q[1][k * nt + P], tab.q[2][k * nt + P]};
-    const R rd[3] = {rk[0] + d[0], rk[1] + d[1], rk[2] + d[2]};
-    cx<R> A0[2] = {}, A1[2][3] = {}, B0 = {}, B1[3] = {};
+  for (int l = 0; l < 7; ++l) {
+    const R rq[3] = {tab.q[0][l * nt + Q], tab.q[1][l * nt + Q], tab.q[2][l * nt + Q]};
+    const R e[3] = {d[0] - rq[0], d[1] - rq[1], d[2] - rq[2]};
+    cx<R> A0[2] = {}, B0 = {}, B1[3] = {};
 #pragma unroll
-    for (int l = 0; l < 7; ++l) {
-      const R x0 = rd[0] - rq[l][0], x1 = rd[1] - rq[l][1], x2 = rd[2] - rq[l][2];
+    for (int k = 0; k < 7; ++k) {
+      const R rk[3] = {tab.q[0][k * nt + P], tab.q[1][k * nt + P], tab.q[2][k * nt + P]};
+      const R x0 = rk[0] + e[0], x1 = rk[1] + e[1], x2 = rk[2] + e[2];
       const R R2 = x0 * x0 + x1 * x1 + x2 * x2;
       const R iR = rsq(R2);
       const R Rl = R2 * iR;
-      const R wl = (R)fc.w[l];
-      const R f = wl * iR * inv4pi;  // w / (4 pi R)
+      const R f = pair_weight(fc, k, l, R(0)) * iR;  // w_k w_l / (4 pi R)
       const R t = iR * iR;
       // exterior medium
       const R ph1 = k1 * Rl;
@@ -246,56 +256,53 @@ __device__ __forceinline__ void regular_pair(const TriTab<R>& tab, int32_t P, in
       A0[1].im += G2.im;
       B0.re += g.re;
       B0.im += g.im;
+      const R rr = rk[0] * rq[0] + rk[1] * rq[1] + rk[2] * rq[2];
+      Irr[0].re += G1.re * rr;
+      Irr[0].im += G1.im * rr;
+      Irr[1].re += G2.re * rr;
+      Irr[1].im += G2.im * rr;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const R q = rq[l][c];
-        A1[0][c].re += G1.re * q;
-        A1[0][c].im += G1.im * q;
-        A1[1][c].re += G2.re * q;
-        A1[1][c].im += G2.im * q;
+        const R q = rk[c];
+        Ir[0][c].re += G1.re * q;
+        Ir[0][c].im += G1.im * q;
+        Ir[1][c].re += G2.re * q;
+        Ir[1][c].im += G2.im * q;
         B1[c].re += g.re * q;
         B1[c].im += g.im * q;
       }
     }
-    const R wk = (R)fc.w[k];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      I0[m].re += wk * A0[m].re;
-      I0[m].im += wk * A0[m].im;
-      cx<R> dot = {rk[0] * A1[m][0].re + rk[1] * A1[m][1].re + rk[2] * A1[m][2].re,
-                   rk[0] * A1[m][0].im + rk[1] * A1[m][1].im + rk[2] * A1[m][2].im};
-      Irr[m].re += wk * dot.re;
-      Irr[m].im += wk * dot.im;
+      I0[m].re += A0[m].re;
+      I0[m].im += A0[m].im;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        Ir[m][c].re += wk * rk[c] * A0[m].re;
-        Ir[m][c].im += wk * rk[c] * A0[m].im;
-        Irq[m][c].re += wk * A1[m][c].re;
-        Irq[m][c].im += wk * A1[m][c].im;
+        Irq[m][c].re += A0[m].re * rq[c];
+        Irq[m][c].im += A0[m].im * rq[c];
       }
     }
-    // K accumulators
-    cx<R> tA[3], tC[3];
+    // K moments of this source point
+    cx<R> X[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      X[c].re = B1[c].re + e[c] * B0.re;  // S_k g X
+      X[c].im = B1[c].im + e[c] * B0.im;
+    }
+    R ex[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-      tA[c].re = rd[c1] * B1[c2].re - rd[c2] * B1[c1].re;  // rd x B1
-      tA[c].im = rd[c1] * B1[c2].im - rd[c2] * B1[c1].im;
-      tC[c].re = rd[c] * B0.re - B1[c].re;                 // rd B0 - B1
-      tC[c].im = rd[c] * B0.im - B1[c].im;
+      ex[c] = e[c1] * rq[c2] - e[c2] * rq[c1];                  // e_l x r~'
+      SC[c].re += X[c].re;
+      SC[c].im += X[c].im;
+      SA[c].re += X[c1].re * rq[c2] - X[c2].re * rq[c1];         // (S_k g X) x r~'
+      SA[c].im += X[c1].im * rq[c2] - X[c2].im * rq[c1];
+      SB[c].re += B1[c1].re * e[c2] - B1[c2].re * e[c1];         // B1 x e_l
+      SB[c].im += B1[c1].im * e[c2] - B1[c2].im * e[c1];
     }
-    S0.re += wk * (rk[0] * tA[0].re + rk[1] * tA[1].re + rk[2] * tA[2].re);
-    S0.im += wk * (rk[0] * tA[0].im + rk[1] * tA[1].im + rk[2] * tA[2].im);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-      SA[c].re += wk * tA[c].re;
-      SA[c].im += wk * tA[c].im;
-      SC[c].re += wk * tC[c].re;
-      SC[c].im += wk * tC[c].im;
-      SB[c].re += wk * (rk[c1] * tC[c2].re - rk[c2] * tC[c1].re);  // rk x tC
-      SB[c].im += wk * (rk[c1] * tC[c2].im - rk[c2] * tC[c1].im);
-    }
+    S0.re += B1[0].re * ex[0] + B1[1].re * ex[1] + B1[2].re * ex[2];
+    S0.im += B1[0].im * ex[0] + B1[1].im * ex[1] + B1[2].im * ex[2];
   }
 
   // epilogue: 3 x 3 local blocks of K, op1, op2
