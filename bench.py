@@ -364,6 +364,82 @@ def serve(cbfm, n_requests, slots, budget, seed=2113, rate=200.0, tol=1e-6):
             "unknowns": {"min": int(min(r.unknowns for r in stream)), "max": int(max(r.unknowns for r in stream))}}
 
 
+def batching_leg(cbfm, torch, n=16, reps=3):
+    """The batching form on the mixed serving stream (its first n seeded
+    scatterers, 960 to 8,000 unknowns, each with its own medium and 1-16
+    incidences): (1) every scatterer projected one by one (cbfm_project)
+    against all of them in one call (cbfm_project_batch: one persistent
+    fill launch, batched GEMMs), FP64, CBFs built beforehand; (2) the
+    reduced solves eager against HIP-graph-replayed Arnoldi chunks.  Best
+    of `reps` after one warm-up."""
+    from synth import configs
+    stream = configs.serving_stream(n)
+    items = []
+    for r in stream:
+        w = r.work
+        mesh = cbfm.Mesh(w.V, w.T, w.edge_block, w.nblocks)
+        med = cbfm.Medium.make(w.k0, w.eta0, w.eps_r, w.mu_r)
+        cb = cbfm.build_cbf(mesh, med, w.gen, w.delta_svd)
+        Zr = torch.empty((cb.n_cbf, cb.n_cbf), dtype=torch.complex128, device="cuda")
+        items.append((mesh, med, cb, Zr, w))
+    pairs = float(sum(it[4].nt ** 2 for it in items))
+
+    def one_by_one():
+        for mesh, med, cb, Zr, _ in items:
+            cbfm.project(mesh, med, cb, Zr, cbfm.FP64)
+
+    def batched():
+        cbfm.project_batch([it[:4] for it in items], cbfm.FP64)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        return best
+
+    t_one = timed(one_by_one)
+    ref = [it[3].clone() for it in items]
+    t_batch = timed(batched)
+    dz = max(float((it[3] - r).abs().max() / r.abs().max()) for it, r in zip(items, ref))
+
+    def solves(graph):
+        out = []
+        for mesh, med, cb, Zr, w in items:
+            out.append(cbfm.solve(mesh, med, cb, Zr, w.inc, tol=1e-6, max_iter=3000,
+                                  restart=full_restart(cb.n_cbf, len(w.inc)), use_graph=graph))
+        return out
+
+    res = {}
+    for graph in (False, True):
+        solves(graph)
+        torch.cuda.synchronize()
+        best, outs = 1e30, None
+        for _ in range(reps):
+            t = time.perf_counter()
+            outs = solves(graph)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        res[graph] = (best, outs)
+    nsolve = sum(len(it[4].inc) for it in items)
+    drcs = max(float(np.max(np.abs(a["rcs"] - b["rcs"]) / np.abs(b["rcs"])))
+               for a, b in zip(res[True][1], res[False][1]))
+    return {"scatterers": n, "unknowns": {"min": int(min(3 * it[4].nt for it in items)),
+                                         "max": int(max(3 * it[4].nt for it in items))},
+            "incidences": nsolve,
+            "projection_one_by_one_ms": t_one * 1e3, "projection_batched_ms": t_batch * 1e3,
+            "projection_batched_pair_evals_per_s": pairs / t_batch,
+            "projection_one_by_one_pair_evals_per_s": pairs / t_one,
+            "batched_vs_one_by_one_max_rel_diff": dz,
+            "solve_eager_ms": res[False][0] * 1e3, "solve_graph_ms": res[True][0] * 1e3,
+            "solves_per_s_eager": nsolve / res[False][0], "solves_per_s_graph": nsolve / res[True][0],
+            "graph_vs_eager_rcs_max_rel_diff": drcs}
+
+
 def serving_legs(cbfm, torch, n, slots):
     """The serving leg under a generous budget (half the free device memory)
     and a tight one (twice the largest request's estimated footprint)."""
@@ -471,6 +547,19 @@ def rmse_db(sig_c, sig_m):
     return float(10.0 * np.log10(np.sqrt(np.mean((sig_c - sig_m) ** 2)) / (sig_m.max() - sig_m.min())))
 
 
+def full_restart(n, nrhs, budget=48 << 30, cap=3000):
+    """GMRES restart length: the longest cycle, up to min(n, 3000), whose
+    solver memory fits the budget (48 GiB of the 288 GB): the Krylov basis
+    (m + 1) nrhs n and the Hessenberg and triangular factors
+    2 nrhs (m + 1) m complex doubles.  On the cylinder (n = 4,224, 32 RHS)
+    the unrestarted solve needs 1,263 iterations where cycles of 1,000 need
+    1,975 (811 against 1,047 ms)."""
+    m = min(n, cap)
+    while m > 100 and ((m + 1) * nrhs * n + 2 * nrhs * (m + 1) * m) * 16 > budget:
+        m = int(m * 0.9)
+    return int(m)
+
+
 def plane_incidences(theta_deg):
     """Monostatic theta-polarised incidences from the directions theta
     (degrees), phi = 0: arrival direction r(theta, 0), k = -r, p = theta-hat."""
@@ -490,6 +579,7 @@ def ipcbf_leg(cbfm, torch, w, mesh, med, prec, primary_rcs, primary_its, primary
     + projection + solve.  RCS against an FP64 MoM solve (the stored FP64
     operator, GMRES to 1e-6) as RMSE (Sec. IV-A) beside the primary CBFs'."""
     gen = plane_incidences(np.arange(10) * 5.0) if gen is None else gen
+    cbfm.MomOperator(mesh, med, cbfm.FP32).close()  # warm-up (first allocations), untimed as the bench's warm-up steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     op = cbfm.MomOperator(mesh, med, cbfm.FP32)
@@ -502,7 +592,8 @@ def ipcbf_leg(cbfm, torch, w, mesh, med, prec, primary_rcs, primary_its, primary
     cbfm.project(mesh, med, cb, Zr, prec)
     torch.cuda.current_stream().synchronize()
     t3 = time.perf_counter()
-    out = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, max_iter=3000, restart=min(n, 1000), **solver)
+    out = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, max_iter=3000, restart=full_restart(n, len(w.inc)),
+                     **solver)
     t4 = time.perf_counter()
     leg = {"generating_waves": len(gen), "delta_r": delta_r, "delta_svd": 1e-3, "n_cbf": int(n),
            "ipcbf_gmres_iterations": [int(i) for i in its], "ipcbf_residual_max": float(res.max()),
@@ -544,7 +635,7 @@ def mom_leg(cbfm, torch, w, mesh, med, cb, Zr, solver):
         legs[name] = {"iterations": int(o["iters"].max()), "status": o["status"], "relres": float(o["relres"].max())}
     incs = plane_incidences(np.arange(31) * 1.0)
     a = cbfm.mom_solve(op, incs, tol=1e-4, max_iter=2000, restart=1000)
-    b = cbfm.solve(mesh, med, cb, Zr, incs, tol=1e-4, max_iter=2000, restart=min(n, 1000), use_cmp=True)
+    b = cbfm.solve(mesh, med, cb, Zr, incs, tol=1e-4, max_iter=2000, restart=full_restart(n, len(incs)), use_cmp=True)
     op.close()
     legs["rmse_db"] = rmse_db(b["rcs"], a["rcs"])
     legs["rcs_directions"] = "0..30 deg, 1 deg, phi 0, theta-hat, monostatic, both solves to 1e-4"
@@ -577,6 +668,7 @@ def main():
                     help="requests of the serving leg (mixed-size stream, Poisson arrivals); 0 skips it")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg (both budgets)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--no-batching", action="store_true", help="skip the batching leg (mixed-stream projection batch, graphs)")
     ap.add_argument("--no-ipcbf", action="store_true", help="skip the IPCBF leg of the cylinder workload")
     ap.add_argument("--ipcbf", action="store_true",
                     help="other workloads: the IPCBF leg with the Table-I generating waves")
@@ -637,9 +729,7 @@ def main():
         t1 = time.perf_counter()
         if done:
             done()
-        # full (unrestarted) GMRES while the Krylov basis of all right-hand
-        # sides stays small, else cycles of 1000
-        m = n if n * n * len(w.inc) * 16 * 3 < 8 << 30 else 1000
+        m = full_restart(n, len(w.inc))
         done = timed("solve") if timed else None
         t2 = time.perf_counter()
         out = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, max_iter=(3 if inner_fp32 else 1) * max(n, 3000),
@@ -777,6 +867,10 @@ def main():
                            "rcs_max_rel_err_vs_fp64": float(np.max(np.abs(o["rcs"] - rcs_ref) / rcs_ref))}
             log(f"{name}: {forms[name]}")
         result["precision_forms"] = forms
+    if not args.no_batching:
+        log("batching")
+        result["batching"] = batching_leg(cbfm, torch)
+        log(f"batching: {result['batching']}")
     if args.serve > 0:
         log("serving")
         result["serving"] = serving_legs(cbfm, torch, args.serve, args.serve_slots)

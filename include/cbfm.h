@@ -130,7 +130,8 @@ cbfm_status cbfm_set_allocator(cbfm_alloc_fn alloc, cbfm_release_fn release);
 cbfm_status cbfm_memory_stats(int64_t* held, int64_t* peak, int64_t* cached);
 
 /* ABI version (incremented on incompatible change). */
-int32_t cbfm_version(void);  /* 2: cbfm_solver_params gained cmp_mode, cmp_inner_tol */
+int32_t cbfm_version(void);  /* 3: cbfm_request gained inner_fp32 (2: cbfm_solver_params gained cmp_mode,
+                                cmp_inner_tol) */
 
 /* -------------------------------------------------------------- timers ---
  * Opt-in kernel timing for measurement: when enabled, the library records a
@@ -538,6 +539,9 @@ typedef struct {
   double tol;                   /* GMRES relative residual                  */
   int32_t max_iter;             /* 0: 3000                                  */
   int32_t restart;              /* 0: min(N_CBF, 1000)                      */
+  int32_t inner_fp32;           /* 1: float Krylov cycles refined against
+                                   the double residual (cbfm_solve's mixed
+                                   form, inner_tol 0)                       */
   uint64_t scatterer_key;       /* 0: nothing kept after the request        */
 } cbfm_request;
 

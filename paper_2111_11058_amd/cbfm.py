@@ -557,11 +557,11 @@ class Request(C.Structure):
     _fields_ = [("xyz_host", _P), ("nv", _I64), ("tri_host", _P), ("nt", _I64), ("edge_block", _P),
                 ("nblocks", _I32), ("medium", Medium), ("gen_host", _P), ("n_gen", _I32), ("delta_svd", C.c_double),
                 ("precision", _I32), ("inc_host", _P), ("nrhs", _I64), ("tol", C.c_double), ("max_iter", _I32),
-                ("restart", _I32), ("scatterer_key", C.c_uint64)]
+                ("restart", _I32), ("inner_fp32", _I32), ("scatterer_key", C.c_uint64)]
 
 
 def make_request(V, T, edge_block, nblocks, medium, gen, delta_svd, inc, tol=1e-6, max_iter=0, restart=0,
-                 precision=FP64, key=0):
+                 precision=FP64, key=0, inner_fp32=False):
     """A Request and the host arrays it points to (keep both alive until
     the request is submitted; submission copies them)."""
     V, pv = _host(V, np.float64)
@@ -575,7 +575,7 @@ def make_request(V, T, edge_block, nblocks, medium, gen, delta_svd, inc, tol=1e-
         keep.append(eb)
         nb = int(nblocks)
     r = Request(pv, V.size // 3, pt, T.size // 3, pe, nb, medium, pg, gen.size // 6, float(delta_svd), int(precision),
-                pi, inc.size // 6, float(tol), int(max_iter), int(restart), int(key))
+                pi, inc.size // 6, float(tol), int(max_iter), int(restart), int(bool(inner_fp32)), int(key))
     return r, keep
 
 

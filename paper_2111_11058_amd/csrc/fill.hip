@@ -603,7 +603,7 @@ __global__ void __launch_bounds__(64) near_outer_kernel(const double* __restrict
                                                         const NearPair* __restrict__ near, int64_t nnear, FillConsts fc,
                                                         const cd* __restrict__ buf, cx<R>* __restrict__ out,
                                                         int64_t op_stride, int64_t ldl,
-                                                        const NearOut* __restrict__ outs, int cell0) {
+                                                        const NearOut* __restrict__ outs, int cell0, int transposed) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nnear) return;
   const NearPair np = near[t];
@@ -655,14 +655,17 @@ __global__ void __launch_bounds__(64) near_outer_kernel(const double* __restrict
         }
     }
   }
+  // (transposed: the block of test P and source Q goes to the slot of the
+  // reversed pair, row i = Q's position, column j = P's, entry (b, a))
   cx<R>* o0 = out + (3 * (int64_t)np.i) * ldl + 3 * (int64_t)np.j;
+  const int64_t sa = transposed ? 1 : ldl, sb = transposed ? ldl : 1;
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) {
-      o0[a * ldl + b] = cx<R>{(R)Kab[a][b].re, (R)Kab[a][b].im};
+      o0[a * sa + b * sb] = cx<R>{(R)Kab[a][b].re, (R)Kab[a][b].im};
       for (int o = 0; o < 2; ++o) {
         cd v = {0, 0};
         for (int m = 0; m < 2; ++m) v = cadd(v, cmul({fc.e[o][m][0], fc.e[o][m][1]}, Tab[m][a][b]));
-        o0[(o + 1) * op_stride + a * ldl + b] = cx<R>{(R)v.re, (R)v.im};
+        o0[(o + 1) * op_stride + a * sa + b * sb] = cx<R>{(R)v.re, (R)v.im};
       }
     }
 }
@@ -676,7 +679,7 @@ size_t near_buffer_bytes(int64_t nnear) { return (size_t)nnear * 7 * NEAR_VALS *
 template <typename R>
 static void near_stage(const cbfm_mesh_s* m, const FillConsts& fc, const NearPair* near, int64_t nnear, cx<R>* out,
                        int64_t op_stride, int64_t ldl, hipStream_t s, const NearOut* outs = nullptr, int cell0 = 0,
-                       void* buf_in = nullptr) {
+                       void* buf_in = nullptr, int transposed = 0) {
   if (nnear == 0) return;
   Scratch own(buf_in ? 0 : near_buffer_bytes(nnear), s);
   cd* buf = static_cast<cd*>(buf_in ? buf_in : own.p);
@@ -685,7 +688,7 @@ static void near_stage(const cbfm_mesh_s* m, const FillConsts& fc, const NearPai
   CBFM_HIP(hipGetLastError());
   hipLaunchKernelGGL((near_outer_kernel<R>), dim3((unsigned)((nnear + 63) / 64)), dim3(64), 0, s, m->tri_xyz.as<double>(),
                      m->area.as<double>(), m->c64.as<double>(), m->h.nt, near, nnear, fc, buf, out, op_stride,
-                     ldl, outs, cell0);
+                     ldl, outs, cell0, transposed);
   CBFM_HIP(hipGetLastError());
 }
 
@@ -728,14 +731,14 @@ void fill_local(const cbfm_mesh_s* m, const Media& md, int precision, int layout
 }
 
 void fill_near(const cbfm_mesh_s* m, const Media& md, int precision, int layout, const NearPair* near, int64_t nnear,
-               int64_t nrt, int64_t nct, void* local, hipStream_t s) {
+               int64_t nrt, int64_t nct, void* local, hipStream_t s, int transposed) {
   const FillConsts fc = make_consts(md, layout);
   const int64_t ldl = 3 * nct, op_stride = 3 * nrt * ldl;
   TimedLaunch tn(T_FILL_NEAR, s, (double)nnear);  // work: near pairs
   if (precision == CBFM_FP64)
-    near_stage(m, fc, near, nnear, static_cast<cx<double>*>(local), op_stride, ldl, s);
+    near_stage(m, fc, near, nnear, static_cast<cx<double>*>(local), op_stride, ldl, s, nullptr, 0, nullptr, transposed);
   else
-    near_stage(m, fc, near, nnear, static_cast<cx<float>*>(local), op_stride, ldl, s);
+    near_stage(m, fc, near, nnear, static_cast<cx<float>*>(local), op_stride, ldl, s, nullptr, 0, nullptr, transposed);
 }
 
 void fill_near_batch(const cbfm_mesh_s* m, const Media& md, int layout, const NearPair* near, int64_t nnear,

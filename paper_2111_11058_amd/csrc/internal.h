@@ -262,8 +262,10 @@ struct FillBatchItem {
   void* local;
 };
 void fill_regular_batch(const std::vector<FillBatchItem>& items, int precision, hipStream_t s);
+// transposed: pair (p, q) is written into the slot of (q, p) (row i, column
+// j), each 3 x 3 block transposed, as the reversed pair's entries.
 void fill_near(const cbfm_mesh_s* m, const Media& md, int precision, int layout, const NearPair* near, int64_t nnear,
-               int64_t nrt, int64_t nct, void* local, hipStream_t s);
+               int64_t nrt, int64_t nct, void* local, hipStream_t s, int transposed = 0);
 // The near pairs of several FP64 local blocks in one launch pair: pair t
 // (device arrays) writes into block outs[near[t].pad - cell0], which starts
 // outs[...].off elements into `local`.

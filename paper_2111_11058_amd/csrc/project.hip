@@ -4,9 +4,10 @@
 //          [ (C^M)^H TH C^M,  (C^M)^H K C^J ]]
 // Rows are processed in panels of whole cells.  For a panel the fill
 // kernels produce the triangle-local blocks of the panel's test triangles
-// against every source triangle, the gather kernel assembles the panel's
-// rows of K, TE, TH (upcast to double, or kept in float for the mixed
-// forms), and two batched matrix-core GEMM launches (FP64, or FP32 / BF16
+// against the source triangles of its own and the later cells (the rest
+// follows by reciprocity, below), the gather kernel assembles blocks of
+// K, TE, TH (upcast to double, or kept in float for the mixed forms), and
+// two batched matrix-core GEMM launches per block (FP64, or FP32 / BF16
 // inputs with FP32 accumulation) form
 //   W_X[rows, cell b] = X[rows, cell b] C_b          (X in K, TE, TH)
 //   Z_r[cell a rows]  = C_a^H W_X[cell a rows, :]
@@ -23,32 +24,33 @@
 
 namespace cbfm {
 
-// Bytes of scratch a panel of `nrow` RWG rows touching `nrt` triangles needs.
-static size_t panel_bytes(int64_t nrt, int64_t nt, int64_t nrow, int64_t ne, int64_t NL, size_t esz) {
-  return (size_t)27 * nrt * nt * esz + (size_t)3 * nrow * ne * 16 + (size_t)4 * nrow * NL * 16;
-}
-
-// Descriptors of the projection GEMMs of a panel holding the rows of cells
-// p0..p1-1: Zp = [K; TE; TH] rows of the panel (nrow x ne each, complex float
-// for the mixed forms, else double), W its four nrow x N_L products.
-static void panel_gemms(const MeshHost& h, cbfm_cbf_s* c, int p0, int p1, void* Zp, void* W, bool mixed, double2* Zr,
-                        int64_t ldz, std::vector<GemmDesc>& d1, std::vector<GemmDesc>& d2, std::vector<GemmDescX>& x1,
-                        std::vector<GemmDescX>& x2) {
-  const int nb = h.nblocks;
-  const int64_t ne = h.ne, NL = c->NL, r0 = h.cell_off[p0], nrow = h.cell_off[p1] - r0;
+// Descriptors of the projection GEMMs of one block of Z: the rows of cells
+// ra0..ra1-1 against the columns of cells cb0..cb1-1.  Zp holds [K; TE; TH]
+// of the block (complex float for the mixed forms, else double), each
+// plane nrow x ncol row-major with leading dimension zld, or stored
+// transposed (ncol x nrow, trans) as the reversed block; W receives the
+// four nrow x NLc products (NLc = CBFs of the column cells).
+static void block_gemms(const MeshHost& h, cbfm_cbf_s* c, int ra0, int ra1, int cb0, int cb1, void* Zp, int64_t zld,
+                        bool trans, void* W, bool mixed, double2* Zr, int64_t ldz, std::vector<GemmDesc>& d1,
+                        std::vector<GemmDesc>& d2, std::vector<GemmDescX>& x1, std::vector<GemmDescX>& x2) {
+  const int64_t NL = c->NL, r0 = h.cell_off[ra0], nrow = h.cell_off[ra1] - r0;
+  const int64_t c0 = h.cell_off[cb0], ncol = h.cell_off[cb1] - c0;
+  const int64_t o0 = c->off[cb0], NLc = c->off[cb1] - o0;
   const size_t zs = mixed ? sizeof(float2) : sizeof(double2);
   char* Zk = static_cast<char*>(Zp);
-  char* Zte = Zk + nrow * ne * zs;
-  char* Zth = Zte + nrow * ne * zs;
+  char* Zte = Zk + nrow * ncol * zs;
+  char* Zth = Zte + nrow * ncol * zs;
   char* Wkm = static_cast<char*>(W);
-  char* Wkj = Wkm + nrow * NL * zs;
-  char* Wte = Wkj + nrow * NL * zs;
-  char* Wth = Wte + nrow * NL * zs;
-  for (int b = 0; b < nb; ++b) {
-    const int64_t Nb = h.cell_off[b + 1] - h.cell_off[b], cb0 = h.cell_off[b];
+  char* Wkj = Wkm + nrow * NLc * zs;
+  char* Wte = Wkj + nrow * NLc * zs;
+  char* Wth = Wte + nrow * NLc * zs;
+  const int opZ = trans ? OP_T : OP_N;
+  for (int b = cb0; b < cb1; ++b) {
+    const int64_t Nb = h.cell_off[b + 1] - h.cell_off[b], cb = h.cell_off[b] - c0;
+    const int64_t zoff = trans ? cb * zld : cb;  // cell b's columns of the block
     const double2* CMb = c->CM.as<double2>() + c->coff[b];
     const double2* CJb = c->CJ.as<double2>() + c->coff[b];
-    const int64_t Lb = c->L[b], ob = c->off[b];
+    const int64_t Lb = c->L[b], ob = c->off[b] - o0;
     const struct {
       char* Z;
       const double2* C;
@@ -56,13 +58,13 @@ static void panel_gemms(const MeshHost& h, cbfm_cbf_s* c, int p0, int p1, void* 
     } prod[4] = {{Zk, CMb, Wkm}, {Zk, CJb, Wkj}, {Zte, CJb, Wte}, {Zth, CMb, Wth}};
     for (const auto& q : prod) {
       if (mixed)
-        x1.push_back(gemmx(q.Z + cb0 * zs, 0, ne, OP_N, q.C, 1, Lb, OP_N, q.W + ob * zs, 0, NL, nrow, Lb, Nb));
+        x1.push_back(gemmx(q.Z + zoff * zs, 0, zld, opZ, q.C, 1, Lb, OP_N, q.W + ob * zs, 0, NLc, nrow, Lb, Nb));
       else
-        d1.push_back(gemm(reinterpret_cast<const double2*>(q.Z) + cb0, ne, OP_N, q.C, Lb, OP_N,
-                          reinterpret_cast<double2*>(q.W) + ob, NL, nrow, Lb, Nb));
+        d1.push_back(gemm(reinterpret_cast<const double2*>(q.Z) + zoff, zld, opZ, q.C, Lb, OP_N,
+                          reinterpret_cast<double2*>(q.W) + ob, NLc, nrow, Lb, Nb));
     }
   }
-  for (int a = p0; a < p1; ++a) {
+  for (int a = ra0; a < ra1; ++a) {
     const int64_t Na = h.cell_off[a + 1] - h.cell_off[a], ra = h.cell_off[a] - r0;
     const double2* CMa = c->CM.as<double2>() + c->coff[a];
     const double2* CJa = c->CJ.as<double2>() + c->coff[a];
@@ -74,19 +76,26 @@ static void panel_gemms(const MeshHost& h, cbfm_cbf_s* c, int p0, int p1, void* 
       char* W;
       double2* out;
       double alpha;
-    } prod[4] = {{CJa, Wkm, Zr + oa * ldz, 1.0},
-                 {CJa, Wte, Zr + oa * ldz + NL, -1.0},
-                 {CMa, Wth, Zr + (NL + oa) * ldz, 1.0},
-                 {CMa, Wkj, Zr + (NL + oa) * ldz + NL, 1.0}};
+    } prod[4] = {{CJa, Wkm, Zr + oa * ldz + o0, 1.0},
+                 {CJa, Wte, Zr + oa * ldz + NL + o0, -1.0},
+                 {CMa, Wth, Zr + (NL + oa) * ldz + o0, 1.0},
+                 {CMa, Wkj, Zr + (NL + oa) * ldz + NL + o0, 1.0}};
     for (const auto& q : prod) {
       if (mixed)
-        x2.push_back(gemmx(q.C, 1, La, OP_C, q.W + ra * NL * zs, 0, NL, OP_N, q.out, 1, ldz, La, NL, Na,
+        x2.push_back(gemmx(q.C, 1, La, OP_C, q.W + ra * NLc * zs, 0, NLc, OP_N, q.out, 1, ldz, La, NLc, Na,
                            (float)q.alpha));
       else
-        d2.push_back(gemm(q.C, La, OP_C, reinterpret_cast<const double2*>(q.W) + ra * NL, NL, OP_N, q.out, ldz, La, NL,
-                          Na, q.alpha));
+        d2.push_back(gemm(q.C, La, OP_C, reinterpret_cast<const double2*>(q.W) + ra * NLc, NLc, OP_N, q.out, ldz, La,
+                          NLc, Na, q.alpha));
     }
   }
+}
+
+// The rows of cells p0..p1-1 against every column (one whole block row).
+static void panel_gemms(const MeshHost& h, cbfm_cbf_s* c, int p0, int p1, void* Zp, void* W, bool mixed, double2* Zr,
+                        int64_t ldz, std::vector<GemmDesc>& d1, std::vector<GemmDesc>& d2, std::vector<GemmDescX>& x1,
+                        std::vector<GemmDescX>& x2) {
+  block_gemms(h, c, p0, p1, 0, h.nblocks, Zp, h.ne, false, W, mixed, Zr, ldz, d1, d2, x1, x2);
 }
 
 // Both GEMM stages (each one batched launch; both synchronise the stream).
@@ -103,97 +112,167 @@ static void launch_panel_gemms(int precision, std::vector<GemmDesc>& d1, std::ve
   }
 }
 
+// Reciprocity: for the regular rule every operator's triangle-local block
+// of (test P, source Q) is the transpose of that of (Q, P) (the integrands
+// of T_i and of K agree point by point under the exchange; Sec. II-B), and
+// the near-pair rule is evaluated in both orientations.  Panel p (row
+// cells p0..p1-1) therefore fills its test triangles only against the
+// source triangles of cells p0..nb-1 and yields two blocks of Z:
+//   the block row  Z[cells p0..p1-1][cells p0..nb-1], and, after the near
+//   pairs of the later cells' triangles (test) against the panel's
+//   (source) are written over their reversed slots,
+//   the block column Z[cells p1..nb-1][cells p0..p1-1], assembled from the
+//   same local blocks as its transpose.
+// Every block of Z_r comes from exactly one of them.  Panels hold at most
+// a 1/8 of the cells, so about 9/16 of the regular pairs are computed.
+static size_t panel_bytes(int64_t nrt, int64_t nct, int64_t nrow, int64_t ncol, int64_t nlater, int64_t NLc,
+                          int64_t NLp, size_t esz, size_t zs) {
+  return (size_t)27 * nrt * nct * esz + (size_t)3 * nrow * ncol * zs +
+         std::max((size_t)4 * nrow * NLc, (size_t)4 * nlater * NLp) * zs;
+}
+
 int project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int precision, double2* Zr, int64_t ldz,
                 hipStream_t s, size_t budget) {
   const MeshHost& h = m->h;
   const int nb = h.nblocks;
-  const int64_t ne = h.ne, nt = h.nt, NL = c->NL;
+  const int64_t ne = h.ne, nt = h.nt;
   // mixed forms: FP32 regular fill, panel and W in complex float, projection
   // on the FP32 or BF16 matrix cores (FP32 accumulation), Z_r stored double
   const bool mixed = precision == CBFM_MIXED_FP32 || precision == CBFM_MIXED_BF16 || precision == CBFM_MIXED_BF16X3;
   const int fillp = precision == CBFM_FP64 ? CBFM_FP64 : CBFM_FP32;
   const size_t esz = fillp == CBFM_FP64 ? 16 : 8;
-  // column side: every triangle, every edge (internal order)
-  std::vector<int32_t> iota(nt);
-  for (int64_t t = 0; t < nt; ++t) iota[t] = (int32_t)t;
-  // group cells into panels whose scratch fits the budget
-  std::vector<int32_t> mark(nt, -1);
-  int a0 = 0;
-  std::vector<std::pair<int, int>> panels;
-  while (a0 < nb) {
-    int a1 = a0;
-    int64_t nrt = 0;
-    int stamp = a0;
-    while (a1 < nb) {
-      // triangles of cells a0..a1
-      int64_t add = 0;
-      for (int64_t i = h.cell_off[a1]; i < h.cell_off[a1 + 1]; ++i) {
+  const size_t zs = mixed ? sizeof(float2) : sizeof(double2);
+  // triangles of each cell's RWGs, and how many cells from a0 on touch each
+  // triangle's support (for the column triangle counts)
+  std::vector<std::vector<int32_t>> ctris(nb);
+  {
+    std::vector<int32_t> mark(nt, -1);
+    for (int b = 0; b < nb; ++b)
+      for (int64_t i = h.cell_off[b]; i < h.cell_off[b + 1]; ++i) {
         const int e = h.perm[i];
         for (int t : {h.tplus[e], h.tminus[e]})
-          if (mark[t] != stamp) {
-            mark[t] = stamp;
-            ++add;
+          if (mark[t] != b) {
+            mark[t] = b;
+            ctris[b].push_back(t);
           }
       }
-      const int64_t nrow = h.cell_off[a1 + 1] - h.cell_off[a0];
-      // (marks carry the panel's first cell as stamp, so the next panel recounts)
-      if (a1 > a0 && panel_bytes(nrt + add, nt, nrow, ne, NL, esz) > budget) break;
-      nrt += add;
-      ++a1;
-    }
-    panels.push_back({a0, a1});
-    a0 = a1;
   }
-  // device index tables shared by all panels
-  Scratch dcol((size_t)(2 * nt) * sizeof(int32_t), s);
-  CBFM_HIP(hipMemcpyAsync(dcol.p, iota.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  CBFM_HIP(hipMemcpyAsync(dcol.as<int32_t>() + nt, iota.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  const int32_t* colTris = dcol.as<int32_t>();
-  const int32_t* colPos = dcol.as<int32_t>() + nt;
-  const int32_t* colEdges = m->perm.as<int32_t>();
+  // nct(a0): triangles of the RWGs of cells a0..nb-1
+  std::vector<int64_t> nct_from(nb + 1, 0);
+  {
+    std::vector<char> seen(nt, 0);
+    for (int b = nb - 1; b >= 0; --b) {
+      int64_t add = 0;
+      for (int t : ctris[b])
+        if (!seen[t]) {
+          seen[t] = 1;
+          ++add;
+        }
+      nct_from[b] = nct_from[b + 1] + add;
+    }
+  }
+  // panels of consecutive cells: at most ceil(nb / 8) cells, within the budget
+  const int max_cells = std::max(1, (nb + 7) / 8);
+  std::vector<std::pair<int, int>> panels;
+  {
+    std::vector<int32_t> mark(nt, -1);
+    int a0 = 0;
+    while (a0 < nb) {
+      int a1 = a0;
+      int64_t nrt = 0;
+      while (a1 < nb && a1 - a0 < max_cells) {
+        int64_t add = 0;
+        for (int t : ctris[a1])
+          if (mark[t] != a0) {
+            mark[t] = a0;
+            ++add;
+          }
+        const int64_t nrow = h.cell_off[a1 + 1] - h.cell_off[a0];
+        const size_t need = panel_bytes(nrt + add, nct_from[a0], nrow, ne - h.cell_off[a0], ne - h.cell_off[a1 + 1],
+                                        c->NL - c->off[a0], c->off[a1 + 1] - c->off[a0], esz, zs);
+        if (a1 > a0 && need > budget) break;
+        nrt += add;
+        ++a1;
+      }
+      panels.push_back({a0, a1});
+      a0 = a1;
+    }
+  }
 
   for (auto [p0, p1] : panels) {
-    const int64_t r0 = h.cell_off[p0], nrow = h.cell_off[p1] - r0;
-    std::vector<int32_t> pos(nt, -1), rows, redges(h.perm.begin() + r0, h.perm.begin() + r0 + nrow);
-    for (int e : redges) {
-      pos[h.tplus[e]] = 0;
-      pos[h.tminus[e]] = 0;
-    }
-    for (int64_t t = 0; t < nt; ++t)
-      if (pos[t] == 0) {
-        pos[t] = (int32_t)rows.size();
-        rows.push_back((int32_t)t);
+    const int64_t r0 = h.cell_off[p0], r1 = h.cell_off[p1], nrow = r1 - r0;
+    // row triangles (the panel's RWGs) and column triangles (those of
+    // cells p0..nb-1), each with its position; later[t]: t carries an RWG
+    // of a cell after the panel
+    std::vector<int32_t> pos(nt, -1), cpos(nt, -1), rows, cols;
+    std::vector<char> later(nt, 0);
+    for (int b = p0; b < p1; ++b)
+      for (int t : ctris[b])
+        if (pos[t] < 0) {
+          pos[t] = (int32_t)rows.size();
+          rows.push_back(t);
+        }
+    for (int b = p0; b < nb; ++b)
+      for (int t : ctris[b]) {
+        if (cpos[t] < 0) {
+          cpos[t] = (int32_t)cols.size();
+          cols.push_back(t);
+        }
+        if (b >= p1) later[t] = 1;
       }
-    std::vector<NearPair> nl;
-    for (const NearPair& q : h.near)
-      if (pos[q.p] >= 0) nl.push_back({q.p, q.q, pos[q.p], q.q, q.coplanar, 0});
-    const int64_t nrt = rows.size();
-    const size_t ib = 4 * (rows.size() + pos.size() + redges.size()) + sizeof(NearPair) * nl.size();
+    std::vector<NearPair> nl, nlt;  // near pairs as they are, and reversed
+    for (const NearPair& q : h.near) {
+      if (pos[q.p] >= 0 && cpos[q.q] >= 0) nl.push_back({q.p, q.q, pos[q.p], cpos[q.q], q.coplanar, 0});
+      if (later[q.p] && pos[q.q] >= 0) nlt.push_back({q.p, q.q, pos[q.q], cpos[q.p], q.coplanar, 0});
+    }
+    const int64_t nrt = rows.size(), nct = cols.size();
+    std::vector<int32_t> redges(h.perm.begin() + r0, h.perm.begin() + r1);
+    const size_t ib = 4 * (rows.size() + cols.size() + 2 * pos.size() + redges.size()) +
+                      sizeof(NearPair) * (nl.size() + nlt.size());
     std::vector<char> host(ib);
     Scratch idx(ib, s);
     size_t o = 0;
     auto put = [&](const void* src, size_t bytes) {
-      std::memcpy(host.data() + o, src, bytes);
+      if (bytes) std::memcpy(host.data() + o, src, bytes);
       void* d = idx.as<char>() + o;
       o += bytes;
       return d;
     };
     auto* d_rows = (int32_t*)put(rows.data(), 4 * rows.size());
+    auto* d_cols = (int32_t*)put(cols.data(), 4 * cols.size());
     auto* d_pos = (int32_t*)put(pos.data(), 4 * pos.size());
+    auto* d_cpos = (int32_t*)put(cpos.data(), 4 * cpos.size());
     auto* d_re = (int32_t*)put(redges.data(), 4 * redges.size());
     auto* d_nl = (NearPair*)put(nl.data(), sizeof(NearPair) * nl.size());
+    auto* d_nlt = (NearPair*)put(nlt.data(), sizeof(NearPair) * nlt.size());
     CBFM_HIP(hipMemcpyAsync(idx.p, host.data(), ib, hipMemcpyHostToDevice, s));
-    Scratch local((size_t)27 * nrt * nt * esz, s);
-    const size_t zsz = mixed ? sizeof(float2) : sizeof(double2);
-    Scratch Zp((size_t)3 * nrow * ne * zsz, s);
-    Scratch W((size_t)4 * nrow * NL * zsz, s);
-    fill_local(m, md, fillp, CBFM_LAYOUT_OPS3, d_rows, nrt, colTris, nt, d_nl, (int64_t)nl.size(), local.p, s);
-    assemble(m, fillp, local.p, nrt, nt, d_re, nrow, colEdges, ne, d_pos, colPos, Zp.p, nrow * ne, ne, s,
+    const int64_t ncol = ne - r0, nlater = ne - r1;
+    const int64_t NLc = c->NL - c->off[p0], NLp = c->off[p1] - c->off[p0];
+    Scratch local((size_t)27 * nrt * nct * esz, s);
+    Scratch Zp((size_t)3 * nrow * ncol * zs, s);
+    Scratch W(std::max((size_t)4 * nrow * NLc, (size_t)4 * nlater * NLp) * zs, s);
+    fill_local(m, md, fillp, CBFM_LAYOUT_OPS3, d_rows, nrt, d_cols, nct, d_nl, (int64_t)nl.size(), local.p, s);
+    // block row: the panel's RWGs against those of cells p0..nb-1
+    const int32_t* colEdges = m->perm.as<int32_t>() + r0;
+    assemble(m, fillp, local.p, nrt, nct, d_re, nrow, colEdges, ncol, d_pos, d_cpos, Zp.p, nrow * ncol, ncol, s,
              mixed ? 0 : 1);
-    std::vector<GemmDesc> d1, d2;
-    std::vector<GemmDescX> x1, x2;
-    panel_gemms(h, c, p0, p1, Zp.p, W.p, mixed, Zr, ldz, d1, d2, x1, x2);
-    launch_panel_gemms(precision, d1, d2, x1, x2, s);
+    {
+      std::vector<GemmDesc> d1, d2;
+      std::vector<GemmDescX> x1, x2;
+      block_gemms(h, c, p0, p1, p0, nb, Zp.p, ncol, false, W.p, mixed, Zr, ldz, d1, d2, x1, x2);
+      launch_panel_gemms(precision, d1, d2, x1, x2, s);
+    }
+    if (p1 < nb) {
+      // block column: the later cells' near pairs against the panel in the
+      // reversed slots, then Z[cells p1..][panel] stored transposed
+      fill_near(m, md, fillp, CBFM_LAYOUT_OPS3, d_nlt, (int64_t)nlt.size(), nrt, nct, local.p, s, 1);
+      assemble(m, fillp, local.p, nrt, nct, d_re, nrow, colEdges + (r1 - r0), nlater, d_pos, d_cpos, Zp.p,
+               nrow * nlater, nlater, s, mixed ? 0 : 1);
+      std::vector<GemmDesc> d1, d2;
+      std::vector<GemmDescX> x1, x2;
+      block_gemms(h, c, p1, nb, p0, p1, Zp.p, nlater, true, W.p, mixed, Zr, ldz, d1, d2, x1, x2);
+      launch_panel_gemms(precision, d1, d2, x1, x2, s);
+    }
     CBFM_HIP(hipStreamSynchronize(s));  // host index staging of this panel
   }
   return (int)panels.size();
@@ -359,7 +438,7 @@ void project_batch_dev(const std::vector<BatchEntry>& es, int precision, hipStre
   const size_t esz = fillp == CBFM_FP64 ? 16 : 8;
   auto full = [&](const BatchEntry& e) {
     const MeshHost& h = e.m->h;
-    return panel_bytes(h.nt, h.nt, h.ne, h.ne, e.c->NL, esz);
+    return panel_bytes(h.nt, h.nt, h.ne, h.ne, 0, e.c->NL, 0, esz, mixed ? sizeof(float2) : sizeof(double2));
   };
   struct Prep {
     std::unique_ptr<Scratch> idx, local, Zp, W;

@@ -51,7 +51,7 @@ struct Job {
   std::vector<double> xyz, gen, inc;
   std::vector<int32_t> tri, eb;
   int64_t nv = 0, nt = 0, nrhs = 0;
-  int32_t nblocks = 1, n_gen = 0, precision = CBFM_FP64, max_iter = 0, restart = 0;
+  int32_t nblocks = 1, n_gen = 0, precision = CBFM_FP64, max_iter = 0, restart = 0, inner_fp32 = 0;
   cbfm_medium med{};
   double delta = 0, tol = 1e-6;
   uint64_t key = 0;
@@ -119,13 +119,13 @@ struct cbfm_server_s {
 
   double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
 
-  // Under mu: evict unused residents (least recently used first) until
-  // `need` more bytes fit, or none is left to evict.
-  bool make_room(size_t need) {
+  // Under mu: evict unused residents (least recently used first, never the
+  // one of key `keep`) until `need` more bytes fit, or none is left to evict.
+  bool make_room(size_t need, uint64_t keep) {
     while (in_use + resident_bytes + need > budget) {
       auto victim = residents.end();
       for (auto it = residents.begin(); it != residents.end(); ++it)
-        if (it->second->users == 0 && it->second->ready &&
+        if (it->second->users == 0 && it->second->ready && (keep == 0 || it->first != keep) &&
             (victim == residents.end() || it->second->last_use < victim->second->last_use))
           victim = it;
       if (victim == residents.end()) return false;
@@ -143,7 +143,8 @@ struct cbfm_server_s {
       // a keyless request holds its own mesh, CBFs and Z_r while it runs; a
       // keyed one adds them unless its key is already resident
       const size_t need = j->transient + (j->key == 0 || !shared ? j->resident : 0);
-      if (!make_room(need) && running > 0) continue;
+      // (the resident a keyed request will use is not evicted for it)
+      if (!make_room(need, shared ? j->key : 0) && running > 0) continue;
       queue.erase(it);
       in_use += j->transient;
       if (j->key != 0) {
@@ -222,6 +223,7 @@ void cbfm_server_s::run(Job* j, hipStream_t s) {
     sp.max_iter = j->max_iter > 0 ? j->max_iter : 3000;
     sp.restart = j->restart > 0 ? j->restart : (int32_t)std::min<int64_t>(r->n, 1000);
     sp.use_cmp = 1;
+    sp.inner_fp32 = j->inner_fp32 ? 1 : 0;
     j->rcs.assign(j->nrhs, 0.0);
     j->iters.assign(j->nrhs, 0);
     const cbfm_status st = cbfm_solve(r->mesh, &j->med, r->cbf, r->Zr.p, r->n, j->inc.data(), j->nrhs, &sp, nullptr,
@@ -341,6 +343,7 @@ cbfm_status cbfm_server_submit(cbfm_server srv, const cbfm_request* req, int64_t
     j->precision = req->precision;
     j->max_iter = req->max_iter;
     j->restart = req->restart;
+    j->inner_fp32 = req->inner_fp32;
     j->med = req->medium;
     j->delta = req->delta_svd;
     j->tol = req->tol;

@@ -66,12 +66,16 @@ def test_refined_solve_matches_fp64(torch_cuda):
     assert out2["status"] == "OK" and _rel(jt.cpu().numpy().T, jref) < 1e-8
 
 
-@pytest.mark.parametrize("name", ["c1", "cyl_small"])
+@pytest.mark.parametrize("name", ["c1", "cyl_small", "cyl_lossy"])
 def test_mixed_end_to_end_rcs(torch_cuda, name):
-    """Float fill + FP32 matrix-core projection + refined float GMRES: the
-    monostatic RCS within 1e-4 of the FP64 oracle, and with split-BF16
-    projection too; with plain BF16 inputs the error is reported and
-    bounded by 5e-2."""
+    """Each precision form against the FP64 oracle (same CBFs, LU of the
+    oracle's Z_r): FP32 regular fill with FP64 projection and solve; float
+    fill + FP32 matrix-core projection + refined float GMRES; the same with
+    split-BF16 and with plain BF16 projection.  Monostatic RCS within 1e-4
+    of the oracle (plain BF16: reported, bounded by 5e-2); the surface
+    current error (relative Frobenius over all incidences) is reported and
+    bounded by 1e-3 (0.2 for plain BF16).  cyl_lossy has the lossy
+    permittivity of the precision workload (4 - 0.1j)."""
     from oracle import excitation
     O = _oracle_cbf(name)
     P = O["P"]
@@ -82,13 +86,18 @@ def test_mixed_end_to_end_rcs(torch_cuda, name):
     jref = O["CMJ"] @ np.linalg.solve(O["Zr"], vr)
     rcs_ref = excitation.monostatic_rcs(m, jref, w.inc, w.k0, w.eta0)
     Z = torch_cuda.zeros((n, n), dtype=torch_cuda.complex128, device="cuda")
-    errs = {}
-    for prec in (cbfm.MIXED_FP32, cbfm.MIXED_BF16, cbfm.MIXED_BF16X3):
+    J = torch_cuda.zeros((len(w.inc), 2 * m.ne), dtype=torch_cuda.complex128, device="cuda")
+    errs, cerr = {}, {}
+    forms = {"fp32_fill": (cbfm.FP32, False), "mixed_fp32": (cbfm.MIXED_FP32, True),
+             "split_bf16": (cbfm.MIXED_BF16X3, True), "bf16": (cbfm.MIXED_BF16, True)}
+    for name_f, (prec, f32) in forms.items():
         cbfm.project(mesh, med, cbf, Z, prec)
-        out = cbfm.solve(mesh, med, cbf, Z, w.inc, tol=1e-8, max_iter=4 * n, restart=n, inner_fp32=True)
+        out = cbfm.solve(mesh, med, cbf, Z, w.inc, tol=1e-8, max_iter=4 * n, restart=n, inner_fp32=f32, j_out=J)
         assert out["status"] == "OK"
-        errs[prec] = np.max(np.abs(out["rcs"] - rcs_ref) / rcs_ref)
-    print(f"{w.name}: monostatic RCS rel err fp32 {errs[cbfm.MIXED_FP32]:.2e} bf16 {errs[cbfm.MIXED_BF16]:.2e} "
-          f"split bf16 {errs[cbfm.MIXED_BF16X3]:.2e}")
-    assert errs[cbfm.MIXED_FP32] < 1e-4 and errs[cbfm.MIXED_BF16X3] < 1e-4
-    assert errs[cbfm.MIXED_BF16] < 5e-2
+        errs[name_f] = np.max(np.abs(out["rcs"] - rcs_ref) / rcs_ref)
+        cerr[name_f] = _rel(J.cpu().numpy().T, jref)
+    print(f"{w.name}: vs the FP64 oracle, monostatic RCS / current rel err: " +
+          ", ".join(f"{k} {errs[k]:.2e} / {cerr[k]:.2e}" for k in forms))
+    for k in ("fp32_fill", "mixed_fp32", "split_bf16"):
+        assert errs[k] < 1e-4 and cerr[k] < 1e-3, k
+    assert errs["bf16"] < 5e-2 and cerr["bf16"] < 0.2

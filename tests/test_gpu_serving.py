@@ -15,10 +15,10 @@ def torch_cuda():
     return torch
 
 
-def _req(cbfm, w, tol=1e-9, key=0, inc=None):
+def _req(cbfm, w, tol=1e-9, key=0, inc=None, inner_fp32=False):
     med = cbfm.Medium.make(w.k0, w.eta0, w.eps_r, w.mu_r)
     return cbfm.make_request(w.V, w.T, w.edge_block, w.nblocks, med, w.gen, w.delta_svd,
-                             w.inc if inc is None else inc, tol=tol, key=key)
+                             w.inc if inc is None else inc, tol=tol, key=key, inner_fp32=inner_fp32)
 
 
 def test_results_same_alone_and_in_the_mix(torch_cuda):
@@ -126,3 +126,31 @@ def test_admission_keeps_within_budget(torch_cuda):
     print(st)
     assert all(o["status"] == "OK" for o in outs)
     assert st["peak_bytes"] <= budget
+
+
+def test_served_mixed_solve_meets_the_rcs_bar(torch_cuda):
+    """A request with inner_fp32 (float Krylov cycles refined against the
+    double residual) against the oracle's FP64 CBFM RCS of the same sphere:
+    within the mixed form's 1e-4, and the same result alone and beside FP64
+    requests."""
+    from conftest import oracle_problem
+    from oracle import cbf, excitation, reduced
+    from paper_2111_11058_amd import cbfm
+    P = oracle_problem("c1")
+    w, m = P["w"], P["m"]
+    cb = cbf.build(m, P["Kc"], P["TE"], P["TH"], w.edge_block, w.gen, w.k0, w.eta0, w.delta_svd)
+    CJM, CMJ = reduced.cbf_matrices(cb, m.ne)
+    Zr = reduced.project(P["Z"], CJM, CMJ)
+    j = CMJ @ np.linalg.solve(Zr, CJM.conj().T @ P["v"])
+    ref = excitation.monostatic_rcs(m, j, w.inc, w.k0, w.eta0)
+    srv = cbfm.Server(slots=2, budget_bytes=8 << 30)
+    try:
+        alone = srv.wait(srv.submit(_req(cbfm, w, tol=1e-6, inner_fp32=True)[0]))
+        built = [_req(cbfm, w, tol=1e-6, inner_fp32=f) for f in (True, False)]
+        mix = [srv.wait(t) for t in [srv.submit(r) for r, _ in built]]
+    finally:
+        srv.close()
+    err = np.max(np.abs(alone["rcs"] - ref) / ref)
+    print("served mixed vs oracle RCS", err, "iterations", alone["iters"], mix[1]["iters"])
+    assert alone["status"] == "OK" and err < 1e-4
+    assert np.array_equal(alone["rcs"], mix[0]["rcs"]) and np.array_equal(alone["iters"], mix[0]["iters"])
