@@ -230,45 +230,57 @@ def write_counters(workload_name, stats_dir, dirs, cmd):
              "# issued_fp64_tflops = 64 (2 FMA_F64 + ADD_F64 + MUL_F64) / duration (likewise FP32);"
              " valu_issue = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs);"
              " mfma_busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs);"
-             " mfma_f64_tflops = 512 MOPS_F64 / duration; durations from the kernel trace of the same command"]
+             " mfma_f64_tflops = 512 MOPS_F64 / duration; clock_ghz = GRBM_GUI_ACTIVE / 8 / duration;"
+             " durations from the kernel trace of the same command; sums over the dispatches of each role"]
     for src in sorted({src for _, src in COUNTER_KERNELS.values()}):
         lines.append(f"# source {src} sha256={hashlib.sha256(open(os.path.join(ROOT, src), 'rb').read()).hexdigest()}")
-    small = defaultdict(lambda: [0, 0])
+    # launch shapes grouped by role, counters and durations summed over the
+    # dispatches of the role: each fill kernel over its panels; the GEMMs
+    # as the GMRES matvec (many dispatches of one shape), the projection
+    # (launches of 1 ms or more) and the rest
+    roles = defaultdict(lambda: defaultdict(float))
     for (lab, grid), c in sorted(merged.items()):
-        ns = dur.get((lab, grid))
-        if not lab.startswith("fill") and (ns or 0) < 1e6 and c.get("dispatches", 0) < 100:
-            small[lab][0] += 1  # short, rare launches (Gauss-Jordan steps, CBF-build GEMMs)
-            small[lab][1] += c.get("dispatches", 0)
-            continue
-        sub, src = COUNTER_KERNELS[lab]
-        f64 = 64.0 * (2 * c.get("SQ_INSTS_VALU_FMA_F64", 0) + c.get("SQ_INSTS_VALU_ADD_F64", 0)
-                      + c.get("SQ_INSTS_VALU_MUL_F64", 0))
-        f32 = 64.0 * (2 * c.get("SQ_INSTS_VALU_FMA_F32", 0) + c.get("SQ_INSTS_VALU_ADD_F32", 0)
-                      + c.get("SQ_INSTS_VALU_MUL_F32", 0))
-        parts = [f"kernel={lab} grid={grid} dispatches={c.get('dispatches', 0)}"]
+        ns, nd = dur.get((lab, grid), 0.0), c.get("dispatches", 0)
+        if lab.startswith("fill"):
+            role = lab
+        elif nd >= 100:
+            role = f"{lab}_gmres_matvec"
+        elif ns >= 1e6:
+            role = f"{lab}_projection"
+        else:
+            role = f"{lab}_other"
+        acc = roles[role]
+        acc["dispatches"] += nd
+        acc["shapes"] += 1
+        acc["ns"] += ns * nd
+        for key, v in c.items():
+            if key != "dispatches":
+                acc[key] += v * nd
+    for role, c in sorted(roles.items()):
+        nd, ns = c["dispatches"], c["ns"]
+        f64 = 64.0 * (2 * c["SQ_INSTS_VALU_FMA_F64"] + c["SQ_INSTS_VALU_ADD_F64"] + c["SQ_INSTS_VALU_MUL_F64"])
+        f32 = 64.0 * (2 * c["SQ_INSTS_VALU_FMA_F32"] + c["SQ_INSTS_VALU_ADD_F32"] + c["SQ_INSTS_VALU_MUL_F32"])
+        parts = [f"kernel={role} dispatches={int(nd)} shapes={int(c['shapes'])}"]
         if ns:
-            parts.append(f"duration_us={ns / 1e3:.1f}")
+            parts.append(f"duration_us_per_dispatch={ns / nd / 1e3:.1f}")
         if f64 or f32:
-            parts.append(f"fp64_valu_flop={f64:.4g} fp32_valu_flop={f32:.4g}")
+            parts.append(f"fp64_valu_flop_per_dispatch={f64 / nd:.4g} fp32_valu_flop_per_dispatch={f32 / nd:.4g}")
             if ns:
                 parts.append(f"issued_fp64_tflops={f64 / ns / 1e3:.2f} issued_fp32_tflops={f32 / ns / 1e3:.2f}")
-            parts.append(f"trans_f64={c.get('SQ_INSTS_VALU_TRANS_F64', 0):.4g} "
-                         f"trans_f32={c.get('SQ_INSTS_VALU_TRANS_F32', 0):.4g}")
-        gui = c.get("GRBM_GUI_ACTIVE")
-        if gui:
-            gui /= N_XCD  # the counter is summed over the XCDs; each runs for the whole dispatch
-        if "SQ_INSTS_VALU" in c and gui:
-            parts.append(f"valu_insts={c['SQ_INSTS_VALU']:.4g} valu_issue={4 * c['SQ_INSTS_VALU'] / (N_SIMD * gui):.3f} "
-                         f"int32={c.get('SQ_INSTS_VALU_INT32', 0):.4g} cvt={c.get('SQ_INSTS_VALU_CVT', 0):.4g} "
-                         f"salu={c.get('SQ_INSTS_SALU', 0):.4g} gui_cycles={gui:.4g}")
-        if "SQ_VALU_MFMA_BUSY_CYCLES" in c and gui:
-            m64 = 512.0 * c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0)
-            parts.append(f"mfma_busy={c['SQ_VALU_MFMA_BUSY_CYCLES'] / (N_SIMD * gui):.3f} mfma_f64_flop={m64:.4g}")
+            parts.append(f"trans_f64_per_dispatch={c['SQ_INSTS_VALU_TRANS_F64'] / nd:.4g} "
+                         f"trans_f32_per_dispatch={c['SQ_INSTS_VALU_TRANS_F32'] / nd:.4g}")
+        gui = c["GRBM_GUI_ACTIVE"] / N_XCD  # the counter is summed over the XCDs; each runs for the whole dispatch
+        if c["SQ_INSTS_VALU"] and gui:
+            parts.append(f"valu_issue={4 * c['SQ_INSTS_VALU'] / (N_SIMD * gui):.3f} "
+                         f"cvt_share={c['SQ_INSTS_VALU_CVT'] / c['SQ_INSTS_VALU']:.3f} "
+                         f"clock_ghz={gui / ns if ns else 0:.2f}")
+        if c["SQ_VALU_MFMA_BUSY_CYCLES"] and gui:
+            m64 = 512.0 * c["SQ_INSTS_VALU_MFMA_MOPS_F64"]
+            parts.append(f"mfma_busy={c['SQ_VALU_MFMA_BUSY_CYCLES'] / (N_SIMD * gui):.3f} "
+                         f"mfma_f64_flop_per_dispatch={m64 / nd:.4g}")
             if ns:
                 parts.append(f"mfma_f64_tflops={m64 / ns / 1e3:.2f}")
         lines.append(" ".join(parts))
-    for lab, (g, n) in small.items():
-        lines.append(f"# {lab}: {g} further launch shapes ({n} dispatches) under 1 ms and under 100 dispatches each")
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", f"valu_mfma_counters_{workload_name}.txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
@@ -656,6 +668,8 @@ def main():
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-fp32", action="store_true", help="skip the precision-form legs")
     ap.add_argument("--fp64-steps", type=int, default=0, help="steps of the FP64 leg (0: half of --steps, at least 1)")
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="only measure what PyTorch's streaming sum and copy reach on this device")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for the HBM byte counters)")
     ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -683,6 +697,29 @@ def main():
         return
     if args.write_counters:
         write_counters(args.workload, args.write_counters[0], args.write_counters[1:], args.traffic_command)
+        return
+    if args.hbm_probe:
+        # what plain streaming code reaches on this device: PyTorch's sum over
+        # 8 GiB (read) and a 2 GiB device copy (read + write), best of 5
+        import torch
+        x = torch.ones(1 << 30, dtype=torch.float64, device="cuda")
+        y = torch.empty(1 << 28, dtype=torch.float64, device="cuda")
+
+        def best(fn):
+            fn()
+            torch.cuda.synchronize()
+            b = 1e30
+            for _ in range(5):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                torch.cuda.synchronize()
+                b = min(b, e0.elapsed_time(e1) * 1e-3)
+            return b
+        print(json.dumps({"sum_read_GBps": x.numel() * 8 / best(lambda: x.sum()) / 1e9,
+                          "copy_read_write_GBps": 2 * y.numel() * 8 / best(lambda: y.copy_(x[: 1 << 28])) / 1e9,
+                          "peak_GBps": PEAK_HBM / 1e9}))
         return
     if args.copy_calibration:
         import torch
