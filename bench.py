@@ -627,6 +627,56 @@ def ipcbf_leg(cbfm, torch, w, mesh, med, prec, primary_rcs, primary_its, primary
     return leg
 
 
+# the paper's IPCBF conditions for the cylinder (Table III): (delta_r, delta_SVD)
+IPCBF_CONDITIONS = ((1e-3, 1e-3), (1e-2, 1e-3), (1e-1, 1e-3), (1e-3, 1e-7))
+
+
+def ipcbf_conditions_leg(cbfm, torch, w, med, cells=(96, 32)):
+    """The paper's four IPCBF conditions on the cylinder (Sec. IV-C): for
+    each cell division (the bench's 96 cells and 32, the paper's count),
+    the IPCBFs of the 10 in-plane waves, the projection (FP32 fill) and the
+    CMP solve of the bench incidences to 1e-6; N_CBF, mean and max
+    iterations, and the RMSE of the RCS against the FP64 MoM solve."""
+    from synth.blocks import rcb_blocks
+    gen = plane_incidences(np.arange(10) * 5.0)
+    base = cbfm.Mesh(w.V, w.T, w.edge_block, w.nblocks)
+    op64 = cbfm.MomOperator(base, med, cbfm.FP64)
+    t0 = time.perf_counter()
+    mom = cbfm.mom_solve(op64, w.inc, tol=1e-6, max_iter=3000, restart=1500)
+    t_mom = time.perf_counter() - t0
+    op64.close()
+    out = {"mom_fp64": {"iterations_max": int(mom["iters"].max()), "status": mom["status"], "ms": t_mom * 1e3},
+           "incidences": len(w.inc), "cells": {}}
+    for nc in cells:
+        eb = w.edge_block if nc == w.nblocks else rcb_blocks(w.V, w.T, nc)
+        mesh = cbfm.Mesh(w.V, w.T, eb, nc)
+        op = cbfm.MomOperator(mesh, med, cbfm.FP32)
+        rows = []
+        for dr, ds in IPCBF_CONDITIONS:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cb, its, res = cbfm.build_ipcbf(op, gen, delta_r=dr, delta_svd=ds, max_iter=1000)
+            t1 = time.perf_counter()
+            n = cb.n_cbf
+            Zr = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+            cbfm.project(mesh, med, cb, Zr, cbfm.FP32)
+            torch.cuda.current_stream().synchronize()
+            t2 = time.perf_counter()
+            o = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, tol=1e-6, max_iter=3000,
+                           restart=full_restart(n, len(w.inc)))
+            t3 = time.perf_counter()
+            rows.append({"delta_r": dr, "delta_svd": ds, "n_cbf": int(n), "generation_iterations_max": int(its.max()),
+                         "iterations_mean": float(o["iters"].mean()), "iterations_max": int(o["iters"].max()),
+                         "status": o["status"], "rmse_db": rmse_db(o["rcs"], mom["rcs"]),
+                         "ms": {"generation": (t1 - t0) * 1e3, "projection": (t2 - t1) * 1e3,
+                                "solve": (t3 - t2) * 1e3}})
+            log(f"ipcbf cells {nc} {rows[-1]}")
+            del Zr
+        op.close()
+        out["cells"][str(nc)] = rows
+    return out
+
+
 def mom_leg(cbfm, torch, w, mesh, med, cb, Zr, solver):
     """The paper's comparison on its arrays (Sec. IV-A, IV-B): iterations to
     1e-6 of the MoM (its arrangement with the diagonal preconditioner, on the
@@ -687,6 +737,8 @@ def main():
     ap.add_argument("--ipcbf", action="store_true",
                     help="other workloads: the IPCBF leg with the Table-I generating waves")
     ap.add_argument("--mom", action="store_true", help="array workloads: the MoM, K-/T-diagonal and RMSE leg")
+    ap.add_argument("--ipcbf-conditions", action="store_true",
+                    help="cylinder: the paper's four IPCBF conditions with 96 and 32 cells, RMSE against the MoM")
     args = ap.parse_args()
     cores = args.cpu_cores or min(16, len(os.sched_getaffinity(0)))
     if args.cpu_baseline_only:
@@ -904,6 +956,9 @@ def main():
                            "rcs_max_rel_err_vs_fp64": float(np.max(np.abs(o["rcs"] - rcs_ref) / rcs_ref))}
             log(f"{name}: {forms[name]}")
         result["precision_forms"] = forms
+    if args.ipcbf_conditions:
+        log("ipcbf conditions")
+        result["ipcbf_conditions"] = ipcbf_conditions_leg(cbfm, torch, w, med)
     if not args.no_batching:
         log("batching")
         result["batching"] = batching_leg(cbfm, torch)

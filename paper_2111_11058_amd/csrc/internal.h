@@ -112,8 +112,10 @@ struct DevBuf {
 // out again, reuse ordered on the stream by an event; blocks from
 // kBigScratch up are matched by size rather than by power-of-two class.
 constexpr size_t kBigScratch = (size_t)256 << 20;
-void* scratch_alloc(size_t bytes, hipStream_t s);
-void scratch_release(void* p, size_t bytes, hipStream_t s);
+// *block receives the size of the block handed out (at least `bytes`; a
+// cached block may be larger), which scratch_release must be given back.
+void* scratch_alloc(size_t bytes, hipStream_t s, size_t* block);
+void scratch_release(void* p, size_t block, hipStream_t s);
 size_t scratch_cached_bytes();  // bytes held by the cache on the current device
 // Before destroying stream s: synchronise it, then call this, so that the
 // cache drops every reference to s and to the events recorded on it.
@@ -130,7 +132,8 @@ void scratch_trim_to(size_t limit);
 struct Scratch {
   void* p = nullptr;
   hipStream_t s = nullptr;
-  size_t n = 0;
+  size_t n = 0;      // bytes asked for
+  size_t block = 0;  // size of the cache block behind p
   ReleaseFn rel = nullptr;
   Scratch(size_t bytes, hipStream_t stream) : s(stream), n(bytes) {
     if (bytes == 0) return;
@@ -140,13 +143,13 @@ struct Scratch {
                    "the caller's allocator returned no memory for " + std::to_string(bytes) + " bytes");
       return;
     }
-    p = scratch_alloc(bytes, stream);
+    p = scratch_alloc(bytes, stream, &block);
   }
   ~Scratch() {
     if (p && rel)
       rel(p, s);
     else if (p)
-      scratch_release(p, n, s);
+      scratch_release(p, block, s);
   }
   Scratch(const Scratch&) = delete;
   Scratch& operator=(const Scratch&) = delete;

@@ -129,7 +129,7 @@ void trim(int dev) {
 
 }  // namespace
 
-void* scratch_alloc(size_t bytes, hipStream_t s) {
+void* scratch_alloc(size_t bytes, hipStream_t s, size_t* block) {
   int dev = 0;
   CBFM_HIP(hipGetDevice(&dev));
   const size_t want = block_size(bytes);
@@ -140,6 +140,7 @@ void* scratch_alloc(size_t bytes, hipStream_t s) {
   // take cached block i (lock held on entry, released on return)
   auto take = [&](std::unique_lock<std::mutex>& lk, size_t i) {
     const Block b = cache().free[i];
+    *block = b.bytes;
     cache().free.erase(cache().free.begin() + (ptrdiff_t)i);  // (keeps the release order)
     lk.unlock();
     if (b.ready) {
@@ -169,6 +170,7 @@ void* scratch_alloc(size_t bytes, hipStream_t s) {
     if (other != SIZE_MAX) return take(lk, other);
   }
   void* p = nullptr;
+  *block = want;
   if (hipMalloc(&p, want) == hipSuccess) {
     device_bytes_add((int64_t)want);
     return p;
@@ -189,7 +191,7 @@ void* scratch_alloc(size_t bytes, hipStream_t s) {
   return p;
 }
 
-void scratch_release(void* p, size_t bytes, hipStream_t s) {
+void scratch_release(void* p, size_t block, hipStream_t s) {
   int dev = 0;
   hipEvent_t ev = nullptr;
   if (hipGetDevice(&dev) != hipSuccess || (ev = take_event(dev)) == nullptr || hipEventRecord(ev, s) != hipSuccess) {
@@ -198,14 +200,14 @@ void scratch_release(void* p, size_t bytes, hipStream_t s) {
     if (ev) (void)hipEventDestroy(ev);
     (void)hipStreamSynchronize(s);
     (void)hipFree(p);
-    device_bytes_add(-(int64_t)block_size(bytes));
+    device_bytes_add(-(int64_t)block);
     return;
   }
   std::vector<Block> drop;
   {
     std::lock_guard<std::mutex> lk(cache().mu);
     auto& f = cache().free;
-    f.push_back({p, block_size(bytes), dev, ev, s, false});
+    f.push_back({p, block, dev, ev, s, false});
     size_t held = 0;
     for (const Block& b : f)
       if (b.dev == dev) held += b.bytes;
