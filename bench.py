@@ -783,7 +783,7 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 3}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+        print(json.dumps({"error": "this implementation runs on one GPU; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
