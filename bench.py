@@ -13,7 +13,9 @@ Workload (default): dielectric cylinder r 1, h 6 wavelengths, eps_r 3,
 19,968 triangles (29,952 RWGs, 59,904 unknowns), 96 cells, 32 monostatic
 incidences, CBFs from the 144 Table-I plane waves, delta_SVD 1e-3, regular
 pairs filled in FP32 (near pairs, CBF build, projection and solve in FP64).
-The FP64 form of the same step runs beside it.
+The FP64 form of the same step runs beside it, then the precision forms,
+the IPCBF leg (the paper's cylinder conditions), the batching and serving
+legs and the CPU oracle baseline (see --help for the switches).
 
 value = logical triangle pair-evaluations (N_tri^2 per step) per second of
 the whole step.  After the timed steps one more step runs with the library's

@@ -313,7 +313,13 @@ void cbfm_cbf_free(cbfm_cbf c);
  * outer CBFM equation): rows [J-test CBFs of cells 1..M ; M-test CBFs],
  * columns [M-trial CBFs ; J-trial CBFs], each group cell after cell.
  * The PMCHWT fill is computed inside and projected on the matrix cores; Z
- * is held only in stream-ordered scratch.  precision: CBFM_FP64, CBFM_FP32
+ * is held only in stream-ordered scratch, one panel of cells at a time.  By
+ * reciprocity of the Galerkin blocks (each operator's block of a triangle
+ * pair is the transpose of the reversed pair's under the regular rule) a
+ * panel fills its test triangles against its own and the later cells'
+ * source triangles only, and the blocks of the later cells' rows against
+ * its columns come from the transposes (near pairs are computed in both
+ * orientations).  precision: CBFM_FP64, CBFM_FP32
  * (fill as in cbfm_fill_pmchwt, projection in double) or the mixed forms
  * CBFM_MIXED_FP32 / CBFM_MIXED_BF16 / CBFM_MIXED_BF16X3 (float fill, float
  * panel, FP32, BF16 or split-BF16 matrix-core projection with FP32
@@ -327,9 +333,10 @@ cbfm_status cbfm_project(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, int32_
 
 /* cbfm_project_ex: cbfm_project with an explicit scratch budget for the row
  * panels (paper Sec. III-C, outer CBFM equation; the same Z_r).  Cells are
- * grouped into panels of consecutive cells whose fill and projection
- * scratch fits panel_bytes (a panel always holds at least one cell; on a
- * mesh of translated cells, groups of cell offsets).  panel_bytes = 0 takes
+ * grouped into panels of consecutive cells, at most an eighth of the cells
+ * each, whose fill and projection scratch fits panel_bytes (a panel always
+ * holds at least one cell; on a mesh of translated cells, groups of cell
+ * offsets).  panel_bytes = 0 takes
  * the default of cbfm_project: a quarter of the free device memory, at most
  * 32 GiB.  npanels_host (or NULL) receives the number of panels used.     */
 cbfm_status cbfm_project_ex(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, int32_t precision,
