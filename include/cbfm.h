@@ -333,8 +333,9 @@ cbfm_status cbfm_project(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, int32_
 
 /* cbfm_project_ex: cbfm_project with an explicit scratch budget for the row
  * panels (paper Sec. III-C, outer CBFM equation; the same Z_r).  Cells are
- * grouped into panels of consecutive cells, at most an eighth of the cells
- * each, whose fill and projection scratch fits panel_bytes (a panel always
+ * grouped into panels of consecutive cells (on meshes of 4,096 triangles
+ * or more at most an eighth of the cells each) whose fill and projection
+ * scratch fits panel_bytes (a panel always
  * holds at least one cell; on a mesh of translated cells, groups of cell
  * offsets).  panel_bytes = 0 takes
  * the default of cbfm_project: a quarter of the free device memory, at most

@@ -123,8 +123,8 @@ static void launch_panel_gemms(int precision, std::vector<GemmDesc>& d1, std::ve
 //   (source) are written over their reversed slots,
 //   the block column Z[cells p1..nb-1][cells p0..p1-1], assembled from the
 //   same local blocks as its transpose.
-// Every block of Z_r comes from exactly one of them.  Panels hold at most
-// a 1/8 of the cells, so about 9/16 of the regular pairs are computed.
+// Every block of Z_r comes from exactly one of them.  With panels of an
+// eighth of the cells about 9/16 of the regular pairs are computed.
 static size_t panel_bytes(int64_t nrt, int64_t nct, int64_t nrow, int64_t ncol, int64_t nlater, int64_t NLc,
                           int64_t NLp, size_t esz, size_t zs) {
   return (size_t)27 * nrt * nct * esz + (size_t)3 * nrow * ncol * zs +
@@ -171,8 +171,11 @@ int project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int precis
       nct_from[b] = nct_from[b + 1] + add;
     }
   }
-  // panels of consecutive cells: at most ceil(nb / 8) cells, within the budget
-  const int max_cells = std::max(1, (nb + 7) / 8);
+  // panels of consecutive cells, within the budget; on meshes of 4,096
+  // triangles or more at most ceil(nb / 8) cells each, so that reciprocity
+  // saves about 7/16 of the regular pairs (on smaller meshes the fixed cost
+  // of a panel outweighs it: one panel when the budget allows)
+  const int max_cells = nt >= 4096 ? std::max(1, (nb + 7) / 8) : nb;
   std::vector<std::pair<int, int>> panels;
   {
     std::vector<int32_t> mark(nt, -1);

@@ -50,13 +50,14 @@ def test_multipanel_projection_parity(torch_cuda, name):
     n = cbf.n_cbf
     # one cell per panel (budget 1 byte), then a budget halved from the
     # whole-mesh scratch until three or more panels form (some holding
-    # several cells)
+    # several cells) in the mixed form, whose panels need the least
+    # scratch (so the other precisions split at least as finely)
     nb = mesh.nblocks
     budgets = [1]
     Z = torch_cuda.full((n, n), complex(np.nan, np.nan), dtype=torch_cuda.complex128, device="cuda")
     b = 64 << 20
     while b > 1 << 16:
-        if cbfm.project(mesh, med, cbf, Z, cbfm.FP64, panel_bytes=b) >= 3:
+        if cbfm.project(mesh, med, cbf, Z, cbfm.MIXED_FP32, panel_bytes=b) >= 3:
             budgets.append(b)
             break
         b //= 2
