@@ -714,6 +714,9 @@ def main():
     ap.add_argument("--workload", default="cylinder19968", choices=WORKLOADS)
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="fill precision of the timed step (default: fp32 for cylinder19968, else fp64)")
+    ap.add_argument("--basis-fp32", action="store_true",
+                    help="time the compressed-basis form (double arithmetic, Krylov basis stored in float) as the "
+                         "main step")
     ap.add_argument("--cpu-sample", type=int, default=300000)
     ap.add_argument("--cpu-cores", type=int, default=0, help="oracle worker processes (0: the host's, at most 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -805,7 +808,7 @@ def main():
     state = {}
     traffic = measured_traffic(args.workload)
 
-    def step(precision, inner_fp32=False, timed=None):
+    def step(precision, inner_fp32=False, timed=None, basis_fp32=False):
         cb = cbfm.build_cbf(mesh, med, w.gen, w.delta_svd, max_L=w.extra.get("max_L", 0))
         n = cb.n_cbf
         Zr = state.get(n)
@@ -823,21 +826,23 @@ def main():
         m = full_restart(n, len(w.inc))
         done = timed("solve") if timed else None
         t2 = time.perf_counter()
-        out = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, max_iter=(3 if inner_fp32 else 1) * max(n, 3000),
-                         restart=m, inner_fp32=inner_fp32, **solver)
+        restarts = inner_fp32 or basis_fp32
+        out = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, max_iter=(3 if restarts else 1) * max(n, 3000),
+                         restart=m, inner_fp32=inner_fp32, basis_fp32=basis_fp32, **solver)
         t3 = time.perf_counter()
         if done:
             done()
         return cb, out, t1 - t0, t3 - t2
 
+    B32 = args.basis_fp32
     for i in range(args.warmup):
         log(f"warmup {i}")
-        step(PREC)
+        step(PREC, basis_fp32=B32)
     torch.cuda.synchronize()
     proj_t, solve_t, iters = [], [], []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        cb, out, tp, ts = step(PREC)
+        cb, out, tp, ts = step(PREC, basis_fp32=B32)
         proj_t.append(tp)
         solve_t.append(ts)
         iters.append(out["iters"])
@@ -846,7 +851,7 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     nt = w.nt
-    roof, roofs = rooflines(cbfm, lambda timed: step(PREC, timed=timed), traffic)
+    roof, roofs = rooflines(cbfm, lambda timed: step(PREC, timed=timed, basis_fp32=B32), traffic)
     nrhs = len(w.inc)
     lat = np.array(solve_t)
     result = {
@@ -860,11 +865,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32-fill/f64" if PREC == cbfm.FP32 else "f64",
+        "dtype": ("f32-fill/f64" if PREC == cbfm.FP32 else "f64") + ("/f32-basis-storage" if B32 else ""),
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {nt} triangles, {3 * nt // 2} RWGs, {3 * nt} unknowns, "
                                f"{w.nblocks} cells, {nrhs} incidences, {len(w.gen)} generating waves",
-                   "fill_precision": prec_name, "n_cbf": int(cb.n_cbf), "solver": solver},
+                   "fill_precision": prec_name, "krylov_basis": "fp32" if B32 else "fp64",
+                   "n_cbf": int(cb.n_cbf), "solver": solver},
         "fill_projection_pair_evals_per_s": nt * nt / float(np.median(proj_t)),
         "solves_per_s": nrhs * args.steps / float(lat.sum()),
         "solves_per_s_end_to_end": nrhs * args.steps / total,
@@ -932,21 +938,26 @@ def main():
             result["eps_r_sweep_tol_1e-4"] = sweep
             log(f"eps_r sweep: {sweep}")
     if not args.no_fp32:
-        # the precision forms on the same workload: the mixed forms (FP32
-        # fill, FP32 or split-BF16 matrix-core projection, float GMRES cycles
-        # refined against the double residual), and the FP32 fill alone when
-        # the timed step is FP64.  CBF build, near pairs, the SVD and the
-        # refinement residual stay FP64.  RCS error against the FP64 step.
+        # the precision forms on the same workload: the compressed-basis
+        # form (the timed step with its Krylov basis stored in float, double
+        # arithmetic, cycles restarted from the double residual), the mixed
+        # forms (FP32 fill, FP32 or split-BF16 matrix-core projection, float
+        # GMRES cycles refined against the double residual), and the FP32
+        # fill alone when the timed step is FP64.  CBF build, near pairs, the
+        # SVD and the refinement residual stay FP64.  RCS error against the
+        # FP64 step.
         forms = {}
-        legs = [("mixed_fp32", cbfm.MIXED_FP32, True), ("mixed_bf16x3", cbfm.MIXED_BF16X3, True)]
+        legs = [("compressed_basis", PREC, dict(basis_fp32=True)),
+                ("mixed_fp32", cbfm.MIXED_FP32, dict(inner_fp32=True)),
+                ("mixed_bf16x3", cbfm.MIXED_BF16X3, dict(inner_fp32=True))][1 if B32 else 0:]
         if PREC == cbfm.FP64:
-            legs.insert(0, ("fp32_fill", cbfm.FP32, False))
-        for name, prec, inner in legs:
-            step(prec, inner)
+            legs.insert(0, ("fp32_fill", cbfm.FP32, {}))
+        for name, prec, kw in legs:
+            step(prec, **kw)
             tp_l, ts_l, tt = [], [], time.perf_counter()
             k = max(1, args.steps // 4)
             for _ in range(k):
-                _, o, tp, ts = step(prec, inner)
+                _, o, tp, ts = step(prec, **kw)
                 tp_l.append(tp)
                 ts_l.append(ts)
             torch.cuda.synchronize()

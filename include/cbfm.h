@@ -130,8 +130,8 @@ cbfm_status cbfm_set_allocator(cbfm_alloc_fn alloc, cbfm_release_fn release);
 cbfm_status cbfm_memory_stats(int64_t* held, int64_t* peak, int64_t* cached);
 
 /* ABI version (incremented on incompatible change). */
-int32_t cbfm_version(void);  /* 3: cbfm_request gained inner_fp32 (2: cbfm_solver_params gained cmp_mode,
-                                cmp_inner_tol) */
+int32_t cbfm_version(void);  /* 4: cbfm_solver_params gained basis_fp32 (3: cbfm_request gained
+                                inner_fp32; 2: cbfm_solver_params gained cmp_mode, cmp_inner_tol) */
 
 /* -------------------------------------------------------------- timers ---
  * Opt-in kernel timing for measurement: when enabled, the library records a
@@ -414,7 +414,7 @@ typedef struct {
                       /* float, each cycle started from the residual       */
                       /* b - A x formed in double (iterative refinement)   */
                       /* and stopped once it has reduced it by inner_tol   */
-  double inner_tol;   /* mixed form only; 0 -> 1e-6                         */
+  double inner_tol;   /* mixed and compressed-basis forms; 0 -> 1e-6        */
   int32_t use_graph;  /* 1: Arnoldi iterations in chunks of four captured   */
                       /* once per cycle into a HIP graph and replayed      */
   int32_t cmp_mode;   /* with use_cmp 1: CBFM_CMP_EXACT, or               */
@@ -425,6 +425,18 @@ typedef struct {
                       /* built from the preconditioned vectors); double   */
                       /* cycles, no graphs                                */
   double cmp_inner_tol; /* inexact CMP allowance; 0 -> 1e-5                */
+  int32_t basis_fp32; /* 1: compressed-basis form -- double arithmetic    */
+                      /* (operator, work vector, Hessenberg, residuals)   */
+                      /* with the Krylov basis stored in float, which     */
+                      /* halves the bytes of the Arnoldi passes; the      */
+                      /* Arnoldi relation then holds to float rounding,   */
+                      /* so each cycle stops once it has reduced the      */
+                      /* residual b - A x (formed in double) by inner_tol */
+                      /* (or reached tol) and the next starts from it.    */
+                      /* Not with inner_fp32 or CBFM_CMP_INNER_GMRES      */
+                      /* (CBFM_E_ARG).  cbfm_mom_solve takes it with an   */
+                      /* FP64 operator (ignored for FP32, whose cycles    */
+                      /* are float); cbfm_solve_matfree rejects it.       */
 } cbfm_solver_params;
 
 cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, const void* Zr_dev,

@@ -50,7 +50,8 @@ CMP_EXACT, CMP_INNER_GMRES = 0, 1
 class SolverParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32),
                 ("use_cmp", C.c_int32), ("inner_fp32", C.c_int32), ("inner_tol", C.c_double),
-                ("use_graph", C.c_int32), ("cmp_mode", C.c_int32), ("cmp_inner_tol", C.c_double)]
+                ("use_graph", C.c_int32), ("cmp_mode", C.c_int32), ("cmp_inner_tol", C.c_double),
+                ("basis_fp32", C.c_int32)]
 
 
 class IpcbfParams(C.Structure):
@@ -466,7 +467,7 @@ def _solve_outputs(nrhs, dirs):
 
 
 def mom_solve(mom: MomOperator, inc, tol=1e-6, max_iter=1000, restart=1000, j_out=None, dirs=None, stream=None,
-              inner_fp32=False, inner_tol=0.0, use_graph=False):
+              inner_fp32=False, inner_tol=0.0, use_graph=False, basis_fp32=False):
     """cbfm_mom_solve (the MoM baseline).  Returns dict(iters, relres, rcs, status)."""
     import torch
     inc, pi = _host(inc, np.float64)
@@ -475,7 +476,7 @@ def mom_solve(mom: MomOperator, inc, tol=1e-6, max_iter=1000, restart=1000, j_ou
     pj = _dev(j_out, torch.complex128, nrhs * mom.n, "j") if j_out is not None else None
     iters, relres, rcs, dirs, pd, nd = _solve_outputs(nrhs, dirs)
     prm = SolverParams(float(tol), int(max_iter), int(restart), 0, int(bool(inner_fp32)), float(inner_tol),
-                       int(bool(use_graph)))
+                       int(bool(use_graph)), basis_fp32=int(bool(basis_fp32)))
     code = lib().cbfm_mom_solve(mom.handle, pi, nrhs, C.byref(prm), pj, iters.ctypes.data_as(C.c_void_p),
                                 relres.ctypes.data_as(C.c_void_p), pd, nd, rcs.ctypes.data_as(C.c_void_p),
                                 _stream(stream))
@@ -519,11 +520,13 @@ def solve_matfree(mom: MomOperator, cbf: CBF, inc, tol=1e-6, max_iter=1000, rest
 
 def solve(mesh: Mesh, medium: Medium, cbf: CBF, Zr, inc, tol=1e-6, max_iter=1000, restart=100,
           use_cmp=True, j_out=None, dirs=None, ldz=None, stream=None, raise_noconv=False, inner_fp32=False,
-          inner_tol=0.0, use_graph=False, cmp_mode=CMP_EXACT, cmp_inner_tol=0.0):
+          inner_tol=0.0, use_graph=False, cmp_mode=CMP_EXACT, cmp_inner_tol=0.0, basis_fp32=False):
     """cbfm_solve.  Returns dict(iters, relres, rcs, status).  inner_fp32
     selects the mixed form (float Krylov cycles refined against the double
-    residual, each cycle reducing it by inner_tol); use_graph replays the
-    Arnoldi iterations from a captured HIP graph."""
+    residual, each cycle reducing it by inner_tol); basis_fp32 the
+    compressed-basis form (double cycles with the basis stored in float,
+    restarted the same way); use_graph replays the Arnoldi iterations from a
+    captured HIP graph."""
     import torch
     inc, pi = _host(inc, np.float64)
     inc = inc.reshape(-1, 6)
@@ -543,7 +546,8 @@ def solve(mesh: Mesh, medium: Medium, cbf: CBF, Zr, inc, tol=1e-6, max_iter=1000
         pd, nd = None, 0
         rcs = np.zeros(nrhs)
     prm = SolverParams(float(tol), int(max_iter), int(restart), int(use_cmp), int(bool(inner_fp32)),
-                       float(inner_tol), int(bool(use_graph)), int(cmp_mode), float(cmp_inner_tol))
+                       float(inner_tol), int(bool(use_graph)), int(cmp_mode), float(cmp_inner_tol),
+                       int(bool(basis_fp32)))
     code = lib().cbfm_solve(mesh.handle, C.byref(medium), cbf.handle, pz, ldz, pi, nrhs, C.byref(prm), pj,
                             iters.ctypes.data_as(C.c_void_p), relres.ctypes.data_as(C.c_void_p), pd, nd,
                             rcs.ctypes.data_as(C.c_void_p), _stream(stream))

@@ -465,6 +465,7 @@ cbfm_status cbfm_mom_solve(cbfm_mom o, const double* inc, int64_t nrhs, const cb
     sp.f32 = prm->inner_fp32 != 0;
     sp.inner_tol = prm->inner_tol;
     sp.graph = prm->use_graph != 0;
+    sp.basis32 = prm->basis_fp32 != 0 && prm->inner_fp32 == 0;
     Scratch jz(nrhs * o->n * sizeof(double2), s), jout(nrhs * o->n * sizeof(double2), s);
     const GmresResult r = full_solve(o, inc, nrhs, sp, jz.as<double2>(), s);
     noconv = r.noconv;
@@ -514,8 +515,8 @@ cbfm_status cbfm_solve_matfree(cbfm_mom o, cbfm_cbf c, const double* inc, int64_
     CBFM_REQUIRE(prm->tol > 0 && prm->max_iter >= 1 && prm->restart >= 1, CBFM_E_ARG, "bad solver parameters");
     CBFM_REQUIRE(prm->use_cmp == 0 || prm->use_cmp == 1, CBFM_E_ARG, "use_cmp must be 0 or 1");
     CBFM_REQUIRE(prm->cmp_mode == CBFM_CMP_EXACT, CBFM_E_ARG, "the matrix-free operator takes the exact CMP");
-    CBFM_REQUIRE(prm->inner_fp32 == 0 && prm->use_graph == 0, CBFM_E_ARG,
-                 "the matrix-free operator runs double Krylov cycles without graphs");
+    CBFM_REQUIRE(prm->inner_fp32 == 0 && prm->use_graph == 0 && prm->basis_fp32 == 0, CBFM_E_ARG,
+                 "the matrix-free operator runs double Krylov cycles with a double basis and without graphs");
     CBFM_REQUIRE(dirs == nullptr || ndir >= 1, CBFM_E_ARG, "ndir must be >= 1 with dirs");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const cbfm_mesh_s* m = o->mesh;

@@ -45,6 +45,8 @@ struct GmresSpec {
   bool f32 = false;        // float Krylov basis, cycles refined against the double residual
   double inner_tol = 0.0;  // f32 only: relative reduction per cycle (0: 1e-6)
   bool graph = false;      // Arnoldi chunks replayed from a HIP graph (dense operators)
+  bool basis32 = false;    // double cycles with the Krylov basis stored in float (dense double
+                           // operator); each cycle stops at a reduction of inner_tol as in f32
 };
 
 struct GmresResult {

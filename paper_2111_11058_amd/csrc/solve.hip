@@ -48,7 +48,8 @@ __device__ inline double2 cmul(double2 a, double2 b) {
 __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 
 // Krylov vectors are stored as complex double (plain form) or complex
-// float (inner solves of the mixed form); arithmetic is always double.
+// float (the basis of the compressed-basis form; basis and work vector of
+// the mixed form's inner solves); arithmetic is always double.
 __device__ inline double2 ld2(const double2* p) { return *p; }
 __device__ inline double2 ld2(const float2* p) {
   const float2 v = *p;
@@ -56,6 +57,11 @@ __device__ inline double2 ld2(const float2* p) {
 }
 __device__ inline void st2(double2* p, double2 v) { *p = v; }
 __device__ inline void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+// v as st2 leaves it in storage of the pointer's type
+__device__ inline double2 stored2(const double2*, double2 v) { return v; }
+__device__ inline double2 stored2(const float2*, double2 v) {
+  return make_double2((double)(float)v.x, (double)(float)v.y);
+}
 
 __device__ inline double2 cconjmul(double2 a, double2 b) {  // conj(a) b
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
@@ -99,15 +105,18 @@ __global__ void __launch_bounds__(256) norm_kernel(const double2* __restrict__ u
   if (threadIdx.x == 0) nrm[c] = sqrt((sh[0] + sh[1]) + (sh[2] + sh[3]));
 }
 
-// out[c] = in[c] / nrm[c] (zero if nrm[c] == 0)
+// out[c] = in[c] / nrm[c] (zero if nrm[c] == 0); with qd, also the stored
+// value in double there
 template <typename TV>
 __global__ void scale_kernel(const double2* __restrict__ in, TV* __restrict__ out, int64_t n,
-                             const double* __restrict__ nrm) {
+                             const double* __restrict__ nrm, double2* __restrict__ qd = nullptr) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
   if (k >= n) return;
   const double s = nrm[c] > 0 ? 1.0 / nrm[c] : 0.0;
   const double2 a = in[c * n + k];
-  st2(out + c * n + k, make_double2(a.x * s, a.y * s));
+  const double2 v = make_double2(a.x * s, a.y * s);
+  st2(out + c * n + k, v);
+  if (qd) qd[c * n + k] = stored2(out, v);
 }
 
 // out = in rounded to complex float
@@ -179,8 +188,8 @@ struct GmresState {
 // RPL = 2 rows per lane) once s1 = sum a_l q_l and s2 = sum b_l q_l are
 // known: q_j <- (q_j - s1) / gamma, w <- (w - s2) / gamma - c_j q_j, and
 // the partial sum of |w|^2 of these rows.
-template <typename TV>
-__device__ inline void finish_rows(TV* V, int64_t vstride, TV* w, int64_t n, int64_t nrhs, int64_t j, int64_t c,
+template <typename TB, typename TW>
+__device__ inline void finish_rows(TB* V, int64_t vstride, TW* w, int64_t n, int64_t nrhs, int64_t j, int64_t c,
                                    int64_t rb, int np, const GmresState& st, const double2 (&s1)[2],
                                    const double2 (&s2)[2], double* part, int lane) {
   const double ig = 1.0 / st.gam[c];
@@ -191,9 +200,9 @@ __device__ inline void finish_rows(TV* V, int64_t vstride, TV* w, int64_t n, int
   for (int r = 0; r < 2; ++r) {
     const int64_t k = (rb * 2 + r) * 64 + lane;
     if (k < n) {
-      TV* qj = V + j * vstride + c * n + k;
+      TB* qj = V + j * vstride + c * n + k;
       const double2 qo = ld2(qj);
-      const double2 qn = cscale(make_double2(qo.x - s1[r].x, qo.y - s1[r].y), ig);
+      const double2 qn = stored2(qj, cscale(make_double2(qo.x - s1[r].x, qo.y - s1[r].y), ig));
       st2(qj, qn);
       const double2 wo = ld2(w + c * n + k);
       const double2 t = cmul(cj, qn);
@@ -223,28 +232,31 @@ __global__ void cycle_init_kernel(GmresState st, int64_t m, int64_t nrhs, double
 }
 
 // d1[i] = q_i^H q_j and d2[i] = q_i^H w for i <= j: one block of four
-// wavefronts per right-hand side and run of four basis vectors; the
-// threads take every 256th row, the loads of all four vectors of a row go
+// wavefronts per right-hand side and run of VPB = 4 basis vectors; the
+// threads take every 256th row, the loads of all VPB vectors of a row go
 // out together, and the wavefronts are summed through LDS in a fixed order.
-template <typename TV, bool UNR>
-__global__ void __launch_bounds__(256) dots2_kernel(const TV* __restrict__ V, int64_t vstride,
-                                                    const TV* __restrict__ w, int64_t n, int64_t nrhs, int64_t j,
+// (For a float basis, runs of 8 vectors measured slower: half the blocks at
+// 4 instead of 7 wavefronts per SIMD.)
+template <typename TB, typename TW, bool UNR, int VPB = 4>
+__global__ void __launch_bounds__(256) dots2_kernel(const TB* __restrict__ V, int64_t vstride,
+                                                    const TW* __restrict__ w, int64_t n, int64_t nrhs, int64_t j,
                                                     GmresState st, const int64_t* __restrict__ jp) {
+  static_assert(!UNR || VPB == 4, "the unrolled rows take four vectors");
   if (jp) j = *jp;  // iteration index from the device (graph replays)
   const int64_t id = blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t runs = (j + 4) / 4;
+  const int64_t runs = (j + VPB) / VPB;
   if (id >= runs * nrhs) return;  // uniform over the block
   const int64_t run = id / nrhs, c = id % nrhs;
   if (!st.active[c]) return;
-  const int64_t i0 = run * 4;
-  const int cnt = (int)std::min<int64_t>(4, j + 1 - i0);
-  const TV* qj = V + j * vstride + c * n;
-  const TV* wc = w + c * n;
-  const TV* qi = V + i0 * vstride + c * n;
-  double2 s1[4], s2[4];
+  const int64_t i0 = run * VPB;
+  const int cnt = (int)std::min<int64_t>(VPB, j + 1 - i0);
+  const TB* qj = V + j * vstride + c * n;
+  const TW* wc = w + c * n;
+  const TB* qi = V + i0 * vstride + c * n;
+  double2 s1[VPB], s2[VPB];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) s1[t] = s2[t] = make_double2(0, 0);
+  for (int t = 0; t < VPB; ++t) s1[t] = s2[t] = make_double2(0, 0);
   int64_t k = threadIdx.x;
   // UNR: four rows per lane at a time, their loads issued together (the
   // sums still take the rows in order), for long vectors and few blocks;
@@ -268,18 +280,18 @@ __global__ void __launch_bounds__(256) dots2_kernel(const TV* __restrict__ V, in
   }
   for (; k < n; k += 256) {
     const double2 x = ld2(qj + k), y = ld2(wc + k);
-    double2 v[4];
+    double2 v[VPB];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) v[t] = ld2(qi + (t < cnt ? t : 0) * vstride + k);  // vectors past j: discarded
+    for (int t = 0; t < VPB; ++t) v[t] = ld2(qi + (t < cnt ? t : 0) * vstride + k);  // vectors past j: discarded
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < VPB; ++t) {
       s1[t] = cadd(s1[t], cconjmul(v[t], x));
       s2[t] = cadd(s2[t], cconjmul(v[t], y));
     }
   }
-  __shared__ double sh[4][4][4];
+  __shared__ double sh[4][VPB][4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < VPB; ++t) {
     const double r0 = wave_sum(s1[t].x), r1 = wave_sum(s1[t].y), r2 = wave_sum(s2[t].x), r3 = wave_sum(s2[t].y);
     if (lane == 0) {
       sh[wv][t][0] = r0;
@@ -531,13 +543,14 @@ __global__ void __launch_bounds__(256) column_kernel(GmresState st, int64_t m, i
 // the tail of the streaming; placed first they held CUs the update blocks
 // needed, and cutting the rows into parts or running them as a separate
 // launch or stream measured slower too.
-template <typename TV, bool SPLIT>
-__global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, int64_t vstride,
-                                                          TV* __restrict__ w, int64_t n, int64_t nrhs, int64_t m,
+template <typename TB, typename TW, bool SPLIT>
+__global__ void __launch_bounds__(512) dcgs_update_kernel(TB* __restrict__ V, int64_t vstride,
+                                                          TW* __restrict__ w, int64_t n, int64_t nrhs, int64_t m,
                                                           int64_t j, int np, GmresState st,
                                                           double* __restrict__ part, const int64_t* __restrict__ jp) {
   if (jp) j = *jp;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // wv is uniform over the wavefront: the coefficient loads below go through scalar loads
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int S = SPLIT ? st.split : 1;
   const int64_t nub = (int64_t)np * nrhs * S;  // update blocks
   if ((int64_t)blockIdx.x >= nub) {
@@ -606,23 +619,26 @@ __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, in
     const int64_t k = (rb * RPL + r) * 64 + lane;
     kk[r] = k < n ? k : 0;  // rows past n: a valid row, discarded
   }
-  const TV* base = V + c * n;
+  const TB* base = V + c * n;
   // this block's basis vectors: i = 8 (part + S t) + wavefront
   const int64_t istep = 8 * (int64_t)S;
   int64_t i = wv + 8 * (int64_t)part_id;
-  // four basis vectors at a time: their loads go out together (the sums
-  // still take the vectors in order)
-  for (; i + 3 * istep < j; i += 4 * istep) {
-    double2 a[4], b[4], v[4][RPL];
+  // U basis vectors at a time (4; 8 for a float basis beside a double w,
+  // the same bytes in flight, measured 201 -> 184 us on 4,224 rows x 32
+  // right-hand sides): their loads go out together (the sums still take
+  // the vectors in order)
+  constexpr int U = sizeof(TB) < sizeof(TW) ? 8 : 4;
+  for (; i + (U - 1) * istep < j; i += U * istep) {
+    double2 a[U], b[U], v[U][RPL];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       a[u] = d1[(i + istep * u) * nrhs + c];
       b[u] = d2[(i + istep * u) * nrhs + c];
 #pragma unroll
       for (int r = 0; r < RPL; ++r) v[u][r] = ld2(base + (i + istep * u) * vstride + kk[r]);
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int r = 0; r < RPL; ++r) {
         s1[r] = cadd(s1[r], cmul(a[u], v[u][r]));
@@ -670,8 +686,8 @@ __global__ void __launch_bounds__(512) dcgs_update_kernel(TV* __restrict__ V, in
 
 // The update of a split pass: one wavefront per 128-row block of a
 // right-hand side adds the parts' sums in part order and completes it.
-template <typename TV>
-__global__ void __launch_bounds__(64) dcgs_finish_kernel(TV* __restrict__ V, int64_t vstride, TV* __restrict__ w,
+template <typename TB, typename TW>
+__global__ void __launch_bounds__(64) dcgs_finish_kernel(TB* __restrict__ V, int64_t vstride, TW* __restrict__ w,
                                                           int64_t n, int64_t nrhs, int64_t j, int np, GmresState st,
                                                           double* __restrict__ part, const int64_t* __restrict__ jp) {
   if (jp) j = *jp;
@@ -693,13 +709,15 @@ __global__ void __launch_bounds__(64) dcgs_finish_kernel(TV* __restrict__ V, int
 }
 
 // nu = sqrt(sum of the np partial sums of |w|^2); H[j+1][j] = nu and
-// q_{j+1} = w / nu (zero if nu == 0); only active right-hand sides.
-template <typename TV>
-__global__ void normalize_kernel(const TV* __restrict__ w, TV* __restrict__ V, int64_t vstride, int64_t n,
+// q_{j+1} = w / nu (zero if nu == 0), with qd also its stored value in
+// double (the operand of the next matrix-vector product); only active
+// right-hand sides.
+template <typename TB, typename TW>
+__global__ void normalize_kernel(const TW* __restrict__ w, TB* __restrict__ V, int64_t vstride, int64_t n,
                                  const double* __restrict__ part, int np, GmresState st, int64_t m, int64_t j,
-                                 int64_t nrhs, const int64_t* __restrict__ jp) {
+                                 int64_t nrhs, const int64_t* __restrict__ jp, double2* __restrict__ qd) {
   if (jp) j = *jp;
-  TV* out = V + (j + 1) * vstride;
+  TB* out = V + (j + 1) * vstride;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
   if (!st.active[c]) return;
   double q = 0;
@@ -711,7 +729,9 @@ __global__ void normalize_kernel(const TV* __restrict__ w, TV* __restrict__ V, i
   }
   if (k >= n) return;
   const double sc = nu > 0 ? 1.0 / nu : 0.0;
-  st2(out + c * n + k, cscale(ld2(w + c * n + k), sc));
+  const double2 v = cscale(ld2(w + c * n + k), sc);
+  st2(out + c * n + k, v);
+  if (qd) qd[c * n + k] = stored2(out, v);
 }
 
 // Device-side iteration counter of graph replays, and the matrix-vector
@@ -985,11 +1005,15 @@ static void apply_op(const double2* A, int64_t lda, int64_t n, int64_t nrhs, con
 // and the device counter jdev), chunks of four iterations are captured once
 // into a HIP graph whose kernels read the iteration index from jdev, and
 // the graph is replayed; the remaining iterations run as plain launches.
-template <typename TV, typename MV>
-static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev, TV* V, TV* w, int64_t vstride,
+// The basis is stored as TB and the work vector w as TW.  With qd (a float
+// basis beside a double w), every matrix-vector product reads its operand
+// from qd, where the newest basis vector's stored value is kept in double.
+template <typename TB, typename TW, typename MV>
+static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev, TB* V, TW* w, int64_t vstride,
                       int64_t n, int64_t nrhs, int64_t mres, int64_t max_iter, int64_t& total, GmresState gs,
-                      double* part, int np, PinnedFlags& flags, double2* x, hipStream_t s, const TV* xb = nullptr) {
-  const double vb = (double)sizeof(TV);
+                      double* part, int np, PinnedFlags& flags, double2* x, hipStream_t s, const TB* xb = nullptr,
+                      double2* qd = nullptr) {
+  const double vb = (double)sizeof(TB), wb = (double)sizeof(TW);
   const int check_every = 4;
   const int64_t ng = (nrhs + 63) / 64;
   auto all_done = [&](const int32_t* a) { return std::none_of(a, a + nrhs, [](int32_t v) { return v != 0; }); };
@@ -997,21 +1021,23 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
   auto iteration = [&](int64_t j, const int64_t* jp, hipStream_t q) {
     const int64_t jg = jp ? mres - 1 : j;  // grids cover the longest column
     if (jp) {
-      using D = typename std::conditional<std::is_same<TV, double2>::value, GemmDesc, GemmDescX>::type;
-      hipLaunchKernelGGL((point_matvec_kernel<D, TV>), dim3(1), dim3(64), 0, q, static_cast<D*>(dyn_desc), V, vstride,
-                         jp);
+      if constexpr (std::is_same<TB, TW>::value) {
+        using D = typename std::conditional<std::is_same<TB, double2>::value, GemmDesc, GemmDescX>::type;
+        hipLaunchKernelGGL((point_matvec_kernel<D, TB>), dim3(1), dim3(64), 0, q, static_cast<D*>(dyn_desc), V,
+                           vstride, jp);
+      }
       dyn->launch(0, q);
     } else {
       mv.launch((size_t)j, q);  // w = A q_j
     }
     {
       // work: bytes of q_0..q_j and w for every right-hand side
-      TimedLaunch tl(T_GMRES_DOTS, q, vb * (double)(j + 2) * (double)nrhs * (double)n);
+      TimedLaunch tl(T_GMRES_DOTS, q, (vb * (double)(j + 1) + wb) * (double)nrhs * (double)n);
       if (n >= 2048 && nrhs < 16)
-        hipLaunchKernelGGL((dots2_kernel<TV, true>), dim3((unsigned)((jg + 4) / 4 * nrhs)), dim3(256), 0, q, V,
+        hipLaunchKernelGGL((dots2_kernel<TB, TW, true>), dim3((unsigned)((jg + 4) / 4 * nrhs)), dim3(256), 0, q, V,
                            vstride, w, n, nrhs, j, gs, jp);
       else
-        hipLaunchKernelGGL((dots2_kernel<TV, false>), dim3((unsigned)((jg + 4) / 4 * nrhs)), dim3(256), 0, q, V,
+        hipLaunchKernelGGL((dots2_kernel<TB, TW, false>), dim3((unsigned)((jg + 4) / 4 * nrhs)), dim3(256), 0, q, V,
                            vstride, w, n, nrhs, j, gs, jp);
     }
     hipLaunchKernelGGL(column_kernel, dim3((unsigned)nrhs), dim3(256), 0, q, gs, mres, j, nrhs, 1, jp);
@@ -1019,20 +1045,20 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
       // work: bytes of q_0..q_{j-1} read, q_j and w read and written, and
       // the j + j (j + 1) / 2 entries of H read for p = H a
       const double hr = (double)j + 0.5 * (double)j * (double)(j + 1);
-      TimedLaunch tl(T_GMRES_UPDATE, q, (vb * (double)(j + 4) * (double)n + 16.0 * hr) * (double)nrhs);
+      TimedLaunch tl(T_GMRES_UPDATE, q, ((vb * (double)(j + 2) + 2.0 * wb) * (double)n + 16.0 * hr) * (double)nrhs);
       const int64_t nhb = (jg + 1) * ng;
       if (gs.split > 1) {
-        hipLaunchKernelGGL((dcgs_update_kernel<TV, true>), dim3((unsigned)(nhb + (int64_t)np * nrhs * gs.split)),
+        hipLaunchKernelGGL((dcgs_update_kernel<TB, TW, true>), dim3((unsigned)(nhb + (int64_t)np * nrhs * gs.split)),
                            dim3(512), 0, q, V, vstride, w, n, nrhs, mres, j, np, gs, part, jp);
-        hipLaunchKernelGGL(dcgs_finish_kernel<TV>, dim3((unsigned)((int64_t)np * nrhs)), dim3(64), 0, q, V, vstride, w,
-                           n, nrhs, j, np, gs, part, jp);
+        hipLaunchKernelGGL((dcgs_finish_kernel<TB, TW>), dim3((unsigned)((int64_t)np * nrhs)), dim3(64), 0, q, V,
+                           vstride, w, n, nrhs, j, np, gs, part, jp);
       } else {
-        hipLaunchKernelGGL((dcgs_update_kernel<TV, false>), dim3((unsigned)(nhb + (int64_t)np * nrhs)), dim3(512), 0,
-                           q, V, vstride, w, n, nrhs, mres, j, np, gs, part, jp);
+        hipLaunchKernelGGL((dcgs_update_kernel<TB, TW, false>), dim3((unsigned)(nhb + (int64_t)np * nrhs)), dim3(512),
+                           0, q, V, vstride, w, n, nrhs, mres, j, np, gs, part, jp);
       }
     }
-    hipLaunchKernelGGL(normalize_kernel<TV>, grid2(n, nrhs), dim3(256), 0, q, w, V, vstride, n, part, np, gs, mres, j,
-                       nrhs, jp);
+    hipLaunchKernelGGL((normalize_kernel<TB, TW>), grid2(n, nrhs), dim3(256), 0, q, w, V, vstride, n, part, np, gs,
+                       mres, j, nrhs, jp, qd);
     if (jp) hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, q, jdev, (int64_t)1, 1);
     CBFM_HIP(hipGetLastError());
   };
@@ -1099,7 +1125,7 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
   if (j > 0) hipLaunchKernelGGL(column_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, mres, j, nrhs, 0, nullptr);
   hipLaunchKernelGGL(backsolve_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, mres, nrhs);
   // x += Q y, or Z y for flexible GMRES (the preconditioned vectors z_j)
-  hipLaunchKernelGGL(x_update_kernel<TV>, dim3((unsigned)((int64_t)np * nrhs)), dim3(512), 0, s, gs, xb ? xb : V,
+  hipLaunchKernelGGL(x_update_kernel<TB>, dim3((unsigned)((int64_t)np * nrhs)), dim3(512), 0, s, gs, xb ? xb : V,
                      vstride, x, n, nrhs,
                      np);
   CBFM_HIP(hipGetLastError());
@@ -1131,16 +1157,23 @@ GmresResult gmres_run(KrylovOp& op, int64_t n, int64_t nrhs, const double2* b, d
   // a float-only operator runs float cycles (its residuals in float too)
   const bool f32 = p.f32 || (A32in != nullptr && A64 == nullptr);
   CBFM_REQUIRE(dense || !f32, CBFM_E_ARG, "float Krylov cycles need a dense operator");
+  // compressed basis: double arithmetic, the basis stored in float
+  const bool b32 = p.basis32 && !f32;
+  CBFM_REQUIRE(!b32 || A64 != nullptr, CBFM_E_ARG, "a float-stored basis needs a dense double operator");
   CBFM_REQUIRE(p.tol > 0 && p.max_iter >= 1 && p.restart >= 1, CBFM_E_ARG, "bad solver parameters");
   const int64_t mres = std::min<int64_t>(p.restart, std::max<int64_t>(p.max_iter, 1));
   // The plain form keeps the Krylov basis in double; the mixed form keeps it
   // and the operator in float and refines: every cycle starts from the
   // residual b - A x formed in double, and stops once it has reduced that
-  // residual by inner_tol (or reached tol).
-  const double inner = f32 ? (p.inner_tol > 0 ? p.inner_tol : 1e-6) : 0.0;
-  const size_t vsz = f32 ? sizeof(float2) : sizeof(double2);
+  // residual by inner_tol (or reached tol).  The compressed-basis form
+  // keeps the plain form's arithmetic and stores only the basis in float
+  // (half the bytes of the Arnoldi passes); its Arnoldi relation then holds
+  // to float rounding, so its cycles stop and restart as the mixed form's.
+  const double inner = f32 || b32 ? (p.inner_tol > 0 ? p.inner_tol : 1e-6) : 0.0;
+  const size_t vsz = f32 || b32 ? sizeof(float2) : sizeof(double2);
   Scratch V((mres + 1) * nrhs * n * vsz, s);
-  Scratch u(nrhs * n * vsz, s), r64(f32 ? nrhs * n * sizeof(double2) : 0, s);
+  Scratch u(nrhs * n * (f32 ? sizeof(float2) : sizeof(double2)), s), r64(f32 ? nrhs * n * sizeof(double2) : 0, s);
+  Scratch qd(b32 ? nrhs * n * sizeof(double2) : 0, s);
   Scratch A32own(f32 && A32in == nullptr ? n * n * sizeof(float2) : 0, s);
   const int np = (int)((n + 127) / 128);  // partial norm sums per vector (128-row blocks)
   const size_t hbytes = (size_t)nrhs * (mres + 1) * mres * sizeof(double2), cbytes = (size_t)nrhs * (mres + 1) * sizeof(double2);
@@ -1212,7 +1245,8 @@ GmresResult gmres_run(KrylovOp& op, int64_t n, int64_t nrhs, const double2* b, d
     }
   } else if (dense) {
     for (int64_t j = 0; j < mres; ++j) {
-      GemmDesc d = gemm(A64, lda64, OP_N, V.as<double2>() + j * vstride, n, OP_T, u.as<double2>(), n, n, nrhs, n);
+      const double2* q = b32 ? qd.as<double2>() : V.as<double2>() + j * vstride;
+      GemmDesc d = gemm(A64, lda64, OP_N, q, n, OP_T, u.as<double2>(), n, n, nrhs, n);
       d.transC = 1;
       mv[j].push_back(d);
     }
@@ -1248,14 +1282,19 @@ GmresResult gmres_run(KrylovOp& op, int64_t n, int64_t nrhs, const double2* b, d
       residual(r);
     hipLaunchKernelGGL(norm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, r, n, gs.nrm, nullptr);
     hipLaunchKernelGGL(cycle_init_kernel, g1, b1, 0, s, gs, mres, nrhs, tol, inner);
-    if (f32)
-      hipLaunchKernelGGL(scale_kernel<float2>, grid2(n, nrhs), dim3(256), 0, s, r, V.as<float2>(), n, gs.nrm);
+    if (f32 || b32)
+      hipLaunchKernelGGL(scale_kernel<float2>, grid2(n, nrhs), dim3(256), 0, s, r, V.as<float2>(), n, gs.nrm,
+                         qd.as<double2>());
     else
       hipLaunchKernelGGL(scale_kernel<double2>, grid2(n, nrhs), dim3(256), 0, s, r, V.as<double2>(), n, gs.nrm);
     if (all_done(flags.sync_read(gs.active, s)) || total >= p.max_iter) break;
     if (f32)
       run_cycle(matvec32, dyn32.get(), dyn32 ? dyn32->desc(0) : nullptr, jdev.as<int64_t>(), V.as<float2>(),
                 u.as<float2>(), vstride, n, nrhs, mres, p.max_iter, total, gs, part.as<double>(), np, flags, x, s);
+    else if (b32)
+      run_cycle(matvec, dyn.get(), dyn ? dyn->desc(0) : nullptr, jdev.as<int64_t>(), V.as<float2>(), u.as<double2>(),
+                vstride, n, nrhs, mres, p.max_iter, total, gs, part.as<double>(), np, flags, x, s, (const float2*)nullptr,
+                qd.as<double2>());
     else if (dense)
       run_cycle(matvec, dyn.get(), dyn ? dyn->desc(0) : nullptr, jdev.as<int64_t>(), V.as<double2>(),
                 u.as<double2>(), vstride, n, nrhs, mres, p.max_iter, total, gs, part.as<double>(), np, flags, x, s);
@@ -1430,8 +1469,11 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
     CBFM_REQUIRE(prm->cmp_mode == CBFM_CMP_EXACT || prm->cmp_mode == CBFM_CMP_INNER_GMRES, CBFM_E_ARG,
                  "unknown CMP mode");
     const bool flexible = prm->use_cmp == 1 && prm->cmp_mode == CBFM_CMP_INNER_GMRES;
-    CBFM_REQUIRE(!flexible || (prm->inner_fp32 == 0 && prm->use_graph == 0), CBFM_E_ARG,
-                 "the inexact CMP runs double Krylov cycles without graphs");
+    CBFM_REQUIRE(!flexible || (prm->inner_fp32 == 0 && prm->use_graph == 0 && prm->basis_fp32 == 0), CBFM_E_ARG,
+                 "the inexact CMP runs double Krylov cycles with a double basis and without graphs");
+    CBFM_REQUIRE(prm->inner_fp32 == 0 || prm->basis_fp32 == 0, CBFM_E_ARG,
+                 "inner_fp32 and basis_fp32 are two different forms");
+    CBFM_REQUIRE(prm->inner_tol >= 0 && prm->inner_tol < 1, CBFM_E_ARG, "inner_tol outside [0, 1)");
     CBFM_REQUIRE(!flexible || (prm->cmp_inner_tol >= 0 && prm->cmp_inner_tol < 1), CBFM_E_ARG,
                  "cmp_inner_tol outside [0, 1)");
     CBFM_REQUIRE(dirs == nullptr || ndir >= 1, CBFM_E_ARG, "ndir must be >= 1 with dirs");
@@ -1488,6 +1530,7 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
     sp.f32 = prm->inner_fp32 != 0;
     sp.inner_tol = prm->inner_tol;
     sp.graph = prm->use_graph != 0;
+    sp.basis32 = prm->basis_fp32 != 0;
     Scratch x(nrhs * n * sizeof(double2), s);
     DenseOp dop(Aop, lda, nullptr, 0);
     FlexCmpOp fop(Zr, ldz, c, prm->cmp_inner_tol > 0 ? prm->cmp_inner_tol : 1e-5, n);

@@ -388,6 +388,54 @@ def test_graph_replayed_solve_matches_eager(torch_cuda):
     assert g["status"] == "OK" and _rel(jg.cpu().numpy(), ref) < 1e-9
 
 
+def test_compressed_basis_solve(torch_cuda):
+    """The compressed-basis form (double arithmetic, Krylov basis stored in
+    float, cycles restarted from the double residual): at tol 1e-12 it
+    reaches LU of the oracle's reduced system like the plain form, for the
+    batch, a single right-hand side (the split update pass) and graph
+    replays; at tol 1e-6 its true residual meets the tolerance (a right-hand
+    side still above it after the first cycle takes a short second one) in
+    about the plain form's iteration count."""
+    from oracle import excitation
+    O = _oracle_cbf("cyl_small")
+    P = O["P"]
+    w, m = P["w"], P["m"]
+    cbfm, mesh, med, cbf = _gpu_handles(w, O)
+    n = cbf.n_cbf
+    Zr = torch_cuda.zeros((n, n), dtype=torch_cuda.complex128, device="cuda")
+    cbfm.project(mesh, med, cbf, Zr, cbfm.FP64)
+    inc = w.inc
+    nr, ne2 = len(inc), 2 * m.ne
+    vr = O["CJM"].conj().T @ excitation.rhs(m, inc, w.k0, w.eta0)
+    jref = O["CMJ"] @ np.linalg.solve(O["Zr"], vr)
+    rcs_ref = excitation.monostatic_rcs(m, jref, inc, w.k0, w.eta0)
+    for graph in (False, True):
+        jt = torch_cuda.zeros((nr, ne2), dtype=torch_cuda.complex128, device="cuda")
+        out = cbfm.solve(mesh, med, cbf, Zr, inc, tol=1e-12, max_iter=6 * n, restart=n + 10, j_out=jt,
+                         basis_fp32=True, use_graph=graph)
+        e, r = _rel(jt.cpu().numpy().T, jref), np.max(np.abs(out["rcs"] - rcs_ref) / rcs_ref)
+        print("compressed basis, graph", graph, out["iters"], out["relres"], "currents", e, "rcs", r)
+        assert out["status"] == "OK" and np.all(out["relres"] <= 1e-12)
+        assert e < 1e-9 and r < 1e-9
+    j1 = torch_cuda.zeros((1, ne2), dtype=torch_cuda.complex128, device="cuda")
+    o1 = cbfm.solve(mesh, med, cbf, Zr, np.ascontiguousarray(inc[:1]), tol=1e-12, max_iter=6 * n, restart=n + 10,
+                    j_out=j1, basis_fp32=True)
+    e1 = _rel(j1.cpu().numpy().T, jref[:, :1])
+    print("compressed basis, one right-hand side", o1["iters"], e1)
+    assert o1["status"] == "OK" and e1 < 1e-9
+    # tol 1e-6: the true residual meets it, in about the plain form's count
+    a = cbfm.solve(mesh, med, cbf, Zr, inc, tol=1e-6, max_iter=6 * n, restart=n + 10)
+    b = cbfm.solve(mesh, med, cbf, Zr, inc, tol=1e-6, max_iter=6 * n, restart=n + 10, basis_fp32=True)
+    print("tol 1e-6 iterations plain", a["iters"], "compressed", b["iters"], "relres", b["relres"])
+    assert b["status"] == "OK" and np.all(b["relres"] <= 1e-6)
+    assert np.all(b["iters"] <= 1.5 * a["iters"] + 10)
+    # forms that do not combine with it
+    with pytest.raises(RuntimeError):
+        cbfm.solve(mesh, med, cbf, Zr, inc, basis_fp32=True, inner_fp32=True, raise_noconv=True)
+    with pytest.raises(RuntimeError):
+        cbfm.solve(mesh, med, cbf, Zr, inc, basis_fp32=True, cmp_mode=cbfm.CMP_INNER_GMRES, raise_noconv=True)
+
+
 def test_batched_projection_matches_single(torch_cuda):
     """Several scatterers (own sizes and media) through one persistent fill
     launch and batched GEMMs give each one's Z_r as cbfm_project does, and

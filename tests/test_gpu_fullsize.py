@@ -335,9 +335,10 @@ def test_precision_forms_on_the_lossy_sphere_against_the_oracle(torch_cuda):
     (written by make_sphere5120_rcs.py from oracle/ alone; the oracle's
     CBFs span the same spaces, so the RCS agrees to the solver tolerance):
     the monostatic RCS and the bistatic pattern (theta = 0..180 deg, phi =
-    0, error relative to the pattern's maximum).  FP64 within 1e-7; FP32
-    fill and mixed FP32 within 1e-4; split BF16 and BF16 reported, bounded
-    by 1e-3 and 0.1."""
+    0, error relative to the pattern's maximum).  FP64, and FP64 with the
+    Krylov basis stored in float (compressed basis), within 1e-7; FP32 fill
+    and mixed FP32 within 1e-4; split BF16 and BF16 reported, bounded by
+    1e-3 and 0.1."""
     from paper_2111_11058_amd import cbfm
     from synth import configs
     mono_ref, th, bi_ref = _golden_c3()
@@ -350,14 +351,15 @@ def test_precision_forms_on_the_lossy_sphere_against_the_oracle(torch_cuda):
     t = np.deg2rad(th)
     dirs = np.stack([np.sin(t), np.zeros_like(t), np.cos(t)], axis=1)
     Z = torch_cuda.zeros((n, n), dtype=torch_cuda.complex128, device="cuda")
-    forms = {"fp64": (cbfm.FP64, False, 1e-7), "fp32_fill": (cbfm.FP32, False, 1e-4),
-             "mixed_fp32": (cbfm.MIXED_FP32, True, 1e-4), "split_bf16": (cbfm.MIXED_BF16X3, True, 1e-3),
-             "bf16": (cbfm.MIXED_BF16, True, 0.1)}
-    for name, (prec, f32, bar) in forms.items():
+    f32, b32 = dict(inner_fp32=True), dict(basis_fp32=True)
+    forms = {"fp64": (cbfm.FP64, {}, 1e-7), "compressed_basis": (cbfm.FP64, b32, 1e-7),
+             "fp32_fill": (cbfm.FP32, {}, 1e-4), "mixed_fp32": (cbfm.MIXED_FP32, f32, 1e-4),
+             "split_bf16": (cbfm.MIXED_BF16X3, f32, 1e-3), "bf16": (cbfm.MIXED_BF16, f32, 0.1)}
+    for name, (prec, kw, bar) in forms.items():
         print(f"sphere5120 {name}", flush=True)
         cbfm.project(mesh, med, cb, Z, prec)
-        mo = cbfm.solve(mesh, med, cb, Z, w.inc, tol=1e-10, max_iter=4 * n, restart=n, inner_fp32=f32)
-        bo = cbfm.solve(mesh, med, cb, Z, w.inc, tol=1e-10, max_iter=4 * n, restart=n, inner_fp32=f32, dirs=dirs)
+        mo = cbfm.solve(mesh, med, cb, Z, w.inc, tol=1e-10, max_iter=4 * n, restart=n, **kw)
+        bo = cbfm.solve(mesh, med, cb, Z, w.inc, tol=1e-10, max_iter=4 * n, restart=n, dirs=dirs, **kw)
         assert mo["status"] == "OK" and bo["status"] == "OK", (name, mo["status"], bo["status"])
         em = abs(mo["rcs"][0] - mono_ref) / mono_ref
         eb = np.abs(bo["rcs"][0] - bi_ref).max() / bi_ref.max()
