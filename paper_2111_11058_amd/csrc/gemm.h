@@ -6,6 +6,7 @@
 #include "internal.h"
 
 #include <cstdint>
+#include <memory>
 #include <vector>
 
 namespace cbfm {
@@ -129,6 +130,7 @@ class GemmPlan {
   std::vector<int64_t> first_, count_, tiles_, m_, n_;
   std::vector<double> flops_;
   std::vector<int> variant_;
+  std::unique_ptr<Scratch> ws_;  // partial tiles of K-split launch shapes
 };
 
 }  // namespace cbfm

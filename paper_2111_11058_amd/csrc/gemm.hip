@@ -12,6 +12,7 @@
 // The accumulator element r of lane L is C[4 r + L / 16][L % 16] (measured
 // on gfx950 with indexed operands: rows are interleaved across the four
 // lane groups).
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -61,10 +62,43 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// C (tile at rows m0.., columns n0..; CT column blocks) = alpha (cr + i ci),
+// or added to C, in the accumulator layout of the FP64 matrix cores.
+template <int CT>
+__device__ __forceinline__ void store_tile(const GemmDesc& d, int64_t m0, int64_t n0, int lane, const dbl4 (&cr)[CT],
+                                           const dbl4 (&ci)[CT]) {
+  const int slot = lane >> 4;
+#pragma unroll
+  for (int u = 0; u < CT; ++u) {
+    const int64_t col = n0 + 16 * u + (lane & 15);
+    if (col >= d.N) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = m0 + 4 * r + slot;
+      if (row < d.M) {
+        const double xr = cr[u][r], xi = ci[u][r];
+        double2 v = make_double2(d.alpha_re * xr - d.alpha_im * xi, d.alpha_re * xi + d.alpha_im * xr);
+        double2* p = d.transC ? d.C + col * d.ldc + row : d.C + row * d.ldc + col;
+        if (d.accumulate) {
+          const double2 o = ld_global(p);
+          v.x += o.x;
+          v.y += o.y;
+        }
+        *p = v;
+      }
+    }
+  }
+}
+
 // SPLITK = 1: each of the 4 wavefronts of a block owns a tile.
 // SPLITK > 1: the SPLITK wavefronts of a block share one tile, each taking
 // every SPLITK-th group of 16 k, and the partial tiles are summed through
 // LDS (few, deep tiles: more loads in flight per tile).
+// KB > 1 (SPLITK > 1, one descriptor only): KB consecutive blocks share a
+// tile, block b of them taking the groups g with g / SPLITK = b mod KB, so
+// that a product of few tiles and long K still has short K loops and fills
+// the chip; each block leaves its partial tile in ws (KB x 64 lanes x 8 CT
+// doubles per tile) and splitk_reduce_kernel adds them in block order.
 // CT > 1 (one descriptor only): a tile is 16 rows by CT adjacent 16-column
 // blocks, so a wavefront loads each part of op(A) once for CT column blocks
 // (a matrix times a few vectors reads the matrix once instead of CT times).
@@ -74,9 +108,12 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) {
 // and reads them back in the matrix-core layout.  Loading the matrix-core
 // layout straight from memory spreads every load instruction over 32 cache
 // lines and runs at about half the speed on the shapes of this library.
+// (Tiles of one column block keep to 128 registers, 4 wavefronts per SIMD,
+// so that a few-tile product's blocks all fit on the chip at once.)
 template <int SPLITK, int CT>
-__global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK)
-    zgemm_batched_kernel(const GemmDesc* __restrict__ desc, int ndesc, int64_t total_tiles) {
+__global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK, CT == 1 ? 4 : 1)
+    zgemm_batched_kernel(const GemmDesc* __restrict__ desc, int ndesc, int64_t total_tiles, int KB = 1,
+                         double* __restrict__ ws = nullptr) {
   constexpr int NW = SPLITK == 1 ? 4 : SPLITK;  // wavefronts per block
   constexpr int NS = 1 + CT;                    // staged sub-tiles per wavefront: A, then B per column block
   constexpr int STAGE = NW * NS * 16 * 17;      // double2, rows padded to 17
@@ -87,7 +124,8 @@ __global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK)
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // wave-uniform tile and descriptor (readfirstlane makes the K loop a scalar
   // loop: the accumulators then stay in the matrix-core registers across it)
-  const int64_t tile = SPLITK == 1 ? (int64_t)blockIdx.x * 4 + wave : (int64_t)blockIdx.x;
+  const int64_t tile = SPLITK == 1 ? (int64_t)blockIdx.x * 4 + wave : (int64_t)blockIdx.x / KB;
+  const int kb = SPLITK == 1 ? 0 : (int)(blockIdx.x % KB);
   if (tile >= total_tiles) return;  // uniform per block when SPLITK > 1
   // descriptor holding this tile (tile_start ascending)
   int lo = 0, hi = ndesc - 1;
@@ -125,7 +163,7 @@ __global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK)
 #pragma unroll
   for (int u = 0; u < CT; ++u) p1[u] = p2[u] = p3[u] = dbl4{0, 0, 0, 0};
   // this wavefront's groups of 16 k: k0 = 16 (wave + SPLITK g), g < ng
-  const int64_t kfirst = SPLITK == 1 ? 0 : 16 * wave, kstep = 16 * SPLITK;
+  const int64_t kfirst = SPLITK == 1 ? 0 : 16 * (wave + (int64_t)SPLITK * kb), kstep = 16 * SPLITK * KB;
   const int64_t ng = kfirst < d.K ? (d.K - kfirst + kstep - 1) / kstep : 0;
   double2 ga[4], gb[CT][4];
   // Lane (slot, li), load q: line 4 q + slot of the operand, element li
@@ -241,27 +279,47 @@ __global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK)
           ci[u][q] += r[8 * u + 4 + q];
         }
     }
-  }
+    if (KB > 1) {  // this block's part of the tile, for splitk_reduce_kernel
+      double* o = ws + (((int64_t)tile * KB + kb) * 64 + lane) * 8 * CT;
 #pragma unroll
-  for (int u = 0; u < CT; ++u) {
-    const int64_t col = n0 + 16 * u + (lane & 15);
-    if (col >= d.N) continue;
+      for (int u = 0; u < CT; ++u)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = m0 + 4 * r + slot;
-      if (row < d.M) {
-        const double xr = cr[u][r], xi = ci[u][r];
-        double2 v = make_double2(d.alpha_re * xr - d.alpha_im * xi, d.alpha_re * xi + d.alpha_im * xr);
-        double2* p = d.transC ? d.C + col * d.ldc + row : d.C + row * d.ldc + col;
-        if (d.accumulate) {
-          const double2 o = ld_global(p);
-          v.x += o.x;
-          v.y += o.y;
+        for (int q = 0; q < 4; ++q) {
+          o[8 * u + q] = cr[u][q];
+          o[8 * u + 4 + q] = ci[u][q];
         }
-        *p = v;
-      }
+      return;
     }
   }
+  store_tile<CT>(d, m0, n0, lane, cr, ci);
+}
+
+// The tiles of a K-split product (one descriptor): one wavefront per tile
+// adds its KB parts from ws in block order and stores the tile.
+template <int CT>
+__global__ void __launch_bounds__(64)
+    splitk_reduce_kernel(const GemmDesc* __restrict__ desc, int64_t total_tiles, int KB, const double* __restrict__ ws) {
+  const int64_t tile = blockIdx.x;
+  if (tile >= total_tiles) return;
+  const int lane = threadIdx.x;
+  const GemmDesc d = desc[0];
+  const int64_t t = tile - (CT == 1 ? d.tile_start : 0);
+  const int64_t ntn = (d.N + 16 * CT - 1) / (16 * CT);
+  const int64_t m0 = (t / ntn) * 16, n0 = (t % ntn) * 16 * CT;
+  dbl4 cr[CT], ci[CT];
+#pragma unroll
+  for (int u = 0; u < CT; ++u) cr[u] = ci[u] = dbl4{0, 0, 0, 0};
+  for (int b = 0; b < KB; ++b) {
+    const double* r = ws + ((tile * KB + b) * 64 + lane) * 8 * CT;
+#pragma unroll
+    for (int u = 0; u < CT; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cr[u][q] += r[8 * u + q];
+        ci[u][q] += r[8 * u + 4 + q];
+      }
+  }
+  store_tile<CT>(d, m0, n0, lane, cr, ci);
 }
 
 // ------------------------------------------------------------------------
@@ -680,11 +738,40 @@ __global__ void __launch_bounds__(256) zgemv_kernel(const GemmDesc* __restrict__
 // Launch shapes: four tiles per block (one per wavefront), or one tile per
 // block with K split over 4 or 8 wavefronts; for a single product also
 // tiles of 2 or 4 adjacent 16-column blocks with K split over 4 wavefronts
-// (op(A) read once for them; with 8 wavefronts they would spill), and for a
-// single matrix-vector product the vector-unit kernel.
-enum { GV_TILE4 = 0, GV_SPLIT4, GV_SPLIT8, GV_WIDE2_S4, GV_WIDE4_S4, GV_GEMV, GV_COUNT };
+// (op(A) read once for them; with 8 wavefronts they would spill), one tile
+// per block with K split over 5 wavefronts, or over 3 wavefronts and 2
+// blocks, or 2 wavefronts and 3 blocks (few tiles and long K: the K loop
+// of a wavefront waits on memory about once per group of 16 k, so the
+// launch is fastest with the shortest loops whose blocks all fit on the
+// chip at once; 528 tiles of 8 wavefronts, say, leave 16 blocks for a
+// second round at 4 wavefronts per SIMD), and for a single
+// matrix-vector product the vector-unit kernel.
+enum {
+  GV_TILE4 = 0,
+  GV_SPLIT4,
+  GV_SPLIT8,
+  GV_WIDE2_S4,
+  GV_WIDE4_S4,
+  GV_SPLIT5,
+  GV_SPLIT3_KB2,
+  GV_SPLIT2_KB3,
+  GV_GEMV,
+  GV_COUNT
+};
 
 static bool single_only(int v) { return v >= GV_WIDE2_S4; }
+
+// column blocks per tile and blocks per tile of the launch shapes
+static int ct_of(int v) { return v == GV_WIDE4_S4 ? 4 : v == GV_WIDE2_S4 ? 2 : 1; }
+static int kb_of(int v) { return v == GV_SPLIT3_KB2 ? 2 : v == GV_SPLIT2_KB3 ? 3 : 1; }
+
+// bytes of partial tiles a launch shape leaves for splitk_reduce_kernel
+static size_t ws_bytes(int v, int64_t tiles, int64_t M, int64_t N) {
+  const int kb = kb_of(v), ct = ct_of(v);
+  if (kb == 1) return 0;
+  const int64_t t = ct == 1 ? tiles : ((M + 15) / 16) * ((N + 16 * ct - 1) / (16 * ct));
+  return (size_t)t * kb * 64 * 8 * ct * sizeof(double);
+}
 
 // The vector-unit kernel takes one column with op(A) rows contiguous.
 static bool gemv_shape(int64_t N, int opA) { return N == 1 && (opA == OP_N || opA == OP_R); }
@@ -692,7 +779,7 @@ static bool gemv_shape(int64_t N, int opA) { return N == 1 && (opA == OP_N || op
 // tiles: 16 x 16 tiles of the group; M, N: the sizes of its product when it
 // has one (the wide shapes number their own tiles)
 static void launch_variant(int v, const GemmDesc* dev, int count, int64_t tiles, int64_t M, int64_t N,
-                           hipStream_t s) {
+                           hipStream_t s, double* ws) {
   const dim3 one((unsigned)tiles);
   auto wide = [&](int ct) { return ((M + 15) / 16) * ((N + 16 * ct - 1) / (16 * ct)); };
   CBFM_REQUIRE(!single_only(v) || count == 1, CBFM_E_ARG, "wide GEMM tiles need a single product");
@@ -712,6 +799,21 @@ static void launch_variant(int v, const GemmDesc* dev, int count, int64_t tiles,
       break;
     case GV_WIDE2_S4:
       hipLaunchKernelGGL((zgemm_batched_kernel<4, 2>), dim3((unsigned)wide(2)), dim3(256), 0, s, dev, count, wide(2));
+      break;
+    case GV_SPLIT5:
+      hipLaunchKernelGGL((zgemm_batched_kernel<5, 1>), one, dim3(320), 0, s, dev, count, tiles);
+      break;
+    case GV_SPLIT3_KB2:
+      CBFM_REQUIRE(ws != nullptr, CBFM_E_ARG, "K-split GEMM without workspace");
+      hipLaunchKernelGGL((zgemm_batched_kernel<3, 1>), dim3((unsigned)(tiles * 2)), dim3(192), 0, s, dev, count, tiles,
+                         2, ws);
+      hipLaunchKernelGGL(splitk_reduce_kernel<1>, one, dim3(64), 0, s, dev, tiles, 2, ws);
+      break;
+    case GV_SPLIT2_KB3:
+      CBFM_REQUIRE(ws != nullptr, CBFM_E_ARG, "K-split GEMM without workspace");
+      hipLaunchKernelGGL((zgemm_batched_kernel<2, 1>), dim3((unsigned)(tiles * 3)), dim3(128), 0, s, dev, count, tiles,
+                         3, ws);
+      hipLaunchKernelGGL(splitk_reduce_kernel<1>, one, dim3(64), 0, s, dev, tiles, 3, ws);
       break;
     default:
       hipLaunchKernelGGL((zgemm_batched_kernel<4, 4>), dim3((unsigned)wide(4)), dim3(256), 0, s, dev, count, wide(4));
@@ -738,8 +840,25 @@ static GemmKey key_of(int dev, const GemmDesc* d, int count, int64_t tiles) {
   return GemmKey{dev, count, d[0].opA, d[0].opB, tiles, d[0].M, d[0].N, K};
 }
 
+// Launch shape v runs a group of this shape class.
+static bool applicable(int v, const GemmKey& k) {
+  return !(single_only(v) && k.count != 1) && !(v == GV_GEMV && !gemv_shape(k.N, k.opA));
+}
+
+// CBFM_GEMM_SHAPE (for tests and tuning studies): the index of a launch
+// shape (the order of the enum above) forced on every group it applies to,
+// in place of the tuned or default choice.
+static int forced_shape() {
+  const char* e = std::getenv("CBFM_GEMM_SHAPE");
+  if (e == nullptr || *e == 0) return -1;
+  const int v = std::atoi(e);
+  return v >= 0 && v < GV_COUNT ? v : -1;
+}
+
 // Without a measurement: few tiles get the K split over four wavefronts.
 static int choose(const GemmKey& k) {
+  const int f = forced_shape();
+  if (f >= 0 && applicable(f, k)) return f;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tuned.find(k);
   if (it != g_tuned.end()) return it->second;
@@ -747,9 +866,9 @@ static int choose(const GemmKey& k) {
 }
 
 static void launch_descs(const GemmDesc* dev, int count, int64_t tiles, int64_t M, int64_t N, double flops,
-                         int variant, hipStream_t s) {
+                         int variant, hipStream_t s, double* ws) {
   TimedLaunch tl(T_GEMM, s, flops);
-  launch_variant(variant, dev, count, tiles, M, N, s);
+  launch_variant(variant, dev, count, tiles, M, N, s, ws);
 }
 
 // Elements spanned by an operand or the result of a descriptor.
@@ -790,12 +909,15 @@ static void tune_group(const GemmKey& key, const GemmDesc* dev, int count, int64
   int best = choose(key);
   float best_ms = 0;
   try {
+    size_t wsb = 0;
+    if (count == 1)
+      for (int v = 0; v < GV_COUNT; ++v) wsb = std::max(wsb, ws_bytes(v, tiles, key.M, key.N));
+    Scratch ws(wsb, s);
     for (int v = 0; v < GV_COUNT; ++v) {
-      if (single_only(v) && count != 1) continue;
-      if (v == GV_GEMV && !gemv_shape(key.N, key.opA)) continue;
-      launch_variant(v, dev, count, tiles, key.M, key.N, s);
+      if (!applicable(v, key)) continue;
+      launch_variant(v, dev, count, tiles, key.M, key.N, s, ws.as<double>());
       CBFM_HIP(hipEventRecord(e0, s));
-      for (int r = 0; r < 3; ++r) launch_variant(v, dev, count, tiles, key.M, key.N, s);
+      for (int r = 0; r < 3; ++r) launch_variant(v, dev, count, tiles, key.M, key.N, s, ws.as<double>());
       CBFM_HIP(hipEventRecord(e1, s));
       CBFM_HIP(hipEventSynchronize(e1));
       float ms = 0;
@@ -826,8 +948,9 @@ void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s) {
   CBFM_HIP(hipMemcpyAsync(dev.p, live.data(), live.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
   int d = 0;
   CBFM_HIP(hipGetDevice(&d));
-  launch_descs(dev.as<GemmDesc>(), (int)live.size(), tiles, live[0].M, live[0].N, flops,
-               choose(key_of(d, live.data(), (int)live.size(), tiles)), s);
+  const int v = choose(key_of(d, live.data(), (int)live.size(), tiles));
+  Scratch ws(ws_bytes(v, tiles, live[0].M, live[0].N), s);
+  launch_descs(dev.as<GemmDesc>(), (int)live.size(), tiles, live[0].M, live[0].N, flops, v, s, ws.as<double>());
   // the descriptor staging buffer is host memory of this frame
   CBFM_HIP(hipStreamSynchronize(s));
 }
@@ -872,12 +995,17 @@ GemmPlan::GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t
     last_variant = choose(k);
     variant_.push_back(last_variant);
   }
+  // one workspace for the partial tiles of every group (launched in turn)
+  size_t wsb = 0;
+  for (size_t g = 0; g < groups.size(); ++g) wsb = std::max(wsb, ws_bytes(variant_[g], tiles_[g], m_[g], n_[g]));
+  ws_.reset(new Scratch(wsb, s));
 }
 
 void GemmPlan::launch(size_t g, hipStream_t s) const {
   CBFM_REQUIRE(g < tiles_.size(), CBFM_E_ARG, "GEMM plan group out of range");
   if (count_[g] == 0) return;
-  launch_descs(dev_.as<GemmDesc>() + first_[g], (int)count_[g], tiles_[g], m_[g], n_[g], flops_[g], variant_[g], s);
+  launch_descs(dev_.as<GemmDesc>() + first_[g], (int)count_[g], tiles_[g], m_[g], n_[g], flops_[g], variant_[g], s,
+               ws_->as<double>());
 }
 
 }  // namespace cbfm

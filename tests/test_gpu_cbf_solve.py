@@ -436,6 +436,39 @@ def test_compressed_basis_solve(torch_cuda):
         cbfm.solve(mesh, med, cbf, Zr, inc, basis_fp32=True, cmp_mode=cbfm.CMP_INNER_GMRES, raise_noconv=True)
 
 
+def test_every_gemm_launch_shape_solves_alike(torch_cuda, monkeypatch):
+    """Every launch shape of the complex GEMM (CBFM_GEMM_SHAPE forces it on
+    each product it applies to; the tuner may pick any of them for the
+    GMRES matrix-vector product): four tiles per block, K split over 4 or 8
+    wavefronts, wide tiles of 2 or 4 column blocks, K split over 5
+    wavefronts, over 3 wavefronts x 2 blocks and 2 wavefronts x 3 blocks
+    (partial tiles added by a second kernel), and the vector-unit
+    matrix-vector kernel (a single right-hand side).  Each solve, at tol
+    1e-12 with the full Krylov space, matches LU of the oracle's reduced
+    system."""
+    from oracle import excitation
+    O = _oracle_cbf("cyl_small")
+    P = O["P"]
+    w, m = P["w"], P["m"]
+    cbfm, mesh, med, cbf = _gpu_handles(w, O)
+    n = cbf.n_cbf
+    Zr = torch_cuda.zeros((n, n), dtype=torch_cuda.complex128, device="cuda")
+    cbfm.project(mesh, med, cbf, Zr, cbfm.FP64)
+    inc = w.inc
+    vr = O["CJM"].conj().T @ excitation.rhs(m, inc, w.k0, w.eta0)
+    jref = O["CMJ"] @ np.linalg.solve(O["Zr"], vr)
+    for shape in range(9):
+        monkeypatch.setenv("CBFM_GEMM_SHAPE", str(shape))
+        for sel in (slice(None), slice(0, 1)):
+            ii = np.ascontiguousarray(inc[sel])
+            jt = torch_cuda.zeros((len(ii), 2 * m.ne), dtype=torch_cuda.complex128, device="cuda")
+            out = cbfm.solve(mesh, med, cbf, Zr, ii, tol=1e-12, max_iter=n + 10, restart=n + 10, j_out=jt)
+            e = _rel(jt.cpu().numpy().T, jref[:, sel])
+            print("GEMM shape", shape, "right-hand sides", len(ii), out["iters"], e)
+            assert out["status"] == "OK" and e < 1e-9, (shape, len(ii))
+    monkeypatch.delenv("CBFM_GEMM_SHAPE")
+
+
 def test_batched_projection_matches_single(torch_cuda):
     """Several scatterers (own sizes and media) through one persistent fill
     launch and batched GEMMs give each one's Z_r as cbfm_project does, and
