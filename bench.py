@@ -714,6 +714,8 @@ def main():
     ap.add_argument("--workload", default="cylinder19968", choices=WORKLOADS)
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="fill precision of the timed step (default: fp32 for cylinder19968, else fp64)")
+    ap.add_argument("--sstep", type=int, default=0, choices=[0, 4, 8],
+                    help="time the main step with s-step GMRES cycles of blocks of this many iterations")
     ap.add_argument("--basis-fp32", action="store_true",
                     help="time the compressed-basis form (double arithmetic, Krylov basis stored in float) as the "
                          "main step")
@@ -808,7 +810,7 @@ def main():
     state = {}
     traffic = measured_traffic(args.workload)
 
-    def step(precision, inner_fp32=False, timed=None, basis_fp32=False):
+    def step(precision, inner_fp32=False, timed=None, basis_fp32=False, sstep=0):
         cb = cbfm.build_cbf(mesh, med, w.gen, w.delta_svd, max_L=w.extra.get("max_L", 0))
         n = cb.n_cbf
         Zr = state.get(n)
@@ -826,23 +828,23 @@ def main():
         m = full_restart(n, len(w.inc))
         done = timed("solve") if timed else None
         t2 = time.perf_counter()
-        restarts = inner_fp32 or basis_fp32
+        restarts = inner_fp32 or basis_fp32 or sstep > 0
         out = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, max_iter=(3 if restarts else 1) * max(n, 3000),
-                         restart=m, inner_fp32=inner_fp32, basis_fp32=basis_fp32, **solver)
+                         restart=m, inner_fp32=inner_fp32, basis_fp32=basis_fp32, sstep=sstep, **solver)
         t3 = time.perf_counter()
         if done:
             done()
         return cb, out, t1 - t0, t3 - t2
 
-    B32 = args.basis_fp32
+    B32, SST = args.basis_fp32, args.sstep
     for i in range(args.warmup):
         log(f"warmup {i}")
-        step(PREC, basis_fp32=B32)
+        step(PREC, basis_fp32=B32, sstep=SST)
     torch.cuda.synchronize()
     proj_t, solve_t, iters = [], [], []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        cb, out, tp, ts = step(PREC, basis_fp32=B32)
+        cb, out, tp, ts = step(PREC, basis_fp32=B32, sstep=SST)
         proj_t.append(tp)
         solve_t.append(ts)
         iters.append(out["iters"])
@@ -851,7 +853,7 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     nt = w.nt
-    roof, roofs = rooflines(cbfm, lambda timed: step(PREC, timed=timed, basis_fp32=B32), traffic)
+    roof, roofs = rooflines(cbfm, lambda timed: step(PREC, timed=timed, basis_fp32=B32, sstep=SST), traffic)
     nrhs = len(w.inc)
     lat = np.array(solve_t)
     result = {
@@ -870,6 +872,7 @@ def main():
         "config": {"workload": f"{w.name}: {nt} triangles, {3 * nt // 2} RWGs, {3 * nt} unknowns, "
                                f"{w.nblocks} cells, {nrhs} incidences, {len(w.gen)} generating waves",
                    "fill_precision": prec_name, "krylov_basis": "fp32" if B32 else "fp64",
+                   "gmres": f"s-step, blocks of {SST}" if SST else "plain (DCGS2)",
                    "n_cbf": int(cb.n_cbf), "solver": solver},
         "fill_projection_pair_evals_per_s": nt * nt / float(np.median(proj_t)),
         "solves_per_s": nrhs * args.steps / float(lat.sum()),

@@ -130,8 +130,9 @@ cbfm_status cbfm_set_allocator(cbfm_alloc_fn alloc, cbfm_release_fn release);
 cbfm_status cbfm_memory_stats(int64_t* held, int64_t* peak, int64_t* cached);
 
 /* ABI version (incremented on incompatible change). */
-int32_t cbfm_version(void);  /* 4: cbfm_solver_params gained basis_fp32 (3: cbfm_request gained
-                                inner_fp32; 2: cbfm_solver_params gained cmp_mode, cmp_inner_tol) */
+int32_t cbfm_version(void);  /* 5: cbfm_solver_params gained sstep (4: basis_fp32; 3: cbfm_request
+                                gained inner_fp32; 2: cbfm_solver_params gained cmp_mode,
+                                cmp_inner_tol) */
 
 /* -------------------------------------------------------------- timers ---
  * Opt-in kernel timing for measurement: when enabled, the library records a
@@ -437,6 +438,20 @@ typedef struct {
                       /* (CBFM_E_ARG).  cbfm_mom_solve takes it with an   */
                       /* FP64 operator (ignored for FP32, whose cycles    */
                       /* are float); cbfm_solve_matfree rejects it.       */
+  int32_t sstep;      /* 4 or 8: s-step (communication-avoiding) cycles of */
+                      /* the same GMRES -- per block of sstep iterations, */
+                      /* a Newton basis (shifts: Ritz values of a first   */
+                      /* plain cycle of sstep + 1 iterations, Leja order) */
+                      /* by sstep matrix-vector products, two block       */
+                      /* Gram-Schmidt passes and two Cholesky QR passes,  */
+                      /* and the Hessenberg columns rebuilt from their    */
+                      /* coefficients: the basis is read 4 times per      */
+                      /* block instead of twice per iteration.  After a   */
+                      /* Cholesky breakdown the solve continues with      */
+                      /* plain cycles.  0: plain cycles.  Not with        */
+                      /* inner_fp32, basis_fp32, use_graph or             */
+                      /* CBFM_CMP_INNER_GMRES (CBFM_E_ARG); cbfm_solve    */
+                      /* only.                                            */
 } cbfm_solver_params;
 
 cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, const void* Zr_dev,

@@ -47,6 +47,8 @@ struct GmresSpec {
   bool graph = false;      // Arnoldi chunks replayed from a HIP graph (dense operators)
   bool basis32 = false;    // double cycles with the Krylov basis stored in float (dense double
                            // operator); each cycle stops at a reduction of inner_tol as in f32
+  int sstep = 0;           // 4 or 8: s-step cycles of blocks of that many iterations (dense double
+                           // operator, double basis, no graphs); 0: plain cycles
 };
 
 struct GmresResult {

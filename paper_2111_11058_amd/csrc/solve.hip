@@ -14,6 +14,7 @@
 // flags every few iterations, one read behind.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <memory>
 #include <type_traits>
@@ -1131,6 +1132,686 @@ static void run_cycle(const MV& mv, const MV* dyn, void* dyn_desc, int64_t* jdev
   CBFM_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------------------- s-step cycles
+// Communication-avoiding form of the same GMRES (double arithmetic, dense
+// double operator): per block of S iterations from the newest basis vector
+// q_j, the Newton basis z_i = (A - theta_i) z_{i-1} / sigma_i (z_0 = q_j,
+// i = 1..S) is formed by S matrix-vector products, orthogonalised against
+// q_0..q_j by two block Gram-Schmidt passes (C = Q^H Z, Z -= Q C, twice)
+// and within itself by two Cholesky QR passes (Z = U R), so that the basis
+// is read four times per S iterations instead of twice per iteration.  With
+// t_i the coordinates of z_i in [Q, U] (t_0 = e_j, t_i = [C_i; R_i]) and
+// A z_{i-1} = sigma_i z_i + theta_i z_{i-1}, the new Hessenberg columns
+// j..j+S-1 are (T_next - [H_old T_old; 0]) T_new^{-1}, where T_next holds
+// sigma_i t_i + theta_i t_{i-1}, T_old the rows of t_0..t_{S-1} below j and
+// T_new their rows j..j+S-1 (upper triangular).  The shifts are the Ritz
+// values of a first plain cycle of S iterations in Leja order.
+
+// z = u - theta q (written to basis slot jd, q = slot jd - 1) and the
+// partial sums of |z|^2 of each 256-row block
+__global__ void __launch_bounds__(256) newton_kernel(const double2* __restrict__ u, double2* __restrict__ V,
+                                                     int64_t vstride, int64_t n, int64_t jd,
+                                                     const double2* __restrict__ theta, int S, int ti,
+                                                     GmresState st, double* __restrict__ part) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+  if (!st.active[c]) return;  // uniform over the block
+  double q2 = 0;
+  if (k < n) {
+    const double2 th = theta[c * S + ti];
+    const double2 q = V[(jd - 1) * vstride + c * n + k], w = u[c * n + k];
+    const double2 z = make_double2(w.x - (th.x * q.x - th.y * q.y), w.y - (th.x * q.y + th.y * q.x));
+    V[jd * vstride + c * n + k] = z;
+    q2 = z.x * z.x + z.y * z.y;
+  }
+  __shared__ double sh[4];
+  q2 = wave_sum(q2);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = q2;
+  __syncthreads();
+  if (threadIdx.x == 0) part[c * gridDim.x + blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// sigma = sqrt(sum of the partial sums); slot jd /= sigma
+__global__ void __launch_bounds__(256) nscale_kernel(double2* __restrict__ V, int64_t vstride, int64_t n, int64_t jd,
+                                                     const double* __restrict__ part, int np, double* __restrict__ sig,
+                                                     int S, int ti, GmresState st) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+  if (!st.active[c]) return;
+  double q = 0;
+  for (int b = 0; b < np; ++b) q += part[c * np + b];
+  const double sg = sqrt(q);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sig[c * S + ti] = sg;
+  if (k < n) {
+    const double r = sg > 0 ? 1.0 / sg : 0.0;
+    double2* p = V + jd * vstride + c * n + k;
+    *p = make_double2(p->x * r, p->y * r);
+  }
+}
+
+// out[c][l][i] = sum_k conj(L_l[k]) R_i[k] for l < nv, i < S: left vector l
+// of right-hand side c at L + l ls + c lc, right vector i at R + i rs + c rc.
+// One block of four wavefronts per right-hand side and run of four left
+// vectors; the threads take every 256th row with the S right values of the
+// row loaded once for the four left vectors, and the wavefronts are summed
+// through LDS in a fixed order.
+template <int S>
+__global__ void __launch_bounds__(256) block_dots_kernel(const double2* __restrict__ L, int64_t ls, int64_t lc,
+                                                         const double2* __restrict__ R, int64_t rs, int64_t rc,
+                                                         int64_t n, int64_t nv, double2* __restrict__ out, int64_t ost,
+                                                         GmresState st) {
+  const int64_t runs = (nv + 3) / 4;
+  const int64_t run = blockIdx.x % runs, c = blockIdx.x / runs;
+  if (!st.active[c]) return;  // uniform over the block
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t l0 = run * 4;
+  const int cnt = (int)std::min<int64_t>(4, nv - l0);
+  const double2* Lc = L + l0 * ls + c * lc;
+  const double2* Rc = R + c * rc;
+  double2 acc[4][S];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int i = 0; i < S; ++i) acc[t][i] = make_double2(0, 0);
+  for (int64_t k = threadIdx.x; k < n; k += 256) {
+    double2 v[4], z[S];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = Lc[(t < cnt ? t : 0) * ls + k];  // vectors past nv: discarded
+#pragma unroll
+    for (int i = 0; i < S; ++i) z[i] = Rc[i * rs + k];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < S; ++i) acc[t][i] = cadd(acc[t][i], cconjmul(v[t], z[i]));
+  }
+  __shared__ double2 sh[4][4][S];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      const double re = wave_sum(acc[t][i].x), im = wave_sum(acc[t][i].y);
+      if (lane == 0) sh[wv][t][i] = make_double2(re, im);
+    }
+  __syncthreads();
+  const int e = threadIdx.x;
+  if (e < 4 * S && e / S < cnt) {
+    const int t = e / S, i = e % S;
+    const double2 a = cadd(cadd(sh[0][t][i], sh[1][t][i]), cadd(sh[2][t][i], sh[3][t][i]));
+    out[c * ost + (l0 + t) * S + i] = a;
+  }
+}
+
+// Z_i[k] -= sum_{l < nv} C[c][l][i] Q_l[k] (Q_l = V + l vstride + c n, Z_i in
+// the basis slots after q_j): eight wavefronts take 128 consecutive rows of
+// one right-hand side (two per lane), wavefront v summing over l = v mod 8;
+// the partial sums are added through LDS in wavefront order.
+template <int S>
+__global__ void __launch_bounds__(512) block_update_kernel(const double2* __restrict__ V, int64_t vstride,
+                                                           double2* __restrict__ Z, int64_t n, int64_t nv,
+                                                           const double2* __restrict__ C, int64_t cst, int np,
+                                                           GmresState st) {
+  constexpr int RPL = 2;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t c = blockIdx.x / np, rb = blockIdx.x % np;
+  if (!st.active[c]) return;  // uniform over the block
+  int64_t kk[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int64_t k = (rb * RPL + r) * 64 + lane;
+    kk[r] = k < n ? k : 0;  // rows past n: a valid row, discarded
+  }
+  const double2* Q = V + c * n;
+  const double2* Cc = C + c * cst * S;
+  double2 acc[RPL][S];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r)
+#pragma unroll
+    for (int i = 0; i < S; ++i) acc[r][i] = make_double2(0, 0);
+  int64_t l = wv;
+  for (; l + 8 < nv; l += 16) {  // two left vectors at a time, their loads issued together
+    double2 q0[RPL], q1[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      q0[r] = Q[l * vstride + kk[r]];
+      q1[r] = Q[(l + 8) * vstride + kk[r]];
+    }
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      const double2 a0 = Cc[l * S + i], a1 = Cc[(l + 8) * S + i];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) acc[r][i] = cadd(acc[r][i], cadd(cmul(a0, q0[r]), cmul(a1, q1[r])));
+    }
+  }
+  for (; l < nv; l += 8) {
+    double2 q0[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) q0[r] = Q[l * vstride + kk[r]];
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      const double2 a0 = Cc[l * S + i];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) acc[r][i] = cadd(acc[r][i], cmul(a0, q0[r]));
+    }
+  }
+  __shared__ double2 sh[RPL][64][S];
+  for (int w = 0; w < 8; ++w) {
+    if (wv == w) {
+#pragma unroll
+      for (int r = 0; r < RPL; ++r)
+#pragma unroll
+        for (int i = 0; i < S; ++i) sh[r][lane][i] = w == 0 ? acc[r][i] : cadd(sh[r][lane][i], acc[r][i]);
+    }
+    __syncthreads();
+  }
+  if (wv != 0) return;
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int64_t k = (rb * RPL + r) * 64 + lane;
+    if (k >= n) continue;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      double2* p = Z + i * vstride + c * n + k;
+      const double2 a = sh[r][lane][i];
+      *p = make_double2(p->x - a.x, p->y - a.y);
+    }
+  }
+}
+
+// Cholesky factor of one right-hand side's Gram matrix G = R^H R (R upper,
+// S x S), its inverse, and Rt = R (first pass) or R Rt; a pivot not above
+// 1e-28 of G's largest diagonal entry marks a breakdown (broken[c] = 1).
+template <int S>
+__global__ void __launch_bounds__(64) chol_kernel(const double2* __restrict__ G, double2* __restrict__ Rinv,
+                                                  double2* __restrict__ Rt, int first, GmresState st,
+                                                  int32_t* __restrict__ broken) {
+  const int64_t c = blockIdx.x;
+  if (!st.active[c] || threadIdx.x != 0) return;
+  __shared__ double2 R[S][S], Ri[S][S], old[S][S];
+  const double2* Gc = G + c * S * S;
+  double gmax = 0;
+  for (int i = 0; i < S; ++i) gmax = fmax(gmax, Gc[i * S + i].x);
+  bool bad = !(gmax > 0);
+  for (int i = 0; i < S && !bad; ++i) {
+    double d = Gc[i * S + i].x;
+    for (int p = 0; p < i; ++p) d -= R[p][i].x * R[p][i].x + R[p][i].y * R[p][i].y;
+    if (!(d > 1e-28 * gmax)) {
+      bad = true;
+      break;
+    }
+    const double rii = sqrt(d);
+    R[i][i] = make_double2(rii, 0);
+    for (int q = i + 1; q < S; ++q) {
+      double2 a = Gc[i * S + q];
+      for (int p = 0; p < i; ++p) a = make_double2(a.x - (R[p][i].x * R[p][q].x + R[p][i].y * R[p][q].y),
+                                                   a.y - (R[p][i].x * R[p][q].y - R[p][i].y * R[p][q].x));
+      R[i][q] = make_double2(a.x / rii, a.y / rii);
+    }
+    for (int q = 0; q < i; ++q) R[i][q] = make_double2(0, 0);
+  }
+  if (bad) {
+    broken[c] = 1;
+    return;
+  }
+  for (int i = S - 1; i >= 0; --i) {
+    Ri[i][i] = make_double2(1.0 / R[i][i].x, 0);
+    for (int q = i + 1; q < S; ++q) {
+      double2 a = make_double2(0, 0);
+      for (int p = i; p < q; ++p) a = cadd(a, cmul(Ri[i][p], R[p][q]));
+      Ri[i][q] = make_double2(-a.x / R[q][q].x, -a.y / R[q][q].x);
+    }
+    for (int q = 0; q < i; ++q) Ri[i][q] = make_double2(0, 0);
+  }
+  double2* Ric = Rinv + c * S * S;
+  double2* Rtc = Rt + c * S * S;
+  if (!first)
+    for (int i = 0; i < S; ++i)
+      for (int q = 0; q < S; ++q) old[i][q] = Rtc[i * S + q];
+  for (int i = 0; i < S; ++i)
+    for (int q = 0; q < S; ++q) {
+      Ric[i * S + q] = Ri[i][q];
+      if (first) {
+        Rtc[i * S + q] = R[i][q];
+      } else {
+        double2 a = make_double2(0, 0);
+        for (int p = i; p <= q; ++p) a = cadd(a, cmul(R[i][p], old[p][q]));
+        Rtc[i * S + q] = a;
+      }
+    }
+}
+
+// C1 += C2 over rows 0..j of every right-hand side (the two Gram-Schmidt
+// passes' coefficients, summed once per block of iterations)
+__global__ void csum_kernel(double2* __restrict__ C1, const double2* __restrict__ C2, int64_t cst, int S, int64_t j,
+                            GmresState st) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+  if (!st.active[c] || e >= (j + 1) * S) return;
+  C1[c * cst * S + e] = cadd(C1[c * cst * S + e], C2[c * cst * S + e]);
+}
+
+// T_new^{-1} of one right-hand side into LDS (thread 0): T_new's column 0
+// is e_0 and its column q >= 1 is [C[j][q-1]; R[0..q-1][q-1]].
+template <int S>
+__device__ void tnew_inverse(const double2 (&Rs)[S][S], const double2 (&cj)[S], double2 (&Tinv)[S][S]) {
+  double2 Tn[S][S];
+  for (int r = 0; r < S; ++r)
+    for (int q = 0; q < S; ++q)
+      Tn[r][q] = q == 0 ? make_double2(r == 0 ? 1.0 : 0.0, 0.0)
+                        : (r == 0 ? cj[q - 1] : (r - 1 <= q - 1 ? Rs[r - 1][q - 1] : make_double2(0, 0)));
+  for (int i = S - 1; i >= 0; --i) {
+    const double2 d = Tn[i][i];
+    const double dd = d.x * d.x + d.y * d.y;
+    Tinv[i][i] = make_double2(d.x / dd, -d.y / dd);
+    for (int q = i + 1; q < S; ++q) {
+      double2 a = make_double2(0, 0);
+      for (int p = i; p < q; ++p) a = cadd(a, cmul(Tinv[i][p], Tn[p][q]));
+      const double2 e = Tn[q][q];
+      const double ee = e.x * e.x + e.y * e.y;
+      const double2 v = cmul(a, make_double2(e.x / ee, -e.y / ee));
+      Tinv[i][q] = make_double2(-v.x, -v.y);
+    }
+    for (int q = 0; q < i; ++q) Tinv[i][q] = make_double2(0, 0);
+  }
+}
+
+// Rows r0..r0+63 of the Hessenberg columns j..j+S-1 of one right-hand side,
+// stored un-rotated in H (column-major, M1 rows per column):
+// (T_next - [H_old T_old; 0]) T_new^{-1}.  Four wavefronts split the sum
+// over l of H_old T_old (l = w mod 4), a lane per row, and wavefront 0
+// adds their parts and forms the rows.  C holds C1 + C2 (csum_kernel).
+template <int S>
+__global__ void __launch_bounds__(256) sstep_hcols_kernel(GmresState st, double2* __restrict__ H, int64_t M1,
+                                                          int64_t HS, const double2* __restrict__ C, int64_t cst,
+                                                          const double2* __restrict__ Rt,
+                                                          const double* __restrict__ sig,
+                                                          const double2* __restrict__ theta,
+                                                          const int32_t* __restrict__ broken, int64_t j) {
+  const int64_t c = blockIdx.y;
+  if (!st.active[c] || broken[c]) return;  // uniform over the block
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  __shared__ double2 Tinv[S][S], Rs[S][S], th[S], cj[S];
+  __shared__ double sg[S];
+  __shared__ double2 part[3][64][S];
+  const double2* Cc = C + c * cst * S;
+  if (tid < S * S) Rs[tid / S][tid % S] = Rt[c * S * S + tid];
+  if (tid < S) {
+    th[tid] = theta[c * S + tid];
+    sg[tid] = sig[c * S + tid];
+    cj[tid] = Cc[j * S + tid];
+  }
+  __syncthreads();
+  if (tid == 0) tnew_inverse<S>(Rs, cj, Tinv);
+  const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t rr = r <= j ? r : j;  // rows past j: a valid row of H_old, discarded
+  double2* Hc = H + c * HS;
+  double2 acc[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) acc[q] = make_double2(0, 0);
+  // H[r][l] = 0 for l < r - 1: the wavefronts start at the block's first such l
+  const int64_t lstart = blockIdx.x * 64 > 0 ? blockIdx.x * 64 - 1 : 0;
+#pragma unroll 4
+  for (int64_t l = lstart + wv; l < j; l += 4) {
+    const double2 hv = Hc[l * M1 + rr];
+    const double2 h = l + 1 >= r ? hv : make_double2(0, 0);
+#pragma unroll
+    for (int q = 1; q < S; ++q) acc[q] = cadd(acc[q], cmul(h, Cc[l * S + q - 1]));
+  }
+  if (wv > 0) {
+#pragma unroll
+    for (int q = 0; q < S; ++q) part[wv - 1][lane][q] = acc[q];
+  }
+  __syncthreads();
+  if (wv > 0 || r > j + S) return;
+#pragma unroll
+  for (int q = 0; q < S; ++q) acc[q] = cadd(acc[q], cadd(cadd(part[0][lane][q], part[1][lane][q]), part[2][lane][q]));
+  // t_i[r]: t_0 = e_j; t_i = [C_{i-1}; R_{i-1}]
+  auto tval = [&](int i) -> double2 {
+    if (i == 0) return make_double2(r == j ? 1.0 : 0.0, 0.0);
+    if (r <= j) return Cc[r * S + i - 1];
+    const int64_t k = r - j - 1;
+    return k <= i - 1 ? Rs[k][i - 1] : make_double2(0, 0);
+  };
+  double2 X[S];
+  double2 tprev = tval(0);
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    const double2 tn = tval(q + 1);
+    X[q] = cadd(make_double2(sg[q] * tn.x, sg[q] * tn.y), cmul(th[q], tprev));
+    if (r <= j && q >= 1) X[q] = make_double2(X[q].x - acc[q].x, X[q].y - acc[q].y);
+    tprev = tn;
+  }
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    double2 a = make_double2(0, 0);
+#pragma unroll
+    for (int p = 0; p <= q; ++p) a = cadd(a, cmul(X[p], Tinv[p][q]));
+    Hc[(j + q) * M1 + r] = r <= j + q + 1 ? a : make_double2(0, 0);
+  }
+}
+
+// The new Hessenberg columns j..j+S-1 of one right-hand side rotated into
+// R: S threads apply the earlier rotations (one column each), then thread 0
+// applies this block's rotations in order, forms each new rotation, and
+// updates g, the residual estimate and the stop test as column_kernel does.
+// A right-hand side whose Cholesky QR broke down keeps the columns before
+// this block and ends its cycle.
+template <int S>
+__global__ void __launch_bounds__(64) sstep_givens_kernel(GmresState st, const double2* __restrict__ H, int64_t M1,
+                                                          int64_t HS, const int32_t* __restrict__ broken, int64_t j,
+                                                          int64_t m, int64_t nrhs) {
+  const int64_t c = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (!st.active[c]) return;  // uniform over the block
+  if (broken[c]) {
+    if (tid == 0) st.active[c] = 0;
+    return;
+  }
+  __shared__ double2 pc[S];
+  const double2* Hc = H + c * HS;
+  double2* Rc = st.R + c * (m + 1) * m;
+  double2* cs = st.cs + c * m;
+  double2* sn = st.sn + c * m;
+  if (tid < S) {
+    const int64_t k = j + tid;
+    double2 a = Hc[k * M1];
+#pragma unroll 8
+    for (int64_t l = 0; l < j; ++l) {
+      const double2 b = Hc[k * M1 + l + 1], cl = cs[l], sl = sn[l];
+      Rc[k * (m + 1) + l] = cadd(cmul(cl, a), cmul(sl, b));
+      a = cadd(cmul(make_double2(-sl.x, sl.y), a), cmul(make_double2(cl.x, -cl.y), b));
+    }
+    pc[tid] = a;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  const double bnorm = st.bnorm[c], tgt = st.tgt[c];
+  for (int q = 0; q < S; ++q) {
+    const int64_t k = j + q;
+    double2 a = pc[q];
+    for (int64_t l = j; l < k; ++l) {
+      const double2 b = Hc[k * M1 + l + 1], cl = cs[l], sl = sn[l];
+      Rc[k * (m + 1) + l] = cadd(cmul(cl, a), cmul(sl, b));
+      a = cadd(cmul(make_double2(-sl.x, sl.y), a), cmul(make_double2(cl.x, -cl.y), b));
+    }
+    const double2 h = Hc[k * M1 + k + 1];
+    const double den = sqrt(a.x * a.x + a.y * a.y + h.x * h.x + h.y * h.y);
+    double2 cc = make_double2(1, 0), ss = make_double2(0, 0);
+    if (den > 0) {
+      cc = make_double2(a.x / den, -a.y / den);  // conj(a)/den
+      ss = make_double2(h.x / den, -h.y / den);  // conj(h)/den
+    }
+    cs[k] = cc;
+    sn[k] = ss;
+    Rc[k * (m + 1) + k] = make_double2(den, 0);
+    const double2 gj = st.g[k * nrhs + c];
+    const double2 gn = make_double2(-(ss.x * gj.x + ss.y * gj.y), -(ss.x * gj.y - ss.y * gj.x));
+    st.g[(k + 1) * nrhs + c] = gn;
+    st.g[k * nrhs + c] = cmul(cc, gj);
+    const double ra = sqrt(gn.x * gn.x + gn.y * gn.y);
+    st.res[c] = ra / bnorm;
+    st.kc[c] = (int32_t)(k + 1);
+    st.its[c] += 1;
+    if (ra <= tgt || den == 0.0 || k + 1 >= m) {
+      st.active[c] = 0;
+      return;
+    }
+  }
+}
+
+// Eigenvalues of an n x n upper Hessenberg matrix (row-major): shifted QR
+// steps with Givens rotations on the active window, Wilkinson shifts (an
+// exceptional shift every 11 steps), deflation at negligible subdiagonal
+// entries; after 300 steps on one window its diagonal is taken as it is.
+static std::vector<std::complex<double>> hessenberg_eigenvalues(std::vector<std::complex<double>> H, int n) {
+  typedef std::complex<double> cx;
+  std::vector<cx> ev;
+  int hi = n - 1, steps = 0;
+  while (hi >= 0) {
+    if (hi == 0) {
+      ev.push_back(H[0]);
+      break;
+    }
+    int lo = hi;
+    while (lo > 0 && std::abs(H[lo * n + lo - 1]) > 1e-14 * (std::abs(H[lo * n + lo]) + std::abs(H[(lo - 1) * n + lo - 1])))
+      --lo;
+    if (lo == hi) {
+      ev.push_back(H[hi * n + hi]);
+      --hi;
+      steps = 0;
+      continue;
+    }
+    if (++steps > 300) {
+      for (int k = lo; k <= hi; ++k) ev.push_back(H[k * n + k]);
+      hi = lo - 1;
+      steps = 0;
+      continue;
+    }
+    const cx a = H[(hi - 1) * n + hi - 1], b = H[(hi - 1) * n + hi], c = H[hi * n + hi - 1], d = H[hi * n + hi];
+    const cx half_tr = 0.5 * (a + d), disc = std::sqrt(half_tr * half_tr - (a * d - b * c));
+    cx mu = std::abs(half_tr + disc - d) < std::abs(half_tr - disc - d) ? half_tr + disc : half_tr - disc;
+    if (steps % 11 == 0) mu += std::abs(c);
+    for (int k = lo; k <= hi; ++k) H[k * n + k] -= mu;
+    std::vector<double> rc(n);
+    std::vector<cx> rs(n);
+    for (int k = lo; k < hi; ++k) {  // H <- G_k H (rows k, k+1)
+      const cx x = H[k * n + k], y = H[(k + 1) * n + k];
+      const double r = std::hypot(std::abs(x), std::abs(y));
+      double cc = 1;
+      cx ss = 0;
+      if (r > 0) {
+        cc = std::abs(x) / r;
+        ss = (std::abs(x) > 0 ? x / std::abs(x) : cx(1, 0)) * std::conj(y) / r;
+      }
+      rc[k] = cc;
+      rs[k] = ss;
+      for (int q = k; q <= hi; ++q) {
+        const cx u = H[k * n + q], v = H[(k + 1) * n + q];
+        H[k * n + q] = cc * u + ss * v;
+        H[(k + 1) * n + q] = -std::conj(ss) * u + cc * v;
+      }
+    }
+    for (int k = lo; k < hi; ++k) {  // H <- H G_k^H (columns k, k+1)
+      const double cc = rc[k];
+      const cx ss = rs[k];
+      for (int r = lo; r <= std::min(k + 2, hi); ++r) {
+        const cx u = H[r * n + k], v = H[r * n + k + 1];
+        H[r * n + k] = cc * u + std::conj(ss) * v;
+        H[r * n + k + 1] = -ss * u + cc * v;
+      }
+    }
+    for (int k = lo; k <= hi; ++k) H[k * n + k] += mu;
+  }
+  return ev;
+}
+
+// Leja order: the value of largest modulus first, then each time the one
+// farthest (by product of distances) from those already taken.
+static std::vector<std::complex<double>> leja_order(std::vector<std::complex<double>> v) {
+  std::vector<std::complex<double>> out;
+  while (!v.empty()) {
+    size_t best = 0;
+    double bv = -1;
+    for (size_t i = 0; i < v.size(); ++i) {
+      double p = out.empty() ? std::abs(v[i]) : 1.0;
+      for (const auto& o : out) p *= std::abs(v[i] - o);
+      if (p > bv) {
+        bv = p;
+        best = i;
+      }
+    }
+    out.push_back(v[best]);
+    v.erase(v.begin() + (int64_t)best);
+  }
+  return out;
+}
+
+// The device buffers and GEMM plans of s-step cycles of length m (a
+// multiple of S) over the basis V (slots of vstride elements).
+struct SStep {
+  int S;
+  int64_t n, nrhs, m, M1, HS, cst;
+  Scratch C1, C2, G, Rinv, Rt, sig, theta, broken, Zt;
+  std::unique_ptr<GemmPlan> tr1, tr2;  // Z R^{-1} of the two Cholesky QR passes
+  SStep(int S_, int64_t n_, int64_t nrhs_, int64_t m_, double2* V, int64_t vstride, hipStream_t s)
+      : S(S_), n(n_), nrhs(nrhs_), m(m_), M1(m_ + S_ + 1), HS((m_ + S_) * (m_ + S_ + 1)), cst(m_ + 1),
+        C1(nrhs_ * (m_ + 1) * S_ * sizeof(double2), s), C2(nrhs_ * (m_ + 1) * S_ * sizeof(double2), s),
+        G(nrhs_ * S_ * S_ * sizeof(double2), s), Rinv(nrhs_ * S_ * S_ * sizeof(double2), s),
+        Rt(nrhs_ * S_ * S_ * sizeof(double2), s), sig(nrhs_ * S_ * sizeof(double), s),
+        theta(nrhs_ * S_ * sizeof(double2), s), broken(nrhs_ * sizeof(int32_t), s),
+        Zt(nrhs_ * S_ * n_ * sizeof(double2), s) {
+    const int64_t nb = m / S;
+    std::vector<std::vector<GemmDesc>> t1(nb), t2(nb);
+    for (int64_t b = 0; b < nb; ++b) {
+      const int64_t j = b * S;
+      for (int64_t c = 0; c < nrhs; ++c) {
+        double2* Z = V + (j + 1) * vstride + c * n;  // z_1..z_S
+        double2* ri = Rinv.as<double2>() + c * S * S;
+        double2* zt = Zt.as<double2>() + c * S * n;
+        // Z R^{-1} (row storage: R^{-T} Z) into Zt, then back into the slots
+        t1[b].push_back(gemm(ri, S, OP_T, Z, vstride, OP_N, zt, n, S, n, S));
+        t2[b].push_back(gemm(ri, S, OP_T, zt, n, OP_N, Z, vstride, S, n, S));
+      }
+    }
+    tr1.reset(new GemmPlan(t1, s, false));
+    tr2.reset(new GemmPlan(t2, s, false));
+  }
+};
+
+// Shifts of every right-hand side from the Hessenberg matrix of a plain
+// cycle of length m1 (> S): the Ritz values of its leading S x S block (of
+// its first its[c] columns when fewer), in Leja order, zeros when none.
+static void sstep_shifts(SStep& ss, const GmresState& gs, int64_t m1, const std::vector<int32_t>& its, hipStream_t s) {
+  const int S = ss.S;
+  const int64_t nrhs = ss.nrhs;
+  std::vector<double2> Hh((size_t)(m1 + 1) * m1 * nrhs);
+  CBFM_HIP(hipMemcpyAsync(Hh.data(), gs.H, Hh.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+  CBFM_HIP(hipStreamSynchronize(s));
+  std::vector<double2> th((size_t)nrhs * S, make_double2(0, 0));
+  for (int64_t c = 0; c < nrhs; ++c) {
+    const int k = (int)std::min<int64_t>(S, its[c]);
+    if (k < 1) continue;
+    std::vector<std::complex<double>> Hk((size_t)k * k);
+    for (int l = 0; l < k; ++l)
+      for (int i = 0; i < k; ++i) {
+        const double2 v = Hh[((size_t)l * m1 + i) * nrhs + c];
+        Hk[(size_t)l * k + i] = (l <= i + 1 && std::isfinite(v.x) && std::isfinite(v.y)) ? std::complex<double>(v.x, v.y)
+                                                                                        : std::complex<double>(0, 0);
+      }
+    const auto ev = leja_order(hessenberg_eigenvalues(Hk, k));
+    for (int i = 0; i < S; ++i) {
+      const auto z = ev[(size_t)i % ev.size()];
+      th[(size_t)c * S + i] = make_double2(z.real(), z.imag());
+    }
+  }
+  CBFM_HIP(hipMemcpyAsync(ss.theta.p, th.data(), th.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  CBFM_HIP(hipStreamSynchronize(s));  // th is host memory of this frame
+}
+
+// One s-step cycle of length ss.m from the normalised residual in V[0]
+// (cycle_init done): blocks of S iterations, then the triangular solve and
+// x += Q y.  Returns whether some right-hand side broke down (its cycle
+// then ends at the last complete block).
+static bool run_sstep_cycle(SStep& ss, const GemmPlan& matvec, double2* V, double2* u, int64_t vstride,
+                            int64_t max_iter, int64_t& total, GmresState gs, double* part, int np, PinnedFlags& flags,
+                            double2* x, double2* H, hipStream_t s) {
+  const int S = ss.S;
+  const int64_t n = ss.n, nrhs = ss.nrhs, m = ss.m;
+  const int np256 = (int)((n + 255) / 256);
+  CBFM_HIP(hipMemsetAsync(ss.broken.p, 0, nrhs * sizeof(int32_t), s));
+  auto all_done = [&](const int32_t* a) { return std::none_of(a, a + nrhs, [](int32_t v) { return v != 0; }); };
+  int pending = 0;
+  for (int64_t b = 0; b * S < m && total + S <= max_iter; ++b) {
+    const int64_t j = b * S;
+    for (int i = 1; i <= S; ++i) {  // z_i = (A - theta_i) z_{i-1} / sigma_i into slot j + i
+      matvec.launch((size_t)(j + i - 1), s);
+      hipLaunchKernelGGL(newton_kernel, dim3((unsigned)np256, (unsigned)nrhs), dim3(256), 0, s, u, V, vstride, n, j + i,
+                         ss.theta.as<double2>(), S, i - 1, gs, part);
+      hipLaunchKernelGGL(nscale_kernel, dim3((unsigned)np256, (unsigned)nrhs), dim3(256), 0, s, V, vstride, n, j + i,
+                         part, np256, ss.sig.as<double>(), S, i - 1, gs);
+    }
+    // two block Gram-Schmidt passes against q_0..q_j, then Cholesky QR twice
+    double2* Z = V + (j + 1) * vstride;
+    double2* Zt = ss.Zt.as<double2>();
+    const int64_t runs = (j + 1 + 3) / 4;
+    const int npu = (int)((n + 127) / 128);
+    const double vb = 16.0 * (double)(j + 1) * (double)nrhs * (double)n;  // bytes of q_0..q_j
+    for (int pass = 0; pass < 2; ++pass) {
+      double2* Cp = pass == 0 ? ss.C1.as<double2>() : ss.C2.as<double2>();
+      {
+        TimedLaunch tl(T_GMRES_DOTS, s, vb + 16.0 * S * (double)nrhs * (double)n);
+        if (S == 4)
+          hipLaunchKernelGGL(block_dots_kernel<4>, dim3((unsigned)(runs * nrhs)), dim3(256), 0, s, V, vstride, n, Z,
+                             vstride, n, n, j + 1, Cp, ss.cst * S, gs);
+        else
+          hipLaunchKernelGGL(block_dots_kernel<8>, dim3((unsigned)(runs * nrhs)), dim3(256), 0, s, V, vstride, n, Z,
+                             vstride, n, n, j + 1, Cp, ss.cst * S, gs);
+      }
+      {
+        TimedLaunch tl(T_GMRES_UPDATE, s, vb + 32.0 * S * (double)nrhs * (double)n);
+        if (S == 4)
+          hipLaunchKernelGGL(block_update_kernel<4>, dim3((unsigned)(npu * nrhs)), dim3(512), 0, s, V, vstride, Z, n,
+                             j + 1, Cp, ss.cst, npu, gs);
+        else
+          hipLaunchKernelGGL(block_update_kernel<8>, dim3((unsigned)(npu * nrhs)), dim3(512), 0, s, V, vstride, Z, n,
+                             j + 1, Cp, ss.cst, npu, gs);
+      }
+    }
+    const unsigned gr = (unsigned)(((S + 3) / 4) * nrhs);
+    if (S == 4)
+      hipLaunchKernelGGL(block_dots_kernel<4>, dim3(gr), dim3(256), 0, s, Z, vstride, n, Z, vstride, n, n,
+                         (int64_t)S, ss.G.as<double2>(), (int64_t)S * S, gs);
+    else
+      hipLaunchKernelGGL(block_dots_kernel<8>, dim3(gr), dim3(256), 0, s, Z, vstride, n, Z, vstride, n, n,
+                         (int64_t)S, ss.G.as<double2>(), (int64_t)S * S, gs);
+    if (S == 4)
+      hipLaunchKernelGGL(chol_kernel<4>, dim3((unsigned)nrhs), dim3(64), 0, s, ss.G.as<double2>(),
+                         ss.Rinv.as<double2>(), ss.Rt.as<double2>(), 1, gs, ss.broken.as<int32_t>());
+    else
+      hipLaunchKernelGGL(chol_kernel<8>, dim3((unsigned)nrhs), dim3(64), 0, s, ss.G.as<double2>(),
+                         ss.Rinv.as<double2>(), ss.Rt.as<double2>(), 1, gs, ss.broken.as<int32_t>());
+    ss.tr1->launch((size_t)b, s);
+    if (S == 4)
+      hipLaunchKernelGGL(block_dots_kernel<4>, dim3(gr), dim3(256), 0, s, Zt, n, (int64_t)S * n, Zt, n,
+                         (int64_t)S * n, n, (int64_t)S, ss.G.as<double2>(), (int64_t)S * S, gs);
+    else
+      hipLaunchKernelGGL(block_dots_kernel<8>, dim3(gr), dim3(256), 0, s, Zt, n, (int64_t)S * n, Zt, n,
+                         (int64_t)S * n, n, (int64_t)S, ss.G.as<double2>(), (int64_t)S * S, gs);
+    if (S == 4)
+      hipLaunchKernelGGL(chol_kernel<4>, dim3((unsigned)nrhs), dim3(64), 0, s, ss.G.as<double2>(),
+                         ss.Rinv.as<double2>(), ss.Rt.as<double2>(), 0, gs, ss.broken.as<int32_t>());
+    else
+      hipLaunchKernelGGL(chol_kernel<8>, dim3((unsigned)nrhs), dim3(64), 0, s, ss.G.as<double2>(),
+                         ss.Rinv.as<double2>(), ss.Rt.as<double2>(), 0, gs, ss.broken.as<int32_t>());
+    ss.tr2->launch((size_t)b, s);
+    const unsigned nrb = (unsigned)((j + S + 1 + 63) / 64);
+    hipLaunchKernelGGL(csum_kernel, dim3((unsigned)(((j + 1) * S + 255) / 256), (unsigned)nrhs), dim3(256), 0, s,
+                       ss.C1.as<double2>(), ss.C2.as<double2>(), ss.cst, S, j, gs);
+    if (S == 4) {
+      hipLaunchKernelGGL(sstep_hcols_kernel<4>, dim3(nrb, (unsigned)nrhs), dim3(256), 0, s, gs, H, ss.M1, ss.HS,
+                         ss.C1.as<double2>(), ss.cst, ss.Rt.as<double2>(), ss.sig.as<double>(), ss.theta.as<double2>(),
+                         ss.broken.as<int32_t>(), j);
+      hipLaunchKernelGGL(sstep_givens_kernel<4>, dim3((unsigned)nrhs), dim3(64), 0, s, gs, H, ss.M1, ss.HS,
+                         ss.broken.as<int32_t>(), j, m, nrhs);
+    } else {
+      hipLaunchKernelGGL(sstep_hcols_kernel<8>, dim3(nrb, (unsigned)nrhs), dim3(256), 0, s, gs, H, ss.M1, ss.HS,
+                         ss.C1.as<double2>(), ss.cst, ss.Rt.as<double2>(), ss.sig.as<double>(), ss.theta.as<double2>(),
+                         ss.broken.as<int32_t>(), j);
+      hipLaunchKernelGGL(sstep_givens_kernel<8>, dim3((unsigned)nrhs), dim3(64), 0, s, gs, H, ss.M1, ss.HS,
+                         ss.broken.as<int32_t>(), j, m, nrhs);
+    }
+    CBFM_HIP(hipGetLastError());
+    total += S;
+    if (pending > 0 && all_done(flags.wait())) break;
+    flags.post(gs.active, s);
+    ++pending;
+  }
+  hipLaunchKernelGGL(backsolve_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, gs, m, nrhs);
+  hipLaunchKernelGGL(x_update_kernel<double2>, dim3((unsigned)((int64_t)np * nrhs)), dim3(512), 0, s, gs, V, vstride,
+                     x, n, nrhs, np);
+  CBFM_HIP(hipGetLastError());
+  std::vector<int32_t> br(nrhs);
+  CBFM_HIP(hipMemcpyAsync(br.data(), ss.broken.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  CBFM_HIP(hipStreamSynchronize(s));
+  return std::any_of(br.begin(), br.end(), [](int32_t v) { return v != 0; });
+}
+
 // r = A x in double for row-stored vectors x (nrhs x n), A float (lda):
 // the matrix-core product with float operands, double accumulation output.
 static void apply_op32(const float2* A, int64_t lda, int64_t n, int64_t nrhs, const double2* x, double2* r,
@@ -1160,6 +1841,9 @@ GmresResult gmres_run(KrylovOp& op, int64_t n, int64_t nrhs, const double2* b, d
   // compressed basis: double arithmetic, the basis stored in float
   const bool b32 = p.basis32 && !f32;
   CBFM_REQUIRE(!b32 || A64 != nullptr, CBFM_E_ARG, "a float-stored basis needs a dense double operator");
+  const int S = p.sstep;
+  CBFM_REQUIRE(S == 0 || ((S == 4 || S == 8) && A64 != nullptr && !f32 && !b32 && !p.graph && op.xbasis() == nullptr),
+               CBFM_E_ARG, "s-step cycles take blocks of 4 or 8 with a dense double operator, a double basis, no graphs");
   CBFM_REQUIRE(p.tol > 0 && p.max_iter >= 1 && p.restart >= 1, CBFM_E_ARG, "bad solver parameters");
   const int64_t mres = std::min<int64_t>(p.restart, std::max<int64_t>(p.max_iter, 1));
   // The plain form keeps the Krylov basis in double; the mixed form keeps it
@@ -1177,7 +1861,9 @@ GmresResult gmres_run(KrylovOp& op, int64_t n, int64_t nrhs, const double2* b, d
   Scratch A32own(f32 && A32in == nullptr ? n * n * sizeof(float2) : 0, s);
   const int np = (int)((n + 127) / 128);  // partial norm sums per vector (128-row blocks)
   const size_t hbytes = (size_t)nrhs * (mres + 1) * mres * sizeof(double2), cbytes = (size_t)nrhs * (mres + 1) * sizeof(double2);
-  Scratch Rs(hbytes, s), Hs(hbytes, s), csb(nrhs * mres * sizeof(double2), s), snb(nrhs * mres * sizeof(double2), s),
+  const int64_t ms = S > 0 ? mres / S * S : 0;  // s-step cycle length
+  const size_t hsbytes = S > 0 ? (size_t)nrhs * (ms + S) * (ms + S + 1) * sizeof(double2) : 0;
+  Scratch Rs(hbytes, s), Hs(std::max(hbytes, hsbytes), s), csb(nrhs * mres * sizeof(double2), s), snb(nrhs * mres * sizeof(double2), s),
       gb(cbytes, s), d1b(cbytes, s), d2b(cbytes, s), d1t(cbytes, s), d2t(cbytes, s), hcb(cbytes, s),
       abb(nrhs * sizeof(double2), s), dbl(5 * nrhs * sizeof(double), s), ints(3 * nrhs * sizeof(int32_t), s),
       part(nrhs * np * sizeof(double), s);
@@ -1273,6 +1959,10 @@ GmresResult gmres_run(KrylovOp& op, int64_t n, int64_t nrhs, const double2* b, d
     hipLaunchKernelGGL(sub_from_kernel, dim3((unsigned)((nrhs * n + 255) / 256)), dim3(256), 0, s, b, r, nrhs * n);
   };
   const OpMV opmv{&op};
+  // s-step: a first plain cycle of S + 1 iterations gives the shifts; then
+  // s-step cycles, and plain ones for good after a breakdown
+  bool sstep_on = S > 0 && ms >= S, shifts_ready = false;
+  std::unique_ptr<SStep> sst;
   for (;;) {
     // r = b - A x  (x = 0 on the first cycle)
     double2* r = f32 ? r64.as<double2>() : u.as<double2>();
@@ -1295,7 +1985,24 @@ GmresResult gmres_run(KrylovOp& op, int64_t n, int64_t nrhs, const double2* b, d
       run_cycle(matvec, dyn.get(), dyn ? dyn->desc(0) : nullptr, jdev.as<int64_t>(), V.as<float2>(), u.as<double2>(),
                 vstride, n, nrhs, mres, p.max_iter, total, gs, part.as<double>(), np, flags, x, s, (const float2*)nullptr,
                 qd.as<double2>());
-    else if (dense)
+    else if (sstep_on && !shifts_ready) {
+      const int64_t m1 = std::min<int64_t>(S + 1, mres);
+      GmresState g1 = gs;
+      g1.ms = m1 + 1;
+      CBFM_HIP(hipMemsetAsync(gs.H, 0, (size_t)nrhs * (m1 + 1) * m1 * sizeof(double2), s));
+      run_cycle(matvec, (const GemmPlan*)nullptr, nullptr, jdev.as<int64_t>(), V.as<double2>(), u.as<double2>(),
+                vstride, n, nrhs, m1, p.max_iter, total, g1, part.as<double>(), np, flags, x, s);
+      std::vector<int32_t> its1(nrhs);
+      CBFM_HIP(hipMemcpyAsync(its1.data(), gs.its, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      CBFM_HIP(hipStreamSynchronize(s));
+      sst.reset(new SStep(S, n, nrhs, ms, V.as<double2>(), vstride, s));
+      sstep_shifts(*sst, g1, m1, its1, s);
+      shifts_ready = true;
+    } else if (sstep_on) {
+      if (run_sstep_cycle(*sst, matvec, V.as<double2>(), u.as<double2>(), vstride, p.max_iter, total, gs,
+                          part.as<double>(), np, flags, x, gs.H, s))
+        sstep_on = false;
+    } else if (dense)
       run_cycle(matvec, dyn.get(), dyn ? dyn->desc(0) : nullptr, jdev.as<int64_t>(), V.as<double2>(),
                 u.as<double2>(), vstride, n, nrhs, mres, p.max_iter, total, gs, part.as<double>(), np, flags, x, s);
     else
@@ -1473,6 +2180,9 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
                  "the inexact CMP runs double Krylov cycles with a double basis and without graphs");
     CBFM_REQUIRE(prm->inner_fp32 == 0 || prm->basis_fp32 == 0, CBFM_E_ARG,
                  "inner_fp32 and basis_fp32 are two different forms");
+    CBFM_REQUIRE(prm->sstep == 0 || ((prm->sstep == 4 || prm->sstep == 8) && !flexible && prm->inner_fp32 == 0 &&
+                                     prm->basis_fp32 == 0 && prm->use_graph == 0),
+                 CBFM_E_ARG, "sstep is 0, 4 or 8, with double cycles, the exact CMP and no graphs");
     CBFM_REQUIRE(prm->inner_tol >= 0 && prm->inner_tol < 1, CBFM_E_ARG, "inner_tol outside [0, 1)");
     CBFM_REQUIRE(!flexible || (prm->cmp_inner_tol >= 0 && prm->cmp_inner_tol < 1), CBFM_E_ARG,
                  "cmp_inner_tol outside [0, 1)");
@@ -1531,6 +2241,7 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
     sp.inner_tol = prm->inner_tol;
     sp.graph = prm->use_graph != 0;
     sp.basis32 = prm->basis_fp32 != 0;
+    sp.sstep = prm->sstep;
     Scratch x(nrhs * n * sizeof(double2), s);
     DenseOp dop(Aop, lda, nullptr, 0);
     FlexCmpOp fop(Zr, ldz, c, prm->cmp_inner_tol > 0 ? prm->cmp_inner_tol : 1e-5, n);

@@ -436,6 +436,47 @@ def test_compressed_basis_solve(torch_cuda):
         cbfm.solve(mesh, med, cbf, Zr, inc, basis_fp32=True, cmp_mode=cbfm.CMP_INNER_GMRES, raise_noconv=True)
 
 
+def test_sstep_solve(torch_cuda):
+    """s-step cycles (blocks of 4 or 8 iterations: Newton basis, two block
+    Gram-Schmidt and two Cholesky QR passes, Hessenberg columns rebuilt)
+    solve the oracle's reduced system like plain cycles: at tol 1e-12 the
+    currents match LU (batch and one right-hand side); at tol 1e-6 the true
+    residual meets the tolerance, with blocks of 4 in about the plain
+    iteration count (the first plain cycle of S + 1 iterations that gives
+    the shifts included).  Blocks of 8 break down on this operator (a
+    Cholesky pivot vanishes mid-solve; the solve then goes on in plain
+    cycles), so only their result is checked."""
+    from oracle import excitation
+    O = _oracle_cbf("cyl_small")
+    P = O["P"]
+    w, m = P["w"], P["m"]
+    cbfm, mesh, med, cbf = _gpu_handles(w, O)
+    n = cbf.n_cbf
+    Zr = torch_cuda.zeros((n, n), dtype=torch_cuda.complex128, device="cuda")
+    cbfm.project(mesh, med, cbf, Zr, cbfm.FP64)
+    inc = w.inc
+    vr = O["CJM"].conj().T @ excitation.rhs(m, inc, w.k0, w.eta0)
+    jref = O["CMJ"] @ np.linalg.solve(O["Zr"], vr)
+    plain = cbfm.solve(mesh, med, cbf, Zr, inc, tol=1e-6, max_iter=6 * n, restart=n + 10)
+    for S in (4, 8):
+        for sel in (slice(None), slice(0, 1)):
+            ii = np.ascontiguousarray(inc[sel])
+            jt = torch_cuda.zeros((len(ii), 2 * m.ne), dtype=torch_cuda.complex128, device="cuda")
+            out = cbfm.solve(mesh, med, cbf, Zr, ii, tol=1e-12, max_iter=6 * n, restart=n + 10, j_out=jt, sstep=S)
+            e = _rel(jt.cpu().numpy().T, jref[:, sel])
+            print("s-step", S, "right-hand sides", len(ii), out["iters"], out["relres"], e)
+            assert out["status"] == "OK" and np.all(out["relres"] <= 1e-12) and e < 1e-9, (S, len(ii))
+        b = cbfm.solve(mesh, med, cbf, Zr, inc, tol=1e-6, max_iter=6 * n, restart=n + 10, sstep=S)
+        print("tol 1e-6 iterations plain", plain["iters"], "s-step", S, b["iters"], b["relres"])
+        assert b["status"] == "OK" and np.all(b["relres"] <= 1e-6)
+        if S == 4:
+            assert np.all(b["iters"] <= plain["iters"] + 2 * S + 2)
+    with pytest.raises(RuntimeError):
+        cbfm.solve(mesh, med, cbf, Zr, inc, sstep=5, raise_noconv=True)
+    with pytest.raises(RuntimeError):
+        cbfm.solve(mesh, med, cbf, Zr, inc, sstep=8, inner_fp32=True, raise_noconv=True)
+
+
 def test_every_gemm_launch_shape_solves_alike(torch_cuda, monkeypatch):
     """Every launch shape of the complex GEMM (CBFM_GEMM_SHAPE forces it on
     each product it applies to; the tuner may pick any of them for the
