@@ -12,7 +12,8 @@ timed region.
 Workload (default): dielectric cylinder r 1, h 6 wavelengths, eps_r 3,
 19,968 triangles (29,952 RWGs, 59,904 unknowns), 96 cells, 32 monostatic
 incidences, CBFs from the 144 Table-I plane waves, delta_SVD 1e-3, regular
-pairs filled in FP32 (near pairs, CBF build, projection and solve in FP64).
+pairs filled in FP32 (near pairs, CBF build, projection and solve in FP64),
+GMRES in s-step cycles of blocks of 8 iterations (--sstep 0: plain cycles).
 The FP64 form of the same step runs beside it, then the precision forms,
 the IPCBF leg (the paper's cylinder conditions), the batching and serving
 legs and the CPU oracle baseline (see --help for the switches).
@@ -83,6 +84,12 @@ FAMILY_SOURCES = {
     "gemm": ("zgemm_batched_kernel", "paper_2111_11058_amd/csrc/gemm.hip"),
     "gmres_dots": ("dots2_kernel", "paper_2111_11058_amd/csrc/solve.hip"),
     "gmres_update": ("dcgs_update_kernel", "paper_2111_11058_amd/csrc/solve.hip"),
+    # s-step cycles (blocks of 8): the block Gram-Schmidt passes
+    "gmres_block_dots": ("block_dots_kernel<8, false>", "paper_2111_11058_amd/csrc/solve.hip"),
+    "gmres_block_update": ("block_update_kernel<8>", "paper_2111_11058_amd/csrc/solve.hip"),
+    # the GMRES matrix-vector product: the launch shape of the complex GEMM
+    # with the most dispatches
+    "gmres_matvec": ("zgemm_batched_kernel", "paper_2111_11058_amd/csrc/gemm.hip"),
 }
 
 
@@ -135,11 +142,18 @@ def write_traffic(workload_name, fetch_dir, write_dir, cfetch_dir, cwrite_dir, c
     import csv
     from collections import defaultdict
 
-    def per_dispatch(d, sub):
-        acc = defaultdict(float)
+    def per_dispatch(d, sub, most_frequent_grid=False):
+        acc, grid = defaultdict(float), {}
         for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
             if sub in r["Kernel_Name"]:
                 acc[r["Dispatch_Id"]] += float(r["Counter_Value"])
+                grid[r["Dispatch_Id"]] = (r["Kernel_Name"], r.get("Grid_Size", ""))
+        if most_frequent_grid and grid:
+            counts = defaultdict(int)
+            for g in grid.values():
+                counts[g] += 1
+            top = max(counts, key=counts.get)
+            return [v for k, v in acc.items() if grid[k] == top]
         return list(acc.values())
 
     gib_kib = float(1 << 20)
@@ -150,7 +164,8 @@ def write_traffic(workload_name, fetch_dir, write_dir, cfetch_dir, cwrite_dir, c
              f"# calibration: a 1 GiB device copy reads {1 / fs:.4f} GiB by FETCH_SIZE and writes "
              f"{1 / ws:.4f} GiB by WRITE_SIZE; scales fetch x{fs:.4f}, write x{ws:.4f}"]
     for fam, (sub, src) in FAMILY_SOURCES.items():
-        f, w = per_dispatch(fetch_dir, sub), per_dispatch(write_dir, sub)
+        top = fam == "gmres_matvec"
+        f, w = per_dispatch(fetch_dir, sub, top), per_dispatch(write_dir, sub, top)
         if not f or not w:
             continue
         sha = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
@@ -289,19 +304,29 @@ def write_counters(workload_name, stats_dir, dirs, cmd):
     print("\n".join(lines))
 
 
-def read_families(cbfm, traffic, phase):
+# kernels and traffic entries of the solve's families under s-step cycles
+SSTEP_KERNELS = {"gmres_dots": ("block_dots_kernel", "gmres_block_dots"),
+                 "gmres_update": ("block_update_kernel", "gmres_block_update")}
+
+
+def read_families(cbfm, traffic, phase, sstep=0):
     """Achieved rate of every timed family since the last timer_enable."""
     rows = {}
     for fam, (kernel, bound, peak, unit, scale) in FAMILIES.items():
         n, ms, work = cbfm.timer_read(fam, with_work=True)
         if n == 0 or ms <= 0:
             continue
+        tkey = fam
+        if phase == "solve" and fam == "gemm":
+            tkey = "gmres_matvec"
+        if sstep and fam in SSTEP_KERNELS:
+            kernel, tkey = SSTEP_KERNELS[fam]
         per_launch = work * scale / n
         avg_s = ms * 1e-3 / n
         ach = per_launch / avg_s
         div = 1e12 if unit == "TFLOP/s" else 1e9
         row = {"bound": bound, "achieved": ach / div, "peak": peak / div, "unit": unit, "frac": ach / peak,
-               "traffic": traffic.get(fam), "kernel": kernel, "phase": phase, "launches": n,
+               "traffic": traffic.get(tkey), "kernel": kernel, "phase": phase, "launches": n,
                "avg_launch_ms": ms / n, "total_ms": ms, "work_per_launch": per_launch}
         if fam == "fill_regular_f32":
             row["frac_of_unpacked_fp32"] = ach / PEAK_FP32_VALU_UNPACKED
@@ -309,7 +334,7 @@ def read_families(cbfm, traffic, phase):
     return rows
 
 
-def rooflines(cbfm, run_phases, traffic, prefix=""):
+def rooflines(cbfm, run_phases, traffic, prefix="", sstep=0):
     """One step with the timers on, the projection and the solve timed
     apart (run_phases calls project() and solve() in turn, each given a
     callback that switches the timers on for that phase)."""
@@ -323,7 +348,7 @@ def rooflines(cbfm, run_phases, traffic, prefix=""):
         cbfm.timer_enable(list(cbfm.TIMERS))
 
         def done():
-            for fam, row in read_families(cbfm, traffic, phase).items():
+            for fam, row in read_families(cbfm, traffic, phase, sstep).items():
                 if fam in names[phase]:
                     rows[prefix + names[phase][fam]] = row
             cbfm.timer_enable(None)
@@ -714,8 +739,9 @@ def main():
     ap.add_argument("--workload", default="cylinder19968", choices=WORKLOADS)
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="fill precision of the timed step (default: fp32 for cylinder19968, else fp64)")
-    ap.add_argument("--sstep", type=int, default=0, choices=[0, 4, 8],
-                    help="time the main step with s-step GMRES cycles of blocks of this many iterations")
+    ap.add_argument("--sstep", type=int, default=8, choices=[0, 4, 8],
+                    help="GMRES of the main step and the FP64 leg: s-step cycles of blocks of this many "
+                         "iterations, or 0 for plain cycles (DCGS2)")
     ap.add_argument("--basis-fp32", action="store_true",
                     help="time the compressed-basis form (double arithmetic, Krylov basis stored in float) as the "
                          "main step")
@@ -836,7 +862,8 @@ def main():
             done()
         return cb, out, t1 - t0, t3 - t2
 
-    B32, SST = args.basis_fp32, args.sstep
+    B32 = args.basis_fp32
+    SST = 0 if B32 else args.sstep  # (the compressed basis runs plain cycles)
     for i in range(args.warmup):
         log(f"warmup {i}")
         step(PREC, basis_fp32=B32, sstep=SST)
@@ -853,7 +880,8 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     nt = w.nt
-    roof, roofs = rooflines(cbfm, lambda timed: step(PREC, timed=timed, basis_fp32=B32, sstep=SST), traffic)
+    roof, roofs = rooflines(cbfm, lambda timed: step(PREC, timed=timed, basis_fp32=B32, sstep=SST), traffic,
+                            sstep=SST)
     nrhs = len(w.inc)
     lat = np.array(solve_t)
     result = {
@@ -889,17 +917,17 @@ def main():
     if PREC != cbfm.FP64 or args.fp64_steps:
         # the plain FP64 form of the same step beside the timed one
         k = args.fp64_steps or max(1, args.steps // 2)
-        step(cbfm.FP64)
+        step(cbfm.FP64, sstep=SST)
         tp_l, ts_l = [], []
         torch.cuda.synchronize()
         tt = time.perf_counter()
         for _ in range(k):
-            _, o64, tp, ts = step(cbfm.FP64)
+            _, o64, tp, ts = step(cbfm.FP64, sstep=SST)
             tp_l.append(tp)
             ts_l.append(ts)
         torch.cuda.synchronize()
         tt = time.perf_counter() - tt
-        _, r64 = rooflines(cbfm, lambda timed: step(cbfm.FP64, timed=timed), traffic)
+        _, r64 = rooflines(cbfm, lambda timed: step(cbfm.FP64, timed=timed, sstep=SST), traffic, sstep=SST)
         rcs_ref = o64["rcs"]
         result["fp64_leg"] = {"steps": k, "value": nt * nt * k / tt, "ms_per_step": tt / k * 1e3,
                               "fill_projection_pair_evals_per_s": nt * nt / float(np.median(tp_l)),

@@ -1192,8 +1192,9 @@ __global__ void __launch_bounds__(256) nscale_kernel(double2* __restrict__ V, in
 // One block of four wavefronts per right-hand side and run of four left
 // vectors; the threads take every 256th row with the S right values of the
 // row loaded once for the four left vectors, and the wavefronts are summed
-// through LDS in a fixed order.
-template <int S>
+// through LDS in a fixed order.  (GRAM: the same for a block's own Gram
+// matrix, a launch of its own name for the profiles.)
+template <int S, bool GRAM>
 __global__ void __launch_bounds__(256) block_dots_kernel(const double2* __restrict__ L, int64_t ls, int64_t lc,
                                                          const double2* __restrict__ R, int64_t rs, int64_t rc,
                                                          int64_t n, int64_t nv, double2* __restrict__ out, int64_t ost,
@@ -1737,10 +1738,10 @@ static bool run_sstep_cycle(SStep& ss, const GemmPlan& matvec, double2* V, doubl
       {
         TimedLaunch tl(T_GMRES_DOTS, s, vb + 16.0 * S * (double)nrhs * (double)n);
         if (S == 4)
-          hipLaunchKernelGGL(block_dots_kernel<4>, dim3((unsigned)(runs * nrhs)), dim3(256), 0, s, V, vstride, n, Z,
+          hipLaunchKernelGGL((block_dots_kernel<4, false>), dim3((unsigned)(runs * nrhs)), dim3(256), 0, s, V, vstride, n, Z,
                              vstride, n, n, j + 1, Cp, ss.cst * S, gs);
         else
-          hipLaunchKernelGGL(block_dots_kernel<8>, dim3((unsigned)(runs * nrhs)), dim3(256), 0, s, V, vstride, n, Z,
+          hipLaunchKernelGGL((block_dots_kernel<8, false>), dim3((unsigned)(runs * nrhs)), dim3(256), 0, s, V, vstride, n, Z,
                              vstride, n, n, j + 1, Cp, ss.cst * S, gs);
       }
       {
@@ -1755,10 +1756,10 @@ static bool run_sstep_cycle(SStep& ss, const GemmPlan& matvec, double2* V, doubl
     }
     const unsigned gr = (unsigned)(((S + 3) / 4) * nrhs);
     if (S == 4)
-      hipLaunchKernelGGL(block_dots_kernel<4>, dim3(gr), dim3(256), 0, s, Z, vstride, n, Z, vstride, n, n,
+      hipLaunchKernelGGL((block_dots_kernel<4, true>), dim3(gr), dim3(256), 0, s, Z, vstride, n, Z, vstride, n, n,
                          (int64_t)S, ss.G.as<double2>(), (int64_t)S * S, gs);
     else
-      hipLaunchKernelGGL(block_dots_kernel<8>, dim3(gr), dim3(256), 0, s, Z, vstride, n, Z, vstride, n, n,
+      hipLaunchKernelGGL((block_dots_kernel<8, true>), dim3(gr), dim3(256), 0, s, Z, vstride, n, Z, vstride, n, n,
                          (int64_t)S, ss.G.as<double2>(), (int64_t)S * S, gs);
     if (S == 4)
       hipLaunchKernelGGL(chol_kernel<4>, dim3((unsigned)nrhs), dim3(64), 0, s, ss.G.as<double2>(),
@@ -1768,10 +1769,10 @@ static bool run_sstep_cycle(SStep& ss, const GemmPlan& matvec, double2* V, doubl
                          ss.Rinv.as<double2>(), ss.Rt.as<double2>(), 1, gs, ss.broken.as<int32_t>());
     ss.tr1->launch((size_t)b, s);
     if (S == 4)
-      hipLaunchKernelGGL(block_dots_kernel<4>, dim3(gr), dim3(256), 0, s, Zt, n, (int64_t)S * n, Zt, n,
+      hipLaunchKernelGGL((block_dots_kernel<4, true>), dim3(gr), dim3(256), 0, s, Zt, n, (int64_t)S * n, Zt, n,
                          (int64_t)S * n, n, (int64_t)S, ss.G.as<double2>(), (int64_t)S * S, gs);
     else
-      hipLaunchKernelGGL(block_dots_kernel<8>, dim3(gr), dim3(256), 0, s, Zt, n, (int64_t)S * n, Zt, n,
+      hipLaunchKernelGGL((block_dots_kernel<8, true>), dim3(gr), dim3(256), 0, s, Zt, n, (int64_t)S * n, Zt, n,
                          (int64_t)S * n, n, (int64_t)S, ss.G.as<double2>(), (int64_t)S * S, gs);
     if (S == 4)
       hipLaunchKernelGGL(chol_kernel<4>, dim3((unsigned)nrhs), dim3(64), 0, s, ss.G.as<double2>(),
