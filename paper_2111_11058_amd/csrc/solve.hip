@@ -1319,63 +1319,104 @@ __global__ void __launch_bounds__(512) block_update_kernel(const double2* __rest
 // Cholesky factor of one right-hand side's Gram matrix G = R^H R (R upper,
 // S x S), its inverse, and Rt = R (first pass) or R Rt; a pivot not above
 // 1e-28 of G's largest diagonal entry marks a breakdown (broken[c] = 1).
+// G is staged in LDS, one thread factors and inverts it there, and the
+// results are written by S x S threads.
 template <int S>
 __global__ void __launch_bounds__(64) chol_kernel(const double2* __restrict__ G, double2* __restrict__ Rinv,
                                                   double2* __restrict__ Rt, int first, GmresState st,
                                                   int32_t* __restrict__ broken) {
   const int64_t c = blockIdx.x;
-  if (!st.active[c] || threadIdx.x != 0) return;
-  __shared__ double2 R[S][S], Ri[S][S], old[S][S];
-  const double2* Gc = G + c * S * S;
-  double gmax = 0;
-  for (int i = 0; i < S; ++i) gmax = fmax(gmax, Gc[i * S + i].x);
-  bool bad = !(gmax > 0);
-  for (int i = 0; i < S && !bad; ++i) {
-    double d = Gc[i * S + i].x;
-    for (int p = 0; p < i; ++p) d -= R[p][i].x * R[p][i].x + R[p][i].y * R[p][i].y;
-    if (!(d > 1e-28 * gmax)) {
-      bad = true;
-      break;
+  const int tid = threadIdx.x;
+  if (!st.active[c]) return;  // uniform over the block
+  __shared__ double2 Gs[S][S], R[S][S], Ri[S][S];
+  __shared__ int bad;
+  for (int e = tid; e < S * S; e += 64) Gs[e / S][e % S] = G[c * S * S + e];
+  __syncthreads();
+  if (tid == 0) {
+    double gmax = 0;
+    for (int i = 0; i < S; ++i) gmax = fmax(gmax, Gs[i][i].x);
+    int b = !(gmax > 0);
+    for (int i = 0; i < S && !b; ++i) {
+      double d = Gs[i][i].x;
+      for (int p = 0; p < i; ++p) d -= R[p][i].x * R[p][i].x + R[p][i].y * R[p][i].y;
+      if (!(d > 1e-28 * gmax)) {
+        b = 1;
+        break;
+      }
+      const double rii = sqrt(d);
+      R[i][i] = make_double2(rii, 0);
+      for (int q = i + 1; q < S; ++q) {
+        double2 a = Gs[i][q];
+        for (int p = 0; p < i; ++p) a = make_double2(a.x - (R[p][i].x * R[p][q].x + R[p][i].y * R[p][q].y),
+                                                     a.y - (R[p][i].x * R[p][q].y - R[p][i].y * R[p][q].x));
+        R[i][q] = make_double2(a.x / rii, a.y / rii);
+      }
+      for (int q = 0; q < i; ++q) R[i][q] = make_double2(0, 0);
     }
-    const double rii = sqrt(d);
-    R[i][i] = make_double2(rii, 0);
-    for (int q = i + 1; q < S; ++q) {
-      double2 a = Gc[i * S + q];
-      for (int p = 0; p < i; ++p) a = make_double2(a.x - (R[p][i].x * R[p][q].x + R[p][i].y * R[p][q].y),
-                                                   a.y - (R[p][i].x * R[p][q].y - R[p][i].y * R[p][q].x));
-      R[i][q] = make_double2(a.x / rii, a.y / rii);
+    if (!b) {
+      for (int i = S - 1; i >= 0; --i) {
+        Ri[i][i] = make_double2(1.0 / R[i][i].x, 0);
+        for (int q = i + 1; q < S; ++q) {
+          double2 a = make_double2(0, 0);
+          for (int p = i; p < q; ++p) a = cadd(a, cmul(Ri[i][p], R[p][q]));
+          Ri[i][q] = make_double2(-a.x / R[q][q].x, -a.y / R[q][q].x);
+        }
+        for (int q = 0; q < i; ++q) Ri[i][q] = make_double2(0, 0);
+      }
     }
-    for (int q = 0; q < i; ++q) R[i][q] = make_double2(0, 0);
+    bad = b;
   }
+  __syncthreads();
   if (bad) {
-    broken[c] = 1;
+    if (tid == 0) broken[c] = 1;
     return;
-  }
-  for (int i = S - 1; i >= 0; --i) {
-    Ri[i][i] = make_double2(1.0 / R[i][i].x, 0);
-    for (int q = i + 1; q < S; ++q) {
-      double2 a = make_double2(0, 0);
-      for (int p = i; p < q; ++p) a = cadd(a, cmul(Ri[i][p], R[p][q]));
-      Ri[i][q] = make_double2(-a.x / R[q][q].x, -a.y / R[q][q].x);
-    }
-    for (int q = 0; q < i; ++q) Ri[i][q] = make_double2(0, 0);
   }
   double2* Ric = Rinv + c * S * S;
   double2* Rtc = Rt + c * S * S;
-  if (!first)
-    for (int i = 0; i < S; ++i)
-      for (int q = 0; q < S; ++q) old[i][q] = Rtc[i * S + q];
-  for (int i = 0; i < S; ++i)
-    for (int q = 0; q < S; ++q) {
-      Ric[i * S + q] = Ri[i][q];
-      if (first) {
-        Rtc[i * S + q] = R[i][q];
-      } else {
-        double2 a = make_double2(0, 0);
-        for (int p = i; p <= q; ++p) a = cadd(a, cmul(R[i][p], old[p][q]));
-        Rtc[i * S + q] = a;
-      }
+  double2 nt[(S * S + 63) / 64];
+#pragma unroll
+  for (int u = 0; u < (S * S + 63) / 64; ++u) {
+    const int e = tid + 64 * u;
+    if (e >= S * S) break;
+    const int i = e / S, q = e % S;
+    Ric[e] = Ri[i][q];
+    if (first) {
+      nt[u] = R[i][q];
+    } else {
+      double2 a = make_double2(0, 0);
+      for (int p = i; p <= q; ++p) a = cadd(a, cmul(R[i][p], Rtc[p * S + q]));
+      nt[u] = a;
     }
+  }
+  __syncthreads();  // every old Rt entry read before any is replaced
+#pragma unroll
+  for (int u = 0; u < (S * S + 63) / 64; ++u) {
+    const int e = tid + 64 * u;
+    if (e < S * S) Rtc[e] = nt[u];
+  }
+}
+
+// Z <- Z R^{-1} in place (Z_i = the basis slot after q_j plus i): each
+// thread takes one row of every right-hand side's S vectors.
+template <int S>
+__global__ void __launch_bounds__(256) trmul_kernel(double2* __restrict__ Z, int64_t vstride, int64_t n,
+                                                    const double2* __restrict__ Rinv, GmresState st) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+  if (!st.active[c]) return;  // uniform over the block
+  __shared__ double2 Ri[S][S];
+  if (threadIdx.x < S * S) Ri[threadIdx.x / S][threadIdx.x % S] = Rinv[c * S * S + threadIdx.x];
+  __syncthreads();
+  if (k >= n) return;
+  double2 z[S];
+#pragma unroll
+  for (int i = 0; i < S; ++i) z[i] = Z[i * vstride + c * n + k];
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    double2 a = make_double2(0, 0);
+#pragma unroll
+    for (int p = 0; p <= i; ++p) a = cadd(a, cmul(z[p], Ri[p][i]));
+    Z[i * vstride + c * n + k] = a;
+  }
 }
 
 // C1 += C2 over rows 0..j of every right-hand side (the two Gram-Schmidt
@@ -1488,15 +1529,19 @@ __global__ void __launch_bounds__(256) sstep_hcols_kernel(GmresState st, double2
 }
 
 // The new Hessenberg columns j..j+S-1 of one right-hand side rotated into
-// R: S threads apply the earlier rotations (one column each), then thread 0
-// applies this block's rotations in order, forms each new rotation, and
-// updates g, the residual estimate and the stop test as column_kernel does.
-// A right-hand side whose Cholesky QR broke down keeps the columns before
-// this block and ends its cycle.
+// R.  The earlier rotations act on each new column as an affine recurrence
+// in the carried entry (a -> -conj(s_l) a + conj(c_l) H[l+1]), so T = 256/S
+// threads per column each compose the maps of a run of rotations, a scan
+// over the runs (in LDS) gives each run its incoming entry, and the runs are
+// replayed in parallel.  Thread 0 then applies this block's rotations in
+// order, forms each new rotation, and updates g, the residual estimate and
+// the stop test as column_kernel does.  A right-hand side whose Cholesky QR
+// broke down keeps the columns before this block and ends its cycle.
 template <int S>
-__global__ void __launch_bounds__(64) sstep_givens_kernel(GmresState st, const double2* __restrict__ H, int64_t M1,
-                                                          int64_t HS, const int32_t* __restrict__ broken, int64_t j,
-                                                          int64_t m, int64_t nrhs) {
+__global__ void __launch_bounds__(256) sstep_givens_kernel(GmresState st, const double2* __restrict__ H, int64_t M1,
+                                                           int64_t HS, const int32_t* __restrict__ broken, int64_t j,
+                                                           int64_t m, int64_t nrhs) {
+  constexpr int T = 256 / S;  // threads per column
   const int64_t c = blockIdx.x;
   const int tid = threadIdx.x;
   if (!st.active[c]) return;  // uniform over the block
@@ -1505,20 +1550,41 @@ __global__ void __launch_bounds__(64) sstep_givens_kernel(GmresState st, const d
     return;
   }
   __shared__ double2 pc[S];
+  __shared__ double2 mapa[S][T], mapb[S][T], inc[S][T];
   const double2* Hc = H + c * HS;
   double2* Rc = st.R + c * (m + 1) * m;
   double2* cs = st.cs + c * m;
   double2* sn = st.sn + c * m;
-  if (tid < S) {
-    const int64_t k = j + tid;
+  const int q = tid / T, t = tid % T;
+  const int64_t k = j + q;
+  const int64_t per = (j + T - 1) / T, l0 = std::min<int64_t>(j, t * per), l1 = std::min<int64_t>(j, l0 + per);
+  // the run's composed map a -> A a + B
+  double2 A = make_double2(1, 0), B = make_double2(0, 0);
+  for (int64_t l = l0; l < l1; ++l) {
+    const double2 cl = cs[l], sl = sn[l], b = Hc[k * M1 + l + 1];
+    const double2 al = make_double2(-sl.x, sl.y), bl = cmul(make_double2(cl.x, -cl.y), b);
+    A = cmul(al, A);
+    B = cadd(cmul(al, B), bl);
+  }
+  mapa[q][t] = A;
+  mapb[q][t] = B;
+  __syncthreads();
+  if (t == 0) {  // incoming entry of every run of this column, in run order
     double2 a = Hc[k * M1];
-#pragma unroll 8
-    for (int64_t l = 0; l < j; ++l) {
-      const double2 b = Hc[k * M1 + l + 1], cl = cs[l], sl = sn[l];
+    for (int u = 0; u < T; ++u) {
+      inc[q][u] = a;
+      a = cadd(cmul(mapa[q][u], a), mapb[q][u]);
+    }
+    pc[q] = a;
+  }
+  __syncthreads();
+  {
+    double2 a = inc[q][t];
+    for (int64_t l = l0; l < l1; ++l) {
+      const double2 cl = cs[l], sl = sn[l], b = Hc[k * M1 + l + 1];
       Rc[k * (m + 1) + l] = cadd(cmul(cl, a), cmul(sl, b));
       a = cadd(cmul(make_double2(-sl.x, sl.y), a), cmul(make_double2(cl.x, -cl.y), b));
     }
-    pc[tid] = a;
   }
   __syncthreads();
   if (tid != 0) return;
@@ -1643,36 +1709,17 @@ static std::vector<std::complex<double>> leja_order(std::vector<std::complex<dou
   return out;
 }
 
-// The device buffers and GEMM plans of s-step cycles of length m (a
-// multiple of S) over the basis V (slots of vstride elements).
+// The device buffers of s-step cycles of length m (a multiple of S).
 struct SStep {
   int S;
   int64_t n, nrhs, m, M1, HS, cst;
-  Scratch C1, C2, G, Rinv, Rt, sig, theta, broken, Zt;
-  std::unique_ptr<GemmPlan> tr1, tr2;  // Z R^{-1} of the two Cholesky QR passes
-  SStep(int S_, int64_t n_, int64_t nrhs_, int64_t m_, double2* V, int64_t vstride, hipStream_t s)
+  Scratch C1, C2, G, Rinv, Rt, sig, theta, broken;
+  SStep(int S_, int64_t n_, int64_t nrhs_, int64_t m_, hipStream_t s)
       : S(S_), n(n_), nrhs(nrhs_), m(m_), M1(m_ + S_ + 1), HS((m_ + S_) * (m_ + S_ + 1)), cst(m_ + 1),
         C1(nrhs_ * (m_ + 1) * S_ * sizeof(double2), s), C2(nrhs_ * (m_ + 1) * S_ * sizeof(double2), s),
         G(nrhs_ * S_ * S_ * sizeof(double2), s), Rinv(nrhs_ * S_ * S_ * sizeof(double2), s),
         Rt(nrhs_ * S_ * S_ * sizeof(double2), s), sig(nrhs_ * S_ * sizeof(double), s),
-        theta(nrhs_ * S_ * sizeof(double2), s), broken(nrhs_ * sizeof(int32_t), s),
-        Zt(nrhs_ * S_ * n_ * sizeof(double2), s) {
-    const int64_t nb = m / S;
-    std::vector<std::vector<GemmDesc>> t1(nb), t2(nb);
-    for (int64_t b = 0; b < nb; ++b) {
-      const int64_t j = b * S;
-      for (int64_t c = 0; c < nrhs; ++c) {
-        double2* Z = V + (j + 1) * vstride + c * n;  // z_1..z_S
-        double2* ri = Rinv.as<double2>() + c * S * S;
-        double2* zt = Zt.as<double2>() + c * S * n;
-        // Z R^{-1} (row storage: R^{-T} Z) into Zt, then back into the slots
-        t1[b].push_back(gemm(ri, S, OP_T, Z, vstride, OP_N, zt, n, S, n, S));
-        t2[b].push_back(gemm(ri, S, OP_T, zt, n, OP_N, Z, vstride, S, n, S));
-      }
-    }
-    tr1.reset(new GemmPlan(t1, s, false));
-    tr2.reset(new GemmPlan(t2, s, false));
-  }
+        theta(nrhs_ * S_ * sizeof(double2), s), broken(nrhs_ * sizeof(int32_t), s) {}
 };
 
 // Shifts of every right-hand side from the Hessenberg matrix of a plain
@@ -1729,7 +1776,6 @@ static bool run_sstep_cycle(SStep& ss, const GemmPlan& matvec, double2* V, doubl
     }
     // two block Gram-Schmidt passes against q_0..q_j, then Cholesky QR twice
     double2* Z = V + (j + 1) * vstride;
-    double2* Zt = ss.Zt.as<double2>();
     const int64_t runs = (j + 1 + 3) / 4;
     const int npu = (int)((n + 127) / 128);
     const double vb = 16.0 * (double)(j + 1) * (double)nrhs * (double)n;  // bytes of q_0..q_j
@@ -1755,32 +1801,22 @@ static bool run_sstep_cycle(SStep& ss, const GemmPlan& matvec, double2* V, doubl
       }
     }
     const unsigned gr = (unsigned)(((S + 3) / 4) * nrhs);
-    if (S == 4)
-      hipLaunchKernelGGL((block_dots_kernel<4, true>), dim3(gr), dim3(256), 0, s, Z, vstride, n, Z, vstride, n, n,
-                         (int64_t)S, ss.G.as<double2>(), (int64_t)S * S, gs);
-    else
-      hipLaunchKernelGGL((block_dots_kernel<8, true>), dim3(gr), dim3(256), 0, s, Z, vstride, n, Z, vstride, n, n,
-                         (int64_t)S, ss.G.as<double2>(), (int64_t)S * S, gs);
-    if (S == 4)
-      hipLaunchKernelGGL(chol_kernel<4>, dim3((unsigned)nrhs), dim3(64), 0, s, ss.G.as<double2>(),
-                         ss.Rinv.as<double2>(), ss.Rt.as<double2>(), 1, gs, ss.broken.as<int32_t>());
-    else
-      hipLaunchKernelGGL(chol_kernel<8>, dim3((unsigned)nrhs), dim3(64), 0, s, ss.G.as<double2>(),
-                         ss.Rinv.as<double2>(), ss.Rt.as<double2>(), 1, gs, ss.broken.as<int32_t>());
-    ss.tr1->launch((size_t)b, s);
-    if (S == 4)
-      hipLaunchKernelGGL((block_dots_kernel<4, true>), dim3(gr), dim3(256), 0, s, Zt, n, (int64_t)S * n, Zt, n,
-                         (int64_t)S * n, n, (int64_t)S, ss.G.as<double2>(), (int64_t)S * S, gs);
-    else
-      hipLaunchKernelGGL((block_dots_kernel<8, true>), dim3(gr), dim3(256), 0, s, Zt, n, (int64_t)S * n, Zt, n,
-                         (int64_t)S * n, n, (int64_t)S, ss.G.as<double2>(), (int64_t)S * S, gs);
-    if (S == 4)
-      hipLaunchKernelGGL(chol_kernel<4>, dim3((unsigned)nrhs), dim3(64), 0, s, ss.G.as<double2>(),
-                         ss.Rinv.as<double2>(), ss.Rt.as<double2>(), 0, gs, ss.broken.as<int32_t>());
-    else
-      hipLaunchKernelGGL(chol_kernel<8>, dim3((unsigned)nrhs), dim3(64), 0, s, ss.G.as<double2>(),
-                         ss.Rinv.as<double2>(), ss.Rt.as<double2>(), 0, gs, ss.broken.as<int32_t>());
-    ss.tr2->launch((size_t)b, s);
+    const dim3 gz((unsigned)((n + 255) / 256), (unsigned)nrhs);
+    for (int pass = 0; pass < 2; ++pass) {  // Cholesky QR, in place
+      if (S == 4) {
+        hipLaunchKernelGGL((block_dots_kernel<4, true>), dim3(gr), dim3(256), 0, s, Z, vstride, n, Z, vstride, n, n,
+                           (int64_t)S, ss.G.as<double2>(), (int64_t)S * S, gs);
+        hipLaunchKernelGGL(chol_kernel<4>, dim3((unsigned)nrhs), dim3(64), 0, s, ss.G.as<double2>(),
+                           ss.Rinv.as<double2>(), ss.Rt.as<double2>(), pass == 0, gs, ss.broken.as<int32_t>());
+        hipLaunchKernelGGL(trmul_kernel<4>, gz, dim3(256), 0, s, Z, vstride, n, ss.Rinv.as<double2>(), gs);
+      } else {
+        hipLaunchKernelGGL((block_dots_kernel<8, true>), dim3(gr), dim3(256), 0, s, Z, vstride, n, Z, vstride, n, n,
+                           (int64_t)S, ss.G.as<double2>(), (int64_t)S * S, gs);
+        hipLaunchKernelGGL(chol_kernel<8>, dim3((unsigned)nrhs), dim3(64), 0, s, ss.G.as<double2>(),
+                           ss.Rinv.as<double2>(), ss.Rt.as<double2>(), pass == 0, gs, ss.broken.as<int32_t>());
+        hipLaunchKernelGGL(trmul_kernel<8>, gz, dim3(256), 0, s, Z, vstride, n, ss.Rinv.as<double2>(), gs);
+      }
+    }
     const unsigned nrb = (unsigned)((j + S + 1 + 63) / 64);
     hipLaunchKernelGGL(csum_kernel, dim3((unsigned)(((j + 1) * S + 255) / 256), (unsigned)nrhs), dim3(256), 0, s,
                        ss.C1.as<double2>(), ss.C2.as<double2>(), ss.cst, S, j, gs);
@@ -1788,13 +1824,13 @@ static bool run_sstep_cycle(SStep& ss, const GemmPlan& matvec, double2* V, doubl
       hipLaunchKernelGGL(sstep_hcols_kernel<4>, dim3(nrb, (unsigned)nrhs), dim3(256), 0, s, gs, H, ss.M1, ss.HS,
                          ss.C1.as<double2>(), ss.cst, ss.Rt.as<double2>(), ss.sig.as<double>(), ss.theta.as<double2>(),
                          ss.broken.as<int32_t>(), j);
-      hipLaunchKernelGGL(sstep_givens_kernel<4>, dim3((unsigned)nrhs), dim3(64), 0, s, gs, H, ss.M1, ss.HS,
+      hipLaunchKernelGGL(sstep_givens_kernel<4>, dim3((unsigned)nrhs), dim3(256), 0, s, gs, H, ss.M1, ss.HS,
                          ss.broken.as<int32_t>(), j, m, nrhs);
     } else {
       hipLaunchKernelGGL(sstep_hcols_kernel<8>, dim3(nrb, (unsigned)nrhs), dim3(256), 0, s, gs, H, ss.M1, ss.HS,
                          ss.C1.as<double2>(), ss.cst, ss.Rt.as<double2>(), ss.sig.as<double>(), ss.theta.as<double2>(),
                          ss.broken.as<int32_t>(), j);
-      hipLaunchKernelGGL(sstep_givens_kernel<8>, dim3((unsigned)nrhs), dim3(64), 0, s, gs, H, ss.M1, ss.HS,
+      hipLaunchKernelGGL(sstep_givens_kernel<8>, dim3((unsigned)nrhs), dim3(256), 0, s, gs, H, ss.M1, ss.HS,
                          ss.broken.as<int32_t>(), j, m, nrhs);
     }
     CBFM_HIP(hipGetLastError());
@@ -1996,7 +2032,7 @@ GmresResult gmres_run(KrylovOp& op, int64_t n, int64_t nrhs, const double2* b, d
       std::vector<int32_t> its1(nrhs);
       CBFM_HIP(hipMemcpyAsync(its1.data(), gs.its, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
       CBFM_HIP(hipStreamSynchronize(s));
-      sst.reset(new SStep(S, n, nrhs, ms, V.as<double2>(), vstride, s));
+      sst.reset(new SStep(S, n, nrhs, ms, s));
       sstep_shifts(*sst, g1, m1, its1, s);
       shifts_ready = true;
     } else if (sstep_on) {
