@@ -62,6 +62,19 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Work unit of block b when one product's units (row of tiles, K part) x
+// column tile are numbered column fastest: blocks go to the 8 XCDs in
+// turn, so within each run of 8 ntn blocks the ntn column tiles of a row
+// and K part go to blocks 8 apart, which one XCD runs one after the other,
+// sharing that part of op(A)'s rows in its L2 (read from HBM once instead
+// of ntn times).  A bijection of [0, units); the last partial run is kept.
+__device__ __forceinline__ int64_t xcd_unit(int64_t b, int64_t units, int64_t ntn) {
+  const int64_t run = 8 * ntn, full = units / run * run;
+  if (b >= full) return b;
+  const int64_t base = b / run * run, r = b - base;
+  return base + (r % 8) * ntn + r / 8;
+}
+
 // C (tile at rows m0.., columns n0..; CT column blocks) = alpha (cr + i ci),
 // or added to C, in the accumulator layout of the FP64 matrix cores.
 template <int CT>
@@ -124,8 +137,14 @@ __global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK, CT == 1 ? 4 :
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // wave-uniform tile and descriptor (readfirstlane makes the K loop a scalar
   // loop: the accumulators then stay in the matrix-core registers across it)
-  const int64_t tile = SPLITK == 1 ? (int64_t)blockIdx.x * 4 + wave : (int64_t)blockIdx.x / KB;
-  const int kb = SPLITK == 1 ? 0 : (int)(blockIdx.x % KB);
+  int64_t tile = SPLITK == 1 ? (int64_t)blockIdx.x * 4 + wave : (int64_t)blockIdx.x / KB;
+  int kb = SPLITK == 1 ? 0 : (int)(blockIdx.x % KB);
+  if (SPLITK > 1 && ndesc == 1) {  // one product, a tile (or K part) per block: XCD-aware order
+    const int64_t ntn0 = (uniform64(desc[0].N) + 16 * CT - 1) / (16 * CT);
+    const int64_t u = xcd_unit(blockIdx.x, total_tiles * KB, ntn0), rk = u / ntn0;
+    tile = (rk / KB) * ntn0 + u % ntn0;
+    kb = (int)(rk % KB);
+  }
   if (tile >= total_tiles) return;  // uniform per block when SPLITK > 1
   // descriptor holding this tile (tile_start ascending)
   int lo = 0, hi = ndesc - 1;
