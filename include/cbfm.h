@@ -448,7 +448,10 @@ typedef struct {
                       /* coefficients: the basis is read 4 times per      */
                       /* block instead of twice per iteration.  After a   */
                       /* Cholesky breakdown the solve continues with      */
-                      /* plain cycles.  0: plain cycles.  Not with        */
+                      /* plain cycles, and so do the last iterations when */
+                      /* fewer than sstep are left before max_iter (the   */
+                      /* count stops at max_iter exactly).  0: plain      */
+                      /* cycles.  Not with                                */
                       /* inner_fp32, basis_fp32, use_graph or             */
                       /* CBFM_CMP_INNER_GMRES (CBFM_E_ARG); cbfm_solve    */
                       /* only.                                            */

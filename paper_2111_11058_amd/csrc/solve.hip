@@ -2015,6 +2015,10 @@ GmresResult gmres_run(KrylovOp& op, int64_t n, int64_t nrhs, const double2* b, d
     else
       hipLaunchKernelGGL(scale_kernel<double2>, grid2(n, nrhs), dim3(256), 0, s, r, V.as<double2>(), n, gs.nrm);
     if (all_done(flags.sync_read(gs.active, s)) || total >= p.max_iter) break;
+    // an s-step cycle takes whole blocks of S iterations: fewer than S left
+    // run in a plain cycle (an s-step cycle would take none and the loop
+    // would make no progress)
+    if (sstep_on && shifts_ready && total + S > p.max_iter) sstep_on = false;
     if (f32)
       run_cycle(matvec32, dyn32.get(), dyn32 ? dyn32->desc(0) : nullptr, jdev.as<int64_t>(), V.as<float2>(),
                 u.as<float2>(), vstride, n, nrhs, mres, p.max_iter, total, gs, part.as<double>(), np, flags, x, s);

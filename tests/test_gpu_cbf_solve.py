@@ -471,6 +471,16 @@ def test_sstep_solve(torch_cuda):
         assert b["status"] == "OK" and np.all(b["relres"] <= 1e-6)
         if S == 4:
             assert np.all(b["iters"] <= plain["iters"] + 2 * S + 2)
+    # an iteration limit that whole blocks cannot reach (the first cycle
+    # of S + 1, two blocks, then 3 iterations in a plain cycle) and a
+    # tolerance no solve meets: the solve stops at the limit, unconverged
+    # (a right-hand side whose block broke down counts that block out)
+    for S in (4, 8):
+        lim = S + 1 + 2 * S + 3
+        c = cbfm.solve(mesh, med, cbf, Zr, inc, tol=1e-30, max_iter=lim, restart=n + 10, sstep=S)
+        print("s-step", S, "iteration limit", lim, c["iters"], c["relres"], c["status"])
+        assert c["status"] == "E_NOCONV" and c["iters"].max() == lim and np.all(c["iters"] <= lim), S
+        assert np.all(c["relres"] < 1), S
     with pytest.raises(RuntimeError):
         cbfm.solve(mesh, med, cbf, Zr, inc, sstep=5, raise_noconv=True)
     with pytest.raises(RuntimeError):
