@@ -146,6 +146,10 @@ int32_t cbfm_version(void);  /* 5: cbfm_solver_params gained sstep (4: basis_fp3
  *                     w and the Hessenberg entries of p = H a)
  *   6 "fill_regular_f32"  triangle pairs of the regular fill in float
  *   7 "xgemm"         real flops of the FP32 / BF16 matrix-core GEMMs
+ *   8 "gemm_panel"    real flops of the "gemm" launches that ran on the
+ *                     row-block kernel (one product of at most 32 columns,
+ *                     such as the GMRES matrix-vector product), its
+ *                     reduction of the K-split parts included
  * ("fill_regular" and "gemm" then count the double-precision launches.)
  * (the GMRES figures count every right-hand side of the batch, also those
  * already converged, which the kernels skip).

@@ -193,7 +193,8 @@ def memory_stats():
     return dict(held=h.value, peak=p.value, cached=c.value)
 
 
-TIMERS = ("fill_regular", "fill_near", "assemble", "gemm", "gmres_dots", "gmres_update", "fill_regular_f32", "xgemm")
+TIMERS = ("fill_regular", "fill_near", "assemble", "gemm", "gmres_dots", "gmres_update", "fill_regular_f32", "xgemm",
+          "gemm_panel")
 
 
 def timer_enable(names=TIMERS):

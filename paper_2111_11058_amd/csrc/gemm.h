@@ -127,7 +127,7 @@ class GemmPlan {
  private:
   bool tune_;
   Scratch dev_;
-  std::vector<int64_t> first_, count_, tiles_, m_, n_;
+  std::vector<int64_t> first_, count_, tiles_, m_, n_, k_;
   std::vector<double> flops_;
   std::vector<int> variant_;
   std::unique_ptr<Scratch> ws_;  // partial tiles of K-split launch shapes

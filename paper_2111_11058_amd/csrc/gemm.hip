@@ -12,6 +12,8 @@
 // The accumulator element r of lane L is C[4 r + L / 16][L % 16] (measured
 // on gfx950 with indexed operands: rows are interleaved across the four
 // lane groups).
+#include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -313,14 +315,17 @@ __global__ void __launch_bounds__(SPLITK == 1 ? 256 : 64 * SPLITK, CT == 1 ? 4 :
   store_tile<CT>(d, m0, n0, lane, cr, ci);
 }
 
-// The tiles of a K-split product (one descriptor): one wavefront per tile
-// adds its KB parts from ws in block order and stores the tile.
+// The tiles of a K-split product (one descriptor): a block of four
+// wavefronts per tile, wavefront w adding the parts b = w, w + 4, ... from
+// ws (its loads all in flight), then wavefront 0 adding the four sums in
+// order through LDS and storing the tile.  With at most four parts this is
+// the block order.
 template <int CT>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
     splitk_reduce_kernel(const GemmDesc* __restrict__ desc, int64_t total_tiles, int KB, const double* __restrict__ ws) {
   const int64_t tile = blockIdx.x;
-  if (tile >= total_tiles) return;
-  const int lane = threadIdx.x;
+  if (tile >= total_tiles) return;  // uniform per block
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const GemmDesc d = desc[0];
   const int64_t t = tile - (CT == 1 ? d.tile_start : 0);
   const int64_t ntn = (d.N + 16 * CT - 1) / (16 * CT);
@@ -328,7 +333,8 @@ __global__ void __launch_bounds__(64)
   dbl4 cr[CT], ci[CT];
 #pragma unroll
   for (int u = 0; u < CT; ++u) cr[u] = ci[u] = dbl4{0, 0, 0, 0};
-  for (int b = 0; b < KB; ++b) {
+#pragma unroll 4
+  for (int b = wave; b < KB; b += 4) {
     const double* r = ws + ((tile * KB + b) * 64 + lane) * 8 * CT;
 #pragma unroll
     for (int u = 0; u < CT; ++u)
@@ -338,6 +344,27 @@ __global__ void __launch_bounds__(64)
         ci[u][q] += r[8 * u + 4 + q];
       }
   }
+  __shared__ double part[3][8 * CT][64];
+  if (wave > 0) {
+#pragma unroll
+    for (int u = 0; u < CT; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        part[wave - 1][8 * u + q][lane] = cr[u][q];
+        part[wave - 1][8 * u + 4 + q][lane] = ci[u][q];
+      }
+  }
+  __syncthreads();
+  if (wave > 0) return;
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+#pragma unroll
+    for (int u = 0; u < CT; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cr[u][q] += part[w][8 * u + q][lane];
+        ci[u][q] += part[w][8 * u + 4 + q][lane];
+      }
   store_tile<CT>(d, m0, n0, lane, cr, ci);
 }
 
@@ -754,6 +781,177 @@ __global__ void __launch_bounds__(256) zgemv_kernel(const GemmDesc* __restrict__
   }
 }
 
+// A single product with at most 32 columns, op(A) rows and op(B) columns
+// contiguous along k (such as the GMRES matrix times a block of vectors):
+// a block of four wavefronts takes 64 rows of op(A), 16 per wavefront,
+// against all 32 columns, over a contiguous range of the K groups (block
+// kb of KB for its rows).  op(A) is read once.  Each group's 16 k x 32
+// columns of op(B) are loaded once per block and shared by the four
+// wavefronts through LDS (two buffers, so one barrier per group), where the
+// tiled kernels load them once per 16 x 16 tile.  Every wavefront holds the
+// raw operands of two groups in flight.  The partial tiles go to ws in
+// splitk_reduce_kernel<2>'s layout (the tile of wavefront w of row block p
+// is 4 p + w); panel_reduce_kernel adds them in block order and stores C.
+__global__ void __launch_bounds__(256, 3) zgemm_panel_kernel(const GemmDesc* __restrict__ desc, int KB,
+                                                          double* __restrict__ ws) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int slot = lane >> 4, li = lane & 15;
+  GemmDesc d = desc[0];
+  d.M = uniform64(d.M);
+  d.N = uniform64(d.N);
+  d.K = uniform64(d.K);
+  d.lda = uniform64(d.lda);
+  d.ldb = uniform64(d.ldb);
+  d.opA = __builtin_amdgcn_readfirstlane(d.opA);
+  d.opB = __builtin_amdgcn_readfirstlane(d.opB);
+  const int64_t rb = blockIdx.x / KB;
+  const int kb = (int)(blockIdx.x % KB);
+  const int64_t G = (d.K + 15) / 16;
+  const int64_t g0 = G * kb / KB, g1 = G * (kb + 1) / KB;  // this block's groups of 16 k
+  const int64_t m0 = rb * 64 + 16 * wave;
+  const double sgA = d.opA == OP_R ? -1.0 : 1.0;
+  const double sgB = d.opB == OP_C ? -1.0 : 1.0;
+  // op(A): lane (slot, li), load q reads row m0 + 4 q + slot at k = 16 g + li;
+  // op(B): thread t, load h reads column 16 h + t / 16 at k = 16 g + t % 16.
+  // Rows past M and columns past N read row M - 1 and column N - 1: they
+  // only reach results that are not stored.
+  const double2* pA[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) pA[q] = d.A + std::min<int64_t>(m0 + 4 * q + slot, d.M - 1) * d.lda + li;
+  const int tc = threadIdx.x >> 4, tk = threadIdx.x & 15;
+  const double2* pB[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) pB[h] = d.B + std::min<int64_t>(16 * h + tc, d.N - 1) * d.ldb + tk;
+  // whole groups (every k inside K) load without conditions, so that the
+  // waits of the loop count the loads of the group in flight exactly; the
+  // last group of a K that is not a multiple of 16 is taken after the loop
+  const int64_t ge = std::min(g1, d.K / 16);
+  auto gload = [&](int64_t g, double2(&ra)[4], double2(&rbv)[2]) {
+    const int64_t k0 = 16 * g;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ra[q] = ld_global(pA[q] + k0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) rbv[h] = ld_global(pB[h] + k0);
+  };
+  __shared__ double2 sa[4][16][17];  // per wavefront: op(A) rows x k
+  __shared__ double2 sb[2][32][17];  // per block, two buffers: op(B) columns x k
+  double2(*as)[17] = sa[wave];
+  auto put = [&](const double2(&ra)[4], const double2(&rbv)[2], int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) as[4 * q + slot][li] = make_double2(ra[q].x, sgA * ra[q].y);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) sb[buf][16 * h + tc][tk] = make_double2(rbv[h].x, sgB * rbv[h].y);
+  };
+  // 3M products as in zgemm_batched_kernel, two column blocks
+  dbl4 p1[2], p2[2], p3[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) p1[u] = p2[u] = p3[u] = dbl4{0, 0, 0, 0};
+  auto mma = [&](int buf) {
+    double2 a[4], b[2][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {  // step s takes k = 4 s + slot
+      a[s] = as[li][4 * s + slot];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) b[u][s] = sb[buf][16 * u + li][4 * s + slot];
+    }
+    // the wavefront's next writes of its op(A) rows stay after these reads
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        p1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].x, b[u][s].x, p1[u], 0, 0, 0);
+        p2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].y, b[u][s].y, p2[u], 0, 0, 0);
+        p3[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].x + a[s].y, b[u][s].x + b[u][s].y, p3[u], 0, 0, 0);
+      }
+  };
+  // a buffer of sb is rewritten two groups after it was read: every
+  // wavefront has passed the barrier of the group in between by then
+  int last = 1;  // buffer of the last group taken
+  if (g0 < ge) {  // uniform over the block
+    double2 ra0[4], rb0[2], ra1[4], rb1[2];
+    // prefetches past this block's whole groups read its last one again
+    gload(g0, ra0, rb0);
+    gload(std::min(g0 + 1, ge - 1), ra1, rb1);
+    // pairs of groups: the loop is entered and repeated only with both
+    // groups' loads in flight, so each wait leaves the other group's loads
+    // outstanding
+    // (the scheduling barriers keep a group's stores to LDS, which wait on
+    // its loads, from being moved above the other group's matrix-core work)
+    int64_t g = g0;
+    for (; g + 1 < ge; g += 2) {  // g, ge: uniform over the block
+      put(ra0, rb0, 0);
+      gload(std::min(g + 2, ge - 1), ra0, rb0);
+      __syncthreads();
+      mma(0);
+      __builtin_amdgcn_sched_barrier(0);
+      put(ra1, rb1, 1);
+      gload(std::min(g + 3, ge - 1), ra1, rb1);
+      __syncthreads();
+      mma(1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (g < ge) {  // one group left, in ra0
+      put(ra0, rb0, 0);
+      __syncthreads();
+      mma(0);
+      last = 0;
+    }
+  }
+  if (d.K % 16 != 0 && g0 <= G - 1 && G - 1 < g1) {  // the partial last group of K, if this block's
+    const int64_t k0 = 16 * ge;
+    double2 ra[4], rbv[2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ra[q] = ld_global(k0 + li < d.K ? pA[q] + k0 : g_zero2);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) rbv[h] = ld_global(k0 + tk < d.K ? pB[h] + k0 : g_zero2);
+    put(ra, rbv, 1 - last);
+    __syncthreads();
+    mma(1 - last);
+  }
+  const int64_t tile = rb * 4 + wave;
+  if (tile >= (d.M + 15) / 16) return;
+  double* o = ws + ((tile * KB + kb) * 64 + lane) * 16;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      o[8 * u + q] = p1[u][q] - p2[u][q];
+      o[8 * u + 4 + q] = p3[u][q] - p1[u][q] - p2[u][q];
+    }
+}
+
+// The row-block kernel's partial tiles (splitk_reduce_kernel<2>'s layout),
+// one thread per element of C: the KB parts added in block order, then
+// alpha and the store as in store_tile.  Eight consecutive threads read one
+// lane's 128 bytes of a part.
+__global__ void __launch_bounds__(256) panel_reduce_kernel(const GemmDesc* __restrict__ desc, int64_t total_tiles,
+                                                           int KB, const double* __restrict__ ws) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total_tiles * 512) return;
+  const int64_t tile = e >> 9;
+  const int lane = (int)(e >> 3) & 63, u = (int)(e >> 2) & 1, q = (int)e & 3;
+  const GemmDesc d = desc[0];
+  const int64_t row = tile * 16 + 4 * q + (lane >> 4), col = 16 * u + (lane & 15);
+  const double* r = ws + (tile * KB * 64 + lane) * 16 + 8 * u + q;
+  double xr = 0, xi = 0;
+#pragma unroll 4
+  for (int b = 0; b < KB; ++b) {
+    xr += r[(int64_t)b * 64 * 16];
+    xi += r[(int64_t)b * 64 * 16 + 4];
+  }
+  if (row >= d.M || col >= d.N) return;
+  double2 v = make_double2(d.alpha_re * xr - d.alpha_im * xi, d.alpha_re * xi + d.alpha_im * xr);
+  double2* p = d.transC ? d.C + col * d.ldc + row : d.C + row * d.ldc + col;
+  if (d.accumulate) {
+    const double2 o = ld_global(p);
+    v.x += o.x;
+    v.y += o.y;
+  }
+  *p = v;
+}
+
 // Launch shapes: four tiles per block (one per wavefront), or one tile per
 // block with K split over 4 or 8 wavefronts; for a single product also
 // tiles of 2 or 4 adjacent 16-column blocks with K split over 4 wavefronts
@@ -763,8 +961,11 @@ __global__ void __launch_bounds__(256) zgemv_kernel(const GemmDesc* __restrict__
 // of a wavefront waits on memory about once per group of 16 k, so the
 // launch is fastest with the shortest loops whose blocks all fit on the
 // chip at once; 528 tiles of 8 wavefronts, say, leave 16 blocks for a
-// second round at 4 wavefronts per SIMD), and for a single
-// matrix-vector product the vector-unit kernel.
+// second round at 4 wavefronts per SIMD), for a single
+// matrix-vector product the vector-unit kernel, and for a single product of
+// at most 32 columns the row-block kernel (zgemm_panel_kernel) with its K
+// range split so that 2 or 3 blocks per compute unit hold every block of the
+// launch at once.
 enum {
   GV_TILE4 = 0,
   GV_SPLIT4,
@@ -775,29 +976,62 @@ enum {
   GV_SPLIT3_KB2,
   GV_SPLIT2_KB3,
   GV_GEMV,
+  GV_PANEL2,
+  GV_PANEL3,
   GV_COUNT
 };
 
 static bool single_only(int v) { return v >= GV_WIDE2_S4; }
 
-// column blocks per tile and blocks per tile of the launch shapes
-static int ct_of(int v) { return v == GV_WIDE4_S4 ? 4 : v == GV_WIDE2_S4 ? 2 : 1; }
-static int kb_of(int v) { return v == GV_SPLIT3_KB2 ? 2 : v == GV_SPLIT2_KB3 ? 3 : 1; }
+static bool panel_shape(int v) { return v == GV_PANEL2 || v == GV_PANEL3; }
+
+// compute units of the current device (read once per process)
+static int cu_count() {
+  static std::atomic<int> n{0};
+  int c = n.load();
+  if (c == 0) {
+    int dev = 0;
+    CBFM_HIP(hipGetDevice(&dev));
+    CBFM_HIP(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
+    c = std::max(c, 1);
+    n.store(c);
+  }
+  return c;
+}
+
+// column blocks per tile and blocks per tile of the launch shapes (the
+// row-block shapes: blocks per 64 rows, 2 or 3 blocks per compute unit over
+// the launch, at most one per group of 16 k)
+static int ct_of(int v) { return v == GV_WIDE4_S4 ? 4 : (v == GV_WIDE2_S4 || panel_shape(v)) ? 2 : 1; }
+static int kb_of(int v, int64_t M, int64_t K) {
+  if (panel_shape(v)) {
+    const int64_t rows = (M + 63) / 64, groups = std::max<int64_t>(1, (K + 15) / 16);
+    const int64_t per = (int64_t)(v == GV_PANEL3 ? 3 : 2) * cu_count();
+    return (int)std::max<int64_t>(1, std::min(groups, per / std::max<int64_t>(1, rows)));
+  }
+  return v == GV_SPLIT3_KB2 ? 2 : v == GV_SPLIT2_KB3 ? 3 : 1;
+}
 
 // bytes of partial tiles a launch shape leaves for splitk_reduce_kernel
-static size_t ws_bytes(int v, int64_t tiles, int64_t M, int64_t N) {
-  const int kb = kb_of(v), ct = ct_of(v);
-  if (kb == 1) return 0;
+static size_t ws_bytes(int v, int64_t tiles, int64_t M, int64_t N, int64_t K) {
+  const int kb = kb_of(v, M, K), ct = ct_of(v);
+  if (kb == 1 && !panel_shape(v)) return 0;
   const int64_t t = ct == 1 ? tiles : ((M + 15) / 16) * ((N + 16 * ct - 1) / (16 * ct));
   return (size_t)t * kb * 64 * 8 * ct * sizeof(double);
+}
+
+// The row-block kernel takes one product of at most 32 columns with op(A)
+// rows and op(B) columns contiguous along k.
+static bool panel_fits(int64_t N, int opA, int opB) {
+  return N <= 32 && (opA == OP_N || opA == OP_R) && (opB == OP_T || opB == OP_C);
 }
 
 // The vector-unit kernel takes one column with op(A) rows contiguous.
 static bool gemv_shape(int64_t N, int opA) { return N == 1 && (opA == OP_N || opA == OP_R); }
 
-// tiles: 16 x 16 tiles of the group; M, N: the sizes of its product when it
-// has one (the wide shapes number their own tiles)
-static void launch_variant(int v, const GemmDesc* dev, int count, int64_t tiles, int64_t M, int64_t N,
+// tiles: 16 x 16 tiles of the group; M, N, K: the sizes of its product when
+// it has one (the wide and row-block shapes number their own tiles)
+static void launch_variant(int v, const GemmDesc* dev, int count, int64_t tiles, int64_t M, int64_t N, int64_t K,
                            hipStream_t s, double* ws) {
   const dim3 one((unsigned)tiles);
   auto wide = [&](int ct) { return ((M + 15) / 16) * ((N + 16 * ct - 1) / (16 * ct)); };
@@ -806,6 +1040,16 @@ static void launch_variant(int v, const GemmDesc* dev, int count, int64_t tiles,
     case GV_GEMV:
       hipLaunchKernelGGL(zgemv_kernel, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, s, dev);
       break;
+    case GV_PANEL2:
+    case GV_PANEL3: {
+      CBFM_REQUIRE(ws != nullptr, CBFM_E_ARG, "K-split GEMM without workspace");
+      CBFM_REQUIRE(N <= 32, CBFM_E_ARG, "row-block GEMM with more than 32 columns");
+      const int kb = kb_of(v, M, K);
+      const int64_t nt = (M + 15) / 16;
+      hipLaunchKernelGGL(zgemm_panel_kernel, dim3((unsigned)((M + 63) / 64 * kb)), dim3(256), 0, s, dev, kb, ws);
+      hipLaunchKernelGGL(panel_reduce_kernel, dim3((unsigned)((nt * 512 + 255) / 256)), dim3(256), 0, s, dev, nt, kb, ws);
+      break;
+    }
     case GV_TILE4:
       hipLaunchKernelGGL((zgemm_batched_kernel<1, 1>), dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, dev, count,
                          tiles);
@@ -826,13 +1070,13 @@ static void launch_variant(int v, const GemmDesc* dev, int count, int64_t tiles,
       CBFM_REQUIRE(ws != nullptr, CBFM_E_ARG, "K-split GEMM without workspace");
       hipLaunchKernelGGL((zgemm_batched_kernel<3, 1>), dim3((unsigned)(tiles * 2)), dim3(192), 0, s, dev, count, tiles,
                          2, ws);
-      hipLaunchKernelGGL(splitk_reduce_kernel<1>, one, dim3(64), 0, s, dev, tiles, 2, ws);
+      hipLaunchKernelGGL(splitk_reduce_kernel<1>, one, dim3(256), 0, s, dev, tiles, 2, ws);
       break;
     case GV_SPLIT2_KB3:
       CBFM_REQUIRE(ws != nullptr, CBFM_E_ARG, "K-split GEMM without workspace");
       hipLaunchKernelGGL((zgemm_batched_kernel<2, 1>), dim3((unsigned)(tiles * 3)), dim3(128), 0, s, dev, count, tiles,
                          3, ws);
-      hipLaunchKernelGGL(splitk_reduce_kernel<1>, one, dim3(64), 0, s, dev, tiles, 3, ws);
+      hipLaunchKernelGGL(splitk_reduce_kernel<1>, one, dim3(256), 0, s, dev, tiles, 3, ws);
       break;
     default:
       hipLaunchKernelGGL((zgemm_batched_kernel<4, 4>), dim3((unsigned)wide(4)), dim3(256), 0, s, dev, count, wide(4));
@@ -861,7 +1105,8 @@ static GemmKey key_of(int dev, const GemmDesc* d, int count, int64_t tiles) {
 
 // Launch shape v runs a group of this shape class.
 static bool applicable(int v, const GemmKey& k) {
-  return !(single_only(v) && k.count != 1) && !(v == GV_GEMV && !gemv_shape(k.N, k.opA));
+  return !(single_only(v) && k.count != 1) && !(v == GV_GEMV && !gemv_shape(k.N, k.opA)) &&
+         !(panel_shape(v) && !panel_fits(k.N, k.opA, k.opB));
 }
 
 // CBFM_GEMM_SHAPE (for tests and tuning studies): the index of a launch
@@ -884,10 +1129,15 @@ static int choose(const GemmKey& k) {
   return k.tiles < 4096 ? GV_SPLIT4 : GV_TILE4;
 }
 
-static void launch_descs(const GemmDesc* dev, int count, int64_t tiles, int64_t M, int64_t N, double flops,
-                         int variant, hipStream_t s, double* ws) {
+static void launch_descs(const GemmDesc* dev, int count, int64_t tiles, int64_t M, int64_t N, int64_t K,
+                         double flops, int variant, hipStream_t s, double* ws) {
   TimedLaunch tl(T_GEMM, s, flops);
-  launch_variant(variant, dev, count, tiles, M, N, s, ws);
+  if (panel_shape(variant)) {
+    TimedLaunch tp(T_GEMM_PANEL, s, flops);
+    launch_variant(variant, dev, count, tiles, M, N, K, s, ws);
+  } else {
+    launch_variant(variant, dev, count, tiles, M, N, K, s, ws);
+  }
 }
 
 // Elements spanned by an operand or the result of a descriptor.
@@ -930,13 +1180,13 @@ static void tune_group(const GemmKey& key, const GemmDesc* dev, int count, int64
   try {
     size_t wsb = 0;
     if (count == 1)
-      for (int v = 0; v < GV_COUNT; ++v) wsb = std::max(wsb, ws_bytes(v, tiles, key.M, key.N));
+      for (int v = 0; v < GV_COUNT; ++v) wsb = std::max(wsb, ws_bytes(v, tiles, key.M, key.N, key.K));
     Scratch ws(wsb, s);
     for (int v = 0; v < GV_COUNT; ++v) {
       if (!applicable(v, key)) continue;
-      launch_variant(v, dev, count, tiles, key.M, key.N, s, ws.as<double>());
+      launch_variant(v, dev, count, tiles, key.M, key.N, key.K, s, ws.as<double>());
       CBFM_HIP(hipEventRecord(e0, s));
-      for (int r = 0; r < 3; ++r) launch_variant(v, dev, count, tiles, key.M, key.N, s, ws.as<double>());
+      for (int r = 0; r < 3; ++r) launch_variant(v, dev, count, tiles, key.M, key.N, key.K, s, ws.as<double>());
       CBFM_HIP(hipEventRecord(e1, s));
       CBFM_HIP(hipEventSynchronize(e1));
       float ms = 0;
@@ -967,9 +1217,10 @@ void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s) {
   CBFM_HIP(hipMemcpyAsync(dev.p, live.data(), live.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
   int d = 0;
   CBFM_HIP(hipGetDevice(&d));
-  const int v = choose(key_of(d, live.data(), (int)live.size(), tiles));
-  Scratch ws(ws_bytes(v, tiles, live[0].M, live[0].N), s);
-  launch_descs(dev.as<GemmDesc>(), (int)live.size(), tiles, live[0].M, live[0].N, flops, v, s, ws.as<double>());
+  const GemmKey key = key_of(d, live.data(), (int)live.size(), tiles);
+  const int v = choose(key);
+  Scratch ws(ws_bytes(v, tiles, key.M, key.N, key.K), s);
+  launch_descs(dev.as<GemmDesc>(), (int)live.size(), tiles, key.M, key.N, key.K, flops, v, s, ws.as<double>());
   // the descriptor staging buffer is host memory of this frame
   CBFM_HIP(hipStreamSynchronize(s));
 }
@@ -1000,6 +1251,9 @@ GemmPlan::GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t
   for (size_t g = 0; g < groups.size(); ++g) {
     m_.push_back(count_[g] > 0 ? all[first_[g]].M : 0);
     n_.push_back(count_[g] > 0 ? all[first_[g]].N : 0);
+    int64_t kmax = 0;
+    for (int64_t i = 0; i < count_[g]; ++i) kmax = std::max(kmax, all[first_[g] + i].K);
+    k_.push_back(kmax);
     if (count_[g] == 0) {
       variant_.push_back(GV_TILE4);
       continue;
@@ -1016,15 +1270,16 @@ GemmPlan::GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t
   }
   // one workspace for the partial tiles of every group (launched in turn)
   size_t wsb = 0;
-  for (size_t g = 0; g < groups.size(); ++g) wsb = std::max(wsb, ws_bytes(variant_[g], tiles_[g], m_[g], n_[g]));
+  for (size_t g = 0; g < groups.size(); ++g)
+    wsb = std::max(wsb, ws_bytes(variant_[g], tiles_[g], m_[g], n_[g], k_[g]));
   ws_.reset(new Scratch(wsb, s));
 }
 
 void GemmPlan::launch(size_t g, hipStream_t s) const {
   CBFM_REQUIRE(g < tiles_.size(), CBFM_E_ARG, "GEMM plan group out of range");
   if (count_[g] == 0) return;
-  launch_descs(dev_.as<GemmDesc>() + first_[g], (int)count_[g], tiles_[g], m_[g], n_[g], flops_[g], variant_[g], s,
-               ws_->as<double>());
+  launch_descs(dev_.as<GemmDesc>() + first_[g], (int)count_[g], tiles_[g], m_[g], n_[g], k_[g], flops_[g],
+               variant_[g], s, ws_->as<double>());
 }
 
 }  // namespace cbfm

@@ -230,7 +230,8 @@ enum TimerId {
   T_GMRES_UPDATE = 5,
   T_FILL_REGULAR_F32 = 6,  // the regular fill in float
   T_XGEMM = 7,             // GEMMs on the FP32 / BF16 matrix cores
-  T_COUNT = 8
+  T_GEMM_PANEL = 8,        // the T_GEMM launches run by the row-block kernel
+  T_COUNT = 9
 };
 struct TimedLaunch {
   TimedLaunch(int id, hipStream_t s, double work = 0.0);

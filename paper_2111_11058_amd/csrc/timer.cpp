@@ -19,8 +19,8 @@ struct Rec {
   double ms = 0, work = 0;
 };
 Rec g_rec[T_COUNT];
-const char* g_names[T_COUNT] = {"fill_regular", "fill_near",    "assemble",         "gemm",
-                                "gmres_dots",   "gmres_update", "fill_regular_f32", "xgemm"};
+const char* g_names[T_COUNT] = {"fill_regular", "fill_near",    "assemble",         "gemm",      "gmres_dots",
+                                "gmres_update", "fill_regular_f32", "xgemm",        "gemm_panel"};
 
 void drain(Rec& r) {
   for (auto& p : r.pending) {

@@ -493,10 +493,12 @@ def test_every_gemm_launch_shape_solves_alike(torch_cuda, monkeypatch):
     GMRES matrix-vector product): four tiles per block, K split over 4 or 8
     wavefronts, wide tiles of 2 or 4 column blocks, K split over 5
     wavefronts, over 3 wavefronts x 2 blocks and 2 wavefronts x 3 blocks
-    (partial tiles added by a second kernel), and the vector-unit
-    matrix-vector kernel (a single right-hand side).  Each solve, at tol
-    1e-12 with the full Krylov space, matches LU of the oracle's reduced
-    system."""
+    (partial tiles added by a second kernel), the vector-unit
+    matrix-vector kernel (a single right-hand side), and the row-block
+    kernel (64 rows x 32 columns per block, K split so that 2 or 3 blocks
+    per compute unit hold the launch; partial tiles added by the second
+    kernel).  Each solve, at tol 1e-12 with the full Krylov space, matches
+    LU of the oracle's reduced system."""
     from oracle import excitation
     O = _oracle_cbf("cyl_small")
     P = O["P"]
@@ -508,7 +510,7 @@ def test_every_gemm_launch_shape_solves_alike(torch_cuda, monkeypatch):
     inc = w.inc
     vr = O["CJM"].conj().T @ excitation.rhs(m, inc, w.k0, w.eta0)
     jref = O["CMJ"] @ np.linalg.solve(O["Zr"], vr)
-    for shape in range(9):
+    for shape in range(11):
         monkeypatch.setenv("CBFM_GEMM_SHAPE", str(shape))
         for sel in (slice(None), slice(0, 1)):
             ii = np.ascontiguousarray(inc[sel])
