@@ -89,7 +89,8 @@ FAMILY_SOURCES = {
     "gmres_dots": ("dots2_kernel", "paper_2111_11058_amd/csrc/solve.hip"),
     "gmres_update": ("dcgs_update_kernel", "paper_2111_11058_amd/csrc/solve.hip"),
     # s-step cycles (blocks of 8): the block Gram-Schmidt passes
-    "gmres_block_dots": ("block_dots_kernel<8, false>", "paper_2111_11058_amd/csrc/solve.hip"),
+    # (the dot pass runs on the row-block GEMM kernel with 16-column tiles)
+    "gmres_block_dots": ("zgemm_panel_kernel<1>", "paper_2111_11058_amd/csrc/gemm.hip"),
     "gmres_block_update": ("block_update_kernel<8>", "paper_2111_11058_amd/csrc/solve.hip"),
     # the GMRES matrix-vector product: the launch shape of the complex GEMM
     # (tiled or row-block kernel) with the most dispatches
@@ -310,7 +311,7 @@ def write_counters(workload_name, stats_dir, dirs, cmd):
 
 
 # kernels and traffic entries of the solve's families under s-step cycles
-SSTEP_KERNELS = {"gmres_dots": ("block_dots_kernel", "gmres_block_dots"),
+SSTEP_KERNELS = {"gmres_dots": ("zgemm_panel_kernel<1>", "gmres_block_dots"),
                  "gmres_update": ("block_update_kernel", "gmres_block_update")}
 
 

@@ -117,6 +117,16 @@ class XGemmPlan {
 // launch shape (only groups whose products overwrite results that overlap
 // no operand) and the fastest is used from then on by every GEMM of that
 // class in the process.
+// nb products C_c = alpha op(A_c) op(B_c) (+ C_c) on the row-block kernel,
+// with A_c = A + c sA, B_c = B + c sB, C_c = C + c sC (elements) and the
+// sizes, leading dimensions and ops of d, which dev holds on the device:
+// 1 to 32 columns, op(A) N or R and op(B) T or C (rows of op(A) and
+// columns of op(B) contiguous along k).  ws: panel_batch_ws_bytes(d, nb)
+// bytes of device memory for the K-split parts.
+size_t panel_batch_ws_bytes(const GemmDesc& d, int64_t nb);
+void panel_batch(const GemmDesc* dev, const GemmDesc& d, int64_t nb, int64_t sA, int64_t sB, int64_t sC, double* ws,
+                 hipStream_t s);
+
 class GemmPlan {
  public:
   GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t s, bool tune = true);

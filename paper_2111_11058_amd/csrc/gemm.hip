@@ -781,19 +781,22 @@ __global__ void __launch_bounds__(256) zgemv_kernel(const GemmDesc* __restrict__
   }
 }
 
-// A single product with at most 32 columns, op(A) rows and op(B) columns
-// contiguous along k (such as the GMRES matrix times a block of vectors):
-// a block of four wavefronts takes 64 rows of op(A), 16 per wavefront,
-// against all 32 columns, over a contiguous range of the K groups (block
-// kb of KB for its rows).  op(A) is read once.  Each group's 16 k x 32
-// columns of op(B) are loaded once per block and shared by the four
-// wavefronts through LDS (two buffers, so one barrier per group), where the
-// tiled kernels load them once per 16 x 16 tile.  Every wavefront holds the
-// raw operands of two groups in flight.  The partial tiles go to ws in
-// splitk_reduce_kernel<2>'s layout (the tile of wavefront w of row block p
-// is 4 p + w); panel_reduce_kernel adds them in block order and stores C.
-__global__ void __launch_bounds__(256, 3) zgemm_panel_kernel(const GemmDesc* __restrict__ desc, int KB,
-                                                          double* __restrict__ ws) {
+// A product with at most 16 CT columns, op(A) rows and op(B) columns
+// contiguous along k (such as the GMRES matrix times a block of vectors),
+// or nb such products whose operands and results lie sA, sB, sC elements
+// apart (one per right-hand side): a block of four wavefronts takes 64 rows
+// of op(A), 16 per wavefront, against all 16 CT columns, over a contiguous
+// range of the K groups (block kb of KB for its rows).  op(A) is read once.
+// Each group's 16 k x 16 CT columns of op(B) are loaded once per block and
+// shared by the four wavefronts through LDS (two buffers, so one barrier
+// per group), where the tiled kernels load them once per 16 x 16 tile.
+// Every wavefront holds the raw operands of two groups in flight.  The
+// partial tiles go to ws in splitk_reduce_kernel<CT>'s layout (the tile of
+// wavefront w of row block p of product c is c T + 4 p + w, T tiles per
+// product); panel_reduce_kernel adds them in block order and stores C.
+template <int CT>
+__global__ void __launch_bounds__(256, CT == 1 ? 4 : 3)
+    zgemm_panel_kernel(const GemmDesc* __restrict__ desc, int KB, double* __restrict__ ws, int64_t sA, int64_t sB) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int slot = lane >> 4, li = lane & 15;
@@ -805,8 +808,11 @@ __global__ void __launch_bounds__(256, 3) zgemm_panel_kernel(const GemmDesc* __r
   d.ldb = uniform64(d.ldb);
   d.opA = __builtin_amdgcn_readfirstlane(d.opA);
   d.opB = __builtin_amdgcn_readfirstlane(d.opB);
-  const int64_t rb = blockIdx.x / KB;
+  const int64_t nrb = (d.M + 63) / 64;
+  const int64_t c = blockIdx.x / (nrb * KB), rb = blockIdx.x / KB % nrb;
   const int kb = (int)(blockIdx.x % KB);
+  d.A += c * sA;
+  d.B += c * sB;
   const int64_t G = (d.K + 15) / 16;
   const int64_t g0 = G * kb / KB, g1 = G * (kb + 1) / KB;  // this block's groups of 16 k
   const int64_t m0 = rb * 64 + 16 * wave;
@@ -820,45 +826,45 @@ __global__ void __launch_bounds__(256, 3) zgemm_panel_kernel(const GemmDesc* __r
 #pragma unroll
   for (int q = 0; q < 4; ++q) pA[q] = d.A + std::min<int64_t>(m0 + 4 * q + slot, d.M - 1) * d.lda + li;
   const int tc = threadIdx.x >> 4, tk = threadIdx.x & 15;
-  const double2* pB[2];
+  const double2* pB[CT];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) pB[h] = d.B + std::min<int64_t>(16 * h + tc, d.N - 1) * d.ldb + tk;
+  for (int h = 0; h < CT; ++h) pB[h] = d.B + std::min<int64_t>(16 * h + tc, d.N - 1) * d.ldb + tk;
   // whole groups (every k inside K) load without conditions, so that the
   // waits of the loop count the loads of the group in flight exactly; the
   // last group of a K that is not a multiple of 16 is taken after the loop
   const int64_t ge = std::min(g1, d.K / 16);
-  auto gload = [&](int64_t g, double2(&ra)[4], double2(&rbv)[2]) {
+  auto gload = [&](int64_t g, double2(&ra)[4], double2(&rbv)[CT]) {
     const int64_t k0 = 16 * g;
 #pragma unroll
     for (int q = 0; q < 4; ++q) ra[q] = ld_global(pA[q] + k0);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) rbv[h] = ld_global(pB[h] + k0);
+    for (int h = 0; h < CT; ++h) rbv[h] = ld_global(pB[h] + k0);
   };
-  __shared__ double2 sa[4][16][17];  // per wavefront: op(A) rows x k
-  __shared__ double2 sb[2][32][17];  // per block, two buffers: op(B) columns x k
+  __shared__ double2 sa[4][16][17];       // per wavefront: op(A) rows x k
+  __shared__ double2 sb[2][16 * CT][17];  // per block, two buffers: op(B) columns x k
   double2(*as)[17] = sa[wave];
-  auto put = [&](const double2(&ra)[4], const double2(&rbv)[2], int buf) {
+  auto put = [&](const double2(&ra)[4], const double2(&rbv)[CT], int buf) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) as[4 * q + slot][li] = make_double2(ra[q].x, sgA * ra[q].y);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) sb[buf][16 * h + tc][tk] = make_double2(rbv[h].x, sgB * rbv[h].y);
+    for (int h = 0; h < CT; ++h) sb[buf][16 * h + tc][tk] = make_double2(rbv[h].x, sgB * rbv[h].y);
   };
-  // 3M products as in zgemm_batched_kernel, two column blocks
-  dbl4 p1[2], p2[2], p3[2];
+  // 3M products as in zgemm_batched_kernel, CT column blocks
+  dbl4 p1[CT], p2[CT], p3[CT];
 #pragma unroll
-  for (int u = 0; u < 2; ++u) p1[u] = p2[u] = p3[u] = dbl4{0, 0, 0, 0};
+  for (int u = 0; u < CT; ++u) p1[u] = p2[u] = p3[u] = dbl4{0, 0, 0, 0};
   auto mma = [&](int buf) {
-    double2 a[4], b[2][4];
+    double2 a[4], b[CT][4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {  // step s takes k = 4 s + slot
       a[s] = as[li][4 * s + slot];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) b[u][s] = sb[buf][16 * u + li][4 * s + slot];
+      for (int u = 0; u < CT; ++u) b[u][s] = sb[buf][16 * u + li][4 * s + slot];
     }
     // the wavefront's next writes of its op(A) rows stay after these reads
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < CT; ++u)
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         p1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s].x, b[u][s].x, p1[u], 0, 0, 0);
@@ -870,7 +876,7 @@ __global__ void __launch_bounds__(256, 3) zgemm_panel_kernel(const GemmDesc* __r
   // wavefront has passed the barrier of the group in between by then
   int last = 1;  // buffer of the last group taken
   if (g0 < ge) {  // uniform over the block
-    double2 ra0[4], rb0[2], ra1[4], rb1[2];
+    double2 ra0[4], rb0[CT], ra1[4], rb1[CT];
     // prefetches past this block's whole groups read its last one again
     gload(g0, ra0, rb0);
     gload(std::min(g0 + 1, ge - 1), ra1, rb1);
@@ -901,20 +907,20 @@ __global__ void __launch_bounds__(256, 3) zgemm_panel_kernel(const GemmDesc* __r
   }
   if (d.K % 16 != 0 && g0 <= G - 1 && G - 1 < g1) {  // the partial last group of K, if this block's
     const int64_t k0 = 16 * ge;
-    double2 ra[4], rbv[2];
+    double2 ra[4], rbv[CT];
 #pragma unroll
     for (int q = 0; q < 4; ++q) ra[q] = ld_global(k0 + li < d.K ? pA[q] + k0 : g_zero2);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) rbv[h] = ld_global(k0 + tk < d.K ? pB[h] + k0 : g_zero2);
+    for (int h = 0; h < CT; ++h) rbv[h] = ld_global(k0 + tk < d.K ? pB[h] + k0 : g_zero2);
     put(ra, rbv, 1 - last);
     __syncthreads();
     mma(1 - last);
   }
-  const int64_t tile = rb * 4 + wave;
-  if (tile >= (d.M + 15) / 16) return;
-  double* o = ws + ((tile * KB + kb) * 64 + lane) * 16;
+  const int64_t nt = (d.M + 15) / 16, tile = rb * 4 + wave;
+  if (tile >= nt) return;
+  double* o = ws + (((c * nt + tile) * KB + kb) * 64 + lane) * 8 * CT;
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+  for (int u = 0; u < CT; ++u)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       o[8 * u + q] = p1[u][q] - p2[u][q];
@@ -922,34 +928,44 @@ __global__ void __launch_bounds__(256, 3) zgemm_panel_kernel(const GemmDesc* __r
     }
 }
 
-// The row-block kernel's partial tiles (splitk_reduce_kernel<2>'s layout),
-// one thread per element of C: the KB parts added in block order, then
-// alpha and the store as in store_tile.  Eight consecutive threads read one
-// lane's 128 bytes of a part.
+// The row-block kernel's partial tiles (splitk_reduce_kernel<CT>'s layout;
+// nb products, results sC elements apart), one thread per element of C:
+// the KB parts added in block order, then alpha and the store as in
+// store_tile.  Consecutive threads read one lane's 64 CT bytes of a part.
+template <int CT>
 __global__ void __launch_bounds__(256) panel_reduce_kernel(const GemmDesc* __restrict__ desc, int64_t total_tiles,
-                                                           int KB, const double* __restrict__ ws) {
+                                                           int KB, const double* __restrict__ ws, int64_t sC) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= total_tiles * 512) return;
-  const int64_t tile = e >> 9;
-  const int lane = (int)(e >> 3) & 63, u = (int)(e >> 2) & 1, q = (int)e & 3;
+  if (e >= total_tiles * 256 * CT) return;
+  const int64_t gt = e / (256 * CT);  // tile over all products
+  const int f = (int)(e % (256 * CT));
+  const int lane = f / (4 * CT), u = f / 4 % CT, q = f % 4;
   const GemmDesc d = desc[0];
-  const int64_t row = tile * 16 + 4 * q + (lane >> 4), col = 16 * u + (lane & 15);
-  const double* r = ws + (tile * KB * 64 + lane) * 16 + 8 * u + q;
+  const int64_t nt = (d.M + 15) / 16, c = gt / nt;
+  const int64_t row = gt % nt * 16 + 4 * q + (lane >> 4), col = 16 * u + (lane & 15);
+  const double* r = ws + (gt * KB * 64 + lane) * 8 * CT + 8 * u + q;
   double xr = 0, xi = 0;
 #pragma unroll 4
   for (int b = 0; b < KB; ++b) {
-    xr += r[(int64_t)b * 64 * 16];
-    xi += r[(int64_t)b * 64 * 16 + 4];
+    xr += r[(int64_t)b * 64 * 8 * CT];
+    xi += r[(int64_t)b * 64 * 8 * CT + 4];
   }
   if (row >= d.M || col >= d.N) return;
   double2 v = make_double2(d.alpha_re * xr - d.alpha_im * xi, d.alpha_re * xi + d.alpha_im * xr);
-  double2* p = d.transC ? d.C + col * d.ldc + row : d.C + row * d.ldc + col;
+  double2* p = (d.transC ? d.C + col * d.ldc + row : d.C + row * d.ldc + col) + c * sC;
   if (d.accumulate) {
     const double2 o = ld_global(p);
     v.x += o.x;
     v.y += o.y;
   }
   *p = v;
+}
+
+// Blocks per 64 rows of the row-block kernel: `per` blocks over the nb
+// products' rows, at most one per group of 16 k.
+static int panel_blocks_per_rows(int64_t M, int64_t K, int64_t nb, int64_t per) {
+  const int64_t rows = nb * ((M + 63) / 64), groups = std::max<int64_t>(1, (K + 15) / 16);
+  return (int)std::max<int64_t>(1, std::min(groups, per / std::max<int64_t>(1, rows)));
 }
 
 // Launch shapes: four tiles per block (one per wavefront), or one tile per
@@ -1004,11 +1020,7 @@ static int cu_count() {
 // the launch, at most one per group of 16 k)
 static int ct_of(int v) { return v == GV_WIDE4_S4 ? 4 : (v == GV_WIDE2_S4 || panel_shape(v)) ? 2 : 1; }
 static int kb_of(int v, int64_t M, int64_t K) {
-  if (panel_shape(v)) {
-    const int64_t rows = (M + 63) / 64, groups = std::max<int64_t>(1, (K + 15) / 16);
-    const int64_t per = (int64_t)(v == GV_PANEL3 ? 3 : 2) * cu_count();
-    return (int)std::max<int64_t>(1, std::min(groups, per / std::max<int64_t>(1, rows)));
-  }
+  if (panel_shape(v)) return panel_blocks_per_rows(M, K, 1, (int64_t)(v == GV_PANEL3 ? 3 : 2) * cu_count());
   return v == GV_SPLIT3_KB2 ? 2 : v == GV_SPLIT2_KB3 ? 3 : 1;
 }
 
@@ -1046,8 +1058,10 @@ static void launch_variant(int v, const GemmDesc* dev, int count, int64_t tiles,
       CBFM_REQUIRE(N <= 32, CBFM_E_ARG, "row-block GEMM with more than 32 columns");
       const int kb = kb_of(v, M, K);
       const int64_t nt = (M + 15) / 16;
-      hipLaunchKernelGGL(zgemm_panel_kernel, dim3((unsigned)((M + 63) / 64 * kb)), dim3(256), 0, s, dev, kb, ws);
-      hipLaunchKernelGGL(panel_reduce_kernel, dim3((unsigned)((nt * 512 + 255) / 256)), dim3(256), 0, s, dev, nt, kb, ws);
+      hipLaunchKernelGGL(zgemm_panel_kernel<2>, dim3((unsigned)((M + 63) / 64 * kb)), dim3(256), 0, s, dev, kb, ws,
+                         (int64_t)0, (int64_t)0);
+      hipLaunchKernelGGL(panel_reduce_kernel<2>, dim3((unsigned)((nt * 512 + 255) / 256)), dim3(256), 0, s, dev, nt, kb,
+                         ws, (int64_t)0);
       break;
     }
     case GV_TILE4:
@@ -1223,6 +1237,38 @@ void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s) {
   launch_descs(dev.as<GemmDesc>(), (int)live.size(), tiles, key.M, key.N, key.K, flops, v, s, ws.as<double>());
   // the descriptor staging buffer is host memory of this frame
   CBFM_HIP(hipStreamSynchronize(s));
+}
+
+// Row-block kernel launches of nb products (see gemm.h): 16 columns per
+// tile up to N = 16, else 32; as many blocks as fit on the chip at once
+// (4 per compute unit with 16 columns, 3 with 32).
+static int panel_ct(int64_t N) { return N <= 16 ? 1 : 2; }
+static int panel_batch_kb(const GemmDesc& d, int64_t nb) {
+  return panel_blocks_per_rows(d.M, d.K, nb, (int64_t)(panel_ct(d.N) == 1 ? 4 : 3) * cu_count());
+}
+
+size_t panel_batch_ws_bytes(const GemmDesc& d, int64_t nb) {
+  const int ct = panel_ct(d.N);
+  return (size_t)nb * ((d.M + 15) / 16) * panel_batch_kb(d, nb) * 64 * 8 * ct * sizeof(double);
+}
+
+void panel_batch(const GemmDesc* dev, const GemmDesc& d, int64_t nb, int64_t sA, int64_t sB, int64_t sC, double* ws,
+                 hipStream_t s) {
+  CBFM_REQUIRE(nb >= 1 && d.M >= 1 && d.N >= 1 && d.K >= 0 && panel_fits(d.N, d.opA, d.opB), CBFM_E_ARG,
+               "row-block GEMM: one to 32 columns, op(A) rows and op(B) columns contiguous along k");
+  CBFM_REQUIRE(ws != nullptr, CBFM_E_ARG, "K-split GEMM without workspace");
+  const int kb = panel_batch_kb(d, nb);
+  const int64_t nt = nb * ((d.M + 15) / 16), blocks = nb * ((d.M + 63) / 64) * kb;
+  if (panel_ct(d.N) == 1) {
+    hipLaunchKernelGGL(zgemm_panel_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, s, dev, kb, ws, sA, sB);
+    hipLaunchKernelGGL(panel_reduce_kernel<1>, dim3((unsigned)((nt * 256 + 255) / 256)), dim3(256), 0, s, dev, nt, kb,
+                       ws, sC);
+  } else {
+    hipLaunchKernelGGL(zgemm_panel_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, s, dev, kb, ws, sA, sB);
+    hipLaunchKernelGGL(panel_reduce_kernel<2>, dim3((unsigned)((nt * 512 + 255) / 256)), dim3(256), 0, s, dev, nt, kb,
+                       ws, sC);
+  }
+  CBFM_HIP(hipGetLastError());
 }
 
 GemmPlan::GemmPlan(const std::vector<std::vector<GemmDesc>>& groups, hipStream_t s, bool tune)

@@ -1714,12 +1714,39 @@ struct SStep {
   int S;
   int64_t n, nrhs, m, M1, HS, cst;
   Scratch C1, C2, G, Rinv, Rt, sig, theta, broken;
+  // the dot passes C = Q^H Z as products of the row-block GEMM, one per
+  // right-hand side: descriptor 2 b + pass for block b (on the host and
+  // the device) and the workspace of their K-split parts
+  std::vector<GemmDesc> dots;
+  std::unique_ptr<Scratch> dots_dev, dots_ws;
   SStep(int S_, int64_t n_, int64_t nrhs_, int64_t m_, hipStream_t s)
       : S(S_), n(n_), nrhs(nrhs_), m(m_), M1(m_ + S_ + 1), HS((m_ + S_) * (m_ + S_ + 1)), cst(m_ + 1),
         C1(nrhs_ * (m_ + 1) * S_ * sizeof(double2), s), C2(nrhs_ * (m_ + 1) * S_ * sizeof(double2), s),
         G(nrhs_ * S_ * S_ * sizeof(double2), s), Rinv(nrhs_ * S_ * S_ * sizeof(double2), s),
         Rt(nrhs_ * S_ * S_ * sizeof(double2), s), sig(nrhs_ * S_ * sizeof(double), s),
         theta(nrhs_ * S_ * sizeof(double2), s), broken(nrhs_ * sizeof(int32_t), s) {}
+  // block b (j = b S) of pass p: C_p[c][l][i] = sum_k conj(q_l[k]) z_i[k]
+  // for l <= j, i < S, right-hand side c (q_l = V + l vstride + c n, the
+  // block's z_i in the basis slots after q_j)
+  void prepare_dots(const double2* V, int64_t vstride, hipStream_t s) {
+    const int64_t nb = m / S;
+    dots.clear();
+    size_t ws = 0;
+    for (int64_t b = 0; b < nb; ++b)
+      for (int p = 0; p < 2; ++p) {
+        const int64_t j = b * S;
+        GemmDesc d = gemm(V, vstride, OP_R, V + (j + 1) * vstride, vstride, OP_T,
+                          (p == 0 ? C1 : C2).as<double2>(), S, j + 1, S, n);
+        dots.push_back(d);
+        ws = std::max(ws, panel_batch_ws_bytes(d, nrhs));
+      }
+    dots_dev.reset(new Scratch(std::max<size_t>(1, dots.size()) * sizeof(GemmDesc), s));
+    if (!dots.empty()) {
+      CBFM_HIP(hipMemcpyAsync(dots_dev->p, dots.data(), dots.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
+      CBFM_HIP(hipStreamSynchronize(s));  // `dots` may be rebuilt while the copy is in flight otherwise
+    }
+    dots_ws.reset(new Scratch(ws, s));
+  }
 };
 
 // Shifts of every right-hand side from the Hessenberg matrix of a plain
@@ -1776,19 +1803,14 @@ static bool run_sstep_cycle(SStep& ss, const GemmPlan& matvec, double2* V, doubl
     }
     // two block Gram-Schmidt passes against q_0..q_j, then Cholesky QR twice
     double2* Z = V + (j + 1) * vstride;
-    const int64_t runs = (j + 1 + 3) / 4;
     const int npu = (int)((n + 127) / 128);
     const double vb = 16.0 * (double)(j + 1) * (double)nrhs * (double)n;  // bytes of q_0..q_j
     for (int pass = 0; pass < 2; ++pass) {
       double2* Cp = pass == 0 ? ss.C1.as<double2>() : ss.C2.as<double2>();
       {
         TimedLaunch tl(T_GMRES_DOTS, s, vb + 16.0 * S * (double)nrhs * (double)n);
-        if (S == 4)
-          hipLaunchKernelGGL((block_dots_kernel<4, false>), dim3((unsigned)(runs * nrhs)), dim3(256), 0, s, V, vstride, n, Z,
-                             vstride, n, n, j + 1, Cp, ss.cst * S, gs);
-        else
-          hipLaunchKernelGGL((block_dots_kernel<8, false>), dim3((unsigned)(runs * nrhs)), dim3(256), 0, s, V, vstride, n, Z,
-                             vstride, n, n, j + 1, Cp, ss.cst * S, gs);
+        const size_t di = (size_t)(2 * b + pass);
+        panel_batch(ss.dots_dev->as<GemmDesc>() + di, ss.dots[di], nrhs, n, n, ss.cst * S, ss.dots_ws->as<double>(), s);
       }
       {
         TimedLaunch tl(T_GMRES_UPDATE, s, vb + 32.0 * S * (double)nrhs * (double)n);
@@ -2037,6 +2059,7 @@ GmresResult gmres_run(KrylovOp& op, int64_t n, int64_t nrhs, const double2* b, d
       CBFM_HIP(hipMemcpyAsync(its1.data(), gs.its, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
       CBFM_HIP(hipStreamSynchronize(s));
       sst.reset(new SStep(S, n, nrhs, ms, s));
+      sst->prepare_dots(V.as<double2>(), vstride, s);
       sstep_shifts(*sst, g1, m1, its1, s);
       shifts_ready = true;
     } else if (sstep_on) {
