@@ -13,11 +13,13 @@ Workload (default): dielectric cylinder r 1, h 6 wavelengths, eps_r 3,
 19,968 triangles (29,952 RWGs, 59,904 unknowns), 96 cells, 32 monostatic
 incidences, CBFs from the 144 Table-I plane waves, delta_SVD 1e-3, regular
 pairs filled in FP32 (near pairs, CBF build, projection and solve in FP64),
-GMRES in s-step cycles of blocks of 8 iterations (--sstep 0: plain cycles;
-the other workloads default to plain cycles, which measured as fast there).
-The FP64 form of the same step runs beside it, then the precision forms,
-the IPCBF leg (the paper's cylinder conditions), the batching and serving
-legs and the CPU oracle baseline (see --help for the switches).
+block GMRES: the 32 incidences share one Krylov space (--block 0: one space
+per incidence, in s-step cycles of blocks of 8 iterations, --sstep 0 plain
+cycles; the other workloads default to one space per incidence).
+The FP64 form of the same step runs beside it, the same step with one
+Krylov space per incidence, then the precision forms, the IPCBF leg (the
+paper's cylinder conditions), the batching and serving legs and the CPU
+oracle baseline (see --help for the switches).
 
 value = logical triangle pair-evaluations (N_tri^2 per step) per second of
 the whole step.  After the timed steps one more step runs with the library's
@@ -92,9 +94,9 @@ FAMILY_SOURCES = {
     # (the dot pass runs on the row-block GEMM kernel with 16-column tiles)
     "gmres_block_dots": ("zgemm_panel_kernel<1>", "paper_2111_11058_amd/csrc/gemm.hip"),
     "gmres_block_update": ("block_update_kernel<8>", "paper_2111_11058_amd/csrc/solve.hip"),
-    # the GMRES matrix-vector product: the launch shape of the complex GEMM
-    # (tiled or row-block kernel) with the most dispatches
-    "gmres_matvec": ("zgemm_", "paper_2111_11058_amd/csrc/gemm.hip"),
+    # the GMRES matrix-vector product: the row-block kernel's launch shape
+    # with the most dispatches
+    "gmres_matvec": ("zgemm_panel_kernel<2>", "paper_2111_11058_amd/csrc/gemm.hip"),
 }
 
 
@@ -315,7 +317,7 @@ SSTEP_KERNELS = {"gmres_dots": ("zgemm_panel_kernel<1>", "gmres_block_dots"),
                  "gmres_update": ("block_update_kernel", "gmres_block_update")}
 
 
-def read_families(cbfm, traffic, phase, sstep=0):
+def read_families(cbfm, traffic, phase, sstep=0, block=0):
     """Achieved rate of every timed family since the last timer_enable."""
     rows = {}
     for fam, (kernel, bound, peak, unit, scale) in FAMILIES.items():
@@ -338,6 +340,21 @@ def read_families(cbfm, traffic, phase, sstep=0):
             row["frac_of_unpacked_fp32"] = ach / PEAK_FP32_VALU_UNPACKED
         rows[fam] = row
     panel = rows.pop("gemm_panel", None)
+    if block and phase == "solve":
+        # block GMRES: the matrix-vector products run on the row-block kernel
+        # (its timer family); "gemm" also holds the block Gram-Schmidt updates,
+        # the operator's formation and the residuals
+        if "gemm" in rows:
+            rows["gemm_all"] = dict(rows.pop("gemm"), kernel="zgemm_batched_kernel and zgemm_panel_kernel",
+                                    traffic=None)
+        if panel:
+            rows["gemm"] = dict(panel, kernel="zgemm_panel_kernel<2>", traffic=traffic.get("gmres_matvec"))
+        if "gmres_dots" in rows:
+            rows["gmres_dots"].update(kernel="zgemm_panel_kernel<2> (block Gram-Schmidt dot pass)", traffic=None)
+        if "gmres_update" in rows:
+            rows["gmres_update"].update(kernel="zgemm_batched_kernel (block Gram-Schmidt update pass)",
+                                        traffic=None)
+        return rows
     if panel and "gemm" in rows:
         g = rows["gemm"]
         g["kernel"] = ("zgemm_panel_kernel" if panel["launches"] == g["launches"] else
@@ -345,7 +362,7 @@ def read_families(cbfm, traffic, phase, sstep=0):
     return rows
 
 
-def rooflines(cbfm, run_phases, traffic, prefix="", sstep=0):
+def rooflines(cbfm, run_phases, traffic, prefix="", sstep=0, block=0):
     """One step with the timers on, the projection and the solve timed
     apart (run_phases calls project() and solve() in turn, each given a
     callback that switches the timers on for that phase)."""
@@ -353,20 +370,20 @@ def rooflines(cbfm, run_phases, traffic, prefix="", sstep=0):
     names = {"project": {"fill_regular": "fill_regular_fp64", "fill_regular_f32": "fill_regular_f32",
                          "gemm": "projection_gemm_fp64", "xgemm": "projection_gemm_xf32"},
              "solve": {"gemm": "gmres_matvec_gemm", "xgemm": "gmres_matvec_xgemm", "gmres_dots": "gmres_dots",
-                       "gmres_update": "gmres_update"}}
+                       "gmres_update": "gmres_update", "gemm_all": "solve_gemm_all"}}
 
     def timed(phase):
         cbfm.timer_enable(list(cbfm.TIMERS))
 
         def done():
-            for fam, row in read_families(cbfm, traffic, phase, sstep).items():
+            for fam, row in read_families(cbfm, traffic, phase, sstep, block).items():
                 if fam in names[phase]:
                     rows[prefix + names[phase][fam]] = row
             cbfm.timer_enable(None)
         return done
 
     run_phases(timed)
-    dom = max(rows, key=lambda k: rows[k]["total_ms"])
+    dom = max((k for k in rows if k != prefix + "solve_gemm_all"), key=lambda k: rows[k]["total_ms"])
     return dict(rows[dom], family=dom), rows
 
 
@@ -754,6 +771,9 @@ def main():
                     help="GMRES of the main step and the FP64 leg: s-step cycles of blocks of this many "
                          "iterations, or 0 for plain cycles (DCGS2); default 8 for cylinder19968 and cube1728 "
                          "(long solves of many incidences, where it measured faster), else 0")
+    ap.add_argument("--block", type=int, default=None,
+                    help="block GMRES (1: groups of up to 32 right-hand sides sharing one Krylov space; 0: off; "
+                         "default 1 for cylinder19968, 0 otherwise)")
     ap.add_argument("--basis-fp32", action="store_true",
                     help="time the compressed-basis form (double arithmetic, Krylov basis stored in float) as the "
                          "main step")
@@ -848,7 +868,7 @@ def main():
     state = {}
     traffic = measured_traffic(args.workload)
 
-    def step(precision, inner_fp32=False, timed=None, basis_fp32=False, sstep=0):
+    def step(precision, inner_fp32=False, timed=None, basis_fp32=False, sstep=0, block=False):
         cb = cbfm.build_cbf(mesh, med, w.gen, w.delta_svd, max_L=w.extra.get("max_L", 0))
         n = cb.n_cbf
         Zr = state.get(n)
@@ -867,24 +887,31 @@ def main():
         done = timed("solve") if timed else None
         t2 = time.perf_counter()
         restarts = inner_fp32 or basis_fp32 or sstep > 0
-        out = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, max_iter=(3 if restarts else 1) * max(n, 3000),
-                         restart=m, inner_fp32=inner_fp32, basis_fp32=basis_fp32, sstep=sstep, **solver)
+        if block:
+            # block iterations: a cycle holds the whole space the library allows
+            out = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, max_iter=3 * n, restart=n, block=True,
+                             **solver)
+        else:
+            out = cbfm.solve(mesh, med, cb, Zr, w.inc, use_cmp=True, max_iter=(3 if restarts else 1) * max(n, 3000),
+                             restart=m, inner_fp32=inner_fp32, basis_fp32=basis_fp32, sstep=sstep, **solver)
         t3 = time.perf_counter()
         if done:
             done()
         return cb, out, t1 - t0, t3 - t2
 
     B32 = args.basis_fp32
+    BLK = 0 if B32 else (args.block if args.block is not None else (1 if args.workload == "cylinder19968" else 0))
     sst_default = 8 if args.workload in ("cylinder19968", "cube1728") else 0
-    SST = 0 if B32 else (sst_default if args.sstep is None else args.sstep)  # (the compressed basis: plain cycles)
+    # (the compressed basis and block GMRES: no s-step cycles)
+    SST = 0 if B32 or BLK else (sst_default if args.sstep is None else args.sstep)
     for i in range(args.warmup):
         log(f"warmup {i}")
-        step(PREC, basis_fp32=B32, sstep=SST)
+        step(PREC, basis_fp32=B32, sstep=SST, block=BLK)
     torch.cuda.synchronize()
     proj_t, solve_t, iters = [], [], []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        cb, out, tp, ts = step(PREC, basis_fp32=B32, sstep=SST)
+        cb, out, tp, ts = step(PREC, basis_fp32=B32, sstep=SST, block=BLK)
         proj_t.append(tp)
         solve_t.append(ts)
         iters.append(out["iters"])
@@ -893,8 +920,8 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     nt = w.nt
-    roof, roofs = rooflines(cbfm, lambda timed: step(PREC, timed=timed, basis_fp32=B32, sstep=SST), traffic,
-                            sstep=SST)
+    roof, roofs = rooflines(cbfm, lambda timed: step(PREC, timed=timed, basis_fp32=B32, sstep=SST, block=BLK),
+                            traffic, sstep=SST, block=BLK)
     nrhs = len(w.inc)
     lat = np.array(solve_t)
     result = {
@@ -913,14 +940,16 @@ def main():
         "config": {"workload": f"{w.name}: {nt} triangles, {3 * nt // 2} RWGs, {3 * nt} unknowns, "
                                f"{w.nblocks} cells, {nrhs} incidences, {len(w.gen)} generating waves",
                    "fill_precision": prec_name, "krylov_basis": "fp32" if B32 else "fp64",
-                   "gmres": f"s-step, blocks of {SST}" if SST else "plain (DCGS2)",
+                   "gmres": ("block (groups of up to 32 right-hand sides, one Krylov space each)" if BLK else
+                             f"s-step, blocks of {SST}" if SST else "plain (DCGS2)"),
                    "n_cbf": int(cb.n_cbf), "solver": solver},
         "fill_projection_pair_evals_per_s": nt * nt / float(np.median(proj_t)),
         "solves_per_s": nrhs * args.steps / float(lat.sum()),
         "solves_per_s_end_to_end": nrhs * args.steps / total,
         "solve_batch_latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                                    "p99": float(np.percentile(lat, 99) * 1e3)},
-        "gmres_iterations": {"mean": float(np.mean(iters)), "max": int(np.max(iters))},
+        "gmres_iterations": {"mean": float(np.mean(iters)), "max": int(np.max(iters)),
+                             "counts": "block iterations" if BLK else "iterations"},
         "gmres_relres_max": float(out["relres"].max()),
         "roofline": roof,
         "roofline_kernels": roofs,
@@ -930,17 +959,18 @@ def main():
     if PREC != cbfm.FP64 or args.fp64_steps:
         # the plain FP64 form of the same step beside the timed one
         k = args.fp64_steps or max(1, args.steps // 2)
-        step(cbfm.FP64, sstep=SST)
+        step(cbfm.FP64, sstep=SST, block=BLK)
         tp_l, ts_l = [], []
         torch.cuda.synchronize()
         tt = time.perf_counter()
         for _ in range(k):
-            _, o64, tp, ts = step(cbfm.FP64, sstep=SST)
+            _, o64, tp, ts = step(cbfm.FP64, sstep=SST, block=BLK)
             tp_l.append(tp)
             ts_l.append(ts)
         torch.cuda.synchronize()
         tt = time.perf_counter() - tt
-        _, r64 = rooflines(cbfm, lambda timed: step(cbfm.FP64, timed=timed, sstep=SST), traffic, sstep=SST)
+        _, r64 = rooflines(cbfm, lambda timed: step(cbfm.FP64, timed=timed, sstep=SST, block=BLK), traffic,
+                           sstep=SST, block=BLK)
         rcs_ref = o64["rcs"]
         result["fp64_leg"] = {"steps": k, "value": nt * nt * k / tt, "ms_per_step": tt / k * 1e3,
                               "fill_projection_pair_evals_per_s": nt * nt / float(np.median(tp_l)),
@@ -949,6 +979,20 @@ def main():
                               "rcs_max_rel_err_of_timed_step": float(np.max(np.abs(out["rcs"] - rcs_ref) / rcs_ref)),
                               "roofline_kernels": r64}
         log(f"fp64 leg: {result['fp64_leg']}")
+    if BLK:
+        # the same step with every right-hand side in its own Krylov space
+        # (s-step cycles of 8, the form the block solve replaces)
+        step(PREC, sstep=8)
+        torch.cuda.synchronize()
+        tt = time.perf_counter()
+        _, o1, tp, ts = step(PREC, sstep=8)
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - tt
+        result["per_rhs_leg"] = {"gmres": "s-step, blocks of 8, one Krylov space per right-hand side",
+                                 "ms_per_step": tt * 1e3, "solve_ms": ts * 1e3, "value": nt * nt / tt,
+                                 "gmres_iterations_max": int(o1["iters"].max()), "status": o1["status"],
+                                 "rcs_max_rel_diff_vs_block": float(np.max(np.abs(o1["rcs"] - out["rcs"]) / o1["rcs"]))}
+        log(f"per-rhs leg: {result['per_rhs_leg']}")
     if (args.workload == "cylinder19968" and not args.no_ipcbf) or args.ipcbf:
         # the cylinder: the paper's in-plane generating waves (its incidences
         # lie in that plane); otherwise the Table-I waves of the primary CBFs

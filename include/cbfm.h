@@ -130,7 +130,7 @@ cbfm_status cbfm_set_allocator(cbfm_alloc_fn alloc, cbfm_release_fn release);
 cbfm_status cbfm_memory_stats(int64_t* held, int64_t* peak, int64_t* cached);
 
 /* ABI version (incremented on incompatible change). */
-int32_t cbfm_version(void);  /* 5: cbfm_solver_params gained sstep (4: basis_fp32; 3: cbfm_request
+int32_t cbfm_version(void);  /* 6: cbfm_solver_params gained block (5: sstep; 4: basis_fp32; 3: cbfm_request
                                 gained inner_fp32; 2: cbfm_solver_params gained cmp_mode,
                                 cmp_inner_tol) */
 
@@ -459,6 +459,30 @@ typedef struct {
                       /* inner_fp32, basis_fp32, use_graph or             */
                       /* CBFM_CMP_INNER_GMRES (CBFM_E_ARG); cbfm_solve    */
                       /* only.                                            */
+  int32_t block;      /* block GMRES: 2..32 -- the right-hand sides, in    */
+                      /* groups of that many, share one Krylov space      */
+                      /* built from the block of their residuals; 1 --    */
+                      /* groups of up to 32, fewer when N_CBF / 33 is     */
+                      /* smaller (so that a cycle holds 32 block          */
+                      /* iterations: shorter restarted cycles stagnate);  */
+                      /* 0 -- off.  Each iterate                          */
+                      /* minimises its own residual over all of it (the   */
+                      /* outer equation of Sec. III-C for many            */
+                      /* incidences at once).  Each block iteration       */
+                      /* applies the operator to the group's last basis   */
+                      /* block; two block Gram-Schmidt passes, each       */
+                      /* followed by a Cholesky QR of the block on a Gram */
+                      /* matrix summed and factored in double-double with */
+                      /* diagonal pivoting (dependent directions, below   */
+                      /* 1e-13 of the block's largest, are replaced by    */
+                      /* random vectors outside the Arnoldi relation);    */
+                      /* the block Hessenberg matrix reduced by           */
+                      /* Householder QR as it grows.  restart and         */
+                      /* max_iter count block iterations (a cycle holds   */
+                      /* at most N_CBF / group - 1) and iters_host        */
+                      /* returns them.  Not with inner_fp32, basis_fp32,  */
+                      /* use_graph, sstep or CBFM_CMP_INNER_GMRES         */
+                      /* (CBFM_E_ARG); cbfm_solve only.                   */
 } cbfm_solver_params;
 
 cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, const void* Zr_dev,

@@ -147,6 +147,30 @@ def gmres(matvec, b, tol=1e-12, restart=100, max_iter=1000):
     return x, it, hist
 
 
+def block_krylov_minimiser(matvec, B, J):
+    """Block GMRES after J block iterations from x0 = 0, for the columns of
+    B (n x p, full column rank) at once: every column's iterate minimises
+    its own residual ||b_c - A x|| over the block Krylov space
+    K_J(A, B) = span{B, A B, ..., A^(J-1) B}, the outer equation of Sec.
+    III-C solved for many incidences together.  The space is spanned by
+    block Arnoldi (each new block A Q_j projected twice against the earlier
+    blocks, then a Householder QR); the minimiser is the least-squares
+    solution over that basis.  matvec maps an n x k block to A times it."""
+    B = np.asarray(B, dtype=np.complex128)
+    Q, _ = np.linalg.qr(B)
+    blocks = [Q]
+    for _ in range(1, J):
+        Vm = np.hstack(blocks)
+        W = matvec(blocks[-1])
+        for _ in range(2):
+            W = W - Vm @ (Vm.conj().T @ W)
+        Q, _ = np.linalg.qr(W)
+        blocks.append(Q)
+    K = np.hstack(blocks)
+    Y = np.linalg.lstsq(matvec(K), B, rcond=None)[0]
+    return K @ Y
+
+
 def cmp_inner(Gcbf, y, tol, restart=None, max_iter=None):
     """The paper's inexact (G^CBF)^{-1} (Sec. III-C, the paragraph on D^CBF):
     GMRES on G^CBF D z = y with the diagonal preconditioner

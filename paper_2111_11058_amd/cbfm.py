@@ -51,7 +51,7 @@ class SolverParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32),
                 ("use_cmp", C.c_int32), ("inner_fp32", C.c_int32), ("inner_tol", C.c_double),
                 ("use_graph", C.c_int32), ("cmp_mode", C.c_int32), ("cmp_inner_tol", C.c_double),
-                ("basis_fp32", C.c_int32), ("sstep", C.c_int32)]
+                ("basis_fp32", C.c_int32), ("sstep", C.c_int32), ("block", C.c_int32)]
 
 
 class IpcbfParams(C.Structure):
@@ -521,13 +521,17 @@ def solve_matfree(mom: MomOperator, cbf: CBF, inc, tol=1e-6, max_iter=1000, rest
 
 def solve(mesh: Mesh, medium: Medium, cbf: CBF, Zr, inc, tol=1e-6, max_iter=1000, restart=100,
           use_cmp=True, j_out=None, dirs=None, ldz=None, stream=None, raise_noconv=False, inner_fp32=False,
-          inner_tol=0.0, use_graph=False, cmp_mode=CMP_EXACT, cmp_inner_tol=0.0, basis_fp32=False, sstep=0):
+          inner_tol=0.0, use_graph=False, cmp_mode=CMP_EXACT, cmp_inner_tol=0.0, basis_fp32=False, sstep=0,
+          block=False):
     """cbfm_solve.  Returns dict(iters, relres, rcs, status).  inner_fp32
     selects the mixed form (float Krylov cycles refined against the double
     residual, each cycle reducing it by inner_tol); basis_fp32 the
     compressed-basis form (double cycles with the basis stored in float,
     restarted the same way); sstep (4 or 8) the s-step cycles of blocks of
-    that many iterations; use_graph replays the Arnoldi iterations from a
+    that many iterations; block the block GMRES (True or 1: one Krylov space
+    per group of up to 32 right-hand sides, sized for cycles of at least 32
+    block iterations; 2..32: groups of that many; max_iter, restart and the
+    returned iters count block iterations); use_graph replays the Arnoldi iterations from a
     captured HIP graph."""
     import torch
     inc, pi = _host(inc, np.float64)
@@ -549,7 +553,7 @@ def solve(mesh: Mesh, medium: Medium, cbf: CBF, Zr, inc, tol=1e-6, max_iter=1000
         rcs = np.zeros(nrhs)
     prm = SolverParams(float(tol), int(max_iter), int(restart), int(use_cmp), int(bool(inner_fp32)),
                        float(inner_tol), int(bool(use_graph)), int(cmp_mode), float(cmp_inner_tol),
-                       int(bool(basis_fp32)), int(sstep))
+                       int(bool(basis_fp32)), int(sstep), int(block))
     code = lib().cbfm_solve(mesh.handle, C.byref(medium), cbf.handle, pz, ldz, pi, nrhs, C.byref(prm), pj,
                             iters.ctypes.data_as(C.c_void_p), relres.ctypes.data_as(C.c_void_p), pd, nd,
                             rcs.ctypes.data_as(C.c_void_p), _stream(stream))

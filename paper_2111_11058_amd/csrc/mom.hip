@@ -455,7 +455,7 @@ cbfm_status cbfm_mom_solve(cbfm_mom o, const double* inc, int64_t nrhs, const cb
     CBFM_REQUIRE(o && inc && prm, CBFM_E_ARG, "null argument");
     CBFM_REQUIRE(nrhs >= 1 && nrhs <= 65535, CBFM_E_ARG, "nrhs out of range");
     CBFM_REQUIRE(prm->tol > 0 && prm->max_iter >= 1 && prm->restart >= 1, CBFM_E_ARG, "bad solver parameters");
-    CBFM_REQUIRE(prm->sstep == 0, CBFM_E_ARG, "s-step cycles are a cbfm_solve form");
+    CBFM_REQUIRE(prm->sstep == 0 && prm->block == 0, CBFM_E_ARG, "s-step and block cycles are cbfm_solve forms");
     CBFM_REQUIRE(dirs == nullptr || ndir >= 1, CBFM_E_ARG, "ndir must be >= 1 with dirs");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const cbfm_mesh_s* m = o->mesh;
@@ -516,7 +516,8 @@ cbfm_status cbfm_solve_matfree(cbfm_mom o, cbfm_cbf c, const double* inc, int64_
     CBFM_REQUIRE(prm->tol > 0 && prm->max_iter >= 1 && prm->restart >= 1, CBFM_E_ARG, "bad solver parameters");
     CBFM_REQUIRE(prm->use_cmp == 0 || prm->use_cmp == 1, CBFM_E_ARG, "use_cmp must be 0 or 1");
     CBFM_REQUIRE(prm->cmp_mode == CBFM_CMP_EXACT, CBFM_E_ARG, "the matrix-free operator takes the exact CMP");
-    CBFM_REQUIRE(prm->inner_fp32 == 0 && prm->use_graph == 0 && prm->basis_fp32 == 0 && prm->sstep == 0, CBFM_E_ARG,
+    CBFM_REQUIRE(prm->inner_fp32 == 0 && prm->use_graph == 0 && prm->basis_fp32 == 0 && prm->sstep == 0 &&
+                     prm->block == 0, CBFM_E_ARG,
                  "the matrix-free operator runs double Krylov cycles with a double basis and without graphs");
     CBFM_REQUIRE(dirs == nullptr || ndir >= 1, CBFM_E_ARG, "ndir must be >= 1 with dirs");
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -49,6 +49,48 @@ struct GmresSpec {
                            // operator); each cycle stops at a reduction of inner_tol as in f32
   int sstep = 0;           // 4 or 8: s-step cycles of blocks of that many iterations (dense double
                            // operator, double basis, no graphs); 0: plain cycles
+  int block = 0;           // block GMRES: the right-hand sides share one Krylov space per group
+                           // (1: groups of up to 32 sized for cycles of 32 block iterations or more;
+                           // 2..32: groups of that many); dense double operator, double basis, no
+                           // graphs; restart and max_iter then count block iterations
+};
+
+// Device flags read back through pinned host memory: post() queues a copy
+// and an event, wait() blocks on the last posted copy; sync_read() copies and
+// waits at once.
+struct PinnedFlags {
+  int64_t n;
+  int32_t* host = nullptr;
+  hipEvent_t ev = nullptr;
+  bool posted = false;
+  explicit PinnedFlags(int64_t count) : n(count) {
+    CBFM_HIP(hipHostMalloc((void**)&host, n * sizeof(int32_t), hipHostMallocDefault));
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipHostFree(host);
+      throw Error{CBFM_E_HIP, "hipEventCreate failed"};
+    }
+  }
+  ~PinnedFlags() {
+    if (posted) (void)hipEventSynchronize(ev);
+    (void)hipEventDestroy(ev);
+    (void)hipHostFree(host);
+  }
+  PinnedFlags(const PinnedFlags&) = delete;
+  PinnedFlags& operator=(const PinnedFlags&) = delete;
+  void post(const int32_t* dev, hipStream_t s) {
+    CBFM_HIP(hipMemcpyAsync(host, dev, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    CBFM_HIP(hipEventRecord(ev, s));
+    posted = true;
+  }
+  const int32_t* wait() {
+    if (posted) CBFM_HIP(hipEventSynchronize(ev));
+    posted = false;
+    return host;
+  }
+  const int32_t* sync_read(const int32_t* dev, hipStream_t s) {
+    post(dev, s);
+    return wait();
+  }
 };
 
 struct GmresResult {
@@ -60,6 +102,11 @@ struct GmresResult {
 // Right-hand sides b and iterate x: nrhs x n double, device (x starts at 0).
 GmresResult gmres_run(KrylovOp& op, int64_t n, int64_t nrhs, const double2* b, double2* x, const GmresSpec& p,
                       hipStream_t s);
+
+// Block GMRES (bgmres.hip) on a dense double operator: b, x as gmres_run;
+// the iteration counts returned are block iterations.
+GmresResult block_gmres_run(const double2* A, int64_t lda, int64_t n, int64_t nrhs, const double2* b, double2* x,
+                            const GmresSpec& p, hipStream_t s);
 
 // Dense row-major operator: the double matrix (lda), the float one (n), or
 // both (a float-only operator forms its residuals in float too).

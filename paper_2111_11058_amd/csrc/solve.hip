@@ -951,44 +951,6 @@ __global__ void __launch_bounds__(256) farfield_kernel(FarArgs fa, const double2
   }
 }
 
-// Device flags read back through pinned host memory: post() queues a copy
-// and an event, wait() blocks on the last posted copy; sync_read() copies and
-// waits at once.
-struct PinnedFlags {
-  int64_t n;
-  int32_t* host = nullptr;
-  hipEvent_t ev = nullptr;
-  bool posted = false;
-  explicit PinnedFlags(int64_t count) : n(count) {
-    CBFM_HIP(hipHostMalloc((void**)&host, n * sizeof(int32_t), hipHostMallocDefault));
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-      (void)hipHostFree(host);
-      throw Error{CBFM_E_HIP, "hipEventCreate failed"};
-    }
-  }
-  ~PinnedFlags() {
-    if (posted) (void)hipEventSynchronize(ev);
-    (void)hipEventDestroy(ev);
-    (void)hipHostFree(host);
-  }
-  PinnedFlags(const PinnedFlags&) = delete;
-  PinnedFlags& operator=(const PinnedFlags&) = delete;
-  void post(const int32_t* dev, hipStream_t s) {
-    CBFM_HIP(hipMemcpyAsync(host, dev, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    CBFM_HIP(hipEventRecord(ev, s));
-    posted = true;
-  }
-  const int32_t* wait() {
-    if (posted) CBFM_HIP(hipEventSynchronize(ev));
-    posted = false;
-    return host;
-  }
-  const int32_t* sync_read(const int32_t* dev, hipStream_t s) {
-    post(dev, s);
-    return wait();
-  }
-};
-
 static dim3 grid2(int64_t n, int64_t m) { return dim3((unsigned)((n + 255) / 256), (unsigned)m); }
 
 // u = A w for row-stored vectors w (nrhs x n): u^T = A w^T.
@@ -1904,6 +1866,11 @@ GmresResult gmres_run(KrylovOp& op, int64_t n, int64_t nrhs, const double2* b, d
   CBFM_REQUIRE(S == 0 || ((S == 4 || S == 8) && A64 != nullptr && !f32 && !b32 && !p.graph && op.xbasis() == nullptr),
                CBFM_E_ARG, "s-step cycles take blocks of 4 or 8 with a dense double operator, a double basis, no graphs");
   CBFM_REQUIRE(p.tol > 0 && p.max_iter >= 1 && p.restart >= 1, CBFM_E_ARG, "bad solver parameters");
+  if (p.block) {
+    CBFM_REQUIRE(A64 != nullptr && !f32 && !b32 && S == 0 && !p.graph && op.xbasis() == nullptr, CBFM_E_ARG,
+                 "block GMRES takes a dense double operator, a double basis, no s-step cycles and no graphs");
+    return block_gmres_run(A64, lda64, n, nrhs, b, x, p, s);
+  }
   const int64_t mres = std::min<int64_t>(p.restart, std::max<int64_t>(p.max_iter, 1));
   // The plain form keeps the Krylov basis in double; the mixed form keeps it
   // and the operator in float and refines: every cycle starts from the
@@ -2247,6 +2214,9 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
     CBFM_REQUIRE(prm->sstep == 0 || ((prm->sstep == 4 || prm->sstep == 8) && !flexible && prm->inner_fp32 == 0 &&
                                      prm->basis_fp32 == 0 && prm->use_graph == 0),
                  CBFM_E_ARG, "sstep is 0, 4 or 8, with double cycles, the exact CMP and no graphs");
+    CBFM_REQUIRE(prm->block == 0 || (prm->block >= 1 && prm->block <= 32 && !flexible && prm->inner_fp32 == 0 && prm->basis_fp32 == 0 &&
+                                     prm->use_graph == 0 && prm->sstep == 0),
+                 CBFM_E_ARG, "block is 0 to 32, with double cycles, the exact CMP, no graphs and no s-step cycles");
     CBFM_REQUIRE(prm->inner_tol >= 0 && prm->inner_tol < 1, CBFM_E_ARG, "inner_tol outside [0, 1)");
     CBFM_REQUIRE(!flexible || (prm->cmp_inner_tol >= 0 && prm->cmp_inner_tol < 1), CBFM_E_ARG,
                  "cmp_inner_tol outside [0, 1)");
@@ -2306,6 +2276,7 @@ extern "C" cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf 
     sp.graph = prm->use_graph != 0;
     sp.basis32 = prm->basis_fp32 != 0;
     sp.sstep = prm->sstep;
+    sp.block = prm->block;
     Scratch x(nrhs * n * sizeof(double2), s);
     DenseOp dop(Aop, lda, nullptr, 0);
     FlexCmpOp fop(Zr, ldz, c, prm->cmp_inner_tol > 0 ? prm->cmp_inner_tol : 1e-5, n);

@@ -487,6 +487,102 @@ def test_sstep_solve(torch_cuda):
         cbfm.solve(mesh, med, cbf, Zr, inc, sstep=8, inner_fp32=True, raise_noconv=True)
 
 
+def test_block_solve(torch_cuda):
+    """Block GMRES (the right-hand sides of a group share one Krylov space;
+    two block Gram-Schmidt passes with Cholesky QR on a double-double Gram
+    matrix, pivoted, dependent directions replaced by random vectors) solves
+    the oracle's reduced system.  N_CBF is 200 here, so the automatic groups
+    hold 6 right-hand sides (cycles of 32 block iterations).  At tol 1e-12
+    the currents match LU for 40 incidences: 30 plane waves one degree apart
+    (numerically dependent: their right-hand sides have rank about 12 at
+    1e-13), one repeated exactly, 8 random; for 32 of them; for one; and
+    for one group of 6 in cycles of 24 block iterations (restarted from the
+    true residual;
+    cycles of 8 stagnate on this operator).
+    At tol 1e-6 the true residual meets the tolerance in fewer block
+    iterations than plain GMRES needs iterations.  An iteration limit stops
+    the solve there, unconverged."""
+    from oracle import excitation
+    from synth.configs import random_incidences, sph_dir
+    O = _oracle_cbf("cyl_small")
+    P = O["P"]
+    w, m = P["w"], P["m"]
+    cbfm, mesh, med, cbf = _gpu_handles(w, O)
+    n = cbf.n_cbf
+    Zr = torch_cuda.zeros((n, n), dtype=torch_cuda.complex128, device="cuda")
+    cbfm.project(mesh, med, cbf, Zr, cbfm.FP64)
+    th = np.deg2rad(np.arange(30.0))
+    r, t, _ = sph_dir(th, np.zeros_like(th))
+    inc = np.concatenate([np.concatenate([-r, t], axis=1), w.inc[:1], w.inc[:1], random_incidences(8, 29)])
+    assert len(inc) == 40
+    vr = O["CJM"].conj().T @ excitation.rhs(m, inc, w.k0, w.eta0)
+    sv = np.linalg.svd(vr[:, :30] / np.linalg.norm(vr[:, :30], axis=0), compute_uv=False)
+    print("right-hand sides of the 30 plane waves: rank at 1e-13", int((sv > 1e-13 * sv[0]).sum()))
+    jref = O["CMJ"] @ np.linalg.solve(O["Zr"], vr)
+    for sel, restart in ((slice(None), n), (slice(0, 32), n), (slice(0, 1), n), (slice(0, 6), 24)):
+        ii = np.ascontiguousarray(inc[sel])
+        jt = torch_cuda.zeros((len(ii), 2 * m.ne), dtype=torch_cuda.complex128, device="cuda")
+        out = cbfm.solve(mesh, med, cbf, Zr, ii, tol=1e-12, max_iter=2000, restart=restart, j_out=jt, block=True)
+        got = jt.cpu().numpy().T
+        e = _rel(got, jref[:, sel])
+        emax = np.max(np.abs(got - jref[:, sel])) / np.max(np.abs(jref[:, sel]))
+        print("block", len(ii), "restart", restart, "iters", out["iters"].max(), "relres", out["relres"].max(),
+              "current err", e, emax, flush=True)
+        assert out["status"] == "OK" and np.all(out["relres"] <= 1e-12) and e < 1e-9 and emax < 1e-9, (len(ii), restart)
+        if len(ii) >= 32:
+            assert np.allclose(got[:, 30], got[:, 31], rtol=0, atol=1e-12 * np.abs(got[:, 30]).max())
+    ii = np.ascontiguousarray(inc[:32])
+    plain = cbfm.solve(mesh, med, cbf, Zr, ii, tol=1e-6, max_iter=6 * n, restart=n + 10)
+    b = cbfm.solve(mesh, med, cbf, Zr, ii, tol=1e-6, max_iter=400, restart=n, block=True)
+    print("tol 1e-6: plain iterations", plain["iters"].max(), "block iterations", b["iters"].max(), b["relres"].max())
+    assert b["status"] == "OK" and np.all(b["relres"] <= 1e-6) and b["iters"].max() < plain["iters"].max()
+    c = cbfm.solve(mesh, med, cbf, Zr, ii, tol=1e-30, max_iter=3, restart=n, block=True)
+    print("iteration limit 3:", c["iters"], c["status"], c["relres"].max())
+    assert c["status"] == "E_NOCONV" and np.all(c["iters"] == 3) and np.all(c["relres"] < 1)
+    with pytest.raises(RuntimeError):
+        cbfm.solve(mesh, med, cbf, Zr, ii, block=True, sstep=4, raise_noconv=True)
+    with pytest.raises(RuntimeError):
+        cbfm.solve(mesh, med, cbf, Zr, ii, block=True, inner_fp32=True, raise_noconv=True)
+    with pytest.raises(RuntimeError):
+        cbfm.solve(mesh, med, cbf, Zr, ii, block=33, raise_noconv=True)
+
+
+def test_block_cycle_matches_the_oracle_minimiser(torch_cuda):
+    """One cycle of block GMRES stopped after J block iterations returns, for
+    every right-hand side, the minimiser of its residual over the block
+    Krylov space K_J(A, B), A = Z_r (G^CBF)^{-1}: against the oracle's
+    block Arnoldi and least squares, for groups of 4 (4 and 8 random
+    incidences, whose right-hand sides are independent) and J = 2, 6."""
+    from oracle import excitation, reduced
+    from synth.configs import random_incidences
+    O = _oracle_cbf("cyl_small")
+    P = O["P"]
+    w, m = P["w"], P["m"]
+    cbfm, mesh, med, cbf = _gpu_handles(w, O)
+    n = cbf.n_cbf
+    Zr = torch_cuda.zeros((n, n), dtype=torch_cuda.complex128, device="cuda")
+    cbfm.project(mesh, med, cbf, Zr, cbfm.FP64)
+    Gi = np.linalg.inv(O["Gc"])
+    A = O["Zr"] @ Gi
+    for nr in (4, 8):
+        inc = random_incidences(nr, 31 + nr)
+        vr = O["CJM"].conj().T @ excitation.rhs(m, inc, w.k0, w.eta0)
+        for g0 in range(0, nr, 4):
+            sv = np.linalg.svd(vr[:, g0:g0 + 4], compute_uv=False)
+            assert sv[-1] > 1e-6 * sv[0]
+        for J in (2, 6):
+            y = np.concatenate([reduced.block_krylov_minimiser(lambda X: A @ X, vr[:, g0:g0 + 4], J)
+                                for g0 in range(0, nr, 4)], axis=1)
+            jref = O["CMJ"] @ (Gi @ y)
+            jt = torch_cuda.zeros((nr, 2 * m.ne), dtype=torch_cuda.complex128, device="cuda")
+            out = cbfm.solve(mesh, med, cbf, Zr, inc, tol=1e-30, max_iter=J, restart=n, j_out=jt, block=4)
+            got = jt.cpu().numpy().T
+            e = _rel(got, jref)
+            emax = np.max(np.abs(got - jref)) / np.max(np.abs(jref))
+            print(f"block cycle nrhs={nr} J={J}: iters {out['iters']}, current err {e:.2e} {emax:.2e}", flush=True)
+            assert out["status"] == "E_NOCONV" and np.all(out["iters"] == J) and e < 1e-9 and emax < 1e-9
+
+
 def test_every_gemm_launch_shape_solves_alike(torch_cuda, monkeypatch):
     """Every launch shape of the complex GEMM (CBFM_GEMM_SHAPE forces it on
     each product it applies to; the tuner may pick any of them for the

@@ -209,6 +209,45 @@ def test_single_rhs_long_vector_solve(torch_cuda):
         assert np.max(np.abs(out["rcs"] - rcs_ref) / rcs_ref) < 1e-9
 
 
+def test_block_solve_groups_of_32(torch_cuda):
+    """Block GMRES in groups of 32 right-hand sides (the automatic size for
+    N_CBF > 1,056) on Z_r = I + E (E seeded, spectral norm about 0.4; the
+    5,120-triangle sphere's imported dual CBFs, N_CBF > 2048), without the
+    CMP, against LU of the same Z_r: 34 incidences (groups of 32 and 2), two
+    of them repeated so that the first group's block is rank deficient
+    (random vectors take the dependent directions), and groups of 8 forced;
+    currents and monostatic RCS at tol 1e-12."""
+    from oracle import excitation, reduced
+    from paper_2111_11058_amd import cbfm
+    from synth import configs
+    D = _c3_random_dual_cbfs()
+    w, m, cb = D["w"], D["m"], D["cb"]
+    mesh = cbfm.Mesh(w.V, w.T, w.edge_block, w.nblocks)
+    med = cbfm.Medium.make(w.k0, w.eta0, w.eps_r, w.mu_r)
+    h = cbfm.cbf_import(mesh, cb.CM, cb.CJ, cb.sigma)
+    n = h.n_cbf
+    assert n > 33 * 32
+    E = configs.random_complex((n, n), 27) * (0.4 / (2.0 * np.sqrt(n)))
+    Zr = np.eye(n) + E
+    CJM, CMJ = reduced.cbf_matrices(cb, m.ne)
+    Zt = torch_cuda.tensor(Zr, dtype=torch_cuda.complex128, device="cuda")
+    inc = configs.random_incidences(32, 28)
+    inc = np.concatenate([inc[:30], inc[3:5], inc[30:]])
+    v = excitation.rhs(m, inc, w.k0, w.eta0)
+    jref = CMJ @ np.linalg.solve(Zr, CJM.conj().T @ v)
+    rcs_ref = excitation.monostatic_rcs(m, jref, inc, w.k0, w.eta0)
+    for block in (1, 8):
+        jt = torch_cuda.zeros((len(inc), 2 * m.ne), dtype=torch_cuda.complex128, device="cuda")
+        print(f"block solve n={n} nrhs={len(inc)} block={block}", flush=True)
+        out = cbfm.solve(mesh, med, h, Zt, inc, tol=1e-12, max_iter=200, restart=n, use_cmp=False, j_out=jt,
+                         block=block)
+        print(out["iters"], out["relres"].max())
+        assert out["status"] == "OK" and np.all(out["relres"] <= 1e-12)
+        r, e = _both(jt.cpu().numpy().T, jref, f"block currents, block={block}")
+        assert r < 1e-9 and e < 1e-9
+        assert np.max(np.abs(out["rcs"] - rcs_ref) / rcs_ref) < 1e-9
+
+
 _C5 = {}
 
 

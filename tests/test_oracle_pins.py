@@ -534,3 +534,34 @@ def test_inexact_cmp_and_flexible_gmres():
     assert np.linalg.norm(xf - ref) <= 1e-8 * np.linalg.norm(ref)
     xi, it_i, _ = reduced.fgmres(lambda u: Zr @ u, lambda q: reduced.cmp_inner(Gc, q, 1e-5)[:, 0], vr, 1e-12, n, n)
     assert np.linalg.norm(xi - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_block_krylov_minimiser():
+    """The oracle's block GMRES iterate (the minimiser of each column's
+    residual over K_J(A, B)), on a random well-conditioned complex system
+    (n 60, p 4): with J p >= n the space is everything and the iterate is
+    the exact solution; with one column it is plain GMRES after J
+    iterations (the oracle's MGS GMRES, independent code); permuting the
+    columns of B permutes the iterates; each residual is orthogonal to
+    A K_J (the least-squares condition, checked on a Krylov basis built by
+    plain powers of A); and the residuals do not grow with J."""
+    rng = np.random.default_rng(5)
+    n, p = 60, 4
+    A = np.eye(n) * 4 + (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    B = rng.standard_normal((n, p)) + 1j * rng.standard_normal((n, p))
+    mv = lambda X: A @ X
+    x = reduced.block_krylov_minimiser(mv, B, n // p)
+    assert np.linalg.norm(x - np.linalg.solve(A, B)) / np.linalg.norm(np.linalg.solve(A, B)) < 1e-11
+    for J in (3, 7):
+        x1 = reduced.block_krylov_minimiser(mv, B[:, :1], J)[:, 0]
+        g, its, _ = reduced.gmres(lambda v: A @ v, B[:, 0], tol=0.0, restart=J, max_iter=J)
+        assert its == J and np.linalg.norm(x1 - g) / np.linalg.norm(g) < 1e-11
+    perm = [2, 0, 3, 1]
+    xp = reduced.block_krylov_minimiser(mv, B[:, perm], 5)
+    x5 = reduced.block_krylov_minimiser(mv, B, 5)
+    assert np.linalg.norm(xp - x5[:, perm]) / np.linalg.norm(x5) < 1e-11
+    K = np.hstack([np.linalg.matrix_power(A, j) @ B for j in range(5)])
+    r = B - A @ x5
+    assert np.max(np.abs((A @ K).conj().T @ r)) < 1e-9 * np.linalg.norm(A @ K) * np.linalg.norm(B)
+    res = [np.linalg.norm(B - A @ reduced.block_krylov_minimiser(mv, B, J), axis=0) for J in (1, 2, 4, 8)]
+    assert all(np.all(res[i + 1] <= res[i] * (1 + 1e-12)) for i in range(3))
