@@ -269,7 +269,10 @@ def write_counters(workload_name, stats_dir, dirs, cmd):
         if lab.startswith("fill"):
             role = lab
         elif nd >= 100:
-            role = f"{lab}_gmres_matvec"
+            # many dispatches of one shape: the GMRES matrix-vector product
+            # (row-block kernel); with block GMRES the tiled kernel's are the
+            # block Gram-Schmidt update passes (one shape for every basis size)
+            role = f"{lab}_gmres_matvec" if lab == "zgemm_panel" else f"{lab}_gmres_repeated"
         elif ns >= 1e6:
             role = f"{lab}_projection"
         else:
@@ -797,6 +800,7 @@ def main():
                     help="requests of the serving leg (mixed-size stream, Poisson arrivals); 0 skips it")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg (both budgets)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--no-per-rhs", action="store_true", help="skip the per-incidence leg beside the block step")
     ap.add_argument("--no-batching", action="store_true", help="skip the batching leg (mixed-stream projection batch, graphs)")
     ap.add_argument("--no-ipcbf", action="store_true", help="skip the IPCBF leg of the cylinder workload")
     ap.add_argument("--ipcbf", action="store_true",
@@ -979,7 +983,7 @@ def main():
                               "rcs_max_rel_err_of_timed_step": float(np.max(np.abs(out["rcs"] - rcs_ref) / rcs_ref)),
                               "roofline_kernels": r64}
         log(f"fp64 leg: {result['fp64_leg']}")
-    if BLK:
+    if BLK and not args.no_per_rhs:
         # the same step with every right-hand side in its own Krylov space
         # (s-step cycles of 8, the form the block solve replaces)
         step(PREC, sstep=8)

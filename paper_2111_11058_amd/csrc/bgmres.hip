@@ -229,65 +229,57 @@ __global__ void __launch_bounds__(256) chol_pivot_kernel(const double* __restric
     }
   }
   __syncthreads();
-  // First in double (the Gram rounded): accepted when every pivot stays above
-  // 1e-10 of the largest diagonal (condition below 1e5, where Cholesky QR in
-  // double loses at most 1e-6 of orthogonality, which the second pass
-  // restores); otherwise the factorisation is redone in double-double.
+  // First in double, without pivoting, on the Gram matrix with unit
+  // diagonal (columns of W scaled to unit norm, which leaves Q unchanged):
+  // accepted when no column of W is below 1e-10 of the largest in norm and
+  // every pivot of the scaled matrix stays above 1e-10 (its condition below
+  // 1e5, where Cholesky QR in double loses at most about 1e-6 of
+  // orthogonality, which the second pass restores); otherwise the
+  // factorisation is redone in double-double with pivoting.  One barrier
+  // per step: each thread takes the pivot row from the matrix itself.
   {
     double2(*Sd)[PMAX] = U;  // U is free until the inverse
-    __shared__ double2 Rd[PMAX];
-    for (int e = tid; e < p * p; e += 256) {
-      const int a = e / p, b = e % p;
-      if (a <= b) Sd[a][b] = make_double2(S[a][b].re.hi + S[a][b].re.lo, S[a][b].im.hi + S[a][b].im.lo);
+    __shared__ double dsc[PMAX];
+    if (tid < p) {
+      const double d = S[tid][tid].re.hi + S[tid][tid].re.lo;
+      dsc[tid] = d > 0 ? sqrt(d) : 0.0;
+      if (!(d >= 1e-20 * dmax0)) redo_s = 1;
     }
     __syncthreads();
-    for (int k = 0; k < p; ++k) {
-      if (tid < 64) {
-        double v = tid < p && !used[tid] ? Sd[tid][tid].x : -1.0;
-        int qi = tid;
-        for (int off = 32; off >= 1; off >>= 1) {
-          const double ov = __shfl_xor(v, off);
-          const int oq = __shfl_xor(qi, off);
-          if (ov > v || (ov == v && oq < qi)) {
-            v = ov;
-            qi = oq;
-          }
-        }
-        if (tid == 0) {
-          if (!(v > 1e-10 * dmax0)) {
-            redo_s = 1;
-            q_s = -1;
-          } else {
-            used[qi] = 1;
-            piv[k] = qi;
-            pos[qi] = k;
-            q_s = qi;
-          }
-        }
+    for (int e = tid; e < p * p; e += 256) {
+      const int a = e / p, b = e % p;
+      if (a <= b && !redo_s) {
+        const double sc = 1.0 / (dsc[a] * dsc[b]);
+        Sd[a][b] = make_double2((S[a][b].re.hi + S[a][b].re.lo) * sc, (S[a][b].im.hi + S[a][b].im.lo) * sc);
       }
-      __syncthreads();
-      const int q = q_s;
-      if (q < 0) break;  // uniform
-      if (tid < p) {
+    }
+    __syncthreads();
+    for (int k = 0; k < p && !redo_s; ++k) {  // redo_s: uniform after each barrier
+      const double pk = Sd[k][k].x;
+      if (!(pk > 1e-10)) {
+        if (tid == 0) redo_s = 1;
+        __syncthreads();
+        break;
+      }
+      const double sq = sqrt(pk), inv = 1.0 / pk;
+      if (tid < p) {  // row k of the scaled factor, unscaled by the column norm
         const int m = tid;
-        double2 v = make_double2(0.0, 0.0);
-        const double rkk = sqrt(Sd[q][q].x);
-        if (m == q) {
-          v.x = rkk;
-        } else if (!used[m]) {
-          const double2 sq = q <= m ? Sd[q][m] : make_double2(Sd[m][q].x, -Sd[m][q].y);
-          v = make_double2(sq.x / rkk, sq.y / rkk);
-        }
-        Rd[m] = v;
-        R[k][m] = v;
+        const double2 v = m < k ? make_double2(0.0, 0.0) : (m == k ? make_double2(sq, 0.0) : Sd[k][m]);
+        const double f = (m == k ? 1.0 : 1.0 / sq) * dsc[m];
+        R[k][m] = make_double2(v.x * f, v.y * f);
       }
-      __syncthreads();
-      for (int e = tid; e < p * p; e += 256) {
+      for (int e = tid; e < p * p; e += 256) {  // Schur update of the trailing pairs
         const int a = e / p, b = e % p;
-        if (a > b || used[a] || used[b]) continue;
-        Sd[a][b] = c_sub(Sd[a][b], c_cjmul(Rd[a], Rd[b]));
+        if (a <= k || a > b) continue;
+        const double2 t = c_cjmul(Sd[k][a], Sd[k][b]);
+        Sd[a][b] = make_double2(Sd[a][b].x - t.x * inv, Sd[a][b].y - t.y * inv);
       }
       __syncthreads();
+    }
+    if (!redo_s && tid < p) {
+      piv[tid] = tid;
+      pos[tid] = tid;
+      used[tid] = 1;
     }
     if (redo_s) {  // uniform: start again in double-double
       for (int e = tid; e < PMAX * PMAX; e += 256) {
@@ -610,7 +602,8 @@ __global__ void __launch_bounds__(256) bls_qr_kernel(const double2* __restrict__
         for (int r = k + half; r < p2; r += 2) s = c_add(s, c_cjmul(v[r], base[r * stride + cidx]));
       s.x += __shfl_xor(s.x, 1);
       s.y += __shfl_xor(s.y, 1);
-      __syncthreads();  // (the reflector's own column is read above before any write)
+      // (each column is read and written by its own two threads only; the
+      // reflector itself sits in v)
       if (base && beta != 0.0)
 #pragma unroll 8
         for (int r = k + half; r < p2; r += 2) {

@@ -30,9 +30,6 @@ def oracle_problem(name):
                              np.array([[0, 0, -1, 1, 0, 0.0]]), configs.generating_set())
     elif name == "c1":
         w = configs.sphere_c1()
-    elif name == "c1_er15":
-        w = configs.sphere_c1()
-        w.eps_r = 1.5 + 0j
     elif name == "cyl_small":
         w = configs.small_cylinder()
     elif name == "cyl_lossy":
