@@ -732,9 +732,9 @@ class BlockGmres {
  public:
   BlockGmres(const double2* A, int64_t lda, int64_t n, int p, int64_t mb, hipStream_t s)
       : A_(A), lda_(lda), n_(n), p_(p), mb_(mb), s_(s), nch_((int)((n + GCH - 1) / GCH)),
-        V_((size_t)(mb + 1) * p * n * sizeof(double2), s), C1_((size_t)(mb + 1) * p * p * sizeof(double2), s),
-        C2_((size_t)(mb + 1) * p * p * sizeof(double2), s), M1_(p * p * sizeof(double2), s),
-        M2_(p * p * sizeof(double2), s), T_(p * p * sizeof(double2), s), rank_(sizeof(int32_t), s),
+        V_((size_t)(mb + 1) * p * n * sizeof(double2), s), C1_(2 * (size_t)(mb + 1) * p * p * sizeof(double2), s),
+        C2_(2 * (size_t)(mb + 1) * p * p * sizeof(double2), s), M1_(2 * p * p * sizeof(double2), s),
+        M2_(2 * p * p * sizeof(double2), s), T_(p * p * sizeof(double2), s), rank_(sizeof(int32_t), s),
         part_((size_t)nch_ * PMAX * PMAX * 4 * sizeof(double), s), gdd_(PMAX * PMAX * 4 * sizeof(double), s),
         G_((size_t)(mb + 1) * p * p * sizeof(double2), s), Rb_((size_t)mb * p * mb * p * sizeof(double2), s),
         Om_((size_t)mb * OMS * OMS * sizeof(double2), s), h_((size_t)p * (mb + 2) * p * sizeof(double2), s),
@@ -750,7 +750,7 @@ class BlockGmres {
       d.transC = 1;
       mv[J].push_back(d);
       for (int ps = 0; ps < 2; ++ps) {
-        double2* C = (ps == 0 ? C1_ : C2_).as<double2>();
+        double2* C = ps == 0 ? C1(J & 1) : C2(J & 1);
         double2* t = ps == 0 ? t1 : t2;
         dots_.push_back(gemm(V, n, OP_R, t, n, OP_T, C, p, (J + 1) * p, p, n));
         upd[2 * J + ps].push_back(gemm(C, p, OP_T, V, n, OP_N, t, n, p, n, (J + 1) * p, -1.0, 1));
@@ -766,7 +766,24 @@ class BlockGmres {
     dots_ws_.reset(new Scratch(ws, s));
     mv_.reset(new GemmPlan(mv, s));
     upd_.reset(new GemmPlan(upd, s, false));
+    CBFM_HIP(hipStreamCreateWithFlags(&ls_, hipStreamNonBlocking));
+    for (int k = 0; k < 2; ++k) {
+      CBFM_HIP(hipEventCreateWithFlags(&ev_ready_[k], hipEventDisableTiming));
+      CBFM_HIP(hipEventCreateWithFlags(&ev_read_[k], hipEventDisableTiming));
+    }
   }
+  ~BlockGmres() {
+    if (ls_) {
+      (void)hipStreamSynchronize(ls_);
+      (void)hipStreamDestroy(ls_);
+    }
+    for (int k = 0; k < 2; ++k) {
+      if (ev_ready_[k]) (void)hipEventDestroy(ev_ready_[k]);
+      if (ev_read_[k]) (void)hipEventDestroy(ev_read_[k]);
+    }
+  }
+  BlockGmres(const BlockGmres&) = delete;
+  BlockGmres& operator=(const BlockGmres&) = delete;
 
   // Solve for the p right-hand sides b (rows) into x (rows, starting at 0).
   void solve(const double2* b, double2* x, double tol, int64_t max_iter, int64_t& total, std::vector<double>& res,
@@ -798,11 +815,11 @@ class BlockGmres {
         residual();
       hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(1), 0, s, ctl_.as<int32_t>());
       // R_0 = V_0 S0: two orthonormalisation passes into slot 0
-      orthonormalise(t1, t2_.as<double2>(), M1_.as<double2>(), seed(cycle, 0, 0), false);
-      orthonormalise(t2_.as<double2>(), V, M2_.as<double2>(), seed(cycle, 0, 1), true);
+      orthonormalise(t1, t2_.as<double2>(), M1(0), seed(cycle, 0, 0), false);
+      orthonormalise(t2_.as<double2>(), V, M2(0), seed(cycle, 0, 1), true);
       const int64_t grows = (mb_ + 1) * p;
-      hipLaunchKernelGGL(s0_kernel, dim3((unsigned)((grows * p + 255) / 256)), dim3(256), 0, s, M1_.as<double2>(),
-                         M2_.as<double2>(), p, G_.as<double2>(), grows);
+      hipLaunchKernelGGL(s0_kernel, dim3((unsigned)((grows * p + 255) / 256)), dim3(256), 0, s, M1(0), M2(0), p,
+                         G_.as<double2>(), grows);
       CBFM_HIP(hipGetLastError());
       const int64_t mbc = std::min<int64_t>(mb_, max_iter - total);
       bool pending = false;
@@ -810,9 +827,10 @@ class BlockGmres {
         iteration(J, cycle);
         ++total;
         if (pending && flags.wait()[0] != 0) break;
-        flags.post(ctl_.as<int32_t>() + CTL_STATE, s);
+        flags.post(ctl_.as<int32_t>() + CTL_STATE, ls_);  // set by the least-squares stream
         pending = true;
       }
+      CBFM_HIP(hipStreamSynchronize(ls_));
       int32_t ctl[2];
       CBFM_HIP(hipMemcpyAsync(ctl, ctl_.p, sizeof(ctl), hipMemcpyDeviceToHost, s));
       CBFM_HIP(hipStreamSynchronize(s));
@@ -865,10 +883,18 @@ class BlockGmres {
                        s_, W, Out, n_, p_, T_.as<double2>(), rank_.as<int32_t>(), sd, ctl);
     CBFM_HIP(hipGetLastError());
   }
+  // Iteration J on the main stream (the product, both projection and
+  // orthonormalisation passes: the next basis block), and its block column
+  // of the least-squares problem on the second stream, where it overlaps
+  // iteration J + 1.  The passes' coefficients (C1, C2, M1, M2) alternate
+  // between two buffers by the parity of J; iteration J + 2 waits until
+  // the column kernel of iteration J has read them.
   void iteration(int64_t J, int cycle) {
     const int p = p_;
     const int64_t n = n_;
+    const int par = (int)(J & 1);
     double2* V = V_.as<double2>();
+    if (J >= 2) CBFM_HIP(hipStreamWaitEvent(s_, ev_read_[par], 0));
     mv_->launch((size_t)J, s_);
     const double vb = 16.0 * (double)(J + 1) * p * (double)n;  // bytes of the basis read by a pass
     for (int ps = 0; ps < 2; ++ps) {
@@ -882,18 +908,25 @@ class BlockGmres {
         upd_->launch((size_t)(2 * J + ps), s_);
       }
       if (ps == 0)
-        orthonormalise(t1_.as<double2>(), t2_.as<double2>(), M1_.as<double2>(), seed(cycle, J + 1, 0), false);
+        orthonormalise(t1_.as<double2>(), t2_.as<double2>(), M1(par), seed(cycle, J + 1, 0), false);
       else
-        orthonormalise(t2_.as<double2>(), V + (J + 1) * p * n, M2_.as<double2>(), seed(cycle, J + 1, 1), true);
+        orthonormalise(t2_.as<double2>(), V + (J + 1) * p * n, M2(par), seed(cycle, J + 1, 1), true);
     }
-    hipLaunchKernelGGL(bls_column_kernel, dim3((unsigned)p), dim3(256), 0, s_, C1_.as<double2>(), C2_.as<double2>(),
-                       M1_.as<double2>(), M2_.as<double2>(), Om_.as<double2>(), J, p, h_.as<double2>(),
-                       (mb_ + 2) * p, Rb_.as<double2>(), mb_ * p, X_.as<double2>(), ctl_.as<int32_t>());
-    hipLaunchKernelGGL(bls_qr_kernel, dim3(1), dim3(256), 0, s_, X_.as<double2>(), J, p, Rb_.as<double2>(), mb_ * p,
+    CBFM_HIP(hipEventRecord(ev_ready_[par], s_));
+    CBFM_HIP(hipStreamWaitEvent(ls_, ev_ready_[par], 0));
+    hipLaunchKernelGGL(bls_column_kernel, dim3((unsigned)p), dim3(256), 0, ls_, C1(par), C2(par), M1(par), M2(par),
+                       Om_.as<double2>(), J, p, h_.as<double2>(), (mb_ + 2) * p, Rb_.as<double2>(), mb_ * p,
+                       X_.as<double2>(), ctl_.as<int32_t>());
+    CBFM_HIP(hipEventRecord(ev_read_[par], ls_));
+    hipLaunchKernelGGL(bls_qr_kernel, dim3(1), dim3(256), 0, ls_, X_.as<double2>(), J, p, Rb_.as<double2>(), mb_ * p,
                        Om_.as<double2>(), G_.as<double2>(), bnorm_.as<double>(), tol_, res_.as<double>(),
                        ctl_.as<int32_t>());
     CBFM_HIP(hipGetLastError());
   }
+  double2* C1(int par) const { return C1_.as<double2>() + (size_t)par * (mb_ + 1) * p_ * p_; }
+  double2* C2(int par) const { return C2_.as<double2>() + (size_t)par * (mb_ + 1) * p_ * p_; }
+  double2* M1(int par) const { return M1_.as<double2>() + (size_t)par * p_ * p_; }
+  double2* M2(int par) const { return M2_.as<double2>() + (size_t)par * p_ * p_; }
 
  public:
   double tol_ = 1e-6;
@@ -909,6 +942,8 @@ class BlockGmres {
   std::vector<GemmDesc> dots_;
   std::unique_ptr<Scratch> dots_dev_, dots_ws_;
   std::unique_ptr<GemmPlan> mv_, upd_;
+  hipStream_t ls_ = nullptr;  // the least-squares stream (default priority)
+  hipEvent_t ev_ready_[2] = {nullptr, nullptr}, ev_read_[2] = {nullptr, nullptr};
 };
 
 }  // namespace
