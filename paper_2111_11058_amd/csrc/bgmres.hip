@@ -41,7 +41,8 @@
 namespace cbfm {
 namespace {
 
-constexpr int PMAX = 32;  // right-hand sides per block
+constexpr int PMAX = 32;  // right-hand sides per block (a power of two: indices below use e >> 5)
+static_assert(PMAX == 32, "index arithmetic assumes 32");
 constexpr int GCH = 32;   // vector entries per block of the Gram partial sums
 constexpr int OMS = 2 * PMAX;  // row stride of a stored 2p x 2p factor (zero past 2p)
 constexpr int RBUF = 6144;     // rows of a block column staged in LDS (mb p <= RBUF)
@@ -203,8 +204,9 @@ __global__ void __launch_bounds__(256) chol_pivot_kernel(const double* __restric
   __shared__ int q_s, r_s, redo_s;
   __shared__ double dmax0;
   const int tid = threadIdx.x;
-  for (int e = tid; e < p * p; e += 256) {
-    const int a = e / p, b = e % p;
+  for (int e = tid; e < PMAX * PMAX; e += 256) {
+    const int a = e >> 5, b = e & (PMAX - 1);
+    if (a >= p || b >= p) continue;
     if (a <= b) {
       const double* g = Gdd + (a * PMAX + b) * 4;
       S[a][b] = cdd{dd{g[0], g[1]}, dd{g[2], g[3]}};
@@ -246,8 +248,9 @@ __global__ void __launch_bounds__(256) chol_pivot_kernel(const double* __restric
       if (!(d >= 1e-20 * dmax0)) redo_s = 1;
     }
     __syncthreads();
-    for (int e = tid; e < p * p; e += 256) {
-      const int a = e / p, b = e % p;
+    for (int e = tid; e < PMAX * PMAX; e += 256) {
+      const int a = e >> 5, b = e & (PMAX - 1);
+      if (a >= p || b >= p) continue;
       if (a <= b && !redo_s) {
         const double sc = 1.0 / (dsc[a] * dsc[b]);
         Sd[a][b] = make_double2((S[a][b].re.hi + S[a][b].re.lo) * sc, (S[a][b].im.hi + S[a][b].im.lo) * sc);
@@ -268,9 +271,9 @@ __global__ void __launch_bounds__(256) chol_pivot_kernel(const double* __restric
         const double f = (m == k ? 1.0 : 1.0 / sq) * dsc[m];
         R[k][m] = make_double2(v.x * f, v.y * f);
       }
-      for (int e = tid; e < p * p; e += 256) {  // Schur update of the trailing pairs
-        const int a = e / p, b = e % p;
-        if (a <= k || a > b) continue;
+      for (int e = tid; e < PMAX * PMAX; e += 256) {  // Schur update of the trailing pairs
+        const int a = e >> 5, b = e & (PMAX - 1);
+        if (a <= k || a > b || b >= p) continue;
         const double2 t = c_cjmul(Sd[k][a], Sd[k][b]);
         Sd[a][b] = make_double2(Sd[a][b].x - t.x * inv, Sd[a][b].y - t.y * inv);
       }
@@ -336,9 +339,9 @@ __global__ void __launch_bounds__(256) chol_pivot_kernel(const double* __restric
       R[k][m] = make_double2(v.re.hi + v.re.lo, v.im.hi + v.im.lo);
     }
     __syncthreads();
-    for (int e = tid; e < p * p; e += 256) {  // Schur update of the remaining pairs
-      const int a = e / p, b = e % p;
-      if (a > b || used[a] || used[b]) continue;
+    for (int e = tid; e < PMAX * PMAX; e += 256) {  // Schur update of the remaining pairs
+      const int a = e >> 5, b = e & (PMAX - 1);
+      if (a > b || b >= p || used[a] || used[b]) continue;
       const cdd x = Rk[a], y = Rk[b];
       // S[a][b] -= conj(x) y
       const dd pr = dd_add(dd_mul(x.re, y.re), dd_mul(x.im, y.im));
@@ -353,7 +356,10 @@ __global__ void __launch_bounds__(256) chol_pivot_kernel(const double* __restric
   // Rp gathered first (into Rk's rows of S, now free), then thread k takes
   // column k, rows from k down to 0
   double2(*Rp)[PMAX] = reinterpret_cast<double2(*)[PMAX]>(&S[0][0]);
-  for (int e = tid; e < r * r; e += 256) Rp[e / r][e % r] = R[e / r][piv[e % r]];
+  for (int e = tid; e < PMAX * PMAX; e += 256) {
+    const int j = e >> 5, l = e & (PMAX - 1);
+    if (j < r && l < r) Rp[j][l] = R[j][piv[l]];
+  }
   for (int e = tid; e < PMAX * PMAX; e += 256) U[e / PMAX][e % PMAX] = make_double2(0.0, 0.0);
   __syncthreads();
   if (tid < r) {
@@ -367,14 +373,15 @@ __global__ void __launch_bounds__(256) chol_pivot_kernel(const double* __restric
     }
   }
   __syncthreads();
-  for (int e = tid; e < p * p; e += 256) {
-    const int l = e / p, a = e % p;
-    M[e] = l < r ? R[l][a] : make_double2(0.0, 0.0);
+  for (int e = tid; e < PMAX * PMAX; e += 256) {
+    const int l = e >> 5, a = e & (PMAX - 1);
+    if (l < p && a < p) M[l * p + a] = l < r ? R[l][a] : make_double2(0.0, 0.0);
   }
-  for (int e = tid; e < p * p; e += 256) {
-    const int a = e / p, l = e % p;
+  for (int e = tid; e < PMAX * PMAX; e += 256) {
+    const int a = e >> 5, l = e & (PMAX - 1);
+    if (a >= p || l >= p) continue;
     const int j = pos[a];  // pivot position of row a, or -1
-    T[e] = l < r && j >= 0 && j <= l ? U[j][l] : make_double2(0.0, 0.0);
+    T[a * p + l] = l < r && j >= 0 && j <= l ? U[j][l] : make_double2(0.0, 0.0);
   }
   if (tid == 0) {
     rank[0] = r;
