@@ -125,7 +125,11 @@ enum { CTL_STATE = 0, CTL_DONE = 1 };
 
 // ---- Gram partial sums: G[a][b] = sum_i conj(W[a][i]) W[b][i] for a <= b
 // < p over the GCH entries of this block, real and imaginary parts in
-// double-double; entry (a, b) at a * PMAX + b of the block's PMAX^2 slots.
+// double-double (DD) or in double (low parts zero: the second pass, whose
+// rows the first has made orthonormal to within about 1e-3 at worst); entry
+// (a, b) at a * PMAX + b of the
+// block's PMAX^2 slots.
+template <bool DD>
 __global__ void __launch_bounds__(256) gram_partial_kernel(const double2* __restrict__ W, int64_t n, int p,
                                                            double* __restrict__ part, const int32_t* __restrict__ ctl) {
   if (ctl[CTL_STATE] != 0) return;  // uniform over the launch
@@ -140,10 +144,19 @@ __global__ void __launch_bounds__(256) gram_partial_kernel(const double2* __rest
     const int a = e / p, b = e % p;
     if (a > b) continue;
     dd sr{0.0, 0.0}, si{0.0, 0.0};
-    for (int k = 0; k < GCH; ++k) {
-      const double2 x = ws[a][k], y = ws[b][k];
-      sr = dd_add(sr, dd_add(dd_prod(x.x, y.x), dd_prod(x.y, y.y)));
-      si = dd_add(si, dd_add(dd_prod(x.x, y.y), dd_prod(-x.y, y.x)));
+    if (DD) {
+      for (int k = 0; k < GCH; ++k) {
+        const double2 x = ws[a][k], y = ws[b][k];
+        sr = dd_add(sr, dd_add(dd_prod(x.x, y.x), dd_prod(x.y, y.y)));
+        si = dd_add(si, dd_add(dd_prod(x.x, y.y), dd_prod(-x.y, y.x)));
+      }
+    } else {
+#pragma unroll 8
+      for (int k = 0; k < GCH; ++k) {
+        const double2 x = ws[a][k], y = ws[b][k];
+        sr.hi = fma(x.x, y.x, fma(x.y, y.y, sr.hi));
+        si.hi = fma(x.x, y.y, fma(-x.y, y.x, si.hi));
+      }
     }
     double* o = part + ((int64_t)blockIdx.x * PMAX * PMAX + a * PMAX + b) * 4;
     o[0] = sr.hi;
@@ -881,7 +894,12 @@ class BlockGmres {
   // Cholesky, random rows past the rank
   void orthonormalise(const double2* W, double2* Out, double2* M, uint64_t sd, bool must_full) {
     const int32_t* ctl = ctl_.as<int32_t>();
-    hipLaunchKernelGGL(gram_partial_kernel, dim3((unsigned)nch_), dim3(256), 0, s_, W, n_, p_, part_.as<double>(), ctl);
+    if (must_full)  // the second pass: rows already nearly orthonormal
+      hipLaunchKernelGGL(gram_partial_kernel<false>, dim3((unsigned)nch_), dim3(256), 0, s_, W, n_, p_,
+                         part_.as<double>(), ctl);
+    else
+      hipLaunchKernelGGL(gram_partial_kernel<true>, dim3((unsigned)nch_), dim3(256), 0, s_, W, n_, p_,
+                         part_.as<double>(), ctl);
     hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((p_ * p_ + 3) / 4)), dim3(256), 0, s_, part_.as<double>(),
                        nch_, p_, gdd_.as<double>(), ctl);
     hipLaunchKernelGGL(chol_pivot_kernel, dim3(1), dim3(256), 0, s_, gdd_.as<double>(), p_, 1e-26, M,
