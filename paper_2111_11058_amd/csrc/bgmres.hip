@@ -663,9 +663,9 @@ __global__ void __launch_bounds__(256) bls_qr_kernel(const double2* __restrict__
 // triangular, column-major with ldr, in p x p diagonal blocks; G and Y
 // row-major, p columns): every block solves the diagonal block b for all p
 // columns (thread c takes column c; a zero diagonal, a direction with no
-// part in the least-squares solution, gives a zero entry), block 0 stores
-// Y_b, and each thread then removes R[k][block b] Y_b from its row k < b p
-// of G.
+// part in the least-squares solution, gives a zero entry), block (0, 0)
+// stores Y_b, and each thread then removes R[k][block b] Y_b from its row
+// k < b p of G, in the eight columns of its blockIdx.y.
 __global__ void __launch_bounds__(256) backsolve_step_kernel(const double2* __restrict__ Rb, int64_t ldr,
                                                              double2* __restrict__ G, int p, int64_t b,
                                                              double2* __restrict__ Y) {
@@ -692,13 +692,15 @@ __global__ void __launch_bounds__(256) backsolve_step_kernel(const double2* __re
     }
   }
   __syncthreads();
-  if (blockIdx.x == 0)
+  if (blockIdx.x == 0 && blockIdx.y == 0)
     for (int e = tid; e < p * p; e += 256) Y[(r0 + e / p) * p + e % p] = yb[e / p][e % p];
+  // row k, the eight columns c0..c0+7 of blockIdx.y
   const int64_t k = (int64_t)blockIdx.x * 256 + tid;
-  if (k >= r0) return;
-  double2 acc[PMAX];
+  const int c0 = blockIdx.y * 8;
+  if (k >= r0 || c0 >= p) return;
+  double2 acc[8];
 #pragma unroll
-  for (int c = 0; c < PMAX; ++c) acc[c] = make_double2(0.0, 0.0);
+  for (int u = 0; u < 8; ++u) acc[u] = make_double2(0.0, 0.0);
   for (int j0 = 0; j0 < p; j0 += 8) {  // eight loads of the row in flight at a time
     double2 rv[8];
 #pragma unroll
@@ -707,13 +709,12 @@ __global__ void __launch_bounds__(256) backsolve_step_kernel(const double2* __re
     for (int u = 0; u < 8; ++u) {
       const int j = j0 + u < p ? j0 + u : j0;  // rv[u] is zero past p
 #pragma unroll
-      for (int c = 0; c < PMAX; ++c)
-        if (c < p) acc[c] = c_add(acc[c], c_mul(rv[u], yb[j][c]));
+      for (int c = 0; c < 8; ++c) acc[c] = c_add(acc[c], c_mul(rv[u], yb[j][c0 + c]));
     }
   }
 #pragma unroll
-  for (int c = 0; c < PMAX; ++c)
-    if (c < p) G[k * p + c] = c_sub(G[k * p + c], acc[c]);
+  for (int c = 0; c < 8; ++c)
+    if (c0 + c < p) G[k * p + c0 + c] = c_sub(G[k * p + c0 + c], acc[c]);
 }
 
 __global__ void __launch_bounds__(256) vec_norms_kernel(const double2* __restrict__ u, int64_t n,
@@ -857,7 +858,8 @@ class BlockGmres {
       const int64_t nb = ctl[CTL_DONE], K = nb * p;
       if (K > 0) {
         for (int64_t bb = nb - 1; bb >= 0; --bb)
-          hipLaunchKernelGGL(backsolve_step_kernel, dim3((unsigned)std::max<int64_t>(1, (bb * p + 255) / 256)),
+          hipLaunchKernelGGL(backsolve_step_kernel,
+                             dim3((unsigned)std::max<int64_t>(1, (bb * p + 255) / 256), (unsigned)((p + 7) / 8)),
                              dim3(256), 0, s, Rb_.as<double2>(), mb_ * p, G_.as<double2>(), p, bb, Y_.as<double2>());
         CBFM_HIP(hipGetLastError());
         // x += Y^T V_0..V_{nb-1}
