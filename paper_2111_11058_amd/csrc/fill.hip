@@ -854,6 +854,66 @@ void assemble(const cbfm_mesh_s* m, int precision, const void* local, int64_t nr
   CBFM_HIP(hipGetLastError());
 }
 
+// The same gather for a list of RWG pairs (pairs[2k] = row r < nrow,
+// pairs[2k + 1] = column c < ncol of the listed edges), written to
+// Z[op][r][c]: the entries of an assembled block whose triangle-local
+// values have since been overwritten in some slots.  The sum runs in the
+// order of assemble_kernel, so an entry whose slots did not change is
+// reproduced bit for bit.
+template <typename R, typename RO>
+__global__ void assemble_pairs_kernel(const cx<R>* __restrict__ local, int64_t op_stride, int64_t ldl,
+                                      const int32_t* __restrict__ rowEdges, const int32_t* __restrict__ colEdges,
+                                      const int32_t* __restrict__ pairs, int64_t npairs,
+                                      const int32_t* __restrict__ tplus, const int32_t* __restrict__ tminus,
+                                      const int32_t* __restrict__ aplus, const int32_t* __restrict__ aminus,
+                                      const int32_t* __restrict__ rowPos, const int32_t* __restrict__ colPos,
+                                      cx<RO>* __restrict__ Z, int64_t zop_stride, int64_t ldz) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npairs) return;
+  const int64_t r = pairs[2 * k], c = pairs[2 * k + 1];
+  const int32_t em = rowEdges[r], en = colEdges[c];
+  const int64_t ri[2] = {3 * (int64_t)rowPos[tplus[em]] + aplus[em], 3 * (int64_t)rowPos[tminus[em]] + aminus[em]};
+  const int64_t ci[2] = {3 * (int64_t)colPos[tplus[en]] + aplus[en], 3 * (int64_t)colPos[tminus[en]] + aminus[en]};
+#pragma unroll
+  for (int o = 0; o < 3; ++o) {
+    RO re = 0, im = 0;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const cx<R> v = local[o * op_stride + ri[x] * ldl + ci[y]];
+        re += (RO)v.re;
+        im += (RO)v.im;
+      }
+    Z[o * zop_stride + r * ldz + c] = cx<RO>{re, im};
+  }
+}
+
+void assemble_pairs(const cbfm_mesh_s* m, int precision, const void* local, int64_t nrt, int64_t nct,
+                    const int32_t* rowEdges, const int32_t* colEdges, const int32_t* pairs, int64_t npairs,
+                    const int32_t* rowPos, const int32_t* colPos, void* Z, int64_t zop_stride, int64_t ldz,
+                    hipStream_t s, int out_fp64) {
+  if (npairs == 0) return;
+  const int64_t ldl = 3 * nct, op_stride = 3 * nrt * ldl;
+  const dim3 grid((unsigned)((npairs + 255) / 256));
+  TimedLaunch tl(T_ASSEMBLE, s);
+  const int32_t *tp = m->tplus.as<int32_t>(), *tm = m->tminus.as<int32_t>();
+  const int32_t *ap = m->aplus.as<int32_t>(), *am = m->aminus.as<int32_t>();
+  if (precision == CBFM_FP64)
+    hipLaunchKernelGGL((assemble_pairs_kernel<double, double>), grid, dim3(256), 0, s,
+                       static_cast<const cx<double>*>(local), op_stride, ldl, rowEdges, colEdges, pairs, npairs, tp,
+                       tm, ap, am, rowPos, colPos, static_cast<cx<double>*>(Z), zop_stride, ldz);
+  else if (out_fp64)
+    hipLaunchKernelGGL((assemble_pairs_kernel<float, double>), grid, dim3(256), 0, s,
+                       static_cast<const cx<float>*>(local), op_stride, ldl, rowEdges, colEdges, pairs, npairs, tp, tm,
+                       ap, am, rowPos, colPos, static_cast<cx<double>*>(Z), zop_stride, ldz);
+  else
+    hipLaunchKernelGGL((assemble_pairs_kernel<float, float>), grid, dim3(256), 0, s,
+                       static_cast<const cx<float>*>(local), op_stride, ldl, rowEdges, colEdges, pairs, npairs, tp, tm,
+                       ap, am, rowPos, colPos, static_cast<cx<float>*>(Z), zop_stride, ldz);
+  CBFM_HIP(hipGetLastError());
+}
+
 // ------------------------------------------------------------- RHS
 __global__ void rhs_kernel(const double* __restrict__ xyz9, const int32_t* __restrict__ tplus,
                            const int32_t* __restrict__ tminus, const int32_t* __restrict__ aplus,

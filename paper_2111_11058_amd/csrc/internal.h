@@ -295,5 +295,11 @@ void assemble(const cbfm_mesh_s* m, int precision, const void* local, int64_t nr
               const int32_t* rowEdges, int64_t nrow, const int32_t* colEdges, int64_t ncol,
               const int32_t* rowPos, const int32_t* colPos, void* Z, int64_t zop_stride, int64_t ldz,
               hipStream_t s, int out_fp64 = 0);
+// The same for the RWG pairs listed in pairs (npairs (row, column) index
+// pairs into rowEdges and colEdges), into Z[op][row][column].
+void assemble_pairs(const cbfm_mesh_s* m, int precision, const void* local, int64_t nrt, int64_t nct,
+                    const int32_t* rowEdges, const int32_t* colEdges, const int32_t* pairs, int64_t npairs,
+                    const int32_t* rowPos, const int32_t* colPos, void* Z, int64_t zop_stride, int64_t ldz,
+                    hipStream_t s, int out_fp64 = 0);
 
 }  // namespace cbfm

@@ -29,17 +29,20 @@ namespace cbfm {
 // of the block (complex float for the mixed forms, else double), each
 // plane nrow x ncol row-major with leading dimension zld, or stored
 // transposed (ncol x nrow, trans) as the reversed block; W receives the
-// four nrow x NLc products (NLc = CBFs of the column cells).
+// four nrow x NLc products (NLc = CBFs of the column cells).  plane: the
+// elements from one operator's plane to the next (0: nrow x ncol).
 static void block_gemms(const MeshHost& h, cbfm_cbf_s* c, int ra0, int ra1, int cb0, int cb1, void* Zp, int64_t zld,
                         bool trans, void* W, bool mixed, double2* Zr, int64_t ldz, std::vector<GemmDesc>& d1,
-                        std::vector<GemmDesc>& d2, std::vector<GemmDescX>& x1, std::vector<GemmDescX>& x2) {
+                        std::vector<GemmDesc>& d2, std::vector<GemmDescX>& x1, std::vector<GemmDescX>& x2,
+                        int64_t plane = 0) {
   const int64_t NL = c->NL, r0 = h.cell_off[ra0], nrow = h.cell_off[ra1] - r0;
   const int64_t c0 = h.cell_off[cb0], ncol = h.cell_off[cb1] - c0;
   const int64_t o0 = c->off[cb0], NLc = c->off[cb1] - o0;
   const size_t zs = mixed ? sizeof(float2) : sizeof(double2);
+  const int64_t zplane = plane > 0 ? plane : nrow * ncol;  // elements between the K, TE, TH planes
   char* Zk = static_cast<char*>(Zp);
-  char* Zte = Zk + nrow * ncol * zs;
-  char* Zth = Zte + nrow * ncol * zs;
+  char* Zte = Zk + zplane * zs;
+  char* Zth = Zte + zplane * zs;
   char* Wkm = static_cast<char*>(W);
   char* Wkj = Wkm + nrow * NLc * zs;
   char* Wte = Wkj + nrow * NLc * zs;
@@ -123,6 +126,12 @@ static void launch_panel_gemms(int precision, std::vector<GemmDesc>& d1, std::ve
 //   (source) are written over their reversed slots,
 //   the block column Z[cells p1..nb-1][cells p0..p1-1], assembled from the
 //   same local blocks as its transpose.
+// The block column stored transposed is the block row's later-cell part,
+// except where a triangle pair of the entry is a near pair: so it is not
+// assembled again; only those entries of the block row's storage are
+// re-gathered after the reversed near values are written (once the block
+// row's GEMMs have read it), and the block column's GEMMs read the same
+// storage.
 // Every block of Z_r comes from exactly one of them.  With panels of an
 // eighth of the cells about 9/16 of the regular pairs are computed.
 static size_t panel_bytes(int64_t nrt, int64_t nct, int64_t nrow, int64_t ncol, int64_t nlater, int64_t NLc,
@@ -230,7 +239,31 @@ int project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int precis
     }
     const int64_t nrt = rows.size(), nct = cols.size();
     std::vector<int32_t> redges(h.perm.begin() + r0, h.perm.begin() + r1);
-    const size_t ib = 4 * (rows.size() + cols.size() + 2 * pos.size() + redges.size()) +
+    // entries (panel RWG, later RWG) of the block column that a reversed near
+    // pair reaches: the RWGs of its source triangle in the panel against
+    // those of its test triangle in the later cells
+    std::vector<int32_t> npairs;
+    {
+      std::vector<int64_t> keys;
+      const int64_t nl_later = ne - r1;
+      for (const NearPair& q : nlt)
+        for (int u = 0; u < 3; ++u) {
+          const int64_t ie = h.iperm[h.tri_edge[(size_t)q.q * 3 + u]];
+          if (ie < r0 || ie >= r1) continue;
+          for (int v = 0; v < 3; ++v) {
+            const int64_t jf = h.iperm[h.tri_edge[(size_t)q.p * 3 + v]];
+            if (jf >= r1) keys.push_back((ie - r0) * nl_later + (jf - r1));
+          }
+        }
+      std::sort(keys.begin(), keys.end());
+      keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+      npairs.reserve(2 * keys.size());
+      for (int64_t k : keys) {
+        npairs.push_back((int32_t)(k / nl_later));
+        npairs.push_back((int32_t)(k % nl_later));
+      }
+    }
+    const size_t ib = 4 * (rows.size() + cols.size() + 2 * pos.size() + redges.size() + npairs.size()) +
                       sizeof(NearPair) * (nl.size() + nlt.size());
     std::vector<char> host(ib);
     Scratch idx(ib, s);
@@ -248,6 +281,7 @@ int project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int precis
     auto* d_re = (int32_t*)put(redges.data(), 4 * redges.size());
     auto* d_nl = (NearPair*)put(nl.data(), sizeof(NearPair) * nl.size());
     auto* d_nlt = (NearPair*)put(nlt.data(), sizeof(NearPair) * nlt.size());
+    auto* d_np = (int32_t*)put(npairs.data(), 4 * npairs.size());
     CBFM_HIP(hipMemcpyAsync(idx.p, host.data(), ib, hipMemcpyHostToDevice, s));
     const int64_t ncol = ne - r0, nlater = ne - r1;
     const int64_t NLc = c->NL - c->off[p0], NLp = c->off[p1] - c->off[p0];
@@ -267,13 +301,16 @@ int project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int precis
     }
     if (p1 < nb) {
       // block column: the later cells' near pairs against the panel in the
-      // reversed slots, then Z[cells p1..][panel] stored transposed
+      // reversed slots, the entries they reach re-gathered into the block
+      // row's later-cell part, which then holds Z[cells p1..][panel]
+      // stored transposed
       fill_near(m, md, fillp, CBFM_LAYOUT_OPS3, d_nlt, (int64_t)nlt.size(), nrt, nct, local.p, s, 1);
-      assemble(m, fillp, local.p, nrt, nct, d_re, nrow, colEdges + (r1 - r0), nlater, d_pos, d_cpos, Zp.p,
-               nrow * nlater, nlater, s, mixed ? 0 : 1);
+      void* Zcol = static_cast<char*>(Zp.p) + (r1 - r0) * zs;
+      assemble_pairs(m, fillp, local.p, nrt, nct, d_re, colEdges + (r1 - r0), d_np, (int64_t)npairs.size() / 2, d_pos,
+                     d_cpos, Zcol, nrow * ncol, ncol, s, mixed ? 0 : 1);
       std::vector<GemmDesc> d1, d2;
       std::vector<GemmDescX> x1, x2;
-      block_gemms(h, c, p1, nb, p0, p1, Zp.p, nlater, true, W.p, mixed, Zr, ldz, d1, d2, x1, x2);
+      block_gemms(h, c, p1, nb, p0, p1, Zcol, ncol, true, W.p, mixed, Zr, ldz, d1, d2, x1, x2, nrow * ncol);
       launch_panel_gemms(precision, d1, d2, x1, x2, s);
     }
     CBFM_HIP(hipStreamSynchronize(s));  // host index staging of this panel
