@@ -47,8 +47,10 @@ inline GemmDesc gemm(const double2* A, int64_t lda, int opA, const double2* B, i
   return d;
 }
 
-// Launch all GEMMs of `descs` in one kernel on stream s (synchronises s).
-void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s);
+// Launch all GEMMs of `descs` in one kernel on stream s (synchronises s;
+// with keep, the staged descriptors move into *keep instead, which the
+// caller holds until it synchronises s).
+void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s, std::vector<std::vector<GemmDesc>>* keep = nullptr);
 
 // Complex GEMM on the FP32 or BF16 matrix cores with FP32 accumulation.
 // Operands and result may each be complex double (converted on load or
@@ -91,8 +93,9 @@ inline GemmDescX gemmx(const void* A, int a64, int64_t lda, int opA, const void*
   return d;
 }
 
-// mode XG_FP32 or XG_BF16; synchronises s.
-void xgemm_batched(std::vector<GemmDescX>& descs, int mode, hipStream_t s);
+// mode XG_FP32 or XG_BF16; synchronises s (keep: as zgemm_batched).
+void xgemm_batched(std::vector<GemmDescX>& descs, int mode, hipStream_t s,
+                   std::vector<std::vector<GemmDescX>>* keep = nullptr);
 
 // As GemmPlan, for the FP32 / BF16 matrix cores (no tuning).
 class XGemmPlan {

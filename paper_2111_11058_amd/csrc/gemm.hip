@@ -671,7 +671,8 @@ static void launch_x(const GemmDescX* dd, int n, int64_t tiles, double flops, in
   CBFM_HIP(hipGetLastError());
 }
 
-void xgemm_batched(std::vector<GemmDescX>& descs, int mode, hipStream_t s) {
+void xgemm_batched(std::vector<GemmDescX>& descs, int mode, hipStream_t s,
+                   std::vector<std::vector<GemmDescX>>* keep) {
   if (descs.empty()) return;
   std::vector<GemmDescX> live;
   double flops = 0;
@@ -681,6 +682,10 @@ void xgemm_batched(std::vector<GemmDescX>& descs, int mode, hipStream_t s) {
   Scratch dev(live.size() * sizeof(GemmDescX), s);
   CBFM_HIP(hipMemcpyAsync(dev.p, live.data(), live.size() * sizeof(GemmDescX), hipMemcpyHostToDevice, s));
   launch_x(dev.as<GemmDescX>(), (int)live.size(), tiles, flops, mode, ab, s);
+  if (keep) {  // the caller keeps the staged descriptors until it synchronises s
+    keep->push_back(std::move(live));
+    return;
+  }
   CBFM_HIP(hipStreamSynchronize(s));  // the descriptor staging buffer is host memory of this frame
 }
 
@@ -1221,7 +1226,7 @@ static void tune_group(const GemmKey& key, const GemmDesc* dev, int count, int64
   g_tuned[key] = best;
 }
 
-void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s) {
+void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s, std::vector<std::vector<GemmDesc>>* keep) {
   if (descs.empty()) return;
   std::vector<GemmDesc> live;
   double flops = 0;
@@ -1235,6 +1240,10 @@ void zgemm_batched(std::vector<GemmDesc>& descs, hipStream_t s) {
   const int v = choose(key);
   Scratch ws(ws_bytes(v, tiles, key.M, key.N, key.K), s);
   launch_descs(dev.as<GemmDesc>(), (int)live.size(), tiles, key.M, key.N, key.K, flops, v, s, ws.as<double>());
+  if (keep) {  // the caller keeps the staged descriptors until it synchronises s
+    keep->push_back(std::move(live));
+    return;
+  }
   // the descriptor staging buffer is host memory of this frame
   CBFM_HIP(hipStreamSynchronize(s));
 }

@@ -102,16 +102,20 @@ static void panel_gemms(const MeshHost& h, cbfm_cbf_s* c, int p0, int p1, void* 
 }
 
 // Both GEMM stages (each one batched launch; both synchronise the stream).
+// (with keepd / keepx the staged descriptors stay with the caller, which
+// synchronises s before releasing them; otherwise each launch synchronises)
 static void launch_panel_gemms(int precision, std::vector<GemmDesc>& d1, std::vector<GemmDesc>& d2,
-                               std::vector<GemmDescX>& x1, std::vector<GemmDescX>& x2, hipStream_t s) {
+                               std::vector<GemmDescX>& x1, std::vector<GemmDescX>& x2, hipStream_t s,
+                               std::vector<std::vector<GemmDesc>>* keepd = nullptr,
+                               std::vector<std::vector<GemmDescX>>* keepx = nullptr) {
   const int mode = precision == CBFM_MIXED_BF16 ? XG_BF16 : precision == CBFM_MIXED_BF16X3 ? XG_BF16X3 : XG_FP32;
   if (!x1.empty()) {
-    xgemm_batched(x1, mode, s);
-    xgemm_batched(x2, mode, s);
+    xgemm_batched(x1, mode, s, keepx);
+    xgemm_batched(x2, mode, s, keepx);
   }
   if (!d1.empty()) {
-    zgemm_batched(d1, s);
-    zgemm_batched(d2, s);
+    zgemm_batched(d1, s, keepd);
+    zgemm_batched(d2, s, keepd);
   }
 }
 
@@ -211,6 +215,13 @@ int project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int precis
     }
   }
 
+  // The panels are queued without waiting for one another: the host
+  // prepares the next panel's index tables while the device works on this
+  // one.  Staged host data (index tables, GEMM descriptors) is kept until
+  // the final synchronisation.
+  std::vector<std::vector<char>> staged;
+  std::vector<std::vector<GemmDesc>> keepd;
+  std::vector<std::vector<GemmDescX>> keepx;
   for (auto [p0, p1] : panels) {
     const int64_t r0 = h.cell_off[p0], r1 = h.cell_off[p1], nrow = r1 - r0;
     // row triangles (the panel's RWGs) and column triangles (those of
@@ -265,7 +276,8 @@ int project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int precis
     }
     const size_t ib = 4 * (rows.size() + cols.size() + 2 * pos.size() + redges.size() + npairs.size()) +
                       sizeof(NearPair) * (nl.size() + nlt.size());
-    std::vector<char> host(ib);
+    staged.emplace_back(ib);
+    std::vector<char>& host = staged.back();
     Scratch idx(ib, s);
     size_t o = 0;
     auto put = [&](const void* src, size_t bytes) {
@@ -297,7 +309,7 @@ int project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int precis
       std::vector<GemmDesc> d1, d2;
       std::vector<GemmDescX> x1, x2;
       block_gemms(h, c, p0, p1, p0, nb, Zp.p, ncol, false, W.p, mixed, Zr, ldz, d1, d2, x1, x2);
-      launch_panel_gemms(precision, d1, d2, x1, x2, s);
+      launch_panel_gemms(precision, d1, d2, x1, x2, s, &keepd, &keepx);
     }
     if (p1 < nb) {
       // block column: the later cells' near pairs against the panel in the
@@ -311,10 +323,10 @@ int project_dev(const cbfm_mesh_s* m, const Media& md, cbfm_cbf_s* c, int precis
       std::vector<GemmDesc> d1, d2;
       std::vector<GemmDescX> x1, x2;
       block_gemms(h, c, p1, nb, p0, p1, Zcol, ncol, true, W.p, mixed, Zr, ldz, d1, d2, x1, x2, nrow * ncol);
-      launch_panel_gemms(precision, d1, d2, x1, x2, s);
+      launch_panel_gemms(precision, d1, d2, x1, x2, s, &keepd, &keepx);
     }
-    CBFM_HIP(hipStreamSynchronize(s));  // host index staging of this panel
   }
+  CBFM_HIP(hipStreamSynchronize(s));  // the staged host data above is released after this
   return (int)panels.size();
 }
 
