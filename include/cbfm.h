@@ -482,7 +482,8 @@ typedef struct {
                       /* at most N_CBF / group - 1) and iters_host        */
                       /* returns them.  Not with inner_fp32, basis_fp32,  */
                       /* use_graph, sstep or CBFM_CMP_INNER_GMRES         */
-                      /* (CBFM_E_ARG); cbfm_solve only.                   */
+                      /* (CBFM_E_ARG); cbfm_solve, and cbfm_mom_solve     */
+                      /* with an FP64 operator.                           */
 } cbfm_solver_params;
 
 cbfm_status cbfm_solve(cbfm_mesh m, const cbfm_medium* med, cbfm_cbf c, const void* Zr_dev,

@@ -468,8 +468,9 @@ def _solve_outputs(nrhs, dirs):
 
 
 def mom_solve(mom: MomOperator, inc, tol=1e-6, max_iter=1000, restart=1000, j_out=None, dirs=None, stream=None,
-              inner_fp32=False, inner_tol=0.0, use_graph=False, basis_fp32=False):
-    """cbfm_mom_solve (the MoM baseline).  Returns dict(iters, relres, rcs, status)."""
+              inner_fp32=False, inner_tol=0.0, use_graph=False, basis_fp32=False, block=False):
+    """cbfm_mom_solve (the MoM baseline; block as in solve(), FP64 operator
+    only).  Returns dict(iters, relres, rcs, status)."""
     import torch
     inc, pi = _host(inc, np.float64)
     inc = inc.reshape(-1, 6)
@@ -477,7 +478,7 @@ def mom_solve(mom: MomOperator, inc, tol=1e-6, max_iter=1000, restart=1000, j_ou
     pj = _dev(j_out, torch.complex128, nrhs * mom.n, "j") if j_out is not None else None
     iters, relres, rcs, dirs, pd, nd = _solve_outputs(nrhs, dirs)
     prm = SolverParams(float(tol), int(max_iter), int(restart), 0, int(bool(inner_fp32)), float(inner_tol),
-                       int(bool(use_graph)), basis_fp32=int(bool(basis_fp32)))
+                       int(bool(use_graph)), basis_fp32=int(bool(basis_fp32)), block=int(block))
     code = lib().cbfm_mom_solve(mom.handle, pi, nrhs, C.byref(prm), pj, iters.ctypes.data_as(C.c_void_p),
                                 relres.ctypes.data_as(C.c_void_p), pd, nd, rcs.ctypes.data_as(C.c_void_p),
                                 _stream(stream))

@@ -455,7 +455,10 @@ cbfm_status cbfm_mom_solve(cbfm_mom o, const double* inc, int64_t nrhs, const cb
     CBFM_REQUIRE(o && inc && prm, CBFM_E_ARG, "null argument");
     CBFM_REQUIRE(nrhs >= 1 && nrhs <= 65535, CBFM_E_ARG, "nrhs out of range");
     CBFM_REQUIRE(prm->tol > 0 && prm->max_iter >= 1 && prm->restart >= 1, CBFM_E_ARG, "bad solver parameters");
-    CBFM_REQUIRE(prm->sstep == 0 && prm->block == 0, CBFM_E_ARG, "s-step and block cycles are cbfm_solve forms");
+    CBFM_REQUIRE(prm->sstep == 0, CBFM_E_ARG, "s-step cycles are a cbfm_solve form");
+    CBFM_REQUIRE(prm->block == 0 || (prm->block >= 1 && prm->block <= 32 && prm->inner_fp32 == 0 &&
+                                     prm->basis_fp32 == 0 && prm->use_graph == 0 && o->precision == CBFM_FP64),
+                 CBFM_E_ARG, "block is 0 to 32, with the FP64 operator, double cycles and no graphs");
     CBFM_REQUIRE(dirs == nullptr || ndir >= 1, CBFM_E_ARG, "ndir must be >= 1 with dirs");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const cbfm_mesh_s* m = o->mesh;
@@ -467,6 +470,7 @@ cbfm_status cbfm_mom_solve(cbfm_mom o, const double* inc, int64_t nrhs, const cb
     sp.inner_tol = prm->inner_tol;
     sp.graph = prm->use_graph != 0;
     sp.basis32 = prm->basis_fp32 != 0 && prm->inner_fp32 == 0;
+    sp.block = prm->block;
     Scratch jz(nrhs * o->n * sizeof(double2), s), jout(nrhs * o->n * sizeof(double2), s);
     const GmresResult r = full_solve(o, inc, nrhs, sp, jz.as<double2>(), s);
     noconv = r.noconv;

@@ -99,6 +99,23 @@ def test_mom_solve_parity(torch_cuda):
     # drift by a couple of iterations)
     print("iterations to 1e-6: GPU", o6["iters"], "oracle", its)
     assert np.all(np.abs(o6["iters"] - np.array(its)) <= np.maximum(2, 0.02 * np.array(its)))
+    # block GMRES on the same operator (the incidences in one Krylov space):
+    # the LU solution at tol 1e-12, for the workload's incidences and for 12
+    # of which 9 are plane waves two degrees apart
+    from synth.configs import sph_dir
+    th = np.deg2rad(2.0 * np.arange(9))
+    rr, tt, _ = sph_dir(th, np.zeros_like(th))
+    for inc in (w.inc, np.concatenate([np.concatenate([-rr, tt], axis=1), w.inc])):
+        vb = excitation.rhs(m, inc, w.k0, w.eta0)
+        jb_ref = np.linalg.solve(P["Z"], vb)
+        jb = torch_cuda.zeros((len(inc), 2 * ne), dtype=torch_cuda.complex128, device="cuda")
+        ob = cbfm.mom_solve(op, inc, tol=1e-12, max_iter=4 * ne, restart=2 * ne, j_out=jb, block=True)
+        print("block MoM solve", len(inc), ob["iters"], ob["relres"].max())
+        assert ob["status"] == "OK"
+        r, e = _both(jb.cpu().numpy().T, jb_ref, f"block MoM currents, {len(inc)} incidences")
+        assert r < 1e-9 and e < 1e-9
+    with pytest.raises(RuntimeError):
+        cbfm.mom_solve(cbfm.MomOperator(mesh, med, cbfm.FP32), w.inc, block=True)
     # the FP32 operator (regular pairs filled in float, A stored in float):
     # its solution moves by about cond(A) times the float rounding of its
     # entries (cond ~ 3e5 for this small cylinder), so the bound is that
