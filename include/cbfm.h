@@ -130,9 +130,9 @@ cbfm_status cbfm_set_allocator(cbfm_alloc_fn alloc, cbfm_release_fn release);
 cbfm_status cbfm_memory_stats(int64_t* held, int64_t* peak, int64_t* cached);
 
 /* ABI version (incremented on incompatible change). */
-int32_t cbfm_version(void);  /* 6: cbfm_solver_params gained block (5: sstep; 4: basis_fp32; 3: cbfm_request
-                                gained inner_fp32; 2: cbfm_solver_params gained cmp_mode,
-                                cmp_inner_tol) */
+int32_t cbfm_version(void);  /* 7: cbfm_ipcbf_params gained block (6: cbfm_solver_params
+                                gained block; 5: sstep; 4: basis_fp32; 3: cbfm_request gained
+                                inner_fp32; 2: cbfm_solver_params gained cmp_mode, cmp_inner_tol) */
 
 /* -------------------------------------------------------------- timers ---
  * Opt-in kernel timing for measurement: when enabled, the library records a
@@ -557,6 +557,11 @@ typedef struct {
   int32_t max_L;          /* 0 = no cap                              */
   int32_t max_iter;
   int32_t restart;        /* 0 = max_iter (full GMRES)               */
+  int32_t block;          /* 0: one Krylov space per wave; 1, 2..32:
+                             block GMRES as cbfm_solver_params.block
+                             (the waves share a Krylov space per group;
+                             max_iter, restart and iters_host count
+                             block iterations)                       */
 } cbfm_ipcbf_params;
 cbfm_status cbfm_build_ipcbf(cbfm_mom o, const cbfm_ipcbf_params* prm, void* stream, cbfm_cbf* out,
                              int32_t* iters_host, double* relres_host);

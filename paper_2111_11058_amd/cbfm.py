@@ -56,7 +56,8 @@ class SolverParams(C.Structure):
 
 class IpcbfParams(C.Structure):
     _fields_ = [("gen_host", C.POINTER(C.c_double)), ("n_gen", C.c_int32), ("delta_r", C.c_double),
-                ("delta_svd", C.c_double), ("max_L", C.c_int32), ("max_iter", C.c_int32), ("restart", C.c_int32)]
+                ("delta_svd", C.c_double), ("max_L", C.c_int32), ("max_iter", C.c_int32), ("restart", C.c_int32),
+                ("block", C.c_int32)]
 
 
 _lib = None
@@ -487,12 +488,15 @@ def mom_solve(mom: MomOperator, inc, tol=1e-6, max_iter=1000, restart=1000, j_ou
     return dict(iters=iters, relres=relres, rcs=rcs, status=STATUS.get(code, code))
 
 
-def build_ipcbf(mom: MomOperator, gen, delta_r=1e-3, delta_svd=1e-3, max_L=0, max_iter=1000, restart=0, stream=None):
-    """cbfm_build_ipcbf: returns (CBF, iterations per wave, residual per wave)."""
+def build_ipcbf(mom: MomOperator, gen, delta_r=1e-3, delta_svd=1e-3, max_L=0, max_iter=1000, restart=0, block=False,
+                stream=None):
+    """cbfm_build_ipcbf: returns (CBF, iterations per wave, residual per wave)
+    (block: True or a group size, block GMRES; the iterations are then block
+    iterations of the wave's group)."""
     gen, _ = _host(gen, np.float64)
     gen = gen.reshape(-1, 6)
     prm = IpcbfParams(gen.ctypes.data_as(C.POINTER(C.c_double)), len(gen), float(delta_r), float(delta_svd),
-                      int(max_L), int(max_iter), int(restart))
+                      int(max_L), int(max_iter), int(restart), int(block))
     h = _P()
     its = np.zeros(len(gen), np.int32)
     res = np.zeros(len(gen))

@@ -751,8 +751,9 @@ __global__ void ctl_reset_kernel(int32_t* ctl) {
 // projected again; slot J + 1 = the orthonormalised rows of t2.
 class BlockGmres {
  public:
-  BlockGmres(const double2* A, int64_t lda, int64_t n, int p, int64_t mb, hipStream_t s)
-      : A_(A), lda_(lda), n_(n), p_(p), mb_(mb), s_(s), nch_((int)((n + GCH - 1) / GCH)),
+  BlockGmres(const double2* A, int64_t lda, const float2* A32, int64_t lda32, int64_t n, int p, int64_t mb,
+             hipStream_t s)
+      : A_(A), lda_(lda), A32_(A32), lda32_(lda32), n_(n), p_(p), mb_(mb), s_(s), nch_((int)((n + GCH - 1) / GCH)),
         V_((size_t)(mb + 1) * p * n * sizeof(double2), s), C1_(2 * (size_t)(mb + 1) * p * p * sizeof(double2), s),
         C2_(2 * (size_t)(mb + 1) * p * p * sizeof(double2), s), M1_(2 * p * p * sizeof(double2), s),
         M2_(2 * p * p * sizeof(double2), s), T_(p * p * sizeof(double2), s), rank_(sizeof(int32_t), s),
@@ -762,14 +763,21 @@ class BlockGmres {
         X_((size_t)2 * p * p * sizeof(double2), s), Y_((size_t)mb * p * p * sizeof(double2), s),
         bnorm_(p * sizeof(double), s), res_(p * sizeof(double), s), ctl_(2 * sizeof(int32_t), s),
         t1_((size_t)p * n * sizeof(double2), s), t2_((size_t)p * n * sizeof(double2), s) {
-    std::vector<std::vector<GemmDesc>> mv(mb), upd(2 * mb);
+    std::vector<std::vector<GemmDesc>> mv(A_ ? mb : 0), upd(2 * mb);
+    std::vector<std::vector<GemmDescX>> mvx(A_ ? 0 : mb);
     double2* V = V_.as<double2>();
     double2* t1 = t1_.as<double2>();
     double2* t2 = t2_.as<double2>();
     for (int64_t J = 0; J < mb; ++J) {
-      GemmDesc d = gemm(A_, lda_, OP_N, V + J * p * n, n, OP_T, t1, n, n, p, n);
-      d.transC = 1;
-      mv[J].push_back(d);
+      if (A_) {
+        GemmDesc d = gemm(A_, lda_, OP_N, V + J * p * n, n, OP_T, t1, n, n, p, n);
+        d.transC = 1;
+        mv[J].push_back(d);
+      } else {  // a float operator: the product on the FP32 matrix cores, vectors in double
+        GemmDescX d = gemmx(A32_, 0, lda32_, OP_N, V + J * p * n, 1, n, OP_T, t1, 1, n, n, p, n);
+        d.transC = 1;
+        mvx[J].push_back(d);
+      }
       for (int ps = 0; ps < 2; ++ps) {
         double2* C = ps == 0 ? C1(J & 1) : C2(J & 1);
         double2* t = ps == 0 ? t1 : t2;
@@ -785,7 +793,10 @@ class BlockGmres {
       CBFM_HIP(hipStreamSynchronize(s));
     }
     dots_ws_.reset(new Scratch(ws, s));
-    mv_.reset(new GemmPlan(mv, s));
+    if (A_)
+      mv_.reset(new GemmPlan(mv, s));
+    else
+      mvx_.reset(new XGemmPlan(mvx, XG_FP32, s));
     upd_.reset(new GemmPlan(upd, s, false));
     CBFM_HIP(hipStreamCreateWithFlags(&ls_, hipStreamNonBlocking));
     for (int k = 0; k < 2; ++k) {
@@ -815,12 +826,22 @@ class BlockGmres {
     double2* V = V_.as<double2>();
     double2* t1 = t1_.as<double2>();
     // t1 = A x (the operator's matrix-vector product shape, tuned)
-    std::vector<std::vector<GemmDesc>> rg(1);
-    rg[0].push_back(gemm(A_, lda_, OP_N, x, n, OP_T, t1, n, n, p, n));
-    rg[0][0].transC = 1;
+    std::vector<std::vector<GemmDesc>> rg(A_ ? 1 : 0);
+    std::vector<std::vector<GemmDescX>> rgx(A_ ? 0 : 1);
+    if (A_) {
+      rg[0].push_back(gemm(A_, lda_, OP_N, x, n, OP_T, t1, n, n, p, n));
+      rg[0][0].transC = 1;
+    } else {
+      rgx[0].push_back(gemmx(A32_, 0, lda32_, OP_N, x, 1, n, OP_T, t1, 1, n, n, p, n));
+      rgx[0][0].transC = 1;
+    }
     const GemmPlan resid(rg, s);
+    const XGemmPlan resid32(rgx, XG_FP32, s);
     auto residual = [&]() {  // t1 = b - A x
-      resid.launch(0, s);
+      if (A_)
+        resid.launch(0, s);
+      else
+        resid32.launch(0, s);
       const int64_t tot = (int64_t)p * n;
       hipLaunchKernelGGL(sub_from_b_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b, t1, tot);
       CBFM_HIP(hipGetLastError());
@@ -922,7 +943,10 @@ class BlockGmres {
     const int par = (int)(J & 1);
     double2* V = V_.as<double2>();
     if (J >= 2) CBFM_HIP(hipStreamWaitEvent(s_, ev_read_[par], 0));
-    mv_->launch((size_t)J, s_);
+    if (mv_)
+      mv_->launch((size_t)J, s_);
+    else
+      mvx_->launch((size_t)J, s_);
     const double vb = 16.0 * (double)(J + 1) * p * (double)n;  // bytes of the basis read by a pass
     for (int ps = 0; ps < 2; ++ps) {
       {
@@ -960,7 +984,9 @@ class BlockGmres {
 
  private:
   const double2* A_;
-  int64_t lda_, n_;
+  int64_t lda_;
+  const float2* A32_;
+  int64_t lda32_, n_;
   int p_;
   int64_t mb_;
   hipStream_t s_;
@@ -969,14 +995,16 @@ class BlockGmres {
   std::vector<GemmDesc> dots_;
   std::unique_ptr<Scratch> dots_dev_, dots_ws_;
   std::unique_ptr<GemmPlan> mv_, upd_;
+  std::unique_ptr<XGemmPlan> mvx_;
   hipStream_t ls_ = nullptr;  // the least-squares stream (default priority)
   hipEvent_t ev_ready_[2] = {nullptr, nullptr}, ev_read_[2] = {nullptr, nullptr};
 };
 
 }  // namespace
 
-GmresResult block_gmres_run(const double2* A, int64_t lda, int64_t n, int64_t nrhs, const double2* b, double2* x,
-                            const GmresSpec& sp, hipStream_t s) {
+GmresResult block_gmres_run(const double2* A, int64_t lda, const float2* A32, int64_t lda32, int64_t n, int64_t nrhs,
+                            const double2* b, double2* x, const GmresSpec& sp, hipStream_t s) {
+  CBFM_REQUIRE(A != nullptr || A32 != nullptr, CBFM_E_ARG, "block GMRES needs a dense operator");
   CBFM_REQUIRE(n >= 2, CBFM_E_ARG, "block GMRES needs vectors of length 2 or more");
   CBFM_REQUIRE(sp.tol > 0 && sp.max_iter >= 1 && sp.restart >= 1, CBFM_E_ARG, "bad solver parameters");
   GmresResult out;
@@ -993,7 +1021,7 @@ GmresResult block_gmres_run(const double2* A, int64_t lda, int64_t n, int64_t nr
     // block iterations per cycle: the restart length, (mb + 1) p <= n, and
     // mb p <= RBUF (a block column of the triangular factor staged in LDS)
     const int64_t mb = std::max<int64_t>(1, std::min<int64_t>({sp.restart, n / p - 1, (int64_t)RBUF / p}));
-    BlockGmres bg(A, lda, n, p, mb, s);
+    BlockGmres bg(A, lda, A32, lda32, n, p, mb, s);
     bg.tol_ = sp.tol;
     int64_t total = 0;
     std::vector<double> res(p, 1.0);

@@ -317,7 +317,7 @@ extern "C" {
 
 const char* cbfm_last_error(void) { return cbfm::g_last_error.c_str(); }
 
-int32_t cbfm_version(void) { return 6; }
+int32_t cbfm_version(void) { return 7; }
 
 // Whether every cell is cell 0 moved by one vector: equal RWG counts, and
 // RWG i of cell b (cell order) lies on triangles whose vertices, in their

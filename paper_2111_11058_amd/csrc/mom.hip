@@ -494,12 +494,14 @@ cbfm_status cbfm_build_ipcbf(cbfm_mom o, const cbfm_ipcbf_params* prm, void* str
     CBFM_REQUIRE(prm->delta_r > 0 && prm->delta_r < 1, CBFM_E_ARG, "delta_r outside (0, 1)");
     CBFM_REQUIRE(prm->delta_svd >= 0 && prm->delta_svd <= 1, CBFM_E_ARG, "delta_svd outside [0, 1]");
     CBFM_REQUIRE(prm->max_iter >= 1, CBFM_E_ARG, "max_iter must be positive");
+    CBFM_REQUIRE(prm->block >= 0 && prm->block <= 32, CBFM_E_ARG, "block must be 0, 1 or a group size up to 32");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t S = prm->n_gen;
     GmresSpec sp;
     sp.tol = prm->delta_r;
     sp.max_iter = prm->max_iter;
     sp.restart = prm->restart > 0 ? prm->restart : prm->max_iter;
+    sp.block = prm->block;
     Scratch jz(S * o->n * sizeof(double2), s);
     const GmresResult r = full_solve(o, prm->gen_host, S, sp, jz.as<double2>(), s);
     if (iters) std::memcpy(iters, r.its.data(), S * sizeof(int32_t));

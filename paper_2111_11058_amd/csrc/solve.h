@@ -51,8 +51,9 @@ struct GmresSpec {
                            // operator, double basis, no graphs); 0: plain cycles
   int block = 0;           // block GMRES: the right-hand sides share one Krylov space per group
                            // (1: groups of up to 32 sized for cycles of 32 block iterations or more;
-                           // 2..32: groups of that many); dense double operator, double basis, no
-                           // graphs; restart and max_iter then count block iterations
+                           // 2..32: groups of that many); dense double or float operator (a float
+                           // one only with f32 unset), double basis, no graphs; restart and
+                           // max_iter then count block iterations
 };
 
 // Device flags read back through pinned host memory: post() queues a copy
@@ -103,10 +104,13 @@ struct GmresResult {
 GmresResult gmres_run(KrylovOp& op, int64_t n, int64_t nrhs, const double2* b, double2* x, const GmresSpec& p,
                       hipStream_t s);
 
-// Block GMRES (bgmres.hip) on a dense double operator: b, x as gmres_run;
-// the iteration counts returned are block iterations.
-GmresResult block_gmres_run(const double2* A, int64_t lda, int64_t n, int64_t nrhs, const double2* b, double2* x,
-                            const GmresSpec& p, hipStream_t s);
+// Block GMRES (bgmres.hip) on a dense operator, double (A) or, when A is
+// null, float (A32: its products on the FP32 matrix cores, the Krylov basis
+// and everything else in double, so the Arnoldi relation holds to float
+// rounding): b, x as gmres_run; the iteration counts returned are block
+// iterations.
+GmresResult block_gmres_run(const double2* A, int64_t lda, const float2* A32, int64_t lda32, int64_t n, int64_t nrhs,
+                            const double2* b, double2* x, const GmresSpec& p, hipStream_t s);
 
 // Dense row-major operator: the double matrix (lda), the float one (n), or
 // both (a float-only operator forms its residuals in float too).

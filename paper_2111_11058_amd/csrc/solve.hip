@@ -1867,9 +1867,9 @@ GmresResult gmres_run(KrylovOp& op, int64_t n, int64_t nrhs, const double2* b, d
                CBFM_E_ARG, "s-step cycles take blocks of 4 or 8 with a dense double operator, a double basis, no graphs");
   CBFM_REQUIRE(p.tol > 0 && p.max_iter >= 1 && p.restart >= 1, CBFM_E_ARG, "bad solver parameters");
   if (p.block) {
-    CBFM_REQUIRE(A64 != nullptr && !f32 && !b32 && S == 0 && !p.graph && op.xbasis() == nullptr, CBFM_E_ARG,
-                 "block GMRES takes a dense double operator, a double basis, no s-step cycles and no graphs");
-    return block_gmres_run(A64, lda64, n, nrhs, b, x, p, s);
+    CBFM_REQUIRE(dense && !p.f32 && !b32 && S == 0 && !p.graph && op.xbasis() == nullptr, CBFM_E_ARG,
+                 "block GMRES takes a dense operator, a double basis, no s-step cycles and no graphs");
+    return block_gmres_run(A64, lda64, A64 ? nullptr : A32in, lda32, n, nrhs, b, x, p, s);
   }
   const int64_t mres = std::min<int64_t>(p.restart, std::max<int64_t>(p.max_iter, 1));
   // The plain form keeps the Krylov basis in double; the mixed form keeps it

@@ -191,6 +191,41 @@ def test_ipcbf_parity(torch_cuda, delta_r):
     assert out["status"] == "OK" and r < 1e-9 and e < 1e-9
 
 
+def test_ipcbf_block(torch_cuda):
+    """IPCBF with block GMRES (the ten waves share one Krylov space): with
+    delta_r -> 0 the kept counts and singular values are those of the exact
+    MoM solutions (the oracle's); with the FP32 operator at delta_r 1e-3
+    every wave meets the allowance in fewer block iterations than the plain
+    cycles' iterations per wave."""
+    from oracle import cbf, excitation, mom as omom
+    from paper_2111_11058_amd import cbfm
+    P = oracle_problem("cyl_small")
+    w, m = P["w"], P["m"]
+    ne = m.ne
+    gen = w.gen[::12][:10]
+    Zt = omom.mom_t_matrix(P["Kc"], P["TE"], P["TH"])
+    cur, _ = omom.ipcbf_currents(Zt, excitation.rhs(m, gen, w.k0, w.eta0), w.edge_block, 1e-12, max_iter=2 * ne)
+    ref = cbf.dual_from_currents(m, w.edge_block, cur, 1e-3, G=cbf.rwg_gram(m))
+    mesh = cbfm.Mesh(w.V, w.T, w.edge_block, w.nblocks)
+    med = cbfm.Medium.make(w.k0, w.eta0, w.eps_r, w.mu_r)
+    op = cbfm.MomOperator(mesh, med, cbfm.FP64)
+    cb, gits, gres = cbfm.build_ipcbf(op, gen, delta_r=1e-12, delta_svd=1e-3, max_iter=ne,
+                                      block=True)
+    print("block IPCBF delta_r 1e-12: iterations", gits, "residuals", gres.max(), flush=True)
+    assert np.all(gres <= 1e-12) and np.array_equal(cb.L, ref.L)
+    sig = np.concatenate(ref.sigma)
+    assert np.max(np.abs(cb.sigma - sig) / sig.max()) < 1e-8
+    op.close()
+    op32 = cbfm.MomOperator(mesh, med, cbfm.FP32)
+    _, pits, pres = cbfm.build_ipcbf(op32, gen, delta_r=1e-3, delta_svd=1e-3, max_iter=ne)
+    cb32, bits, bres = cbfm.build_ipcbf(op32, gen, delta_r=1e-3, delta_svd=1e-3, max_iter=ne, block=True)
+    print("FP32 operator, delta_r 1e-3: block iterations", bits, "plain", pits, "residuals", bres, flush=True)
+    assert np.all(bres <= 1e-3) and np.all(pres <= 1e-3) and bits.max() < pits.max()
+    assert cb32.n_cbf > 0
+    with pytest.raises(cbfm.CBFMError):
+        cbfm.build_ipcbf(op32, gen, delta_r=1e-3, block=33)
+
+
 def test_t_diagonal_cbfm_parity(torch_cuda):
     """use_cmp = 2, the T-diagonal CBFM (Sec. IV-A): GMRES on Z_r with its
     column halves swapped reaches the oracle's solution of the T-diagonal

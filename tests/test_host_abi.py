@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(cb):
     L = cb.lib()
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
-    assert L.cbfm_version() == 6
+    assert L.cbfm_version() == 7
 
 
 @pytest.mark.parametrize("make", [configs.sphere_c1, configs.cube_c2, configs.small_cylinder],
